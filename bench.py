@@ -1,0 +1,184 @@
+"""Benchmark of the arrested-Newton-flow hot path on one MI355X.
+
+Workload (default): the large Ginzburg-Landau lattice, 4096 x 4096 interior
+sites, kappa = 1.5 (lambda = 2 kappa^2 = 4.5), h = 0.2, 256 unit vortices at
+seeded Poisson-disc positions (minimum separation 3) inside the centred square
+of side 0.6 L, U(+-1e-3) noise, FP32 fields with FP64 reductions. A "step" is
+one full RK4 flow step (4 fused stage passes, arrest test, FP64 energy).
+
+Prints one JSON line: site-updates/s over K timed steps (inputs resident in
+HBM), the roofline of the dominant pass (algorithmic bytes per launch over its
+mean HIP-event duration), and the CPU oracle's rate on a bounded sample of the
+same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM traffic of each pass, in field sets (C planes) read and
+# written per interior site (halo re-reads served by cache are not counted):
+#   P1 reads phi, writes a1; P2 reads phi, v, writes a2; P3 reads phi, v, a1, a2,
+#   writes q; P4 reads phi, v, a2, q, a1, writes phi', v'.
+PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2)}
+STEP_SETS = 17
+
+WORKLOADS = {
+    "gl4096": dict(theory="abelian_higgs", N=4096, h=0.2, kappa=1.5, nv=256, seed=4, dtype="f32"),
+    "cm512": dict(theory="chiral_magnet", N=512, h=0.05, seed=2, dtype="f32"),
+    "ah128": dict(theory="abelian_higgs", N=128, h=0.1, kappa=2 ** -0.5, nv=1, seed=1, dtype="f64"),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_24370_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_solver(wl):
+    import paper_2603_24370_amd as ss
+    from paper_2603_24370_amd import inputs as I
+    if wl["theory"] == "abelian_higgs":
+        lam = I.gl_lambda_from_kappa(wl["kappa"])
+        s = ss.Solver("abelian_higgs", wl["N"], wl["N"], wl["h"], [lam], dtype=wl["dtype"])
+        if wl["nv"] == 1:
+            centres = [(0.0, 0.0)]
+        else:
+            centres = I.poisson_disc(wl["seed"], wl["nv"], 3.0, 0.5 * 0.6 * wl["N"] * wl["h"])
+        s.init_vortices(centres, seed=wl["seed"], noise_amp=1e-3)
+        params = [lam]
+    else:
+        params = [1.0, 1.0, 0.1, 0.6]
+        s = ss.Solver("chiral_magnet", wl["N"], wl["N"], wl["h"], params, dtype=wl["dtype"])
+        s.init_skyrmion(R=2.0, gamma=-math.pi / 2, seed=wl["seed"], noise_amp=1e-3)
+    return s, params
+
+
+def cpu_baseline(s, wl, params, window=1024, steps=10):
+    """The FP64 oracle (single thread) on a central window of the same field."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    f = s.get_field().double().cpu().numpy()
+    N = wl["N"]
+    w = min(window, N)
+    a = (N - w) // 2
+    sub = np.ascontiguousarray(f[:, a:a + w + 4, a:a + w + 4])
+    t0 = time.perf_counter()
+    oracle.flow(wl["theory"], sub, np.zeros_like(sub), wl["h"], params, steps)
+    dt = time.perf_counter() - t0
+    return {"value": w * w * steps / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} RK4 steps of the central {w}x{w} window of the same field (its neighbours as a "
+                      f"fixed halo), FP64, {dt:.1f} s"}
+
+
+def traffic_record(pass_name, wl_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source") != kernel_source_hash():
+        return None
+    return rec.get(wl_name, {}).get(pass_name)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="gl4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--timing-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the lattice fits one "
+              f"MI355X; see the design notes for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP GPU", file=sys.stderr)
+        sys.exit(1)
+    wl = WORKLOADS[args.workload]
+    s, params = make_solver(wl)
+    N = wl["N"]
+    sites = N * N
+    C = s.C
+    b = 4 if wl["dtype"] == "f32" else 8
+
+    # warm-up (real flow steps)
+    s.flow_step(args.warmup, want_info=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.flow_step(args.steps, want_info=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    info = s.info()
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    value = sites * args.steps / elapsed
+
+    # per-pass device time with HIP events on the library's stream
+    ms = s.time_passes(args.timing_steps)
+    passes = {}
+    for k, name in enumerate(["P1", "P2", "P3", "P4"]):
+        r, w_ = PASS_SETS[name]
+        nbytes = sites * C * b * (r + w_)
+        passes[name] = {"ms": ms[k], "GB_per_launch": nbytes / 1e9, "GBps": nbytes / (ms[k] * 1e-3) / 1e9}
+    dom = max(passes, key=lambda k: passes[k]["ms"])
+    ach = passes[dom]["GBps"]
+    step_gbps = STEP_SETS * C * b * sites / (ms_step * 1e-3) / 1e9
+    tr = traffic_record(dom, args.workload)
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": f"stage_pass {dom}",
+            "step_GBps": round(step_gbps, 1), "step_frac": round(step_gbps / HBM_PEAK_GBS, 4),
+            "passes": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in passes.items()}}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(s, wl, params)
+
+    out = {
+        "metric": "site-updates/s",
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 fields, f64 reductions" if wl["dtype"] == "f32" else "f64",
+        "data": "synthetic (seeded ansatz + noise)",
+        "config": {"workload": args.workload, "theory": wl["theory"], "Nx": N, "Ny": N, "h": wl["h"],
+                   "kappa": wl.get("kappa"), "vortices": wl.get("nv"), "grad_form": "euler-lagrange",
+                   "integrator": "RK4 arrested Newton flow, dt = 0.5 h", "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "state": {"energy": info["energy"], "n_arrests": info["n_arrests"], "step": info["step"]},
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,242 @@
+/*
+ * ss.h -- C ABI of the MI355X (gfx950) soliton energy-minimisation library.
+ *
+ * The library minimises a discretised energy E_h[phi] of a multi-component
+ * field on a 2-D lattice by arrested Newton flow, as set out in
+ * "soliton_solver" (arXiv 2603.24370):
+ *   - lattice: Nx x Ny interior sites, spacing h, fixed halo of width 2
+ *     (Sec. 3.1);
+ *   - derivatives: the 4th-order central stencils of eq. (1) and eq. (2);
+ *   - flow: eq. (3), phi'' = -grad E_h, integrated as a first-order system in
+ *     (phi, phidot) by classical 4th-order Runge-Kutta with dt = C h, C = 0.5
+ *     by default (Sec. 3.1-3.2); the flow starts from rest;
+ *   - arrest: eq. (4), after a step that raised E_h the velocity is set to zero
+ *     and the flow continues from the new configuration;
+ *   - constraint: the chiral magnet's unit length is enforced in every
+ *     Runge-Kutta stage (Sec. 3.2);
+ *   - reductions: energy, convergence norm and observables are reduced on the
+ *     GPU (Sec. 3.3), here entirely on the device in FP64.
+ *
+ * Theories (Tab. 1; eq. (5) without demagnetisation):
+ *   "abelian_higgs" (aliases "Abelian Higgs", "Ginzburg-Landau", "GL", "AH"):
+ *       C = 4 components (psi_1, psi_2, A_1, A_2), u = e = 1, D = grad - iA,
+ *       e = 1/2 |D psi|^2 + 1/2 (d_1 A_2 - d_2 A_1)^2 + lambda/8 (1 - |psi|^2)^2.
+ *       params.f = {lambda [, courant]}.
+ *   "chiral_magnet" (aliases "Chiral magnet", "CM"):
+ *       C = 3 components (n_1, n_2, n_3), |n| = 1, bulk DMI d_k = e_k,
+ *       e = J/2 |grad n|^2 + D sum_k e_k.(n x d_k n) + K (1 - n_3^2) + B (1 - n_3).
+ *       params.f = {J, D, K, B [, courant]}.
+ *   params.i (optional) = {grad_mode}: SS_GRAD_EL (default) evaluates the
+ *   continuum Euler-Lagrange derivative with eq. (1)-(2); SS_GRAD_EXACT uses
+ *   h^-2 dE_h/dphi, the exact derivative of the discrete energy.
+ *
+ * Memory layout of every field array passed in or out: planar, component
+ * major, rows of x fastest, shape (C, Ny + 4, Nx + 4) including the halo,
+ * contiguous; element (c, j, i) of interior site (i, j) is at
+ * c * (Ny + 4) * (Nx + 4) + (j + 2) * (Nx + 4) + (i + 2). Element type is
+ * float (SS_F32) or double (SS_F64), the context's dtype.
+ *
+ * Ownership: every device buffer (fields, gradients, the workspace) belongs
+ * to the caller; the library never calls hipMalloc. The library owns the
+ * host-side context and the HIP graph and stream objects it creates;
+ * ss_destroy releases them. The workspace must stay valid and untouched by
+ * the caller between ss_create and ss_destroy.
+ *
+ * Streams: work is queued on the stream given to ss_create (NULL = the
+ * default stream). Calls that return host values synchronise that stream.
+ *
+ * Errors: functions return SS_OK (0), a positive warning, or a negative
+ * error code; ss_last_error() gives a thread-local message for the last
+ * failure. No exception crosses this boundary. A context is not thread-safe:
+ * use one context per host thread.
+ */
+#ifndef SS_H
+#define SS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SS_OK 0
+#define SS_NOT_CONVERGED 1
+#define SS_EINVAL (-1)
+#define SS_ETHEORY (-2)
+#define SS_ESHAPE (-3)
+#define SS_EHIP (-4)
+#define SS_ENONFINITE (-5)
+#define SS_ESTATE (-6)
+
+/* element types */
+#define SS_F32 0
+#define SS_F64 1
+
+/* theories */
+#define SS_THEORY_AH 0
+#define SS_THEORY_CM 1
+
+/* gradient forms */
+#define SS_GRAD_EL 0
+#define SS_GRAD_EXACT 1
+
+/* stop reasons reported by ss_minimise */
+#define SS_STOP_NONE 0
+#define SS_STOP_GRAD 1
+#define SS_STOP_STALL 2
+#define SS_STOP_MAXSTEPS 3
+#define SS_STOP_NONFINITE 4
+
+typedef struct ss_ctx ss_ctx;
+
+/* Theory parameters packed as float and int arrays (Sec. 3.1: theory-specific
+ * parameters are packed into integer and floating-point arrays). Pointers are
+ * host memory, read during the call only. */
+typedef struct {
+  const double* f;
+  int nf;
+  const int* i;
+  int ni;
+} ss_params;
+
+/* Result of a run of flow steps; all values refer to the field at the end. */
+typedef struct {
+  double energy;      /* E_h of the current field (FP64 reduction) */
+  double energy_prev; /* E_h compared against by the next arrest test */
+  double gnorm_inf;   /* max |G| over interior sites and components */
+  int64_t step;       /* RK4 steps completed since ss_set_field */
+  int64_t n_arrests;  /* arrests since ss_set_field */
+  int32_t arrested;   /* 1 if the last arrest test fired */
+  int32_t nonfinite;  /* number of non-finite values seen by the last test */
+} ss_step_info;
+
+/* Stop rule for ss_minimise. The first rule met ends the run:
+ *   gnorm_inf < grad_tol                                    (SS_STOP_GRAD)
+ *   window > 0, step >= window and
+ *   |E(step) - E(step - window)| <= rel_e_tol |E(step)|     (SS_STOP_STALL)
+ *   step >= max_steps                                        (SS_STOP_MAXSTEPS)
+ * graph_steps: flow steps per replayed HIP graph (0 = library default; an even
+ * number). window <= 128. */
+typedef struct {
+  double grad_tol;
+  double rel_e_tol;
+  int32_t window;
+  int32_t graph_steps;
+  int64_t max_steps;
+} ss_stop;
+
+typedef struct {
+  ss_step_info last; /* state at the stop */
+  int32_t reason;    /* SS_STOP_* */
+  int32_t converged; /* 1 for SS_STOP_GRAD or SS_STOP_STALL */
+} ss_min_info;
+
+/* Observables (FP64). Abelian Higgs: flux = h^2 sum B; n_rho = h^2 sum rho with
+ * rho = [B W + 2 (P1 Q2 - Q1 P2)] / (2 pi), D_k psi = P_k + i Q_k, W = 1 - |psi|^2;
+ * n_wind = phase winding of psi along the ring of outermost interior sites,
+ * counter-clockwise; bogo_r1 = h^2 sum |(P1 - Q2) + i (Q1 + P2)|^2,
+ * bogo_r2 = h^2 sum (B - W/2)^2. Chiral magnet: q_fd = h^2/(4 pi) sum
+ * n.(D1 n x D2 n); q_bl = Berg-Luescher solid-angle charge over all plaquettes
+ * of the padded lattice. Fields that do not apply are 0. */
+typedef struct {
+  double energy;
+  double flux;
+  double n_rho;
+  double n_wind;
+  double bogo_r1;
+  double bogo_r2;
+  double q_fd;
+  double q_bl;
+  double gnorm_inf;
+} ss_obs;
+
+/* Canonical theory id of a name or alias (Sec. 2.3 registry), or SS_ETHEORY. */
+int ss_theory_id(const char* name);
+
+/* Number of field components of a theory, or SS_ETHEORY. */
+int ss_components(const char* theory);
+
+/* Workspace bytes ss_create needs for this theory, grid and dtype. */
+int ss_workspace_bytes(const char* theory, int Nx, int Ny, int dtype, size_t* bytes);
+
+/* Create a context. Parameters are validated and resolved before any device
+ * work (Sec. 3.1). workspace: device memory of at least ss_workspace_bytes,
+ * 256-byte aligned. stream: a hipStream_t or NULL. Requires 8 <= Nx, Ny <=
+ * 65536 and h > 0. */
+int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype,
+              void* workspace, size_t ws_bytes, void* stream, ss_ctx** out);
+
+void ss_destroy(ss_ctx* ctx);
+
+/* Copy the initial field (device array of the context's dtype and the layout
+ * above; its halo holds the fixed boundary values) into the context, start
+ * from rest (phidot = 0, Sec. 3.2) and reset step and arrest counters. */
+int ss_set_field(ss_ctx* ctx, const void* field);
+
+/* Initial field from an analytic ansatz, computed on the device (the paper's
+ * "model-specific ansatz", Sec. 4.1), then the same reset as ss_set_field.
+ *   Abelian Higgs, kind SS_ANSATZ_VORTICES: n vortices at xy[2k], xy[2k+1]
+ *     (host array, lattice coordinates x_i = (i - (Nx-1)/2) h) with windings
+ *     w[k] (host array or NULL = all +1):
+ *       psi = prod_k tanh(r_k) exp(i w_k theta_k),
+ *       A   = sum_k w_k (1 - exp(-r_k^2)) / r_k^2 (-(y - y_k), x - x_k);
+ *     the halo holds the pure-gauge vacuum psi = exp(i sum w_k theta_k),
+ *     A = sum_k w_k grad theta_k.
+ *   Chiral magnet, kind SS_ANSATZ_SKYRMION: n = 1, xy = centre, shape = {R, gamma}:
+ *       n = (sin T cos(theta + gamma), sin T sin(theta + gamma), cos T),
+ *       T = 2 atan(R / r) (Belavin-Polyakov); halo n = e_3.
+ * Noise: if noise_amp > 0, every interior component gets noise_amp * (2u - 1),
+ * u the SplitMix64 counter draw of (seed, c, j, i) (same generator as the
+ * project's input module); the chiral magnet is renormalised afterwards.
+ * Synchronises. */
+#define SS_ANSATZ_VORTICES 0
+#define SS_ANSATZ_SKYRMION 1
+int ss_init_ansatz(ss_ctx* ctx, int kind, int n, const double* xy, const double* w, const double* shape,
+                   uint64_t seed, double noise_amp);
+
+/* Mean device time per launch of each of the passes, measured with HIP events
+ * on the context's stream over n_steps flow steps (the steps are real flow
+ * steps). ms[0..3] = stage passes P1..P4, ms[4] = whole step. Synchronises. */
+int ss_time_passes(ss_ctx* ctx, int n_steps, double* ms);
+
+/* Copy the current field and (if velocity != NULL) velocity to device arrays. */
+int ss_get_field(ss_ctx* ctx, void* field, void* velocity);
+
+/* E_h and gradient of a field: `field` (device, NULL = the current field).
+ * If grad != NULL it receives G (device array, layout above, zero halo): the
+ * gradient of the selected form; for the chiral magnet, at the normalised
+ * field and projected on the tangent plane. Does not change the flow state.
+ * Synchronises; energy and gnorm_inf (may be NULL) are host outputs. */
+int ss_energy_grad(ss_ctx* ctx, const void* field, void* grad, double* energy, double* gnorm_inf);
+
+/* n_steps arrested-Newton-flow steps, then the arrest test of the final field
+ * (so the state afterwards is that of eq. (4) applied after every step).
+ * If info != NULL the stream is synchronised and info filled. */
+int ss_flow_step(ss_ctx* ctx, int n_steps, ss_step_info* info);
+
+/* Flow until a stop rule holds, replaying a captured HIP graph of
+ * stop->graph_steps steps; each kernel skips its work once the device-side
+ * stop flag is set, so the field stops exactly at the first state meeting a
+ * rule. Returns SS_OK if converged, SS_NOT_CONVERGED at max_steps,
+ * SS_ENONFINITE if a non-finite value appeared. */
+int ss_minimise(ss_ctx* ctx, const ss_stop* stop, ss_min_info* info);
+
+/* Observables of the current field. Synchronises. */
+int ss_observables(ss_ctx* ctx, ss_obs* out);
+
+/* Read the device status into info (synchronises). */
+int ss_get_info(ss_ctx* ctx, ss_step_info* info);
+
+/* Text of a status code, and the calling thread's last error message. */
+const char* ss_status_string(int code);
+const char* ss_last_error(void);
+
+/* GL helper: lambda = 2 kappa^2 in units u = e = 1 (textbook relation). */
+double ss_gl_lambda_from_kappa(double kappa);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SS_H */

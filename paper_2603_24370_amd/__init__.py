@@ -1,0 +1,303 @@
+"""Python binding of libss, the MI355X soliton energy-minimisation library.
+
+Thin ctypes marshalling over the C ABI of ``include/ss.h``: the functions
+below carry the C names and arguments; PyTorch supplies device memory and the
+stream. All computation happens in the library's HIP kernels. There is no CPU
+fallback: if ``libss.so`` is missing or no GPU is present, calls raise.
+
+``Solver`` is a convenience holder of one context and its workspace tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libss.so")
+
+SS_OK, SS_NOT_CONVERGED = 0, 1
+SS_F32, SS_F64 = 0, 1
+SS_GRAD_EL, SS_GRAD_EXACT = 0, 1
+SS_THEORY_AH, SS_THEORY_CM = 0, 1
+SS_ANSATZ_VORTICES, SS_ANSATZ_SKYRMION = 0, 1
+STOP_REASONS = {0: "none", 1: "grad", 2: "stall", 3: "max_steps", 4: "nonfinite"}
+
+
+class ss_params(ctypes.Structure):
+    _fields_ = [("f", ctypes.POINTER(ctypes.c_double)), ("nf", ctypes.c_int),
+                ("i", ctypes.POINTER(ctypes.c_int)), ("ni", ctypes.c_int)]
+
+
+class ss_step_info(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_double), ("energy_prev", ctypes.c_double), ("gnorm_inf", ctypes.c_double),
+                ("step", ctypes.c_int64), ("n_arrests", ctypes.c_int64), ("arrested", ctypes.c_int32),
+                ("nonfinite", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ss_stop(ctypes.Structure):
+    _fields_ = [("grad_tol", ctypes.c_double), ("rel_e_tol", ctypes.c_double), ("window", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32), ("max_steps", ctypes.c_int64)]
+
+
+class ss_min_info(ctypes.Structure):
+    _fields_ = [("last", ss_step_info), ("reason", ctypes.c_int32), ("converged", ctypes.c_int32)]
+
+
+class ss_obs(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("energy", "flux", "n_rho", "n_wind", "bogo_r1", "bogo_r2", "q_fd", "q_bl", "gnorm_inf")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libss error {code}: {msg}")
+        self.code = code
+
+
+EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "ss_destroy", "ss_set_field",
+           "ss_init_ansatz", "ss_time_passes",
+           "ss_get_field", "ss_energy_grad", "ss_flow_step", "ss_minimise", "ss_observables", "ss_get_info",
+           "ss_status_string", "ss_last_error", "ss_gl_lambda_from_kappa"]
+
+_lib = None
+
+
+def lib():
+    """Load libss.so (built by ``paper_2603_24370_amd.build``); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_24370_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, cp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_char_p
+    L.ss_theory_id.argtypes = [cp]
+    L.ss_components.argtypes = [cp]
+    L.ss_workspace_bytes.argtypes = [cp, i, i, i, ctypes.POINTER(ctypes.c_size_t)]
+    L.ss_create.argtypes = [cp, i, i, d, ctypes.POINTER(ss_params), i, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.ss_destroy.argtypes = [vp]
+    L.ss_destroy.restype = None
+    L.ss_set_field.argtypes = [vp, vp]
+    L.ss_get_field.argtypes = [vp, vp, vp]
+    dp = ctypes.POINTER(d)
+    L.ss_init_ansatz.argtypes = [vp, i, i, dp, dp, dp, ctypes.c_uint64, d]
+    L.ss_time_passes.argtypes = [vp, i, dp]
+    L.ss_energy_grad.argtypes = [vp, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d)]
+    L.ss_flow_step.argtypes = [vp, i, ctypes.POINTER(ss_step_info)]
+    L.ss_minimise.argtypes = [vp, ctypes.POINTER(ss_stop), ctypes.POINTER(ss_min_info)]
+    L.ss_observables.argtypes = [vp, ctypes.POINTER(ss_obs)]
+    L.ss_get_info.argtypes = [vp, ctypes.POINTER(ss_step_info)]
+    L.ss_status_string.argtypes = [i]
+    L.ss_status_string.restype = cp
+    L.ss_last_error.argtypes = []
+    L.ss_last_error.restype = cp
+    L.ss_gl_lambda_from_kappa.argtypes = [d]
+    L.ss_gl_lambda_from_kappa.restype = d
+    _lib = L
+    return L
+
+
+def _check(rc, allow=(SS_OK,)):
+    if rc in allow:
+        return rc
+    if rc < 0 or rc not in (SS_OK, SS_NOT_CONVERGED):
+        raise SSError(rc, lib().ss_last_error().decode())
+    return rc
+
+
+def _b(s: str) -> bytes:
+    return s.encode() if isinstance(s, str) else s
+
+
+# ----------------------------------------------------------- C-ABI mirrors
+
+def ss_theory_id(name: str) -> int:
+    return lib().ss_theory_id(_b(name))
+
+
+def ss_components(theory: str) -> int:
+    return _check_nonneg(lib().ss_components(_b(theory)))
+
+
+def _check_nonneg(rc):
+    if rc < 0:
+        raise SSError(rc, lib().ss_last_error().decode() or "error")
+    return rc
+
+
+def ss_workspace_bytes(theory: str, Nx: int, Ny: int, dtype: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().ss_workspace_bytes(_b(theory), Nx, Ny, dtype, ctypes.byref(n)))
+    return n.value
+
+
+def ss_create(theory, Nx, Ny, h, f_params, i_params, dtype, workspace_ptr, ws_bytes, stream_ptr):
+    fa = (ctypes.c_double * max(1, len(f_params)))(*f_params)
+    ia = (ctypes.c_int * max(1, len(i_params)))(*i_params)
+    p = ss_params(fa, len(f_params), ia, len(i_params))
+    out = ctypes.c_void_p(0)
+    _check(lib().ss_create(_b(theory), Nx, Ny, h, ctypes.byref(p), dtype, ctypes.c_void_p(workspace_ptr), ws_bytes,
+                           ctypes.c_void_p(stream_ptr), ctypes.byref(out)))
+    return out
+
+
+def ss_destroy(ctx):
+    lib().ss_destroy(ctx)
+
+
+def ss_set_field(ctx, field_ptr):
+    _check(lib().ss_set_field(ctx, ctypes.c_void_p(field_ptr)))
+
+
+def _darr(x):
+    if x is None:
+        return None
+    vals = [float(v) for v in x]
+    return (ctypes.c_double * max(1, len(vals)))(*vals)
+
+
+def ss_init_ansatz(ctx, kind, centres, windings=None, shape=None, seed=0, noise_amp=0.0):
+    flat = [float(v) for p in centres for v in p]
+    n = len(flat) // 2
+    _check(lib().ss_init_ansatz(ctx, kind, n, _darr(flat), _darr(windings), _darr(shape), int(seed),
+                                float(noise_amp)))
+
+
+def ss_time_passes(ctx, n_steps):
+    ms = (ctypes.c_double * 5)()
+    _check(lib().ss_time_passes(ctx, int(n_steps), ms))
+    return list(ms)
+
+
+def ss_get_field(ctx, field_ptr, vel_ptr=None):
+    _check(lib().ss_get_field(ctx, ctypes.c_void_p(field_ptr), ctypes.c_void_p(vel_ptr or 0)))
+
+
+def ss_energy_grad(ctx, field_ptr=None, grad_ptr=None):
+    e, g = ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib().ss_energy_grad(ctx, ctypes.c_void_p(field_ptr or 0), ctypes.c_void_p(grad_ptr or 0),
+                                ctypes.byref(e), ctypes.byref(g)))
+    return e.value, g.value
+
+
+def ss_flow_step(ctx, n_steps, want_info=True):
+    info = ss_step_info()
+    _check(lib().ss_flow_step(ctx, int(n_steps), ctypes.byref(info) if want_info else None))
+    return info.as_dict() if want_info else None
+
+
+def ss_minimise(ctx, grad_tol=0.0, rel_e_tol=0.0, window=0, max_steps=100000, graph_steps=0):
+    s = ss_stop(grad_tol, rel_e_tol, window, graph_steps, max_steps)
+    info = ss_min_info()
+    rc = _check(lib().ss_minimise(ctx, ctypes.byref(s), ctypes.byref(info)), allow=(SS_OK, SS_NOT_CONVERGED))
+    d = info.last.as_dict()
+    d.update(reason=STOP_REASONS.get(info.reason, str(info.reason)), converged=bool(info.converged), rc=rc)
+    return d
+
+
+def ss_observables(ctx):
+    o = ss_obs()
+    _check(lib().ss_observables(ctx, ctypes.byref(o)))
+    return o.as_dict()
+
+
+def ss_get_info(ctx):
+    info = ss_step_info()
+    _check(lib().ss_get_info(ctx, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def ss_gl_lambda_from_kappa(kappa: float) -> float:
+    return lib().ss_gl_lambda_from_kappa(kappa)
+
+
+# ------------------------------------------------------------ convenience
+
+class Solver:
+    """One library context plus its torch-allocated workspace on a CUDA/HIP device."""
+
+    def __init__(self, theory, Nx, Ny, h, params, dtype="f32", grad_mode=SS_GRAD_EL, courant=None,
+                 device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libss needs a HIP GPU; none is available")
+        self.torch = torch
+        self.theory, self.Nx, self.Ny, self.h = theory, int(Nx), int(Ny), float(h)
+        self.dtype_code = SS_F32 if dtype in ("f32", torch.float32) else SS_F64
+        self.tdtype = torch.float32 if self.dtype_code == SS_F32 else torch.float64
+        self.C = ss_components(theory)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = ss_workspace_bytes(theory, self.Nx, self.Ny, self.dtype_code)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        f = list(params) + ([courant] if courant is not None else [])
+        self.ctx = ss_create(theory, self.Nx, self.Ny, self.h, f, [grad_mode], self.dtype_code, self._ws_ptr,
+                             nbytes, self.stream.cuda_stream)
+
+    @property
+    def shape(self):
+        return (self.C, self.Ny + 4, self.Nx + 4)
+
+    def _dev(self, x):
+        t = self.torch.as_tensor(x)
+        return t.to(device=self.device, dtype=self.tdtype).contiguous()
+
+    def init_vortices(self, centres, windings=None, seed=0, noise_amp=0.0):
+        ss_init_ansatz(self.ctx, SS_ANSATZ_VORTICES, centres, windings, None, seed, noise_amp)
+
+    def init_skyrmion(self, R=2.0, gamma=-1.5707963267948966, centre=(0.0, 0.0), seed=0, noise_amp=0.0):
+        ss_init_ansatz(self.ctx, SS_ANSATZ_SKYRMION, [centre], None, [R, gamma], seed, noise_amp)
+
+    def time_passes(self, n_steps):
+        return ss_time_passes(self.ctx, n_steps)
+
+    def set_field(self, field):
+        t = self._dev(field)
+        if tuple(t.shape) != self.shape:
+            raise ValueError(f"field shape {tuple(t.shape)} != {self.shape}")
+        ss_set_field(self.ctx, t.data_ptr())
+        self.stream.synchronize()
+
+    def get_field(self, velocity=False):
+        f = self.torch.empty(self.shape, dtype=self.tdtype, device=self.device)
+        v = self.torch.empty(self.shape, dtype=self.tdtype, device=self.device) if velocity else None
+        ss_get_field(self.ctx, f.data_ptr(), v.data_ptr() if velocity else None)
+        return (f, v) if velocity else f
+
+    def energy_grad(self, field=None, want_grad=True):
+        src = None if field is None else self._dev(field)
+        g = self.torch.empty(self.shape, dtype=self.tdtype, device=self.device) if want_grad else None
+        E, gmax = ss_energy_grad(self.ctx, src.data_ptr() if src is not None else None,
+                                 g.data_ptr() if g is not None else None)
+        return E, gmax, g
+
+    def flow_step(self, n=1, want_info=True):
+        return ss_flow_step(self.ctx, n, want_info)
+
+    def minimise(self, **kw):
+        return ss_minimise(self.ctx, **kw)
+
+    def observables(self):
+        return ss_observables(self.ctx)
+
+    def info(self):
+        return ss_get_info(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            ss_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

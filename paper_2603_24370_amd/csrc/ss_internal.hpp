@@ -1,0 +1,123 @@
+// Internal definitions shared by the host API and the HIP kernels of libss.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ss {
+
+constexpr int kHalo = 2;          // Sec. 3.1: default halo width two
+constexpr int kHistLen = 128;     // ring of energies for the stall rule
+constexpr int kMaxComp = 4;
+
+// Device-resident state of one flow (written only by kernels, read by the host
+// through a stream-ordered copy).
+struct DevStatus {
+  double E;          // E_h of the field at the last arrest test
+  double E_prev;     // energy the next arrest test compares with
+  double gmax;       // max |G| at the last arrest test
+  double eval_E;     // result slots of ss_energy_grad
+  double eval_gmax;
+  double grad_tol;   // stop rules (used when minimise != 0)
+  double rel_e_tol;
+  long long max_steps;
+  long long step;        // RK4 steps started since set_field
+  long long n_arrests;
+  int arrest;            // 1 if the last arrest test fired
+  int done;              // stop reason once a stop rule held (SS_STOP_*), else 0
+  int nonfinite;         // non-finite count of the last test
+  int window;
+  int minimise;          // 1: the arrest pass applies the stop rules
+  unsigned counter;      // last-block counter of the arrest pass
+  unsigned counter_obs;  // last-block counter of the observable passes
+  int pad_;
+  double hist[kHistLen]; // E at step s is kept at hist[s % kHistLen]
+  double obs[16];        // observable sums (see ss_api)
+};
+
+// Field buffers of one context, in the device layout: component planes of
+// (Ny + 4) rows of `pitch` elements; element (c, j, i) at c*plane + (j+2)*pitch + (i+2).
+template <class T>
+struct Bufs {
+  T* phi[2];   // ping-pong field
+  T* vel[2];   // ping-pong fictitious velocity
+  T* a1;       // stage-1 acceleration
+  T* a2;       // stage-2 acceleration
+  T* q;        // a1 + 2 a2 + 2 a3
+  long pitch;
+  long plane;
+  int Nx, Ny;
+};
+
+// Theory constants packed for the kernels.
+struct Coeffs {
+  double h, dt;
+  double p[4];  // AH: {lambda}; CM: {J, D, K, B}
+};
+
+// Passes of one RK4 step and the single-evaluation variants.
+enum Pass : int {
+  kP1 = 0,     // stage 1: a1 = -G(phi), energy, arrest test and stop rules
+  kP2 = 1,     // stage 2: a2 = -G(phi + dt/2 v)
+  kP3 = 2,     // stage 3: q  = a1 + 2 a2 + 2 a3, a3 = -G(phi + dt/2 v + dt^2/4 a1)
+  kP4 = 3,     // stage 4: a4 = -G(phi + dt v + dt^2/2 a2); phi', v'
+  kEval = 4,   // G and E of a given field; flow state untouched
+  kCheck = 5,  // arrest test of the current field only (after a run of steps)
+};
+
+// Map a launched workgroup id to a tile so that the workgroups one XCD receives
+// (ids congruent mod 8 go to the same XCD) cover a contiguous range of tiles
+// and share their halos in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nlaunch) {
+  const int per = nlaunch >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+__device__ __forceinline__ int wave_isum(int x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Workgroup reduction of (sum, max, count) in a fixed order; the result is valid
+// in thread 0. `red` needs 3 * (blockDim/64) doubles of LDS.
+template <int NT>
+__device__ __forceinline__ void block_reduce3(double& s, double& m, int& n, double* red) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63;
+  const int w = (threadIdx.y * blockDim.x + threadIdx.x) >> 6;
+  s = wave_sum(s);
+  m = wave_max(m);
+  n = wave_isum(n);
+  if (lane == 0) {
+    red[w] = s;
+    red[NW + w] = m;
+    red[2 * NW + w] = (double)n;
+  }
+  __syncthreads();
+  if (w == 0 && lane == 0) {
+    double ss = 0.0, mm = 0.0, nn = 0.0;
+    for (int k = 0; k < NW; ++k) {
+      ss += red[k];
+      mm = fmax(mm, red[NW + k]);
+      nn += red[2 * NW + k];
+    }
+    s = ss;
+    m = mm;
+    n = (int)nn;
+  }
+}
+
+}  // namespace ss

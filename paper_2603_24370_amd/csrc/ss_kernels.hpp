@@ -1,0 +1,617 @@
+// HIP kernels of the arrested-Newton-flow hot path (gfx950).
+//
+// One RK4 step (eq. (3), classical RK4 on (phi, phidot), dt = C h) is four
+// launches of stage_pass<..., P1..P4>. Each launch stages the stage point
+// S = phi + c_v v + c_a a of a (TX + 4) x (TY + 4) tile (halo 2, Sec. 3.1) in
+// LDS, evaluates the Euler-Lagrange gradient with eq. (1)-(2) from LDS, and
+// writes only what the next pass needs:
+//   P1: S = phi                                  -> a1 = -G(S), E_h(phi), arrest test
+//   P2: S = phi + dt/2 v                         -> a2 = -G(S)
+//   P3: S = phi + dt/2 v + dt^2/4 a1             -> q  = a1 + 2 a2 + 2 a3
+//   P4: S = phi + dt v + dt^2/2 a2               -> phi' = phi + dt v + dt^2/12 (q + a1)
+//                                                   v'   = v + dt/6 (q + a4)
+// (v is replaced by 0 once the arrest test of P1 fired, eq. (4)). For the
+// chiral magnet every stage point is put back on the unit sphere and G is
+// projected on its tangent plane; phi' is renormalised and v' projected.
+// P1 also reduces E_h (FP64 from the stored values), max |G| and a non-finite
+// count; its last workgroup sums the per-workgroup partials in a fixed order,
+// applies the arrest test E > E_prev (strict) and the stop rules, and
+// advances the step counter, all on the device.
+#pragma once
+
+#include "ss_internal.hpp"
+#include "ss_theory.hpp"
+
+namespace ss {
+
+template <int TH>
+struct NComp;
+template <>
+struct NComp<0> { static constexpr int value = 4; };
+template <>
+struct NComp<1> { static constexpr int value = 3; };
+
+// Derivatives of one LDS plane at (lx, ly) by eq. (1) and eq. (2); the mixed
+// derivative applies eq. (1) along x to eq. (1) along y.
+template <class T, int LX, bool MIXED>
+__device__ __forceinline__ Jet<T> lds_jet(const T* __restrict__ s, int lx, int ly, T c1, T c2) {
+  const T* r = s + ly * LX + lx;
+  Jet<T> J;
+  const T f0 = r[0];
+  const T xm2 = r[-2], xm1 = r[-1], xp1 = r[1], xp2 = r[2];
+  const T ym2 = r[-2 * LX], ym1 = r[-LX], yp1 = r[LX], yp2 = r[2 * LX];
+  J.f = f0;
+  J.x = c1 * ((xm2 - xp2) + T(8) * (xp1 - xm1));
+  J.y = c1 * ((ym2 - yp2) + T(8) * (yp1 - ym1));
+  J.xx = c2 * (T(16) * (xp1 + xm1) - (xp2 + xm2) - T(30) * f0);
+  J.yy = c2 * (T(16) * (yp1 + ym1) - (yp2 + ym2) - T(30) * f0);
+  if (MIXED) {
+    T acc = T(0);
+    const T w[5] = {T(1), T(-8), T(0), T(8), T(-1)};
+#pragma unroll
+    for (int n = -2; n <= 2; ++n) {
+      if (n == 0) continue;
+      const T* rr = r + n * LX;
+      const T dxr = (rr[-2] - rr[2]) + T(8) * (rr[1] - rr[-1]);
+      acc += w[n + 2] * dxr;
+    }
+    J.xy = c1 * c1 * acc;
+  } else {
+    J.xy = T(0);
+  }
+  return J;
+}
+
+// First derivatives only, in FP64 from the stored values (energy density).
+template <class T, int LX>
+__device__ __forceinline__ Jet<double> lds_jet64(const T* __restrict__ s, int lx, int ly, double c1) {
+  const T* r = s + ly * LX + lx;
+  Jet<double> J;
+  J.f = (double)r[0];
+  J.x = c1 * (((double)r[-2] - (double)r[2]) + 8.0 * ((double)r[1] - (double)r[-1]));
+  J.y = c1 * (((double)r[-2 * LX] - (double)r[2 * LX]) + 8.0 * ((double)r[LX] - (double)r[-LX]));
+  J.xx = J.yy = J.xy = 0.0;
+  return J;
+}
+
+template <class T>
+struct PassArgs {
+  Bufs<T> B;
+  Coeffs cf;
+  DevStatus* st;
+  double* partials;
+  const T* src;  // kEval: field to evaluate (nullptr = current field)
+  long src_pitch, src_plane;
+  T* out;        // kEval: gradient output (nullptr = none)
+  long out_pitch, out_plane;
+  int nlaunch;   // launched workgroups (a multiple of 8)
+  int ntx, nty;  // tiles along x and y
+};
+
+template <class T, int TH, int PASS, int TX, int TY, int RY>
+__global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
+  constexpr int C = NComp<TH>::value;
+  constexpr int LX = TX + 4, LY = TY + 4;
+  constexpr int NT = TX * (TY / RY);
+  constexpr bool REDUCE = (PASS == kP1 || PASS == kEval || PASS == kCheck);
+  constexpr bool ENERGY_PASS = REDUCE;
+  __shared__ T s[C][LY * LX];
+  __shared__ double red[3 * (NT / 64)];
+
+  DevStatus* __restrict__ st = a.st;
+  if (PASS != kEval && st->done) return;
+
+  const int Nx = a.B.Nx, Ny = a.B.Ny;
+  const long long step = st->step;
+  const int cur = (PASS == kP2 || PASS == kP3 || PASS == kP4) ? int((step - 1) & 1) : int(step & 1);
+  const T* __restrict__ ph = a.B.phi[cur];
+  long pitch = a.B.pitch, plane = a.B.plane;
+  if (PASS == kEval && a.src != nullptr) {
+    ph = a.src;
+    pitch = a.src_pitch;
+    plane = a.src_plane;
+  }
+  const T* __restrict__ vv = a.B.vel[cur];
+  const T* __restrict__ aa = (PASS == kP3) ? a.B.a1 : a.B.a2;
+  const bool arrest = (PASS == kP2 || PASS == kP3 || PASS == kP4) ? (st->arrest != 0) : false;
+  const T dt = (T)a.cf.dt;
+  T cv = T(0), ca = T(0);
+  if (PASS == kP2) cv = T(0.5) * dt;
+  if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
+  if (PASS == kP4) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (arrest) cv = T(0);
+
+  const int tid = threadIdx.y * TX + threadIdx.x;
+  const int t = xcd_tile(blockIdx.x, a.nlaunch);
+  const bool active = t < a.ntx * a.nty;
+  const int tyi = active ? t / a.ntx : 0;
+  const int x0 = (t - tyi * a.ntx) * TX, y0 = tyi * TY;
+
+  // ---- stage the tile + halo-2 of the stage point in LDS
+  if (active) {
+    for (int idx = tid; idx < LX * LY; idx += NT) {
+      const int ly = idx / LX, lx = idx - ly * LX;
+      const int gi = x0 - 2 + lx, gj = y0 - 2 + ly;
+      const bool inpad = (gi <= Nx + 1) && (gj <= Ny + 1);
+      const bool inner = (gi >= 0) && (gi < Nx) && (gj >= 0) && (gj < Ny);
+      const long off = (long)(gj + 2) * pitch + (gi + 2);
+      T val[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        T x = T(0);
+        if (inpad) {
+          x = ph[c * plane + off];
+          if ((PASS == kP2 || PASS == kP3 || PASS == kP4) && inner) {
+            x += cv * vv[c * plane + off];
+            if (PASS == kP3 || PASS == kP4) x += ca * aa[c * plane + off];
+          }
+        }
+        val[c] = x;
+      }
+      if (TH == 1 && (PASS == kP2 || PASS == kP3 || PASS == kP4) && inner) {
+        const T inv = T(1) / sqrt(val[0] * val[0] + val[1] * val[1] + val[2] * val[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) val[c] *= inv;
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) s[c][idx] = val[c];
+    }
+  }
+  __syncthreads();
+
+  const double h = a.cf.h;
+  const T c1 = T(1.0 / (12.0 * h)), c2 = T(1.0 / (12.0 * h * h));
+  double e_acc = 0.0, g_acc = 0.0;
+  int nf = 0;
+  const int lx = threadIdx.x + 2;
+  const int gi = x0 + threadIdx.x;
+
+  // ---- E_h density in FP64 from the stored (unnormalised) values
+  if (ENERGY_PASS && active) {
+    const double d1 = 1.0 / (12.0 * h);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int ly = threadIdx.y * RY + r + 2;
+      const int gj = y0 + ly - 2;
+      if (gi < Nx && gj < Ny) {
+        Jet<double> J[4];
+#pragma unroll
+        for (int c = 0; c < C; ++c) J[c] = lds_jet64<T, LX>(s[c], lx, ly, d1);
+        double e;
+        if (TH == 0) e = ah_density<double>(J, a.cf.p[0]);
+        else e = cm_density<double>(J, a.cf.p[0], a.cf.p[1], a.cf.p[2], a.cf.p[3]);
+        e_acc += e;
+        if (!isfinite(e)) ++nf;
+      }
+    }
+  }
+  if (TH == 1 && ENERGY_PASS) {
+    // the flow evaluates G at the normalised field
+    __syncthreads();
+    if (active) {
+      for (int idx = tid; idx < LX * LY; idx += NT) {
+        const int ly = idx / LX, lx2 = idx - ly * LX;
+        const int gi2 = x0 - 2 + lx2, gj2 = y0 - 2 + ly;
+        if (gi2 >= 0 && gi2 < Nx && gj2 >= 0 && gj2 < Ny) {
+          const T n0 = s[0][idx], n1 = s[1][idx], n2 = s[2][idx];
+          const T inv = T(1) / sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+          s[0][idx] = n0 * inv;
+          s[1][idx] = n1 * inv;
+          s[2][idx] = n2 * inv;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- gradient and pass epilogue
+  if (active) {
+    T* __restrict__ phn = a.B.phi[cur ^ 1];
+    T* __restrict__ vn = a.B.vel[cur ^ 1];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int ly = threadIdx.y * RY + r + 2;
+      const int gj = y0 + ly - 2;
+      if (gi >= Nx || gj >= Ny) continue;
+      Jet<T> J[4];
+#pragma unroll
+      for (int c = 0; c < C; ++c) J[c] = lds_jet<T, LX, TH == 0>(s[c], lx, ly, c1, c2);
+      T G[4];
+      if (TH == 0) {
+        ah_el_gradient<T>(J, (T)a.cf.p[0], G);
+      } else {
+        cm_el_gradient<T>(J, (T)a.cf.p[0], (T)a.cf.p[1], (T)a.cf.p[2], (T)a.cf.p[3], G);
+        const T gn = G[0] * J[0].f + G[1] * J[1].f + G[2] * J[2].f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G[c] -= gn * J[c].f;
+      }
+      const long off = (long)(gj + 2) * a.B.pitch + (gi + 2);
+      if (REDUCE) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const double g = fabs((double)G[c]);
+          g_acc = fmax(g_acc, g);
+          if (!isfinite(G[c])) ++nf;
+        }
+      }
+      if (PASS == kP1) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) a.B.a1[c * a.B.plane + off] = -G[c];
+      } else if (PASS == kEval) {
+        if (a.out != nullptr) {
+          const long o = (long)(gj + 2) * a.out_pitch + (gi + 2);
+#pragma unroll
+          for (int c = 0; c < C; ++c) a.out[c * a.out_plane + o] = G[c];
+        }
+      } else if (PASS == kP2) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) a.B.a2[c * a.B.plane + off] = -G[c];
+      } else if (PASS == kP3) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const long k = c * a.B.plane + off;
+          a.B.q[k] = a.B.a1[k] + T(2) * a.B.a2[k] - T(2) * G[c];
+        }
+      } else if (PASS == kP4) {
+        T pn[4], vnew[4];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const long k = c * a.B.plane + off;
+          const T v0 = arrest ? T(0) : vv[k];
+          const T qq = a.B.q[k];
+          pn[c] = ph[k] + dt * v0 + (dt * dt / T(12)) * (qq + a.B.a1[k]);
+          vnew[c] = v0 + (dt / T(6)) * (qq - G[c]);
+        }
+        if (TH == 1) {
+          const T inv = T(1) / sqrt(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) pn[c] *= inv;
+          const T vd = vnew[0] * pn[0] + vnew[1] * pn[1] + vnew[2] * pn[2];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) vnew[c] -= vd * pn[c];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const long k = c * a.B.plane + off;
+          phn[k] = pn[c];
+          vn[k] = vnew[c];
+        }
+      }
+    }
+  }
+
+  if (!REDUCE) return;
+
+  // ---- two-level FP64 reduction with a deterministic last-workgroup finalise
+  block_reduce3<NT>(e_acc, g_acc, nf, red);
+  __shared__ int is_last;
+  if (tid == 0) {
+    double* p = a.partials + 4 * (long)blockIdx.x;
+    p[0] = e_acc;
+    p[1] = g_acc;
+    p[2] = (double)nf;
+    __threadfence();
+    const unsigned prev = atomicAdd(&st->counter, 1u);
+    is_last = (prev == (unsigned)(a.nlaunch - 1));
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double se = 0.0, sg = 0.0;
+  int sn = 0;
+  for (int k = tid; k < a.nlaunch; k += NT) {
+    const double* p = a.partials + 4 * (long)k;
+    se += __builtin_nontemporal_load(p);
+    sg = fmax(sg, __builtin_nontemporal_load(p + 1));
+    sn += (int)__builtin_nontemporal_load(p + 2);
+  }
+  __syncthreads();
+  block_reduce3<NT>(se, sg, sn, red);
+  if (tid == 0) {
+    const double E = h * h * se;
+    st->counter = 0u;
+    if (PASS == kEval) {
+      st->eval_E = E;
+      st->eval_gmax = sg;
+      st->nonfinite = sn;
+    } else {
+      const int arr = (E > st->E_prev) ? 1 : 0;
+      st->arrest = arr;
+      if (arr) st->n_arrests += 1;
+      st->E_prev = E;
+      st->E = E;
+      st->gmax = sg;
+      st->nonfinite = sn;
+      const long long s0 = st->step;
+      st->hist[s0 % kHistLen] = E;
+      int done = 0;
+      if (sn > 0) {
+        done = 4;
+      } else if (st->minimise) {
+        const int W = st->window;
+        if (sg < st->grad_tol) done = 1;
+        else if (W > 0 && s0 >= W && fabs(E - st->hist[(s0 - W) % kHistLen]) <= st->rel_e_tol * fabs(E)) done = 2;
+        else if (s0 >= st->max_steps) done = 3;
+      }
+      if (done) st->done = done;
+      else if (PASS == kP1) st->step = s0 + 1;
+    }
+  }
+}
+
+// Zero the velocity of the current field if the last arrest test fired.
+template <class T>
+__global__ void apply_arrest(Bufs<T> B, const DevStatus* __restrict__ st, int C) {
+  if (!st->arrest) return;
+  const int cur = int(st->step & 1);
+  const long n = (long)C * B.plane;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+    B.vel[cur][k] = T(0);
+}
+
+// Reset the stop flag and load the stop rules before a run of steps.
+__global__ void arm_status(DevStatus* st, int minimise, double grad_tol, double rel_e_tol, int window,
+                           long long max_steps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->done = 0;
+    st->minimise = minimise;
+    st->grad_tol = grad_tol;
+    st->rel_e_tol = rel_e_tol;
+    st->window = window;
+    st->max_steps = max_steps;
+  }
+}
+
+// ---------------------------------------------------------------- observables
+// Sums over interior sites (FP64 from the stored values, first derivatives by
+// eq. (1)), two-level reduction into st->obs[0..4]:
+//   AH: E density, B, rho = [B W + 2 (P1 Q2 - Q1 P2)]/(2 pi), |r1|^2, r2^2
+//   CM: E density, n.(d_x n x d_y n)
+template <int N, int NT>
+__device__ __forceinline__ void reduce_n_to(double (&v)[N], double* partials, unsigned* counter,
+                                            int nlaunch, double* dst) {
+  constexpr int NW = NT / 64;
+  __shared__ double red[N * NW];
+  __shared__ int last;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double x = wave_sum(v[k]);
+    if (lane == 0) red[k * NW + w] = x;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int k = 0; k < N; ++k) {
+      double s = 0.0;
+      for (int j = 0; j < NW; ++j) s += red[k * NW + j];
+      partials[(long)blockIdx.x * N + k] = s;
+    }
+    __threadfence();
+    last = (atomicAdd(counter, 1u) == (unsigned)(nlaunch - 1));
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double acc[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) acc[k] = 0.0;
+  for (int b = tid; b < nlaunch; b += NT)
+#pragma unroll
+    for (int k = 0; k < N; ++k) acc[k] += __builtin_nontemporal_load(partials + (long)b * N + k);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double x = wave_sum(acc[k]);
+    if (lane == 0) red[k * NW + w] = x;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int k = 0; k < N; ++k) {
+      double s = 0.0;
+      for (int j = 0; j < NW; ++j) s += red[k * NW + j];
+      dst[k] = s;
+    }
+    *counter = 0u;
+  }
+}
+
+template <class T, int TH>
+__global__ void __launch_bounds__(256) obs_sites(Bufs<T> B, Coeffs cf, DevStatus* st, double* partials,
+                                                 int nlaunch) {
+  const int cur = int(st->step & 1);
+  const T* __restrict__ ph = B.phi[cur];
+  const long nsite = (long)B.Nx * B.Ny;
+  const double c1 = 1.0 / (12.0 * cf.h);
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const double inv2pi = 0.15915494309189533577;
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < nsite; k += (long)gridDim.x * 256L) {
+    const int j = (int)(k / B.Nx), i = (int)(k - (long)j * B.Nx);
+    const long off = (long)(j + 2) * B.pitch + (i + 2);
+    double f[4], dx[4], dy[4];
+    for (int c = 0; c < (TH == 0 ? 4 : 3); ++c) {
+      const T* p = ph + c * B.plane + off;
+      f[c] = p[0];
+      dx[c] = c1 * (((double)p[-2] - (double)p[2]) + 8.0 * ((double)p[1] - (double)p[-1]));
+      dy[c] = c1 * (((double)p[-2 * B.pitch] - (double)p[2 * B.pitch]) +
+                    8.0 * ((double)p[B.pitch] - (double)p[-B.pitch]));
+    }
+    if (TH == 0) {
+      const double p = f[0], q = f[1], ax = f[2], ay = f[3];
+      const double P1 = dx[0] + ax * q, Q1 = dx[1] - ax * p, P2 = dy[0] + ay * q, Q2 = dy[1] - ay * p;
+      const double Bf = dx[3] - dy[2], W = 1.0 - (p * p + q * q);
+      v[0] += 0.5 * (P1 * P1 + Q1 * Q1 + P2 * P2 + Q2 * Q2) + 0.5 * Bf * Bf + 0.125 * cf.p[0] * W * W;
+      v[1] += Bf;
+      v[2] += (Bf * W + 2.0 * (P1 * Q2 - Q1 * P2)) * inv2pi;
+      const double r1r = P1 - Q2, r1i = Q1 + P2, r2 = Bf - 0.5 * W;
+      v[3] += r1r * r1r + r1i * r1i;
+      v[4] += r2 * r2;
+    } else {
+      const double cx = dy[2], cy = -dx[2], cz = dx[1] - dy[0];
+      double ex = 0.0;
+      for (int c = 0; c < 3; ++c) ex += dx[c] * dx[c] + dy[c] * dy[c];
+      v[0] += 0.5 * cf.p[0] * ex - cf.p[1] * (f[0] * cx + f[1] * cy + f[2] * cz) + cf.p[2] * (1.0 - f[2] * f[2]) +
+              cf.p[3] * (1.0 - f[2]);
+      // n . (d_x n x d_y n)
+      const double tx = dx[1] * dy[2] - dx[2] * dy[1], ty = dx[2] * dy[0] - dx[0] * dy[2],
+                   tz = dx[0] * dy[1] - dx[1] * dy[0];
+      v[1] += f[0] * tx + f[1] * ty + f[2] * tz;
+    }
+  }
+  reduce_n_to<5, 256>(v, partials, &st->counter_obs, nlaunch, st->obs);
+}
+
+// Berg-Luescher charge: every plaquette (i, j) .. (i+1, j+1) of the padded
+// lattice, split into triangles (a, b, c) and (a, c, d), each contributing its
+// signed solid angle 2 atan2(a.(b x c), 1 + a.b + b.c + c.a). Sum into st->obs[5].
+template <class T>
+__global__ void __launch_bounds__(256) obs_berg_luscher(Bufs<T> B, DevStatus* st, double* partials, int nlaunch) {
+  const int cur = int(st->step & 1);
+  const T* __restrict__ ph = B.phi[cur];
+  const int PW = B.Nx + 3, PH = B.Ny + 3;  // plaquettes per row / column
+  double v[1] = {0.0};
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < (long)PW * PH; k += (long)gridDim.x * 256L) {
+    const int j = (int)(k / PW), i = (int)(k - (long)j * PW);  // padded indices of corner a
+    double n[4][3];
+    const int cj[4] = {j, j, j + 1, j + 1}, ci[4] = {i, i + 1, i + 1, i};
+    for (int q = 0; q < 4; ++q)
+      for (int c = 0; c < 3; ++c) n[q][c] = (double)ph[c * B.plane + (long)cj[q] * B.pitch + ci[q]];
+    const int tri[2][3] = {{0, 1, 2}, {0, 2, 3}};
+    for (int t = 0; t < 2; ++t) {
+      const double* A = n[tri[t][0]];
+      const double* Bv = n[tri[t][1]];
+      const double* Cv = n[tri[t][2]];
+      const double bx = Bv[1] * Cv[2] - Bv[2] * Cv[1], by = Bv[2] * Cv[0] - Bv[0] * Cv[2],
+                   bz = Bv[0] * Cv[1] - Bv[1] * Cv[0];
+      const double num = A[0] * bx + A[1] * by + A[2] * bz;
+      const double den = 1.0 + (A[0] * Bv[0] + A[1] * Bv[1] + A[2] * Bv[2]) +
+                         (Bv[0] * Cv[0] + Bv[1] * Cv[1] + Bv[2] * Cv[2]) + (Cv[0] * A[0] + Cv[1] * A[1] + Cv[2] * A[2]);
+      v[0] += 2.0 * atan2(num, den);
+    }
+  }
+  reduce_n_to<1, 256>(v, partials, &st->counter_obs, nlaunch, st->obs + 5);
+}
+
+// Phase winding of psi along the ring of outermost interior sites (one
+// workgroup, fixed order), into st->obs[6] (in units of 2 pi).
+template <class T>
+__global__ void __launch_bounds__(256) obs_winding(Bufs<T> B, DevStatus* st) {
+  const int cur = int(st->step & 1);
+  const T* __restrict__ ph = B.phi[cur];
+  const int Nx = B.Nx, Ny = B.Ny;
+  const long L = 2L * (Nx - 1) + 2L * (Ny - 1);
+  auto site = [&](long k, int& j, int& i) {
+    if (k < Nx - 1) { j = 0; i = (int)k; return; }
+    k -= Nx - 1;
+    if (k < Ny - 1) { j = (int)k; i = Nx - 1; return; }
+    k -= Ny - 1;
+    if (k < Nx - 1) { j = Ny - 1; i = Nx - 1 - (int)k; return; }
+    k -= Nx - 1;
+    j = Ny - 1 - (int)k; i = 0;
+  };
+  double acc[1] = {0.0};
+  const double pi = 3.14159265358979323846;
+  for (long k = threadIdx.x; k < L; k += 256) {
+    int ja, ia, jb, ib;
+    site(k, ja, ia);
+    site((k + 1) % L, jb, ib);
+    const long oa = (long)(ja + 2) * B.pitch + ia + 2, ob = (long)(jb + 2) * B.pitch + ib + 2;
+    double d = atan2((double)ph[B.plane + ob], (double)ph[ob]) - atan2((double)ph[B.plane + oa], (double)ph[oa]);
+    if (d > pi) d -= 2.0 * pi;
+    if (d <= -pi) d += 2.0 * pi;
+    acc[0] += d;
+  }
+  __shared__ double red[4];
+  const double x = wave_sum(acc[0]);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) st->obs[6] = (red[0] + red[1] + red[2] + red[3]) / (2.0 * pi);
+}
+
+// --------------------------------------------------------------- state init
+// SplitMix64 (Steele, Lea and Flood 2014): output function, and the counter
+// draw u(seed, stream, n) = mix(key + (n + 1) * golden) with
+// key = mix(seed * golden + stream), as double in [0, 1).
+__device__ __forceinline__ unsigned long long splitmix_mix(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double splitmix_u01(unsigned long long key, unsigned long long n) {
+  const unsigned long long z = splitmix_mix(key + (n + 1ULL) * 0x9E3779B97F4A7C15ULL);
+  return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+struct InitArgs {
+  int kind, n;
+  const double* xy;  // device copy of the centres
+  const double* w;   // device copy of the windings
+  double R, gamma;
+  unsigned long long key;  // noise stream key (0 = no noise)
+  double amp;
+};
+
+// One thread per padded site; writes phi[0] and phi[1].
+template <class T>
+__global__ void __launch_bounds__(256) init_ansatz(Bufs<T> B, Coeffs cf, InitArgs ia) {
+  const long W = B.Nx + 4, H = B.Ny + 4;
+  const long k = blockIdx.x * 256L + threadIdx.x;
+  if (k >= W * H) return;
+  const int jj = (int)(k / W), ii = (int)(k - (long)jj * W);  // padded indices
+  const int i = ii - 2, j = jj - 2;
+  const bool inner = i >= 0 && i < B.Nx && j >= 0 && j < B.Ny;
+  const double x = (i - 0.5 * (B.Nx - 1)) * cf.h, y = (j - 0.5 * (B.Ny - 1)) * cf.h;
+  double out[4] = {0.0, 0.0, 0.0, 0.0};
+  int C = 3;
+  if (ia.kind == 0) {
+    C = 4;
+    double mod = 1.0, ph = 0.0, ax = 0.0, ay = 0.0;
+    for (int v = 0; v < ia.n; ++v) {
+      const double dx = x - ia.xy[2 * v], dy = y - ia.xy[2 * v + 1], wv = ia.w[v];
+      const double r2 = dx * dx + dy * dy;
+      ph += wv * atan2(dy, dx);
+      double prof;
+      if (inner) {
+        mod *= tanh(sqrt(r2));
+        prof = r2 > 1e-300 ? -expm1(-r2) / r2 : 1.0;
+      } else {
+        prof = r2 > 1e-300 ? 1.0 / r2 : 0.0;
+      }
+      ax += wv * prof * (-dy);
+      ay += wv * prof * dx;
+    }
+    out[0] = mod * cos(ph);
+    out[1] = mod * sin(ph);
+    out[2] = ax;
+    out[3] = ay;
+  } else {
+    if (inner) {
+      const double dx = x - ia.xy[0], dy = y - ia.xy[1];
+      const double r = sqrt(dx * dx + dy * dy), th = atan2(dy, dx);
+      const double Th = 2.0 * atan2(ia.R, r);
+      out[0] = sin(Th) * cos(th + ia.gamma);
+      out[1] = sin(Th) * sin(th + ia.gamma);
+      out[2] = cos(Th);
+    } else {
+      out[2] = 1.0;
+    }
+  }
+  if (inner && ia.key != 0ULL) {
+    for (int c = 0; c < C; ++c) {
+      const unsigned long long n = ((unsigned long long)c * B.Ny + j) * B.Nx + i;
+      out[c] += ia.amp * (2.0 * splitmix_u01(ia.key, n) - 1.0);
+    }
+    if (ia.kind == 1) {
+      const double r = sqrt(out[0] * out[0] + out[1] * out[1] + out[2] * out[2]);
+      for (int c = 0; c < 3; ++c) out[c] /= r;
+    }
+  }
+  const long off = (long)jj * B.pitch + ii;
+  for (int c = 0; c < C; ++c) {
+    B.phi[0][c * B.plane + off] = (T)out[c];
+    B.phi[1][c * B.plane + off] = (T)out[c];
+  }
+}
+
+}  // namespace ss

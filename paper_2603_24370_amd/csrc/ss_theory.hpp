@@ -1,0 +1,75 @@
+// Per-site physics of the two theories on the device: energy density and the
+// Euler-Lagrange gradient, written in complex / vector form.
+#pragma once
+
+#include "ss_internal.hpp"
+
+namespace ss {
+
+// Local jet of one component at one site: value and derivatives by eq. (1)-(2).
+template <class T>
+struct Jet {
+  T f, x, y, xx, yy, xy;
+};
+
+// Abelian Higgs with u = e = 1, D_k = d_k - i A_k, psi = p + i q (Tab. 1).
+//   e = 1/2 sum_k |D_k psi|^2 + 1/2 B^2 + lambda/8 (1 - |psi|^2)^2,   B = d_x A_y - d_y A_x.
+// Euler-Lagrange gradient:
+//   G_psi = -sum_k D_k D_k psi - lambda/2 (1 - |psi|^2) psi,
+//     D_k D_k psi = d_kk psi - i (d_k A_k) psi - 2 i A_k d_k psi - A_k^2 psi;
+//   G_Ax = (q d_x p - p d_x q) + A_x |psi|^2 + d_y B,
+//   G_Ay = (q d_y p - p d_y q) + A_y |psi|^2 - d_x B.
+template <class T>
+__device__ __forceinline__ void ah_el_gradient(const Jet<T> (&J)[4], T lambda, T (&G)[4]) {
+  const T p = J[0].f, q = J[1].f, ax = J[2].f, ay = J[3].f;
+  const T m2 = p * p + q * q;
+  const T a2 = ax * ax + ay * ay;
+  const T divA = J[2].x + J[3].y;
+  const T lap_p = J[0].xx + J[0].yy, lap_q = J[1].xx + J[1].yy;
+  const T agp = ax * J[0].x + ay * J[0].y;  // A . grad p
+  const T agq = ax * J[1].x + ay * J[1].y;  // A . grad q
+  const T pot = T(0.5) * lambda * (T(1) - m2);
+  // real and imaginary parts of -(D.D psi) - pot psi
+  G[0] = -lap_p - divA * q - T(2) * agq + a2 * p - pot * p;
+  G[1] = -lap_q + divA * p + T(2) * agp + a2 * q - pot * q;
+  const T dxB = J[3].xx - J[2].xy;  // d_x (d_x A_y - d_y A_x)
+  const T dyB = J[3].xy - J[2].yy;  // d_y (d_x A_y - d_y A_x)
+  G[2] = (q * J[0].x - p * J[1].x) + ax * m2 + dyB;
+  G[3] = (q * J[0].y - p * J[1].y) + ay * m2 - dxB;
+}
+
+template <class T>
+__device__ __forceinline__ double ah_density(const Jet<T> (&J)[4], double lambda) {
+  const double p = J[0].f, q = J[1].f, ax = J[2].f, ay = J[3].f;
+  const double rx = (double)J[0].x + ax * q, ix = (double)J[1].x - ax * p;
+  const double ry = (double)J[0].y + ay * q, iy = (double)J[1].y - ay * p;
+  const double B = (double)J[3].x - (double)J[2].y;
+  const double W = 1.0 - (p * p + q * q);
+  return 0.5 * (rx * rx + ix * ix + ry * ry + iy * iy) + 0.5 * B * B + 0.125 * lambda * W * W;
+}
+
+// Chiral magnet (eq. (5), local terms, bulk DMI d_k = e_k), unit field n.
+// With curl n = (d_y n_z, -d_x n_z, d_x n_y - d_y n_x) in the plane:
+//   e = J/2 |grad n|^2 - D n . curl n + K (1 - n_z^2) + B (1 - n_z),
+//   G = -J lap n - 2 D curl n - (2 K n_z + B) e_z   (before projection).
+template <class T>
+__device__ __forceinline__ void cm_el_gradient(const Jet<T> (&J)[4], T Jx, T Dm, T K, T Bz, T (&G)[4]) {
+  const T cx = J[2].y, cy = -J[2].x, cz = J[1].x - J[0].y;
+  G[0] = -Jx * (J[0].xx + J[0].yy) - T(2) * Dm * cx;
+  G[1] = -Jx * (J[1].xx + J[1].yy) - T(2) * Dm * cy;
+  G[2] = -Jx * (J[2].xx + J[2].yy) - T(2) * Dm * cz - (T(2) * K * J[2].f + Bz);
+  G[3] = T(0);
+}
+
+template <class T>
+__device__ __forceinline__ double cm_density(const Jet<T> (&J)[4], double Jx, double Dm, double K,
+                                             double Bz) {
+  double ex = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ex += (double)J[c].x * J[c].x + (double)J[c].y * J[c].y;
+  const double nx = J[0].f, ny = J[1].f, nz = J[2].f;
+  const double cx = J[2].y, cy = -(double)J[2].x, cz = (double)J[1].x - (double)J[0].y;
+  return 0.5 * Jx * ex - Dm * (nx * cx + ny * cy + nz * cz) + K * (1.0 - nz * nz) + Bz * (1.0 - nz);
+}
+
+}  // namespace ss

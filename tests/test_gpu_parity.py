@@ -1,0 +1,325 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Both sides receive the same seeded inputs (for FP32 runs the oracle gets the
+FP32-rounded field). Tolerances:
+  * FP64: gradients to 1e-10 of max|G|, energies to 1e-12 relative, fields
+    after a few steps to 1e-11 relative (rounding order only).
+  * FP32: energies are reduced in FP64 from the stored values, so E matches
+    to 1e-12 relative on the same field; gradients are FP32 stencil
+    arithmetic: each of the ~13/h^2-weighted stencil sums rounds at
+    2^-24 relative, so |dG| <= 32 * 2^-24 * 13 * max|phi| / h^2 (derived in the
+    design notes); fields after a step agree to 1e-5 relative (the north
+    bound), since G enters the update with weight dt^2 / 6 = h^2 / 24.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2603_24370_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+AH, CM = "abelian_higgs", "chiral_magnet"
+P_CM = [1.0, 1.0, 0.1, 0.6]
+EPS32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a HIP device"
+    return t
+
+
+@pytest.fixture(scope="module")
+def ss(torch):
+    import paper_2603_24370_amd as m
+    m.lib()
+    return m
+
+
+def _field(theory, Nx, Ny, h, seed, kind="ansatz"):
+    if theory == AH:
+        if kind == "ansatz":
+            L = 0.3 * min(Nx, Ny) * h
+            cen = I.uniform_centres(seed, 3, L)
+            return I.ah_vortex_ansatz(Nx, Ny, h, cen) + I.noise(seed, 4, Nx, Ny, 1e-3)
+        rng = np.random.default_rng(seed)
+        return rng.normal(size=(4, Ny + 4, Nx + 4))
+    if kind == "ansatz":
+        f = I.cm_skyrmion_ansatz(Nx, Ny, h, R=min(Nx, Ny) * h / 8)
+        return I.renormalise_interior(f + I.noise(seed, 3, Nx, Ny, 1e-3))
+    rng = np.random.default_rng(seed)
+    f = rng.normal(size=(3, Ny + 4, Nx + 4))
+    return I.renormalise_interior(f)
+
+
+def _params(theory):
+    return [1.0] if theory == AH else P_CM
+
+
+def _grad_tol(dtype, phi, h):
+    if dtype == "f64":
+        return None
+    return 32 * EPS32 * 13 * np.abs(phi).max() / h ** 2
+
+
+def _solver(ss, theory, f, h, dtype, params=None):
+    C, H, W = f.shape
+    s = ss.Solver(theory, W - 4, H - 4, h, params or _params(theory), dtype=dtype)
+    return s
+
+
+def _as_np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+SHAPES = [(150, 37), (64, 16), (8, 8), (129, 70)]
+
+
+@pytest.mark.parametrize("theory", [AH, CM])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_energy_and_gradient(ss, theory, dtype, shape, orc):
+    Nx, Ny = shape
+    h = 0.17
+    print(f"[case] energy_grad {theory} {dtype} {shape}", flush=True)
+    f = _field(theory, Nx, Ny, h, seed=Nx * 7 + Ny)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    s = _solver(ss, theory, f, h, dtype)
+    s.set_field(f)
+    E, gmax, G = s.energy_grad()
+    G = _as_np(G)
+    E_ref = orc.energy(theory, f, h, _params(theory))
+    a_ref = orc.acceleration(theory, f, h, _params(theory))  # -G (projected for CM)
+    G_ref = -a_ref
+    assert E == pytest.approx(E_ref, rel=1e-12, abs=1e-12)
+    scale = np.abs(G_ref).max()
+    tol = 1e-10 * scale if dtype == "f64" else _grad_tol(dtype, f, h)
+    assert np.abs(G - G_ref).max() <= tol
+    assert gmax == pytest.approx(np.abs(G_ref[:, 2:-2, 2:-2]).max(), rel=1e-9 if dtype == "f64" else 1e-4)
+    assert np.all(G[:, :2, :] == 0) and np.all(G[:, :, :2] == 0)
+    assert np.all(G[:, -2:, :] == 0) and np.all(G[:, :, -2:] == 0)
+    # the context's own field gives the same numbers
+    E2, g2, _ = s.energy_grad(field=f, want_grad=False)
+    assert E2 == E and g2 == gmax
+    s.close()
+
+
+@pytest.mark.parametrize("theory", [AH, CM])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_flow_steps_track_oracle(ss, theory, dtype, orc):
+    Nx, Ny, h = 150, 37, 0.17
+    print(f"[case] flow {theory} {dtype}", flush=True)
+    f = _field(theory, Nx, Ny, h, seed=11)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    s = _solver(ss, theory, f, h, dtype)
+    s.set_field(f)
+    n = 6
+    info = s.flow_step(n)
+    phi, vel = s.get_field(velocity=True)
+    phi, vel = _as_np(phi), _as_np(vel)
+    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), n)
+    rel = 1e-11 if dtype == "f64" else 1e-5
+    assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max()
+    assert np.abs(vel - v_r).max() <= rel * max(np.abs(phi_r).max(), 1.0)
+    assert info["step"] == n and info["n_arrests"] == na_r
+    assert info["energy"] == pytest.approx(E_r, rel=1e-12 if dtype == "f64" else 1e-6)
+    # halo is never written
+    assert np.array_equal(phi[:, :2, :], f[:, :2, :]) and np.array_equal(phi[:, :, -2:], f[:, :, -2:])
+    if theory == CM:
+        nrm = np.sqrt((phi[:, 2:-2, 2:-2] ** 2).sum(0))
+        assert np.abs(nrm - 1).max() < (1e-14 if dtype == "f64" else 1e-6)
+    s.close()
+
+
+def test_arrests_match_oracle_over_a_long_run(ss, orc):
+    """FP64 trajectories agree to rounding, so the arrest pattern must agree too."""
+    Nx, Ny, h = 48, 40, 0.25
+    f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.3, -0.2), (-1.1, 0.9)]) + I.noise(5, 4, Nx, Ny, 1e-3)
+    s = _solver(ss, AH, f, h, "f64")
+    s.set_field(f)
+    E = None
+    phi_r, v_r = f, np.zeros_like(f)
+    total = 0
+    for chunk in range(4):
+        info = s.flow_step(50)
+        phi_r, v_r, E, na = orc.flow(AH, phi_r, v_r, h, [1.0], 50, E_cur=E)
+        total += na
+        assert info["n_arrests"] == total
+        assert info["energy"] == pytest.approx(E, rel=1e-11)
+    assert total > 0
+    phi = _as_np(s.get_field())
+    assert np.abs(phi - phi_r).max() < 1e-9
+    s.close()
+
+
+@pytest.mark.parametrize("theory", [AH, CM])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_observables(ss, theory, dtype, orc):
+    Nx, Ny, h = 96, 80, 0.2
+    f = _field(theory, Nx, Ny, h, seed=3)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    s = _solver(ss, theory, f, h, dtype)
+    s.set_field(f)
+    o = s.observables()
+    r = orc.observables(theory, f, h, _params(theory))
+    if theory == AH:
+        for k_gpu, k_ref in [("energy", "E"), ("flux", "flux"), ("n_rho", "N_rho"), ("bogo_r1", "R1"),
+                             ("bogo_r2", "R2"), ("n_wind", "N_wind")]:
+            assert o[k_gpu] == pytest.approx(r[k_ref], rel=1e-11, abs=1e-11), k_gpu
+        assert o["n_wind"] == pytest.approx(3.0, abs=1e-12)
+    else:
+        assert o["energy"] == pytest.approx(r["E"], rel=1e-11)
+        assert o["q_fd"] == pytest.approx(r["Q_fd"], rel=1e-11, abs=1e-12)
+        assert o["q_bl"] == pytest.approx(r["Q_bl"], abs=1e-11)
+        # the solid-angle sum is an integer for exactly unit vectors; FP32 rounding of
+        # the stored unit field moves it by O(2^-24) per plaquette
+        assert o["q_bl"] == pytest.approx(-1.0, abs=1e-9 if dtype == "f64" else 1e-6)
+    s.close()
+
+
+def test_critical_vortex_minimum_fp64(ss, orc):
+    """C1: lambda = 1, 128^2, h = 0.1, FP64, flow to max|G| < 1e-6. E = pi, flux = 2 pi,
+    N = 1 within the lattice and box errors; the oracle, polishing from the GPU's
+    minimum, moves it by less than the stated tolerances."""
+    inst = I.ah_single_vortex(128, 0.1, seed=1)
+    f = inst.field()
+    s = _solver(ss, AH, f, 0.1, "f64")
+    s.set_field(f)
+    res = s.minimise(grad_tol=1e-6, max_steps=400000, graph_steps=64)
+    print("[C1]", res, flush=True)
+    assert res["converged"] and res["reason"] == "grad"
+    o = s.observables()
+    assert o["energy"] == pytest.approx(math.pi, rel=5e-5)
+    assert o["flux"] == pytest.approx(2 * math.pi, rel=2e-3)
+    assert o["n_rho"] == pytest.approx(1.0, abs=1e-5)
+    assert o["n_wind"] == pytest.approx(1.0, abs=1e-12)
+    phi = _as_np(s.get_field())
+    # oracle checks: the GPU minimum satisfies the oracle's stop rule
+    a = orc.acceleration(AH, phi, 0.1, [1.0])
+    assert np.abs(a).max() < 1.01e-6
+    assert orc.energy(AH, phi, 0.1, [1.0]) == pytest.approx(o["energy"], rel=1e-12)
+    s.close()
+
+
+def test_minimise_stops_exactly_where_the_oracle_does(ss, orc):
+    """The device-side stop rule halts inside a replayed graph at the first state
+    meeting the rule: same step count and field as the oracle (FP64)."""
+    Nx, Ny, h = 40, 40, 0.25
+    f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.2, 0.1)]) + I.noise(8, 4, Nx, Ny, 1e-3)
+    s = _solver(ss, AH, f, h, "f64")
+    s.set_field(f)
+    res = s.minimise(grad_tol=3e-3, max_steps=5000, graph_steps=16)
+    phi_r, v_r, info_r = orc.minimise(AH, f, h, [1.0], grad_tol=3e-3, max_steps=5000)
+    assert res["reason"] == "grad" and info_r["reason"] == 1
+    assert res["step"] == info_r["steps"]
+    assert res["n_arrests"] == info_r["arrests"]
+    phi = _as_np(s.get_field())
+    assert np.abs(phi - phi_r).max() < 1e-10
+    s.close()
+
+
+def test_max_steps_and_stall_rules(ss, orc):
+    Nx, Ny, h = 32, 32, 0.25
+    f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.2, 0.1)]) + I.noise(8, 4, Nx, Ny, 1e-3)
+    s = _solver(ss, AH, f, h, "f64")
+    s.set_field(f)
+    res = s.minimise(grad_tol=1e-14, max_steps=37, graph_steps=8)
+    assert res["rc"] == 1 and res["reason"] == "max_steps" and res["step"] == 37
+    s.set_field(f)
+    res = s.minimise(grad_tol=0.0, rel_e_tol=1e-4, window=20, max_steps=5000)
+    _, _, info_r = orc.minimise(AH, f, h, [1.0], grad_tol=0.0, rel_e_tol=1e-4, window=20, max_steps=5000)
+    assert res["reason"] == "stall" and info_r["reason"] == 2
+    assert res["step"] == info_r["steps"]
+    s.close()
+
+
+def test_nonfinite_is_reported(ss):
+    Nx, Ny, h = 40, 24, 0.25
+    f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.2, 0.1)])
+    f[1, 10, 13] = np.nan
+    s = _solver(ss, AH, f, h, "f32")
+    s.set_field(f)
+    with pytest.raises(ss.SSError) as e:
+        s.energy_grad()
+    assert e.value.code == -5
+    with pytest.raises(ss.SSError):
+        s.minimise(grad_tol=1e-6, max_steps=100)
+    s.close()
+
+
+def test_cm_skyrmion_keeps_charge_minus_one(ss, orc):
+    """C2 at reduced size: FP32 field, FP64 reductions; Berg-Luescher charge stays -1."""
+    N, h = 128, 0.05 * 4
+    inst = I.cm_single_skyrmion(N, h, seed=2)
+    f = inst.field().astype(np.float32).astype(np.float64)
+    s = _solver(ss, CM, f, h, "f32")
+    s.set_field(f)
+    s.flow_step(300)
+    o = s.observables()
+    assert o["q_bl"] == pytest.approx(-1.0, abs=1e-6)
+    phi = _as_np(s.get_field())
+    assert orc.observables(CM, phi, h, P_CM)["Q_bl"] == pytest.approx(o["q_bl"], abs=1e-9)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_device_vortex_ansatz_matches_input_module(ss, dtype):
+    Nx, Ny, h = 150, 37, 0.2
+    cen = [(0.3, -0.4), (-5.0, 1.2), (7.7, 0.0)]
+    wnd = [1.0, -1.0, 2.0]
+    s = ss.Solver(AH, Nx, Ny, h, [1.0], dtype=dtype)
+    s.init_vortices(cen, windings=wnd, seed=77, noise_amp=1e-3)
+    got = _as_np(s.get_field())
+    want = I.ah_vortex_ansatz(Nx, Ny, h, cen, wnd) + I.noise(77, 4, Nx, Ny, 1e-3)
+    tol = 1e-12 if dtype == "f64" else 4e-7 * max(1.0, np.abs(want).max())
+    assert np.abs(got - want).max() <= tol
+    info = s.info()
+    assert info["step"] == 0 and info["n_arrests"] == 0
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_device_skyrmion_ansatz_matches_input_module(ss, dtype):
+    Nx, Ny, h = 96, 70, 0.1
+    s = ss.Solver(CM, Nx, Ny, h, P_CM, dtype=dtype)
+    s.init_skyrmion(R=2.0, gamma=-math.pi / 2, centre=(0.15, -0.05), seed=5, noise_amp=1e-3)
+    got = _as_np(s.get_field())
+    want = I.renormalise_interior(I.cm_skyrmion_ansatz(Nx, Ny, h, R=2.0, centre=(0.15, -0.05))
+                                  + I.noise(5, 3, Nx, Ny, 1e-3))
+    tol = 1e-12 if dtype == "f64" else 4e-7
+    assert np.abs(got - want).max() <= tol
+    s.close()
+
+
+def test_large_lattice_sampled_parity(ss, orc):
+    """The 4096^2 GL workload in the launch configuration the benchmark times:
+    energy to 1e-9 relative (FP64 reduction of FP32 values vs the oracle's FP64
+    sum) and G on sampled 64x64 windows against the oracle on the same windows."""
+    N, h = 4096, 0.2
+    inst = I.gl_large_instance(N, h)
+    lam = I.gl_lambda_from_kappa(1.5)
+    s = ss.Solver(AH, N, N, h, [lam], dtype="f32")
+    s.init_vortices(inst.centres, seed=4, noise_amp=1e-3)
+    E, gmax, G = s.energy_grad()
+    f = s.get_field()
+    ff = f.double().cpu().numpy()
+    E_ref = orc.energy(AH, ff, h, [lam])
+    assert E == pytest.approx(E_ref, rel=1e-9)
+    Gn = G.cpu().numpy()
+    rng = np.random.default_rng(0)
+    for k in range(6):
+        j0, i0 = (rng.integers(0, N - 64, size=2) if k < 4 else ((0, 0) if k == 4 else (N - 64, N - 64)))
+        win = np.ascontiguousarray(ff[:, j0:j0 + 68, i0:i0 + 68])
+        # the oracle's interior of this window is the GPU's interior sites (j0..j0+63, i0..i0+63)
+        g_ref = -orc.acceleration(AH, win, h, [lam])[:, 2:-2, 2:-2]
+        g_gpu = Gn[:, j0 + 2:j0 + 66, i0 + 2:i0 + 66].astype(np.float64)
+        assert np.abs(g_gpu - g_ref).max() <= _grad_tol("f32", win, h)
+    info = s.flow_step(3)
+    assert info["nonfinite"] == 0 and info["step"] == 3
+    s.close()
