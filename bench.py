@@ -37,7 +37,48 @@ WORKLOADS = {
     "gl4096": dict(theory="abelian_higgs", N=4096, h=0.2, kappa=1.5, nv=256, seed=4, dtype="f32"),
     "cm512": dict(theory="chiral_magnet", N=512, h=0.05, seed=2, dtype="f32"),
     "ah128": dict(theory="abelian_higgs", N=128, h=0.1, kappa=2 ** -0.5, nv=1, seed=1, dtype="f64"),
+    "batch256": dict(theory="abelian_higgs", n=256, base_seed=3000, h=0.2, dtype="f32"),
 }
+
+
+def run_batch(args, wl):
+    """256 independent GL lattices (sides 64..384, kappa 0.5..2, 1..8 vortices)
+    advanced by batched launches (one launch per pass for all members)."""
+    import torch
+    import paper_2603_24370_amd as ss
+    from paper_2603_24370_amd import inputs as I
+    insts = [I.gl_batch_instance(b, wl["base_seed"], wl["h"]) for b in range(wl["n"])]
+    B = ss.Batch("abelian_higgs", [(m.Nx, m.Ny, m.h, m.params) for m in insts], dtype=wl["dtype"])
+    tune = B.autotune(args.autotune_steps) if args.autotune_steps else None
+    for m, mem in zip(insts, B.members):
+        mem.init_vortices(m.centres, seed=m.seed, noise_amp=1e-3)
+    sites = sum(m.Nx * m.Ny for m in insts)
+    B.flow_step(args.warmup, want_info=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.flow_step(args.steps, want_info=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_step = 1e3 * el / args.steps
+    step_gbps = STEP_SETS * 4 * 4 * sites / (ms_step * 1e-3) / 1e9
+    out = {"metric": "site-updates/s", "value": sites * args.steps / el, "unit": "site-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 fields, f64 reductions",
+           "data": "synthetic (seeded ansatz + noise)",
+           "config": {"workload": "batch256", "members": wl["n"], "interior_sites": sites, "h": wl["h"],
+                      "grad_form": "euler-lagrange", "parallelism": "single GPU, one launch per pass"},
+           "roofline": {"bound": "hbm", "achieved": round(step_gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(step_gbps / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "batch_pass (whole step)"},
+           "tile": {"chosen": list(ss_tile(tune[0])) if tune else None,
+                    "step_ms_by_tile": [round(x, 4) for x in tune[1]] if tune else None},
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+    B.close()
+
+
+def ss_tile(i):
+    import paper_2603_24370_amd as ss
+    return ss.ss_tile_shape(i)
 
 
 def kernel_source_hash() -> str:
@@ -49,12 +90,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_solver(wl):
+def make_solver(wl, autotune_steps=10):
     import paper_2603_24370_amd as ss
     from paper_2603_24370_amd import inputs as I
+    tune = None
     if wl["theory"] == "abelian_higgs":
         lam = I.gl_lambda_from_kappa(wl["kappa"])
         s = ss.Solver("abelian_higgs", wl["N"], wl["N"], wl["h"], [lam], dtype=wl["dtype"])
+        if autotune_steps:
+            tune = s.autotune(autotune_steps)
         if wl["nv"] == 1:
             centres = [(0.0, 0.0)]
         else:
@@ -64,8 +108,10 @@ def make_solver(wl):
     else:
         params = [1.0, 1.0, 0.1, 0.6]
         s = ss.Solver("chiral_magnet", wl["N"], wl["N"], wl["h"], params, dtype=wl["dtype"])
+        if autotune_steps:
+            tune = s.autotune(autotune_steps)
         s.init_skyrmion(R=2.0, gamma=-math.pi / 2, seed=wl["seed"], noise_amp=1e-3)
-    return s, params
+    return s, params, tune
 
 
 def cpu_baseline(s, wl, params, window=1024, steps=10):
@@ -107,7 +153,20 @@ def main():
     ap.add_argument("--workload", default="gl4096", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--timing-steps", type=int, default=20)
+    ap.add_argument("--autotune-steps", type=int, default=10, help="0 = keep the default tile shape")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 times), to scale HBM counters")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "repeats": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the lattice fits one "
               f"MI355X; see the design notes for how it would shard)", file=sys.stderr)
@@ -118,7 +177,10 @@ def main():
         print("bench.py needs a HIP GPU", file=sys.stderr)
         sys.exit(1)
     wl = WORKLOADS[args.workload]
-    s, params = make_solver(wl)
+    if args.workload.startswith("batch"):
+        run_batch(args, wl)
+        return
+    s, params, tune = make_solver(wl, args.autotune_steps)
     N = wl["N"]
     sites = N * N
     C = s.C
@@ -173,6 +235,8 @@ def main():
                    "kappa": wl.get("kappa"), "vortices": wl.get("nv"), "grad_form": "euler-lagrange",
                    "integrator": "RK4 arrested Newton flow, dt = 0.5 h", "parallelism": "single GPU"},
         "roofline": roof,
+        "tile": {"chosen": list(ss_tile(tune[0])) if tune else None,
+                 "step_ms_by_tile": [round(x, 4) for x in tune[1]] if tune else None},
         "cpu_baseline": cpu,
         "state": {"energy": info["energy"], "n_arrests": info["n_arrests"], "step": info["step"]},
     }

@@ -226,6 +226,54 @@ int ss_minimise(ss_ctx* ctx, const ss_stop* stop, ss_min_info* info);
 /* Observables of the current field. Synchronises. */
 int ss_observables(ss_ctx* ctx, ss_obs* out);
 
+/* Tile shapes of the fused stage kernels. The library carries ss_tile_count()
+ * compiled shapes (a workgroup covers TX x TY sites, each thread RY rows of
+ * one column). ss_set_tile selects one for a context; ss_autotune times every
+ * shape over n_steps flow steps of a uniform vacuum on the context's lattice,
+ * keeps the fastest, writes each shape's mean step time in ms_out (may be NULL,
+ * else ss_tile_count() doubles) and returns the chosen index (>= 0). It
+ * overwrites the field: call ss_set_field or ss_init_ansatz afterwards. The
+ * environment variable SS_TILE selects the initial shape of new contexts. */
+int ss_tile_count(void);
+int ss_tile_shape(int tile, int* tx, int* ty, int* ry);
+int ss_set_tile(ss_ctx* ctx, int tile);
+int ss_get_tile(ss_ctx* ctx);
+int ss_autotune(ss_ctx* ctx, int n_steps, double* ms_out);
+
+/* ------------------------------------------------------------ batching
+ * Many independent minimisations (uneven lattices and couplings, one theory
+ * and dtype) advanced together: each flow pass is one launch over a flat list
+ * of the tiles of all members still running, with per-member reductions,
+ * arrest tests and stop rules on the device. ss_batch_minimise replays a
+ * captured HIP graph of stop->graph_steps steps and drops stopped members'
+ * tiles from the list between replays. Each member is an ss_ctx carved from
+ * the batch workspace (ss_batch_member): set its field with ss_set_field or
+ * ss_init_ansatz and read results with the single-context calls; do not
+ * destroy it separately. */
+typedef struct {
+  int Nx, Ny;
+  double h;
+  const double* f; /* theory float parameters as in ss_params.f (host) */
+  int nf;
+} ss_instance;
+
+typedef struct ss_batch ss_batch;
+
+int ss_batch_workspace_bytes(const char* theory, int n, const ss_instance* inst, int dtype, size_t* bytes);
+int ss_batch_create(const char* theory, int n, const ss_instance* inst, int dtype, void* workspace, size_t ws_bytes,
+                    void* stream, ss_batch** out);
+void ss_batch_destroy(ss_batch* batch);
+ss_ctx* ss_batch_member(ss_batch* batch, int i);
+int ss_batch_size(ss_batch* batch);
+/* n_steps for every member, then the arrest test; infos (n entries, may be NULL). */
+int ss_batch_flow_step(ss_batch* batch, int n_steps, ss_step_info* infos);
+/* Same stop rule for every member; infos (n entries, may be NULL). Returns
+ * SS_OK if all converged, SS_NOT_CONVERGED if any hit max_steps. */
+int ss_batch_minimise(ss_batch* batch, const ss_stop* stop, ss_min_info* infos);
+int ss_batch_set_tile(ss_batch* batch, int tile);
+/* Times every tile shape over n_steps batch steps (overwrites all fields with the vacuum). */
+int ss_batch_autotune(ss_batch* batch, int n_steps, double* ms_out);
+
 /* Read the device status into info (synchronises). */
 int ss_get_info(ss_ctx* ctx, ss_step_info* info);
 

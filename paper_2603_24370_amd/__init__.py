@@ -54,6 +54,11 @@ class ss_obs(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ss_instance(ctypes.Structure):
+    _fields_ = [("Nx", ctypes.c_int), ("Ny", ctypes.c_int), ("h", ctypes.c_double),
+                ("f", ctypes.POINTER(ctypes.c_double)), ("nf", ctypes.c_int)]
+
+
 class SSError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libss error {code}: {msg}")
@@ -63,7 +68,10 @@ class SSError(RuntimeError):
 EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "ss_destroy", "ss_set_field",
            "ss_init_ansatz", "ss_time_passes",
            "ss_get_field", "ss_energy_grad", "ss_flow_step", "ss_minimise", "ss_observables", "ss_get_info",
-           "ss_status_string", "ss_last_error", "ss_gl_lambda_from_kappa"]
+           "ss_status_string", "ss_last_error", "ss_gl_lambda_from_kappa", "ss_tile_count", "ss_tile_shape",
+           "ss_set_tile", "ss_get_tile", "ss_autotune", "ss_batch_workspace_bytes", "ss_batch_create",
+           "ss_batch_destroy", "ss_batch_member", "ss_batch_size", "ss_batch_flow_step", "ss_batch_minimise",
+           "ss_batch_set_tile", "ss_batch_autotune"]
 
 _lib = None
 
@@ -99,6 +107,24 @@ def lib():
     L.ss_last_error.restype = cp
     L.ss_gl_lambda_from_kappa.argtypes = [d]
     L.ss_gl_lambda_from_kappa.restype = d
+    ip = ctypes.POINTER(i)
+    L.ss_tile_count.argtypes = []
+    L.ss_tile_shape.argtypes = [i, ip, ip, ip]
+    L.ss_set_tile.argtypes = [vp, i]
+    L.ss_get_tile.argtypes = [vp]
+    L.ss_autotune.argtypes = [vp, i, dp]
+    ins = ctypes.POINTER(ss_instance)
+    L.ss_batch_workspace_bytes.argtypes = [cp, i, ins, i, ctypes.POINTER(ctypes.c_size_t)]
+    L.ss_batch_create.argtypes = [cp, i, ins, i, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.ss_batch_destroy.argtypes = [vp]
+    L.ss_batch_destroy.restype = None
+    L.ss_batch_member.argtypes = [vp, i]
+    L.ss_batch_member.restype = vp
+    L.ss_batch_size.argtypes = [vp]
+    L.ss_batch_flow_step.argtypes = [vp, i, ctypes.POINTER(ss_step_info)]
+    L.ss_batch_minimise.argtypes = [vp, ctypes.POINTER(ss_stop), ctypes.POINTER(ss_min_info)]
+    L.ss_batch_set_tile.argtypes = [vp, i]
+    L.ss_batch_autotune.argtypes = [vp, i, dp]
     _lib = L
     return L
 
@@ -213,8 +239,100 @@ def ss_get_info(ctx):
     return info.as_dict()
 
 
+def ss_tile_count() -> int:
+    return lib().ss_tile_count()
+
+
+def ss_tile_shape(tile: int):
+    tx, ty, ry = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().ss_tile_shape(tile, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(ry)))
+    return tx.value, ty.value, ry.value
+
+
+def ss_set_tile(ctx, tile: int):
+    _check(lib().ss_set_tile(ctx, tile))
+
+
+def ss_get_tile(ctx) -> int:
+    return _check_nonneg(lib().ss_get_tile(ctx))
+
+
+def ss_autotune(ctx, n_steps=10):
+    ms = (ctypes.c_double * ss_tile_count())()
+    best = _check_nonneg(lib().ss_autotune(ctx, int(n_steps), ms))
+    return best, list(ms)
+
+
 def ss_gl_lambda_from_kappa(kappa: float) -> float:
     return lib().ss_gl_lambda_from_kappa(kappa)
+
+
+def _instances(instances):
+    arr = (ss_instance * len(instances))()
+    keep = []
+    for k, (Nx, Ny, h, params) in enumerate(instances):
+        fa = (ctypes.c_double * len(params))(*[float(x) for x in params])
+        keep.append(fa)
+        arr[k] = ss_instance(int(Nx), int(Ny), float(h), fa, len(params))
+    return arr, keep
+
+
+def ss_batch_workspace_bytes(theory, instances, dtype) -> int:
+    arr, keep = _instances(instances)
+    n = ctypes.c_size_t(0)
+    _check(lib().ss_batch_workspace_bytes(_b(theory), len(instances), arr, dtype, ctypes.byref(n)))
+    return n.value
+
+
+def ss_batch_create(theory, instances, dtype, workspace_ptr, ws_bytes, stream_ptr):
+    arr, keep = _instances(instances)
+    out = ctypes.c_void_p(0)
+    _check(lib().ss_batch_create(_b(theory), len(instances), arr, dtype, ctypes.c_void_p(workspace_ptr), ws_bytes,
+                                 ctypes.c_void_p(stream_ptr), ctypes.byref(out)))
+    return out
+
+
+def ss_batch_destroy(batch):
+    lib().ss_batch_destroy(batch)
+
+
+def ss_batch_member(batch, i):
+    p = lib().ss_batch_member(batch, i)
+    if not p:
+        raise SSError(-1, lib().ss_last_error().decode())
+    return ctypes.c_void_p(p)
+
+
+def ss_batch_size(batch) -> int:
+    return _check_nonneg(lib().ss_batch_size(batch))
+
+
+def ss_batch_flow_step(batch, n_steps, n_members=None):
+    infos = (ss_step_info * n_members)() if n_members else None
+    _check(lib().ss_batch_flow_step(batch, int(n_steps), infos))
+    return [x.as_dict() for x in infos] if infos is not None else None
+
+
+def ss_batch_minimise(batch, n_members, grad_tol=0.0, rel_e_tol=0.0, window=0, max_steps=100000, graph_steps=0):
+    s = ss_stop(grad_tol, rel_e_tol, window, graph_steps, max_steps)
+    infos = (ss_min_info * n_members)()
+    rc = _check(lib().ss_batch_minimise(batch, ctypes.byref(s), infos), allow=(SS_OK, SS_NOT_CONVERGED))
+    out = []
+    for x in infos:
+        d = x.last.as_dict()
+        d.update(reason=STOP_REASONS.get(x.reason, str(x.reason)), converged=bool(x.converged))
+        out.append(d)
+    return rc, out
+
+
+def ss_batch_set_tile(batch, tile):
+    _check(lib().ss_batch_set_tile(batch, tile))
+
+
+def ss_batch_autotune(batch, n_steps=5):
+    ms = (ctypes.c_double * ss_tile_count())()
+    best = _check_nonneg(lib().ss_batch_autotune(batch, int(n_steps), ms))
+    return best, list(ms)
 
 
 # ------------------------------------------------------------ convenience
@@ -223,11 +341,23 @@ class Solver:
     """One library context plus its torch-allocated workspace on a CUDA/HIP device."""
 
     def __init__(self, theory, Nx, Ny, h, params, dtype="f32", grad_mode=SS_GRAD_EL, courant=None,
-                 device="cuda:0", stream=None):
+                 device="cuda:0", stream=None, _ctx=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libss needs a HIP GPU; none is available")
         self.torch = torch
+        if _ctx is not None:
+            # a member of a Batch: the batch owns the context and the workspace
+            self.theory, self.Nx, self.Ny, self.h = theory, int(Nx), int(Ny), float(h)
+            self.dtype_code = SS_F32 if dtype in ("f32", torch.float32) else SS_F64
+            self.tdtype = torch.float32 if self.dtype_code == SS_F32 else torch.float64
+            self.C = ss_components(theory)
+            self.device = torch.device(device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ctx = _ctx
+            self._owned = False
+            return
+        self._owned = True
         self.theory, self.Nx, self.Ny, self.h = theory, int(Nx), int(Ny), float(h)
         self.dtype_code = SS_F32 if dtype in ("f32", torch.float32) else SS_F64
         self.tdtype = torch.float32 if self.dtype_code == SS_F32 else torch.float64
@@ -255,6 +385,12 @@ class Solver:
 
     def init_skyrmion(self, R=2.0, gamma=-1.5707963267948966, centre=(0.0, 0.0), seed=0, noise_amp=0.0):
         ss_init_ansatz(self.ctx, SS_ANSATZ_SKYRMION, [centre], None, [R, gamma], seed, noise_amp)
+
+    def autotune(self, n_steps=10):
+        return ss_autotune(self.ctx, n_steps)
+
+    def set_tile(self, tile):
+        ss_set_tile(self.ctx, tile)
 
     def time_passes(self, n_steps):
         return ss_time_passes(self.ctx, n_steps)
@@ -292,9 +428,59 @@ class Solver:
         return ss_get_info(self.ctx)
 
     def close(self):
-        if getattr(self, "ctx", None) is not None:
+        if getattr(self, "ctx", None) is not None and getattr(self, "_owned", True):
             ss_destroy(self.ctx)
-            self.ctx = None
+        self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent lattices of one theory advanced by batched launches.
+
+    instances: list of (Nx, Ny, h, params). Members are Solver views (members[i])."""
+
+    def __init__(self, theory, instances, dtype="f32", device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libss needs a HIP GPU; none is available")
+        self.torch = torch
+        self.theory = theory
+        self.instances = [tuple(x) for x in instances]
+        self.n = len(self.instances)
+        self.dtype_code = SS_F32 if dtype in ("f32", torch.float32) else SS_F64
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = ss_batch_workspace_bytes(theory, self.instances, self.dtype_code)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.batch = ss_batch_create(theory, self.instances, self.dtype_code, ptr, nbytes, self.stream.cuda_stream)
+        self.members = [Solver(theory, Nx, Ny, h, p, dtype=dtype, device=device, stream=self.stream,
+                               _ctx=ss_batch_member(self.batch, i))
+                        for i, (Nx, Ny, h, p) in enumerate(self.instances)]
+
+    def flow_step(self, n=1, want_info=True):
+        return ss_batch_flow_step(self.batch, n, self.n if want_info else None)
+
+    def minimise(self, **kw):
+        return ss_batch_minimise(self.batch, self.n, **kw)
+
+    def set_tile(self, tile):
+        ss_batch_set_tile(self.batch, tile)
+
+    def autotune(self, n_steps=5):
+        return ss_batch_autotune(self.batch, n_steps)
+
+    def close(self):
+        if getattr(self, "batch", None) is not None:
+            for m in self.members:
+                m.ctx = None
+            ss_batch_destroy(self.batch)
+            self.batch = None
 
     def __del__(self):
         try:

@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <new>
@@ -39,9 +40,17 @@ int fail(int code, const std::string& msg) {
       return fail(SS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));                \
   } while (0)
 
-// Tile of one workgroup: TX x TY sites, RY rows per thread (256 threads).
-constexpr int kTX = 64, kTY = 16, kRY = 4;
+// Tile shapes compiled into the library: a workgroup covers TX x TY sites,
+// each thread RY rows of one column. ss_autotune times them on the caller's
+// lattice; SS_TILE (environment) or ss_set_tile force one.
+struct TileCfg {
+  int TX, TY, RY;
+};
+constexpr TileCfg kTiles[] = {{64, 16, 2}, {64, 8, 2}, {64, 16, 4}, {64, 32, 4}};
+constexpr int kNumTiles = 4;
+constexpr int kDefaultTile = 0;
 constexpr int kDefaultGraphSteps = 16;
+constexpr long kMaxGroups = 2048;  // persistent launch: at most 8 workgroups per CU
 
 int lower_eq(const char* a, const char* b) {
   for (; *a && *b; ++a, ++b) {
@@ -63,22 +72,29 @@ struct Layout {
   long pitch, plane;        // elements
   size_t set_bytes;         // bytes of one C-plane field set (256-B aligned)
   size_t status_off, partial_off, init_off, total;
-  int ntx, nty, nlaunch;
+  int ntx, nty, nlaunch;    // for the selected tile shape
 };
+
+void set_tiles(Layout& L, int Nx, int Ny, int tile) {
+  const TileCfg tc = kTiles[tile];
+  L.ntx = (Nx + tc.TX - 1) / tc.TX;
+  L.nty = (Ny + tc.TY - 1) / tc.TY;
+  L.nlaunch = (int)std::min<long>(round_up((long)L.ntx * L.nty, 8), kMaxGroups);
+}
 
 Layout make_layout(int C, int Nx, int Ny, int esize) {
   Layout L;
-  L.pitch = round_up(Nx + 4, 32);
+  // 16-byte staging loads of a tile row may run up to roundup(Nx, TX) + 4
+  // columns for any tile width TX dividing 256; keep them inside the row
+  L.pitch = round_up(Nx, 256) + 64;
   L.plane = round_up(L.pitch * (Ny + 4), 64);
   L.set_bytes = (size_t)round_up((long)C * L.plane * esize, 256);
-  L.ntx = (Nx + kTX - 1) / kTX;
-  L.nty = (Ny + kTY - 1) / kTY;
-  L.nlaunch = (int)round_up((long)L.ntx * L.nty, 8);
+  set_tiles(L, Nx, Ny, kDefaultTile);
   L.status_off = 7 * L.set_bytes;
   L.partial_off = L.status_off + (size_t)round_up(sizeof(DevStatus), 256);
   // partials: 4 doubles per stage-pass workgroup, 5 per observable workgroup
   const long nobs = 1024;
-  const long nparts = std::max<long>(4L * L.nlaunch, 5L * nobs);
+  const long nparts = std::max<long>(4L * kMaxGroups, 5L * nobs);
   L.init_off = L.partial_off + (size_t)round_up(nparts * 8, 256);
   // staging of ansatz centres and windings for ss_init_ansatz
   L.total = L.init_off + (size_t)round_up(3L * kMaxVortices * 8, 256);
@@ -86,6 +102,8 @@ Layout make_layout(int C, int Nx, int Ny, int esize) {
 }
 
 }  // namespace
+
+struct ss_batch;
 
 struct ss_ctx {
   int theory, dtype, grad_mode, C, Nx, Ny;
@@ -104,6 +122,7 @@ struct ss_ctx {
   double* partials;
   hipGraphExec_t graph;
   int graph_steps;
+  int tile;
 };
 
 namespace {
@@ -141,24 +160,34 @@ PassArgs<T> pass_args(const ss_ctx* c) {
   a.st = c->st;
   a.partials = c->partials;
   a.src = nullptr;
-  a.src_pitch = a.src_plane = 0;
   a.out = nullptr;
   a.out_pitch = a.out_plane = 0;
-  a.nlaunch = c->L.nlaunch;
   a.ntx = c->L.ntx;
   a.nty = c->L.nty;
   return a;
 }
 
+template <class T, int TH, int PASS, int CFG>
+void launch_cfg(const PassArgs<T>& a, int nlaunch, hipStream_t s) {
+  constexpr TileCfg tc = kTiles[CFG];
+  hipLaunchKernelGGL((stage_pass<T, TH, PASS, tc.TX, tc.TY, tc.RY>), dim3(nlaunch), dim3(tc.TX, tc.TY / tc.RY), 0,
+                     s, a);
+}
+
 template <class T, int TH, int PASS>
-void launch_pass_t(const PassArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL((stage_pass<T, TH, PASS, kTX, kTY, kRY>), dim3(a.nlaunch), dim3(kTX, kTY / kRY), 0, s, a);
+void launch_pass_t(int tile, const PassArgs<T>& a, int nlaunch, hipStream_t s) {
+  switch (tile) {
+    case 0: launch_cfg<T, TH, PASS, 0>(a, nlaunch, s); break;
+    case 1: launch_cfg<T, TH, PASS, 1>(a, nlaunch, s); break;
+    case 2: launch_cfg<T, TH, PASS, 2>(a, nlaunch, s); break;
+    default: launch_cfg<T, TH, PASS, 3>(a, nlaunch, s); break;
+  }
 }
 
 template <class T, int PASS>
 void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
-  if (c->theory == SS_THEORY_AH) launch_pass_t<T, 0, PASS>(a, s);
-  else launch_pass_t<T, 1, PASS>(a, s);
+  if (c->theory == SS_THEORY_AH) launch_pass_t<T, 0, PASS>(c->tile, a, c->L.nlaunch, s);
+  else launch_pass_t<T, 1, PASS>(c->tile, a, c->L.nlaunch, s);
 }
 
 template <class T>
@@ -303,6 +332,12 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   c->partials = (double*)(c->ws + c->L.partial_off);
   c->graph = nullptr;
   c->graph_steps = 0;
+  c->tile = kDefaultTile;
+  if (const char* env = std::getenv("SS_TILE")) {
+    const int t = std::atoi(env);
+    if (t >= 0 && t < kNumTiles) c->tile = t;
+  }
+  set_tiles(c->L, Nx, Ny, c->tile);
   hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete c;
@@ -447,25 +482,30 @@ int ss_get_field(ss_ctx* c, void* field, void* velocity) {
 int ss_energy_grad(ss_ctx* c, const void* field, void* grad, double* energy, double* gnorm_inf) {
   if (!c) return fail(SS_EINVAL, "ctx is NULL");
   const size_t es = esize_of(c->dtype);
-  const long upitch = c->Nx + 4, uplane = upitch * (c->Ny + 4);
-  if (grad) SS_HIP(hipMemsetAsync(grad, 0, (size_t)c->C * uplane * es, c->stream));
+  const size_t upitch = (size_t)(c->Nx + 4) * es;
+  const size_t uplane = upitch * (c->Ny + 4);
+  if (grad) SS_HIP(hipMemsetAsync(grad, 0, (size_t)c->C * uplane, c->stream));
+  // a caller's field is first copied into the q stage array (internal layout);
+  // q is rewritten by every third stage pass before it is read, so the flow
+  // state is not disturbed
+  if (field)
+    for (int comp = 0; comp < c->C; ++comp)
+      SS_HIP(hipMemcpy2DAsync((char*)c->q + comp * c->L.plane * es, c->L.pitch * es,
+                              (const char*)field + comp * uplane, upitch, upitch, c->Ny + 4,
+                              hipMemcpyDeviceToDevice, c->stream));
   if (c->dtype == SS_F32) {
     PassArgs<float> a = pass_args<float>(c);
-    a.src = (const float*)field;
-    a.src_pitch = upitch;
-    a.src_plane = uplane;
+    a.src = field ? (const float*)c->q : nullptr;
     a.out = (float*)grad;
-    a.out_pitch = upitch;
-    a.out_plane = uplane;
+    a.out_pitch = c->Nx + 4;
+    a.out_plane = (long)(c->Nx + 4) * (c->Ny + 4);
     launch_pass<float, kEval>(c, a, c->stream);
   } else {
     PassArgs<double> a = pass_args<double>(c);
-    a.src = (const double*)field;
-    a.src_pitch = upitch;
-    a.src_plane = uplane;
+    a.src = field ? (const double*)c->q : nullptr;
     a.out = (double*)grad;
-    a.out_pitch = upitch;
-    a.out_plane = uplane;
+    a.out_pitch = c->Nx + 4;
+    a.out_plane = (long)(c->Nx + 4) * (c->Ny + 4);
     launch_pass<double, kEval>(c, a, c->stream);
   }
   SS_HIP(hipGetLastError());
@@ -587,6 +627,60 @@ int ss_observables(ss_ctx* c, ss_obs* out) {
   return SS_OK;
 }
 
+int ss_set_tile(ss_ctx* c, int tile) {
+  if (!c) return fail(SS_EINVAL, "ctx is NULL");
+  if (tile < 0 || tile >= kNumTiles) return fail(SS_EINVAL, "tile index out of range");
+  SS_HIP(hipStreamSynchronize(c->stream));
+  c->tile = tile;
+  set_tiles(c->L, c->Nx, c->Ny, tile);
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return SS_OK;
+}
+
+int ss_tile_count(void) { return kNumTiles; }
+
+int ss_tile_shape(int tile, int* tx, int* ty, int* ry) {
+  if (tile < 0 || tile >= kNumTiles || !tx || !ty || !ry) return fail(SS_EINVAL, "bad tile query");
+  *tx = kTiles[tile].TX;
+  *ty = kTiles[tile].TY;
+  *ry = kTiles[tile].RY;
+  return SS_OK;
+}
+
+int ss_autotune(ss_ctx* c, int n_steps, double* ms_out) {
+  if (!c || n_steps <= 0) return fail(SS_EINVAL, "bad arguments");
+  // a uniform vacuum (psi = 1, A = 0; n = e_3) keeps every pass finite
+  const double zero[2] = {0.0, 0.0};
+  const double shape[2] = {0.0, 0.0};
+  int rc = c->theory == SS_THEORY_AH ? ss_init_ansatz(c, SS_ANSATZ_VORTICES, 0, nullptr, nullptr, nullptr, 0, 0.0)
+                                     : ss_init_ansatz(c, SS_ANSATZ_SKYRMION, 1, zero, nullptr, shape, 0, 0.0);
+  if (rc) return rc;
+  int best = c->tile;
+  double best_ms = 1e300;
+  for (int t = 0; t < kNumTiles; ++t) {
+    rc = ss_set_tile(c, t);
+    if (rc) return rc;
+    double ms[5];
+    rc = ss_time_passes(c, 2, ms);  // warm-up
+    if (rc) return rc;
+    rc = ss_time_passes(c, n_steps, ms);
+    if (rc) return rc;
+    if (ms_out) ms_out[t] = ms[4];
+    if (ms[4] < best_ms) {
+      best_ms = ms[4];
+      best = t;
+    }
+  }
+  rc = ss_set_tile(c, best);
+  if (rc) return rc;
+  return reset_state(c) ? SS_EHIP : best;
+}
+
+int ss_get_tile(ss_ctx* c) { return c ? c->tile : SS_EINVAL; }
+
 int ss_get_info(ss_ctx* c, ss_step_info* info) {
   if (!c || !info) return fail(SS_EINVAL, "ctx or info is NULL");
   DevStatus d;
@@ -613,5 +707,457 @@ const char* ss_status_string(int code) {
 const char* ss_last_error(void) { return g_last_error.c_str(); }
 
 double ss_gl_lambda_from_kappa(double kappa) { return 2.0 * kappa * kappa; }
+
+}  // extern "C"
+
+// ======================================================================= batch
+
+struct ss_batch {
+  int theory, dtype, C, n, tile;
+  hipStream_t stream;
+  hipStream_t cap_stream;
+  std::vector<ss_ctx*> members;
+  std::vector<int> ntiles_of;   // tiles per member (current tile shape)
+  std::vector<int> tile0_of;    // first global tile of each member
+  int ntiles_total;
+  // device tables (inside the workspace)
+  char* tables;
+  void* inst;          // BatchInst<T>[n]
+  DevStatus** st_ptrs; // [n]
+  int* tile_inst;      // [max tiles]
+  int* work;           // [max tiles]
+  int* nwork;          // [1]
+  int* done_flags;     // [n]
+  double* partials;    // [4 * max tiles]
+  int max_tiles;
+  hipGraphExec_t graph;
+  int graph_steps;
+};
+
+namespace {
+
+size_t batch_table_bytes(int n, int max_tiles) {
+  size_t b = 0;
+  b += (size_t)round_up((long)n * (long)sizeof(BatchInst<double>), 256);
+  b += (size_t)round_up((long)n * 8, 256);
+  b += 2 * (size_t)round_up((long)max_tiles * 4, 256);
+  b += 256;
+  b += (size_t)round_up((long)n * 4, 256);
+  b += (size_t)round_up((long)max_tiles * 32, 256);
+  return b;
+}
+
+// upper bound of tiles over all tile shapes
+int batch_max_tiles(const int* Nx, const int* Ny, int n) {
+  long mx = 0;
+  for (int t = 0; t < kNumTiles; ++t) {
+    long sum = 0;
+    for (int i = 0; i < n; ++i)
+      sum += (long)((Nx[i] + kTiles[t].TX - 1) / kTiles[t].TX) * ((Ny[i] + kTiles[t].TY - 1) / kTiles[t].TY);
+    mx = std::max(mx, sum);
+  }
+  return (int)mx;
+}
+
+template <class T>
+BatchInst<T> batch_inst_of(const ss_ctx* c, int tile0) {
+  BatchInst<T> I;
+  Bufs<T> B = bufs_of<T>(c);
+  Coeffs cf = coeffs_of(c);
+  I.V.phi[0] = B.phi[0]; I.V.phi[1] = B.phi[1];
+  I.V.vel[0] = B.vel[0]; I.V.vel[1] = B.vel[1];
+  I.V.a1 = B.a1; I.V.a2 = B.a2; I.V.q = B.q;
+  I.V.pitch = B.pitch; I.V.plane = B.plane;
+  I.V.Nx = B.Nx; I.V.Ny = B.Ny;
+  I.V.h = cf.h; I.V.dt = cf.dt;
+  for (int k = 0; k < 4; ++k) I.V.p[k] = cf.p[k];
+  I.st = c->st;
+  I.ntx = c->L.ntx;
+  I.nty = c->L.nty;
+  I.tile0 = tile0;
+  I.ntiles = c->L.ntx * c->L.nty;
+  return I;
+}
+
+// (Re)build the per-member tile counts, the global tile -> member map, the
+// member descriptors, and a full work list, for the batch's tile shape.
+int batch_build_tables(ss_batch* b) {
+  b->ntiles_of.assign(b->n, 0);
+  b->tile0_of.assign(b->n, 0);
+  int tot = 0;
+  for (int i = 0; i < b->n; ++i) {
+    ss_ctx* c = b->members[i];
+    c->tile = b->tile;
+    set_tiles(c->L, c->Nx, c->Ny, b->tile);
+    b->tile0_of[i] = tot;
+    b->ntiles_of[i] = c->L.ntx * c->L.nty;
+    tot += b->ntiles_of[i];
+  }
+  if (tot > b->max_tiles) return fail(SS_EINVAL, "batch tile table overflow");
+  b->ntiles_total = tot;
+  std::vector<int> ti(tot), wk(tot);
+  for (int i = 0; i < b->n; ++i)
+    for (int k = 0; k < b->ntiles_of[i]; ++k) ti[b->tile0_of[i] + k] = i;
+  for (int g = 0; g < tot; ++g) wk[g] = g;
+  SS_HIP(hipMemcpyAsync(b->tile_inst, ti.data(), tot * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  SS_HIP(hipMemcpyAsync(b->work, wk.data(), tot * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  SS_HIP(hipMemcpyAsync(b->nwork, &tot, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  std::vector<DevStatus*> sp(b->n);
+  for (int i = 0; i < b->n; ++i) sp[i] = b->members[i]->st;
+  SS_HIP(hipMemcpyAsync(b->st_ptrs, sp.data(), b->n * sizeof(DevStatus*), hipMemcpyHostToDevice, b->stream));
+  if (b->dtype == SS_F32) {
+    std::vector<BatchInst<float>> I(b->n);
+    for (int i = 0; i < b->n; ++i) I[i] = batch_inst_of<float>(b->members[i], b->tile0_of[i]);
+    SS_HIP(hipMemcpyAsync(b->inst, I.data(), I.size() * sizeof(I[0]), hipMemcpyHostToDevice, b->stream));
+  } else {
+    std::vector<BatchInst<double>> I(b->n);
+    for (int i = 0; i < b->n; ++i) I[i] = batch_inst_of<double>(b->members[i], b->tile0_of[i]);
+    SS_HIP(hipMemcpyAsync(b->inst, I.data(), I.size() * sizeof(I[0]), hipMemcpyHostToDevice, b->stream));
+  }
+  SS_HIP(hipStreamSynchronize(b->stream));
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  return SS_OK;
+}
+
+// Work list of the members that have not stopped.
+int batch_compact(ss_batch* b, const std::vector<int>& done) {
+  std::vector<int> wk;
+  wk.reserve(b->ntiles_total);
+  for (int i = 0; i < b->n; ++i)
+    if (!done[i])
+      for (int k = 0; k < b->ntiles_of[i]; ++k) wk.push_back(b->tile0_of[i] + k);
+  const int nw = (int)wk.size();
+  if (nw) SS_HIP(hipMemcpyAsync(b->work, wk.data(), nw * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  SS_HIP(hipMemcpyAsync(b->nwork, &nw, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  SS_HIP(hipStreamSynchronize(b->stream));
+  return SS_OK;
+}
+
+template <class T, int TH, int PASS, int CFG>
+void batch_launch_cfg(const BatchArgs<T>& a, int nlaunch, hipStream_t s) {
+  constexpr TileCfg tc = kTiles[CFG];
+  hipLaunchKernelGGL((batch_pass<T, TH, PASS, tc.TX, tc.TY, tc.RY>), dim3(nlaunch), dim3(tc.TX, tc.TY / tc.RY), 0,
+                     s, a);
+}
+
+template <class T, int TH, int PASS>
+void batch_launch_t(int tile, const BatchArgs<T>& a, int nlaunch, hipStream_t s) {
+  switch (tile) {
+    case 0: batch_launch_cfg<T, TH, PASS, 0>(a, nlaunch, s); break;
+    case 1: batch_launch_cfg<T, TH, PASS, 1>(a, nlaunch, s); break;
+    case 2: batch_launch_cfg<T, TH, PASS, 2>(a, nlaunch, s); break;
+    default: batch_launch_cfg<T, TH, PASS, 3>(a, nlaunch, s); break;
+  }
+}
+
+template <class T, int PASS>
+void batch_launch(const ss_batch* b, hipStream_t s) {
+  BatchArgs<T> a;
+  a.inst = (const BatchInst<T>*)b->inst;
+  a.work = b->work;
+  a.nwork = b->nwork;
+  a.tile_inst = b->tile_inst;
+  a.partials = b->partials;
+  const int nlaunch = (int)std::min<long>(round_up(b->ntiles_total, 8), kMaxGroups);
+  if (b->theory == SS_THEORY_AH) batch_launch_t<T, 0, PASS>(b->tile, a, nlaunch, s);
+  else batch_launch_t<T, 1, PASS>(b->tile, a, nlaunch, s);
+}
+
+template <class T>
+void batch_enqueue_steps(const ss_batch* b, int n, hipStream_t s) {
+  for (int k = 0; k < n; ++k) {
+    batch_launch<T, kP1>(b, s);
+    batch_launch<T, kP2>(b, s);
+    batch_launch<T, kP3>(b, s);
+    batch_launch<T, kP4>(b, s);
+  }
+}
+
+void batch_enqueue_steps_any(const ss_batch* b, int n, hipStream_t s) {
+  if (b->dtype == SS_F32) batch_enqueue_steps<float>(b, n, s);
+  else batch_enqueue_steps<double>(b, n, s);
+}
+
+void batch_enqueue_check(const ss_batch* b, hipStream_t s) {
+  if (b->dtype == SS_F32) {
+    batch_launch<float, kCheck>(b, s);
+    hipLaunchKernelGGL((batch_apply_arrest<float>), dim3(b->n), dim3(256), 0, s,
+                       (const BatchInst<float>*)b->inst, b->C);
+  } else {
+    batch_launch<double, kCheck>(b, s);
+    hipLaunchKernelGGL((batch_apply_arrest<double>), dim3(b->n), dim3(256), 0, s,
+                       (const BatchInst<double>*)b->inst, b->C);
+  }
+}
+
+void batch_enqueue_apply_arrest(const ss_batch* b, hipStream_t s) {
+  if (b->dtype == SS_F32)
+    hipLaunchKernelGGL((batch_apply_arrest<float>), dim3(b->n), dim3(256), 0, s, (const BatchInst<float>*)b->inst,
+                       b->C);
+  else
+    hipLaunchKernelGGL((batch_apply_arrest<double>), dim3(b->n), dim3(256), 0, s, (const BatchInst<double>*)b->inst,
+                       b->C);
+}
+
+int batch_read_done(ss_batch* b, std::vector<int>& done) {
+  hipLaunchKernelGGL(batch_done_flags, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->st_ptrs, b->n,
+                     b->done_flags);
+  SS_HIP(hipGetLastError());
+  done.assign(b->n, 0);
+  SS_HIP(hipMemcpyAsync(done.data(), b->done_flags, b->n * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  SS_HIP(hipStreamSynchronize(b->stream));
+  return SS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_batch_workspace_bytes(const char* theory, int n, const ss_instance* inst, int dtype, size_t* bytes) {
+  if (n <= 0 || !inst || !bytes) return fail(SS_EINVAL, "bad batch description");
+  size_t tot = 0;
+  std::vector<int> nx(n), ny(n);
+  for (int i = 0; i < n; ++i) {
+    size_t b = 0;
+    int rc = ss_workspace_bytes(theory, inst[i].Nx, inst[i].Ny, dtype, &b);
+    if (rc) return rc;
+    tot += (size_t)round_up((long)b, 256);
+    nx[i] = inst[i].Nx;
+    ny[i] = inst[i].Ny;
+  }
+  tot += batch_table_bytes(n, batch_max_tiles(nx.data(), ny.data(), n));
+  *bytes = tot;
+  return SS_OK;
+}
+
+int ss_batch_create(const char* theory, int n, const ss_instance* inst, int dtype, void* workspace, size_t ws_bytes,
+                    void* stream, ss_batch** out) {
+  if (!out) return fail(SS_EINVAL, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  int rc = ss_batch_workspace_bytes(theory, n, inst, dtype, &need);
+  if (rc) return rc;
+  if (!workspace || ws_bytes < need) return fail(SS_EINVAL, "workspace missing or smaller than ss_batch_workspace_bytes");
+  if (((uintptr_t)workspace) % 256 != 0) return fail(SS_EINVAL, "workspace must be 256-byte aligned");
+  ss_batch* b = new (std::nothrow) ss_batch();
+  if (!b) return fail(SS_EINVAL, "out of host memory");
+  b->theory = ss_theory_id(theory);
+  b->dtype = dtype;
+  b->C = b->theory == SS_THEORY_AH ? 4 : 3;
+  b->n = n;
+  b->tile = kDefaultTile;
+  b->stream = (hipStream_t)stream;
+  b->graph = nullptr;
+  b->graph_steps = 0;
+  char* p = (char*)workspace;
+  for (int i = 0; i < n; ++i) {
+    size_t wb = 0;
+    ss_workspace_bytes(theory, inst[i].Nx, inst[i].Ny, dtype, &wb);
+    wb = (size_t)round_up((long)wb, 256);
+    ss_params prm;
+    prm.f = inst[i].f;
+    prm.nf = inst[i].nf;
+    prm.i = nullptr;
+    prm.ni = 0;
+    ss_ctx* c = nullptr;
+    rc = ss_create(theory, inst[i].Nx, inst[i].Ny, inst[i].h, &prm, dtype, p, wb, stream, &c);
+    if (rc) {
+      for (ss_ctx* m : b->members) ss_destroy(m);
+      delete b;
+      return rc;
+    }
+    b->members.push_back(c);
+    p += wb;
+  }
+  std::vector<int> nx(n), ny(n);
+  for (int i = 0; i < n; ++i) {
+    nx[i] = inst[i].Nx;
+    ny[i] = inst[i].Ny;
+  }
+  b->max_tiles = batch_max_tiles(nx.data(), ny.data(), n);
+  char* t = p;
+  b->inst = t; t += round_up((long)n * (long)sizeof(BatchInst<double>), 256);
+  b->st_ptrs = (DevStatus**)t; t += round_up((long)n * 8, 256);
+  b->tile_inst = (int*)t; t += round_up((long)b->max_tiles * 4, 256);
+  b->work = (int*)t; t += round_up((long)b->max_tiles * 4, 256);
+  b->nwork = (int*)t; t += 256;
+  b->done_flags = (int*)t; t += round_up((long)n * 4, 256);
+  b->partials = (double*)t;
+  hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    for (ss_ctx* m : b->members) ss_destroy(m);
+    delete b;
+    return fail(SS_EHIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+  }
+  if (const char* env = std::getenv("SS_TILE")) {
+    const int tl = std::atoi(env);
+    if (tl >= 0 && tl < kNumTiles) b->tile = tl;
+  }
+  rc = batch_build_tables(b);
+  if (rc) {
+    ss_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return SS_OK;
+}
+
+void ss_batch_destroy(ss_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  (void)hipStreamDestroy(b->cap_stream);
+  for (ss_ctx* m : b->members) ss_destroy(m);
+  delete b;
+}
+
+ss_ctx* ss_batch_member(ss_batch* b, int i) {
+  if (!b || i < 0 || i >= b->n) {
+    fail(SS_EINVAL, "member index out of range");
+    return nullptr;
+  }
+  return b->members[i];
+}
+
+int ss_batch_size(ss_batch* b) { return b ? b->n : SS_EINVAL; }
+
+int ss_batch_set_tile(ss_batch* b, int tile) {
+  if (!b) return fail(SS_EINVAL, "batch is NULL");
+  if (tile < 0 || tile >= kNumTiles) return fail(SS_EINVAL, "tile index out of range");
+  SS_HIP(hipStreamSynchronize(b->stream));
+  b->tile = tile;
+  return batch_build_tables(b);
+}
+
+int ss_batch_flow_step(ss_batch* b, int n_steps, ss_step_info* infos) {
+  if (!b || n_steps < 0) return fail(SS_EINVAL, "bad arguments");
+  hipLaunchKernelGGL(batch_arm, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->st_ptrs, b->n, 0, 0.0, 0.0, 0,
+                     0LL);
+  std::vector<int> none(b->n, 0);
+  int rc = batch_compact(b, none);
+  if (rc) return rc;
+  batch_enqueue_steps_any(b, n_steps, b->stream);
+  batch_enqueue_check(b, b->stream);
+  SS_HIP(hipGetLastError());
+  if (infos) {
+    for (int i = 0; i < b->n; ++i) {
+      rc = ss_get_info(b->members[i], &infos[i]);
+      if (rc) return rc;
+    }
+  }
+  return SS_OK;
+}
+
+int ss_batch_minimise(ss_batch* b, const ss_stop* stop, ss_min_info* infos) {
+  if (!b || !stop) return fail(SS_EINVAL, "batch or stop is NULL");
+  if (stop->window < 0 || stop->window > kHistLen) return fail(SS_EINVAL, "window must lie in [0, 128]");
+  int K = stop->graph_steps > 0 ? stop->graph_steps : kDefaultGraphSteps;
+  if (b->graph && b->graph_steps != K) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  std::vector<int> done(b->n, 0);
+  int rc = batch_compact(b, done);
+  if (rc) return rc;
+  if (!b->graph) {
+    hipGraph_t g;
+    SS_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
+    batch_enqueue_steps_any(b, K, b->cap_stream);
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (e != hipSuccess) return fail(SS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->graph = nullptr;
+      return fail(SS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    b->graph_steps = K;
+  }
+  hipLaunchKernelGGL(batch_arm, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->st_ptrs, b->n, 1,
+                     stop->grad_tol, stop->rel_e_tol, stop->window, (long long)stop->max_steps);
+  SS_HIP(hipGetLastError());
+  int ndone = 0;
+  for (;;) {
+    for (int r = 0; r < 2; ++r) SS_HIP(hipGraphLaunch(b->graph, b->stream));
+    std::vector<int> now;
+    rc = batch_read_done(b, now);
+    if (rc) return rc;
+    int nd = 0;
+    for (int i = 0; i < b->n; ++i) nd += now[i] != 0;
+    if (nd == b->n) break;
+    if (nd != ndone) {
+      rc = batch_compact(b, now);  // drop the tiles of stopped members
+      if (rc) return rc;
+      ndone = nd;
+    }
+  }
+  batch_enqueue_apply_arrest(b, b->stream);
+  rc = batch_compact(b, std::vector<int>(b->n, 0));
+  if (rc) return rc;
+  int worst = SS_OK;
+  for (int i = 0; i < b->n; ++i) {
+    DevStatus d;
+    rc = read_status(b->members[i], &d);
+    if (rc) return rc;
+    if (infos) {
+      fill_info(d, &infos[i].last);
+      infos[i].reason = d.done;
+      infos[i].converged = (d.done == SS_STOP_GRAD || d.done == SS_STOP_STALL) ? 1 : 0;
+    }
+    if (d.done == SS_STOP_NONFINITE) worst = SS_ENONFINITE;
+    else if (d.done == SS_STOP_MAXSTEPS && worst == SS_OK) worst = SS_NOT_CONVERGED;
+  }
+  if (worst == SS_ENONFINITE) return fail(SS_ENONFINITE, "non-finite value in a batch member");
+  return worst;
+}
+
+int ss_batch_autotune(ss_batch* b, int n_steps, double* ms_out) {
+  if (!b || n_steps <= 0) return fail(SS_EINVAL, "bad arguments");
+  for (ss_ctx* c : b->members) {
+    int rc = c->theory == SS_THEORY_AH ? ss_init_ansatz(c, SS_ANSATZ_VORTICES, 0, nullptr, nullptr, nullptr, 0, 0.0)
+                                       : 0;
+    if (c->theory == SS_THEORY_CM) {
+      const double zero[2] = {0.0, 0.0}, shape[2] = {0.0, 0.0};
+      rc = ss_init_ansatz(c, SS_ANSATZ_SKYRMION, 1, zero, nullptr, shape, 0, 0.0);
+    }
+    if (rc) return rc;
+  }
+  int best = b->tile;
+  double best_ms = 1e300;
+  hipEvent_t e0, e1;
+  SS_HIP(hipEventCreate(&e0));
+  SS_HIP(hipEventCreate(&e1));
+  for (int t = 0; t < kNumTiles; ++t) {
+    int rc = ss_batch_set_tile(b, t);
+    if (rc) return rc;
+    hipLaunchKernelGGL(batch_arm, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->st_ptrs, b->n, 0, 0.0, 0.0,
+                       0, 0LL);
+    batch_enqueue_steps_any(b, 2, b->stream);
+    SS_HIP(hipEventRecord(e0, b->stream));
+    batch_enqueue_steps_any(b, n_steps, b->stream);
+    SS_HIP(hipEventRecord(e1, b->stream));
+    SS_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    SS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double per = ms / n_steps;
+    if (ms_out) ms_out[t] = per;
+    if (per < best_ms) {
+      best_ms = per;
+      best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  int rc = ss_batch_set_tile(b, best);
+  if (rc) return rc;
+  for (ss_ctx* c : b->members) {
+    rc = reset_state(c);
+    if (rc) return rc;
+  }
+  return best;
+}
 
 }  // extern "C"

@@ -31,47 +31,42 @@ struct NComp<0> { static constexpr int value = 4; };
 template <>
 struct NComp<1> { static constexpr int value = 3; };
 
-// Derivatives of one LDS plane at (lx, ly) by eq. (1) and eq. (2); the mixed
-// derivative applies eq. (1) along x to eq. (1) along y.
-template <class T, int LX, bool MIXED>
-__device__ __forceinline__ Jet<T> lds_jet(const T* __restrict__ s, int lx, int ly, T c1, T c2) {
-  const T* r = s + ly * LX + lx;
-  Jet<T> J;
-  const T f0 = r[0];
-  const T xm2 = r[-2], xm1 = r[-1], xp1 = r[1], xp2 = r[2];
-  const T ym2 = r[-2 * LX], ym1 = r[-LX], yp1 = r[LX], yp2 = r[2 * LX];
-  J.f = f0;
-  J.x = c1 * ((xm2 - xp2) + T(8) * (xp1 - xm1));
-  J.y = c1 * ((ym2 - yp2) + T(8) * (yp1 - ym1));
-  J.xx = c2 * (T(16) * (xp1 + xm1) - (xp2 + xm2) - T(30) * f0);
-  J.yy = c2 * (T(16) * (yp1 + ym1) - (yp2 + ym2) - T(30) * f0);
-  if (MIXED) {
-    T acc = T(0);
-    const T w[5] = {T(1), T(-8), T(0), T(8), T(-1)};
+// Jets of one component for RY consecutive rows of one LDS column (rows
+// ly0 .. ly0 + RY - 1, column lx), by eq. (1) and eq. (2); the mixed derivative
+// applies eq. (1) along y to the eq. (1) x-stencil sums of the rows around.
+// The y-neighbours are read once per column, the x-stencil of a row is shared
+// by D_x, D_xx and the mixed derivative. If E64, the first derivatives are
+// also formed in FP64 from the same stored values (for the energy density).
+template <class T, int LX, int RY, bool MIXED, bool E64>
+__device__ __forceinline__ void column_jets(const T* __restrict__ s, int lx, int ly0, T c1, T c2, double d1,
+                                            Jet<T> (&J)[RY], double (&ex)[RY], double (&ey)[RY]) {
+  T col[RY + 4];
 #pragma unroll
-    for (int n = -2; n <= 2; ++n) {
-      if (n == 0) continue;
-      const T* rr = r + n * LX;
-      const T dxr = (rr[-2] - rr[2]) + T(8) * (rr[1] - rr[-1]);
-      acc += w[n + 2] * dxr;
+  for (int k = 0; k < RY + 4; ++k) col[k] = s[(ly0 - 2 + k) * LX + lx];
+  constexpr int K0 = MIXED ? 0 : 2, K1 = MIXED ? RY + 4 : RY + 2;
+  T ddx[RY + 4];
+#pragma unroll
+  for (int k = K0; k < K1; ++k) {
+    const T* r = s + (ly0 - 2 + k) * LX + lx;
+    const T xm2 = r[-2], xm1 = r[-1], xp1 = r[1], xp2 = r[2];
+    ddx[k] = (xm2 - xp2) + T(8) * (xp1 - xm1);
+    if (k >= 2 && k < RY + 2) {
+      J[k - 2].xx = c2 * (T(16) * (xp1 + xm1) - (xp2 + xm2) - T(30) * col[k]);
+      if (E64) ex[k - 2] = d1 * (((double)xm2 - (double)xp2) + 8.0 * ((double)xp1 - (double)xm1));
     }
-    J.xy = c1 * c1 * acc;
-  } else {
-    J.xy = T(0);
   }
-  return J;
-}
-
-// First derivatives only, in FP64 from the stored values (energy density).
-template <class T, int LX>
-__device__ __forceinline__ Jet<double> lds_jet64(const T* __restrict__ s, int lx, int ly, double c1) {
-  const T* r = s + ly * LX + lx;
-  Jet<double> J;
-  J.f = (double)r[0];
-  J.x = c1 * (((double)r[-2] - (double)r[2]) + 8.0 * ((double)r[1] - (double)r[-1]));
-  J.y = c1 * (((double)r[-2 * LX] - (double)r[2 * LX]) + 8.0 * ((double)r[LX] - (double)r[-LX]));
-  J.xx = J.yy = J.xy = 0.0;
-  return J;
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int k = r + 2;
+    J[r].f = col[k];
+    J[r].x = c1 * ddx[k];
+    J[r].y = c1 * ((col[k - 2] - col[k + 2]) + T(8) * (col[k + 1] - col[k - 1]));
+    J[r].yy = c2 * (T(16) * (col[k + 1] + col[k - 1]) - (col[k + 2] + col[k - 2]) - T(30) * col[k]);
+    if (MIXED) J[r].xy = c1 * c1 * ((ddx[k - 2] - ddx[k + 2]) + T(8) * (ddx[k + 1] - ddx[k - 1]));
+    else J[r].xy = T(0);
+    if (E64)
+      ey[r] = d1 * (((double)col[k - 2] - (double)col[k + 2]) + 8.0 * ((double)col[k + 1] - (double)col[k - 1]));
+  }
 }
 
 template <class T>
@@ -80,115 +75,203 @@ struct PassArgs {
   Coeffs cf;
   DevStatus* st;
   double* partials;
-  const T* src;  // kEval: field to evaluate (nullptr = current field)
-  long src_pitch, src_plane;
-  T* out;        // kEval: gradient output (nullptr = none)
+  const T* src;  // kEval: field to evaluate in the internal layout (nullptr = current field)
+  T* out;        // kEval: gradient output in the caller's layout (nullptr = none)
   long out_pitch, out_plane;
-  int nlaunch;   // launched workgroups (a multiple of 8)
   int ntx, nty;  // tiles along x and y
 };
 
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <>
+struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+
+template <class T>
+__device__ __forceinline__ void vload(const T* p, T (&x)[16 / sizeof(T)]) {
+  typedef typename Vec16<T>::type V;
+  const V v = *reinterpret_cast<const V*>(p);
+  if constexpr (sizeof(T) == 4) { x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w; }
+  else { x[0] = v.x; x[1] = v.y; }
+}
+
+template <class T>
+__device__ __forceinline__ void vstore_lds(T* p, const T (&x)[16 / sizeof(T)]) {
+  typedef typename Vec16<T>::type V;
+  V v;
+  if constexpr (sizeof(T) == 4) { v.x = x[0]; v.y = x[1]; v.z = x[2]; v.w = x[3]; }
+  else { v.x = x[0]; v.y = x[1]; }
+  *reinterpret_cast<V*>(p) = v;
+}
+
+// One lattice as the stage passes see it (single context or one batch member).
+template <class T>
+struct InstView {
+  T* phi[2];
+  T* vel[2];
+  T* a1;
+  T* a2;
+  T* q;
+  long pitch, plane;
+  int Nx, Ny;
+  double h, dt;
+  double p[4];
+};
+
+template <class T>
+__device__ __forceinline__ InstView<T> view_of(const Bufs<T>& B, const Coeffs& cf) {
+  InstView<T> V;
+  V.phi[0] = B.phi[0]; V.phi[1] = B.phi[1];
+  V.vel[0] = B.vel[0]; V.vel[1] = B.vel[1];
+  V.a1 = B.a1; V.a2 = B.a2; V.q = B.q;
+  V.pitch = B.pitch; V.plane = B.plane;
+  V.Nx = B.Nx; V.Ny = B.Ny;
+  V.h = cf.h; V.dt = cf.dt;
+  for (int k = 0; k < 4; ++k) V.p[k] = cf.p[k];
+  return V;
+}
+
+template <int TH, int TX, int TY>
+struct TileLds {
+  static constexpr int C = NComp<TH>::value;
+  static constexpr int LX = TX + 4, LY = TY + 4;
+};
+
+// One tile of one pass. Thread (tx, ty) owns column tx and rows ty*RY ..
+// ty*RY + RY - 1 of the tile: it loads those sites' raw inputs into registers
+// (reused by the epilogue, so no array is read twice) and writes their stage
+// point to LDS; the halo ring of the tile is loaded cooperatively. Reduction
+// contributions (energy, max |G|, non-finite count) are added to the caller's
+// accumulators. Ends with a barrier (LDS is reused by the next tile).
 template <class T, int TH, int PASS, int TX, int TY, int RY>
-__global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
+__device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool arrest, const T* __restrict__ src,
+                                          T* __restrict__ out, long out_pitch, long out_plane, int x0, int y0,
+                                          T* __restrict__ lds, double& e_acc, double& g_acc, int& nf) {
   constexpr int C = NComp<TH>::value;
   constexpr int LX = TX + 4, LY = TY + 4;
   constexpr int NT = TX * (TY / RY);
+  constexpr int NRING = 4 * LX + 4 * TY;
   constexpr bool REDUCE = (PASS == kP1 || PASS == kEval || PASS == kCheck);
-  constexpr bool ENERGY_PASS = REDUCE;
-  __shared__ T s[C][LY * LX];
-  __shared__ double red[3 * (NT / 64)];
+  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  constexpr bool WITH_A = (PASS == kP3 || PASS == kP4);
+  T* s[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) s[c] = lds + c * (LY * LX);
 
-  DevStatus* __restrict__ st = a.st;
-  if (PASS != kEval && st->done) return;
-
-  const int Nx = a.B.Nx, Ny = a.B.Ny;
-  const long long step = st->step;
-  const int cur = (PASS == kP2 || PASS == kP3 || PASS == kP4) ? int((step - 1) & 1) : int(step & 1);
-  const T* __restrict__ ph = a.B.phi[cur];
-  long pitch = a.B.pitch, plane = a.B.plane;
-  if (PASS == kEval && a.src != nullptr) {
-    ph = a.src;
-    pitch = a.src_pitch;
-    plane = a.src_plane;
-  }
-  const T* __restrict__ vv = a.B.vel[cur];
-  const T* __restrict__ aa = (PASS == kP3) ? a.B.a1 : a.B.a2;
-  const bool arrest = (PASS == kP2 || PASS == kP3 || PASS == kP4) ? (st->arrest != 0) : false;
-  const T dt = (T)a.cf.dt;
+  const int Nx = V.Nx, Ny = V.Ny;
+  const long pitch = V.pitch, plane = V.plane;
+  const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : V.phi[cur];
+  const T* __restrict__ vv = V.vel[cur];
+  const T* __restrict__ aa = (PASS == kP3) ? V.a1 : V.a2;
+  const T dt = (T)V.dt;
   T cv = T(0), ca = T(0);
   if (PASS == kP2) cv = T(0.5) * dt;
   if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
   if (PASS == kP4) { cv = dt; ca = T(0.5) * dt * dt; }
   if (arrest) cv = T(0);
-
+  const double h = V.h;
+  const T c1 = T(1.0 / (12.0 * h)), c2 = T(1.0 / (12.0 * h * h));
+  const double d1 = 1.0 / (12.0 * h);
   const int tid = threadIdx.y * TX + threadIdx.x;
-  const int t = xcd_tile(blockIdx.x, a.nlaunch);
-  const bool active = t < a.ntx * a.nty;
-  const int tyi = active ? t / a.ntx : 0;
-  const int x0 = (t - tyi * a.ntx) * TX, y0 = tyi * TY;
+  const int lx = threadIdx.x + 2;
+  const int ly0 = threadIdx.y * RY + 2;
+  const int gi = x0 + threadIdx.x;
 
-  // ---- stage the tile + halo-2 of the stage point in LDS
-  if (active) {
-    for (int idx = tid; idx < LX * LY; idx += NT) {
-      const int ly = idx / LX, lx = idx - ly * LX;
-      const int gi = x0 - 2 + lx, gj = y0 - 2 + ly;
-      const bool inpad = (gi <= Nx + 1) && (gj <= Ny + 1);
-      const bool inner = (gi >= 0) && (gi < Nx) && (gj >= 0) && (gj < Ny);
-      const long off = (long)(gj + 2) * pitch + (gi + 2);
-      T val[C];
+  // stage point of padded element (gi, gj) (interior coordinates), and its raw inputs
+  auto stage_at = [&](int gi_, int gj_, T (&raw_p)[4], T (&raw_v)[4], T (&raw_a)[4], T (&S)[4]) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        T x = T(0);
-        if (inpad) {
-          x = ph[c * plane + off];
-          if ((PASS == kP2 || PASS == kP3 || PASS == kP4) && inner) {
-            x += cv * vv[c * plane + off];
-            if (PASS == kP3 || PASS == kP4) x += ca * aa[c * plane + off];
-          }
+    for (int c = 0; c < 4; ++c) raw_p[c] = raw_v[c] = raw_a[c] = S[c] = T(0);
+    if (gj_ > Ny + 1) return;
+    const long off = (long)(gj_ + 2) * pitch + (gi_ + 2);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      raw_p[c] = ph[c * plane + off];
+      T x = raw_p[c];
+      if (STAGED) {
+        raw_v[c] = vv[c * plane + off];
+        x += cv * raw_v[c];
+        if (WITH_A) {
+          raw_a[c] = aa[c * plane + off];
+          x += ca * raw_a[c];
         }
-        val[c] = x;
       }
-      if (TH == 1 && (PASS == kP2 || PASS == kP3 || PASS == kP4) && inner) {
-        const T inv = T(1) / sqrt(val[0] * val[0] + val[1] * val[1] + val[2] * val[2]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) val[c] *= inv;
-      }
-#pragma unroll
-      for (int c = 0; c < C; ++c) s[c][idx] = val[c];
+      S[c] = x;
     }
+    if (TH == 1 && STAGED && gi_ >= 0 && gi_ < Nx && gj_ >= 0 && gj_ < Ny) {
+      const T inv = T(1) / sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+      S[0] *= inv;
+      S[1] *= inv;
+      S[2] *= inv;
+    }
+  };
+
+  // ---- own sites: raw inputs kept in registers, stage point to LDS
+  T rp[RY][4], rv[RY][4], ra[RY][4];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    T S[4];
+    stage_at(gi, y0 + ly0 - 2 + r, rp[r], rv[r], ra[r], S);
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c][(ly0 + r) * LX + lx] = S[c];
+  }
+  // ---- halo ring of the tile
+  for (int idx = tid; idx < NRING; idx += NT) {
+    int ly, lxr;
+    if (idx < 4 * LX) {
+      const int rr = idx / LX;
+      ly = rr < 2 ? rr : LY - 4 + rr;
+      lxr = idx - rr * LX;
+    } else {
+      const int j = idx - 4 * LX;
+      ly = 2 + (j >> 2);
+      const int cc = j & 3;
+      lxr = cc < 2 ? cc : LX - 4 + cc;
+    }
+    T d0[4], d1v[4], d2[4], S[4];
+    stage_at(x0 - 2 + lxr, y0 - 2 + ly, d0, d1v, d2, S);
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c][ly * LX + lxr] = S[c];
   }
   __syncthreads();
 
-  const double h = a.cf.h;
-  const T c1 = T(1.0 / (12.0 * h)), c2 = T(1.0 / (12.0 * h * h));
-  double e_acc = 0.0, g_acc = 0.0;
-  int nf = 0;
-  const int lx = threadIdx.x + 2;
-  const int gi = x0 + threadIdx.x;
+  Jet<T> J[C][RY];
+  double ex[C][RY], ey[C][RY];
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+    column_jets<T, LX, RY, TH == 0, REDUCE && TH == 0>(s[c], lx, ly0, c1, c2, d1, J[c], ex[c], ey[c]);
 
   // ---- E_h density in FP64 from the stored (unnormalised) values
-  if (ENERGY_PASS && active) {
-    const double d1 = 1.0 / (12.0 * h);
+  if (REDUCE) {
+    if (TH == 1) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        Jet<T> Jr[RY];
+        column_jets<T, LX, RY, false, true>(s[c], lx, ly0, c1, c2, d1, Jr, ex[c], ey[c]);
+      }
+    }
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      const int ly = threadIdx.y * RY + r + 2;
-      const int gj = y0 + ly - 2;
+      const int gj = y0 + ly0 - 2 + r;
       if (gi < Nx && gj < Ny) {
-        Jet<double> J[4];
+        Jet<double> Jd[4];
 #pragma unroll
-        for (int c = 0; c < C; ++c) J[c] = lds_jet64<T, LX>(s[c], lx, ly, d1);
+        for (int c = 0; c < C; ++c) {
+          Jd[c].f = (double)J[c][r].f;
+          Jd[c].x = ex[c][r];
+          Jd[c].y = ey[c][r];
+          Jd[c].xx = Jd[c].yy = Jd[c].xy = 0.0;
+        }
         double e;
-        if (TH == 0) e = ah_density<double>(J, a.cf.p[0]);
-        else e = cm_density<double>(J, a.cf.p[0], a.cf.p[1], a.cf.p[2], a.cf.p[3]);
+        if (TH == 0) e = ah_density<double>(Jd, V.p[0]);
+        else e = cm_density<double>(Jd, V.p[0], V.p[1], V.p[2], V.p[3]);
         e_acc += e;
         if (!isfinite(e)) ++nf;
       }
     }
-  }
-  if (TH == 1 && ENERGY_PASS) {
-    // the flow evaluates G at the normalised field
-    __syncthreads();
-    if (active) {
+    if (TH == 1) {
+      // the flow evaluates G at the normalised field
+      __syncthreads();
       for (int idx = tid; idx < LX * LY; idx += NT) {
         const int ly = idx / LX, lx2 = idx - ly * LX;
         const int gi2 = x0 - 2 + lx2, gj2 = y0 - 2 + ly;
@@ -200,89 +283,160 @@ __global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
           s[2][idx] = n2 * inv;
         }
       }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        column_jets<T, LX, RY, false, false>(s[c], lx, ly0, c1, c2, d1, J[c], ex[c], ey[c]);
     }
-    __syncthreads();
   }
 
   // ---- gradient and pass epilogue
-  if (active) {
-    T* __restrict__ phn = a.B.phi[cur ^ 1];
-    T* __restrict__ vn = a.B.vel[cur ^ 1];
+  T* __restrict__ phn = V.phi[cur ^ 1];
+  T* __restrict__ vn = V.vel[cur ^ 1];
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      const int ly = threadIdx.y * RY + r + 2;
-      const int gj = y0 + ly - 2;
-      if (gi >= Nx || gj >= Ny) continue;
-      Jet<T> J[4];
+  for (int r = 0; r < RY; ++r) {
+    const int gj = y0 + ly0 - 2 + r;
+    if (gi >= Nx || gj >= Ny) continue;
+    Jet<T> Js[4];
 #pragma unroll
-      for (int c = 0; c < C; ++c) J[c] = lds_jet<T, LX, TH == 0>(s[c], lx, ly, c1, c2);
-      T G[4];
-      if (TH == 0) {
-        ah_el_gradient<T>(J, (T)a.cf.p[0], G);
-      } else {
-        cm_el_gradient<T>(J, (T)a.cf.p[0], (T)a.cf.p[1], (T)a.cf.p[2], (T)a.cf.p[3], G);
-        const T gn = G[0] * J[0].f + G[1] * J[1].f + G[2] * J[2].f;
+    for (int c = 0; c < C; ++c) Js[c] = J[c][r];
+    T G[4];
+    if (TH == 0) {
+      ah_el_gradient<T>(Js, (T)V.p[0], G);
+    } else {
+      cm_el_gradient<T>(Js, (T)V.p[0], (T)V.p[1], (T)V.p[2], (T)V.p[3], G);
+      const T gn = G[0] * Js[0].f + G[1] * Js[1].f + G[2] * Js[2].f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) G[c] -= gn * J[c].f;
+      for (int c = 0; c < 3; ++c) G[c] -= gn * Js[c].f;
+    }
+    const long off = (long)(gj + 2) * pitch + (gi + 2);
+    if (REDUCE) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        g_acc = fmax(g_acc, fabs((double)G[c]));
+        if (!isfinite(G[c])) ++nf;
       }
-      const long off = (long)(gj + 2) * a.B.pitch + (gi + 2);
-      if (REDUCE) {
+    }
+    if (PASS == kP1) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const double g = fabs((double)G[c]);
-          g_acc = fmax(g_acc, g);
-          if (!isfinite(G[c])) ++nf;
-        }
+      for (int c = 0; c < C; ++c) V.a1[c * plane + off] = -G[c];
+    } else if (PASS == kEval) {
+      if (out != nullptr) {
+        const long o = (long)(gj + 2) * out_pitch + (gi + 2);
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[c * out_plane + o] = G[c];
       }
-      if (PASS == kP1) {
+    } else if (PASS == kP2) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) a.B.a1[c * a.B.plane + off] = -G[c];
-      } else if (PASS == kEval) {
-        if (a.out != nullptr) {
-          const long o = (long)(gj + 2) * a.out_pitch + (gi + 2);
+      for (int c = 0; c < C; ++c) V.a2[c * plane + off] = -G[c];
+    } else if (PASS == kP3) {
+      // q = a1 + 2 a2 + 2 a3; a1 (a raw stage input) is in registers
 #pragma unroll
-          for (int c = 0; c < C; ++c) a.out[c * a.out_plane + o] = G[c];
-        }
-      } else if (PASS == kP2) {
+      for (int c = 0; c < C; ++c) {
+        const long k = c * plane + off;
+        V.q[k] = ra[r][c] + T(2) * V.a2[k] - T(2) * G[c];
+      }
+    } else if (PASS == kP4) {
+      T pn[4], vnew[4];
 #pragma unroll
-        for (int c = 0; c < C; ++c) a.B.a2[c * a.B.plane + off] = -G[c];
-      } else if (PASS == kP3) {
+      for (int c = 0; c < C; ++c) {
+        const long k = c * plane + off;
+        const T v0 = arrest ? T(0) : rv[r][c];
+        const T qq = V.q[k];
+        pn[c] = rp[r][c] + dt * v0 + (dt * dt / T(12)) * (qq + V.a1[k]);
+        vnew[c] = v0 + (dt / T(6)) * (qq - G[c]);
+      }
+      if (TH == 1) {
+        const T inv = T(1) / sqrt(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const long k = c * a.B.plane + off;
-          a.B.q[k] = a.B.a1[k] + T(2) * a.B.a2[k] - T(2) * G[c];
-        }
-      } else if (PASS == kP4) {
-        T pn[4], vnew[4];
+        for (int c = 0; c < 3; ++c) pn[c] *= inv;
+        const T vd = vnew[0] * pn[0] + vnew[1] * pn[1] + vnew[2] * pn[2];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const long k = c * a.B.plane + off;
-          const T v0 = arrest ? T(0) : vv[k];
-          const T qq = a.B.q[k];
-          pn[c] = ph[k] + dt * v0 + (dt * dt / T(12)) * (qq + a.B.a1[k]);
-          vnew[c] = v0 + (dt / T(6)) * (qq - G[c]);
-        }
-        if (TH == 1) {
-          const T inv = T(1) / sqrt(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+        for (int c = 0; c < 3; ++c) vnew[c] -= vd * pn[c];
+      }
 #pragma unroll
-          for (int c = 0; c < 3; ++c) pn[c] *= inv;
-          const T vd = vnew[0] * pn[0] + vnew[1] * pn[1] + vnew[2] * pn[2];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) vnew[c] -= vd * pn[c];
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const long k = c * a.B.plane + off;
-          phn[k] = pn[c];
-          vn[k] = vnew[c];
-        }
+      for (int c = 0; c < C; ++c) {
+        const long k = c * plane + off;
+        phn[k] = pn[c];
+        vn[k] = vnew[c];
       }
     }
   }
+  __syncthreads();
+}
 
+// Status update after a reduction of one field (thread 0 of the finalising
+// workgroup): arrest test E > E_prev (strict, eq. (4)), the stop rules when
+// minimising, and the step counter (P1 only). E is already multiplied by h^2.
+template <int PASS>
+__device__ __forceinline__ void finalise_status(DevStatus* st, double E, double gmax, int nfin) {
+  st->counter = 0u;
+  if (PASS == kEval) {
+    st->eval_E = E;
+    st->eval_gmax = gmax;
+    st->nonfinite = nfin;
+    return;
+  }
+  const int arr = (E > st->E_prev) ? 1 : 0;
+  st->arrest = arr;
+  if (arr) st->n_arrests += 1;
+  st->E_prev = E;
+  st->E = E;
+  st->gmax = gmax;
+  st->nonfinite = nfin;
+  const long long s0 = st->step;
+  st->hist[s0 % kHistLen] = E;
+  int done = 0;
+  if (nfin > 0) {
+    done = 4;
+  } else if (st->minimise) {
+    const int W = st->window;
+    if (gmax < st->grad_tol) done = 1;
+    else if (W > 0 && s0 >= W && fabs(E - st->hist[(s0 - W) % kHistLen]) <= st->rel_e_tol * fabs(E)) done = 2;
+    else if (s0 >= st->max_steps) done = 3;
+  }
+  if (done) st->done = done;
+  else if (PASS == kP1) st->step = s0 + 1;
+}
+
+// Launch: gridDim.x is a multiple of 8. Workgroup b runs on XCD b % 8; the XCD
+// owns the contiguous tile range [x * per, (x + 1) * per) and its m = gridDim.x / 8
+// workgroups sweep that range together (tiles x*per + q, + m, + 2m, ...), so the
+// tiles in flight on one XCD are neighbours and share halo rows in its L2.
+// Each workgroup accumulates its tiles' reductions into one partial; the last
+// workgroup to finish sums the partials in a fixed order and updates the status.
+template <class T, int TH, int PASS, int TX, int TY, int RY>
+__global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
+  constexpr int C = NComp<TH>::value;
+  constexpr int LX = TX + 4, LY = TY + 4;
+  constexpr int NT = TX * (TY / RY);
+  constexpr bool REDUCE = (PASS == kP1 || PASS == kEval || PASS == kCheck);
+  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  __shared__ __align__(16) T lds[C * LY * LX];
+  __shared__ double red[3 * (NT / 64)];
+
+  DevStatus* __restrict__ st = a.st;
+  if (PASS != kEval && st->done) return;
+  const long long step = st->step;
+  const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
+  const bool arrest = STAGED ? (st->arrest != 0) : false;
+  const InstView<T> V = view_of<T>(a.B, a.cf);
+
+  double e_acc = 0.0, g_acc = 0.0;
+  int nf = 0;
+  const int ntiles = a.ntx * a.nty;
+  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int per = (ntiles + 7) >> 3;
+  const int tend = min(ntiles, (xcd + 1) * per);
+  for (int t = xcd * per + q; t < tend; t += m) {
+    const int tyi = t / a.ntx;
+    tile_body<T, TH, PASS, TX, TY, RY>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane,
+                                       (t - tyi * a.ntx) * TX, tyi * TY, lds, e_acc, g_acc, nf);
+  }
   if (!REDUCE) return;
 
   // ---- two-level FP64 reduction with a deterministic last-workgroup finalise
+  const int tid = threadIdx.y * TX + threadIdx.x;
   block_reduce3<NT>(e_acc, g_acc, nf, red);
   __shared__ int is_last;
   if (tid == 0) {
@@ -292,14 +446,14 @@ __global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
     p[2] = (double)nf;
     __threadfence();
     const unsigned prev = atomicAdd(&st->counter, 1u);
-    is_last = (prev == (unsigned)(a.nlaunch - 1));
+    is_last = (prev == (unsigned)(gridDim.x - 1));
   }
   __syncthreads();
   if (!is_last) return;
   __threadfence();
   double se = 0.0, sg = 0.0;
   int sn = 0;
-  for (int k = tid; k < a.nlaunch; k += NT) {
+  for (int k = tid; k < (int)gridDim.x; k += NT) {
     const double* p = a.partials + 4 * (long)k;
     se += __builtin_nontemporal_load(p);
     sg = fmax(sg, __builtin_nontemporal_load(p + 1));
@@ -307,36 +461,124 @@ __global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
   }
   __syncthreads();
   block_reduce3<NT>(se, sg, sn, red);
-  if (tid == 0) {
-    const double E = h * h * se;
-    st->counter = 0u;
-    if (PASS == kEval) {
-      st->eval_E = E;
-      st->eval_gmax = sg;
-      st->nonfinite = sn;
-    } else {
-      const int arr = (E > st->E_prev) ? 1 : 0;
-      st->arrest = arr;
-      if (arr) st->n_arrests += 1;
-      st->E_prev = E;
-      st->E = E;
-      st->gmax = sg;
-      st->nonfinite = sn;
-      const long long s0 = st->step;
-      st->hist[s0 % kHistLen] = E;
-      int done = 0;
-      if (sn > 0) {
-        done = 4;
-      } else if (st->minimise) {
-        const int W = st->window;
-        if (sg < st->grad_tol) done = 1;
-        else if (W > 0 && s0 >= W && fabs(E - st->hist[(s0 - W) % kHistLen]) <= st->rel_e_tol * fabs(E)) done = 2;
-        else if (s0 >= st->max_steps) done = 3;
-      }
-      if (done) st->done = done;
-      else if (PASS == kP1) st->step = s0 + 1;
+  if (tid == 0) finalise_status<PASS>(st, a.cf.h * a.cf.h * se, sg, sn);
+}
+
+// ------------------------------------------------------------------ batching
+// Many independent lattices (uneven sizes and couplings) stepped by one launch
+// per pass. Global tile g belongs to instance tile_inst[g]; the launch walks
+// the work list work[0 .. *nwork) (the tiles of the instances still running,
+// rebuilt by the host between graph replays). Reductions are per instance:
+// each tile writes its own partial, and the workgroup finishing the last tile
+// of an instance sums that instance's partials in tile order and updates the
+// instance's status.
+template <class T>
+struct BatchInst {
+  InstView<T> V;
+  DevStatus* st;
+  int ntx, nty;
+  int tile0, ntiles;
+};
+
+template <class T>
+struct BatchArgs {
+  const BatchInst<T>* inst;
+  const int* work;
+  const int* nwork;
+  const int* tile_inst;
+  double* partials;  // 4 doubles per global tile
+};
+
+template <class T, int TH, int PASS, int TX, int TY, int RY>
+__global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
+  constexpr int C = NComp<TH>::value;
+  constexpr int LX = TX + 4, LY = TY + 4;
+  constexpr int NT = TX * (TY / RY);
+  constexpr bool REDUCE = (PASS == kP1 || PASS == kCheck);
+  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  __shared__ __align__(16) T lds[C * LY * LX];
+  __shared__ double red[3 * (NT / 64)];
+  __shared__ int is_last;
+  const int tid = threadIdx.y * TX + threadIdx.x;
+
+  const int nwork = *a.nwork;
+  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, qb = blockIdx.x >> 3;
+  const int per = (nwork + 7) >> 3;
+  const int wend = min(nwork, (xcd + 1) * per);
+  for (int w = xcd * per + qb; w < wend; w += m) {
+    const int g = a.work[w];
+    const int i = a.tile_inst[g];
+    const BatchInst<T>& I = a.inst[i];
+    DevStatus* __restrict__ st = I.st;
+    if (st->done) continue;
+    const long long step = st->step;
+    const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
+    const bool arrest = STAGED ? (st->arrest != 0) : false;
+    const int l = g - I.tile0;
+    const int tyi = l / I.ntx;
+    double e_acc = 0.0, g_acc = 0.0;
+    int nf = 0;
+    tile_body<T, TH, PASS, TX, TY, RY>(I.V, cur, arrest, nullptr, nullptr, 0, 0, (l - tyi * I.ntx) * TX, tyi * TY,
+                                       lds, e_acc, g_acc, nf);
+    if (!REDUCE) continue;
+    block_reduce3<NT>(e_acc, g_acc, nf, red);
+    if (tid == 0) {
+      double* p = a.partials + 4 * (long)g;
+      p[0] = e_acc;
+      p[1] = g_acc;
+      p[2] = (double)nf;
+      __threadfence();
+      const unsigned prev = atomicAdd(&st->counter, 1u);
+      is_last = (prev == (unsigned)(I.ntiles - 1));
     }
+    __syncthreads();
+    if (is_last) {
+      __threadfence();
+      double se = 0.0, sg = 0.0;
+      int sn = 0;
+      for (int k = tid; k < I.ntiles; k += NT) {
+        const double* p = a.partials + 4 * (long)(I.tile0 + k);
+        se += __builtin_nontemporal_load(p);
+        sg = fmax(sg, __builtin_nontemporal_load(p + 1));
+        sn += (int)__builtin_nontemporal_load(p + 2);
+      }
+      __syncthreads();
+      block_reduce3<NT>(se, sg, sn, red);
+      if (tid == 0) finalise_status<PASS>(st, I.V.h * I.V.h * se, sg, sn);
+    }
+    __syncthreads();
   }
+}
+
+// Zero the velocity of every batch member whose last arrest test fired.
+template <class T>
+__global__ void __launch_bounds__(256) batch_apply_arrest(const BatchInst<T>* inst, int C) {
+  const BatchInst<T>& I = inst[blockIdx.x];
+  if (!I.st->arrest) return;
+  T* v = I.V.vel[int(I.st->step & 1)];
+  const long n = (long)C * I.V.plane;
+  for (long k = threadIdx.x; k < n; k += 256) v[k] = T(0);
+}
+
+// Arm every batch member for a run (same rule for all).
+__global__ void batch_arm(DevStatus* const* st, int n, int minimise, double grad_tol, double rel_e_tol, int window,
+                          long long max_steps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    DevStatus* s = st[i];
+    s->done = 0;
+    s->minimise = minimise;
+    s->grad_tol = grad_tol;
+    s->rel_e_tol = rel_e_tol;
+    s->window = window;
+    s->max_steps = max_steps;
+  }
+}
+
+// Collect the stop flags of all batch members (host reads n ints, not n status blocks).
+__global__ void batch_done_flags(DevStatus* const* st, int n, int* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = st[i]->done;
 }
 
 // Zero the velocity of the current field if the last arrest test fired.

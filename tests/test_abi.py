@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     src = open(os.path.join(ROOT, "include", "ss.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = set(re.findall(r"^\s*(?:const\s+)?(?:int|void|double|char\s*\*|const char\s*\*)\s*\**\s*(ss_\w+)\s*\(",
+    names = set(re.findall(r"^\s*(?:const\s+)?(?:int|void|double|char|ss_ctx)\s*\**\s*(ss_\w+)\s*\(",
                            src, flags=re.M))
     return names
 
@@ -45,12 +45,12 @@ def test_theory_registry_names_and_aliases(L):
 
 
 def test_workspace_bytes_grow_with_size_and_dtype(L):
-    a = ss.ss_workspace_bytes("AH", 64, 64, ss.SS_F32)
-    b = ss.ss_workspace_bytes("AH", 128, 64, ss.SS_F32)
-    c = ss.ss_workspace_bytes("AH", 64, 64, ss.SS_F64)
+    a = ss.ss_workspace_bytes("AH", 256, 64, ss.SS_F32)
+    b = ss.ss_workspace_bytes("AH", 512, 64, ss.SS_F32)
+    c = ss.ss_workspace_bytes("AH", 256, 64, ss.SS_F64)
     assert a < b and a < c
     # seven C-plane field sets (phi x2, v x2, a1, a2, q) dominate
-    assert b >= 7 * 4 * (128 + 4) * (64 + 4) * 4
+    assert b >= 7 * 4 * (512 + 4) * (64 + 4) * 4
 
 
 @pytest.mark.parametrize("args,code", [

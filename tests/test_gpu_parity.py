@@ -323,3 +323,35 @@ def test_large_lattice_sampled_parity(ss, orc):
     info = s.flow_step(3)
     assert info["nonfinite"] == 0 and info["step"] == 3
     s.close()
+
+
+@pytest.mark.parametrize("theory,dtype", [(AH, "f32"), (CM, "f64")])
+def test_every_tile_shape_matches_oracle(ss, theory, dtype, orc):
+    """Each compiled tile shape gives the oracle's flow (ragged lattice)."""
+    Nx, Ny, h = 150, 37, 0.17
+    f = _field(theory, Nx, Ny, h, seed=21)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), 4)
+    rel = 1e-11 if dtype == "f64" else 1e-5
+    for tile in range(ss.ss_tile_count()):
+        s = _solver(ss, theory, f, h, dtype)
+        s.set_tile(tile)
+        s.set_field(f)
+        info = s.flow_step(4)
+        phi = _as_np(s.get_field())
+        assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max(), tile
+        assert info["energy"] == pytest.approx(E_r, rel=1e-12 if dtype == "f64" else 1e-6)
+        s.close()
+
+
+def test_autotune_picks_a_shape_and_leaves_a_usable_context(ss, orc):
+    Nx, Ny, h = 256, 96, 0.2
+    f = _field(AH, Nx, Ny, h, seed=5).astype(np.float32).astype(np.float64)
+    s = _solver(ss, AH, f, h, "f32")
+    best, ms = s.autotune(3)
+    assert 0 <= best < ss.ss_tile_count() and ms[best] == min(ms) and all(m > 0 for m in ms)
+    s.set_field(f)
+    E, _, _ = s.energy_grad(want_grad=False)
+    assert E == pytest.approx(orc.energy(AH, f, h, [1.0]), rel=1e-12)
+    s.close()
