@@ -38,7 +38,61 @@ WORKLOADS = {
     "cm512": dict(theory="chiral_magnet", N=512, h=0.05, seed=2, dtype="f32"),
     "ah128": dict(theory="abelian_higgs", N=128, h=0.1, kappa=2 ** -0.5, nv=1, seed=1, dtype="f64"),
     "batch256": dict(theory="abelian_higgs", n=256, base_seed=3000, h=0.2, dtype="f32"),
+    "unet256": dict(levels=4, base=32, cin=2, cout=4, N=8, H=256, W=256),
 }
+
+BF16_DENSE_PEAK_TFLOPS = 2500.0
+
+
+def run_unet(args, wl):
+    """Training throughput of the learned initialiser's U-Net (BF16 MFMA, FP32
+    accumulate): forward + backward + Adam on batches of 8 images of 256^2."""
+    import numpy as np
+    import torch
+    import paper_2603_24370_amd as ss
+    net = ss.Net(wl["levels"], wl["base"], wl["cin"], wl["cout"], wl["N"], wl["H"], wl["W"])
+    rng = np.random.default_rng(0)
+    # He-uniform weights, zero biases, in the exchange order
+    from paper_2603_24370_amd.learned import unet_param_shapes
+    flat = []
+    for name, shp in unet_param_shapes(wl["levels"], wl["base"], wl["cin"], wl["cout"]):
+        if name.endswith(".b"):
+            flat.append(np.zeros(int(np.prod(shp))))
+        else:
+            lim = np.sqrt(6.0 / int(np.prod(shp[1:])))
+            flat.append(rng.uniform(-lim, lim, size=int(np.prod(shp))))
+    net.set_weights(np.concatenate(flat).astype(np.float32))
+    x = torch.randn((wl["N"], wl["H"], wl["W"], wl["cin"]), device="cuda:0")
+    t = torch.randn((wl["N"], wl["H"], wl["W"], wl["cout"]), device="cuda:0")
+    for _ in range(args.warmup):
+        net.train_step(x, t, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(x, t, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    f_fwd, f_bwd = net.flops()
+    tfl = args.steps * wl["N"] * (f_fwd + f_bwd) / el / 1e12
+    # inference alone
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    el_f = time.perf_counter() - t1
+    tfl_f = args.steps * wl["N"] * f_fwd / el_f / 1e12
+    out = {"metric": "training images/s", "value": args.steps * wl["N"] / el, "unit": "images/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)",
+           "data": "synthetic", "config": {"workload": "unet256", **wl},
+           "roofline": {"bound": "mfma", "achieved": round(tfl, 2), "peak": BF16_DENSE_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tfl / BF16_DENSE_PEAK_TFLOPS, 4), "traffic": None,
+                        "kernel": "conv3x3_mfma + conv3x3_wgrad (whole training step)",
+                        "inference_TFLOPs": round(tfl_f, 2)},
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+    net.close()
 
 
 def run_batch(args, wl):
@@ -179,6 +233,9 @@ def main():
     wl = WORKLOADS[args.workload]
     if args.workload.startswith("batch"):
         run_batch(args, wl)
+        return
+    if args.workload.startswith("unet"):
+        run_unet(args, wl)
         return
     s, params, tune = make_solver(wl, args.autotune_steps)
     N = wl["N"]

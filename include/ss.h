@@ -88,6 +88,7 @@ extern "C" {
 #define SS_STOP_STALL 2
 #define SS_STOP_MAXSTEPS 3
 #define SS_STOP_NONFINITE 4
+#define SS_STOP_TARGET 5
 
 typedef struct ss_ctx ss_ctx;
 
@@ -116,6 +117,7 @@ typedef struct {
  *   gnorm_inf < grad_tol                                    (SS_STOP_GRAD)
  *   window > 0, step >= window and
  *   |E(step) - E(step - window)| <= rel_e_tol |E(step)|     (SS_STOP_STALL)
+ *   E(step) <= the context's energy target (ss_set_energy_target)  (SS_STOP_TARGET)
  *   step >= max_steps                                        (SS_STOP_MAXSTEPS)
  * graph_steps: flow steps per replayed HIP graph (0 = library default; an even
  * number). window <= 128. */
@@ -225,6 +227,30 @@ int ss_minimise(ss_ctx* ctx, const ss_stop* stop, ss_min_info* info);
 
 /* Observables of the current field. Synchronises. */
 int ss_observables(ss_ctx* ctx, ss_obs* out);
+
+/* Energy target of the minimise stop rule SS_STOP_TARGET (E <= e_target);
+ * -infinity (the value after ss_set_field / ss_init_*) disables it. Used to
+ * time the flow to a reference energy. Synchronises. */
+int ss_set_energy_target(ss_ctx* ctx, double e_target);
+
+/* ------------------------------------------- learned initialiser (Abelian Higgs)
+ * The network (include/ssn.h) maps an input image to smooth corrections of the
+ * vortex ansatz. Images are fp32 device arrays over the interior grid, row-major
+ * (Ny, Nx, channels):
+ *   ss_learned_input:   (Ny, Nx, 2): sum_k exp(-r_k^2 / 2) at the n centres xy
+ *                       (host, lattice coordinates), and the constant kappa;
+ *   ss_learned_targets: (Ny, Nx, 4) from the context's current field psi, A:
+ *                       |psi| - f_ans, wrap(arg psi - sum_k w_k theta_k) to
+ *                       [-pi, pi), A_x - A_ans_x, A_y - A_ans_y, with the
+ *                       ansatz of ss_init_ansatz for the same centres and windings;
+ *   ss_init_learned:    sets psi = (f_ans + c0) exp(i (sum w_k theta_k + c1)),
+ *                       A = A_ans + (c2, c3) on the interior from corrections
+ *                       corr (Ny, Nx, 4), the vacuum on the halo, and starts the
+ *                       flow from rest (as ss_set_field).
+ * The first two synchronise. */
+int ss_learned_input(ss_ctx* ctx, int n, const double* xy, double kappa, float* out);
+int ss_learned_targets(ss_ctx* ctx, int n, const double* xy, const double* w, float* out);
+int ss_init_learned(ss_ctx* ctx, int n, const double* xy, const double* w, const float* corr);
 
 /* Tile shapes of the fused stage kernels. The library carries ss_tile_count()
  * compiled shapes (a workgroup covers TX x TY sites, each thread RY rows of

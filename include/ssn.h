@@ -1,0 +1,70 @@
+/*
+ * ssn.h -- C ABI of the learned initialiser's network (BF16 MFMA, gfx950).
+ *
+ * A U-Net (Ronneberger, Fischer and Brox 2015) with `levels` resolution
+ * levels and `base` channels at the top (doubling per level): per encoder
+ * level two 3x3 convolutions with SiLU, kept as the skip, then 2x2 average
+ * pooling; a bottleneck of two 3x3 convolutions; per decoder level a nearest
+ * 2x upsampling, concatenation [upsampled, skip], two 3x3 convolutions with
+ * SiLU; a 1x1 head to `cout` channels. Convolutions are zero-padded with bias.
+ * It maps the vortex image of ss_learned_input (cin = 2) to the corrections
+ * of ss_init_learned (cout = 4); it is not part of the paper's method but the
+ * learned start of this project's minimisation workloads.
+ *
+ * Arithmetic: activations and weights BF16, products on v_mfma_f32_32x32x16_bf16
+ * with FP32 accumulation; master weights, gradients and Adam moments FP32;
+ * reductions in fixed order (a run is bitwise repeatable).
+ *
+ * Memory: images are fp32 device arrays (n, H, W, channels) row-major. The
+ * caller owns the workspace (ssn_workspace_bytes, 256-byte aligned) and all
+ * device buffers; the library owns the host object. Work is queued on the
+ * stream given to ssn_create; calls returning host data synchronise it.
+ * Parameters are exchanged as one flat fp32 host array in the order: for
+ * each 3x3 layer (encoder levels top-down, bottleneck, decoder levels
+ * bottom-up, each level "a" then "b") weight [co][ky][kx][ci] then bias [co];
+ * then the head weight [cout][base] and bias [cout].
+ * Errors: 0 OK, negative codes of ss.h; ssn_last_error() gives the message.
+ */
+#ifndef SSN_H
+#define SSN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssn_net ssn_net;
+
+/* Number of parameters in the flat exchange order. */
+long ssn_param_count(int levels, int base, int cin, int cout);
+/* Workspace for batches of up to N images of H x W (H, W multiples of
+ * 16 * 2^(levels-1); base a multiple of 16; cin <= 16; cout * base <= 256). */
+int ssn_workspace_bytes(int levels, int base, int cin, int cout, int N, int H, int W, size_t* bytes);
+int ssn_create(int levels, int base, int cin, int cout, int N, int H, int W, void* workspace, size_t ws_bytes,
+               void* stream, ssn_net** out);
+void ssn_destroy(ssn_net* net);
+long ssn_num_params(ssn_net* net);
+/* Set all parameters from a host array (also resets the Adam state); read them back. */
+int ssn_set_weights(ssn_net* net, const float* host, long count);
+int ssn_get_weights(ssn_net* net, float* host, long count);
+/* Gradients of the last ssn_backward, same order. */
+int ssn_get_grads(ssn_net* net, float* host, long count);
+/* Forward pass of n <= N images x (n, H, W, cin); the output (n, H, W, cout)
+ * is kept for ssn_backward and copied to out if out != NULL. */
+int ssn_forward(ssn_net* net, const float* x, int n, float* out);
+/* Gradients of the mean squared error between the last output and target
+ * (n, H, W, cout); *loss (may be NULL) receives the loss (synchronises). */
+int ssn_backward(ssn_net* net, const float* target, int n, double* loss);
+/* One Adam step (Kingma and Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. */
+int ssn_adam_step(ssn_net* net, float lr);
+/* forward + backward + Adam. */
+int ssn_train_step(ssn_net* net, const float* x, const float* target, int n, float lr, double* loss);
+/* Multiply-add flops (2 per MAC) of one image's forward and backward passes. */
+int ssn_flops(ssn_net* net, double* fwd, double* bwd);
+const char* ssn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SSN_H */

@@ -20,7 +20,7 @@ SS_F32, SS_F64 = 0, 1
 SS_GRAD_EL, SS_GRAD_EXACT = 0, 1
 SS_THEORY_AH, SS_THEORY_CM = 0, 1
 SS_ANSATZ_VORTICES, SS_ANSATZ_SKYRMION = 0, 1
-STOP_REASONS = {0: "none", 1: "grad", 2: "stall", 3: "max_steps", 4: "nonfinite"}
+STOP_REASONS = {0: "none", 1: "grad", 2: "stall", 3: "max_steps", 4: "nonfinite", 5: "target"}
 
 
 class ss_params(ctypes.Structure):
@@ -71,7 +71,11 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_status_string", "ss_last_error", "ss_gl_lambda_from_kappa", "ss_tile_count", "ss_tile_shape",
            "ss_set_tile", "ss_get_tile", "ss_autotune", "ss_batch_workspace_bytes", "ss_batch_create",
            "ss_batch_destroy", "ss_batch_member", "ss_batch_size", "ss_batch_flow_step", "ss_batch_minimise",
-           "ss_batch_set_tile", "ss_batch_autotune"]
+           "ss_batch_set_tile", "ss_batch_autotune", "ss_set_energy_target", "ss_learned_input",
+           "ss_learned_targets", "ss_init_learned"]
+SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
+               "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_backward", "ssn_adam_step",
+               "ssn_train_step", "ssn_flops", "ssn_last_error"]
 
 _lib = None
 
@@ -392,6 +396,9 @@ class Solver:
     def set_tile(self, tile):
         ss_set_tile(self.ctx, tile)
 
+    def set_energy_target(self, e_target):
+        ss_set_energy_target(self.ctx, e_target)
+
     def time_passes(self, n_steps):
         return ss_time_passes(self.ctx, n_steps)
 
@@ -481,6 +488,155 @@ class Batch:
                 m.ctx = None
             ss_batch_destroy(self.batch)
             self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------ learned initialiser (C ABI)
+
+def _ssn_lib():
+    L = lib()
+    if getattr(L, "_ssn_ready", False):
+        return L
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    fp = ctypes.POINTER(ctypes.c_float)
+    dp = ctypes.POINTER(d)
+    L.ss_set_energy_target.argtypes = [vp, d]
+    L.ss_learned_input.argtypes = [vp, i, dp, d, vp]
+    L.ss_learned_targets.argtypes = [vp, i, dp, dp, vp]
+    L.ss_init_learned.argtypes = [vp, i, dp, dp, vp]
+    L.ssn_param_count.argtypes = [i, i, i, i]
+    L.ssn_param_count.restype = ctypes.c_long
+    L.ssn_workspace_bytes.argtypes = [i, i, i, i, i, i, i, ctypes.POINTER(ctypes.c_size_t)]
+    L.ssn_create.argtypes = [i, i, i, i, i, i, i, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.ssn_destroy.argtypes = [vp]
+    L.ssn_destroy.restype = None
+    L.ssn_num_params.argtypes = [vp]
+    L.ssn_num_params.restype = ctypes.c_long
+    L.ssn_set_weights.argtypes = [vp, fp, ctypes.c_long]
+    L.ssn_get_weights.argtypes = [vp, fp, ctypes.c_long]
+    L.ssn_get_grads.argtypes = [vp, fp, ctypes.c_long]
+    L.ssn_forward.argtypes = [vp, vp, i, vp]
+    L.ssn_backward.argtypes = [vp, vp, i, dp]
+    L.ssn_adam_step.argtypes = [vp, ctypes.c_float]
+    L.ssn_train_step.argtypes = [vp, vp, vp, i, ctypes.c_float, dp]
+    L.ssn_flops.argtypes = [vp, dp, dp]
+    L.ssn_last_error.argtypes = []
+    L.ssn_last_error.restype = ctypes.c_char_p
+    L._ssn_ready = True
+    return L
+
+
+def _ncheck(rc):
+    if rc < 0:
+        raise SSError(rc, _ssn_lib().ssn_last_error().decode() or lib().ss_last_error().decode())
+    return rc
+
+
+def ss_set_energy_target(ctx, e_target):
+    _check(_ssn_lib().ss_set_energy_target(ctx, float(e_target)))
+
+
+def ss_learned_input(ctx, centres, kappa, out_ptr):
+    flat = [float(v) for p in centres for v in p]
+    _check(_ssn_lib().ss_learned_input(ctx, len(flat) // 2, _darr(flat), float(kappa), ctypes.c_void_p(out_ptr)))
+
+
+def ss_learned_targets(ctx, centres, windings, out_ptr):
+    flat = [float(v) for p in centres for v in p]
+    _check(_ssn_lib().ss_learned_targets(ctx, len(flat) // 2, _darr(flat), _darr(windings), ctypes.c_void_p(out_ptr)))
+
+
+def ss_init_learned(ctx, centres, windings, corr_ptr):
+    flat = [float(v) for p in centres for v in p]
+    _check(_ssn_lib().ss_init_learned(ctx, len(flat) // 2, _darr(flat), _darr(windings), ctypes.c_void_p(corr_ptr)))
+
+
+def ssn_param_count(levels, base, cin, cout):
+    return _ssn_lib().ssn_param_count(levels, base, cin, cout)
+
+
+class Net:
+    """The learned initialiser's U-Net (ssn_* C ABI); torch supplies memory and the stream."""
+
+    def __init__(self, levels=4, base=32, cin=2, cout=4, N=8, H=256, W=256, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the network needs a HIP GPU; none is available")
+        self.torch = torch
+        self.levels, self.base, self.cin, self.cout, self.N, self.H, self.W = levels, base, cin, cout, N, H, W
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L = _ssn_lib()
+        nb = ctypes.c_size_t(0)
+        _ncheck(L.ssn_workspace_bytes(levels, base, cin, cout, N, H, W, ctypes.byref(nb)))
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        out = ctypes.c_void_p(0)
+        _ncheck(L.ssn_create(levels, base, cin, cout, N, H, W, ctypes.c_void_p(ptr), nb.value,
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(out)))
+        self.net = out
+        self.n_params = L.ssn_num_params(self.net)
+
+    def _fp(self, a):
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+    def set_weights(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _ncheck(_ssn_lib().ssn_set_weights(self.net, self._fp(a), a.size))
+
+    def get_weights(self):
+        import numpy as np
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _ncheck(_ssn_lib().ssn_get_weights(self.net, self._fp(a), a.size))
+        return a
+
+    def get_grads(self):
+        import numpy as np
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _ncheck(_ssn_lib().ssn_get_grads(self.net, self._fp(a), a.size))
+        return a
+
+    def _dev(self, x):
+        return self.torch.as_tensor(x).to(device=self.device, dtype=self.torch.float32).contiguous()
+
+    def forward(self, x):
+        x = self._dev(x)
+        n = x.shape[0]
+        out = self.torch.empty((n, self.H, self.W, self.cout), dtype=self.torch.float32, device=self.device)
+        _ncheck(_ssn_lib().ssn_forward(self.net, ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def backward(self, target):
+        t = self._dev(target)
+        loss = ctypes.c_double(0)
+        _ncheck(_ssn_lib().ssn_backward(self.net, ctypes.c_void_p(t.data_ptr()), t.shape[0], ctypes.byref(loss)))
+        return loss.value
+
+    def adam_step(self, lr):
+        _ncheck(_ssn_lib().ssn_adam_step(self.net, float(lr)))
+
+    def train_step(self, x, target, lr, want_loss=True):
+        x, t = self._dev(x), self._dev(target)
+        loss = ctypes.c_double(0)
+        _ncheck(_ssn_lib().ssn_train_step(self.net, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                          x.shape[0], float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def flops(self):
+        f, b = ctypes.c_double(0), ctypes.c_double(0)
+        _ncheck(_ssn_lib().ssn_flops(self.net, ctypes.byref(f), ctypes.byref(b)))
+        return f.value, b.value
+
+    def close(self):
+        if getattr(self, "net", None) is not None:
+            _ssn_lib().ssn_destroy(self.net)
+            self.net = None
 
     def __del__(self):
         try:

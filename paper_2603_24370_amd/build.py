@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libss.so")
-SOURCES = ["ss_api.hip"]
+SOURCES = ["ss_api.hip", "ssn_unet.hip"]
 HEADERS = ["ss_internal.hpp", "ss_theory.hpp", "ss_kernels.hpp"]
 
 HIPCC_FLAGS = [

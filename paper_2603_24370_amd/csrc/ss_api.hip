@@ -70,6 +70,7 @@ constexpr int kMaxVortices = 8192;
 
 struct Layout {
   long pitch, plane;        // elements
+  long col0;                // element offset of padded column 0 from the set base
   size_t set_bytes;         // bytes of one C-plane field set (256-B aligned)
   size_t status_off, partial_off, init_off, total;
   int ntx, nty, nlaunch;    // for the selected tile shape
@@ -86,9 +87,14 @@ Layout make_layout(int C, int Nx, int Ny, int esize) {
   Layout L;
   // 16-byte staging loads of a tile row may run up to roundup(Nx, TX) + 4
   // columns for any tile width TX dividing 256; keep them inside the row
-  L.pitch = round_up(Nx, 256) + 64;
+  // Interior column 0 of every row sits on a 128-byte line: padded column 0
+  // (the first halo column) is at element col0 = 128 / esize - 2 of the row, so
+  // a wave's row of loads or stores covers whole lines. The kernels address a
+  // set through a base pointer shifted by col0.
+  L.col0 = 128 / esize - 2;
+  L.pitch = round_up(L.col0 + round_up(Nx, 256) + 4, 64);
   L.plane = round_up(L.pitch * (Ny + 4), 64);
-  L.set_bytes = (size_t)round_up((long)C * L.plane * esize, 256);
+  L.set_bytes = (size_t)round_up(((long)C * L.plane + L.col0) * esize, 256);
   set_tiles(L, Nx, Ny, kDefaultTile);
   L.status_off = 7 * L.set_bytes;
   L.partial_off = L.status_off + (size_t)round_up(sizeof(DevStatus), 256);
@@ -243,11 +249,12 @@ size_t esize_of(int dtype) { return dtype == SS_F32 ? 4 : 8; }
 
 // Start from rest (Sec. 3.2): zero velocity and stage arrays, reset counters.
 int reset_state(ss_ctx* c) {
-  SS_HIP(hipMemsetAsync(c->vel[0], 0, 5 * c->L.set_bytes, c->stream));
+  SS_HIP(hipMemsetAsync(c->ws + 2 * c->L.set_bytes, 0, 5 * c->L.set_bytes, c->stream));
   DevStatus s;
   std::memset(&s, 0, sizeof(s));
   s.E = s.E_prev = std::numeric_limits<double>::infinity();
   s.gmax = std::numeric_limits<double>::infinity();
+  s.e_target = -std::numeric_limits<double>::infinity();
   SS_HIP(hipMemcpyAsync(c->st, &s, sizeof(s), hipMemcpyHostToDevice, c->stream));
   SS_HIP(hipStreamSynchronize(c->stream));
   return SS_OK;
@@ -327,7 +334,7 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   c->ws = (char*)workspace;
   c->L = make_layout(c->C, Nx, Ny, (int)esize_of(dtype));
   void** sets[7] = {&c->phi[0], &c->phi[1], &c->vel[0], &c->vel[1], &c->a1, &c->a2, &c->q};
-  for (int k = 0; k < 7; ++k) *sets[k] = c->ws + k * c->L.set_bytes;
+  for (int k = 0; k < 7; ++k) *sets[k] = c->ws + k * c->L.set_bytes + c->L.col0 * esize_of(dtype);
   c->st = (DevStatus*)(c->ws + c->L.status_off);
   c->partials = (double*)(c->ws + c->L.partial_off);
   c->graph = nullptr;
@@ -577,7 +584,7 @@ int ss_minimise(ss_ctx* c, const ss_stop* stop, ss_min_info* info) {
   if (info) {
     fill_info(d, &info->last);
     info->reason = d.done;
-    info->converged = (d.done == SS_STOP_GRAD || d.done == SS_STOP_STALL) ? 1 : 0;
+    info->converged = (d.done == SS_STOP_GRAD || d.done == SS_STOP_STALL || d.done == SS_STOP_TARGET) ? 1 : 0;
   }
   if (d.done == SS_STOP_NONFINITE) return fail(SS_ENONFINITE, "non-finite value in the flow");
   if (d.done == SS_STOP_MAXSTEPS) return SS_NOT_CONVERGED;
@@ -680,6 +687,81 @@ int ss_autotune(ss_ctx* c, int n_steps, double* ms_out) {
 }
 
 int ss_get_tile(ss_ctx* c) { return c ? c->tile : SS_EINVAL; }
+
+int ss_set_energy_target(ss_ctx* c, double e_target) {
+  if (!c) return fail(SS_EINVAL, "ctx is NULL");
+  SS_HIP(hipMemcpyAsync(&c->st->e_target, &e_target, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  SS_HIP(hipStreamSynchronize(c->stream));
+  return SS_OK;
+}
+
+namespace {
+// copy centres (and windings, default +1) into the workspace staging area
+int stage_centres(ss_ctx* c, int n, const double* xy, const double* w, double** dxy, double** dw) {
+  if (n < 0 || n > kMaxVortices || (n > 0 && !xy)) return fail(SS_EINVAL, "bad vortex list");
+  std::vector<double> host(3 * (size_t)std::max(n, 1), 0.0);
+  for (int k = 0; k < n; ++k) {
+    host[2 * k] = xy[2 * k];
+    host[2 * k + 1] = xy[2 * k + 1];
+    host[2 * (size_t)n + k] = w ? w[k] : 1.0;
+  }
+  double* dev = (double*)(c->ws + c->L.init_off);
+  SS_HIP(hipMemcpyAsync(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  *dxy = dev;
+  *dw = dev + 2 * (size_t)n;
+  return SS_OK;
+}
+}  // namespace
+
+int ss_learned_input(ss_ctx* c, int n, const double* xy, double kappa, float* out) {
+  if (!c || !out) return fail(SS_EINVAL, "ctx or out is NULL");
+  double *dxy, *dw;
+  int rc = stage_centres(c, n, xy, nullptr, &dxy, &dw);
+  if (rc) return rc;
+  const long sites = (long)c->Nx * c->Ny;
+  hipLaunchKernelGGL(learned_input, dim3((unsigned)((sites + 255) / 256)), dim3(256), 0, c->stream, c->Nx, c->Ny,
+                     c->h, (const double*)dxy, n, kappa, out);
+  SS_HIP(hipGetLastError());
+  SS_HIP(hipStreamSynchronize(c->stream));
+  return SS_OK;
+}
+
+int ss_learned_targets(ss_ctx* c, int n, const double* xy, const double* w, float* out) {
+  if (!c || !out) return fail(SS_EINVAL, "ctx or out is NULL");
+  if (c->theory != SS_THEORY_AH) return fail(SS_EINVAL, "learned targets exist for the Abelian Higgs model only");
+  double *dxy, *dw;
+  int rc = stage_centres(c, n, xy, w, &dxy, &dw);
+  if (rc) return rc;
+  const long sites = (long)c->Nx * c->Ny;
+  const dim3 g((unsigned)((sites + 255) / 256));
+  if (c->dtype == SS_F32)
+    hipLaunchKernelGGL((learned_targets<float>), g, dim3(256), 0, c->stream, bufs_of<float>(c), coeffs_of(c), c->st,
+                       (const double*)dxy, (const double*)dw, n, out);
+  else
+    hipLaunchKernelGGL((learned_targets<double>), g, dim3(256), 0, c->stream, bufs_of<double>(c), coeffs_of(c), c->st,
+                       (const double*)dxy, (const double*)dw, n, out);
+  SS_HIP(hipGetLastError());
+  SS_HIP(hipStreamSynchronize(c->stream));
+  return SS_OK;
+}
+
+int ss_init_learned(ss_ctx* c, int n, const double* xy, const double* w, const float* corr) {
+  if (!c || !corr) return fail(SS_EINVAL, "ctx or corrections are NULL");
+  if (c->theory != SS_THEORY_AH) return fail(SS_EINVAL, "the learned start exists for the Abelian Higgs model only");
+  double *dxy, *dw;
+  int rc = stage_centres(c, n, xy, w, &dxy, &dw);
+  if (rc) return rc;
+  const long sites = (long)(c->Nx + 4) * (c->Ny + 4);
+  const dim3 g((unsigned)((sites + 255) / 256));
+  if (c->dtype == SS_F32)
+    hipLaunchKernelGGL((init_learned<float>), g, dim3(256), 0, c->stream, bufs_of<float>(c), coeffs_of(c),
+                       (const double*)dxy, (const double*)dw, n, corr);
+  else
+    hipLaunchKernelGGL((init_learned<double>), g, dim3(256), 0, c->stream, bufs_of<double>(c), coeffs_of(c),
+                       (const double*)dxy, (const double*)dw, n, corr);
+  SS_HIP(hipGetLastError());
+  return reset_state(c);
+}
 
 int ss_get_info(ss_ctx* c, ss_step_info* info) {
   if (!c || !info) return fail(SS_EINVAL, "ctx or info is NULL");
@@ -1105,7 +1187,7 @@ int ss_batch_minimise(ss_batch* b, const ss_stop* stop, ss_min_info* infos) {
     if (infos) {
       fill_info(d, &infos[i].last);
       infos[i].reason = d.done;
-      infos[i].converged = (d.done == SS_STOP_GRAD || d.done == SS_STOP_STALL) ? 1 : 0;
+      infos[i].converged = (d.done == SS_STOP_GRAD || d.done == SS_STOP_STALL || d.done == SS_STOP_TARGET) ? 1 : 0;
     }
     if (d.done == SS_STOP_NONFINITE) worst = SS_ENONFINITE;
     else if (d.done == SS_STOP_MAXSTEPS && worst == SS_OK) worst = SS_NOT_CONVERGED;

@@ -31,6 +31,7 @@ struct DevStatus {
   unsigned counter;      // last-block counter of the arrest pass
   unsigned counter_obs;  // last-block counter of the observable passes
   int pad_;
+  double e_target;       // minimise stops once E <= e_target (-inf: never)
   double hist[kHistLen]; // E at step s is kept at hist[s % kHistLen]
   double obs[16];        // observable sums (see ss_api)
 };

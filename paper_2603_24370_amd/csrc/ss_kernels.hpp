@@ -161,8 +161,10 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
 
   const int Nx = V.Nx, Ny = V.Ny;
   const long pitch = V.pitch, plane = V.plane;
-  const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : V.phi[cur];
-  const T* __restrict__ vv = V.vel[cur];
+  // select ping-pong buffers without indexing V's arrays by a runtime value
+  // (that would place V in private scratch memory)
+  const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : (cur ? V.phi[1] : V.phi[0]);
+  const T* __restrict__ vv = cur ? V.vel[1] : V.vel[0];
   const T* __restrict__ aa = (PASS == kP3) ? V.a1 : V.a2;
   const T dt = (T)V.dt;
   T cv = T(0), ca = T(0);
@@ -290,9 +292,11 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
     }
   }
 
-  // ---- gradient and pass epilogue
-  T* __restrict__ phn = V.phi[cur ^ 1];
-  T* __restrict__ vn = V.vel[cur ^ 1];
+  // ---- gradient and pass epilogue. Outputs are streamed with non-temporal stores,
+  // and arrays read only at a thread's own sites with non-temporal loads, so
+  // that L2 keeps the staged arrays whose halo rows neighbouring tiles re-read.
+  T* __restrict__ phn = cur ? V.phi[0] : V.phi[1];
+  T* __restrict__ vn = cur ? V.vel[0] : V.vel[1];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int gj = y0 + ly0 - 2 + r;
@@ -319,7 +323,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
     }
     if (PASS == kP1) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) V.a1[c * plane + off] = -G[c];
+      for (int c = 0; c < C; ++c) __builtin_nontemporal_store(-G[c], &V.a1[c * plane + off]);
     } else if (PASS == kEval) {
       if (out != nullptr) {
         const long o = (long)(gj + 2) * out_pitch + (gi + 2);
@@ -328,13 +332,13 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
       }
     } else if (PASS == kP2) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) V.a2[c * plane + off] = -G[c];
+      for (int c = 0; c < C; ++c) __builtin_nontemporal_store(-G[c], &V.a2[c * plane + off]);
     } else if (PASS == kP3) {
       // q = a1 + 2 a2 + 2 a3; a1 (a raw stage input) is in registers
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const long k = c * plane + off;
-        V.q[k] = ra[r][c] + T(2) * V.a2[k] - T(2) * G[c];
+        __builtin_nontemporal_store(ra[r][c] + T(2) * __builtin_nontemporal_load(&V.a2[k]) - T(2) * G[c], &V.q[k]);
       }
     } else if (PASS == kP4) {
       T pn[4], vnew[4];
@@ -342,8 +346,8 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
       for (int c = 0; c < C; ++c) {
         const long k = c * plane + off;
         const T v0 = arrest ? T(0) : rv[r][c];
-        const T qq = V.q[k];
-        pn[c] = rp[r][c] + dt * v0 + (dt * dt / T(12)) * (qq + V.a1[k]);
+        const T qq = __builtin_nontemporal_load(&V.q[k]);
+        pn[c] = rp[r][c] + dt * v0 + (dt * dt / T(12)) * (qq + __builtin_nontemporal_load(&V.a1[k]));
         vnew[c] = v0 + (dt / T(6)) * (qq - G[c]);
       }
       if (TH == 1) {
@@ -357,8 +361,8 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         const long k = c * plane + off;
-        phn[k] = pn[c];
-        vn[k] = vnew[c];
+        __builtin_nontemporal_store(pn[c], &phn[k]);
+        __builtin_nontemporal_store(vnew[c], &vn[k]);
       }
     }
   }
@@ -393,6 +397,7 @@ __device__ __forceinline__ void finalise_status(DevStatus* st, double E, double 
     const int W = st->window;
     if (gmax < st->grad_tol) done = 1;
     else if (W > 0 && s0 >= W && fabs(E - st->hist[(s0 - W) % kHistLen]) <= st->rel_e_tol * fabs(E)) done = 2;
+    else if (E <= st->e_target) done = 5;
     else if (s0 >= st->max_steps) done = 3;
   }
   if (done) st->done = done;
@@ -851,6 +856,107 @@ __global__ void __launch_bounds__(256) init_ansatz(Bufs<T> B, Coeffs cf, InitArg
   }
   const long off = (long)jj * B.pitch + ii;
   for (int c = 0; c < C; ++c) {
+    B.phi[0][c * B.plane + off] = (T)out[c];
+    B.phi[1][c * B.plane + off] = (T)out[c];
+  }
+}
+
+// ------------------------------------------------------- learned initialiser
+// Network input on the interior grid (Ny x Nx x 2, fp32, row-major):
+// channel 0 = sum_k exp(-r_k^2 / 2) (unit Gaussians at the vortex centres),
+// channel 1 = kappa.
+__global__ void __launch_bounds__(256) learned_input(int Nx, int Ny, double h, const double* xy, int n, double kappa,
+                                                     float* out) {
+  const long k = blockIdx.x * 256L + threadIdx.x;
+  if (k >= (long)Nx * Ny) return;
+  const int j = (int)(k / Nx), i = (int)(k - (long)j * Nx);
+  const double x = (i - 0.5 * (Nx - 1)) * h, y = (j - 0.5 * (Ny - 1)) * h;
+  double b = 0.0;
+  for (int v = 0; v < n; ++v) {
+    const double dx = x - xy[2 * v], dy = y - xy[2 * v + 1];
+    b += exp(-0.5 * (dx * dx + dy * dy));
+  }
+  out[2 * k] = (float)b;
+  out[2 * k + 1] = (float)kappa;
+}
+
+// Ansatz modulus, phase and gauge field at one point (product ansatz of the
+// Abelian-Higgs vortices, as in init_ansatz).
+__device__ __forceinline__ void ah_ansatz_parts(double x, double y, const double* xy, const double* w, int n,
+                                                double& mod, double& ph, double& ax, double& ay) {
+  mod = 1.0; ph = 0.0; ax = 0.0; ay = 0.0;
+  for (int v = 0; v < n; ++v) {
+    const double dx = x - xy[2 * v], dy = y - xy[2 * v + 1], wv = w[v];
+    const double r2 = dx * dx + dy * dy;
+    ph += wv * atan2(dy, dx);
+    mod *= tanh(sqrt(r2));
+    const double prof = r2 > 1e-300 ? -expm1(-r2) / r2 : 1.0;
+    ax += wv * prof * (-dy);
+    ay += wv * prof * dx;
+  }
+}
+
+// Training target of a relaxed field: (|psi| - f_ans, wrap(arg psi - sum theta),
+// A_x - A_ans_x, A_y - A_ans_y) at every interior site (Ny x Nx x 4, fp32).
+template <class T>
+__global__ void __launch_bounds__(256) learned_targets(Bufs<T> B, Coeffs cf, const DevStatus* st, const double* xy,
+                                                       const double* w, int n, float* out) {
+  const long k = blockIdx.x * 256L + threadIdx.x;
+  if (k >= (long)B.Nx * B.Ny) return;
+  const int j = (int)(k / B.Nx), i = (int)(k - (long)j * B.Nx);
+  const double x = (i - 0.5 * (B.Nx - 1)) * cf.h, y = (j - 0.5 * (B.Ny - 1)) * cf.h;
+  double mod, ph, ax, ay;
+  ah_ansatz_parts(x, y, xy, w, n, mod, ph, ax, ay);
+  const T* f = st->step & 1 ? B.phi[1] : B.phi[0];
+  const long off = (long)(j + 2) * B.pitch + (i + 2);
+  const double p = f[off], q = f[B.plane + off];
+  double d = atan2(q, p) - ph;
+  d -= 6.283185307179586 * floor((d + 3.141592653589793) / 6.283185307179586);
+  out[4 * k] = (float)(sqrt(p * p + q * q) - mod);
+  out[4 * k + 1] = (float)d;
+  out[4 * k + 2] = (float)((double)f[2 * B.plane + off] - ax);
+  out[4 * k + 3] = (float)((double)f[3 * B.plane + off] - ay);
+}
+
+// Field from the ansatz plus predicted corrections: psi = (f_ans + c0) e^{i(theta + c1)},
+// A = A_ans + (c2, c3) on the interior; the halo gets the pure-gauge vacuum.
+template <class T>
+__global__ void __launch_bounds__(256) init_learned(Bufs<T> B, Coeffs cf, const double* xy, const double* w, int n,
+                                                    const float* corr) {
+  const long W = B.Nx + 4, H = B.Ny + 4;
+  const long k = blockIdx.x * 256L + threadIdx.x;
+  if (k >= W * H) return;
+  const int jj = (int)(k / W), ii = (int)(k - (long)jj * W);
+  const int i = ii - 2, j = jj - 2;
+  const bool inner = i >= 0 && i < B.Nx && j >= 0 && j < B.Ny;
+  const double x = (i - 0.5 * (B.Nx - 1)) * cf.h, y = (j - 0.5 * (B.Ny - 1)) * cf.h;
+  double out[4];
+  if (inner) {
+    double mod, ph, ax, ay;
+    ah_ansatz_parts(x, y, xy, w, n, mod, ph, ax, ay);
+    const float* c = corr + 4 * ((long)j * B.Nx + i);
+    const double m = mod + c[0], t = ph + c[1];
+    out[0] = m * cos(t);
+    out[1] = m * sin(t);
+    out[2] = ax + c[2];
+    out[3] = ay + c[3];
+  } else {
+    double ph = 0.0, ax = 0.0, ay = 0.0;
+    for (int v = 0; v < n; ++v) {
+      const double dx = x - xy[2 * v], dy = y - xy[2 * v + 1], wv = w[v];
+      const double r2 = dx * dx + dy * dy;
+      ph += wv * atan2(dy, dx);
+      const double prof = r2 > 1e-300 ? 1.0 / r2 : 0.0;
+      ax += wv * prof * (-dy);
+      ay += wv * prof * dx;
+    }
+    out[0] = cos(ph);
+    out[1] = sin(ph);
+    out[2] = ax;
+    out[3] = ay;
+  }
+  const long off = (long)jj * B.pitch + ii;
+  for (int c = 0; c < 4; ++c) {
     B.phi[0][c * B.plane + off] = (T)out[c];
     B.phi[1][c * B.plane + off] = (T)out[c];
   }

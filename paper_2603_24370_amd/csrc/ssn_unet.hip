@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/ss.h"
+#include "../../include/ssn.h"
 
 namespace ssn {
 
@@ -399,3 +400,519 @@ __global__ void pack_conv_weights(const float* __restrict__ w, int Co, int Ci, b
 }
 
 }  // namespace ssn
+
+// ================================================================ host side
+
+using namespace ssn;
+
+namespace {
+
+thread_local std::string g_ssn_err;
+
+int nfail(int code, const std::string& m) {
+  g_ssn_err = m;
+  return code;
+}
+
+#define SN_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return nfail(SS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+long rup(long x, long m) { return (x + m - 1) / m * m; }
+
+struct HT {  // host handle of one NHWC bf16 buffer (capacity Ncap)
+  bf16_t* p = nullptr;
+  int H = 0, W = 0, cs = 0;
+  TV view(int n, int coff, int C) const {
+    TV t;
+    t.p = p;
+    t.N = n;
+    t.H = H;
+    t.W = W;
+    t.cs = cs;
+    t.coff = coff;
+    t.C = C;
+    return t;
+  }
+  TV all(int n) const { return view(n, 0, cs); }
+};
+
+struct ConvL {
+  int Ci, Ci_real, Co, H, W;
+  long w_off, b_off;  // float offsets into the flat parameter arrays
+  bf16_t* wf;         // [rup(Co, 32)][9][Ci]
+  bf16_t* wb;         // [rup(Ci, 32)][9][Co]
+};
+
+constexpr int kPartBlocks = 64;
+constexpr long kWgradPartFloats = 1024L * 9 * 1024;
+
+}  // namespace
+
+struct ssn_net {
+  int levels, base, cin, cout, cin_pad, Ncap, H, W, L;
+  hipStream_t stream;
+  float *P, *G, *M, *V;
+  long np;
+  std::vector<ConvL> conv;  // enc0a enc0b ... mid.a mid.b dec(L-1)a dec(L-1)b ... dec0a dec0b
+  long hw_off, hb_off;
+  std::vector<int> ch;      // channels per level
+  // activations
+  HT X0;
+  std::vector<HT> ZA, AA, ZB, CAT, Pin;  // Pin[l]: pooled input of level l (l >= 1), Pin[L]: bottleneck input
+  HT ZMa, AMa, ZMb, AMb;
+  std::vector<HT> ZDa, ADa, ZDb, ADb;
+  // gradients
+  std::vector<HT> gCAT, gT1, gT2, gP;
+  HT gM1, gM2;
+  float *OUT, *GOUT, *part, *cpart;
+  double* lpart;
+  int adam_t;
+  size_t bytes;
+};
+
+namespace {
+
+// Carve (or, with base == nullptr, size) the workspace of a network.
+size_t net_carve(ssn_net* n, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t b) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += (size_t)rup((long)b, 256);
+    return p;
+  };
+  const int L = n->L, N = n->Ncap;
+  auto tensor = [&](HT& t, int H, int W, int cs) {
+    t.H = H;
+    t.W = W;
+    t.cs = cs;
+    t.p = (bf16_t*)take((size_t)N * H * W * cs * 2);
+  };
+  n->P = (float*)take(n->np * 4);
+  n->G = (float*)take(n->np * 4);
+  n->M = (float*)take(n->np * 4);
+  n->V = (float*)take(n->np * 4);
+  for (ConvL& c : n->conv) {
+    c.wf = (bf16_t*)take((size_t)rup(c.Co, 32) * 9 * c.Ci * 2);
+    c.wb = (bf16_t*)take((size_t)rup(c.Ci, 32) * 9 * c.Co * 2);
+  }
+  tensor(n->X0, n->H, n->W, n->cin_pad);
+  n->ZA.assign(L, HT()); n->AA.assign(L, HT()); n->ZB.assign(L, HT()); n->CAT.assign(L, HT());
+  n->Pin.assign(L + 1, HT());
+  n->ZDa.assign(L, HT()); n->ADa.assign(L, HT()); n->ZDb.assign(L, HT()); n->ADb.assign(L, HT());
+  n->gCAT.assign(L, HT()); n->gT1.assign(L, HT()); n->gT2.assign(L, HT()); n->gP.assign(L + 1, HT());
+  for (int l = 0; l < L; ++l) {
+    const int H = n->H >> l, W = n->W >> l, c = n->ch[l], cn = n->ch[l + 1];
+    tensor(n->ZA[l], H, W, c); tensor(n->AA[l], H, W, c); tensor(n->ZB[l], H, W, c);
+    tensor(n->CAT[l], H, W, cn + c);
+    tensor(n->ZDa[l], H, W, c); tensor(n->ADa[l], H, W, c); tensor(n->ZDb[l], H, W, c); tensor(n->ADb[l], H, W, c);
+    tensor(n->gCAT[l], H, W, cn + c); tensor(n->gT1[l], H, W, c); tensor(n->gT2[l], H, W, c);
+    if (l >= 1) {
+      tensor(n->Pin[l], H, W, n->ch[l - 1]);
+      tensor(n->gP[l], H, W, n->ch[l - 1]);
+    }
+  }
+  const int HL = n->H >> L, WL = n->W >> L, cL = n->ch[L];
+  tensor(n->Pin[L], HL, WL, n->ch[L - 1]);
+  tensor(n->gP[L], HL, WL, n->ch[L - 1]);
+  tensor(n->ZMa, HL, WL, cL); tensor(n->AMa, HL, WL, cL); tensor(n->ZMb, HL, WL, cL); tensor(n->AMb, HL, WL, cL);
+  tensor(n->gM1, HL, WL, cL); tensor(n->gM2, HL, WL, cL);
+  n->OUT = (float*)take((size_t)N * n->H * n->W * n->cout * 4);
+  n->GOUT = (float*)take((size_t)N * n->H * n->W * n->cout * 4);
+  n->part = (float*)take(kWgradPartFloats * 4);
+  n->cpart = (float*)take((size_t)kPartBlocks * 1024 * 4);
+  n->lpart = (double*)take(256 * 8);
+  return off;
+}
+
+// Layer table and parameter offsets (oracle order; layer 0 input padded to 16).
+void net_layers(ssn_net* n) {
+  n->L = n->levels - 1;
+  n->ch.clear();
+  for (int l = 0; l < n->levels; ++l) n->ch.push_back(n->base << l);
+  n->conv.clear();
+  long off = 0;
+  auto add = [&](int Ci_real, int Ci, int Co, int H, int W) {
+    ConvL c;
+    c.Ci = Ci; c.Ci_real = Ci_real; c.Co = Co; c.H = H; c.W = W;
+    c.w_off = off; off += (long)Co * 9 * Ci;
+    c.b_off = off; off += Co;
+    c.wf = c.wb = nullptr;
+    n->conv.push_back(c);
+  };
+  int cprev = n->cin;
+  for (int l = 0; l < n->L; ++l) {
+    const int H = n->H >> l, W = n->W >> l;
+    add(cprev, l == 0 ? n->cin_pad : cprev, n->ch[l], H, W);
+    add(n->ch[l], n->ch[l], n->ch[l], H, W);
+    cprev = n->ch[l];
+  }
+  add(cprev, cprev, n->ch[n->L], n->H >> n->L, n->W >> n->L);
+  add(n->ch[n->L], n->ch[n->L], n->ch[n->L], n->H >> n->L, n->W >> n->L);
+  cprev = n->ch[n->L];
+  for (int l = n->L - 1; l >= 0; --l) {
+    const int H = n->H >> l, W = n->W >> l;
+    add(cprev + n->ch[l], cprev + n->ch[l], n->ch[l], H, W);
+    add(n->ch[l], n->ch[l], n->ch[l], H, W);
+    cprev = n->ch[l];
+  }
+  n->hw_off = off; off += (long)n->cout * n->ch[0];
+  n->hb_off = off; off += n->cout;
+  n->np = off;
+}
+
+int enc_a(int l) { return 2 * l; }
+int enc_b(int l) { return 2 * l + 1; }
+int mid_a(const ssn_net* n) { return 2 * n->L; }
+int mid_b(const ssn_net* n) { return 2 * n->L + 1; }
+int dec_a(const ssn_net* n, int l) { return 2 * n->L + 2 + 2 * (n->L - 1 - l); }
+int dec_b(const ssn_net* n, int l) { return dec_a(n, l) + 1; }
+
+int grid1(long n) { return (int)std::min<long>((n + 255) / 256, 65535); }
+
+void launch_conv_fwd(const ssn_net* n, const ConvL& c, TV in, TV z, TV a) {
+  ConvArgs ca;
+  ca.in = in;
+  ca.w = c.wf;
+  ca.bias = n->P + c.b_off;
+  ca.Co = c.Co;
+  ca.out_z = z;
+  ca.out = a;
+  ca.zprev.p = nullptr;
+  ca.mode = 0;
+  ca.accumulate = 0;
+  const long P = (long)in.N * in.H * in.W;
+  dim3 grid((unsigned)((P + 255) / 256), (unsigned)((c.Co + 31) / 32));
+  hipLaunchKernelGGL((conv3x3_mfma<2>), grid, dim3(256), 0, n->stream, ca);
+}
+
+// gradient w.r.t. the layer input: out = conv(gz, wb) [* SiLU'(zprev)]
+void launch_conv_bwd_data(const ssn_net* n, const ConvL& c, TV gz, TV out, const TV* zprev) {
+  ConvArgs ca;
+  ca.in = gz;
+  ca.w = c.wb;
+  ca.bias = nullptr;
+  ca.Co = c.Ci;
+  ca.out_z.p = nullptr;
+  ca.out = out;
+  if (zprev) ca.zprev = *zprev;
+  else ca.zprev.p = nullptr;
+  ca.mode = 1;
+  ca.accumulate = 0;
+  const long P = (long)gz.N * gz.H * gz.W;
+  dim3 grid((unsigned)((P + 255) / 256), (unsigned)((c.Ci + 31) / 32));
+  hipLaunchKernelGGL((conv3x3_mfma<2>), grid, dim3(256), 0, n->stream, ca);
+}
+
+void launch_wgrad(ssn_net* n, const ConvL& c, TV gz, TV x) {
+  const int cw = std::min(kCW, x.W);
+  const long nchunks = (long)x.N * x.H * (x.W / cw);
+  const int tci = (c.Ci + 31) / 32, tco = (c.Co + 31) / 32;
+  int nsplit = (int)std::max<long>(1, std::min<long>(nchunks, 1024 / (tci * tco)));
+  while ((long)nsplit * c.Co * 9 * c.Ci > kWgradPartFloats) nsplit /= 2;
+  WgradArgs wa;
+  wa.gz = gz;
+  wa.x = x;
+  wa.part = n->part;
+  wa.nsplit = nsplit;
+  wa.cw = cw;
+  hipLaunchKernelGGL(conv3x3_wgrad, dim3(tci, tco, nsplit), dim3(576), 0, n->stream, wa);
+  const long nw = (long)c.Co * 9 * c.Ci;
+  hipLaunchKernelGGL(reduce_splits, dim3(grid1(nw)), dim3(256), 0, n->stream, n->part, nsplit, nw, n->G + c.w_off);
+  // bias gradient: per-channel sums of gz
+  hipLaunchKernelGGL(channel_sums, dim3(kPartBlocks), dim3(256), 0, n->stream, gz, (const float*)nullptr, 0,
+                     (long)gz.N * gz.H * gz.W, c.Co, n->cpart);
+  hipLaunchKernelGGL(reduce_splits, dim3(1), dim3(256), 0, n->stream, n->cpart, kPartBlocks, (long)c.Co,
+                     n->G + c.b_off);
+}
+
+void pack_all(ssn_net* n) {
+  for (const ConvL& c : n->conv) {
+    const long nw = (long)c.Co * 9 * c.Ci;
+    hipLaunchKernelGGL(pack_conv_weights, dim3(grid1(nw)), dim3(256), 0, n->stream, n->P + c.w_off, c.Co, c.Ci, c.wf,
+                       c.wb);
+  }
+}
+
+__global__ void input_to_bf16(const float* __restrict__ x, int cin, long npix, TV X) {
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < npix * X.C; k += (long)gridDim.x * blockDim.x) {
+    const long p = k / X.C;
+    const int c = (int)(k - p * X.C);
+    X.p[p * X.cs + X.coff + c] = f2bf(c < cin ? x[p * cin + c] : 0.0f);
+  }
+}
+
+int net_forward(ssn_net* n, const float* x, int nb) {
+  const int L = n->L;
+  const long npix = (long)nb * n->H * n->W;
+  hipLaunchKernelGGL(input_to_bf16, dim3(grid1(npix * n->cin_pad)), dim3(256), 0, n->stream, x, n->cin, npix,
+                     n->X0.all(nb));
+  for (int l = 0; l < L; ++l) {
+    const int c = n->ch[l], cn = n->ch[l + 1];
+    TV in = l == 0 ? n->X0.all(nb) : n->Pin[l].all(nb);
+    launch_conv_fwd(n, n->conv[enc_a(l)], in, n->ZA[l].all(nb), n->AA[l].all(nb));
+    TV skip = n->CAT[l].view(nb, cn, c);
+    launch_conv_fwd(n, n->conv[enc_b(l)], n->AA[l].all(nb), n->ZB[l].all(nb), skip);
+    TV pooled = n->Pin[l + 1].all(nb);
+    hipLaunchKernelGGL(avgpool2_fwd, dim3(grid1((long)nb * pooled.H * pooled.W * c)), dim3(256), 0, n->stream, skip,
+                       pooled);
+  }
+  launch_conv_fwd(n, n->conv[mid_a(n)], n->Pin[L].all(nb), n->ZMa.all(nb), n->AMa.all(nb));
+  launch_conv_fwd(n, n->conv[mid_b(n)], n->AMa.all(nb), n->ZMb.all(nb), n->AMb.all(nb));
+  for (int l = L - 1; l >= 0; --l) {
+    const int cn = n->ch[l + 1];
+    TV prev = l == L - 1 ? n->AMb.all(nb) : n->ADb[l + 1].all(nb);
+    TV up = n->CAT[l].view(nb, 0, cn);
+    hipLaunchKernelGGL(upsample2_fwd, dim3(grid1((long)nb * up.H * up.W * cn)), dim3(256), 0, n->stream, prev, up);
+    launch_conv_fwd(n, n->conv[dec_a(n, l)], n->CAT[l].all(nb), n->ZDa[l].all(nb), n->ADa[l].all(nb));
+    launch_conv_fwd(n, n->conv[dec_b(n, l)], n->ADa[l].all(nb), n->ZDb[l].all(nb), n->ADb[l].all(nb));
+  }
+  hipLaunchKernelGGL(head_fwd, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, n->stream, n->ADb[0].all(nb),
+                     n->P + n->hw_off, n->P + n->hb_off, n->cout, n->OUT, npix);
+  SN_HIP(hipGetLastError());
+  return SS_OK;
+}
+
+int net_backward(ssn_net* n, const float* target, int nb, double* loss) {
+  const int L = n->L;
+  const long npix = (long)nb * n->H * n->W;
+  const long nout = npix * n->cout;
+  hipLaunchKernelGGL(mse_fwd_bwd, dim3(256), dim3(256), 0, n->stream, n->OUT, target, nout, n->GOUT, n->lpart);
+  // head
+  hipLaunchKernelGGL(head_wgrad, dim3(kPartBlocks), dim3(256), 0, n->stream, n->GOUT, n->ADb[0].all(nb), n->cout, npix,
+                     n->cpart);
+  hipLaunchKernelGGL(reduce_splits, dim3(1), dim3(256), 0, n->stream, n->cpart, kPartBlocks,
+                     (long)n->cout * n->ch[0], n->G + n->hw_off);
+  TV none;
+  none.p = nullptr;
+  hipLaunchKernelGGL(channel_sums, dim3(kPartBlocks), dim3(256), 0, n->stream, none, n->GOUT, n->cout, npix, n->cout,
+                     n->cpart);
+  hipLaunchKernelGGL(reduce_splits, dim3(1), dim3(256), 0, n->stream, n->cpart, kPartBlocks, (long)n->cout,
+                     n->G + n->hb_off);
+  hipLaunchKernelGGL(head_bwd_data, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, n->stream, n->GOUT,
+                     n->P + n->hw_off, n->cout, n->ZDb[0].all(nb), n->gT1[0].all(nb), npix);
+  // decoder, top level first
+  for (int l = 0; l < L; ++l) {
+    const int cn = n->ch[l + 1];
+    const ConvL& cb = n->conv[dec_b(n, l)];
+    const ConvL& ca = n->conv[dec_a(n, l)];
+    launch_wgrad(n, cb, n->gT1[l].all(nb), n->ADa[l].all(nb));
+    TV za = n->ZDa[l].all(nb);
+    launch_conv_bwd_data(n, cb, n->gT1[l].all(nb), n->gT2[l].all(nb), &za);
+    launch_wgrad(n, ca, n->gT2[l].all(nb), n->CAT[l].all(nb));
+    launch_conv_bwd_data(n, ca, n->gT2[l].all(nb), n->gCAT[l].all(nb), nullptr);
+    // the upsampled half of the concatenation feeds back to the level below
+    TV gup = n->gCAT[l].view(nb, 0, cn);
+    TV dst = l == L - 1 ? n->gM2.all(nb) : n->gT1[l + 1].all(nb);
+    TV zsrc = l == L - 1 ? n->ZMb.all(nb) : n->ZDb[l + 1].all(nb);
+    hipLaunchKernelGGL(upsample2_bwd, dim3(grid1((long)nb * dst.H * dst.W * cn)), dim3(256), 0, n->stream, gup, dst);
+    hipLaunchKernelGGL(silu_bwd_inplace, dim3(grid1((long)nb * dst.H * dst.W * cn)), dim3(256), 0, n->stream, dst,
+                       zsrc);
+  }
+  // bottleneck
+  {
+    const ConvL& cb = n->conv[mid_b(n)];
+    const ConvL& ca = n->conv[mid_a(n)];
+    launch_wgrad(n, cb, n->gM2.all(nb), n->AMa.all(nb));
+    TV za = n->ZMa.all(nb);
+    launch_conv_bwd_data(n, cb, n->gM2.all(nb), n->gM1.all(nb), &za);
+    launch_wgrad(n, ca, n->gM1.all(nb), n->Pin[L].all(nb));
+    launch_conv_bwd_data(n, ca, n->gM1.all(nb), n->gP[L].all(nb), nullptr);
+  }
+  // encoder, bottom level first
+  for (int l = L - 1; l >= 0; --l) {
+    const int c = n->ch[l], cn = n->ch[l + 1];
+    TV gS = n->gCAT[l].view(nb, cn, c);
+    hipLaunchKernelGGL(avgpool2_bwd, dim3(grid1((long)nb * gS.H * gS.W * c)), dim3(256), 0, n->stream,
+                       n->gP[l + 1].all(nb), gS, 1);
+    hipLaunchKernelGGL(silu_bwd_inplace, dim3(grid1((long)nb * gS.H * gS.W * c)), dim3(256), 0, n->stream, gS,
+                       n->ZB[l].all(nb));
+    const ConvL& cb = n->conv[enc_b(l)];
+    const ConvL& ca = n->conv[enc_a(l)];
+    launch_wgrad(n, cb, gS, n->AA[l].all(nb));
+    TV za = n->ZA[l].all(nb);
+    launch_conv_bwd_data(n, cb, gS, n->gT2[l].all(nb), &za);
+    TV in = l == 0 ? n->X0.all(nb) : n->Pin[l].all(nb);
+    launch_wgrad(n, ca, n->gT2[l].all(nb), in);
+    if (l > 0) launch_conv_bwd_data(n, ca, n->gT2[l].all(nb), n->gP[l].all(nb), nullptr);
+  }
+  SN_HIP(hipGetLastError());
+  if (loss) {
+    double parts[256];
+    SN_HIP(hipMemcpyAsync(parts, n->lpart, sizeof(parts), hipMemcpyDeviceToHost, n->stream));
+    SN_HIP(hipStreamSynchronize(n->stream));
+    double s = 0.0;
+    for (int k = 0; k < 256; ++k) s += parts[k];
+    *loss = s / (double)nout;
+  }
+  return SS_OK;
+}
+
+// oracle-order flat index <-> padded layout, for one parameter block
+template <class F>
+void for_each_param(const ssn_net* n, F&& f) {
+  long o = 0;  // oracle offset
+  for (const ConvL& c : n->conv) {
+    for (int co = 0; co < c.Co; ++co)
+      for (int t = 0; t < 9; ++t)
+        for (int ci = 0; ci < c.Ci_real; ++ci) f(o++, c.w_off + ((long)co * 9 + t) * c.Ci + ci);
+    for (int co = 0; co < c.Co; ++co) f(o++, c.b_off + co);
+  }
+  for (int k = 0; k < n->cout * n->ch[0]; ++k) f(o++, n->hw_off + k);
+  for (int k = 0; k < n->cout; ++k) f(o++, n->hb_off + k);
+}
+
+long oracle_count(const ssn_net* n) {
+  long c = 0;
+  for_each_param(n, [&](long, long) { ++c; });
+  return c;
+}
+
+int check_shape(int levels, int base, int cin, int cout, int N, int H, int W) {
+  if (levels < 2 || levels > 6) return nfail(SS_EINVAL, "levels must lie in [2, 6]");
+  if (base < 16 || base % 16 || (base << (levels - 1)) > 1024) return nfail(SS_EINVAL, "base must be a multiple of 16");
+  if (cin < 1 || cin > 16) return nfail(SS_EINVAL, "cin must lie in [1, 16]");
+  if (cout < 1 || cout > 8 || cout * base > 256) return nfail(SS_EINVAL, "cout must lie in [1, 8] with cout*base <= 256");
+  const int m = 16 << (levels - 1);
+  if (N < 1 || H < m || W < m || H % m || W % m)
+    return nfail(SS_ESHAPE, "H and W must be multiples of 16 * 2^(levels-1)");
+  return SS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+long ssn_param_count(int levels, int base, int cin, int cout) {
+  ssn_net n;
+  n.levels = levels; n.base = base; n.cin = cin; n.cout = cout; n.cin_pad = 16;
+  n.H = n.W = 16 << (levels - 1);
+  net_layers(&n);
+  return oracle_count(&n);
+}
+
+int ssn_workspace_bytes(int levels, int base, int cin, int cout, int N, int H, int W, size_t* bytes) {
+  int rc = check_shape(levels, base, cin, cout, N, H, W);
+  if (rc) return rc;
+  if (!bytes) return nfail(SS_EINVAL, "bytes is NULL");
+  ssn_net n;
+  n.levels = levels; n.base = base; n.cin = cin; n.cout = cout; n.cin_pad = 16;
+  n.Ncap = N; n.H = H; n.W = W;
+  net_layers(&n);
+  *bytes = net_carve(&n, nullptr);
+  return SS_OK;
+}
+
+int ssn_create(int levels, int base, int cin, int cout, int N, int H, int W, void* ws, size_t ws_bytes, void* stream,
+               ssn_net** out) {
+  if (!out) return nfail(SS_EINVAL, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  int rc = ssn_workspace_bytes(levels, base, cin, cout, N, H, W, &need);
+  if (rc) return rc;
+  if (!ws || ws_bytes < need || ((uintptr_t)ws) % 256) return nfail(SS_EINVAL, "workspace missing, small or misaligned");
+  ssn_net* n = new (std::nothrow) ssn_net();
+  if (!n) return nfail(SS_EINVAL, "out of host memory");
+  n->levels = levels; n->base = base; n->cin = cin; n->cout = cout; n->cin_pad = 16;
+  n->Ncap = N; n->H = H; n->W = W;
+  n->stream = (hipStream_t)stream;
+  n->adam_t = 0;
+  net_layers(n);
+  n->bytes = net_carve(n, (char*)ws);
+  hipError_t e = hipMemsetAsync(ws, 0, n->bytes, n->stream);
+  if (e != hipSuccess) {
+    delete n;
+    return nfail(SS_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+  }
+  *out = n;
+  return SS_OK;
+}
+
+void ssn_destroy(ssn_net* n) { delete n; }
+
+long ssn_num_params(ssn_net* n) { return n ? oracle_count(n) : SS_EINVAL; }
+
+int ssn_set_weights(ssn_net* n, const float* host, long count) {
+  if (!n || !host || count != oracle_count(n)) return nfail(SS_EINVAL, "weights: wrong count");
+  std::vector<float> flat(n->np, 0.0f);
+  for_each_param(n, [&](long o, long d) { flat[d] = host[o]; });
+  SN_HIP(hipMemcpyAsync(n->P, flat.data(), n->np * 4, hipMemcpyHostToDevice, n->stream));
+  SN_HIP(hipMemsetAsync(n->M, 0, n->np * 4, n->stream));
+  SN_HIP(hipMemsetAsync(n->V, 0, n->np * 4, n->stream));
+  n->adam_t = 0;
+  pack_all(n);
+  SN_HIP(hipGetLastError());
+  SN_HIP(hipStreamSynchronize(n->stream));
+  return SS_OK;
+}
+
+static int copy_out(ssn_net* n, const float* dev, float* host, long count) {
+  if (!n || !host || count != oracle_count(n)) return nfail(SS_EINVAL, "wrong count");
+  std::vector<float> flat(n->np);
+  SN_HIP(hipMemcpyAsync(flat.data(), dev, n->np * 4, hipMemcpyDeviceToHost, n->stream));
+  SN_HIP(hipStreamSynchronize(n->stream));
+  for_each_param(n, [&](long o, long d) { host[o] = flat[d]; });
+  return SS_OK;
+}
+
+int ssn_get_weights(ssn_net* n, float* host, long count) { return copy_out(n, n ? n->P : nullptr, host, count); }
+int ssn_get_grads(ssn_net* n, float* host, long count) { return copy_out(n, n ? n->G : nullptr, host, count); }
+
+int ssn_forward(ssn_net* n, const float* x, int nb, float* out) {
+  if (!n || !x || nb < 1 || nb > n->Ncap) return nfail(SS_EINVAL, "bad forward arguments");
+  int rc = net_forward(n, x, nb);
+  if (rc) return rc;
+  if (out)
+    SN_HIP(hipMemcpyAsync(out, n->OUT, (size_t)nb * n->H * n->W * n->cout * 4, hipMemcpyDeviceToDevice, n->stream));
+  return SS_OK;
+}
+
+int ssn_backward(ssn_net* n, const float* target, int nb, double* loss) {
+  if (!n || !target || nb < 1 || nb > n->Ncap) return nfail(SS_EINVAL, "bad backward arguments");
+  return net_backward(n, target, nb, loss);
+}
+
+int ssn_adam_step(ssn_net* n, float lr) {
+  if (!n || !(lr > 0.0f)) return nfail(SS_EINVAL, "bad Adam arguments");
+  n->adam_t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - std::pow(b1, (float)n->adam_t), c2 = 1.0f - std::pow(b2, (float)n->adam_t);
+  hipLaunchKernelGGL(adam_update, dim3(grid1(n->np)), dim3(256), 0, n->stream, n->P, n->M, n->V, n->G, n->np, lr, b1,
+                     b2, 1e-8f, c1, c2);
+  pack_all(n);
+  SN_HIP(hipGetLastError());
+  return SS_OK;
+}
+
+int ssn_train_step(ssn_net* n, const float* x, const float* target, int nb, float lr, double* loss) {
+  int rc = ssn_forward(n, x, nb, nullptr);
+  if (rc) return rc;
+  rc = ssn_backward(n, target, nb, loss);
+  if (rc) return rc;
+  return ssn_adam_step(n, lr);
+}
+
+// Forward and backward multiply-add flops of one sample (2 flops per MAC),
+// counting the 3x3 and 1x1 convolutions at their real channel counts.
+int ssn_flops(ssn_net* n, double* fwd, double* bwd) {
+  if (!n) return nfail(SS_EINVAL, "net is NULL");
+  double f = 0.0, b = 0.0;
+  for (size_t k = 0; k < n->conv.size(); ++k) {
+    const ConvL& c = n->conv[k];
+    const double mac = (double)c.H * c.W * 9.0 * c.Co * c.Ci_real;
+    f += 2.0 * mac;
+    b += (k == 0 ? 2.0 : 4.0) * mac;  // weight gradient (+ input gradient except for the first layer)
+  }
+  const double head = (double)n->H * n->W * n->cout * n->ch[0];
+  f += 2.0 * head;
+  b += 4.0 * head;
+  if (fwd) *fwd = f;
+  if (bwd) *bwd = b;
+  return SS_OK;
+}
+
+const char* ssn_last_error(void) { return g_ssn_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+"""Learned initialiser for batched Ginzburg-Landau minimisations.
+
+Pipeline (every arithmetic step runs in the library's HIP kernels):
+  1. data: seeded instances (vortex centres, kappa) are relaxed by the batched
+     arrested-Newton flow; the library turns each relaxed field into the
+     network's target (smooth corrections to the vortex ansatz) and each
+     instance into the network's input (vortex blob map, kappa);
+  2. training: the BF16-MFMA U-Net minimises the mean squared error with Adam;
+  3. use: input -> network -> ss_init_learned -> flow.
+The plain ansatz start (ss_init_ansatz) remains the fallback and the baseline
+of the comparison: both starts are flowed to the same reference energy and
+their wall times are compared.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+import paper_2603_24370_amd as ss
+from paper_2603_24370_amd import inputs as I
+
+
+def unet_param_shapes(levels=4, base=32, cin=2, cout=4):
+    """(name, shape) of the network's parameters in the library's exchange order."""
+    shapes = []
+    ch = [base << l for l in range(levels)]
+    c_prev = cin
+    for l in range(levels - 1):
+        shapes += [(f"enc{l}a.w", (ch[l], 3, 3, c_prev)), (f"enc{l}a.b", (ch[l],)),
+                   (f"enc{l}b.w", (ch[l], 3, 3, ch[l])), (f"enc{l}b.b", (ch[l],))]
+        c_prev = ch[l]
+    L = levels - 1
+    shapes += [("mid.a.w", (ch[L], 3, 3, c_prev)), ("mid.a.b", (ch[L],)),
+               ("mid.b.w", (ch[L], 3, 3, ch[L])), ("mid.b.b", (ch[L],))]
+    c_prev = ch[L]
+    for l in reversed(range(levels - 1)):
+        shapes += [(f"dec{l}a.w", (ch[l], 3, 3, c_prev + ch[l])), (f"dec{l}a.b", (ch[l],)),
+                   (f"dec{l}b.w", (ch[l], 3, 3, ch[l])), (f"dec{l}b.b", (ch[l],))]
+        c_prev = ch[l]
+    shapes += [("head.w", (cout, c_prev)), ("head.b", (cout,))]
+    return shapes
+
+
+def init_weights(seed=0, levels=4, base=32, cin=2, cout=4):
+    """He-uniform weights and zero biases as one flat fp32 array (exchange order)."""
+    rng = np.random.default_rng(seed)
+    flat = []
+    for name, shp in unet_param_shapes(levels, base, cin, cout):
+        k = int(np.prod(shp))
+        if name.endswith(".b"):
+            flat.append(np.zeros(k))
+        else:
+            lim = np.sqrt(6.0 / int(np.prod(shp[1:])))
+            flat.append(rng.uniform(-lim, lim, size=k))
+    return np.concatenate(flat).astype(np.float32)
+
+
+def learned_instance(i: int, base_seed: int = 5_000_000, side: int = 256, h: float = 0.2) -> I.Instance:
+    """Instance i of the learned-initialiser workload: the batched-GL distributions
+    (kappa ~ U[0.5, 2], N ~ U{1..8}, centres uniform in the centred 0.6 L square)
+    at a fixed side."""
+    seed = base_seed + i
+    u = I.uniform01(seed, I.STREAM_INSTANCE, np.arange(3, dtype=np.uint64))
+    kappa = 0.5 + 1.5 * u[1]
+    nv = 1 + min(int(u[2] * 8), 7)
+    centres = I.uniform_centres(seed, nv, 0.5 * 0.6 * side * h)
+    return I.Instance("abelian_higgs", side, side, h, [I.gl_lambda_from_kappa(kappa)], centres, seed, kappa=kappa)
+
+
+def generate_dataset(insts, batch=64, rel_e_tol=1e-7, window=100, max_steps=4000, device="cuda:0", log=None):
+    """Relax the instances with the batched solver (FP32 fields, FP64 reductions) and
+    return (inputs (n, H, W, 2), targets (n, H, W, 4)) as fp32 device tensors."""
+    import torch
+    n = len(insts)
+    H, W = insts[0].Ny, insts[0].Nx
+    X = torch.empty((n, H, W, 2), dtype=torch.float32, device=device)
+    T = torch.empty((n, H, W, 4), dtype=torch.float32, device=device)
+    stats = []
+    for b0 in range(0, n, batch):
+        chunk = insts[b0:b0 + batch]
+        B = ss.Batch("abelian_higgs", [(m.Nx, m.Ny, m.h, m.params) for m in chunk], dtype="f32", device=device)
+        for m, mem in zip(chunk, B.members):
+            mem.init_vortices(m.centres, seed=m.seed, noise_amp=1e-3)
+        rc, infos = B.minimise(grad_tol=0.0, rel_e_tol=rel_e_tol, window=window, max_steps=max_steps, graph_steps=16)
+        for k, (m, mem) in enumerate(zip(chunk, B.members)):
+            ss.ss_learned_input(mem.ctx, m.centres, m.kappa, X[b0 + k].data_ptr())
+            ss.ss_learned_targets(mem.ctx, m.centres, None, T[b0 + k].data_ptr())
+            stats.append(infos[k]["step"])
+        B.close()
+        if log:
+            log(f"[data] {b0 + len(chunk)}/{n} relaxed (median steps {int(np.median(stats))})")
+    return X, T, stats
+
+
+def train(net, X, T, epochs=10, batch=8, lr=1e-3, seed=0, log=None):
+    """Adam on the mean squared error; returns the per-epoch mean losses and the
+    achieved training rate (TFLOP/s of the MFMA convolutions)."""
+    import torch
+    n = X.shape[0]
+    rng = np.random.default_rng(seed)
+    f_fwd, f_bwd = net.flops()
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    for ep in range(epochs):
+        perm = rng.permutation(n)
+        tot, cnt = 0.0, 0
+        for b0 in range(0, n - batch + 1, batch):
+            idx = torch.as_tensor(perm[b0:b0 + batch], device=X.device)
+            loss = net.train_step(X.index_select(0, idx), T.index_select(0, idx),
+                                  lr * 0.5 * (1 + math.cos(math.pi * ep / max(1, epochs))))
+            tot += loss
+            cnt += 1
+            steps += 1
+        losses.append(tot / max(cnt, 1))
+        if log:
+            log(f"[train] epoch {ep + 1}/{epochs} loss {losses[-1]:.4e}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tflops = steps * batch * (f_fwd + f_bwd) / el / 1e12
+    return losses, tflops, el
+
+
+def time_to_target(solver, start, e_target, max_steps):
+    """Wall time and steps of one minimisation from a start function to E <= e_target."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start()
+    ss.ss_set_energy_target(solver.ctx, e_target)
+    res = solver.minimise(grad_tol=0.0, rel_e_tol=0.0, window=0, max_steps=max_steps, graph_steps=16)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, res
+
+
+def ab_compare(net, insts, tol=1e-6, ref_rel_e_tol=1e-9, ref_window=100, ref_max_steps=50000, max_steps=50000,
+               device="cuda:0", log=None):
+    """For each instance: a long ansatz-start run gives E_ref (stalled energy); then the
+    ansatz start and the learned start are flowed until E <= E_ref + tol |E_ref|.
+    Returns per-instance records; the learned start's time includes the network."""
+    import torch
+    m0 = insts[0]
+    s = ss.Solver("abelian_higgs", m0.Nx, m0.Ny, m0.h, m0.params, dtype="f32", device=device)
+    x = torch.empty((1, m0.Ny, m0.Nx, 2), dtype=torch.float32, device=device)
+    recs = []
+    for k, m in enumerate(insts):
+        s.close()
+        s = ss.Solver("abelian_higgs", m.Nx, m.Ny, m.h, m.params, dtype="f32", device=device)
+        s.init_vortices(m.centres, seed=m.seed, noise_amp=1e-3)
+        ref = s.minimise(grad_tol=0.0, rel_e_tol=ref_rel_e_tol, window=ref_window, max_steps=ref_max_steps,
+                         graph_steps=16)
+        E_ref = ref["energy"]
+        target = E_ref + tol * abs(E_ref)
+
+        def ansatz_start():
+            s.init_vortices(m.centres, seed=m.seed, noise_amp=1e-3)
+
+        def learned_start():
+            ss.ss_learned_input(s.ctx, m.centres, m.kappa, x.data_ptr())
+            corr = net.forward(x)
+            ss.ss_init_learned(s.ctx, m.centres, None, corr.data_ptr())
+
+        ta, ra = time_to_target(s, ansatz_start, target, max_steps)
+        tl, rl = time_to_target(s, learned_start, target, max_steps)
+        rec = {"kappa": m.kappa, "n_vortices": len(m.centres), "E_ref": E_ref, "ref_steps": ref["step"],
+               "ansatz_s": ta, "ansatz_steps": ra["step"], "ansatz_reached": ra["reason"] == "target",
+               "learned_s": tl, "learned_steps": rl["step"], "learned_reached": rl["reason"] == "target"}
+        recs.append(rec)
+        if log and (k + 1) % 16 == 0:
+            log(f"[ab] {k + 1}/{len(insts)}")
+    s.close()
+    return recs
+
+
+def summarise(recs):
+    both = [r for r in recs if r["ansatz_reached"] and r["learned_reached"]]
+    ratio = [r["learned_s"] / r["ansatz_s"] for r in both]
+    sratio = [r["learned_steps"] / max(1, r["ansatz_steps"]) for r in both]
+    return {"instances": len(recs), "both_reached": len(both),
+            "learned_missed": sum(1 for r in recs if not r["learned_reached"]),
+            "median_time_ratio": float(np.median(ratio)) if ratio else None,
+            "median_step_ratio": float(np.median(sratio)) if sratio else None,
+            "learned_win_fraction": float(np.mean([x < 1 for x in ratio])) if ratio else None,
+            "median_ansatz_s": float(np.median([r["ansatz_s"] for r in both])) if both else None,
+            "median_learned_s": float(np.median([r["learned_s"] for r in both])) if both else None}

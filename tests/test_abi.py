@@ -11,10 +11,10 @@ import paper_2603_24370_amd as ss
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "ss.h")).read()
+def _declared_functions(header="ss.h", prefix="ss_"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = set(re.findall(r"^\s*(?:const\s+)?(?:int|void|double|char|ss_ctx)\s*\**\s*(ss_\w+)\s*\(",
+    names = set(re.findall(r"^\s*(?:const\s+)?(?:int|void|double|long|char|ss_ctx)\s*\**\s*(" + prefix + r"\w+)\s*\(",
                            src, flags=re.M))
     return names
 
@@ -33,6 +33,27 @@ def test_every_declared_symbol_is_exported(L):
     for n in names:
         assert hasattr(L, n), n
     assert set(ss.EXPORTS) == names
+    nn = _declared_functions("ssn.h", "ssn_")
+    assert {"ssn_create", "ssn_forward", "ssn_backward", "ssn_adam_step"} <= nn
+    for n in nn:
+        assert hasattr(L, n), n
+    assert set(ss.SSN_EXPORTS) == nn
+
+
+def test_network_parameter_count_matches_oracle(L):
+    from oracle import unet as U
+    import numpy as np
+    for lv, base in [(3, 16), (4, 32)]:
+        want = sum(int(np.prod(s)) for _, s in U.layer_shapes(lv, base, 2, 4))
+        assert ss.ssn_param_count(lv, base, 2, 4) == want
+
+
+def test_network_validates_shapes(L):
+    import ctypes as ct
+    n = ct.c_size_t(0)
+    assert ss._ssn_lib().ssn_workspace_bytes(4, 32, 2, 4, 8, 100, 256, ct.byref(n)) == -3  # H not a multiple of 128
+    assert ss._ssn_lib().ssn_workspace_bytes(4, 24, 2, 4, 8, 256, 256, ct.byref(n)) == -1  # base not a multiple of 16
+    assert ss._ssn_lib().ssn_workspace_bytes(4, 32, 2, 4, 8, 256, 256, ct.byref(n)) == 0 and n.value > 0
 
 
 def test_theory_registry_names_and_aliases(L):

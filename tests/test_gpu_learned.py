@@ -1,0 +1,181 @@
+"""Learned initialiser on the GPU: the BF16-MFMA U-Net against the FP64 oracle
+network, and the solver-side input / target / reconstruction kernels.
+
+Tolerances (BF16, 8 significant bits): every 3x3 layer rounds its activation
+and pre-activation to BF16 (relative 2^-9) and its weights are BF16 copies of
+the FP32 master; through the ~13 layers of the test network these roundings
+compound to a few per cent. The test asks for a relative L2 error <= 3e-2 on
+outputs and <= 6e-2 on parameter gradients (whose sums over pixels also see
+BF16 activation gradients), and exact agreement of the FP32 Adam update given
+the same gradients.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import unet as U
+from paper_2603_24370_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+LV, BASE, CIN, COUT, H = 3, 16, 2, 4, 64
+
+
+@pytest.fixture(scope="module")
+def ss():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2603_24370_amd as m
+    m.lib()
+    return m
+
+
+def _flat(P, levels=LV, base=BASE, cin=CIN, cout=COUT):
+    return np.concatenate([P[name].reshape(-1) for name, _ in U.layer_shapes(levels, base, cin, cout)])
+
+
+def _unflat(v, levels=LV, base=BASE, cin=CIN, cout=COUT):
+    out, o = {}, 0
+    for name, shp in U.layer_shapes(levels, base, cin, cout):
+        k = int(np.prod(shp))
+        out[name] = v[o:o + k].reshape(shp)
+        o += k
+    return out
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _setup(ss, seed=0):
+    rng = np.random.default_rng(seed)
+    P = U.init_params(seed=seed, levels=LV, base=BASE, cin=CIN, cout=COUT)
+    for k in P:
+        if k.endswith(".b"):
+            P[k] = 0.05 * rng.normal(size=P[k].shape)
+    x = rng.normal(size=(2, H, H, CIN))
+    t = rng.normal(size=(2, H, H, COUT)) * 0.5
+    net = ss.Net(levels=LV, base=BASE, cin=CIN, cout=COUT, N=2, H=H, W=H)
+    assert net.n_params == sum(int(np.prod(s)) for _, s in U.layer_shapes(LV, BASE, CIN, COUT))
+    # the oracle runs with the BF16-rounded weights the GPU uses
+    flat = _flat(P).astype(np.float32)
+    net.set_weights(flat)
+    back = net.get_weights()
+    assert np.array_equal(back, flat)
+    return P, x, t, net
+
+
+def _bf16(a):
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
+def test_forward_matches_oracle(ss):
+    P, x, t, net = _setup(ss)
+    out = net.forward(x).cpu().numpy().astype(np.float64)
+    Pr = {k: (_bf16(v) if k.endswith(".w") and not k.startswith("head") else v) for k, v in P.items()}
+    ref, _ = U.forward(Pr, _bf16(x), LV)
+    assert _rel(out, ref) <= 3e-2
+    net.close()
+
+
+def test_backward_matches_oracle(ss):
+    P, x, t, net = _setup(ss, seed=1)
+    net.forward(x)
+    loss = net.backward(t)
+    G = _unflat(net.get_grads().astype(np.float64))
+    Pr = {k: (_bf16(v) if k.endswith(".w") and not k.startswith("head") else v) for k, v in P.items()}
+    out, cache = U.forward(Pr, _bf16(x), LV)
+    loss_ref, g = U.mse(out, t)
+    Gr = U.backward(Pr, cache, g, LV)
+    assert loss == pytest.approx(loss_ref, rel=3e-2)
+    for name, _ in U.layer_shapes(LV, BASE, CIN, COUT):
+        assert _rel(G[name], Gr[name]) <= 6e-2, name
+    net.close()
+
+
+def test_adam_step_matches_oracle_update(ss):
+    P, x, t, net = _setup(ss, seed=2)
+    w0 = net.get_weights().astype(np.float64)
+    net.forward(x)
+    net.backward(t)
+    g = net.get_grads().astype(np.float64)
+    net.adam_step(1e-3)
+    w1 = net.get_weights().astype(np.float64)
+    Pd, Gd = {"w": w0.copy()}, {"w": g}
+    U.adam_step(Pd, Gd, {}, lr=1e-3)
+    assert np.abs(w1 - Pd["w"]).max() <= 1e-6
+    net.close()
+
+
+def test_training_reduces_the_loss(ss):
+    P, x, t, net = _setup(ss, seed=3)
+    losses = [net.train_step(x, t, 3e-3) for _ in range(30)]
+    assert losses[-1] < 0.7 * losses[0]
+    # a second identical run is bitwise repeatable (fixed-order reductions)
+    net2 = ss.Net(levels=LV, base=BASE, cin=CIN, cout=COUT, N=2, H=H, W=H)
+    net2.set_weights(_flat(P).astype(np.float32))
+    losses2 = [net2.train_step(x, t, 3e-3) for _ in range(30)]
+    assert losses == losses2
+    net.close()
+    net2.close()
+
+
+def test_learned_input_and_targets(ss, orc):
+    N, h = 64, 0.2
+    cen = [(0.7, -1.1), (-2.3, 1.9)]
+    s = ss.Solver("abelian_higgs", N, N, h, [2.0], dtype="f64")
+    import torch
+    x = torch.empty((N, N, 2), dtype=torch.float32, device="cuda:0")
+    ss.ss_learned_input(s.ctx, cen, 1.3, x.data_ptr())
+    blob = I.blob_map(cen, N, h)
+    assert np.abs(x[..., 0].cpu().numpy() - blob).max() < 1e-6
+    assert np.all(x[..., 1].cpu().numpy() == np.float32(1.3))
+    # targets of the pure ansatz are zero; of a perturbed field they are the perturbation
+    f = I.ah_vortex_ansatz(N, N, h, cen)
+    rng = np.random.default_rng(0)
+    d = np.zeros_like(f)
+    d[:, 2:-2, 2:-2] = 1e-2 * rng.normal(size=(4, N, N))
+    s.set_field(f + d)
+    t = torch.empty((N, N, 4), dtype=torch.float32, device="cuda:0")
+    ss.ss_learned_targets(s.ctx, cen, None, t.data_ptr())
+    tt = t.cpu().numpy().astype(np.float64)
+    psi = (f + d)[0, 2:-2, 2:-2] + 1j * (f + d)[1, 2:-2, 2:-2]
+    psa = f[0, 2:-2, 2:-2] + 1j * f[1, 2:-2, 2:-2]
+    want_mod = np.abs(psi) - np.abs(psa)
+    assert np.abs(tt[..., 0] - want_mod).max() < 1e-6
+    assert np.abs(tt[..., 2] - d[2, 2:-2, 2:-2]).max() < 1e-6
+    assert np.abs(tt[..., 3] - d[3, 2:-2, 2:-2]).max() < 1e-6
+    # reconstruction from the targets returns the field (away from the cores, where
+    # the phase is defined) and zero corrections give the plain ansatz
+    ss.ss_init_learned(s.ctx, cen, None, t.data_ptr())
+    g = s.get_field().cpu().numpy()
+    far = np.abs(psa) > 0.3
+    assert np.abs((g[0, 2:-2, 2:-2] + 1j * g[1, 2:-2, 2:-2] - psi)[far]).max() < 1e-5
+    z = torch.zeros_like(t)
+    ss.ss_init_learned(s.ctx, cen, None, z.data_ptr())
+    g0 = s.get_field().cpu().numpy()
+    s.init_vortices(cen)
+    ga = s.get_field().cpu().numpy()
+    assert np.abs(g0 - ga).max() < 1e-12
+    s.close()
+
+
+def test_energy_target_stop_rule(ss):
+    N, h = 48, 0.25
+    f = I.ah_vortex_ansatz(N, N, h, [(0.2, 0.1)]) + I.noise(3, 4, N, N, 1e-3)
+    s = ss.Solver("abelian_higgs", N, N, h, [1.0], dtype="f64")
+    s.set_field(f)
+    E = []
+    for k in range(60):
+        E.append(s.flow_step(1)["energy"])
+    target = E[40]
+    first = next(i for i, e in enumerate(E) if e <= target) + 1  # step count at which E <= target
+    s.set_field(f)
+    ss.ss_set_energy_target(s.ctx, target)
+    res = s.minimise(grad_tol=0.0, max_steps=1000, graph_steps=8)
+    assert res["reason"] == "target" and res["converged"]
+    assert res["step"] == first and res["energy"] <= target
+    s.close()
