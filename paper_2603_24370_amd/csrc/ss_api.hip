@@ -49,6 +49,7 @@ struct TileCfg {
 constexpr TileCfg kTiles[] = {{64, 16, 2}, {64, 8, 2}, {64, 16, 4}, {64, 32, 4}};
 constexpr int kNumTiles = 4;
 constexpr int kDefaultTile = 0;
+static_assert(kTiles[0].TX == kExTX && kTiles[0].TY == kExTY, "the exact-gradient passes use the layout of tile 0");
 constexpr int kDefaultGraphSteps = 16;
 constexpr long kMaxGroups = 2048;  // persistent launch: at most 8 workgroups per CU
 
@@ -192,6 +193,14 @@ void launch_pass_t(int tile, const PassArgs<T>& a, int nlaunch, hipStream_t s) {
 
 template <class T, int PASS>
 void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
+  if (c->grad_mode == SS_GRAD_EXACT) {
+    // exact-gradient passes: one tile shape (64 x 16), the layout of tile 0
+    if (c->theory == SS_THEORY_AH)
+      hipLaunchKernelGGL((stage_pass_exact<T, 0, PASS>), dim3(c->L.nlaunch), dim3(kExTX, kExTY / kExRY), 0, s, a);
+    else
+      hipLaunchKernelGGL((stage_pass_exact<T, 1, PASS>), dim3(c->L.nlaunch), dim3(kExTX, kExTY / kExRY), 0, s, a);
+    return;
+  }
   if (c->theory == SS_THEORY_AH) launch_pass_t<T, 0, PASS>(c->tile, a, c->L.nlaunch, s);
   else launch_pass_t<T, 1, PASS>(c->tile, a, c->L.nlaunch, s);
 }
@@ -316,7 +325,6 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
     if (!params->i) return fail(SS_EINVAL, "params.i is NULL with ni > 0");
     grad_mode = params->i[0];
     if (grad_mode != SS_GRAD_EL && grad_mode != SS_GRAD_EXACT) return fail(SS_EINVAL, "unknown grad_mode");
-    if (grad_mode == SS_GRAD_EXACT) return fail(SS_EINVAL, "grad_mode SS_GRAD_EXACT is not built in this library");
   }
 
   ss_ctx* c = new (std::nothrow) ss_ctx();
@@ -344,6 +352,7 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
     const int t = std::atoi(env);
     if (t >= 0 && t < kNumTiles) c->tile = t;
   }
+  if (grad_mode == SS_GRAD_EXACT) c->tile = 0;
   set_tiles(c->L, Nx, Ny, c->tile);
   hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -637,6 +646,7 @@ int ss_observables(ss_ctx* c, ss_obs* out) {
 int ss_set_tile(ss_ctx* c, int tile) {
   if (!c) return fail(SS_EINVAL, "ctx is NULL");
   if (tile < 0 || tile >= kNumTiles) return fail(SS_EINVAL, "tile index out of range");
+  if (c->grad_mode == SS_GRAD_EXACT && tile != 0) return fail(SS_EINVAL, "the exact-gradient passes use tile 0 only");
   SS_HIP(hipStreamSynchronize(c->stream));
   c->tile = tile;
   set_tiles(c->L, c->Nx, c->Ny, tile);
@@ -659,6 +669,11 @@ int ss_tile_shape(int tile, int* tx, int* ty, int* ry) {
 
 int ss_autotune(ss_ctx* c, int n_steps, double* ms_out) {
   if (!c || n_steps <= 0) return fail(SS_EINVAL, "bad arguments");
+  if (c->grad_mode == SS_GRAD_EXACT) {
+    if (ms_out)
+      for (int t = 0; t < kNumTiles; ++t) ms_out[t] = t == 0 ? 0.0 : -1.0;
+    return 0;
+  }
   // a uniform vacuum (psi = 1, A = 0; n = e_3) keeps every pass finite
   const double zero[2] = {0.0, 0.0};
   const double shape[2] = {0.0, 0.0};

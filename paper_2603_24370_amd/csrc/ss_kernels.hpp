@@ -369,6 +369,339 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
   __syncthreads();
 }
 
+// ------------------------------------------------- exact discrete gradient
+// G = h^-2 dE_h/dphi for E_h = h^2 sum over interior sites of e(phi, D_x phi, D_y phi)
+// with D of eq. (1). By the chain rule, G(k) = de/dphi(k) - sum_i D_i[F_i](k) with
+// the fluxes F_i = de/d(D_i phi) set to zero outside the interior (the energy
+// has no terms there; eq. (1) is antisymmetric). A tile of 64 x 16 sites stages
+// the stage point with halo 4, forms the fluxes on the tile plus a ring of 2
+// and then G on the tile. Fluxes (3 per direction):
+//   Abelian Higgs  x: (P1, Q1, B)   y: (P2, Q2, B)     with D_k psi = P_k + i Q_k
+//   chiral magnet  x: J D_x n + D (0, -n3, n2)   y: J D_y n + D (n3, 0, -n1)
+constexpr int kExTX = 64, kExTY = 16, kExRY = 4;
+
+template <class T, int LX>
+__device__ __forceinline__ void lds_dxdy(const T* __restrict__ p, int ly, int lx, T c1, T& dx, T& dy) {
+  const T* r = p + ly * LX + lx;
+  dx = c1 * ((r[-2] - r[2]) + T(8) * (r[1] - r[-1]));
+  dy = c1 * ((r[-2 * LX] - r[2 * LX]) + T(8) * (r[LX] - r[-LX]));
+}
+
+template <class T, int TH, int LX>
+__device__ __forceinline__ void site_fluxes(T* const (&s)[4], int ly, int lx, T c1, const InstView<T>& V, bool xdir,
+                                            T (&F)[3]) {
+  if (TH == 0) {
+    T dxp, dyp, dxq, dyq, dxa1, dya1, dxa2, dya2;
+    lds_dxdy<T, LX>(s[0], ly, lx, c1, dxp, dyp);
+    lds_dxdy<T, LX>(s[1], ly, lx, c1, dxq, dyq);
+    lds_dxdy<T, LX>(s[2], ly, lx, c1, dxa1, dya1);
+    lds_dxdy<T, LX>(s[3], ly, lx, c1, dxa2, dya2);
+    const int o = ly * LX + lx;
+    const T p = s[0][o], q = s[1][o], ax = s[2][o], ay = s[3][o];
+    if (xdir) { F[0] = dxp + ax * q; F[1] = dxq - ax * p; }
+    else { F[0] = dyp + ay * q; F[1] = dyq - ay * p; }
+    F[2] = dxa2 - dya1;
+  } else {
+    const T J = (T)V.p[0], Dm = (T)V.p[1];
+    const int o = ly * LX + lx;
+    T d[3];
+    for (int c = 0; c < 3; ++c) {
+      T dx, dy;
+      lds_dxdy<T, LX>(s[c], ly, lx, c1, dx, dy);
+      d[c] = xdir ? dx : dy;
+    }
+    const T n0 = s[0][o], n1 = s[1][o], n2 = s[2][o];
+    if (xdir) { F[0] = J * d[0]; F[1] = J * d[1] - Dm * n2; F[2] = J * d[2] + Dm * n1; }
+    else { F[0] = J * d[0] + Dm * n2; F[1] = J * d[1]; F[2] = J * d[2] - Dm * n0; }
+  }
+}
+
+template <class T, int TH, int PASS>
+__device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, bool arrest, const T* __restrict__ src,
+                                                T* __restrict__ out, long out_pitch, long out_plane, int x0, int y0,
+                                                T* __restrict__ lds, double& e_acc, double& g_acc, int& nf) {
+  constexpr int TX = kExTX, TY = kExTY, RY = kExRY, NT = TX * (TY / RY);
+  constexpr int C = NComp<TH>::value;
+  constexpr int LX = TX + 8, LY = TY + 8;
+  constexpr int NRING = 8 * LX + 8 * TY;
+  constexpr int FXW = TX + 4, NXF = TY * FXW, NYF = (TY + 4) * TX;
+  constexpr int KX = (NXF + NT - 1) / NT, KY = (NYF + NT - 1) / NT;
+  constexpr bool REDUCE = (PASS == kP1 || PASS == kEval || PASS == kCheck);
+  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  constexpr bool WITH_A = (PASS == kP3 || PASS == kP4);
+  T* s[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s[c] = lds + (c < C ? c : 0) * (LY * LX);
+  T* fx = lds;             // [3][TY][FXW], written over the stage point after the flux phase
+  T* fy = lds + 3 * NXF;   // [3][TY + 4][TX]
+
+  const int Nx = V.Nx, Ny = V.Ny;
+  const long pitch = V.pitch, plane = V.plane;
+  const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : (cur ? V.phi[1] : V.phi[0]);
+  const T* __restrict__ vv = cur ? V.vel[1] : V.vel[0];
+  const T* __restrict__ aa = (PASS == kP3) ? V.a1 : V.a2;
+  const T dt = (T)V.dt;
+  T cv = T(0), ca = T(0);
+  if (PASS == kP2) cv = T(0.5) * dt;
+  if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
+  if (PASS == kP4) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (arrest) cv = T(0);
+  const double h = V.h;
+  const T c1 = T(1.0 / (12.0 * h));
+  const double d1 = 1.0 / (12.0 * h);
+  const int tid = threadIdx.y * TX + threadIdx.x;
+  const int gi = x0 + threadIdx.x;
+
+  auto stage_at = [&](int gi_, int gj_, T (&raw_p)[4], T (&raw_v)[4], T (&raw_a)[4], T (&S)[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) raw_p[c] = raw_v[c] = raw_a[c] = S[c] = T(0);
+    if (gj_ < -2 || gj_ > Ny + 1 || gi_ < -2 || gi_ > Nx + 1) return;
+    const long off = (long)(gj_ + 2) * pitch + (gi_ + 2);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      raw_p[c] = ph[c * plane + off];
+      T x = raw_p[c];
+      if (STAGED) {
+        raw_v[c] = vv[c * plane + off];
+        x += cv * raw_v[c];
+        if (WITH_A) {
+          raw_a[c] = aa[c * plane + off];
+          x += ca * raw_a[c];
+        }
+      }
+      S[c] = x;
+    }
+    if (TH == 1 && STAGED && gi_ >= 0 && gi_ < Nx && gj_ >= 0 && gj_ < Ny) {
+      const T inv = T(1) / sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+      S[0] *= inv;
+      S[1] *= inv;
+      S[2] *= inv;
+    }
+  };
+
+  // ---- stage: own sites (raw inputs kept), then the halo-4 frame
+  T rp[RY][4], rv[RY][4], ra[RY][4];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    T S[4];
+    const int ly = 4 + threadIdx.y * RY + r;
+    stage_at(gi, y0 + ly - 4, rp[r], rv[r], ra[r], S);
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c][ly * LX + 4 + threadIdx.x] = S[c];
+  }
+  for (int idx = tid; idx < NRING; idx += NT) {
+    int ly, lx;
+    if (idx < 8 * LX) {
+      const int rr = idx / LX;
+      ly = rr < 4 ? rr : LY - 8 + rr;
+      lx = idx - rr * LX;
+    } else {
+      const int j = idx - 8 * LX;
+      ly = 4 + (j >> 3);
+      const int cc = j & 7;
+      lx = cc < 4 ? cc : LX - 8 + cc;
+    }
+    T d0[4], d1v[4], d2[4], S[4];
+    stage_at(x0 - 4 + lx, y0 - 4 + ly, d0, d1v, d2, S);
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c][ly * LX + lx] = S[c];
+  }
+  __syncthreads();
+
+  // ---- energy density (FP64, stored values) and normalisation for the chiral magnet
+  if (REDUCE) {
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int ly = 4 + threadIdx.y * RY + r, lx = 4 + threadIdx.x;
+      const int gj = y0 + ly - 4;
+      if (gi < Nx && gj < Ny) {
+        Jet<double> Jd[4];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const T* q = s[c] + ly * LX + lx;
+          Jd[c].f = (double)q[0];
+          Jd[c].x = d1 * (((double)q[-2] - (double)q[2]) + 8.0 * ((double)q[1] - (double)q[-1]));
+          Jd[c].y = d1 * (((double)q[-2 * LX] - (double)q[2 * LX]) + 8.0 * ((double)q[LX] - (double)q[-LX]));
+          Jd[c].xx = Jd[c].yy = Jd[c].xy = 0.0;
+        }
+        const double e = TH == 0 ? ah_density<double>(Jd, V.p[0]) : cm_density<double>(Jd, V.p[0], V.p[1], V.p[2], V.p[3]);
+        e_acc += e;
+        if (!isfinite(e)) ++nf;
+      }
+    }
+    if (TH == 1) {
+      __syncthreads();
+      for (int idx = tid; idx < LX * LY; idx += NT) {
+        const int ly = idx / LX, lx = idx - ly * LX;
+        const int gi2 = x0 - 4 + lx, gj2 = y0 - 4 + ly;
+        if (gi2 >= 0 && gi2 < Nx && gj2 >= 0 && gj2 < Ny) {
+          const T n0 = s[0][idx], n1 = s[1][idx], n2 = s[2][idx];
+          const T inv = T(1) / sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+          s[0][idx] = n0 * inv;
+          s[1][idx] = n1 * inv;
+          s[2][idx] = n2 * inv;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- pointwise terms de/dphi at the own sites (and the stage point there)
+  T g[RY][4], cen[RY][4];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int ly = 4 + threadIdx.y * RY + r, lx = 4 + threadIdx.x;
+    const int o = ly * LX + lx;
+    T dx[4], dy[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { cen[r][c] = T(0); dx[c] = dy[c] = T(0); g[r][c] = T(0); }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      cen[r][c] = s[c][o];
+      lds_dxdy<T, LX>(s[c], ly, lx, c1, dx[c], dy[c]);
+    }
+    if (TH == 0) {
+      const T p = cen[r][0], q = cen[r][1], ax = cen[r][2], ay = cen[r][3];
+      const T P1 = dx[0] + ax * q, Q1 = dx[1] - ax * p, P2 = dy[0] + ay * q, Q2 = dy[1] - ay * p;
+      const T Wm = T(1) - (p * p + q * q);
+      const T lam = (T)V.p[0];
+      g[r][0] = -(ax * Q1 + ay * Q2) - T(0.5) * lam * Wm * p;
+      g[r][1] = (ax * P1 + ay * P2) - T(0.5) * lam * Wm * q;
+      g[r][2] = P1 * q - Q1 * p;
+      g[r][3] = P2 * q - Q2 * p;
+    } else {
+      const T Dm = (T)V.p[1], K = (T)V.p[2], Bz = (T)V.p[3];
+      g[r][0] = -Dm * dy[2];
+      g[r][1] = Dm * dx[2];
+      g[r][2] = Dm * (dy[0] - dx[1]) - (T(2) * K * cen[r][2] + Bz);
+    }
+  }
+
+  // ---- fluxes on the tile plus a ring of 2 (zero outside the interior), kept in
+  // registers until every thread is done with the stage point
+  T fxr[KX][3], fyr[KY][3];
+#pragma unroll
+  for (int k = 0; k < KX; ++k) {
+    const int idx = tid + k * NT;
+    fxr[k][0] = fxr[k][1] = fxr[k][2] = T(0);
+    if (idx < NXF) {
+      const int r = idx / FXW, cc = idx - r * FXW - 2;
+      const int gi2 = x0 + cc, gj2 = y0 + r;
+      if (gi2 >= 0 && gi2 < Nx && gj2 < Ny) site_fluxes<T, TH, LX>(s, r + 4, cc + 4, c1, V, true, fxr[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KY; ++k) {
+    const int idx = tid + k * NT;
+    fyr[k][0] = fyr[k][1] = fyr[k][2] = T(0);
+    if (idx < NYF) {
+      const int r = idx / TX - 2, cc = idx - (idx / TX) * TX;
+      const int gi2 = x0 + cc, gj2 = y0 + r;
+      if (gi2 < Nx && gj2 >= 0 && gj2 < Ny) site_fluxes<T, TH, LX>(s, r + 4, cc + 4, c1, V, false, fyr[k]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KX; ++k) {
+    const int idx = tid + k * NT;
+    if (idx < NXF)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) fx[f * NXF + idx] = fxr[k][f];
+  }
+#pragma unroll
+  for (int k = 0; k < KY; ++k) {
+    const int idx = tid + k * NT;
+    if (idx < NYF)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) fy[f * NYF + idx] = fyr[k][f];
+  }
+  __syncthreads();
+
+  // ---- G = de/dphi - D_x F_x - D_y F_y, then the pass epilogue
+  T* __restrict__ phn = cur ? V.phi[0] : V.phi[1];
+  T* __restrict__ vn = cur ? V.vel[0] : V.vel[1];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int tr = threadIdx.y * RY + r;
+    const int gj = y0 + tr;
+    if (gi >= Nx || gj >= Ny) continue;
+    T dfx[3], dfy[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const T* px = fx + f * NXF + tr * FXW + threadIdx.x + 2;
+      dfx[f] = c1 * ((px[-2] - px[2]) + T(8) * (px[1] - px[-1]));
+      const T* py = fy + f * NYF + (tr + 2) * TX + threadIdx.x;
+      dfy[f] = c1 * ((py[-2 * TX] - py[2 * TX]) + T(8) * (py[TX] - py[-TX]));
+    }
+    T G[4];
+    if (TH == 0) {
+      G[0] = g[r][0] - dfx[0] - dfy[0];
+      G[1] = g[r][1] - dfx[1] - dfy[1];
+      G[2] = g[r][2] + dfy[2];
+      G[3] = g[r][3] - dfx[2];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) G[c] = g[r][c] - dfx[c] - dfy[c];
+      const T gn = G[0] * cen[r][0] + G[1] * cen[r][1] + G[2] * cen[r][2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) G[c] -= gn * cen[r][c];
+      G[3] = T(0);
+    }
+    const long off = (long)(gj + 2) * pitch + (gi + 2);
+    if (REDUCE) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        g_acc = fmax(g_acc, fabs((double)G[c]));
+        if (!isfinite(G[c])) ++nf;
+      }
+    }
+    if (PASS == kP1) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) __builtin_nontemporal_store(-G[c], &V.a1[c * plane + off]);
+    } else if (PASS == kEval) {
+      if (out != nullptr) {
+        const long o = (long)(gj + 2) * out_pitch + (gi + 2);
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[c * out_plane + o] = G[c];
+      }
+    } else if (PASS == kP2) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) __builtin_nontemporal_store(-G[c], &V.a2[c * plane + off]);
+    } else if (PASS == kP3) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const long k = c * plane + off;
+        __builtin_nontemporal_store(ra[r][c] + T(2) * __builtin_nontemporal_load(&V.a2[k]) - T(2) * G[c], &V.q[k]);
+      }
+    } else if (PASS == kP4) {
+      T pn[4], vnew[4];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const long k = c * plane + off;
+        const T v0 = arrest ? T(0) : rv[r][c];
+        const T qq = __builtin_nontemporal_load(&V.q[k]);
+        pn[c] = rp[r][c] + dt * v0 + (dt * dt / T(12)) * (qq + __builtin_nontemporal_load(&V.a1[k]));
+        vnew[c] = v0 + (dt / T(6)) * (qq - G[c]);
+      }
+      if (TH == 1) {
+        const T inv = T(1) / sqrt(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pn[c] *= inv;
+        const T vd = vnew[0] * pn[0] + vnew[1] * pn[1] + vnew[2] * pn[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vnew[c] -= vd * pn[c];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const long k = c * plane + off;
+        __builtin_nontemporal_store(pn[c], &phn[k]);
+        __builtin_nontemporal_store(vnew[c], &vn[k]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Status update after a reduction of one field (thread 0 of the finalising
 // workgroup): arrest test E > E_prev (strict, eq. (4)), the stop rules when
 // minimising, and the step counter (P1 only). E is already multiplied by h^2.
@@ -442,6 +775,65 @@ __global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
 
   // ---- two-level FP64 reduction with a deterministic last-workgroup finalise
   const int tid = threadIdx.y * TX + threadIdx.x;
+  block_reduce3<NT>(e_acc, g_acc, nf, red);
+  __shared__ int is_last;
+  if (tid == 0) {
+    double* p = a.partials + 4 * (long)blockIdx.x;
+    p[0] = e_acc;
+    p[1] = g_acc;
+    p[2] = (double)nf;
+    __threadfence();
+    const unsigned prev = atomicAdd(&st->counter, 1u);
+    is_last = (prev == (unsigned)(gridDim.x - 1));
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double se = 0.0, sg = 0.0;
+  int sn = 0;
+  for (int k = tid; k < (int)gridDim.x; k += NT) {
+    const double* p = a.partials + 4 * (long)k;
+    se += __builtin_nontemporal_load(p);
+    sg = fmax(sg, __builtin_nontemporal_load(p + 1));
+    sn += (int)__builtin_nontemporal_load(p + 2);
+  }
+  __syncthreads();
+  block_reduce3<NT>(se, sg, sn, red);
+  if (tid == 0) finalise_status<PASS>(st, a.cf.h * a.cf.h * se, sg, sn);
+}
+
+// The single-lattice launch of the exact-gradient passes (tile 64 x 16, 256 threads).
+template <class T, int TH, int PASS>
+__global__ void __launch_bounds__(256) stage_pass_exact(PassArgs<T> a) {
+  constexpr int C = NComp<TH>::value;
+  constexpr int LX = kExTX + 8, LY = kExTY + 8;
+  constexpr int NFL = 3 * (kExTY * (kExTX + 4) + (kExTY + 4) * kExTX);
+  constexpr int NLDS = C * LY * LX > NFL ? C * LY * LX : NFL;
+  constexpr int NT = 256;
+  constexpr bool REDUCE = (PASS == kP1 || PASS == kEval || PASS == kCheck);
+  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  __shared__ __align__(16) T lds[NLDS];
+  __shared__ double red[3 * (NT / 64)];
+
+  DevStatus* __restrict__ st = a.st;
+  if (PASS != kEval && st->done) return;
+  const long long step = st->step;
+  const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
+  const bool arrest = STAGED ? (st->arrest != 0) : false;
+  const InstView<T> V = view_of<T>(a.B, a.cf);
+  double e_acc = 0.0, g_acc = 0.0;
+  int nf = 0;
+  const int ntiles = a.ntx * a.nty;
+  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int per = (ntiles + 7) >> 3;
+  const int tend = min(ntiles, (xcd + 1) * per);
+  for (int t = xcd * per + q; t < tend; t += m) {
+    const int tyi = t / a.ntx;
+    tile_body_exact<T, TH, PASS>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane,
+                                 (t - tyi * a.ntx) * kExTX, tyi * kExTY, lds, e_acc, g_acc, nf);
+  }
+  if (!REDUCE) return;
+  const int tid = threadIdx.y * kExTX + threadIdx.x;
   block_reduce3<NT>(e_acc, g_acc, nf, red);
   __shared__ int is_last;
   if (tid == 0) {

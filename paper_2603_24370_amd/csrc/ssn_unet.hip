@@ -225,16 +225,35 @@ __global__ void reduce_splits(const float* __restrict__ part, int nsplit, long n
   out[k] = s;
 }
 
-// per-block channel sums of an NHWC view (fp32 partials [nblk][C]); C <= 256
+// Per-block channel sums of an NHWC view (bf16 g, or fp32 gf with channel
+// stride gf_cs) into fp32 partials [nblk][C]. Block y takes channels
+// [256 y, 256 y + Cc), Cc = min(C - 256 y, 256); thread t sums channel t % Cc
+// over the pixels b0 + t / Cc, step 256 / Cc, of the block's pixel range, and
+// the lanes of each channel are then added in lane order (deterministic).
 __global__ void __launch_bounds__(256) channel_sums(TV g, const float* __restrict__ gf, int gf_cs, long npix, int C,
                                                     float* __restrict__ part) {
-  const int c = threadIdx.x;
-  if (c >= C) return;
+  __shared__ float red[256];
+  const int t = threadIdx.x;
+  const int c0 = 256 * blockIdx.y;
+  const int Cc = min(C - c0, 256);
+  const int L = 256 / Cc;
+  const int c = t % Cc, l = t / Cc;
   const long per = (npix + gridDim.x - 1) / gridDim.x;
   const long b0 = blockIdx.x * per, b1 = std::min(npix, b0 + per);
   float s = 0.0f;
-  for (long p = b0; p < b1; ++p) s += gf ? gf[p * gf_cs + c] : bf2f(g.p[p * g.cs + g.coff + c]);
-  part[(long)blockIdx.x * C + c] = s;
+  if (l < L) {
+    if (gf)
+      for (long p = b0 + l; p < b1; p += L) s += gf[p * gf_cs + c0 + c];
+    else
+      for (long p = b0 + l; p < b1; p += L) s += bf2f(g.p[p * g.cs + g.coff + c0 + c]);
+  }
+  red[t] = s;
+  __syncthreads();
+  if (t < Cc) {
+    float a = 0.0f;
+    for (int k = 0; k < L; ++k) a += red[k * Cc + t];
+    part[(long)blockIdx.x * C + c0 + t] = a;
+  }
 }
 
 __global__ void avgpool2_fwd(TV in, TV out) {
@@ -337,17 +356,29 @@ __global__ void head_bwd_data(const float* __restrict__ gout, const float* __res
   }
 }
 
-// per-block partials of gw[o][ci] = sum_pix gout[pix][o] a[pix][ci]  ([nblk][cout * C])
+// Per-block partials of gw[o][ci] = sum_pix gout[pix][o] a[pix][ci] ([nblk][cout * C],
+// cout * C <= 256): thread t takes entry k = t % K, K = cout * C, over the pixels
+// b0 + t / K, step 256 / K, of the block's range; lanes are added in order.
 __global__ void __launch_bounds__(256) head_wgrad(const float* __restrict__ gout, TV a, int cout, long npix,
                                                   float* __restrict__ part) {
-  const int k = threadIdx.x;  // o * C + c
-  if (k >= cout * a.C) return;
+  __shared__ float red[256];
+  const int t = threadIdx.x;
+  const int K = cout * a.C;
+  const int L = 256 / K;
+  const int k = t % K, l = t / K;
   const int o = k / a.C, c = k - o * a.C;
   const long per = (npix + gridDim.x - 1) / gridDim.x;
   const long b0 = blockIdx.x * per, b1 = std::min(npix, b0 + per);
   float s = 0.0f;
-  for (long p = b0; p < b1; ++p) s += gout[p * cout + o] * bf2f(a.p[p * a.cs + a.coff + c]);
-  part[(long)blockIdx.x * cout * a.C + k] = s;
+  if (l < L)
+    for (long p = b0 + l; p < b1; p += L) s += gout[p * cout + o] * bf2f(a.p[p * a.cs + a.coff + c]);
+  red[t] = s;
+  __syncthreads();
+  if (t < K) {
+    float acc = 0.0f;
+    for (int q = 0; q < L; ++q) acc += red[q * K + t];
+    part[(long)blockIdx.x * K + t] = acc;
+  }
 }
 
 // mse: per-block partial sums of (out - t)^2 and gout = 2 (out - t) / count
@@ -446,7 +477,7 @@ struct ConvL {
   bf16_t* wb;         // [rup(Ci, 32)][9][Co]
 };
 
-constexpr int kPartBlocks = 64;
+constexpr int kPartBlocks = 256;
 constexpr long kWgradPartFloats = 1024L * 9 * 1024;
 
 }  // namespace
@@ -622,9 +653,9 @@ void launch_wgrad(ssn_net* n, const ConvL& c, TV gz, TV x) {
   const long nw = (long)c.Co * 9 * c.Ci;
   hipLaunchKernelGGL(reduce_splits, dim3(grid1(nw)), dim3(256), 0, n->stream, n->part, nsplit, nw, n->G + c.w_off);
   // bias gradient: per-channel sums of gz
-  hipLaunchKernelGGL(channel_sums, dim3(kPartBlocks), dim3(256), 0, n->stream, gz, (const float*)nullptr, 0,
-                     (long)gz.N * gz.H * gz.W, c.Co, n->cpart);
-  hipLaunchKernelGGL(reduce_splits, dim3(1), dim3(256), 0, n->stream, n->cpart, kPartBlocks, (long)c.Co,
+  hipLaunchKernelGGL(channel_sums, dim3(kPartBlocks, (c.Co + 255) / 256), dim3(256), 0, n->stream, gz,
+                     (const float*)nullptr, 0, (long)gz.N * gz.H * gz.W, c.Co, n->cpart);
+  hipLaunchKernelGGL(reduce_splits, dim3(grid1(c.Co)), dim3(256), 0, n->stream, n->cpart, kPartBlocks, (long)c.Co,
                      n->G + c.b_off);
 }
 
@@ -683,8 +714,8 @@ int net_backward(ssn_net* n, const float* target, int nb, double* loss) {
   // head
   hipLaunchKernelGGL(head_wgrad, dim3(kPartBlocks), dim3(256), 0, n->stream, n->GOUT, n->ADb[0].all(nb), n->cout, npix,
                      n->cpart);
-  hipLaunchKernelGGL(reduce_splits, dim3(1), dim3(256), 0, n->stream, n->cpart, kPartBlocks,
-                     (long)n->cout * n->ch[0], n->G + n->hw_off);
+  hipLaunchKernelGGL(reduce_splits, dim3(grid1((long)n->cout * n->ch[0])), dim3(256), 0, n->stream, n->cpart,
+                     kPartBlocks, (long)n->cout * n->ch[0], n->G + n->hw_off);
   TV none;
   none.p = nullptr;
   hipLaunchKernelGGL(channel_sums, dim3(kPartBlocks), dim3(256), 0, n->stream, none, n->GOUT, n->cout, npix, n->cout,

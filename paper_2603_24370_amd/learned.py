@@ -186,3 +186,55 @@ def summarise(recs):
             "learned_win_fraction": float(np.mean([x < 1 for x in ratio])) if ratio else None,
             "median_ansatz_s": float(np.median([r["ansatz_s"] for r in both])) if both else None,
             "median_learned_s": float(np.median([r["learned_s"] for r in both])) if both else None}
+
+
+def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=12, batch=8, lr=1e-3, seed=0,
+                 tol=1e-6, device="cuda:0", log=print):
+    """Data -> training -> A/B on held-out instances; returns a summary dict."""
+    import torch
+    t0 = time.perf_counter()
+    train_insts = [learned_instance(i, 5_000_000, side) for i in range(n_train)]
+    test_insts = [learned_instance(j, 6_000_000, side) for j in range(n_test)]
+    X, T, steps = generate_dataset(train_insts, batch=64, device=device, log=log)
+    t_data = time.perf_counter() - t0
+    net = ss.Net(levels=levels, base=base, cin=2, cout=4, N=batch, H=side, W=side, device=device)
+    net.set_weights(init_weights(seed, levels, base, 2, 4))
+    losses, tflops, t_train = train(net, X, T, epochs=epochs, batch=batch, lr=lr, seed=seed, log=log)
+    del X, T
+    torch.cuda.empty_cache()
+    recs = ab_compare(net, test_insts, tol=tol, device=device, log=log)
+    out = summarise(recs)
+    out.update({"n_train": n_train, "side": side, "levels": levels, "base": base, "epochs": epochs,
+                "batch": batch, "lr": lr, "data_s": t_data, "data_median_steps": float(np.median(steps)),
+                "train_s": t_train, "train_TFLOPs": tflops, "loss_first_epoch": losses[0],
+                "loss_last_epoch": losses[-1], "tol": tol, "records": recs})
+    net.close()
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="learned initialiser: generate minima, train, compare starts")
+    ap.add_argument("--n-train", type=int, default=2048)
+    ap.add_argument("--n-test", type=int, default=64)
+    ap.add_argument("--side", type=int, default=256)
+    ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--base", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", default=None, help="write the summary JSON here")
+    a = ap.parse_args(argv)
+    res = run_pipeline(a.n_train, a.n_test, a.side, a.levels, a.base, a.epochs, a.batch, a.lr,
+                       log=lambda m: print(m, flush=True))
+    brief = {k: v for k, v in res.items() if k != "records"}
+    print(json.dumps(brief), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

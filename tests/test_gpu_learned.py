@@ -110,10 +110,34 @@ def test_adam_step_matches_oracle_update(ss):
     net.close()
 
 
-def test_training_reduces_the_loss(ss):
-    P, x, t, net = _setup(ss, seed=3)
+def _learnable(x):
+    """Pointwise targets that a stack of 3x3 convolutions can represent."""
+    t = np.empty(x.shape[:3] + (COUT,))
+    t[..., 0] = np.tanh(x[..., 0])
+    t[..., 1] = 0.5 * x[..., 1]
+    t[..., 2] = 0.25 * x[..., 0] * x[..., 1]
+    t[..., 3] = -0.3 * np.tanh(x[..., 1])
+    return t
+
+
+def test_training_follows_the_oracle(ss):
+    """30 Adam steps on the GPU (BF16 MFMA, FP32 master weights) against the same
+    30 steps of the FP64 oracle network: the loss curves agree within 15 per cent
+    at every step (BF16 rounding of weights and activations) and both fall."""
+    P, x, _, net = _setup(ss, seed=3)
+    t = _learnable(x)
     losses = [net.train_step(x, t, 3e-3) for _ in range(30)]
-    assert losses[-1] < 0.7 * losses[0]
+    Po = {k: v.copy() for k, v in _unflat(_flat(P).astype(np.float32).astype(np.float64)).items()}
+    state, ref = {}, []
+    for _ in range(30):
+        out, cache = U.forward(Po, x, LV)
+        loss, g = U.mse(out, t)
+        U.adam_step(Po, U.backward(Po, cache, g, LV), state, lr=3e-3)
+        ref.append(loss)
+    print("[train] gpu", losses[0], losses[-1], "oracle", ref[0], ref[-1], flush=True)
+    for a, b in zip(losses, ref):
+        assert abs(a - b) <= 0.15 * b
+    assert losses[-1] < 0.35 * losses[0]
     # a second identical run is bitwise repeatable (fixed-order reductions)
     net2 = ss.Net(levels=LV, base=BASE, cin=CIN, cout=COUT, N=2, H=H, W=H)
     net2.set_weights(_flat(P).astype(np.float32))
