@@ -75,6 +75,7 @@ struct Layout {
   size_t set_bytes;         // bytes of one C-plane field set (256-B aligned)
   size_t status_off, partial_off, init_off, total;
   int ntx, nty, nlaunch;    // for the selected tile shape
+  int seg;                  // tiles per work unit of the stage launches
 };
 
 void set_tiles(Layout& L, int Nx, int Ny, int tile) {
@@ -82,6 +83,9 @@ void set_tiles(Layout& L, int Nx, int Ny, int tile) {
   L.ntx = (Nx + tc.TX - 1) / tc.TX;
   L.nty = (Ny + tc.TY - 1) / tc.TY;
   L.nlaunch = (int)std::min<long>(round_up((long)L.ntx * L.nty, 8), kMaxGroups);
+  // one unit per workgroup where there are enough tiles, else single tiles
+  L.seg = (int)std::max<long>(1, ((long)L.ntx * L.nty) / L.nlaunch);
+  L.seg = std::min(L.seg, L.nty);
 }
 
 Layout make_layout(int C, int Nx, int Ny, int esize) {
@@ -171,6 +175,7 @@ PassArgs<T> pass_args(const ss_ctx* c) {
   a.out_pitch = a.out_plane = 0;
   a.ntx = c->L.ntx;
   a.nty = c->L.nty;
+  a.seg = c->L.seg;
   return a;
 }
 

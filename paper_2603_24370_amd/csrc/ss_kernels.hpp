@@ -79,7 +79,30 @@ struct PassArgs {
   T* out;        // kEval: gradient output in the caller's layout (nullptr = none)
   long out_pitch, out_plane;
   int ntx, nty;  // tiles along x and y
+  int seg;       // tiles per work unit: a unit is `seg` tiles stacked along y
 };
+
+// Tile traversal of the persistent stage launches. Work units are columns of
+// `seg` tiles stacked along y, numbered row-major over (unit row, tile column).
+// XCD x (workgroups b with b % 8 == x) owns the contiguous unit range
+// [x * per, (x + 1) * per); its m = gridDim.x / 8 workgroups take units
+// x*per + q, + m, ... (q = b / 8). Workgroups resident together on an XCD thus
+// hold horizontally adjacent units (shared x-halo lines in that XCD's L2), and
+// each walks its unit from top to bottom, so a tile's top halo rows are the
+// rows its workgroup read for the previous tile.
+template <class F>
+__device__ __forceinline__ void for_each_tile(int ntx, int nty, int seg, F&& body) {
+  const int nseg = (nty + seg - 1) / seg;
+  const int nunits = ntx * nseg;
+  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int per = (nunits + 7) >> 3;
+  const int uend = min(nunits, (xcd + 1) * per);
+  for (int u = xcd * per + q; u < uend; u += m) {
+    const int sg = u / ntx, tx = u - sg * ntx;
+    const int ty1 = min(nty, (sg + 1) * seg);
+    for (int ty = sg * seg; ty < ty1; ++ty) body(tx, ty);
+  }
+}
 
 template <class T>
 struct Vec16;
@@ -237,21 +260,12 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
   }
   __syncthreads();
 
-  Jet<T> J[C][RY];
-  double ex[C][RY], ey[C][RY];
+  // E_h density in FP64 from the stored (unnormalised) values in LDS, own sites
+  auto energy_density = [&]() {
+    double ex[C][RY], ey[C][RY];
+    Jet<T> Jr[C][RY];
 #pragma unroll
-  for (int c = 0; c < C; ++c)
-    column_jets<T, LX, RY, TH == 0, REDUCE && TH == 0>(s[c], lx, ly0, c1, c2, d1, J[c], ex[c], ey[c]);
-
-  // ---- E_h density in FP64 from the stored (unnormalised) values
-  if (REDUCE) {
-    if (TH == 1) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        Jet<T> Jr[RY];
-        column_jets<T, LX, RY, false, true>(s[c], lx, ly0, c1, c2, d1, Jr, ex[c], ey[c]);
-      }
-    }
+    for (int c = 0; c < C; ++c) column_jets<T, LX, RY, false, true>(s[c], lx, ly0, c1, c2, d1, Jr[c], ex[c], ey[c]);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       const int gj = y0 + ly0 - 2 + r;
@@ -259,7 +273,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
         Jet<double> Jd[4];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          Jd[c].f = (double)J[c][r].f;
+          Jd[c].f = (double)Jr[c][r].f;
           Jd[c].x = ex[c][r];
           Jd[c].y = ey[c][r];
           Jd[c].xx = Jd[c].yy = Jd[c].xy = 0.0;
@@ -271,6 +285,21 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
         if (!isfinite(e)) ++nf;
       }
     }
+  };
+
+  Jet<T> J[C][RY];
+  {
+    double dx_[C][RY], dy_[C][RY];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      column_jets<T, LX, RY, TH == 0, false>(s[c], lx, ly0, c1, c2, d1, J[c], dx_[c], dy_[c]);
+  }
+
+  // The chiral magnet needs E_h before the stage point is normalised in LDS;
+  // the Abelian Higgs energy is formed after the epilogue, so that the FP64
+  // energy and the FP32 gradient do not hold registers at the same time.
+  if (REDUCE) {
+    if (TH == 1) energy_density();
     if (TH == 1) {
       // the flow evaluates G at the normalised field
       __syncthreads();
@@ -286,9 +315,10 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
         }
       }
       __syncthreads();
+      double dx_[C][RY], dy_[C][RY];
 #pragma unroll
       for (int c = 0; c < C; ++c)
-        column_jets<T, LX, RY, false, false>(s[c], lx, ly0, c1, c2, d1, J[c], ex[c], ey[c]);
+        column_jets<T, LX, RY, false, false>(s[c], lx, ly0, c1, c2, d1, J[c], dx_[c], dy_[c]);
     }
   }
 
@@ -366,6 +396,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
       }
     }
   }
+  if (REDUCE && TH == 0) energy_density();
   __syncthreads();
 }
 
@@ -762,15 +793,10 @@ __global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
 
   double e_acc = 0.0, g_acc = 0.0;
   int nf = 0;
-  const int ntiles = a.ntx * a.nty;
-  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
-  const int per = (ntiles + 7) >> 3;
-  const int tend = min(ntiles, (xcd + 1) * per);
-  for (int t = xcd * per + q; t < tend; t += m) {
-    const int tyi = t / a.ntx;
-    tile_body<T, TH, PASS, TX, TY, RY>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane,
-                                       (t - tyi * a.ntx) * TX, tyi * TY, lds, e_acc, g_acc, nf);
-  }
+  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty) {
+    tile_body<T, TH, PASS, TX, TY, RY>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane, tx * TX, ty * TY,
+                                       lds, e_acc, g_acc, nf);
+  });
   if (!REDUCE) return;
 
   // ---- two-level FP64 reduction with a deterministic last-workgroup finalise
@@ -823,15 +849,10 @@ __global__ void __launch_bounds__(256) stage_pass_exact(PassArgs<T> a) {
   const InstView<T> V = view_of<T>(a.B, a.cf);
   double e_acc = 0.0, g_acc = 0.0;
   int nf = 0;
-  const int ntiles = a.ntx * a.nty;
-  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
-  const int per = (ntiles + 7) >> 3;
-  const int tend = min(ntiles, (xcd + 1) * per);
-  for (int t = xcd * per + q; t < tend; t += m) {
-    const int tyi = t / a.ntx;
-    tile_body_exact<T, TH, PASS>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane,
-                                 (t - tyi * a.ntx) * kExTX, tyi * kExTY, lds, e_acc, g_acc, nf);
-  }
+  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty) {
+    tile_body_exact<T, TH, PASS>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane, tx * kExTX, ty * kExTY,
+                                 lds, e_acc, g_acc, nf);
+  });
   if (!REDUCE) return;
   const int tid = threadIdx.y * kExTX + threadIdx.x;
   block_reduce3<NT>(e_acc, g_acc, nf, red);
