@@ -239,18 +239,22 @@ int ss_set_energy_target(ss_ctx* ctx, double e_target);
  * (Ny, Nx, channels):
  *   ss_learned_input:   (Ny, Nx, 2): sum_k exp(-r_k^2 / 2) at the n centres xy
  *                       (host, lattice coordinates), and the constant kappa;
- *   ss_learned_targets: (Ny, Nx, 4) from the context's current field psi, A:
- *                       |psi| - f_ans, wrap(arg psi - sum_k w_k theta_k) to
- *                       [-pi, pi), A_x - A_ans_x, A_y - A_ans_y, with the
- *                       ansatz of ss_init_ansatz for the same centres and windings;
- *   ss_init_learned:    sets psi = (f_ans + c0) exp(i (sum w_k theta_k + c1)),
- *                       A = A_ans + (c2, c3) on the interior from corrections
+ *   ss_learned_targets: (Ny, Nx, 4) from the context's current field psi, A in
+ *                       the co-rotating frame of the ansatz: Re and Im of
+ *                       psi exp(-i Theta) - f_ans, then A_x - A_ans_x, A_y - A_ans_y,
+ *                       with Theta = sum_k w_k theta_k and f_ans, A_ans the ansatz
+ *                       of ss_init_ansatz for the same centres and windings;
+ *   ss_init_learned:    sets psi = (f_ans + env (c0 + i c1)) exp(i Theta),
+ *                       A = A_ans + env (c2, c3) on the interior from corrections
  *                       corr (Ny, Nx, 4), the vacuum on the halo, and starts the
- *                       flow from rest (as ss_set_field).
+ *                       flow from rest (as ss_set_field). The envelope
+ *                       env = 1 - prod_k (1 - exp(-r_k^2 / (2 sigma^2))) keeps the
+ *                       corrections near the vortices; sigma <= 0 gives env = 1,
+ *                       for which ss_init_learned inverts ss_learned_targets.
  * The first two synchronise. */
 int ss_learned_input(ss_ctx* ctx, int n, const double* xy, double kappa, float* out);
 int ss_learned_targets(ss_ctx* ctx, int n, const double* xy, const double* w, float* out);
-int ss_init_learned(ss_ctx* ctx, int n, const double* xy, const double* w, const float* corr);
+int ss_init_learned(ss_ctx* ctx, int n, const double* xy, const double* w, const float* corr, double sigma);
 
 /* Tile shapes of the fused stage kernels. The library carries ss_tile_count()
  * compiled shapes (a workgroup covers TX x TY sites, each thread RY rows of

@@ -1309,8 +1309,10 @@ __device__ __forceinline__ void ah_ansatz_parts(double x, double y, const double
   }
 }
 
-// Training target of a relaxed field: (|psi| - f_ans, wrap(arg psi - sum theta),
-// A_x - A_ans_x, A_y - A_ans_y) at every interior site (Ny x Nx x 4, fp32).
+// Training target of a relaxed field in the co-rotating frame of the ansatz:
+// (Re, Im) of psi e^{-i Theta} - f_ans, then A_x - A_ans_x, A_y - A_ans_y, at every
+// interior site (Ny x Nx x 4, fp32). Theta = sum_k w_k theta_k. The first pair is
+// smooth through the vortex cores (no phase cut, no 0/0 where |psi| vanishes).
 template <class T>
 __global__ void __launch_bounds__(256) learned_targets(Bufs<T> B, Coeffs cf, const DevStatus* st, const double* xy,
                                                        const double* w, int n, float* out) {
@@ -1323,19 +1325,23 @@ __global__ void __launch_bounds__(256) learned_targets(Bufs<T> B, Coeffs cf, con
   const T* f = st->step & 1 ? B.phi[1] : B.phi[0];
   const long off = (long)(j + 2) * B.pitch + (i + 2);
   const double p = f[off], q = f[B.plane + off];
-  double d = atan2(q, p) - ph;
-  d -= 6.283185307179586 * floor((d + 3.141592653589793) / 6.283185307179586);
-  out[4 * k] = (float)(sqrt(p * p + q * q) - mod);
-  out[4 * k + 1] = (float)d;
+  const double cs = cos(ph), sn = sin(ph);
+  out[4 * k] = (float)(p * cs + q * sn - mod);
+  out[4 * k + 1] = (float)(q * cs - p * sn);
   out[4 * k + 2] = (float)((double)f[2 * B.plane + off] - ax);
   out[4 * k + 3] = (float)((double)f[3 * B.plane + off] - ay);
 }
 
-// Field from the ansatz plus predicted corrections: psi = (f_ans + c0) e^{i(theta + c1)},
-// A = A_ans + (c2, c3) on the interior; the halo gets the pure-gauge vacuum.
+// Field from the ansatz plus predicted corrections c, weighted by an envelope
+// that is 1 at the vortex centres and decays away from them,
+//   env = 1 - prod_k (1 - exp(-r_k^2 / (2 sigma^2)))   (sigma <= 0: env = 1),
+// so that a network's small errors far from the vortices (where the ansatz is
+// already the vacuum) do not seed slow, lattice-wide modes:
+//   psi = (f_ans + env (c0 + i c1)) e^{i Theta},   A = A_ans + env (c2, c3)
+// on the interior; the halo gets the pure-gauge vacuum.
 template <class T>
 __global__ void __launch_bounds__(256) init_learned(Bufs<T> B, Coeffs cf, const double* xy, const double* w, int n,
-                                                    const float* corr) {
+                                                    const float* corr, double sigma) {
   const long W = B.Nx + 4, H = B.Ny + 4;
   const long k = blockIdx.x * 256L + threadIdx.x;
   if (k >= W * H) return;
@@ -1347,12 +1353,23 @@ __global__ void __launch_bounds__(256) init_learned(Bufs<T> B, Coeffs cf, const 
   if (inner) {
     double mod, ph, ax, ay;
     ah_ansatz_parts(x, y, xy, w, n, mod, ph, ax, ay);
+    double env = 1.0;
+    if (sigma > 0.0) {
+      double far = 1.0;
+      const double s2 = 0.5 / (sigma * sigma);
+      for (int v = 0; v < n; ++v) {
+        const double dx = x - xy[2 * v], dy = y - xy[2 * v + 1];
+        far *= -expm1(-(dx * dx + dy * dy) * s2);
+      }
+      env = 1.0 - far;
+    }
     const float* c = corr + 4 * ((long)j * B.Nx + i);
-    const double m = mod + c[0], t = ph + c[1];
-    out[0] = m * cos(t);
-    out[1] = m * sin(t);
-    out[2] = ax + c[2];
-    out[3] = ay + c[3];
+    const double re = mod + env * c[0], im = env * c[1];
+    const double cs = cos(ph), sn = sin(ph);
+    out[0] = re * cs - im * sn;
+    out[1] = re * sn + im * cs;
+    out[2] = ax + env * c[2];
+    out[3] = ay + env * c[3];
   } else {
     double ph = 0.0, ax = 0.0, ay = 0.0;
     for (int v = 0; v < n; ++v) {

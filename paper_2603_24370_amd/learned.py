@@ -136,18 +136,17 @@ def time_to_target(solver, start, e_target, max_steps):
     return time.perf_counter() - t0, res
 
 
-def ab_compare(net, insts, tol=1e-6, ref_rel_e_tol=1e-9, ref_window=100, ref_max_steps=50000, max_steps=50000,
-               device="cuda:0", log=None):
-    """For each instance: a long ansatz-start run gives E_ref (stalled energy); then the
-    ansatz start and the learned start are flowed until E <= E_ref + tol |E_ref|.
-    Returns per-instance records; the learned start's time includes the network."""
+def ab_compare(net, insts, tol=1e-6, sigmas=(3.0,), ref_rel_e_tol=1e-9, ref_window=100, ref_max_steps=50000,
+               max_steps=50000, device="cuda:0", log=None):
+    """For each instance: a long ansatz-start run gives E_ref (its stalled energy);
+    then the ansatz start and the learned start (for each envelope width sigma)
+    are flowed until E <= E_ref + tol |E_ref|. Returns per-instance records; the
+    learned start's time includes building the input and running the network."""
     import torch
     m0 = insts[0]
-    s = ss.Solver("abelian_higgs", m0.Nx, m0.Ny, m0.h, m0.params, dtype="f32", device=device)
     x = torch.empty((1, m0.Ny, m0.Nx, 2), dtype=torch.float32, device=device)
     recs = []
     for k, m in enumerate(insts):
-        s.close()
         s = ss.Solver("abelian_higgs", m.Nx, m.Ny, m.h, m.params, dtype="f32", device=device)
         s.init_vortices(m.centres, seed=m.seed, noise_amp=1e-3)
         ref = s.minimise(grad_tol=0.0, rel_e_tol=ref_rel_e_tol, window=ref_window, max_steps=ref_max_steps,
@@ -158,38 +157,47 @@ def ab_compare(net, insts, tol=1e-6, ref_rel_e_tol=1e-9, ref_window=100, ref_max
         def ansatz_start():
             s.init_vortices(m.centres, seed=m.seed, noise_amp=1e-3)
 
-        def learned_start():
-            ss.ss_learned_input(s.ctx, m.centres, m.kappa, x.data_ptr())
-            corr = net.forward(x)
-            ss.ss_init_learned(s.ctx, m.centres, None, corr.data_ptr())
-
         ta, ra = time_to_target(s, ansatz_start, target, max_steps)
-        tl, rl = time_to_target(s, learned_start, target, max_steps)
         rec = {"kappa": m.kappa, "n_vortices": len(m.centres), "E_ref": E_ref, "ref_steps": ref["step"],
                "ansatz_s": ta, "ansatz_steps": ra["step"], "ansatz_reached": ra["reason"] == "target",
-               "learned_s": tl, "learned_steps": rl["step"], "learned_reached": rl["reason"] == "target"}
+               "ansatz_E": ra["energy"]}
+        for sg in sigmas:
+            def learned_start():
+                ss.ss_learned_input(s.ctx, m.centres, m.kappa, x.data_ptr())
+                corr = net.forward(x)
+                ss.ss_init_learned(s.ctx, m.centres, None, corr.data_ptr(), sigma=sg)
+
+            tl, rl = time_to_target(s, learned_start, target, max_steps)
+            rec.update({f"learned_s@{sg}": tl, f"learned_steps@{sg}": rl["step"],
+                        f"learned_reached@{sg}": rl["reason"] == "target", f"learned_E@{sg}": rl["energy"]})
         recs.append(rec)
-        if log and (k + 1) % 16 == 0:
+        s.close()
+        if log and (k + 1) % 8 == 0:
             log(f"[ab] {k + 1}/{len(insts)}")
-    s.close()
     return recs
 
 
-def summarise(recs):
-    both = [r for r in recs if r["ansatz_reached"] and r["learned_reached"]]
-    ratio = [r["learned_s"] / r["ansatz_s"] for r in both]
-    sratio = [r["learned_steps"] / max(1, r["ansatz_steps"]) for r in both]
-    return {"instances": len(recs), "both_reached": len(both),
-            "learned_missed": sum(1 for r in recs if not r["learned_reached"]),
+def summarise(recs, sigma):
+    """Median time and step ratios (learned / ansatz) over the instances both starts
+    brought to the target, the win fraction, and the misses of the learned start."""
+    key = f"@{sigma}"
+    both = [r for r in recs if r["ansatz_reached"] and r["learned_reached" + key]]
+    ratio = [r["learned_s" + key] / r["ansatz_s"] for r in both]
+    sratio = [r["learned_steps" + key] / max(1, r["ansatz_steps"]) for r in both]
+    return {"sigma": sigma, "instances": len(recs), "both_reached": len(both),
+            "learned_missed": sum(1 for r in recs if not r["learned_reached" + key]),
+            "ansatz_missed": sum(1 for r in recs if not r["ansatz_reached"]),
             "median_time_ratio": float(np.median(ratio)) if ratio else None,
             "median_step_ratio": float(np.median(sratio)) if sratio else None,
             "learned_win_fraction": float(np.mean([x < 1 for x in ratio])) if ratio else None,
             "median_ansatz_s": float(np.median([r["ansatz_s"] for r in both])) if both else None,
-            "median_learned_s": float(np.median([r["learned_s"] for r in both])) if both else None}
+            "median_learned_s": float(np.median([r["learned_s" + key] for r in both])) if both else None,
+            "total_ansatz_s": float(sum(r["ansatz_s"] for r in recs)),
+            "total_learned_s": float(sum(r["learned_s" + key] for r in recs))}
 
 
-def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=12, batch=8, lr=1e-3, seed=0,
-                 tol=1e-6, device="cuda:0", log=print):
+def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20, batch=8, lr=2e-3, seed=0,
+                 tol=1e-6, sigmas=(0.0, 3.0), device="cuda:0", log=print):
     """Data -> training -> A/B on held-out instances; returns a summary dict."""
     import torch
     t0 = time.perf_counter()
@@ -202,12 +210,13 @@ def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=12
     losses, tflops, t_train = train(net, X, T, epochs=epochs, batch=batch, lr=lr, seed=seed, log=log)
     del X, T
     torch.cuda.empty_cache()
-    recs = ab_compare(net, test_insts, tol=tol, device=device, log=log)
-    out = summarise(recs)
-    out.update({"n_train": n_train, "side": side, "levels": levels, "base": base, "epochs": epochs,
-                "batch": batch, "lr": lr, "data_s": t_data, "data_median_steps": float(np.median(steps)),
-                "train_s": t_train, "train_TFLOPs": tflops, "loss_first_epoch": losses[0],
-                "loss_last_epoch": losses[-1], "tol": tol, "records": recs})
+    recs = ab_compare(net, test_insts, tol=tol, sigmas=sigmas, device=device, log=log)
+    out = {"summary": [summarise(recs, sg) for sg in sigmas]}
+    out.update({"n_train": n_train, "n_test": n_test, "side": side, "levels": levels, "base": base,
+                "epochs": epochs, "batch": batch, "lr": lr, "data_s": t_data,
+                "data_median_steps": float(np.median(steps)), "train_s": t_train, "train_TFLOPs": tflops,
+                "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1], "losses": losses, "tol": tol,
+                "records": recs})
     net.close()
     return out
 
@@ -221,14 +230,16 @@ def main(argv=None):
     ap.add_argument("--side", type=int, default=256)
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--base", type=int, default=32)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--sigmas", default="0,3", help="envelope widths of the learned start (comma list)")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     a = ap.parse_args(argv)
-    res = run_pipeline(a.n_train, a.n_test, a.side, a.levels, a.base, a.epochs, a.batch, a.lr,
+    sig = tuple(float(v) for v in a.sigmas.split(","))
+    res = run_pipeline(a.n_train, a.n_test, a.side, a.levels, a.base, a.epochs, a.batch, a.lr, sigmas=sig,
                        log=lambda m: print(m, flush=True))
-    brief = {k: v for k, v in res.items() if k != "records"}
+    brief = {k: v for k, v in res.items() if k not in ("records", "losses")}
     print(json.dumps(brief), flush=True)
     if a.out:
         with open(a.out, "w") as f:

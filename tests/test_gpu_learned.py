@@ -157,33 +157,52 @@ def test_learned_input_and_targets(ss, orc):
     blob = I.blob_map(cen, N, h)
     assert np.abs(x[..., 0].cpu().numpy() - blob).max() < 1e-6
     assert np.all(x[..., 1].cpu().numpy() == np.float32(1.3))
-    # targets of the pure ansatz are zero; of a perturbed field they are the perturbation
+    # targets of the pure ansatz are zero; of a perturbed field they are the
+    # perturbation seen in the co-rotating frame: (d0 + i d1) e^{-i Theta}, d2, d3
     f = I.ah_vortex_ansatz(N, N, h, cen)
     rng = np.random.default_rng(0)
     d = np.zeros_like(f)
     d[:, 2:-2, 2:-2] = 1e-2 * rng.normal(size=(4, N, N))
-    s.set_field(f + d)
+    s.set_field(f)
     t = torch.empty((N, N, 4), dtype=torch.float32, device="cuda:0")
     ss.ss_learned_targets(s.ctx, cen, None, t.data_ptr())
+    assert np.abs(t.cpu().numpy()).max() < 1e-6
+    s.set_field(f + d)
+    ss.ss_learned_targets(s.ctx, cen, None, t.data_ptr())
     tt = t.cpu().numpy().astype(np.float64)
-    psi = (f + d)[0, 2:-2, 2:-2] + 1j * (f + d)[1, 2:-2, 2:-2]
-    psa = f[0, 2:-2, 2:-2] + 1j * f[1, 2:-2, 2:-2]
-    want_mod = np.abs(psi) - np.abs(psa)
-    assert np.abs(tt[..., 0] - want_mod).max() < 1e-6
+    X, Y = I.grid(N, N, h)
+    X, Y = X[2:-2, 2:-2], Y[2:-2, 2:-2]
+    theta = sum(np.arctan2(Y - cy, X - cx) for cx, cy in cen)
+    rot = (d[0, 2:-2, 2:-2] + 1j * d[1, 2:-2, 2:-2]) * np.exp(-1j * theta)
+    assert np.abs(tt[..., 0] - rot.real).max() < 1e-6
+    assert np.abs(tt[..., 1] - rot.imag).max() < 1e-6
     assert np.abs(tt[..., 2] - d[2, 2:-2, 2:-2]).max() < 1e-6
     assert np.abs(tt[..., 3] - d[3, 2:-2, 2:-2]).max() < 1e-6
-    # reconstruction from the targets returns the field (away from the cores, where
-    # the phase is defined) and zero corrections give the plain ansatz
+    # without an envelope the reconstruction inverts the targets at every interior
+    # site (to the fp32 rounding of the targets); zero corrections give the ansatz
     ss.ss_init_learned(s.ctx, cen, None, t.data_ptr())
     g = s.get_field().cpu().numpy()
-    far = np.abs(psa) > 0.3
-    assert np.abs((g[0, 2:-2, 2:-2] + 1j * g[1, 2:-2, 2:-2] - psi)[far]).max() < 1e-5
+    assert np.abs(g[:, 2:-2, 2:-2] - (f + d)[:, 2:-2, 2:-2]).max() < 1e-6
     z = torch.zeros_like(t)
     ss.ss_init_learned(s.ctx, cen, None, z.data_ptr())
     g0 = s.get_field().cpu().numpy()
     s.init_vortices(cen)
     ga = s.get_field().cpu().numpy()
     assert np.abs(g0 - ga).max() < 1e-12
+    # the envelope weights a unit correction of c0 by 1 - prod_k (1 - exp(-r_k^2 / 2 sigma^2))
+    sigma = 1.5
+    one = torch.zeros_like(t)
+    one[..., 0] = 1.0
+    ss.ss_init_learned(s.ctx, cen, None, one.data_ptr(), sigma=sigma)
+    g1 = s.get_field().cpu().numpy()
+    far = np.ones_like(X)
+    for cx, cy in cen:
+        far *= 1.0 - np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * sigma ** 2))
+    env = 1.0 - far
+    psi1 = (g1[0, 2:-2, 2:-2] + 1j * g1[1, 2:-2, 2:-2]) * np.exp(-1j * theta)
+    psia = (ga[0, 2:-2, 2:-2] + 1j * ga[1, 2:-2, 2:-2]) * np.exp(-1j * theta)
+    assert np.abs(psi1 - psia - env).max() < 1e-12
+    assert np.array_equal(g1[2:, :, :], ga[2:, :, :])
     s.close()
 
 
