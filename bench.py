@@ -4,7 +4,9 @@ Workload (default): the large Ginzburg-Landau lattice, 4096 x 4096 interior
 sites, kappa = 1.5 (lambda = 2 kappa^2 = 4.5), h = 0.2, 256 unit vortices at
 seeded Poisson-disc positions (minimum separation 3) inside the centred square
 of side 0.6 L, U(+-1e-3) noise, FP32 fields with FP64 reductions. A "step" is
-one full RK4 flow step (4 fused stage passes, arrest test, FP64 energy).
+one full RK4 flow step: the first stage pass (gradient, FP64 energy, arrest
+test, stop rules) and either one fused pass for stages 2-4 and the update or
+three separate stage passes, whichever plan the autotuner picks.
 
 Prints one JSON line: site-updates/s over K timed steps (inputs resident in
 HBM), the roofline of the dominant pass (algorithmic bytes per launch over its
@@ -30,8 +32,11 @@ HBM_PEAK_GBS = 8000.0
 # written per interior site (halo re-reads served by cache are not counted):
 #   P1 reads phi, writes a1; P2 reads phi, v, writes a2; P3 reads phi, v, a1, a2,
 #   writes q; P4 reads phi, v, a2, q, a1, writes phi', v'.
-PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2)}
-STEP_SETS = 17
+#   P234 (fused stages 2-4) reads phi, v, a1, writes phi', v'.
+PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "P234": (3, 2)}
+STEP_SETS = 17          # separate stage passes
+STEP_SETS_FUSED = 7     # P1 + fused stages 2-4
+PLAN_NAMES = ["stages", "fused", "fused_1024"]
 
 WORKLOADS = {
     "gl4096": dict(theory="abelian_higgs", N=4096, h=0.2, kappa=1.5, nv=256, seed=4, dtype="f32"),
@@ -256,19 +261,24 @@ def main():
     value = sites * args.steps / elapsed
 
     # per-pass device time with HIP events on the library's stream
+    plan = s.plan
     ms = s.time_passes(args.timing_steps)
+    names = ["P1", "P2", "P3", "P4"] if plan == 0 else ["P1", "P234"]
     passes = {}
-    for k, name in enumerate(["P1", "P2", "P3", "P4"]):
+    for k, name in enumerate(names):
         r, w_ = PASS_SETS[name]
         nbytes = sites * C * b * (r + w_)
         passes[name] = {"ms": ms[k], "GB_per_launch": nbytes / 1e9, "GBps": nbytes / (ms[k] * 1e-3) / 1e9}
     dom = max(passes, key=lambda k: passes[k]["ms"])
     ach = passes[dom]["GBps"]
-    step_gbps = STEP_SETS * C * b * sites / (ms_step * 1e-3) / 1e9
+    step_sets = STEP_SETS if plan == 0 else STEP_SETS_FUSED
+    step_gbps = step_sets * C * b * sites / (ms_step * 1e-3) / 1e9
     tr = traffic_record(dom, args.workload)
+    kname = f"stage_pass {dom}" if dom != "P234" else "stage_pass_fused (stages 2-4)"
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": f"stage_pass {dom}",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": kname,
             "step_GBps": round(step_gbps, 1), "step_frac": round(step_gbps / HBM_PEAK_GBS, 4),
+            "step_sets": step_sets,
             "passes": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in passes.items()}}
 
     cpu = None
@@ -292,8 +302,9 @@ def main():
                    "kappa": wl.get("kappa"), "vortices": wl.get("nv"), "grad_form": "euler-lagrange",
                    "integrator": "RK4 arrested Newton flow, dt = 0.5 h", "parallelism": "single GPU"},
         "roofline": roof,
-        "tile": {"chosen": list(ss_tile(tune[0])) if tune else None,
-                 "step_ms_by_tile": [round(x, 4) for x in tune[1]] if tune else None},
+        "tile": {"chosen": list(ss_tile(tune[0])) if tune else None, "plan": PLAN_NAMES[plan],
+                 "step_ms_by_plan_and_tile": {PLAN_NAMES[p]: [round(x, 4) for x in row]
+                                              for p, row in enumerate(tune[2])} if tune else None},
         "cpu_baseline": cpu,
         "state": {"energy": info["energy"], "n_arrests": info["n_arrests"], "step": info["step"]},
     }

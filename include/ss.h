@@ -200,7 +200,8 @@ int ss_init_ansatz(ss_ctx* ctx, int kind, int n, const double* xy, const double*
 
 /* Mean device time per launch of each of the passes, measured with HIP events
  * on the context's stream over n_steps flow steps (the steps are real flow
- * steps). ms[0..3] = stage passes P1..P4, ms[4] = whole step. Synchronises. */
+ * steps). ms[0..3] = stage passes P1..P4, ms[4] = whole step; under a fused
+ * plan ms[1] is the pass of stages 2-4 and ms[2] = ms[3] = 0. Synchronises. */
 int ss_time_passes(ss_ctx* ctx, int n_steps, double* ms);
 
 /* Copy the current field and (if velocity != NULL) velocity to device arrays. */
@@ -256,14 +257,36 @@ int ss_learned_input(ss_ctx* ctx, int n, const double* xy, double kappa, float* 
 int ss_learned_targets(ss_ctx* ctx, int n, const double* xy, const double* w, float* out);
 int ss_init_learned(ss_ctx* ctx, int n, const double* xy, const double* w, const float* corr, double sigma);
 
-/* Tile shapes of the fused stage kernels. The library carries ss_tile_count()
+/* Plans: how the four stages of an RK4 step (Sec. 3.2, eq. (3)) are launched.
+ *   SS_PLAN_STAGES      one pass per stage, P1..P4 (17 field sets of HBM
+ *                       traffic per site and step);
+ *   SS_PLAN_FUSED       P1, then one pass that evaluates stages 2, 3 and 4 and
+ *                       the update on a tile, recomputing stage 2 on a ring
+ *                       of 2 around it (7 field sets per site and step);
+ *                       workgroups of 512 threads;
+ *   SS_PLAN_FUSED_1024  the same pass with workgroups of 1024 threads.
+ * All plans give the same step up to rounding order. The fused plans exist for
+ * the Euler-Lagrange gradient only (SS_EINVAL otherwise). New FP32 contexts
+ * with the Euler-Lagrange gradient start with SS_PLAN_FUSED, others with
+ * SS_PLAN_STAGES. ss_set_plan synchronises the stream. */
+#define SS_PLAN_STAGES 0
+#define SS_PLAN_FUSED 1
+#define SS_PLAN_FUSED_1024 2
+#define SS_NUM_PLANS 3
+int ss_set_plan(ss_ctx* ctx, int plan);
+int ss_get_plan(ss_ctx* ctx);
+
+/* Tile shapes of the stage kernels. The library carries ss_tile_count()
  * compiled shapes (a workgroup covers TX x TY sites, each thread RY rows of
- * one column). ss_set_tile selects one for a context; ss_autotune times every
- * shape over n_steps flow steps of a uniform vacuum on the context's lattice,
- * keeps the fastest, writes each shape's mean step time in ms_out (may be NULL,
- * else ss_tile_count() doubles) and returns the chosen index (>= 0). It
- * overwrites the field: call ss_set_field or ss_init_ansatz afterwards. The
- * environment variable SS_TILE selects the initial shape of new contexts. */
+ * one column); under a fused plan the shape applies to P1. ss_set_tile selects
+ * one for a context. ss_autotune times every plan with every shape over
+ * n_steps flow steps of a uniform vacuum on the context's lattice, keeps the
+ * fastest pair, writes the mean step times in ms_out (may be NULL, else
+ * SS_NUM_PLANS * ss_tile_count() doubles, index plan * ss_tile_count() + tile;
+ * -1 where a pair does not apply) and returns the chosen tile index (>= 0; the
+ * plan is read with ss_get_plan). It overwrites the field: call ss_set_field
+ * or ss_init_ansatz afterwards. The environment variable SS_TILE selects the
+ * initial shape of new contexts. */
 int ss_tile_count(void);
 int ss_tile_shape(int tile, int* tx, int* ty, int* ry);
 int ss_set_tile(ss_ctx* ctx, int tile);

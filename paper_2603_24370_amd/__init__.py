@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libss.so")
 SS_OK, SS_NOT_CONVERGED = 0, 1
 SS_F32, SS_F64 = 0, 1
 SS_GRAD_EL, SS_GRAD_EXACT = 0, 1
+SS_PLAN_STAGES, SS_PLAN_FUSED, SS_PLAN_FUSED_1024 = 0, 1, 2
+SS_NUM_PLANS = 3
 SS_THEORY_AH, SS_THEORY_CM = 0, 1
 SS_ANSATZ_VORTICES, SS_ANSATZ_SKYRMION = 0, 1
 STOP_REASONS = {0: "none", 1: "grad", 2: "stall", 3: "max_steps", 4: "nonfinite", 5: "target"}
@@ -69,7 +71,8 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_init_ansatz", "ss_time_passes",
            "ss_get_field", "ss_energy_grad", "ss_flow_step", "ss_minimise", "ss_observables", "ss_get_info",
            "ss_status_string", "ss_last_error", "ss_gl_lambda_from_kappa", "ss_tile_count", "ss_tile_shape",
-           "ss_set_tile", "ss_get_tile", "ss_autotune", "ss_batch_workspace_bytes", "ss_batch_create",
+           "ss_set_tile", "ss_get_tile", "ss_autotune", "ss_set_plan", "ss_get_plan", "ss_batch_workspace_bytes",
+           "ss_batch_create",
            "ss_batch_destroy", "ss_batch_member", "ss_batch_size", "ss_batch_flow_step", "ss_batch_minimise",
            "ss_batch_set_tile", "ss_batch_autotune", "ss_set_energy_target", "ss_learned_input",
            "ss_learned_targets", "ss_init_learned"]
@@ -117,6 +120,8 @@ def lib():
     L.ss_set_tile.argtypes = [vp, i]
     L.ss_get_tile.argtypes = [vp]
     L.ss_autotune.argtypes = [vp, i, dp]
+    L.ss_set_plan.argtypes = [vp, i]
+    L.ss_get_plan.argtypes = [vp]
     ins = ctypes.POINTER(ss_instance)
     L.ss_batch_workspace_bytes.argtypes = [cp, i, ins, i, ctypes.POINTER(ctypes.c_size_t)]
     L.ss_batch_create.argtypes = [cp, i, ins, i, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
@@ -261,10 +266,21 @@ def ss_get_tile(ctx) -> int:
     return _check_nonneg(lib().ss_get_tile(ctx))
 
 
+def ss_set_plan(ctx, plan: int):
+    _check(lib().ss_set_plan(ctx, plan))
+
+
+def ss_get_plan(ctx) -> int:
+    return _check_nonneg(lib().ss_get_plan(ctx))
+
+
 def ss_autotune(ctx, n_steps=10):
-    ms = (ctypes.c_double * ss_tile_count())()
+    """Returns (tile, plan, ms) with ms[plan][tile] the mean step time (-1: not timed)."""
+    nt = ss_tile_count()
+    ms = (ctypes.c_double * (SS_NUM_PLANS * nt))()
     best = _check_nonneg(lib().ss_autotune(ctx, int(n_steps), ms))
-    return best, list(ms)
+    grid = [list(ms[p * nt:(p + 1) * nt]) for p in range(SS_NUM_PLANS)]
+    return best, ss_get_plan(ctx), grid
 
 
 def ss_gl_lambda_from_kappa(kappa: float) -> float:
@@ -395,6 +411,13 @@ class Solver:
 
     def set_tile(self, tile):
         ss_set_tile(self.ctx, tile)
+
+    def set_plan(self, plan):
+        ss_set_plan(self.ctx, plan)
+
+    @property
+    def plan(self):
+        return ss_get_plan(self.ctx)
 
     def set_energy_target(self, e_target):
         ss_set_energy_target(self.ctx, e_target)

@@ -49,6 +49,7 @@ struct TileCfg {
 constexpr TileCfg kTiles[] = {{64, 16, 2}, {64, 8, 2}, {64, 16, 4}, {64, 32, 4}};
 constexpr int kNumTiles = 4;
 constexpr int kDefaultTile = 0;
+constexpr int kDefaultPlanF32 = SS_PLAN_FUSED;
 static_assert(kTiles[0].TX == kExTX && kTiles[0].TY == kExTY, "the exact-gradient passes use the layout of tile 0");
 constexpr int kDefaultGraphSteps = 16;
 constexpr long kMaxGroups = 2048;  // persistent launch: at most 8 workgroups per CU
@@ -134,6 +135,7 @@ struct ss_ctx {
   hipGraphExec_t graph;
   int graph_steps;
   int tile;
+  int plan;  // SS_PLAN_*: how stages 2-4 of a step are launched
 };
 
 namespace {
@@ -210,11 +212,36 @@ void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   else launch_pass_t<T, 1, PASS>(c->tile, a, c->L.nlaunch, s);
 }
 
+// Fused stages 2-4: the 64 x 16 tiling of tile 0, one of two workgroup shapes.
+template <class T, int TH>
+void launch_fused_t(int plan, const PassArgs<T>& a, int nlaunch, hipStream_t s) {
+  if (plan == SS_PLAN_FUSED)
+    hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, 16, 2>), dim3(nlaunch), dim3(64, 8), 0, s, a);
+  else
+    hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, 16, 1>), dim3(nlaunch), dim3(64, 16), 0, s, a);
+}
+
+template <class T>
+void launch_fused(const ss_ctx* c, hipStream_t s) {
+  PassArgs<T> a = pass_args<T>(c);
+  Layout L = c->L;
+  set_tiles(L, c->Nx, c->Ny, 0);
+  a.ntx = L.ntx;
+  a.nty = L.nty;
+  a.seg = L.seg;
+  if (c->theory == SS_THEORY_AH) launch_fused_t<T, 0>(c->plan, a, L.nlaunch, s);
+  else launch_fused_t<T, 1>(c->plan, a, L.nlaunch, s);
+}
+
 template <class T>
 void enqueue_steps(const ss_ctx* c, int n, hipStream_t s) {
   PassArgs<T> a = pass_args<T>(c);
   for (int k = 0; k < n; ++k) {
     launch_pass<T, kP1>(c, a, s);
+    if (c->plan != SS_PLAN_STAGES) {
+      launch_fused<T>(c, s);
+      continue;
+    }
     launch_pass<T, kP2>(c, a, s);
     launch_pass<T, kP3>(c, a, s);
     launch_pass<T, kP4>(c, a, s);
@@ -359,6 +386,7 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   }
   if (grad_mode == SS_GRAD_EXACT) c->tile = 0;
   set_tiles(c->L, Nx, Ny, c->tile);
+  c->plan = (grad_mode == SS_GRAD_EL && dtype == SS_F32) ? kDefaultPlanF32 : SS_PLAN_STAGES;
   hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete c;
@@ -448,7 +476,21 @@ int ss_time_passes(ss_ctx* c, int n_steps, double* ms) {
   hipLaunchKernelGGL(arm_status, dim3(1), dim3(64), 0, c->stream, c->st, 0, 0.0, 0.0, 0, 0LL);
   for (int s = 0; s < n_steps; ++s) {
     SS_HIP(hipEventRecord(ev[0], c->stream));
-    if (c->dtype == SS_F32) {
+    if (c->plan != SS_PLAN_STAGES) {
+      // stages 2-4 in one pass: its time in ms[1], zero in ms[2] and ms[3]
+      if (c->dtype == SS_F32) {
+        PassArgs<float> a = pass_args<float>(c);
+        launch_pass<float, kP1>(c, a, c->stream); SS_HIP(hipEventRecord(ev[1], c->stream));
+        launch_fused<float>(c, c->stream);
+      } else {
+        PassArgs<double> a = pass_args<double>(c);
+        launch_pass<double, kP1>(c, a, c->stream); SS_HIP(hipEventRecord(ev[1], c->stream));
+        launch_fused<double>(c, c->stream);
+      }
+      SS_HIP(hipEventRecord(ev[2], c->stream));
+      SS_HIP(hipEventRecord(ev[3], c->stream));
+      SS_HIP(hipEventRecord(ev[4], c->stream));
+    } else if (c->dtype == SS_F32) {
       PassArgs<float> a = pass_args<float>(c);
       launch_pass<float, kP1>(c, a, c->stream); SS_HIP(hipEventRecord(ev[1], c->stream));
       launch_pass<float, kP2>(c, a, c->stream); SS_HIP(hipEventRecord(ev[2], c->stream));
@@ -662,6 +704,22 @@ int ss_set_tile(ss_ctx* c, int tile) {
   return SS_OK;
 }
 
+int ss_set_plan(ss_ctx* c, int plan) {
+  if (!c) return fail(SS_EINVAL, "ctx is NULL");
+  if (plan < 0 || plan >= SS_NUM_PLANS) return fail(SS_EINVAL, "unknown plan");
+  if (plan != SS_PLAN_STAGES && c->grad_mode != SS_GRAD_EL)
+    return fail(SS_EINVAL, "the fused plans evaluate the Euler-Lagrange gradient only");
+  SS_HIP(hipStreamSynchronize(c->stream));
+  c->plan = plan;
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return SS_OK;
+}
+
+int ss_get_plan(ss_ctx* c) { return c ? c->plan : SS_EINVAL; }
+
 int ss_tile_count(void) { return kNumTiles; }
 
 int ss_tile_shape(int tile, int* tx, int* ty, int* ry) {
@@ -674,9 +732,10 @@ int ss_tile_shape(int tile, int* tx, int* ty, int* ry) {
 
 int ss_autotune(ss_ctx* c, int n_steps, double* ms_out) {
   if (!c || n_steps <= 0) return fail(SS_EINVAL, "bad arguments");
+  if (ms_out)
+    for (int k = 0; k < SS_NUM_PLANS * kNumTiles; ++k) ms_out[k] = -1.0;
   if (c->grad_mode == SS_GRAD_EXACT) {
-    if (ms_out)
-      for (int t = 0; t < kNumTiles; ++t) ms_out[t] = t == 0 ? 0.0 : -1.0;
+    if (ms_out) ms_out[0] = 0.0;
     return 0;
   }
   // a uniform vacuum (psi = 1, A = 0; n = e_3) keeps every pass finite
@@ -685,25 +744,32 @@ int ss_autotune(ss_ctx* c, int n_steps, double* ms_out) {
   int rc = c->theory == SS_THEORY_AH ? ss_init_ansatz(c, SS_ANSATZ_VORTICES, 0, nullptr, nullptr, nullptr, 0, 0.0)
                                      : ss_init_ansatz(c, SS_ANSATZ_SKYRMION, 1, zero, nullptr, shape, 0, 0.0);
   if (rc) return rc;
-  int best = c->tile;
+  int best_t = c->tile, best_p = c->plan;
   double best_ms = 1e300;
-  for (int t = 0; t < kNumTiles; ++t) {
-    rc = ss_set_tile(c, t);
+  for (int p = 0; p < SS_NUM_PLANS; ++p) {
+    rc = ss_set_plan(c, p);
     if (rc) return rc;
-    double ms[5];
-    rc = ss_time_passes(c, 2, ms);  // warm-up
-    if (rc) return rc;
-    rc = ss_time_passes(c, n_steps, ms);
-    if (rc) return rc;
-    if (ms_out) ms_out[t] = ms[4];
-    if (ms[4] < best_ms) {
-      best_ms = ms[4];
-      best = t;
+    for (int t = 0; t < kNumTiles; ++t) {
+      rc = ss_set_tile(c, t);
+      if (rc) return rc;
+      double ms[5];
+      rc = ss_time_passes(c, 2, ms);  // warm-up
+      if (rc) return rc;
+      rc = ss_time_passes(c, n_steps, ms);
+      if (rc) return rc;
+      if (ms_out) ms_out[p * kNumTiles + t] = ms[4];
+      if (ms[4] < best_ms) {
+        best_ms = ms[4];
+        best_t = t;
+        best_p = p;
+      }
     }
   }
-  rc = ss_set_tile(c, best);
+  rc = ss_set_plan(c, best_p);
   if (rc) return rc;
-  return reset_state(c) ? SS_EHIP : best;
+  rc = ss_set_tile(c, best_t);
+  if (rc) return rc;
+  return reset_state(c) ? SS_EHIP : best_t;
 }
 
 int ss_get_tile(ss_ctx* c) { return c ? c->tile : SS_EINVAL; }

@@ -768,10 +768,7 @@ __device__ __forceinline__ void finalise_status(DevStatus* st, double E, double 
   else if (PASS == kP1) st->step = s0 + 1;
 }
 
-// Launch: gridDim.x is a multiple of 8. Workgroup b runs on XCD b % 8; the XCD
-// owns the contiguous tile range [x * per, (x + 1) * per) and its m = gridDim.x / 8
-// workgroups sweep that range together (tiles x*per + q, + m, + 2m, ...), so the
-// tiles in flight on one XCD are neighbours and share halo rows in its L2.
+// Launch: gridDim.x is a multiple of 8; tiles are assigned by for_each_tile.
 // Each workgroup accumulates its tiles' reductions into one partial; the last
 // workgroup to finish sums the partials in a fixed order and updates the status.
 template <class T, int TH, int PASS, int TX, int TY, int RY>
@@ -826,6 +823,372 @@ __global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
   __syncthreads();
   block_reduce3<NT>(se, sg, sn, red);
   if (tid == 0) finalise_status<PASS>(st, a.cf.h * a.cf.h * se, sg, sn);
+}
+
+// ------------------------------------------------- fused stages 2-4 (EL gradient)
+// One pass computes stages 2, 3 and 4 of the step and the update, reading phi, v
+// and a1 (written by P1) and writing phi', v':
+//   S2 = phi + dt/2 v            a2 = -G(S2)     on the tile plus a ring of 2
+//   S3 = S2 + dt^2/4 a1          a3 = -G(S3)     on the tile
+//   S4 = phi + dt v + dt^2/2 a2  a4 = -G(S4)     on the tile
+//   q = a1 + 2 a2 + 2 a3, phi' = phi + dt v + dt^2 (q + a1) / 12, v' = v + dt (q + a4) / 6
+// (v -> 0 after an arrest; chiral magnet: stage points normalised, forces
+// projected, phi' normalised and v' projected, as in the separate passes).
+// a2 is needed at the halo of S4's stencil, so it is recomputed on a ring of 2
+// around the tile from S2 staged with halo 4. Per site the pass reads 3 field
+// sets and writes 2, against 10 and 4 for P2, P3 and P4 run separately.
+
+// Jets of one site from an LDS plane with row length LX, arithmetic as column_jets.
+template <class T, int LX, bool MIXED>
+__device__ __forceinline__ void site_jet(const T* __restrict__ s, int ly, int lx, T c1, T c2, Jet<T>& J) {
+  const T* r0 = s + ly * LX + lx;
+  const T xm2 = r0[-2], xm1 = r0[-1], xp1 = r0[1], xp2 = r0[2], f = r0[0];
+  const T ym2 = r0[-2 * LX], ym1 = r0[-LX], yp1 = r0[LX], yp2 = r0[2 * LX];
+  J.f = f;
+  J.x = c1 * ((xm2 - xp2) + T(8) * (xp1 - xm1));
+  J.xx = c2 * (T(16) * (xp1 + xm1) - (xp2 + xm2) - T(30) * f);
+  J.y = c1 * ((ym2 - yp2) + T(8) * (yp1 - ym1));
+  J.yy = c2 * (T(16) * (yp1 + ym1) - (yp2 + ym2) - T(30) * f);
+  if (MIXED) {
+    T ddx[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const T* r = s + (ly - 2 + k) * LX + lx;
+      ddx[k] = (r[-2] - r[2]) + T(8) * (r[1] - r[-1]);
+    }
+    J.xy = c1 * c1 * ((ddx[0] - ddx[4]) + T(8) * (ddx[3] - ddx[1]));
+  } else {
+    J.xy = T(0);
+  }
+}
+
+// G at one site from its jets (the chiral magnet's G is projected at the site).
+template <class T, int TH>
+__device__ __forceinline__ void site_gradient(const Jet<T> (&Js)[4], const InstView<T>& V, T (&G)[4]) {
+  if (TH == 0) {
+    ah_el_gradient<T>(Js, (T)V.p[0], G);
+  } else {
+    cm_el_gradient<T>(Js, (T)V.p[0], (T)V.p[1], (T)V.p[2], (T)V.p[3], G);
+    const T gn = G[0] * Js[0].f + G[1] * Js[1].f + G[2] * Js[2].f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) G[c] -= gn * Js[c].f;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void unit3(T (&x)[4]) {
+  const T inv = T(1) / sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+  x[0] *= inv;
+  x[1] *= inv;
+  x[2] *= inv;
+}
+
+template <class T, int TH, int TX, int TY, int RY>
+__device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, bool arrest, int x0, int y0,
+                                                T* __restrict__ la, T* __restrict__ lb) {
+  constexpr int C = NComp<TH>::value;
+  constexpr int AX = TX + 8, AY = TY + 8;   // plane A: S2 with halo 4, then S3 / S4 with halo 2
+  constexpr int BX = TX + 4, BY = TY + 4;   // plane B: a2 with halo 2
+  constexpr int NT = TX * (TY / RY);
+  constexpr int NRA = AX * AY - TX * TY;    // ring of A around the tile
+  constexpr int NRB = BX * BY - TX * TY;    // ring of B around the tile
+  constexpr int KRB = (NRB + NT - 1) / NT;
+  constexpr bool MIXED = (TH == 0);
+  T* sa[4];
+  T* sb[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    sa[c] = la + (c < C ? c : 0) * (AX * AY);
+    sb[c] = lb + (c < C ? c : 0) * (BX * BY);
+  }
+  const int Nx = V.Nx, Ny = V.Ny;
+  const long pitch = V.pitch, plane = V.plane;
+  const T* __restrict__ ph = cur ? V.phi[1] : V.phi[0];
+  const T* __restrict__ vv = cur ? V.vel[1] : V.vel[0];
+  const T* __restrict__ a1p = V.a1;
+  const T dt = (T)V.dt;
+  const T cv2 = arrest ? T(0) : T(0.5) * dt;
+  const T cv4 = arrest ? T(0) : dt;
+  const T ca3 = T(0.25) * dt * dt, ca4 = T(0.5) * dt * dt;
+  const double h = V.h;
+  const T c1 = T(1.0 / (12.0 * h)), c2 = T(1.0 / (12.0 * h * h));
+  const int tid = threadIdx.y * TX + threadIdx.x;
+  const int gi = x0 + threadIdx.x;
+  auto inside = [&](int x, int y) { return x >= 0 && x < Nx && y >= 0 && y < Ny; };
+  // site (x, y) of the padded lattice (x, y in [-2, N + 1]) as an element offset
+  auto offs = [&](int x, int y) { return (long)(y + 2) * pitch + (x + 2); };
+  auto in_pad = [&](int x, int y) { return x >= -2 && x <= Nx + 1 && y >= -2 && y <= Ny + 1; };
+
+  // ---- phase 1: raw phi, v of the own sites; S2 on the tile plus halo 4 -> A
+  T rp[RY][4], rv[RY][4];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int gj = y0 + threadIdx.y * RY + r;
+    T S[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rp[r][c] = rv[r][c] = S[c] = T(0);
+    if (in_pad(gi, gj)) {
+      const long o = offs(gi, gj);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        rp[r][c] = ph[c * plane + o];
+        rv[r][c] = vv[c * plane + o];
+        S[c] = rp[r][c] + cv2 * rv[r][c];
+      }
+      if (TH == 1 && inside(gi, gj)) unit3(S);
+    }
+    const int la_ = (4 + threadIdx.y * RY + r) * AX + 4 + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sa[c][la_] = S[c];
+  }
+  for (int idx = tid; idx < NRA; idx += NT) {
+    int ly, lx;
+    if (idx < 8 * AX) {
+      const int rr = idx / AX;
+      ly = rr < 4 ? rr : AY - 8 + rr;
+      lx = idx - rr * AX;
+    } else {
+      const int j = idx - 8 * AX;
+      ly = 4 + (j >> 3);
+      const int cc = j & 7;
+      lx = cc < 4 ? cc : AX - 8 + cc;
+    }
+    const int x = x0 - 4 + lx, y = y0 - 4 + ly;
+    T S[4] = {T(0), T(0), T(0), T(0)};
+    if (in_pad(x, y)) {
+      const long o = offs(x, y);
+#pragma unroll
+      for (int c = 0; c < C; ++c) S[c] = ph[c * plane + o] + cv2 * vv[c * plane + o];
+      if (TH == 1 && inside(x, y)) unit3(S);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) sa[c][ly * AX + lx] = S[c];
+  }
+  __syncthreads();
+
+  // ---- phase 2: a2 = -G(S2) on the tile plus a ring of 2 -> B; 0 off the interior
+  {
+    Jet<T> J[C][RY];
+    double dx_[C][RY], dy_[C][RY];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      column_jets<T, AX, RY, MIXED, false>(sa[c], 4 + threadIdx.x, 4 + threadIdx.y * RY, c1, c2, 0.0, J[c], dx_[c],
+                                           dy_[c]);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      Jet<T> Js[4];
+#pragma unroll
+      for (int c = 0; c < C; ++c) Js[c] = J[c][r];
+      T G[4] = {T(0), T(0), T(0), T(0)};
+      site_gradient<T, TH>(Js, V, G);
+      const bool in = inside(gi, y0 + threadIdx.y * RY + r);
+      const int lb_ = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
+#pragma unroll
+      for (int c = 0; c < C; ++c) sb[c][lb_] = in ? -G[c] : T(0);
+    }
+  }
+  // ring of B (its raw phi, v are read again in phases 3 and 5, from L2)
+#pragma unroll
+  for (int k = 0; k < KRB; ++k) {
+    const int idx = tid + k * NT;
+    if (idx < NRB) {
+      int by, bx;
+      if (idx < 4 * BX) {
+        const int rr = idx / BX;
+        by = rr < 2 ? rr : BY - 4 + rr;
+        bx = idx - rr * BX;
+      } else {
+        const int j = idx - 4 * BX;
+        by = 2 + (j >> 2);
+        const int cc = j & 3;
+        bx = cc < 2 ? cc : BX - 4 + cc;
+      }
+      const int x = x0 - 2 + bx, y = y0 - 2 + by;
+      T a[4] = {T(0), T(0), T(0), T(0)};
+      if (inside(x, y)) {
+        Jet<T> Js[4];
+#pragma unroll
+        for (int c = 0; c < C; ++c) site_jet<T, AX, MIXED>(sa[c], by + 2, bx + 2, c1, c2, Js[c]);
+        T G[4] = {T(0), T(0), T(0), T(0)};
+        site_gradient<T, TH>(Js, V, G);
+#pragma unroll
+        for (int c = 0; c < C; ++c) a[c] = -G[c];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) sb[c][by * BX + bx] = a[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 3: S3 = phi + dt/2 v + dt^2/4 a1 on the tile plus halo 2 -> A (offset 2)
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int gj = y0 + threadIdx.y * RY + r;
+    T S[4] = {T(0), T(0), T(0), T(0)};
+    if (in_pad(gi, gj)) {
+      const long o = offs(gi, gj);
+#pragma unroll
+      for (int c = 0; c < C; ++c) S[c] = rp[r][c] + cv2 * rv[r][c] + ca3 * a1p[c * plane + o];
+    }
+    if (TH == 1 && inside(gi, gj)) unit3(S);
+    const int la_ = (4 + threadIdx.y * RY + r) * AX + 4 + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sa[c][la_] = S[c];
+  }
+#pragma unroll
+  for (int k = 0; k < KRB; ++k) {
+    const int idx = tid + k * NT;
+    if (idx < NRB) {
+      int by, bx;
+      if (idx < 4 * BX) {
+        const int rr = idx / BX;
+        by = rr < 2 ? rr : BY - 4 + rr;
+        bx = idx - rr * BX;
+      } else {
+        const int j = idx - 4 * BX;
+        by = 2 + (j >> 2);
+        const int cc = j & 3;
+        bx = cc < 2 ? cc : BX - 4 + cc;
+      }
+      const int x = x0 - 2 + bx, y = y0 - 2 + by;
+      T S[4] = {T(0), T(0), T(0), T(0)};
+      if (in_pad(x, y)) {
+        const long o = offs(x, y);
+#pragma unroll
+        for (int c = 0; c < C; ++c) S[c] = ph[c * plane + o] + cv2 * vv[c * plane + o] + ca3 * a1p[c * plane + o];
+        if (TH == 1 && inside(x, y)) unit3(S);
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) sa[c][(by + 2) * AX + bx + 2] = S[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 4: q = a1 + 2 a2 - 2 G(S3) at the own sites
+  T qo[RY][4];
+  {
+    Jet<T> J[C][RY];
+    double dx_[C][RY], dy_[C][RY];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      column_jets<T, AX, RY, MIXED, false>(sa[c], 4 + threadIdx.x, 4 + threadIdx.y * RY, c1, c2, 0.0, J[c], dx_[c],
+                                           dy_[c]);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      Jet<T> Js[4];
+#pragma unroll
+      for (int c = 0; c < C; ++c) Js[c] = J[c][r];
+      T G[4] = {T(0), T(0), T(0), T(0)};
+      site_gradient<T, TH>(Js, V, G);
+      const int gj = y0 + threadIdx.y * RY + r;
+      const int lb_ = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
+      const long o = in_pad(gi, gj) ? offs(gi, gj) : 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) qo[r][c] = T(0);
+#pragma unroll
+      for (int c = 0; c < C; ++c) qo[r][c] = a1p[c * plane + o] + T(2) * sb[c][lb_] - T(2) * G[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 5: S4 = phi + dt v + dt^2/2 a2 on the tile plus halo 2 -> A
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int gj = y0 + threadIdx.y * RY + r;
+    T S[4] = {T(0), T(0), T(0), T(0)};
+    const int lb_ = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) S[c] = rp[r][c] + cv4 * rv[r][c] + ca4 * sb[c][lb_];
+    if (TH == 1 && inside(gi, gj)) unit3(S);
+    const int la_ = (4 + threadIdx.y * RY + r) * AX + 4 + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sa[c][la_] = S[c];
+  }
+#pragma unroll
+  for (int k = 0; k < KRB; ++k) {
+    const int idx = tid + k * NT;
+    if (idx < NRB) {
+      int by, bx;
+      if (idx < 4 * BX) {
+        const int rr = idx / BX;
+        by = rr < 2 ? rr : BY - 4 + rr;
+        bx = idx - rr * BX;
+      } else {
+        const int j = idx - 4 * BX;
+        by = 2 + (j >> 2);
+        const int cc = j & 3;
+        bx = cc < 2 ? cc : BX - 4 + cc;
+      }
+      const int x = x0 - 2 + bx, y = y0 - 2 + by;
+      T S[4] = {T(0), T(0), T(0), T(0)};
+      if (in_pad(x, y)) {
+        const long o = offs(x, y);
+#pragma unroll
+        for (int c = 0; c < C; ++c) S[c] = ph[c * plane + o] + cv4 * vv[c * plane + o] + ca4 * sb[c][by * BX + bx];
+        if (TH == 1 && inside(x, y)) unit3(S);
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) sa[c][(by + 2) * AX + bx + 2] = S[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 6: a4 = -G(S4); phi', v' at the own sites
+  T* __restrict__ phn = cur ? V.phi[0] : V.phi[1];
+  T* __restrict__ vn = cur ? V.vel[0] : V.vel[1];
+  {
+    Jet<T> J[C][RY];
+    double dx_[C][RY], dy_[C][RY];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      column_jets<T, AX, RY, MIXED, false>(sa[c], 4 + threadIdx.x, 4 + threadIdx.y * RY, c1, c2, 0.0, J[c], dx_[c],
+                                           dy_[c]);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int gj = y0 + threadIdx.y * RY + r;
+      if (gi >= Nx || gj >= Ny) continue;
+      Jet<T> Js[4];
+#pragma unroll
+      for (int c = 0; c < C; ++c) Js[c] = J[c][r];
+      T G[4] = {T(0), T(0), T(0), T(0)};
+      site_gradient<T, TH>(Js, V, G);
+      const long o = offs(gi, gj);
+      T pn[4], vnew[4];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const T v0 = arrest ? T(0) : rv[r][c];
+        pn[c] = rp[r][c] + dt * v0 + (dt * dt / T(12)) * (qo[r][c] + a1p[c * plane + o]);
+        vnew[c] = v0 + (dt / T(6)) * (qo[r][c] - G[c]);
+      }
+      if (TH == 1) {
+        unit3(pn);
+        const T vd = vnew[0] * pn[0] + vnew[1] * pn[1] + vnew[2] * pn[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vnew[c] -= vd * pn[c];
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        __builtin_nontemporal_store(pn[c], &phn[c * plane + o]);
+        __builtin_nontemporal_store(vnew[c], &vn[c * plane + o]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <class T, int TH, int TX, int TY, int RY>
+__global__ void __launch_bounds__(TX*(TY / RY)) stage_pass_fused(PassArgs<T> a) {
+  constexpr int C = NComp<TH>::value;
+  __shared__ __align__(16) T la[C * (TX + 8) * (TY + 8)];
+  __shared__ __align__(16) T lb[C * (TX + 4) * (TY + 4)];
+  DevStatus* __restrict__ st = a.st;
+  if (st->done) return;
+  const int cur = int((st->step - 1) & 1);
+  const bool arrest = st->arrest != 0;
+  const InstView<T> V = view_of<T>(a.B, a.cf);
+  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty) {
+    tile_body_fused<T, TH, TX, TY, RY>(V, cur, arrest, tx * TX, ty * TY, la, lb);
+  });
 }
 
 // The single-lattice launch of the exact-gradient passes (tile 64 x 16, 256 threads).

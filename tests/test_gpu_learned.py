@@ -96,6 +96,40 @@ def test_backward_matches_oracle(ss):
     net.close()
 
 
+def test_production_shape_matches_oracle(ss):
+    """The learned start's own network shape (4 levels, widths 32/64/128/256,
+    concatenations of up to 384 channels) on one 128^2 image: forward and every
+    parameter gradient against the FP64 oracle. Two more BF16 layers than the
+    small case compound the rounding, so outputs are held to 5e-2 and gradients
+    to 8e-2 relative L2."""
+    lv, base, H2 = 4, 32, 128
+    rng = np.random.default_rng(7)
+    P = U.init_params(seed=7, levels=lv, base=base, cin=CIN, cout=COUT)
+    for k in P:
+        if k.endswith(".b"):
+            P[k] = 0.05 * rng.normal(size=P[k].shape)
+    x = rng.normal(size=(1, H2, H2, CIN))
+    t = rng.normal(size=(1, H2, H2, COUT)) * 0.5
+    net = ss.Net(levels=lv, base=base, cin=CIN, cout=COUT, N=1, H=H2, W=H2)
+    net.set_weights(_flat(P, lv, base).astype(np.float32))
+    out = net.forward(x).cpu().numpy().astype(np.float64)
+    Pr = {k: (_bf16(v) if k.endswith(".w") and not k.startswith("head") else v) for k, v in P.items()}
+    Pr = {k: (v if k.endswith(".w") and not k.startswith("head") else v.astype(np.float32).astype(np.float64))
+          for k, v in Pr.items()}
+    ref, cache = U.forward(Pr, _bf16(x), lv)
+    print("[prod] forward rel", _rel(out, ref), flush=True)
+    assert _rel(out, ref) <= 5e-2
+    loss = net.backward(t)
+    G = _unflat(net.get_grads().astype(np.float64), lv, base)
+    loss_ref, g = U.mse(ref, t)
+    Gr = U.backward(Pr, cache, g, lv)
+    assert loss == pytest.approx(loss_ref, rel=5e-2)
+    worst = max((_rel(G[name], Gr[name]), name) for name, _ in U.layer_shapes(lv, base, CIN, COUT))
+    print("[prod] worst gradient rel", worst, flush=True)
+    assert worst[0] <= 8e-2, worst
+    net.close()
+
+
 def test_adam_step_matches_oracle_update(ss):
     P, x, t, net = _setup(ss, seed=2)
     w0 = net.get_weights().astype(np.float64)

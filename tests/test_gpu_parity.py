@@ -360,16 +360,98 @@ def test_every_tile_shape_matches_oracle(ss, theory, dtype, orc):
         info = s.flow_step(4)
         phi = _as_np(s.get_field())
         assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max(), tile
-        assert info["energy"] == pytest.approx(E_r, rel=1e-12 if dtype == "f64" else 1e-6)
+        _check_trajectory_energy(info["energy"], phi, E_r, phi_r, theory, h, dtype, orc)
         s.close()
+
+
+PLANS = [("stages", 0), ("fused", 1), ("fused_1024", 2)]
+
+
+@pytest.mark.parametrize("plan_name,plan", PLANS)
+@pytest.mark.parametrize("theory", [AH, CM])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(150, 37), (64, 16), (8, 8), (129, 70)])
+def test_every_plan_tracks_the_oracle(ss, plan_name, plan, theory, dtype, shape, orc):
+    """Each launch plan of a step (separate stage passes, fused stages 2-4 in
+    workgroups of 512 or 1024) gives the oracle's flow: FP64 to rounding, FP32
+    within the FP32 trajectory bound; arrests and steps agree exactly."""
+    Nx, Ny = shape
+    h = 0.17
+    print(f"[case] plan {plan_name} {theory} {dtype} {shape}", flush=True)
+    f = _field(theory, Nx, Ny, h, seed=Nx + 3 * Ny)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    s = _solver(ss, theory, f, h, dtype)
+    s.set_plan(plan)
+    assert s.plan == plan
+    s.set_field(f)
+    n = 5
+    info = s.flow_step(n)
+    phi, vel = s.get_field(velocity=True)
+    phi, vel = _as_np(phi), _as_np(vel)
+    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), n)
+    rel = 1e-11 if dtype == "f64" else 1e-5
+    assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max()
+    assert np.abs(vel - v_r).max() <= rel * max(np.abs(phi_r).max(), 1.0)
+    assert info["step"] == n and info["n_arrests"] == na_r
+    _check_trajectory_energy(info["energy"], phi, E_r, phi_r, theory, h, dtype, orc)
+    assert np.array_equal(phi[:, :2, :], f[:, :2, :]) and np.array_equal(phi[:, :, -2:], f[:, :, -2:])
+    s.close()
+
+
+def test_fused_plan_handles_arrests_like_the_oracle(ss, orc):
+    """A long FP64 run under the fused plan: arrests (v -> 0 inside the fused
+    stages) fire at the oracle's steps."""
+    Nx, Ny, h = 48, 40, 0.25
+    f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.3, -0.2), (-1.1, 0.9)]) + I.noise(5, 4, Nx, Ny, 1e-3)
+    for plan in (1, 2):
+        s = _solver(ss, AH, f, h, "f64")
+        s.set_plan(plan)
+        s.set_field(f)
+        E = None
+        phi_r, v_r = f, np.zeros_like(f)
+        total = 0
+        for chunk in range(4):
+            info = s.flow_step(50)
+            phi_r, v_r, E, na = orc.flow(AH, phi_r, v_r, h, [1.0], 50, E_cur=E)
+            total += na
+            assert info["n_arrests"] == total
+            assert info["energy"] == pytest.approx(E, rel=1e-11)
+        assert total > 0
+        assert np.abs(_as_np(s.get_field()) - phi_r).max() < 1e-9
+        s.close()
+
+
+def test_fused_plan_minimise_stops_where_the_oracle_does(ss, orc):
+    Nx, Ny, h = 40, 40, 0.25
+    f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.2, 0.1)]) + I.noise(8, 4, Nx, Ny, 1e-3)
+    s = _solver(ss, AH, f, h, "f64")
+    s.set_plan(1)
+    s.set_field(f)
+    res = s.minimise(grad_tol=3e-3, max_steps=5000, graph_steps=16)
+    phi_r, v_r, info_r = orc.minimise(AH, f, h, [1.0], grad_tol=3e-3, max_steps=5000)
+    assert res["reason"] == "grad" and res["step"] == info_r["steps"] and res["n_arrests"] == info_r["arrests"]
+    assert np.abs(_as_np(s.get_field()) - phi_r).max() < 1e-10
+    s.close()
+
+
+def test_exact_mode_rejects_fused_plans(ss):
+    s = ss.Solver(AH, 64, 64, 0.2, [1.0], dtype="f32", grad_mode=ss.SS_GRAD_EXACT)
+    assert s.plan == 0
+    with pytest.raises(ss.SSError):
+        s.set_plan(1)
+    s.close()
 
 
 def test_autotune_picks_a_shape_and_leaves_a_usable_context(ss, orc):
     Nx, Ny, h = 256, 96, 0.2
     f = _field(AH, Nx, Ny, h, seed=5).astype(np.float32).astype(np.float64)
     s = _solver(ss, AH, f, h, "f32")
-    best, ms = s.autotune(3)
-    assert 0 <= best < ss.ss_tile_count() and ms[best] == min(ms) and all(m > 0 for m in ms)
+    best, plan, ms = s.autotune(3)
+    flat = [m for row in ms for m in row]
+    assert 0 <= best < ss.ss_tile_count() and 0 <= plan < ss.SS_NUM_PLANS
+    assert ms[plan][best] == min(flat) and all(m > 0 for m in flat)
+    assert s.plan == plan
     s.set_field(f)
     E, _, _ = s.energy_grad(want_grad=False)
     assert E == pytest.approx(orc.energy(AH, f, h, [1.0]), rel=1e-12)
