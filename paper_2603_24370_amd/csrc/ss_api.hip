@@ -51,6 +51,8 @@ constexpr int kNumTiles = 4;
 constexpr int kDefaultTile = 0;
 constexpr int kDefaultPlanF32 = SS_PLAN_FUSED;
 static_assert(kTiles[0].TX == kExTX && kTiles[0].TY == kExTY, "the exact-gradient passes use the layout of tile 0");
+static_assert(kTiles[0].TX == 64 && kTiles[0].TY == 16 && kTiles[1].TX == 64 && kTiles[1].TY == 8,
+              "the fused passes use the layouts of tiles 0 (FP32) and 1 (FP64)");
 constexpr int kDefaultGraphSteps = 16;
 constexpr long kMaxGroups = 2048;  // persistent launch: at most 8 workgroups per CU
 
@@ -212,20 +214,28 @@ void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   else launch_pass_t<T, 1, PASS>(c->tile, a, c->L.nlaunch, s);
 }
 
-// Fused stages 2-4: the 64 x 16 tiling of tile 0, one of two workgroup shapes.
+// Fused stages 2-4: FP32 on the 64 x 16 tiling of tile 0, FP64 on the 64 x 8
+// tiling of tile 1 (its LDS planes are twice as large); RY = 2 or 1 rows per thread.
+template <class T>
+struct FusedTile {
+  static constexpr int TY = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int layout_tile = sizeof(T) == 4 ? 0 : 1;
+};
+
 template <class T, int TH>
 void launch_fused_t(int plan, const PassArgs<T>& a, int nlaunch, hipStream_t s) {
+  constexpr int TY = FusedTile<T>::TY;
   if (plan == SS_PLAN_FUSED)
-    hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, 16, 2>), dim3(nlaunch), dim3(64, 8), 0, s, a);
+    hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, TY, 2>), dim3(nlaunch), dim3(64, TY / 2), 0, s, a);
   else
-    hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, 16, 1>), dim3(nlaunch), dim3(64, 16), 0, s, a);
+    hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, TY, 1>), dim3(nlaunch), dim3(64, TY), 0, s, a);
 }
 
 template <class T>
 void launch_fused(const ss_ctx* c, hipStream_t s) {
   PassArgs<T> a = pass_args<T>(c);
   Layout L = c->L;
-  set_tiles(L, c->Nx, c->Ny, 0);
+  set_tiles(L, c->Nx, c->Ny, FusedTile<T>::layout_tile);
   a.ntx = L.ntx;
   a.nty = L.nty;
   a.seg = L.seg;

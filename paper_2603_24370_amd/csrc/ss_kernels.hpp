@@ -885,21 +885,29 @@ __device__ __forceinline__ void unit3(T (&x)[4]) {
 
 template <class T, int TH, int TX, int TY, int RY>
 __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, bool arrest, int x0, int y0,
-                                                T* __restrict__ la, T* __restrict__ lb) {
+                                                T* __restrict__ lds) {
   constexpr int C = NComp<TH>::value;
-  constexpr int AX = TX + 8, AY = TY + 8;   // plane A: S2 with halo 4, then S3 / S4 with halo 2
-  constexpr int BX = TX + 4, BY = TY + 4;   // plane B: a2 with halo 2
+  constexpr int AX = TX + 8, AY = TY + 8;   // A: S2 with halo 4, then S3 / S4 with halo 2
+  constexpr int BX = TX + 4, BY = TY + 4;   // B-shaped planes (tile plus halo 2)
+  constexpr int NA = AX * AY, NB = BX * BY;
   constexpr int NT = TX * (TY / RY);
-  constexpr int NRA = AX * AY - TX * TY;    // ring of A around the tile
-  constexpr int NRB = BX * BY - TX * TY;    // ring of B around the tile
+  constexpr int NRB = NB - TX * TY;         // ring of B around the tile
   constexpr int KRB = (NRB + NT - 1) / NT;
   constexpr bool MIXED = (TH == 0);
+  // LDS: A [C][AY][AX] | a2 [C][BY][BX] | phi [C][BY][BX] | v [C][BY][BX] | a1 [C][BY][BX]
   T* sa[4];
-  T* sb[4];
+  T* s2[4];
+  T* sp[4];
+  T* sv[4];
+  T* s1[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    sa[c] = la + (c < C ? c : 0) * (AX * AY);
-    sb[c] = lb + (c < C ? c : 0) * (BX * BY);
+    const int cc = c < C ? c : 0;
+    sa[c] = lds + cc * NA;
+    s2[c] = lds + C * NA + cc * NB;
+    sp[c] = lds + C * NA + C * NB + cc * NB;
+    sv[c] = lds + C * NA + 2 * C * NB + cc * NB;
+    s1[c] = lds + C * NA + 3 * C * NB + cc * NB;
   }
   const int Nx = V.Nx, Ny = V.Ny;
   const long pitch = V.pitch, plane = V.plane;
@@ -919,54 +927,41 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
   auto offs = [&](int x, int y) { return (long)(y + 2) * pitch + (x + 2); };
   auto in_pad = [&](int x, int y) { return x >= -2 && x <= Nx + 1 && y >= -2 && y <= Ny + 1; };
 
-  // ---- phase 1: raw phi, v of the own sites; S2 on the tile plus halo 4 -> A
-  T rp[RY][4], rv[RY][4];
-#pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    const int gj = y0 + threadIdx.y * RY + r;
-    T S[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) rp[r][c] = rv[r][c] = S[c] = T(0);
-    if (in_pad(gi, gj)) {
-      const long o = offs(gi, gj);
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        rp[r][c] = ph[c * plane + o];
-        rv[r][c] = vv[c * plane + o];
-        S[c] = rp[r][c] + cv2 * rv[r][c];
-      }
-      if (TH == 1 && inside(gi, gj)) unit3(S);
-    }
-    const int la_ = (4 + threadIdx.y * RY + r) * AX + 4 + threadIdx.x;
-#pragma unroll
-    for (int c = 0; c < C; ++c) sa[c][la_] = S[c];
-  }
-  for (int idx = tid; idx < NRA; idx += NT) {
-    int ly, lx;
-    if (idx < 8 * AX) {
-      const int rr = idx / AX;
-      ly = rr < 4 ? rr : AY - 8 + rr;
-      lx = idx - rr * AX;
-    } else {
-      const int j = idx - 8 * AX;
-      ly = 4 + (j >> 3);
-      const int cc = j & 7;
-      lx = cc < 4 ? cc : AX - 8 + cc;
-    }
+  // ---- phase 1 (all global reads of the tile): phi, v on the tile plus halo 4,
+  // S2 = phi + dt/2 v -> A; raw phi, v and a1 on the tile plus halo 2 -> LDS
+#pragma unroll 2
+  for (int idx = tid; idx < NA; idx += NT) {
+    const int ly = idx / AX, lx = idx - ly * AX;
     const int x = x0 - 4 + lx, y = y0 - 4 + ly;
-    T S[4] = {T(0), T(0), T(0), T(0)};
+    const bool inb = ly >= 2 && ly < AY - 2 && lx >= 2 && lx < AX - 2;
+    const int ib = (ly - 2) * BX + (lx - 2);
+    T P[4] = {T(0), T(0), T(0), T(0)}, W[4] = {T(0), T(0), T(0), T(0)}, S[4] = {T(0), T(0), T(0), T(0)};
+    T A1[4] = {T(0), T(0), T(0), T(0)};
     if (in_pad(x, y)) {
       const long o = offs(x, y);
 #pragma unroll
-      for (int c = 0; c < C; ++c) S[c] = ph[c * plane + o] + cv2 * vv[c * plane + o];
+      for (int c = 0; c < C; ++c) {
+        P[c] = ph[c * plane + o];
+        W[c] = vv[c * plane + o];
+        if (inb) A1[c] = a1p[c * plane + o];
+        S[c] = P[c] + cv2 * W[c];
+      }
       if (TH == 1 && inside(x, y)) unit3(S);
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) sa[c][ly * AX + lx] = S[c];
+    for (int c = 0; c < C; ++c) sa[c][idx] = S[c];
+    if (inb) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        sp[c][ib] = P[c];
+        sv[c][ib] = W[c];
+        s1[c][ib] = A1[c];
+      }
+    }
   }
   __syncthreads();
 
-  // ---- phase 2: a2 = -G(S2) on the tile plus a ring of 2 -> B; 0 off the interior
+  // ---- phase 2: a2 = -G(S2) on the tile (column jets) and its ring (site jets); 0 off the interior
   {
     Jet<T> J[C][RY];
     double dx_[C][RY], dy_[C][RY];
@@ -982,12 +977,11 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
       T G[4] = {T(0), T(0), T(0), T(0)};
       site_gradient<T, TH>(Js, V, G);
       const bool in = inside(gi, y0 + threadIdx.y * RY + r);
-      const int lb_ = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
+      const int ib = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
 #pragma unroll
-      for (int c = 0; c < C; ++c) sb[c][lb_] = in ? -G[c] : T(0);
+      for (int c = 0; c < C; ++c) s2[c][ib] = in ? -G[c] : T(0);
     }
   }
-  // ring of B (its raw phi, v are read again in phases 3 and 5, from L2)
 #pragma unroll
   for (int k = 0; k < KRB; ++k) {
     const int idx = tid + k * NT;
@@ -1003,9 +997,8 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
         const int cc = j & 3;
         bx = cc < 2 ? cc : BX - 4 + cc;
       }
-      const int x = x0 - 2 + bx, y = y0 - 2 + by;
       T a[4] = {T(0), T(0), T(0), T(0)};
-      if (inside(x, y)) {
+      if (inside(x0 - 2 + bx, y0 - 2 + by)) {
         Jet<T> Js[4];
 #pragma unroll
         for (int c = 0; c < C; ++c) site_jet<T, AX, MIXED>(sa[c], by + 2, bx + 2, c1, c2, Js[c]);
@@ -1015,53 +1008,27 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
         for (int c = 0; c < C; ++c) a[c] = -G[c];
       }
 #pragma unroll
-      for (int c = 0; c < C; ++c) sb[c][by * BX + bx] = a[c];
+      for (int c = 0; c < C; ++c) s2[c][by * BX + bx] = a[c];
     }
   }
   __syncthreads();
 
-  // ---- phase 3: S3 = phi + dt/2 v + dt^2/4 a1 on the tile plus halo 2 -> A (offset 2)
-#pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    const int gj = y0 + threadIdx.y * RY + r;
-    T S[4] = {T(0), T(0), T(0), T(0)};
-    if (in_pad(gi, gj)) {
-      const long o = offs(gi, gj);
-#pragma unroll
-      for (int c = 0; c < C; ++c) S[c] = rp[r][c] + cv2 * rv[r][c] + ca3 * a1p[c * plane + o];
-    }
-    if (TH == 1 && inside(gi, gj)) unit3(S);
-    const int la_ = (4 + threadIdx.y * RY + r) * AX + 4 + threadIdx.x;
-#pragma unroll
-    for (int c = 0; c < C; ++c) sa[c][la_] = S[c];
-  }
-#pragma unroll
-  for (int k = 0; k < KRB; ++k) {
-    const int idx = tid + k * NT;
-    if (idx < NRB) {
-      int by, bx;
-      if (idx < 4 * BX) {
-        const int rr = idx / BX;
-        by = rr < 2 ? rr : BY - 4 + rr;
-        bx = idx - rr * BX;
-      } else {
-        const int j = idx - 4 * BX;
-        by = 2 + (j >> 2);
-        const int cc = j & 3;
-        bx = cc < 2 ? cc : BX - 4 + cc;
-      }
-      const int x = x0 - 2 + bx, y = y0 - 2 + by;
+  // stage point on the tile plus halo 2 -> A (offset 2): phi + cv v + ca acc
+  auto stage_b = [&](T cv, T ca, T* const (&acc)[4]) {
+#pragma unroll 1
+    for (int ib = tid; ib < NB; ib += NT) {
+      const int by = ib / BX, bx = ib - by * BX;
       T S[4] = {T(0), T(0), T(0), T(0)};
-      if (in_pad(x, y)) {
-        const long o = offs(x, y);
 #pragma unroll
-        for (int c = 0; c < C; ++c) S[c] = ph[c * plane + o] + cv2 * vv[c * plane + o] + ca3 * a1p[c * plane + o];
-        if (TH == 1 && inside(x, y)) unit3(S);
-      }
+      for (int c = 0; c < C; ++c) S[c] = sp[c][ib] + cv * sv[c][ib] + ca * acc[c][ib];
+      if (TH == 1 && inside(x0 - 2 + bx, y0 - 2 + by)) unit3(S);
 #pragma unroll
       for (int c = 0; c < C; ++c) sa[c][(by + 2) * AX + bx + 2] = S[c];
     }
-  }
+  };
+
+  // ---- phase 3: S3 = phi + dt/2 v + dt^2/4 a1
+  stage_b(cv2, ca3, s1);
   __syncthreads();
 
   // ---- phase 4: q = a1 + 2 a2 - 2 G(S3) at the own sites
@@ -1080,57 +1047,17 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
       for (int c = 0; c < C; ++c) Js[c] = J[c][r];
       T G[4] = {T(0), T(0), T(0), T(0)};
       site_gradient<T, TH>(Js, V, G);
-      const int gj = y0 + threadIdx.y * RY + r;
-      const int lb_ = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
-      const long o = in_pad(gi, gj) ? offs(gi, gj) : 0;
+      const int ib = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
 #pragma unroll
       for (int c = 0; c < 4; ++c) qo[r][c] = T(0);
 #pragma unroll
-      for (int c = 0; c < C; ++c) qo[r][c] = a1p[c * plane + o] + T(2) * sb[c][lb_] - T(2) * G[c];
+      for (int c = 0; c < C; ++c) qo[r][c] = s1[c][ib] + T(2) * s2[c][ib] - T(2) * G[c];
     }
   }
   __syncthreads();
 
-  // ---- phase 5: S4 = phi + dt v + dt^2/2 a2 on the tile plus halo 2 -> A
-#pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    const int gj = y0 + threadIdx.y * RY + r;
-    T S[4] = {T(0), T(0), T(0), T(0)};
-    const int lb_ = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
-#pragma unroll
-    for (int c = 0; c < C; ++c) S[c] = rp[r][c] + cv4 * rv[r][c] + ca4 * sb[c][lb_];
-    if (TH == 1 && inside(gi, gj)) unit3(S);
-    const int la_ = (4 + threadIdx.y * RY + r) * AX + 4 + threadIdx.x;
-#pragma unroll
-    for (int c = 0; c < C; ++c) sa[c][la_] = S[c];
-  }
-#pragma unroll
-  for (int k = 0; k < KRB; ++k) {
-    const int idx = tid + k * NT;
-    if (idx < NRB) {
-      int by, bx;
-      if (idx < 4 * BX) {
-        const int rr = idx / BX;
-        by = rr < 2 ? rr : BY - 4 + rr;
-        bx = idx - rr * BX;
-      } else {
-        const int j = idx - 4 * BX;
-        by = 2 + (j >> 2);
-        const int cc = j & 3;
-        bx = cc < 2 ? cc : BX - 4 + cc;
-      }
-      const int x = x0 - 2 + bx, y = y0 - 2 + by;
-      T S[4] = {T(0), T(0), T(0), T(0)};
-      if (in_pad(x, y)) {
-        const long o = offs(x, y);
-#pragma unroll
-        for (int c = 0; c < C; ++c) S[c] = ph[c * plane + o] + cv4 * vv[c * plane + o] + ca4 * sb[c][by * BX + bx];
-        if (TH == 1 && inside(x, y)) unit3(S);
-      }
-#pragma unroll
-      for (int c = 0; c < C; ++c) sa[c][(by + 2) * AX + bx + 2] = S[c];
-    }
-  }
+  // ---- phase 5: S4 = phi + dt v + dt^2/2 a2
+  stage_b(cv4, ca4, s2);
   __syncthreads();
 
   // ---- phase 6: a4 = -G(S4); phi', v' at the own sites
@@ -1152,12 +1079,12 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
       for (int c = 0; c < C; ++c) Js[c] = J[c][r];
       T G[4] = {T(0), T(0), T(0), T(0)};
       site_gradient<T, TH>(Js, V, G);
-      const long o = offs(gi, gj);
+      const int ib = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
       T pn[4], vnew[4];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const T v0 = arrest ? T(0) : rv[r][c];
-        pn[c] = rp[r][c] + dt * v0 + (dt * dt / T(12)) * (qo[r][c] + a1p[c * plane + o]);
+        const T v0 = arrest ? T(0) : sv[c][ib];
+        pn[c] = sp[c][ib] + dt * v0 + (dt * dt / T(12)) * (qo[r][c] + s1[c][ib]);
         vnew[c] = v0 + (dt / T(6)) * (qo[r][c] - G[c]);
       }
       if (TH == 1) {
@@ -1166,6 +1093,7 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
 #pragma unroll
         for (int c = 0; c < 3; ++c) vnew[c] -= vd * pn[c];
       }
+      const long o = offs(gi, gj);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         __builtin_nontemporal_store(pn[c], &phn[c * plane + o]);
@@ -1176,18 +1104,23 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
   __syncthreads();
 }
 
+// LDS elements of the fused pass for a tile shape
+template <class T, int TH, int TX, int TY>
+struct FusedLds {
+  static constexpr int C = NComp<TH>::value;
+  static constexpr int value = C * ((TX + 8) * (TY + 8) + 4 * (TX + 4) * (TY + 4));
+};
+
 template <class T, int TH, int TX, int TY, int RY>
 __global__ void __launch_bounds__(TX*(TY / RY)) stage_pass_fused(PassArgs<T> a) {
-  constexpr int C = NComp<TH>::value;
-  __shared__ __align__(16) T la[C * (TX + 8) * (TY + 8)];
-  __shared__ __align__(16) T lb[C * (TX + 4) * (TY + 4)];
+  __shared__ __align__(16) T lds[FusedLds<T, TH, TX, TY>::value];
   DevStatus* __restrict__ st = a.st;
   if (st->done) return;
   const int cur = int((st->step - 1) & 1);
   const bool arrest = st->arrest != 0;
   const InstView<T> V = view_of<T>(a.B, a.cf);
   for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty) {
-    tile_body_fused<T, TH, TX, TY, RY>(V, cur, arrest, tx * TX, ty * TY, la, lb);
+    tile_body_fused<T, TH, TX, TY, RY>(V, cur, arrest, tx * TX, ty * TY, lds);
   });
 }
 
