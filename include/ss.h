@@ -250,12 +250,16 @@ int ss_set_energy_target(ss_ctx* ctx, double e_target);
  *                       corr (Ny, Nx, 4), the vacuum on the halo, and starts the
  *                       flow from rest (as ss_set_field). The envelope
  *                       env = 1 - prod_k (1 - exp(-r_k^2 / (2 sigma^2))) keeps the
- *                       corrections near the vortices; sigma <= 0 gives env = 1,
- *                       for which ss_init_learned inverts ss_learned_targets.
+ *                       corrections near the vortices (sigma <= 0: env = 1); with
+ *                       pin > 0 the psi correction is also multiplied by
+ *                       prod_k (1 - exp(-r_k^2 / (2 pin^2))), which keeps the zeros
+ *                       of psi at the centres (pin <= 0: factor 1). With sigma <= 0
+ *                       and pin <= 0 ss_init_learned inverts ss_learned_targets.
  * The first two synchronise. */
 int ss_learned_input(ss_ctx* ctx, int n, const double* xy, double kappa, float* out);
 int ss_learned_targets(ss_ctx* ctx, int n, const double* xy, const double* w, float* out);
-int ss_init_learned(ss_ctx* ctx, int n, const double* xy, const double* w, const float* corr, double sigma);
+int ss_init_learned(ss_ctx* ctx, int n, const double* xy, const double* w, const float* corr, double sigma,
+                    double pin);
 
 /* Plans: how the four stages of an RK4 step (Sec. 3.2, eq. (3)) are launched.
  *   SS_PLAN_STAGES      one pass per stage, P1..P4 (17 field sets of HBM

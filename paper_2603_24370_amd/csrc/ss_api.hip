@@ -841,9 +841,10 @@ int ss_learned_targets(ss_ctx* c, int n, const double* xy, const double* w, floa
   return SS_OK;
 }
 
-int ss_init_learned(ss_ctx* c, int n, const double* xy, const double* w, const float* corr, double sigma) {
+int ss_init_learned(ss_ctx* c, int n, const double* xy, const double* w, const float* corr, double sigma,
+                    double pin) {
   if (!c || !corr) return fail(SS_EINVAL, "ctx or corrections are NULL");
-  if (!(sigma <= 0.0 || std::isfinite(sigma))) return fail(SS_EINVAL, "sigma must be finite");
+  if (!std::isfinite(sigma) || !std::isfinite(pin)) return fail(SS_EINVAL, "sigma and pin must be finite");
   if (c->theory != SS_THEORY_AH) return fail(SS_EINVAL, "the learned start exists for the Abelian Higgs model only");
   double *dxy, *dw;
   int rc = stage_centres(c, n, xy, w, &dxy, &dw);
@@ -852,10 +853,10 @@ int ss_init_learned(ss_ctx* c, int n, const double* xy, const double* w, const f
   const dim3 g((unsigned)((sites + 255) / 256));
   if (c->dtype == SS_F32)
     hipLaunchKernelGGL((init_learned<float>), g, dim3(256), 0, c->stream, bufs_of<float>(c), coeffs_of(c),
-                       (const double*)dxy, (const double*)dw, n, corr, sigma);
+                       (const double*)dxy, (const double*)dw, n, corr, sigma, pin);
   else
     hipLaunchKernelGGL((init_learned<double>), g, dim3(256), 0, c->stream, bufs_of<double>(c), coeffs_of(c),
-                       (const double*)dxy, (const double*)dw, n, corr, sigma);
+                       (const double*)dxy, (const double*)dw, n, corr, sigma, pin);
   SS_HIP(hipGetLastError());
   return reset_state(c);
 }

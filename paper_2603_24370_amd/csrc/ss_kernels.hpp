@@ -1632,12 +1632,15 @@ __global__ void __launch_bounds__(256) learned_targets(Bufs<T> B, Coeffs cf, con
 // that is 1 at the vortex centres and decays away from them,
 //   env = 1 - prod_k (1 - exp(-r_k^2 / (2 sigma^2)))   (sigma <= 0: env = 1),
 // so that a network's small errors far from the vortices (where the ansatz is
-// already the vacuum) do not seed slow, lattice-wide modes:
-//   psi = (f_ans + env (c0 + i c1)) e^{i Theta},   A = A_ans + env (c2, c3)
+// already the vacuum) do not seed slow, lattice-wide modes, and (pin > 0) a
+// factor on the psi correction that vanishes at every centre,
+//   pinf = prod_k (1 - exp(-r_k^2 / (2 pin^2)))        (pin <= 0: pinf = 1),
+// which keeps the zeros of psi at the given centres:
+//   psi = (f_ans + env pinf (c0 + i c1)) e^{i Theta},   A = A_ans + env (c2, c3)
 // on the interior; the halo gets the pure-gauge vacuum.
 template <class T>
 __global__ void __launch_bounds__(256) init_learned(Bufs<T> B, Coeffs cf, const double* xy, const double* w, int n,
-                                                    const float* corr, double sigma) {
+                                                    const float* corr, double sigma, double pin) {
   const long W = B.Nx + 4, H = B.Ny + 4;
   const long k = blockIdx.x * 256L + threadIdx.x;
   if (k >= W * H) return;
@@ -1659,8 +1662,16 @@ __global__ void __launch_bounds__(256) init_learned(Bufs<T> B, Coeffs cf, const 
       }
       env = 1.0 - far;
     }
+    double pinf = 1.0;
+    if (pin > 0.0) {
+      const double s2 = 0.5 / (pin * pin);
+      for (int v = 0; v < n; ++v) {
+        const double dx = x - xy[2 * v], dy = y - xy[2 * v + 1];
+        pinf *= -expm1(-(dx * dx + dy * dy) * s2);
+      }
+    }
     const float* c = corr + 4 * ((long)j * B.Nx + i);
-    const double re = mod + env * c[0], im = env * c[1];
+    const double re = mod + env * pinf * c[0], im = env * pinf * c[1];
     const double cs = cos(ph), sn = sin(ph);
     out[0] = re * cs - im * sn;
     out[1] = re * sn + im * cs;

@@ -237,6 +237,17 @@ def test_learned_input_and_targets(ss, orc):
     psia = (ga[0, 2:-2, 2:-2] + 1j * ga[1, 2:-2, 2:-2]) * np.exp(-1j * theta)
     assert np.abs(psi1 - psia - env).max() < 1e-12
     assert np.array_equal(g1[2:, :, :], ga[2:, :, :])
+    # the pin factor prod_k (1 - exp(-r_k^2 / 2 pin^2)) multiplies the psi correction only
+    pin = 0.4
+    one[..., 2] = 1.0
+    ss.ss_init_learned(s.ctx, cen, None, one.data_ptr(), sigma=0.0, pin=pin)
+    g2 = s.get_field().cpu().numpy()
+    pinf = np.ones_like(X)
+    for cx, cy in cen:
+        pinf *= 1.0 - np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * pin ** 2))
+    psi2 = (g2[0, 2:-2, 2:-2] + 1j * g2[1, 2:-2, 2:-2]) * np.exp(-1j * theta)
+    assert np.abs(psi2 - psia - pinf).max() < 1e-12
+    assert np.abs(g2[2, 2:-2, 2:-2] - ga[2, 2:-2, 2:-2] - 1.0).max() < 1e-12
     s.close()
 
 
