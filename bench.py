@@ -140,10 +140,15 @@ def ss_tile(i):
     return ss.ss_tile_shape(i)
 
 
+STAGE_SOURCES = ["ss_internal.hpp", "ss_theory.hpp", "ss_kernels.hpp", "ss_api.hip"]
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources the stage kernels are built from (traffic counters
+    taken on other sources are not reported)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_24370_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in STAGE_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
