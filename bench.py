@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "P234": (3, 2)}
 STEP_SETS = 17          # separate stage passes
 STEP_SETS_FUSED = 7     # P1 + fused stages 2-4
-PLAN_NAMES = ["stages", "fused", "fused_1024"]
+PLAN_NAMES = ["stages", "fused"]
 
 WORKLOADS = {
     "gl4096": dict(theory="abelian_higgs", N=4096, h=0.2, kappa=1.5, nv=256, seed=4, dtype="f32"),

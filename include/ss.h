@@ -266,17 +266,14 @@ int ss_init_learned(ss_ctx* ctx, int n, const double* xy, const double* w, const
  *                       traffic per site and step);
  *   SS_PLAN_FUSED       P1, then one pass that evaluates stages 2, 3 and 4 and
  *                       the update on a tile, recomputing stage 2 on a ring
- *                       of 2 around it (7 field sets per site and step);
- *                       workgroups of 512 threads;
- *   SS_PLAN_FUSED_1024  the same pass with workgroups of 1024 threads.
+ *                       of 2 around it (7 field sets per site and step).
  * All plans give the same step up to rounding order. The fused plans exist for
  * the Euler-Lagrange gradient only (SS_EINVAL otherwise). New FP32 contexts
  * with the Euler-Lagrange gradient start with SS_PLAN_FUSED, others with
  * SS_PLAN_STAGES. ss_set_plan synchronises the stream. */
 #define SS_PLAN_STAGES 0
 #define SS_PLAN_FUSED 1
-#define SS_PLAN_FUSED_1024 2
-#define SS_NUM_PLANS 3
+#define SS_NUM_PLANS 2
 int ss_set_plan(ss_ctx* ctx, int plan);
 int ss_get_plan(ss_ctx* ctx);
 

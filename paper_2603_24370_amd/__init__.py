@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(HERE, "libss.so")
 SS_OK, SS_NOT_CONVERGED = 0, 1
 SS_F32, SS_F64 = 0, 1
 SS_GRAD_EL, SS_GRAD_EXACT = 0, 1
-SS_PLAN_STAGES, SS_PLAN_FUSED, SS_PLAN_FUSED_1024 = 0, 1, 2
-SS_NUM_PLANS = 3
+SS_PLAN_STAGES, SS_PLAN_FUSED = 0, 1
+SS_NUM_PLANS = 2
 SS_THEORY_AH, SS_THEORY_CM = 0, 1
 SS_ANSATZ_VORTICES, SS_ANSATZ_SKYRMION = 0, 1
 STOP_REASONS = {0: "none", 1: "grad", 2: "stall", 3: "max_steps", 4: "nonfinite", 5: "target"}

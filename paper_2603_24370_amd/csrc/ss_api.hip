@@ -215,7 +215,7 @@ void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
 }
 
 // Fused stages 2-4: FP32 on the 64 x 16 tiling of tile 0, FP64 on the 64 x 8
-// tiling of tile 1 (its LDS planes are twice as large); RY = 2 or 1 rows per thread.
+// tiling of tile 1 (its LDS planes are twice as large); two rows per thread.
 template <class T>
 struct FusedTile {
   static constexpr int TY = sizeof(T) == 4 ? 16 : 8;
@@ -223,12 +223,9 @@ struct FusedTile {
 };
 
 template <class T, int TH>
-void launch_fused_t(int plan, const PassArgs<T>& a, int nlaunch, hipStream_t s) {
+void launch_fused_t(const PassArgs<T>& a, int nlaunch, hipStream_t s) {
   constexpr int TY = FusedTile<T>::TY;
-  if (plan == SS_PLAN_FUSED)
-    hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, TY, 2>), dim3(nlaunch), dim3(64, TY / 2), 0, s, a);
-  else
-    hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, TY, 1>), dim3(nlaunch), dim3(64, TY), 0, s, a);
+  hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, TY, 2>), dim3(nlaunch), dim3(64, TY / 2), 0, s, a);
 }
 
 template <class T>
@@ -239,8 +236,8 @@ void launch_fused(const ss_ctx* c, hipStream_t s) {
   a.ntx = L.ntx;
   a.nty = L.nty;
   a.seg = L.seg;
-  if (c->theory == SS_THEORY_AH) launch_fused_t<T, 0>(c->plan, a, L.nlaunch, s);
-  else launch_fused_t<T, 1>(c->plan, a, L.nlaunch, s);
+  if (c->theory == SS_THEORY_AH) launch_fused_t<T, 0>(a, L.nlaunch, s);
+  else launch_fused_t<T, 1>(a, L.nlaunch, s);
 }
 
 template <class T>

@@ -364,7 +364,7 @@ def test_every_tile_shape_matches_oracle(ss, theory, dtype, orc):
         s.close()
 
 
-PLANS = [("stages", 0), ("fused", 1), ("fused_1024", 2)]
+PLANS = [("stages", 0), ("fused", 1)]
 
 
 @pytest.mark.parametrize("plan_name,plan", PLANS)
@@ -372,9 +372,9 @@ PLANS = [("stages", 0), ("fused", 1), ("fused_1024", 2)]
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(150, 37), (64, 16), (8, 8), (129, 70)])
 def test_every_plan_tracks_the_oracle(ss, plan_name, plan, theory, dtype, shape, orc):
-    """Each launch plan of a step (separate stage passes, fused stages 2-4 in
-    workgroups of 512 or 1024) gives the oracle's flow: FP64 to rounding, FP32
-    within the FP32 trajectory bound; arrests and steps agree exactly."""
+    """Each launch plan of a step (separate stage passes, fused stages 2-4) gives
+    the oracle's flow: FP64 to rounding, FP32 within the FP32 trajectory bound;
+    arrests and steps agree exactly."""
     Nx, Ny = shape
     h = 0.17
     print(f"[case] plan {plan_name} {theory} {dtype} {shape}", flush=True)
@@ -404,7 +404,7 @@ def test_fused_plan_handles_arrests_like_the_oracle(ss, orc):
     stages) fire at the oracle's steps."""
     Nx, Ny, h = 48, 40, 0.25
     f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.3, -0.2), (-1.1, 0.9)]) + I.noise(5, 4, Nx, Ny, 1e-3)
-    for plan in (1, 2):
+    for plan in (1,):
         s = _solver(ss, AH, f, h, "f64")
         s.set_plan(plan)
         s.set_field(f)
