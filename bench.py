@@ -279,9 +279,12 @@ def main():
     step_sets = STEP_SETS if plan == 0 else STEP_SETS_FUSED
     step_gbps = step_sets * C * b * sites / (ms_step * 1e-3) / 1e9
     tr = traffic_record(dom, args.workload)
+    tr_gb = tr["total_GB"] if tr else None
     kname = f"stage_pass {dom}" if dom != "P234" else "stage_pass_fused (stages 2-4)"
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr, "kernel": kname,
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr_gb, "traffic_unit": "GB per launch (rocprofv3 "
+            "FETCH_SIZE x2 + WRITE_SIZE x1, scaled on a plain copy)", "traffic_over_algorithmic": tr["ratio"] if tr else None,
+            "kernel": kname,
             "step_GBps": round(step_gbps, 1), "step_frac": round(step_gbps / HBM_PEAK_GBS, 4),
             "step_sets": step_sets,
             "passes": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in passes.items()}}
