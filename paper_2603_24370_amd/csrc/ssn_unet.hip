@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -75,15 +76,15 @@ struct ConvArgs {
   int accumulate;    // backward: out += result
 };
 
-// Each wave: 32 output channels x (32 * WN) pixels; block: 4 waves along pixels.
-template <int WN>
-__global__ void __launch_bounds__(256) conv3x3_mfma(ConvArgs a) {
+// Each wave: 32 output channels x (32 * WN) pixels; block: WB waves along pixels.
+template <int WN, int WB>
+__global__ void __launch_bounds__(64 * WB) conv3x3_mfma(ConvArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 31, half = lane >> 5;
   const int co0 = blockIdx.y * 32;
   const int H = a.in.H, W = a.in.W, Ci = a.in.C;
   const long P = (long)a.in.N * H * W;
-  const long pixbase = ((long)blockIdx.x * 4 + wave) * (32 * WN);
+  const long pixbase = ((long)blockIdx.x * WB + wave) * (32 * WN);
   int pn[WN], py[WN], px[WN];
   bool pv[WN];
 #pragma unroll
@@ -484,6 +485,7 @@ constexpr long kWgradPartFloats = 1024L * 9 * 1024;
 
 struct ssn_net {
   int levels, base, cin, cout, cin_pad, Ncap, H, W, L;
+  int conv_shape;  // 0: by problem size, 1: large workgroups, 2: small workgroups
   hipStream_t stream;
   float *P, *G, *M, *V;
   long np;
@@ -603,6 +605,21 @@ int dec_b(const ssn_net* n, int l) { return dec_a(n, l) + 1; }
 
 int grid1(long n) { return (int)std::min<long>((n + 255) / 256, 65535); }
 
+// Large problems: blocks of 4 waves, 64 pixels per wave. Small ones (few images,
+// deep levels) would leave most CUs idle that way: one wave per block and 32
+// pixels per wave give 8x more workgroups.
+void launch_conv(const ssn_net* n, const ConvArgs& ca, long P, int Co) {
+  const unsigned gy = (unsigned)((Co + 31) / 32);
+  const bool large = n->conv_shape == 1 || (n->conv_shape == 0 && (P + 255) / 256 * gy >= 1024);
+  if (large) {
+    dim3 grid((unsigned)((P + 255) / 256), gy);
+    hipLaunchKernelGGL((conv3x3_mfma<2, 4>), grid, dim3(256), 0, n->stream, ca);
+  } else {
+    dim3 grid((unsigned)((P + 31) / 32), gy);
+    hipLaunchKernelGGL((conv3x3_mfma<1, 1>), grid, dim3(64), 0, n->stream, ca);
+  }
+}
+
 void launch_conv_fwd(const ssn_net* n, const ConvL& c, TV in, TV z, TV a) {
   ConvArgs ca;
   ca.in = in;
@@ -614,9 +631,7 @@ void launch_conv_fwd(const ssn_net* n, const ConvL& c, TV in, TV z, TV a) {
   ca.zprev.p = nullptr;
   ca.mode = 0;
   ca.accumulate = 0;
-  const long P = (long)in.N * in.H * in.W;
-  dim3 grid((unsigned)((P + 255) / 256), (unsigned)((c.Co + 31) / 32));
-  hipLaunchKernelGGL((conv3x3_mfma<2>), grid, dim3(256), 0, n->stream, ca);
+  launch_conv(n, ca, (long)in.N * in.H * in.W, c.Co);
 }
 
 // gradient w.r.t. the layer input: out = conv(gz, wb) [* SiLU'(zprev)]
@@ -632,9 +647,7 @@ void launch_conv_bwd_data(const ssn_net* n, const ConvL& c, TV gz, TV out, const
   else ca.zprev.p = nullptr;
   ca.mode = 1;
   ca.accumulate = 0;
-  const long P = (long)gz.N * gz.H * gz.W;
-  dim3 grid((unsigned)((P + 255) / 256), (unsigned)((c.Ci + 31) / 32));
-  hipLaunchKernelGGL((conv3x3_mfma<2>), grid, dim3(256), 0, n->stream, ca);
+  launch_conv(n, ca, (long)gz.N * gz.H * gz.W, c.Ci);
 }
 
 void launch_wgrad(ssn_net* n, const ConvL& c, TV gz, TV x) {
@@ -850,6 +863,11 @@ int ssn_create(int levels, int base, int cin, int cout, int N, int H, int W, voi
   n->Ncap = N; n->H = H; n->W = W;
   n->stream = (hipStream_t)stream;
   n->adam_t = 0;
+  n->conv_shape = 0;
+  if (const char* env = std::getenv("SSN_CONV_SHAPE")) {
+    const int v = std::atoi(env);
+    if (v >= 0 && v <= 2) n->conv_shape = v;
+  }
   net_layers(n);
   n->bytes = net_carve(n, (char*)ws);
   hipError_t e = hipMemsetAsync(ws, 0, n->bytes, n->stream);

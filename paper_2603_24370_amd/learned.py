@@ -222,6 +222,17 @@ def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20
     net = ss.Net(levels=levels, base=base, cin=2, cout=4, N=batch, H=side, W=side, device=device)
     net.set_weights(init_weights(seed, levels, base, 2, 4))
     losses, tflops, t_train = train(net, X, T, epochs=epochs, batch=batch, lr=lr, seed=seed, log=log)
+    # network time of one learned start (batch of one image), after a warm-up
+    x1 = X[:1].contiguous()
+    net.forward(x1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        net.forward(x1)
+    torch.cuda.synchronize()
+    infer_ms = (time.perf_counter() - t1) / 20 * 1e3
+    if log:
+        log(f"[infer] {infer_ms:.3f} ms per image at batch 1")
     del X, T
     torch.cuda.empty_cache()
     recs = ab_compare(net, test_insts, tol=tol, sigmas=sigmas, pin=pin, device=device, log=log)
@@ -231,6 +242,7 @@ def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20
                 "data_median_steps": float(np.median(steps)), "train_s": t_train, "train_TFLOPs": tflops,
                 "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1], "losses": losses, "tol": tol,
                 "target_steps": target_steps, "target_mean_square": zero_mse, "pin": pin,
+                "inference_ms_batch1": infer_ms,
                 "records": recs})
     net.close()
     return out

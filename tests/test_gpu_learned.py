@@ -72,7 +72,9 @@ def _bf16(a):
     return u.view(np.float32).astype(np.float64)
 
 
-def test_forward_matches_oracle(ss):
+@pytest.mark.parametrize("shape", ["1", "2"])
+def test_forward_matches_oracle(ss, shape, monkeypatch):
+    monkeypatch.setenv("SSN_CONV_SHAPE", shape)
     P, x, t, net = _setup(ss)
     out = net.forward(x).cpu().numpy().astype(np.float64)
     Pr = {k: (_bf16(v) if k.endswith(".w") and not k.startswith("head") else v) for k, v in P.items()}
@@ -81,7 +83,9 @@ def test_forward_matches_oracle(ss):
     net.close()
 
 
-def test_backward_matches_oracle(ss):
+@pytest.mark.parametrize("shape", ["1", "2"])
+def test_backward_matches_oracle(ss, shape, monkeypatch):
+    monkeypatch.setenv("SSN_CONV_SHAPE", shape)
     P, x, t, net = _setup(ss, seed=1)
     net.forward(x)
     loss = net.backward(t)
