@@ -119,7 +119,9 @@ def run_batch(args, wl):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms_step = 1e3 * el / args.steps
-    step_gbps = STEP_SETS * 4 * 4 * sites / (ms_step * 1e-3) / 1e9
+    batch_plan = B.plan if (not tune or tune[0] == 0) else 0  # the fused pass runs on tile 0 (FP32)
+    step_sets = STEP_SETS_FUSED if batch_plan == 1 else STEP_SETS
+    step_gbps = step_sets * 4 * 4 * sites / (ms_step * 1e-3) / 1e9
     out = {"metric": "site-updates/s", "value": sites * args.steps / el, "unit": "site-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32 fields, f64 reductions",
@@ -127,9 +129,13 @@ def run_batch(args, wl):
            "config": {"workload": "batch256", "members": wl["n"], "interior_sites": sites, "h": wl["h"],
                       "grad_form": "euler-lagrange", "parallelism": "single GPU, one launch per pass"},
            "roofline": {"bound": "hbm", "achieved": round(step_gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(step_gbps / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "batch_pass (whole step)"},
+                        "frac": round(step_gbps / HBM_PEAK_GBS, 4), "traffic": None, "step_sets": step_sets,
+                        "kernel": "batch_pass + batch_pass_fused (whole step)" if step_sets == STEP_SETS_FUSED
+                        else "batch_pass (whole step)"},
            "tile": {"chosen": list(ss_tile(tune[0])) if tune else None,
-                    "step_ms_by_tile": [round(x, 4) for x in tune[1]] if tune else None},
+                    "plan": PLAN_NAMES[batch_plan],
+                    "step_ms_by_plan_and_tile": {PLAN_NAMES[p]: [round(x, 4) for x in row]
+                                                 for p, row in enumerate(tune[2])} if tune else None},
            "cpu_baseline": None}
     print(json.dumps(out), flush=True)
     B.close()

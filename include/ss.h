@@ -325,7 +325,16 @@ int ss_batch_flow_step(ss_batch* batch, int n_steps, ss_step_info* infos);
  * SS_OK if all converged, SS_NOT_CONVERGED if any hit max_steps. */
 int ss_batch_minimise(ss_batch* batch, const ss_stop* stop, ss_min_info* infos);
 int ss_batch_set_tile(ss_batch* batch, int tile);
-/* Times every tile shape over n_steps batch steps (overwrites all fields with the vacuum). */
+/* Plan of the batch's steps (SS_PLAN_*, default SS_PLAN_FUSED). The fused pass
+ * runs on one tile shape, 64 x 16 (FP32) or 64 x 8 (FP64), i.e. tile 0 or 1;
+ * with any other shape the batch runs separate stage passes. */
+int ss_batch_set_plan(ss_batch* batch, int plan);
+int ss_batch_get_plan(ss_batch* batch);
+/* Times every plan with every tile shape it runs on over n_steps batch steps
+ * (overwrites all fields with the vacuum), keeps the fastest pair, writes the
+ * step times in ms_out (may be NULL, else SS_NUM_PLANS * ss_tile_count()
+ * doubles, index plan * ss_tile_count() + tile, -1 where a pair does not
+ * apply) and returns the chosen tile (the plan: ss_batch_get_plan). */
 int ss_batch_autotune(ss_batch* batch, int n_steps, double* ms_out);
 
 /* Read the device status into info (synchronises). */

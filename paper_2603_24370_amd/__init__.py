@@ -74,7 +74,7 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_set_tile", "ss_get_tile", "ss_autotune", "ss_set_plan", "ss_get_plan", "ss_batch_workspace_bytes",
            "ss_batch_create",
            "ss_batch_destroy", "ss_batch_member", "ss_batch_size", "ss_batch_flow_step", "ss_batch_minimise",
-           "ss_batch_set_tile", "ss_batch_autotune", "ss_set_energy_target", "ss_learned_input",
+           "ss_batch_set_tile", "ss_batch_autotune", "ss_batch_set_plan", "ss_batch_get_plan", "ss_set_energy_target", "ss_learned_input",
            "ss_learned_targets", "ss_init_learned"]
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_backward", "ssn_adam_step",
@@ -134,6 +134,8 @@ def lib():
     L.ss_batch_minimise.argtypes = [vp, ctypes.POINTER(ss_stop), ctypes.POINTER(ss_min_info)]
     L.ss_batch_set_tile.argtypes = [vp, i]
     L.ss_batch_autotune.argtypes = [vp, i, dp]
+    L.ss_batch_set_plan.argtypes = [vp, i]
+    L.ss_batch_get_plan.argtypes = [vp]
     _lib = L
     return L
 
@@ -349,10 +351,21 @@ def ss_batch_set_tile(batch, tile):
     _check(lib().ss_batch_set_tile(batch, tile))
 
 
+def ss_batch_set_plan(batch, plan: int):
+    _check(lib().ss_batch_set_plan(batch, plan))
+
+
+def ss_batch_get_plan(batch) -> int:
+    return _check_nonneg(lib().ss_batch_get_plan(batch))
+
+
 def ss_batch_autotune(batch, n_steps=5):
-    ms = (ctypes.c_double * ss_tile_count())()
+    """Returns (tile, plan, ms) with ms[plan][tile] the mean step time (-1: not timed)."""
+    nt = ss_tile_count()
+    ms = (ctypes.c_double * (SS_NUM_PLANS * nt))()
     best = _check_nonneg(lib().ss_batch_autotune(batch, int(n_steps), ms))
-    return best, list(ms)
+    grid = [list(ms[p * nt:(p + 1) * nt]) for p in range(SS_NUM_PLANS)]
+    return best, ss_batch_get_plan(batch), grid
 
 
 # ------------------------------------------------------------ convenience
@@ -504,6 +517,13 @@ class Batch:
 
     def autotune(self, n_steps=5):
         return ss_batch_autotune(self.batch, n_steps)
+
+    def set_plan(self, plan):
+        ss_batch_set_plan(self.batch, plan)
+
+    @property
+    def plan(self):
+        return ss_batch_get_plan(self.batch)
 
     def close(self):
         if getattr(self, "batch", None) is not None:

@@ -891,6 +891,7 @@ double ss_gl_lambda_from_kappa(double kappa) { return 2.0 * kappa * kappa; }
 
 struct ss_batch {
   int theory, dtype, C, n, tile;
+  int plan;  // SS_PLAN_*; the fused pass runs on the tile shape of FusedTile only
   hipStream_t stream;
   hipStream_t cap_stream;
   std::vector<ss_ctx*> members;
@@ -1044,9 +1045,35 @@ void batch_launch(const ss_batch* b, hipStream_t s) {
 }
 
 template <class T>
+bool batch_fused(const ss_batch* b) {
+  return b->plan == SS_PLAN_FUSED && b->tile == FusedTile<T>::layout_tile;
+}
+
+template <class T>
+void batch_launch_fused(const ss_batch* b, hipStream_t s) {
+  BatchArgs<T> a;
+  a.inst = (const BatchInst<T>*)b->inst;
+  a.work = b->work;
+  a.nwork = b->nwork;
+  a.tile_inst = b->tile_inst;
+  a.partials = b->partials;
+  const int nlaunch = (int)std::min<long>(round_up(b->ntiles_total, 8), kMaxGroups);
+  constexpr int TY = FusedTile<T>::TY;
+  if (b->theory == SS_THEORY_AH)
+    hipLaunchKernelGGL((batch_pass_fused<T, 0, 64, TY, 2>), dim3(nlaunch), dim3(64, TY / 2), 0, s, a);
+  else
+    hipLaunchKernelGGL((batch_pass_fused<T, 1, 64, TY, 2>), dim3(nlaunch), dim3(64, TY / 2), 0, s, a);
+}
+
+template <class T>
 void batch_enqueue_steps(const ss_batch* b, int n, hipStream_t s) {
+  const bool fused = batch_fused<T>(b);
   for (int k = 0; k < n; ++k) {
     batch_launch<T, kP1>(b, s);
+    if (fused) {
+      batch_launch_fused<T>(b, s);
+      continue;
+    }
     batch_launch<T, kP2>(b, s);
     batch_launch<T, kP3>(b, s);
     batch_launch<T, kP4>(b, s);
@@ -1126,6 +1153,7 @@ int ss_batch_create(const char* theory, int n, const ss_instance* inst, int dtyp
   b->C = b->theory == SS_THEORY_AH ? 4 : 3;
   b->n = n;
   b->tile = kDefaultTile;
+  b->plan = SS_PLAN_FUSED;
   b->stream = (hipStream_t)stream;
   b->graph = nullptr;
   b->graph_steps = 0;
@@ -1208,6 +1236,20 @@ int ss_batch_set_tile(ss_batch* b, int tile) {
   b->tile = tile;
   return batch_build_tables(b);
 }
+
+int ss_batch_set_plan(ss_batch* b, int plan) {
+  if (!b) return fail(SS_EINVAL, "batch is NULL");
+  if (plan < 0 || plan >= SS_NUM_PLANS) return fail(SS_EINVAL, "unknown plan");
+  SS_HIP(hipStreamSynchronize(b->stream));
+  b->plan = plan;
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  return SS_OK;
+}
+
+int ss_batch_get_plan(ss_batch* b) { return b ? b->plan : SS_EINVAL; }
 
 int ss_batch_flow_step(ss_batch* b, int n_steps, ss_step_info* infos) {
   if (!b || n_steps < 0) return fail(SS_EINVAL, "bad arguments");
@@ -1302,33 +1344,44 @@ int ss_batch_autotune(ss_batch* b, int n_steps, double* ms_out) {
     }
     if (rc) return rc;
   }
-  int best = b->tile;
+  if (ms_out)
+    for (int k = 0; k < SS_NUM_PLANS * kNumTiles; ++k) ms_out[k] = -1.0;
+  const int fused_tile = b->dtype == SS_F32 ? FusedTile<float>::layout_tile : FusedTile<double>::layout_tile;
+  int best = b->tile, best_plan = b->plan;
   double best_ms = 1e300;
   hipEvent_t e0, e1;
   SS_HIP(hipEventCreate(&e0));
   SS_HIP(hipEventCreate(&e1));
-  for (int t = 0; t < kNumTiles; ++t) {
-    int rc = ss_batch_set_tile(b, t);
-    if (rc) return rc;
-    hipLaunchKernelGGL(batch_arm, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->st_ptrs, b->n, 0, 0.0, 0.0,
-                       0, 0LL);
-    batch_enqueue_steps_any(b, 2, b->stream);
-    SS_HIP(hipEventRecord(e0, b->stream));
-    batch_enqueue_steps_any(b, n_steps, b->stream);
-    SS_HIP(hipEventRecord(e1, b->stream));
-    SS_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    SS_HIP(hipEventElapsedTime(&ms, e0, e1));
-    const double per = ms / n_steps;
-    if (ms_out) ms_out[t] = per;
-    if (per < best_ms) {
-      best_ms = per;
-      best = t;
+  for (int p = 0; p < SS_NUM_PLANS; ++p) {
+    for (int t = 0; t < kNumTiles; ++t) {
+      if (p == SS_PLAN_FUSED && t != fused_tile) continue;  // the fused pass has one tile shape
+      int rc = ss_batch_set_plan(b, p);
+      if (rc) return rc;
+      rc = ss_batch_set_tile(b, t);
+      if (rc) return rc;
+      hipLaunchKernelGGL(batch_arm, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->st_ptrs, b->n, 0, 0.0,
+                         0.0, 0, 0LL);
+      batch_enqueue_steps_any(b, 2, b->stream);
+      SS_HIP(hipEventRecord(e0, b->stream));
+      batch_enqueue_steps_any(b, n_steps, b->stream);
+      SS_HIP(hipEventRecord(e1, b->stream));
+      SS_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SS_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double per = ms / n_steps;
+      if (ms_out) ms_out[p * kNumTiles + t] = per;
+      if (per < best_ms) {
+        best_ms = per;
+        best = t;
+        best_plan = p;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  int rc = ss_batch_set_tile(b, best);
+  int rc = ss_batch_set_plan(b, best_plan);
+  if (rc) return rc;
+  rc = ss_batch_set_tile(b, best);
   if (rc) return rc;
   for (ss_ctx* c : b->members) {
     rc = reset_state(c);

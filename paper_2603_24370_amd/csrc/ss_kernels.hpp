@@ -1264,6 +1264,28 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
   }
 }
 
+// Fused stages 2-4 for the batch: the work list's tiles, each with its member's
+// arrest flag and step parity (members that stopped are skipped).
+template <class T, int TH, int TX, int TY, int RY>
+__global__ void __launch_bounds__(TX*(TY / RY)) batch_pass_fused(BatchArgs<T> a) {
+  __shared__ __align__(16) T lds[FusedLds<T, TH, TX, TY>::value];
+  const int nwork = *a.nwork;
+  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, qb = blockIdx.x >> 3;
+  const int per = (nwork + 7) >> 3;
+  const int wend = min(nwork, (xcd + 1) * per);
+  for (int w = xcd * per + qb; w < wend; w += m) {
+    const int g = a.work[w];
+    const BatchInst<T>& I = a.inst[a.tile_inst[g]];
+    const DevStatus* __restrict__ st = I.st;
+    if (st->done) continue;
+    const int cur = int((st->step - 1) & 1);
+    const bool arrest = st->arrest != 0;
+    const int l = g - I.tile0;
+    const int tyi = l / I.ntx;
+    tile_body_fused<T, TH, TX, TY, RY>(I.V, cur, arrest, (l - tyi * I.ntx) * TX, tyi * TY, lds);
+  }
+}
+
 // Zero the velocity of every batch member whose last arrest test fired.
 template <class T>
 __global__ void __launch_bounds__(256) batch_apply_arrest(const BatchInst<T>* inst, int C) {
