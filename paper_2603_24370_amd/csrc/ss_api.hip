@@ -52,7 +52,7 @@ constexpr int kDefaultTile = 0;
 constexpr int kDefaultPlanF32 = SS_PLAN_FUSED;
 static_assert(kTiles[0].TX == kExTX && kTiles[0].TY == kExTY, "the exact-gradient passes use the layout of tile 0");
 static_assert(kTiles[0].TX == 64 && kTiles[0].TY == 16 && kTiles[1].TX == 64 && kTiles[1].TY == 8,
-              "the fused passes use the layouts of tiles 0 (FP32) and 1 (FP64)");
+              "the fused passes use the layouts of tiles 0 (64 x 16) and 1 (64 x 8)");
 constexpr int kDefaultGraphSteps = 16;
 constexpr long kMaxGroups = 2048;  // persistent launch: at most 8 workgroups per CU
 
@@ -214,30 +214,38 @@ void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   else launch_pass_t<T, 1, PASS>(c->tile, a, c->L.nlaunch, s);
 }
 
-// Fused stages 2-4: FP32 on the 64 x 16 tiling of tile 0, FP64 on the 64 x 8
-// tiling of tile 1 (its LDS planes are twice as large); two rows per thread.
+// Fused stages 2-4 run on 64 x 16 tiles (tile 0) or 64 x 8 tiles (tile 1), two
+// rows per thread. FP32 follows the context's tile when it is one of these two
+// (so the autotuner can pick either) and uses 64 x 16 otherwise; FP64 always
+// uses 64 x 8 (its LDS planes are twice as large).
 template <class T>
-struct FusedTile {
-  static constexpr int TY = sizeof(T) == 4 ? 16 : 8;
-  static constexpr int layout_tile = sizeof(T) == 4 ? 0 : 1;
-};
+int fused_layout_tile(int tile) {
+  if (sizeof(T) == 8) return 1;
+  return tile == 1 ? 1 : 0;
+}
 
 template <class T, int TH>
-void launch_fused_t(const PassArgs<T>& a, int nlaunch, hipStream_t s) {
-  constexpr int TY = FusedTile<T>::TY;
-  hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, TY, 2>), dim3(nlaunch), dim3(64, TY / 2), 0, s, a);
+void launch_fused_t(int layout_tile, const PassArgs<T>& a, int nlaunch, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (layout_tile == 0) {
+      hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, 16, 2>), dim3(nlaunch), dim3(64, 8), 0, s, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((stage_pass_fused<T, TH, 64, 8, 2>), dim3(nlaunch), dim3(64, 4), 0, s, a);
 }
 
 template <class T>
 void launch_fused(const ss_ctx* c, hipStream_t s) {
   PassArgs<T> a = pass_args<T>(c);
   Layout L = c->L;
-  set_tiles(L, c->Nx, c->Ny, FusedTile<T>::layout_tile);
+  const int lt = fused_layout_tile<T>(c->tile);
+  set_tiles(L, c->Nx, c->Ny, lt);
   a.ntx = L.ntx;
   a.nty = L.nty;
   a.seg = L.seg;
-  if (c->theory == SS_THEORY_AH) launch_fused_t<T, 0>(a, L.nlaunch, s);
-  else launch_fused_t<T, 1>(a, L.nlaunch, s);
+  if (c->theory == SS_THEORY_AH) launch_fused_t<T, 0>(lt, a, L.nlaunch, s);
+  else launch_fused_t<T, 1>(lt, a, L.nlaunch, s);
 }
 
 template <class T>
@@ -891,7 +899,7 @@ double ss_gl_lambda_from_kappa(double kappa) { return 2.0 * kappa * kappa; }
 
 struct ss_batch {
   int theory, dtype, C, n, tile;
-  int plan;  // SS_PLAN_*; the fused pass runs on the tile shape of FusedTile only
+  int plan;  // SS_PLAN_*; the fused pass runs on tiles 0 and 1 only (see batch_fused)
   hipStream_t stream;
   hipStream_t cap_stream;
   std::vector<ss_ctx*> members;
@@ -1046,7 +1054,7 @@ void batch_launch(const ss_batch* b, hipStream_t s) {
 
 template <class T>
 bool batch_fused(const ss_batch* b) {
-  return b->plan == SS_PLAN_FUSED && b->tile == FusedTile<T>::layout_tile;
+  return b->plan == SS_PLAN_FUSED && b->tile == fused_layout_tile<T>(b->tile);
 }
 
 template <class T>
@@ -1058,11 +1066,20 @@ void batch_launch_fused(const ss_batch* b, hipStream_t s) {
   a.tile_inst = b->tile_inst;
   a.partials = b->partials;
   const int nlaunch = (int)std::min<long>(round_up(b->ntiles_total, 8), kMaxGroups);
-  constexpr int TY = FusedTile<T>::TY;
+  // the batch's tile is 64 x 16 (tile 0, FP32 only) or 64 x 8 (tile 1); see batch_fused
+  if constexpr (sizeof(T) == 4) {
+    if (b->tile == 0) {
+      if (b->theory == SS_THEORY_AH)
+        hipLaunchKernelGGL((batch_pass_fused<T, 0, 64, 16, 2>), dim3(nlaunch), dim3(64, 8), 0, s, a);
+      else
+        hipLaunchKernelGGL((batch_pass_fused<T, 1, 64, 16, 2>), dim3(nlaunch), dim3(64, 8), 0, s, a);
+      return;
+    }
+  }
   if (b->theory == SS_THEORY_AH)
-    hipLaunchKernelGGL((batch_pass_fused<T, 0, 64, TY, 2>), dim3(nlaunch), dim3(64, TY / 2), 0, s, a);
+    hipLaunchKernelGGL((batch_pass_fused<T, 0, 64, 8, 2>), dim3(nlaunch), dim3(64, 4), 0, s, a);
   else
-    hipLaunchKernelGGL((batch_pass_fused<T, 1, 64, TY, 2>), dim3(nlaunch), dim3(64, TY / 2), 0, s, a);
+    hipLaunchKernelGGL((batch_pass_fused<T, 1, 64, 8, 2>), dim3(nlaunch), dim3(64, 4), 0, s, a);
 }
 
 template <class T>
@@ -1346,7 +1363,7 @@ int ss_batch_autotune(ss_batch* b, int n_steps, double* ms_out) {
   }
   if (ms_out)
     for (int k = 0; k < SS_NUM_PLANS * kNumTiles; ++k) ms_out[k] = -1.0;
-  const int fused_tile = b->dtype == SS_F32 ? FusedTile<float>::layout_tile : FusedTile<double>::layout_tile;
+
   int best = b->tile, best_plan = b->plan;
   double best_ms = 1e300;
   hipEvent_t e0, e1;
@@ -1354,7 +1371,9 @@ int ss_batch_autotune(ss_batch* b, int n_steps, double* ms_out) {
   SS_HIP(hipEventCreate(&e1));
   for (int p = 0; p < SS_NUM_PLANS; ++p) {
     for (int t = 0; t < kNumTiles; ++t) {
-      if (p == SS_PLAN_FUSED && t != fused_tile) continue;  // the fused pass has one tile shape
+      // the fused pass runs on tiles 0 and 1 in FP32 and tile 1 in FP64
+      if (p == SS_PLAN_FUSED && t != (b->dtype == SS_F32 ? fused_layout_tile<float>(t) : fused_layout_tile<double>(t)))
+        continue;
       int rc = ss_batch_set_plan(b, p);
       if (rc) return rc;
       rc = ss_batch_set_tile(b, t);

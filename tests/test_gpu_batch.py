@@ -36,11 +36,10 @@ def _np(t):
 
 
 # (plan, tile): the fused pass runs on tile 0 in FP32 and tile 1 in FP64
-BATCH_PLANS = {"f32": [(0, 0), (1, 0)], "f64": [(0, 0), (1, 1)]}
+BATCH_PLANS = {"f32": [(0, 0), (1, 0), (1, 1)], "f64": [(0, 0), (1, 1)]}
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("dtype,which", [("f64", 0), ("f64", 1), ("f32", 0), ("f32", 1), ("f32", 2)])
 def test_batch_flow_matches_oracle_per_member(ss, orc, dtype, which):
     plan, tile = BATCH_PLANS[dtype][which]
     insts = _members(0, 6, sides=[40, 71, 96, 33, 128, 64])
@@ -102,7 +101,7 @@ def test_batch_tiles_and_autotune(ss, orc):
     best, plan, ms = B.autotune(2)
     timed = [m for row in ms for m in row if m >= 0]
     assert 0 <= best < ss.ss_tile_count() and ms[plan][best] == min(timed)
-    assert len(timed) == ss.ss_tile_count() + 1  # every tile for the stages plan, one for the fused
+    assert len(timed) == ss.ss_tile_count() + 2  # every tile for the stages plan, tiles 0 and 1 fused
     B.set_plan(0)
     for tile in range(ss.ss_tile_count()):
         B.set_tile(tile)

@@ -371,7 +371,8 @@ PLANS = [("stages", 0), ("fused", 1)]
 @pytest.mark.parametrize("theory", [AH, CM])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(150, 37), (64, 16), (8, 8), (129, 70)])
-def test_every_plan_tracks_the_oracle(ss, plan_name, plan, theory, dtype, shape, orc):
+@pytest.mark.parametrize("tile", [0, 1])
+def test_every_plan_tracks_the_oracle(ss, plan_name, plan, theory, dtype, shape, tile, orc):
     """Each launch plan of a step (separate stage passes, fused stages 2-4) gives
     the oracle's flow: FP64 to rounding, FP32 within the FP32 trajectory bound;
     arrests and steps agree exactly."""
@@ -383,6 +384,7 @@ def test_every_plan_tracks_the_oracle(ss, plan_name, plan, theory, dtype, shape,
         f = f.astype(np.float32).astype(np.float64)
     s = _solver(ss, theory, f, h, dtype)
     s.set_plan(plan)
+    s.set_tile(tile)  # the fused pass follows tiles 0 (64 x 16) and 1 (64 x 8) in FP32
     assert s.plan == plan
     s.set_field(f)
     n = 5
