@@ -15,10 +15,13 @@
  * with FP32 accumulation; master weights, gradients and Adam moments FP32;
  * reductions in fixed order (a run is bitwise repeatable).
  *
- * Launch shape: a convolution runs in workgroups of 4 waves (64 pixels per
- * wave) when that gives at least 1024 workgroups, else in single-wave
- * workgroups of 32 pixels (few images, deep levels). The environment variable
- * SSN_CONV_SHAPE, read by ssn_create, forces one (1: large, 2: small).
+ * Launch shape: a convolution runs as an LDS-tiled GEMM (input patch and
+ * weights staged per 32 input channels) where image rows are at least 32
+ * pixels wide and that gives at least 256 workgroups; otherwise its MFMA
+ * operands are read directly, in workgroups of 4 waves (64 pixels per wave)
+ * when that gives at least 1024 workgroups, else of one wave (32 pixels). The
+ * environment variable SSN_CONV_SHAPE, read by ssn_create, forces one
+ * (1: direct large, 2: direct small, 3: tiled where rows allow it).
  *
  * Memory: images are fp32 device arrays (n, H, W, channels) row-major. The
  * caller owns the workspace (ssn_workspace_bytes, 256-byte aligned) and all

@@ -148,6 +148,89 @@ __global__ void __launch_bounds__(64 * WB) conv3x3_mfma(ConvArgs a) {
   }
 }
 
+// LDS-tiled implicit GEMM for the larger layers. Block: WCO x WPX waves; wave
+// (i, j) computes 32 output channels (co0 + 32 i ..) x 32 pixels (x0 + 32 j ..) of
+// one image row. Input channels are taken in chunks of 32: the chunk's input
+// patch (3 rows x (32 WPX + 2) pixels, zero outside the image) and its weights
+// (32 WCO rows x 9 taps) are staged in LDS, each entry padded to kKP channels
+// so that lanes reading neighbouring pixels or rows fall in different banks;
+// every MFMA then takes both operands from LDS. Requires W % (32 WPX) == 0,
+// in.C % 16 == 0 and, for WCO = 2, Co % 64 == 0 (weight rows exist up to
+// gridDim.y * 32 WCO).
+constexpr int kKC = 32, kKP = 40;
+
+template <int WCO, int WPX>
+__global__ void __launch_bounds__(64 * WCO * WPX) conv3x3_tiled(ConvArgs a) {
+  constexpr int NT = 64 * WCO * WPX, PX = 32 * WPX, PW = PX + 2, CO = 32 * WCO;
+  __shared__ __align__(16) bf16_t sin_[3 * PW * kKP];
+  __shared__ __align__(16) bf16_t sw[9 * CO * kKP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave / WPX, wj = wave - wi * WPX;
+  const int r = lane & 31, half = lane >> 5;
+  const int H = a.in.H, W = a.in.W, Ci = a.in.C;
+  const int xt = W / PX;
+  const int bx = blockIdx.x;
+  const int n = bx / (H * xt);
+  const int rem = bx - n * H * xt;
+  const int y = rem / xt;
+  const int x0 = (rem - y * xt) * PX;
+  const int co0 = blockIdx.y * CO;
+  bf16x8 zero;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) zero[j] = (__bf16)0.0f;
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  for (int c0 = 0; c0 < Ci; c0 += kKC) {
+    const int kc = min(kKC, Ci - c0);  // 32, or 16 for the last chunk
+    const int nv = kc >> 3;            // 16-byte vectors per entry
+    __syncthreads();
+    for (int it = tid; it < 3 * PW * nv; it += NT) {
+      const int v = it % nv, q = it / nv;
+      const int px = q % PW, row = q / PW;
+      const int yy = y + row - 1, xx = x0 + px - 1;
+      bf16x8 val = zero;
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+        val = *reinterpret_cast<const bf16x8*>(a.in.p + tv_at(a.in, n, yy, xx) + c0 + v * 8);
+      *reinterpret_cast<bf16x8*>(sin_ + (row * PW + px) * kKP + v * 8) = val;
+    }
+    for (int it = tid; it < CO * 9 * nv; it += NT) {
+      const int v = it % nv, q = it / nv;
+      const int t = q % 9, co = q / 9;
+      const bf16x8 val = *reinterpret_cast<const bf16x8*>(a.w + ((long)(co0 + co) * 9 + t) * Ci + c0 + v * 8);
+      *reinterpret_cast<bf16x8*>(sw + (t * CO + co) * kKP + v * 8) = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3, dx = t % 3;
+      for (int ks = 0; ks < kc; ks += 16) {
+        const bf16x8 A = *reinterpret_cast<const bf16x8*>(sw + (t * CO + wi * 32 + r) * kKP + ks + half * 8);
+        const bf16x8 B = *reinterpret_cast<const bf16x8*>(sin_ + (dy * PW + wj * 32 + r + dx) * kKP + ks + half * 8);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc, 0, 0, 0);
+      }
+    }
+  }
+  // D[row][col]: lane holds col = r (pixel) and rows 8 (v / 4) + 4 half + v % 4 (channels)
+  const int x = x0 + wj * 32 + r;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int co = co0 + wi * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
+    if (co >= a.Co) continue;
+    float val = acc[v];
+    if (a.mode == 0) {
+      const float z = val + (a.bias ? a.bias[co] : 0.0f);
+      if (a.out_z.p) a.out_z.p[tv_at(a.out_z, n, y, x) + co] = f2bf(z);
+      a.out.p[tv_at(a.out, n, y, x) + co] = f2bf(silu_f(z));
+    } else {
+      if (a.zprev.p) val *= silu_grad_f(bf2f(a.zprev.p[tv_at(a.zprev, n, y, x) + co]));
+      bf16_t* o = a.out.p + tv_at(a.out, n, y, x) + co;
+      if (a.accumulate) val += bf2f(*o);
+      *o = f2bf(val);
+    }
+  }
+}
+
 // Weight gradient: part[split][co][t][ci] = sum over this split's pixel chunks of
 // gz[pix][co] * x[pix + d_t][ci]. Block = 9 waves (one per tap), tile 32 co x 32 ci.
 // A chunk is cw pixels of one image row (cw = 64 or W); its gz rows and the
@@ -485,7 +568,7 @@ constexpr long kWgradPartFloats = 1024L * 9 * 1024;
 
 struct ssn_net {
   int levels, base, cin, cout, cin_pad, Ncap, H, W, L;
-  int conv_shape;  // 0: by problem size, 1: large workgroups, 2: small workgroups
+  int conv_shape;  // 0: by problem size, 1: large direct blocks, 2: small direct blocks, 3: LDS-tiled
   hipStream_t stream;
   float *P, *G, *M, *V;
   long np;
@@ -605,12 +688,38 @@ int dec_b(const ssn_net* n, int l) { return dec_a(n, l) + 1; }
 
 int grid1(long n) { return (int)std::min<long>((n + 255) / 256, 65535); }
 
-// Large problems: blocks of 4 waves, 64 pixels per wave. Small ones (few images,
-// deep levels) would leave most CUs idle that way: one wave per block and 32
-// pixels per wave give 8x more workgroups.
+template <int WCO, int WPX>
+void launch_tiled(const ssn_net* n, const ConvArgs& ca, int Co) {
+  const TV& in = ca.in;
+  dim3 grid((unsigned)((long)in.N * in.H * (in.W / (32 * WPX))), (unsigned)((Co + 32 * WCO - 1) / (32 * WCO)));
+  hipLaunchKernelGGL((conv3x3_tiled<WCO, WPX>), grid, dim3(64 * WCO * WPX), 0, n->stream, ca);
+}
+
+// Launch shapes: the LDS-tiled GEMM where rows are at least 32 pixels wide and
+// the grid has at least 256 workgroups; otherwise direct-operand blocks of 4
+// waves with 64 pixels per wave (large grids) or of one wave with 32 pixels
+// (few images, deep levels: 8x more workgroups).
 void launch_conv(const ssn_net* n, const ConvArgs& ca, long P, int Co) {
   const unsigned gy = (unsigned)((Co + 31) / 32);
-  const bool large = n->conv_shape == 1 || (n->conv_shape == 0 && (P + 255) / 256 * gy >= 1024);
+  const int W = ca.in.W;
+  const int wpx = W >= 128 ? 4 : W >= 64 ? 2 : 1;
+  const int wco = Co % 64 == 0 ? 2 : 1;
+  const long tiled_blocks = (long)ca.in.N * ca.in.H * (W / (32 * wpx)) * ((Co + 32 * wco - 1) / (32 * wco));
+  const bool tiled_ok = W >= 32 && W % (32 * wpx) == 0;
+  const bool tiled = tiled_ok && (n->conv_shape == 3 || (n->conv_shape == 0 && tiled_blocks >= 256));
+  if (tiled) {
+    if (wco == 2) {
+      if (wpx == 4) launch_tiled<2, 4>(n, ca, Co);
+      else if (wpx == 2) launch_tiled<2, 2>(n, ca, Co);
+      else launch_tiled<2, 1>(n, ca, Co);
+    } else {
+      if (wpx == 4) launch_tiled<1, 4>(n, ca, Co);
+      else if (wpx == 2) launch_tiled<1, 2>(n, ca, Co);
+      else launch_tiled<1, 1>(n, ca, Co);
+    }
+    return;
+  }
+  const bool large = n->conv_shape == 1 || (n->conv_shape != 2 && (P + 255) / 256 * gy >= 1024);
   if (large) {
     dim3 grid((unsigned)((P + 255) / 256), gy);
     hipLaunchKernelGGL((conv3x3_mfma<2, 4>), grid, dim3(256), 0, n->stream, ca);
@@ -866,7 +975,7 @@ int ssn_create(int levels, int base, int cin, int cout, int N, int H, int W, voi
   n->conv_shape = 0;
   if (const char* env = std::getenv("SSN_CONV_SHAPE")) {
     const int v = std::atoi(env);
-    if (v >= 0 && v <= 2) n->conv_shape = v;
+    if (v >= 0 && v <= 3) n->conv_shape = v;
   }
   net_layers(n);
   n->bytes = net_carve(n, (char*)ws);

@@ -72,7 +72,7 @@ def _bf16(a):
     return u.view(np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("shape", ["1", "2"])
+@pytest.mark.parametrize("shape", ["1", "2", "3"])
 def test_forward_matches_oracle(ss, shape, monkeypatch):
     monkeypatch.setenv("SSN_CONV_SHAPE", shape)
     P, x, t, net = _setup(ss)
@@ -83,7 +83,7 @@ def test_forward_matches_oracle(ss, shape, monkeypatch):
     net.close()
 
 
-@pytest.mark.parametrize("shape", ["1", "2"])
+@pytest.mark.parametrize("shape", ["1", "2", "3"])
 def test_backward_matches_oracle(ss, shape, monkeypatch):
     monkeypatch.setenv("SSN_CONV_SHAPE", shape)
     P, x, t, net = _setup(ss, seed=1)
