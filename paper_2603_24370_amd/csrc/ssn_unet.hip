@@ -148,47 +148,50 @@ __global__ void __launch_bounds__(64 * WB) conv3x3_mfma(ConvArgs a) {
   }
 }
 
-// LDS-tiled implicit GEMM for the larger layers. Block: WCO x WPX waves; wave
-// (i, j) computes 32 output channels (co0 + 32 i ..) x 32 pixels (x0 + 32 j ..) of
-// one image row. Input channels are taken in chunks of 32: the chunk's input
-// patch (3 rows x (32 WPX + 2) pixels, zero outside the image) and its weights
-// (32 WCO rows x 9 taps) are staged in LDS, each entry padded to kKP channels
-// so that lanes reading neighbouring pixels or rows fall in different banks;
-// every MFMA then takes both operands from LDS. Requires W % (32 WPX) == 0,
-// in.C % 16 == 0 and, for WCO = 2, Co % 64 == 0 (weight rows exist up to
-// gridDim.y * 32 WCO).
+// LDS-tiled implicit GEMM for the larger layers. Block: WCO x WPX waves over R
+// image rows; wave (i, j) computes 32 output channels (co0 + 32 i ..) x 32 pixels
+// (x0 + 32 j ..) of each of the rows y0 .. y0 + R - 1. Input channels are taken
+// in chunks of 32: the chunk's input patch (R + 2 rows x (32 WPX + 2) pixels,
+// zero outside the image) and its weights (32 WCO rows x 9 taps) are staged in
+// LDS, each entry padded to kKP channels so that lanes reading neighbouring
+// pixels or rows fall in different banks; every MFMA takes both operands from
+// LDS and each weight fragment serves R rows. Requires W % (32 WPX) == 0,
+// H % R == 0, in.C % 16 == 0 and, for WCO = 2, Co % 64 == 0 (weight rows exist
+// up to gridDim.y * 32 WCO).
 constexpr int kKC = 32, kKP = 40;
 
-template <int WCO, int WPX>
+template <int WCO, int WPX, int R>
 __global__ void __launch_bounds__(64 * WCO * WPX) conv3x3_tiled(ConvArgs a) {
-  constexpr int NT = 64 * WCO * WPX, PX = 32 * WPX, PW = PX + 2, CO = 32 * WCO;
-  __shared__ __align__(16) bf16_t sin_[3 * PW * kKP];
+  constexpr int NT = 64 * WCO * WPX, PX = 32 * WPX, PW = PX + 2, CO = 32 * WCO, PR = R + 2;
+  __shared__ __align__(16) bf16_t sin_[PR * PW * kKP];
   __shared__ __align__(16) bf16_t sw[9 * CO * kKP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave / WPX, wj = wave - wi * WPX;
   const int r = lane & 31, half = lane >> 5;
   const int H = a.in.H, W = a.in.W, Ci = a.in.C;
-  const int xt = W / PX;
+  const int xt = W / PX, yt = H / R;
   const int bx = blockIdx.x;
-  const int n = bx / (H * xt);
-  const int rem = bx - n * H * xt;
-  const int y = rem / xt;
-  const int x0 = (rem - y * xt) * PX;
+  const int n = bx / (yt * xt);
+  const int rem = bx - n * yt * xt;
+  const int y0 = (rem / xt) * R;
+  const int x0 = (rem - (rem / xt) * xt) * PX;
   const int co0 = blockIdx.y * CO;
   bf16x8 zero;
 #pragma unroll
   for (int j = 0; j < 8; ++j) zero[j] = (__bf16)0.0f;
-  f32x16 acc;
+  f32x16 acc[R];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[q][v] = 0.0f;
   for (int c0 = 0; c0 < Ci; c0 += kKC) {
     const int kc = min(kKC, Ci - c0);  // 32, or 16 for the last chunk
     const int nv = kc >> 3;            // 16-byte vectors per entry
     __syncthreads();
-    for (int it = tid; it < 3 * PW * nv; it += NT) {
+    for (int it = tid; it < PR * PW * nv; it += NT) {
       const int v = it % nv, q = it / nv;
       const int px = q % PW, row = q / PW;
-      const int yy = y + row - 1, xx = x0 + px - 1;
+      const int yy = y0 + row - 1, xx = x0 + px - 1;
       bf16x8 val = zero;
       if (yy >= 0 && yy < H && xx >= 0 && xx < W)
         val = *reinterpret_cast<const bf16x8*>(a.in.p + tv_at(a.in, n, yy, xx) + c0 + v * 8);
@@ -206,27 +209,35 @@ __global__ void __launch_bounds__(64 * WCO * WPX) conv3x3_tiled(ConvArgs a) {
       const int dy = t / 3, dx = t % 3;
       for (int ks = 0; ks < kc; ks += 16) {
         const bf16x8 A = *reinterpret_cast<const bf16x8*>(sw + (t * CO + wi * 32 + r) * kKP + ks + half * 8);
-        const bf16x8 B = *reinterpret_cast<const bf16x8*>(sin_ + (dy * PW + wj * 32 + r + dx) * kKP + ks + half * 8);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const bf16x8 B =
+              *reinterpret_cast<const bf16x8*>(sin_ + ((q + dy) * PW + wj * 32 + r + dx) * kKP + ks + half * 8);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[q], 0, 0, 0);
+        }
       }
     }
   }
   // D[row][col]: lane holds col = r (pixel) and rows 8 (v / 4) + 4 half + v % 4 (channels)
   const int x = x0 + wj * 32 + r;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int co = co0 + wi * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
-    if (co >= a.Co) continue;
-    float val = acc[v];
-    if (a.mode == 0) {
-      const float z = val + (a.bias ? a.bias[co] : 0.0f);
-      if (a.out_z.p) a.out_z.p[tv_at(a.out_z, n, y, x) + co] = f2bf(z);
-      a.out.p[tv_at(a.out, n, y, x) + co] = f2bf(silu_f(z));
-    } else {
-      if (a.zprev.p) val *= silu_grad_f(bf2f(a.zprev.p[tv_at(a.zprev, n, y, x) + co]));
-      bf16_t* o = a.out.p + tv_at(a.out, n, y, x) + co;
-      if (a.accumulate) val += bf2f(*o);
-      *o = f2bf(val);
+  for (int q = 0; q < R; ++q) {
+    const int y = y0 + q;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int co = co0 + wi * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
+      if (co >= a.Co) continue;
+      float val = acc[q][v];
+      if (a.mode == 0) {
+        const float z = val + (a.bias ? a.bias[co] : 0.0f);
+        if (a.out_z.p) a.out_z.p[tv_at(a.out_z, n, y, x) + co] = f2bf(z);
+        a.out.p[tv_at(a.out, n, y, x) + co] = f2bf(silu_f(z));
+      } else {
+        if (a.zprev.p) val *= silu_grad_f(bf2f(a.zprev.p[tv_at(a.zprev, n, y, x) + co]));
+        bf16_t* o = a.out.p + tv_at(a.out, n, y, x) + co;
+        if (a.accumulate) val += bf2f(*o);
+        *o = f2bf(val);
+      }
     }
   }
 }
@@ -688,34 +699,37 @@ int dec_b(const ssn_net* n, int l) { return dec_a(n, l) + 1; }
 
 int grid1(long n) { return (int)std::min<long>((n + 255) / 256, 65535); }
 
-template <int WCO, int WPX>
+template <int WCO, int WPX, int R>
 void launch_tiled(const ssn_net* n, const ConvArgs& ca, int Co) {
   const TV& in = ca.in;
-  dim3 grid((unsigned)((long)in.N * in.H * (in.W / (32 * WPX))), (unsigned)((Co + 32 * WCO - 1) / (32 * WCO)));
-  hipLaunchKernelGGL((conv3x3_tiled<WCO, WPX>), grid, dim3(64 * WCO * WPX), 0, n->stream, ca);
+  dim3 grid((unsigned)((long)in.N * (in.H / R) * (in.W / (32 * WPX))), (unsigned)((Co + 32 * WCO - 1) / (32 * WCO)));
+  hipLaunchKernelGGL((conv3x3_tiled<WCO, WPX, R>), grid, dim3(64 * WCO * WPX), 0, n->stream, ca);
 }
 
 // Launch shapes: the LDS-tiled GEMM where rows are at least 32 pixels wide and
-// the grid has at least 256 workgroups; otherwise direct-operand blocks of 4
-// waves with 64 pixels per wave (large grids) or of one wave with 32 pixels
-// (few images, deep levels: 8x more workgroups).
+// the grid has at least 256 workgroups (2 rows per workgroup on rows of 128 or
+// more pixels, 4 on narrower ones); otherwise direct-operand blocks of 4 waves
+// with 64 pixels per wave (large grids) or of one wave with 32 pixels (few
+// images, deep levels: 8x more workgroups).
 void launch_conv(const ssn_net* n, const ConvArgs& ca, long P, int Co) {
   const unsigned gy = (unsigned)((Co + 31) / 32);
-  const int W = ca.in.W;
+  const int W = ca.in.W, H = ca.in.H;
   const int wpx = W >= 128 ? 4 : W >= 64 ? 2 : 1;
   const int wco = Co % 64 == 0 ? 2 : 1;
-  const long tiled_blocks = (long)ca.in.N * ca.in.H * (W / (32 * wpx)) * ((Co + 32 * wco - 1) / (32 * wco));
-  const bool tiled_ok = W >= 32 && W % (32 * wpx) == 0;
+  const int R = wpx == 4 ? 2 : 4;
+  const long tiled_blocks =
+      (long)ca.in.N * (H / R) * (W / (32 * wpx)) * ((Co + 32 * wco - 1) / (32 * wco));
+  const bool tiled_ok = W >= 32 && W % (32 * wpx) == 0 && H % R == 0;
   const bool tiled = tiled_ok && (n->conv_shape == 3 || (n->conv_shape == 0 && tiled_blocks >= 256));
   if (tiled) {
     if (wco == 2) {
-      if (wpx == 4) launch_tiled<2, 4>(n, ca, Co);
-      else if (wpx == 2) launch_tiled<2, 2>(n, ca, Co);
-      else launch_tiled<2, 1>(n, ca, Co);
+      if (wpx == 4) launch_tiled<2, 4, 2>(n, ca, Co);
+      else if (wpx == 2) launch_tiled<2, 2, 4>(n, ca, Co);
+      else launch_tiled<2, 1, 4>(n, ca, Co);
     } else {
-      if (wpx == 4) launch_tiled<1, 4>(n, ca, Co);
-      else if (wpx == 2) launch_tiled<1, 2>(n, ca, Co);
-      else launch_tiled<1, 1>(n, ca, Co);
+      if (wpx == 4) launch_tiled<1, 4, 2>(n, ca, Co);
+      else if (wpx == 2) launch_tiled<1, 2, 4>(n, ca, Co);
+      else launch_tiled<1, 1, 4>(n, ca, Co);
     }
     return;
   }
@@ -763,7 +777,7 @@ void launch_wgrad(ssn_net* n, const ConvL& c, TV gz, TV x) {
   const int cw = std::min(kCW, x.W);
   const long nchunks = (long)x.N * x.H * (x.W / cw);
   const int tci = (c.Ci + 31) / 32, tco = (c.Co + 31) / 32;
-  int nsplit = (int)std::max<long>(1, std::min<long>(nchunks, 1024 / (tci * tco)));
+  int nsplit = (int)std::max<long>(1, std::min<long>(nchunks, 256 / (tci * tco)));
   while ((long)nsplit * c.Co * 9 * c.Ci > kWgradPartFloats) nsplit /= 2;
   WgradArgs wa;
   wa.gz = gz;
