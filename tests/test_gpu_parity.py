@@ -344,6 +344,77 @@ def test_large_lattice_sampled_parity(ss, orc):
     s.close()
 
 
+@pytest.mark.parametrize("tile", [0, 1])
+def test_large_lattice_fused_step_sampled_parity(ss, orc, tile):
+    """One RK4 step of the 4096^2 GL workload under the fused plan (the launch
+    configuration the benchmark times), checked on sampled windows: the oracle
+    steps a window whose outer ring of M >= 8 sites (four stages of a radius-2
+    stencil) is held fixed, so the window's centre is exact."""
+    N, h, M, S = 4096, 0.2, 10, 64
+    inst = I.gl_large_instance(N, h)
+    lam = I.gl_lambda_from_kappa(1.5)
+    s = ss.Solver(AH, N, N, h, [lam], dtype="f32")
+    s.set_plan(ss.SS_PLAN_FUSED)
+    s.set_tile(tile)
+    s.init_vortices(inst.centres, seed=4, noise_amp=1e-3)
+    f0 = s.get_field().double().cpu().numpy()
+    info = s.flow_step(1)
+    assert info["step"] == 1 and info["nonfinite"] == 0
+    f1 = s.get_field().double().cpu().numpy()
+    rng = np.random.default_rng(1)
+    origins = [tuple(rng.integers(M, N - S - M, size=2)) for _ in range(5)] + [(0, 0), (N - S, N - S)]
+    for j0, i0 in origins:
+        # window interior sites [a, b) in each direction, clipped at the lattice (the real halo)
+        ja, jb = max(j0 - M, 0), min(j0 + S + M, N)
+        ia, ib = max(i0 - M, 0), min(i0 + S + M, N)
+        win = np.ascontiguousarray(f0[:, ja:jb + 4, ia:ib + 4])
+        w1, _, _, _ = orc.flow(AH, win, np.zeros_like(win), h, [lam], 1)
+        got = f1[:, j0 + 2:j0 + S + 2, i0 + 2:i0 + S + 2]
+        ref = w1[:, j0 - ja + 2:j0 - ja + S + 2, i0 - ia + 2:i0 - ia + S + 2]
+        assert np.abs(got - ref).max() <= 1e-5 * max(np.abs(ref).max(), 1.0), (j0, i0)
+    s.close()
+
+
+def test_batch256_sampled_members_track_the_oracle(ss, orc):
+    """The 256-member batch workload in the benchmark's configuration (fused
+    plan, tile 0): three steps, then the smallest and largest members and two
+    others against the oracle's flow of each member."""
+    insts = [I.gl_batch_instance(b, 3000, 0.2) for b in range(256)]
+    B = ss.Batch(AH, [(m.Nx, m.Ny, m.h, m.params) for m in insts], dtype="f32")
+    assert B.plan == ss.SS_PLAN_FUSED
+    for m, mem in zip(insts, B.members):
+        mem.init_vortices(m.centres, seed=m.seed, noise_amp=1e-3)
+    sides = [m.Nx for m in insts]
+    picks = sorted({int(np.argmin(sides)), int(np.argmax(sides)), 17, 200})
+    start = {k: B.members[k].get_field().double().cpu().numpy() for k in picks}
+    infos = B.flow_step(3)
+    for k in picks:
+        m = insts[k]
+        phi_r, _, E_r, na = orc.flow(AH, start[k], np.zeros_like(start[k]), m.h, m.params, 3)
+        phi = B.members[k].get_field().double().cpu().numpy()
+        assert np.abs(phi - phi_r).max() <= 1e-5 * np.abs(phi_r).max(), k
+        assert infos[k]["step"] == 3 and infos[k]["n_arrests"] == na, k
+    B.close()
+
+
+def test_cm512_skyrmion_relaxes_with_charge_minus_one(ss, orc):
+    """The chiral-magnet workload at full size (512^2, h = 0.05, FP32 fields, FP64
+    reductions): relaxed to an energy stall, the Berg-Luescher charge is -1 to
+    1e-6 and agrees with the oracle's on the same field."""
+    N, h = 512, 0.05
+    s = ss.Solver(CM, N, N, h, P_CM, dtype="f32")
+    s.init_skyrmion(R=2.0, gamma=-math.pi / 2, seed=2, noise_amp=1e-3)
+    res = s.minimise(grad_tol=0.0, rel_e_tol=1e-9, window=100, max_steps=40000, graph_steps=32)
+    print("[cm512]", res, flush=True)
+    assert res["reason"] in ("stall", "max_steps") and res["nonfinite"] == 0
+    o = s.observables()
+    assert o["q_bl"] == pytest.approx(-1.0, abs=1e-6)
+    phi = _as_np(s.get_field())
+    assert orc.observables(CM, phi, h, P_CM)["Q_bl"] == pytest.approx(o["q_bl"], abs=1e-9)
+    assert o["energy"] == pytest.approx(orc.energy(CM, phi, h, P_CM), rel=1e-12)
+    s.close()
+
+
 @pytest.mark.parametrize("theory,dtype", [(AH, "f32"), (CM, "f64")])
 def test_every_tile_shape_matches_oracle(ss, theory, dtype, orc):
     """Each compiled tile shape gives the oracle's flow (ragged lattice)."""
