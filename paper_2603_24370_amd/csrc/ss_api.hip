@@ -967,20 +967,6 @@ BatchInst<T> batch_inst_of(const ss_ctx* c, int tile0) {
 
 // (Re)build the per-member tile counts, the global tile -> member map, the
 // member descriptors, and a full work list, for the batch's tile shape.
-// The tiles of the members that have not stopped, each member's column by column
-// (global tile of member i at tile column tx, row ty: tile0 + ty * ntx + tx).
-void batch_worklist(const ss_batch* b, const std::vector<int>& done, std::vector<int>& wk) {
-  wk.clear();
-  wk.reserve(b->ntiles_total);
-  for (int i = 0; i < b->n; ++i) {
-    if (done[i]) continue;
-    const ss_ctx* c = b->members[i];
-    const int ntx = c->L.ntx, nty = c->L.nty;
-    for (int tx = 0; tx < ntx; ++tx)
-      for (int ty = 0; ty < nty; ++ty) wk.push_back(b->tile0_of[i] + ty * ntx + tx);
-  }
-}
-
 int batch_build_tables(ss_batch* b) {
   b->ntiles_of.assign(b->n, 0);
   b->tile0_of.assign(b->n, 0);
@@ -995,10 +981,10 @@ int batch_build_tables(ss_batch* b) {
   }
   if (tot > b->max_tiles) return fail(SS_EINVAL, "batch tile table overflow");
   b->ntiles_total = tot;
-  std::vector<int> ti(tot), wk;
+  std::vector<int> ti(tot), wk(tot);
   for (int i = 0; i < b->n; ++i)
     for (int k = 0; k < b->ntiles_of[i]; ++k) ti[b->tile0_of[i] + k] = i;
-  batch_worklist(b, std::vector<int>(b->n, 0), wk);
+  for (int g = 0; g < tot; ++g) wk[g] = g;
   SS_HIP(hipMemcpyAsync(b->tile_inst, ti.data(), tot * sizeof(int), hipMemcpyHostToDevice, b->stream));
   SS_HIP(hipMemcpyAsync(b->work, wk.data(), tot * sizeof(int), hipMemcpyHostToDevice, b->stream));
   SS_HIP(hipMemcpyAsync(b->nwork, &tot, sizeof(int), hipMemcpyHostToDevice, b->stream));
@@ -1025,7 +1011,10 @@ int batch_build_tables(ss_batch* b) {
 // Work list of the members that have not stopped.
 int batch_compact(ss_batch* b, const std::vector<int>& done) {
   std::vector<int> wk;
-  batch_worklist(b, done, wk);
+  wk.reserve(b->ntiles_total);
+  for (int i = 0; i < b->n; ++i)
+    if (!done[i])
+      for (int k = 0; k < b->ntiles_of[i]; ++k) wk.push_back(b->tile0_of[i] + k);
   const int nw = (int)wk.size();
   if (nw) SS_HIP(hipMemcpyAsync(b->work, wk.data(), nw * sizeof(int), hipMemcpyHostToDevice, b->stream));
   SS_HIP(hipMemcpyAsync(b->nwork, &nw, sizeof(int), hipMemcpyHostToDevice, b->stream));

@@ -1182,25 +1182,10 @@ __global__ void __launch_bounds__(256) stage_pass_exact(PassArgs<T> a) {
 // Many independent lattices (uneven sizes and couplings) stepped by one launch
 // per pass. Global tile g belongs to instance tile_inst[g]; the launch walks
 // the work list work[0 .. *nwork) (the tiles of the instances still running,
-// column by column, rebuilt by the host between graph replays). Reductions are per instance:
+// rebuilt by the host between graph replays). Reductions are per instance:
 // each tile writes its own partial, and the workgroup finishing the last tile
 // of an instance sums that instance's partials in tile order and updates the
 // instance's status.
-// Work-list traversal of the batch launches: XCD x (workgroups b with b % 8 == x)
-// owns the contiguous item range [x * per, (x + 1) * per), and each of its
-// workgroups takes one contiguous run of it. The list holds each member's tiles
-// column by column, so a run walks down tile columns and a tile's top halo
-// rows are rows the same workgroup has just read.
-template <class F>
-__device__ __forceinline__ void for_each_work(int nwork, F&& body) {
-  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
-  const int per = (nwork + 7) >> 3;
-  const int w0 = xcd * per, w1 = min(nwork, w0 + per);
-  const int L = (per + m - 1) / m;
-  const int a = w0 + q * L, b = min(w1, a + L);
-  for (int w = a; w < b; ++w) body(w);
-}
-
 template <class T>
 struct BatchInst {
   InstView<T> V;
@@ -1230,12 +1215,16 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
   __shared__ int is_last;
   const int tid = threadIdx.y * TX + threadIdx.x;
 
-  for_each_work(*a.nwork, [&](int w) {
+  const int nwork = *a.nwork;
+  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, qb = blockIdx.x >> 3;
+  const int per = (nwork + 7) >> 3;
+  const int wend = min(nwork, (xcd + 1) * per);
+  for (int w = xcd * per + qb; w < wend; w += m) {
     const int g = a.work[w];
     const int i = a.tile_inst[g];
     const BatchInst<T>& I = a.inst[i];
     DevStatus* __restrict__ st = I.st;
-    if (st->done) return;
+    if (st->done) continue;
     const long long step = st->step;
     const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
     const bool arrest = STAGED ? (st->arrest != 0) : false;
@@ -1245,7 +1234,7 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
     int nf = 0;
     tile_body<T, TH, PASS, TX, TY, RY>(I.V, cur, arrest, nullptr, nullptr, 0, 0, (l - tyi * I.ntx) * TX, tyi * TY,
                                        lds, e_acc, g_acc, nf);
-    if (!REDUCE) return;
+    if (!REDUCE) continue;
     block_reduce3<NT>(e_acc, g_acc, nf, red);
     if (tid == 0) {
       double* p = a.partials + 4 * (long)g;
@@ -1272,7 +1261,7 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
       if (tid == 0) finalise_status<PASS>(st, I.V.h * I.V.h * se, sg, sn);
     }
     __syncthreads();
-  });
+  }
 }
 
 // Fused stages 2-4 for the batch: the work list's tiles, each with its member's
@@ -1280,17 +1269,21 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
 template <class T, int TH, int TX, int TY, int RY>
 __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass_fused(BatchArgs<T> a) {
   __shared__ __align__(16) T lds[FusedLds<T, TH, TX, TY>::value];
-  for_each_work(*a.nwork, [&](int w) {
+  const int nwork = *a.nwork;
+  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, qb = blockIdx.x >> 3;
+  const int per = (nwork + 7) >> 3;
+  const int wend = min(nwork, (xcd + 1) * per);
+  for (int w = xcd * per + qb; w < wend; w += m) {
     const int g = a.work[w];
     const BatchInst<T>& I = a.inst[a.tile_inst[g]];
     const DevStatus* __restrict__ st = I.st;
-    if (st->done) return;
+    if (st->done) continue;
     const int cur = int((st->step - 1) & 1);
     const bool arrest = st->arrest != 0;
     const int l = g - I.tile0;
     const int tyi = l / I.ntx;
     tile_body_fused<T, TH, TX, TY, RY>(I.V, cur, arrest, (l - tyi * I.ntx) * TX, tyi * TY, lds);
-  });
+  }
 }
 
 // Zero the velocity of every batch member whose last arrest test fired.
