@@ -1215,11 +1215,23 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
   __shared__ int is_last;
   const int tid = threadIdx.y * TX + threadIdx.x;
 
+  // Passes without a reduction interleave the XCD's items over its workgroups
+  // (w = x * per + q, + m, ...). The reducing passes give each workgroup one
+  // contiguous run of items and reduce once per run of tiles of the same member:
+  // every tile's partial slot is written exactly once per pass (the run's sum in
+  // its last tile's slot, zeros in the others), so the member's finaliser still
+  // sums its slots in tile order.
   const int nwork = *a.nwork;
   const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, qb = blockIdx.x >> 3;
   const int per = (nwork + 7) >> 3;
   const int wend = min(nwork, (xcd + 1) * per);
-  for (int w = xcd * per + qb; w < wend; w += m) {
+  const int L = (per + m - 1) / m;
+  const int wa = REDUCE ? xcd * per + qb * L : xcd * per + qb;
+  const int wb = REDUCE ? min(wend, wa + L) : wend;
+  const int wstep = REDUCE ? 1 : m;
+  double e_acc = 0.0, g_acc = 0.0;
+  int nf = 0, run = 0;
+  for (int w = wa; w < wb; w += wstep) {
     const int g = a.work[w];
     const int i = a.tile_inst[g];
     const BatchInst<T>& I = a.inst[i];
@@ -1230,11 +1242,20 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
     const bool arrest = STAGED ? (st->arrest != 0) : false;
     const int l = g - I.tile0;
     const int tyi = l / I.ntx;
-    double e_acc = 0.0, g_acc = 0.0;
-    int nf = 0;
     tile_body<T, TH, PASS, TX, TY, RY>(I.V, cur, arrest, nullptr, nullptr, 0, 0, (l - tyi * I.ntx) * TX, tyi * TY,
                                        lds, e_acc, g_acc, nf);
     if (!REDUCE) continue;
+    ++run;
+    if (w + 1 < wb && a.tile_inst[a.work[w + 1]] == i) {
+      // the run of this member goes on: this tile's slot holds no part of the sum
+      if (tid == 0) {
+        double* p = a.partials + 4 * (long)g;
+        p[0] = 0.0;
+        p[1] = 0.0;
+        p[2] = 0.0;
+      }
+      continue;
+    }
     block_reduce3<NT>(e_acc, g_acc, nf, red);
     if (tid == 0) {
       double* p = a.partials + 4 * (long)g;
@@ -1242,9 +1263,13 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
       p[1] = g_acc;
       p[2] = (double)nf;
       __threadfence();
-      const unsigned prev = atomicAdd(&st->counter, 1u);
-      is_last = (prev == (unsigned)(I.ntiles - 1));
+      const unsigned prev = atomicAdd(&st->counter, (unsigned)run);
+      is_last = (prev + (unsigned)run == (unsigned)I.ntiles);
     }
+    e_acc = 0.0;
+    g_acc = 0.0;
+    nf = 0;
+    run = 0;
     __syncthreads();
     if (is_last) {
       __threadfence();
