@@ -63,6 +63,12 @@ int ssn_get_grads(ssn_net* net, float* host, long count);
 int ssn_forward(ssn_net* net, const float* x, int n, float* out);
 /* Gradients of the mean squared error between the last output and target
  * (n, H, W, cout); *loss (may be NULL) receives the loss (synchronises). */
+/* As ssn_forward (out required), but the forward pass is captured as a HIP
+ * graph on the first call for a given (x, n, out) and replayed afterwards (one
+ * launch instead of one per kernel); a call with other pointers or n captures
+ * anew. The graph reads the weights at replay, so training between calls is
+ * seen. For callers that repeat small forwards on fixed buffers. */
+int ssn_forward_graph(ssn_net* net, const float* x, int n, float* out);
 int ssn_backward(ssn_net* net, const float* target, int n, double* loss);
 /* One Adam step (Kingma and Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. */
 int ssn_adam_step(ssn_net* net, float lr);

@@ -77,7 +77,8 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_batch_set_tile", "ss_batch_autotune", "ss_batch_set_plan", "ss_batch_get_plan", "ss_set_energy_target", "ss_learned_input",
            "ss_learned_targets", "ss_init_learned"]
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
-               "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_backward", "ssn_adam_step",
+               "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
+               "ssn_adam_step",
                "ssn_train_step", "ssn_flops", "ssn_last_error"]
 
 _lib = None
@@ -564,6 +565,7 @@ def _ssn_lib():
     L.ssn_get_weights.argtypes = [vp, fp, ctypes.c_long]
     L.ssn_get_grads.argtypes = [vp, fp, ctypes.c_long]
     L.ssn_forward.argtypes = [vp, vp, i, vp]
+    L.ssn_forward_graph.argtypes = [vp, vp, i, vp]
     L.ssn_backward.argtypes = [vp, vp, i, dp]
     L.ssn_adam_step.argtypes = [vp, ctypes.c_float]
     L.ssn_train_step.argtypes = [vp, vp, vp, i, ctypes.c_float, dp]
@@ -649,11 +651,17 @@ class Net:
     def _dev(self, x):
         return self.torch.as_tensor(x).to(device=self.device, dtype=self.torch.float32).contiguous()
 
-    def forward(self, x):
+    def forward(self, x, out=None, graph=False):
+        """Forward pass; with graph=True (x and out kept by the caller between calls)
+        it replays a captured HIP graph."""
         x = self._dev(x)
         n = x.shape[0]
-        out = self.torch.empty((n, self.H, self.W, self.cout), dtype=self.torch.float32, device=self.device)
-        _ncheck(_ssn_lib().ssn_forward(self.net, ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(out.data_ptr())))
+        if out is None:
+            if graph:
+                raise ValueError("graph=True needs a persistent out buffer")
+            out = self.torch.empty((n, self.H, self.W, self.cout), dtype=self.torch.float32, device=self.device)
+        fn = _ssn_lib().ssn_forward_graph if graph else _ssn_lib().ssn_forward
+        _ncheck(fn(self.net, ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(out.data_ptr())))
         return out
 
     def backward(self, target):

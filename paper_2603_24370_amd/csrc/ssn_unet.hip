@@ -579,6 +579,12 @@ constexpr long kWgradPartFloats = 1024L * 9 * 1024;
 
 struct ssn_net {
   int levels, base, cin, cout, cin_pad, Ncap, H, W, L;
+  // forward pass captured as a HIP graph for one (x, nb, out) triple
+  hipGraphExec_t fgraph = nullptr;
+  hipStream_t fcap = nullptr;
+  const float* fx = nullptr;
+  float* fout = nullptr;
+  int fnb = 0;
   int conv_shape;  // 0: by problem size, 1: large direct blocks, 2: small direct blocks, 3: LDS-tiled
   hipStream_t stream;
   float *P, *G, *M, *V;
@@ -803,6 +809,10 @@ void pack_all(ssn_net* n) {
   }
 }
 
+__global__ void copy_f32(const float* __restrict__ src, float* __restrict__ dst, long n) {
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) dst[k] = src[k];
+}
+
 __global__ void input_to_bf16(const float* __restrict__ x, int cin, long npix, TV X) {
   for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < npix * X.C; k += (long)gridDim.x * blockDim.x) {
     const long p = k / X.C;
@@ -1002,7 +1012,12 @@ int ssn_create(int levels, int base, int cin, int cout, int N, int H, int W, voi
   return SS_OK;
 }
 
-void ssn_destroy(ssn_net* n) { delete n; }
+void ssn_destroy(ssn_net* n) {
+  if (!n) return;
+  if (n->fgraph) (void)hipGraphExecDestroy(n->fgraph);
+  if (n->fcap) (void)hipStreamDestroy(n->fcap);
+  delete n;
+}
 
 long ssn_num_params(ssn_net* n) { return n ? oracle_count(n) : SS_EINVAL; }
 
@@ -1038,6 +1053,41 @@ int ssn_forward(ssn_net* n, const float* x, int nb, float* out) {
   if (rc) return rc;
   if (out)
     SN_HIP(hipMemcpyAsync(out, n->OUT, (size_t)nb * n->H * n->W * n->cout * 4, hipMemcpyDeviceToDevice, n->stream));
+  return SS_OK;
+}
+
+int ssn_forward_graph(ssn_net* n, const float* x, int nb, float* out) {
+  if (!n || !x || !out || nb < 1 || nb > n->Ncap) return nfail(SS_EINVAL, "bad forward arguments");
+  if (!n->fgraph || n->fx != x || n->fout != out || n->fnb != nb) {
+    if (n->fgraph) {
+      (void)hipGraphExecDestroy(n->fgraph);
+      n->fgraph = nullptr;
+    }
+    if (!n->fcap) SN_HIP(hipStreamCreateWithFlags(&n->fcap, hipStreamNonBlocking));
+    hipStream_t s0 = n->stream;
+    n->stream = n->fcap;  // the forward's launches go to the capture stream
+    hipError_t e = hipStreamBeginCapture(n->fcap, hipStreamCaptureModeRelaxed);
+    int rc = e == hipSuccess ? net_forward(n, x, nb) : SS_EHIP;
+    if (rc == SS_OK) {
+      hipLaunchKernelGGL(copy_f32, dim3(grid1((long)nb * n->H * n->W * n->cout)), dim3(256), 0, n->fcap, n->OUT, out,
+                         (long)nb * n->H * n->W * n->cout);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(n->fcap, &g);
+    n->stream = s0;
+    if (e != hipSuccess || e2 != hipSuccess || rc != SS_OK)
+      return nfail(SS_EHIP, std::string("forward capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    e = hipGraphInstantiate(&n->fgraph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      n->fgraph = nullptr;
+      return nfail(SS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    n->fx = x;
+    n->fout = out;
+    n->fnb = nb;
+  }
+  SN_HIP(hipGraphLaunch(n->fgraph, n->stream));
   return SS_OK;
 }
 

@@ -134,6 +134,22 @@ def test_production_shape_matches_oracle(ss):
     net.close()
 
 
+def test_forward_graph_replays_match_eager(ss):
+    """The captured forward, replayed three times with training steps (eager work
+    that changes the weights) in between, equals the eager forward bit for bit."""
+    import torch
+    P, x, t, net = _setup(ss, seed=4)
+    xd = torch.as_tensor(x, dtype=torch.float32, device="cuda:0").contiguous()
+    out = torch.empty((2, H, H, COUT), dtype=torch.float32, device="cuda:0")
+    for k in range(3):
+        net.forward(xd, out=out, graph=True)
+        got = out.cpu().numpy().copy()
+        ref = net.forward(xd).cpu().numpy()
+        assert np.array_equal(got, ref), k
+        net.train_step(x, t, 1e-3)
+    net.close()
+
+
 def test_adam_step_matches_oracle_update(ss):
     P, x, t, net = _setup(ss, seed=2)
     w0 = net.get_weights().astype(np.float64)
