@@ -255,17 +255,17 @@ def main(argv=None):
     import argparse
     import json
     ap = argparse.ArgumentParser(description="learned initialiser: generate minima, train, compare starts")
-    ap.add_argument("--n-train", type=int, default=2048)
+    ap.add_argument("--n-train", type=int, default=4096)
     ap.add_argument("--n-test", type=int, default=64)
     ap.add_argument("--side", type=int, default=256)
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--base", type=int, default=32)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=32)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--target-steps", type=int, default=150, help="flow steps behind each training target")
-    ap.add_argument("--pin", type=float, default=0.0, help="radius that pins the zeros of psi at the centres")
-    ap.add_argument("--sigmas", default="0,3", help="envelope widths of the learned start (comma list)")
+    ap.add_argument("--pin", type=float, default=0.5, help="radius that pins the zeros of psi at the centres")
+    ap.add_argument("--sigmas", default="3", help="envelope widths of the learned start (comma list)")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     a = ap.parse_args(argv)
     sig = tuple(float(v) for v in a.sigmas.split(","))

@@ -287,3 +287,37 @@ def test_energy_target_stop_rule(ss):
     assert res["reason"] == "target" and res["converged"]
     assert res["step"] == first and res["energy"] <= target
     s.close()
+
+
+@pytest.mark.slow
+def test_trained_network_starts_lower_in_energy(ss):
+    """What the trained network gains over the ansatz start, with a reduced budget
+    (1024 training fields at 256^2, 24 epochs; the full pipeline uses 4096 and
+    32): on held-out instances the learned start's energy excess over the relaxed
+    energy is, at the median, well under the ansatz start's, and on most of them
+    under half of it. Fewer flow steps to the 1e-6 tolerance is not asserted: at
+    this budget the learned start still takes more steps on most instances, and
+    the step and time comparison belongs to the full A/B run."""
+    from paper_2603_24370_amd import learned as L
+    side = 256
+    train = [L.learned_instance(i, 5_000_000, side) for i in range(1024)]
+    test = [L.learned_instance(j, 6_000_000, side) for j in range(8)]
+    X, T, _ = L.generate_dataset(train, batch=64, max_steps=150)
+    net = ss.Net(levels=4, base=32, cin=2, cout=4, N=8, H=side, W=side)
+    net.set_weights(L.init_weights(0, 4, 32, 2, 4))
+    losses, _, _ = L.train(net, X, T, epochs=24, batch=8, lr=1e-3)
+    zero = float(T.pow(2).mean())
+    print("[learned] loss", losses[-1], "zero", zero, flush=True)
+    assert losses[-1] < 0.2 * zero
+    del X, T
+    recs = L.ab_compare(net, test, sigmas=(3.0,), pin=0.5, ref_max_steps=20000, max_steps=20000)
+    ea, el = [], []
+    for r in recs:
+        ea.append((r["ansatz_E0"] - r["E_ref"]) / abs(r["E_ref"]))
+        el.append((r["learned_E0@3.0"] - r["E_ref"]) / abs(r["E_ref"]))
+        print("[learned]", r["n_vortices"], round(r["kappa"], 2), f"{ea[-1]:.1e} {el[-1]:.1e}",
+              r["ansatz_steps"], r["learned_steps@3.0"], flush=True)
+    assert min(ea) > 0 and min(el) > 0  # both starts lie above the relaxed energy
+    assert np.median(el) < 0.25 * np.median(ea)
+    assert sum(l < 0.5 * a for a, l in zip(ea, el)) >= 5
+    net.close()
