@@ -119,7 +119,7 @@ def run_batch(args, wl):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms_step = 1e3 * el / args.steps
-    batch_plan = B.plan if (not tune or tune[0] == 0) else 0  # the fused pass runs on tile 0 (FP32)
+    batch_plan = B.plan
     step_sets = STEP_SETS_FUSED if batch_plan == 1 else STEP_SETS
     step_gbps = step_sets * 4 * 4 * sites / (ms_step * 1e-3) / 1e9
     out = {"metric": "site-updates/s", "value": sites * args.steps / el, "unit": "site-updates/s", "n_gpus": 1,

@@ -904,13 +904,15 @@ struct ss_batch {
   hipStream_t cap_stream;
   std::vector<ss_ctx*> members;
   std::vector<int> ntiles_of;   // tiles per member (current tile shape)
-  std::vector<int> tile0_of;    // first global tile of each member
+  std::vector<int> unit0_of;    // first unit of each member
+  std::vector<int> nunits_of;   // units per member
   int ntiles_total;
+  int nunits_total;
   // device tables (inside the workspace)
   char* tables;
   void* inst;          // BatchInst<T>[n]
   DevStatus** st_ptrs; // [n]
-  int* tile_inst;      // [max tiles]
+  BatchUnit* units;    // [max tiles] (a unit holds at least one tile)
   int* work;           // [max tiles]
   int* nwork;          // [1]
   int* done_flags;     // [n]
@@ -926,7 +928,8 @@ size_t batch_table_bytes(int n, int max_tiles) {
   size_t b = 0;
   b += (size_t)round_up((long)n * (long)sizeof(BatchInst<double>), 256);
   b += (size_t)round_up((long)n * 8, 256);
-  b += 2 * (size_t)round_up((long)max_tiles * 4, 256);
+  b += (size_t)round_up((long)max_tiles * (long)sizeof(BatchUnit), 256);
+  b += (size_t)round_up((long)max_tiles * 4, 256);
   b += 256;
   b += (size_t)round_up((long)n * 4, 256);
   b += (size_t)round_up((long)max_tiles * 32, 256);
@@ -946,7 +949,7 @@ int batch_max_tiles(const int* Nx, const int* Ny, int n) {
 }
 
 template <class T>
-BatchInst<T> batch_inst_of(const ss_ctx* c, int tile0) {
+BatchInst<T> batch_inst_of(const ss_ctx* c, int unit0, int nunits) {
   BatchInst<T> I;
   Bufs<T> B = bufs_of<T>(c);
   Coeffs cf = coeffs_of(c);
@@ -958,46 +961,67 @@ BatchInst<T> batch_inst_of(const ss_ctx* c, int tile0) {
   I.V.h = cf.h; I.V.dt = cf.dt;
   for (int k = 0; k < 4; ++k) I.V.p[k] = cf.p[k];
   I.st = c->st;
-  I.ntx = c->L.ntx;
-  I.nty = c->L.nty;
-  I.tile0 = tile0;
-  I.ntiles = c->L.ntx * c->L.nty;
+  I.unit0 = unit0;
+  I.nunits = nunits;
   return I;
 }
 
-// (Re)build the per-member tile counts, the global tile -> member map, the
-// member descriptors, and a full work list, for the batch's tile shape.
+// Workgroups of a batch launch (persistent, at most 8 per CU).
+int batch_nlaunch(const ss_batch* b) { return (int)std::min<long>(round_up(b->nunits_total, 8), kMaxGroups); }
+
+// (Re)build, for the batch's tile shape, the per-member tile and unit counts,
+// the units, the member descriptors and a full work list. Units are column
+// segments: seg is the tile count over the launch's workgroups (as for a single
+// lattice), and each member's tile columns are cut into ceil(nty / seg)
+// segments of near-equal length, so that units differ little in work. A
+// member's units are numbered row-major over (segment row, tile column).
 int batch_build_tables(ss_batch* b) {
   b->ntiles_of.assign(b->n, 0);
-  b->tile0_of.assign(b->n, 0);
-  int tot = 0;
+  b->unit0_of.assign(b->n, 0);
+  b->nunits_of.assign(b->n, 0);
+  long tot = 0;
   for (int i = 0; i < b->n; ++i) {
     ss_ctx* c = b->members[i];
     c->tile = b->tile;
     set_tiles(c->L, c->Nx, c->Ny, b->tile);
-    b->tile0_of[i] = tot;
     b->ntiles_of[i] = c->L.ntx * c->L.nty;
     tot += b->ntiles_of[i];
   }
   if (tot > b->max_tiles) return fail(SS_EINVAL, "batch tile table overflow");
-  b->ntiles_total = tot;
-  std::vector<int> ti(tot), wk(tot);
-  for (int i = 0; i < b->n; ++i)
-    for (int k = 0; k < b->ntiles_of[i]; ++k) ti[b->tile0_of[i] + k] = i;
-  for (int g = 0; g < tot; ++g) wk[g] = g;
-  SS_HIP(hipMemcpyAsync(b->tile_inst, ti.data(), tot * sizeof(int), hipMemcpyHostToDevice, b->stream));
-  SS_HIP(hipMemcpyAsync(b->work, wk.data(), tot * sizeof(int), hipMemcpyHostToDevice, b->stream));
-  SS_HIP(hipMemcpyAsync(b->nwork, &tot, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  b->ntiles_total = (int)tot;
+  const long groups = std::min<long>(round_up(tot, 8), kMaxGroups);
+  const int seg = (int)std::max<long>(1, tot / groups);
+  std::vector<BatchUnit> un;
+  un.reserve(tot);
+  for (int i = 0; i < b->n; ++i) {
+    const Layout& L = b->members[i]->L;
+    const int nseg = (L.nty + seg - 1) / seg;
+    const int base = L.nty / nseg, rem = L.nty % nseg;
+    b->unit0_of[i] = (int)un.size();
+    for (int k = 0, ty0 = 0; k < nseg; ++k) {
+      const int len = base + (k < rem ? 1 : 0);
+      for (int tx = 0; tx < L.ntx; ++tx) un.push_back(BatchUnit{i, tx, ty0, len});
+      ty0 += len;
+    }
+    b->nunits_of[i] = (int)un.size() - b->unit0_of[i];
+  }
+  const int nu = (int)un.size();
+  b->nunits_total = nu;
+  std::vector<int> wk(nu);
+  for (int u = 0; u < nu; ++u) wk[u] = u;
+  SS_HIP(hipMemcpyAsync(b->units, un.data(), nu * sizeof(BatchUnit), hipMemcpyHostToDevice, b->stream));
+  SS_HIP(hipMemcpyAsync(b->work, wk.data(), nu * sizeof(int), hipMemcpyHostToDevice, b->stream));
+  SS_HIP(hipMemcpyAsync(b->nwork, &nu, sizeof(int), hipMemcpyHostToDevice, b->stream));
   std::vector<DevStatus*> sp(b->n);
   for (int i = 0; i < b->n; ++i) sp[i] = b->members[i]->st;
   SS_HIP(hipMemcpyAsync(b->st_ptrs, sp.data(), b->n * sizeof(DevStatus*), hipMemcpyHostToDevice, b->stream));
   if (b->dtype == SS_F32) {
     std::vector<BatchInst<float>> I(b->n);
-    for (int i = 0; i < b->n; ++i) I[i] = batch_inst_of<float>(b->members[i], b->tile0_of[i]);
+    for (int i = 0; i < b->n; ++i) I[i] = batch_inst_of<float>(b->members[i], b->unit0_of[i], b->nunits_of[i]);
     SS_HIP(hipMemcpyAsync(b->inst, I.data(), I.size() * sizeof(I[0]), hipMemcpyHostToDevice, b->stream));
   } else {
     std::vector<BatchInst<double>> I(b->n);
-    for (int i = 0; i < b->n; ++i) I[i] = batch_inst_of<double>(b->members[i], b->tile0_of[i]);
+    for (int i = 0; i < b->n; ++i) I[i] = batch_inst_of<double>(b->members[i], b->unit0_of[i], b->nunits_of[i]);
     SS_HIP(hipMemcpyAsync(b->inst, I.data(), I.size() * sizeof(I[0]), hipMemcpyHostToDevice, b->stream));
   }
   SS_HIP(hipStreamSynchronize(b->stream));
@@ -1011,10 +1035,10 @@ int batch_build_tables(ss_batch* b) {
 // Work list of the members that have not stopped.
 int batch_compact(ss_batch* b, const std::vector<int>& done) {
   std::vector<int> wk;
-  wk.reserve(b->ntiles_total);
+  wk.reserve(b->nunits_total);
   for (int i = 0; i < b->n; ++i)
     if (!done[i])
-      for (int k = 0; k < b->ntiles_of[i]; ++k) wk.push_back(b->tile0_of[i] + k);
+      for (int k = 0; k < b->nunits_of[i]; ++k) wk.push_back(b->unit0_of[i] + k);
   const int nw = (int)wk.size();
   if (nw) SS_HIP(hipMemcpyAsync(b->work, wk.data(), nw * sizeof(int), hipMemcpyHostToDevice, b->stream));
   SS_HIP(hipMemcpyAsync(b->nwork, &nw, sizeof(int), hipMemcpyHostToDevice, b->stream));
@@ -1044,10 +1068,10 @@ void batch_launch(const ss_batch* b, hipStream_t s) {
   BatchArgs<T> a;
   a.inst = (const BatchInst<T>*)b->inst;
   a.work = b->work;
+  a.units = b->units;
   a.nwork = b->nwork;
-  a.tile_inst = b->tile_inst;
   a.partials = b->partials;
-  const int nlaunch = (int)std::min<long>(round_up(b->ntiles_total, 8), kMaxGroups);
+  const int nlaunch = batch_nlaunch(b);
   if (b->theory == SS_THEORY_AH) batch_launch_t<T, 0, PASS>(b->tile, a, nlaunch, s);
   else batch_launch_t<T, 1, PASS>(b->tile, a, nlaunch, s);
 }
@@ -1062,10 +1086,10 @@ void batch_launch_fused(const ss_batch* b, hipStream_t s) {
   BatchArgs<T> a;
   a.inst = (const BatchInst<T>*)b->inst;
   a.work = b->work;
+  a.units = b->units;
   a.nwork = b->nwork;
-  a.tile_inst = b->tile_inst;
   a.partials = b->partials;
-  const int nlaunch = (int)std::min<long>(round_up(b->ntiles_total, 8), kMaxGroups);
+  const int nlaunch = batch_nlaunch(b);
   // the batch's tile is 64 x 16 (tile 0, FP32 only) or 64 x 8 (tile 1); see batch_fused
   if constexpr (sizeof(T) == 4) {
     if (b->tile == 0) {
@@ -1203,7 +1227,7 @@ int ss_batch_create(const char* theory, int n, const ss_instance* inst, int dtyp
   char* t = p;
   b->inst = t; t += round_up((long)n * (long)sizeof(BatchInst<double>), 256);
   b->st_ptrs = (DevStatus**)t; t += round_up((long)n * 8, 256);
-  b->tile_inst = (int*)t; t += round_up((long)b->max_tiles * 4, 256);
+  b->units = (BatchUnit*)t; t += round_up((long)b->max_tiles * (long)sizeof(BatchUnit), 256);
   b->work = (int*)t; t += round_up((long)b->max_tiles * 4, 256);
   b->nwork = (int*)t; t += 256;
   b->done_flags = (int*)t; t += round_up((long)n * 4, 256);

@@ -929,8 +929,7 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
 
   // ---- phase 1 (all global reads of the tile): phi, v on the tile plus halo 4,
   // S2 = phi + dt/2 v -> A; raw phi, v and a1 on the tile plus halo 2 -> LDS
-#pragma unroll 2
-  for (int idx = tid; idx < NA; idx += NT) {
+  auto load_entry = [&](int idx) {
     const int ly = idx / AX, lx = idx - ly * AX;
     const int x = x0 - 4 + lx, y = y0 - 4 + ly;
     const bool inb = ly >= 2 && ly < AY - 2 && lx >= 2 && lx < AX - 2;
@@ -958,6 +957,17 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
         s1[c][ib] = A1[c];
       }
     }
+  };
+  // Tall tiles take one fully unrolled sweep (every load of the tile in flight
+  // at once); 64 x 8 tiles schedule better with two sweeps in flight (measured).
+  if constexpr (TY >= 16) {
+    constexpr int KA = (NA + NT - 1) / NT;
+#pragma unroll
+    for (int k = 0; k < KA; ++k)
+      if (tid + k * NT < NA) load_entry(tid + k * NT);
+  } else {
+#pragma unroll 2
+    for (int idx = tid; idx < NA; idx += NT) load_entry(idx);
   }
   __syncthreads();
 
@@ -1104,6 +1114,14 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
   __syncthreads();
 }
 
+// Waves per SIMD the fused pass is compiled for. With FP32 fields two
+// workgroups share a CU (LDS), so registers are capped at 256 per lane; with
+// FP64 fields the LDS of one workgroup fills the CU and no cap applies.
+template <class T>
+struct FusedWaves {
+  static constexpr int value = sizeof(T) == 4 ? 2 : 1;
+};
+
 // LDS elements of the fused pass for a tile shape
 template <class T, int TH, int TX, int TY>
 struct FusedLds {
@@ -1112,7 +1130,8 @@ struct FusedLds {
 };
 
 template <class T, int TH, int TX, int TY, int RY>
-__global__ void __launch_bounds__(TX*(TY / RY)) stage_pass_fused(PassArgs<T> a) {
+__global__ void __launch_bounds__(TX*(TY / RY)) __attribute__((amdgpu_waves_per_eu(FusedWaves<T>::value)))
+stage_pass_fused(PassArgs<T> a) {
   __shared__ __align__(16) T lds[FusedLds<T, TH, TX, TY>::value];
   DevStatus* __restrict__ st = a.st;
   if (st->done) return;
@@ -1180,28 +1199,45 @@ __global__ void __launch_bounds__(256) stage_pass_exact(PassArgs<T> a) {
 
 // ------------------------------------------------------------------ batching
 // Many independent lattices (uneven sizes and couplings) stepped by one launch
-// per pass. Global tile g belongs to instance tile_inst[g]; the launch walks
-// the work list work[0 .. *nwork) (the tiles of the instances still running,
-// rebuilt by the host between graph replays). Reductions are per instance:
-// each tile writes its own partial, and the workgroup finishing the last tile
-// of an instance sums that instance's partials in tile order and updates the
-// instance's status.
+// per pass. The unit of work is a column segment of one member: n tiles stacked
+// along y from tile row ty0 in tile column tx, walked top to bottom by one
+// workgroup (so a tile's top halo rows are the rows that workgroup just read).
+// The launch walks the work list work[0 .. *nwork) (the units of the members
+// still running, rebuilt by the host between graph replays) as for_each_tile
+// walks one lattice. Reductions are per member: each unit writes its own
+// partial, and the workgroup finishing the member's last unit sums that
+// member's partials in unit order and updates the member's status.
 template <class T>
 struct BatchInst {
   InstView<T> V;
   DevStatus* st;
-  int ntx, nty;
-  int tile0, ntiles;
+  int unit0, nunits;  // the member's units (and partial slots): unit0 .. unit0 + nunits - 1
+};
+
+struct BatchUnit {
+  int inst, tx, ty0, n;
 };
 
 template <class T>
 struct BatchArgs {
   const BatchInst<T>* inst;
-  const int* work;
+  const BatchUnit* units;
+  const int* work;   // indices into units
   const int* nwork;
-  const int* tile_inst;
-  double* partials;  // 4 doubles per global tile
+  double* partials;  // 4 doubles per unit
 };
+
+// XCD x owns the contiguous item range [x * per, (x + 1) * per) of the work
+// list; its m = gridDim.x / 8 workgroups take items x*per + q, + m, ...
+// (q = blockIdx.x / 8), so workgroups resident together on an XCD hold
+// neighbouring units of the same members.
+template <class F>
+__device__ __forceinline__ void for_each_item(int nwork, F&& body) {
+  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int per = (nwork + 7) >> 3;
+  const int wend = min(nwork, (xcd + 1) * per);
+  for (int w = xcd * per + q; w < wend; w += m) body(w);
+}
 
 template <class T, int TH, int PASS, int TX, int TY, int RY>
 __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
@@ -1214,69 +1250,38 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
   __shared__ double red[3 * (NT / 64)];
   __shared__ int is_last;
   const int tid = threadIdx.y * TX + threadIdx.x;
-
-  // Passes without a reduction interleave the XCD's items over its workgroups
-  // (w = x * per + q, + m, ...). The reducing passes give each workgroup one
-  // contiguous run of items and reduce once per run of tiles of the same member:
-  // every tile's partial slot is written exactly once per pass (the run's sum in
-  // its last tile's slot, zeros in the others), so the member's finaliser still
-  // sums its slots in tile order.
-  const int nwork = *a.nwork;
-  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, qb = blockIdx.x >> 3;
-  const int per = (nwork + 7) >> 3;
-  const int wend = min(nwork, (xcd + 1) * per);
-  const int L = (per + m - 1) / m;
-  const int wa = REDUCE ? xcd * per + qb * L : xcd * per + qb;
-  const int wb = REDUCE ? min(wend, wa + L) : wend;
-  const int wstep = REDUCE ? 1 : m;
-  double e_acc = 0.0, g_acc = 0.0;
-  int nf = 0, run = 0;
-  for (int w = wa; w < wb; w += wstep) {
-    const int g = a.work[w];
-    const int i = a.tile_inst[g];
-    const BatchInst<T>& I = a.inst[i];
+  for_each_item(*a.nwork, [&](int w) {
+    const int u = a.work[w];
+    const BatchUnit U = a.units[u];
+    const BatchInst<T>& I = a.inst[U.inst];
     DevStatus* __restrict__ st = I.st;
-    if (st->done) continue;
+    if (st->done) return;
     const long long step = st->step;
     const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
     const bool arrest = STAGED ? (st->arrest != 0) : false;
-    const int l = g - I.tile0;
-    const int tyi = l / I.ntx;
-    tile_body<T, TH, PASS, TX, TY, RY>(I.V, cur, arrest, nullptr, nullptr, 0, 0, (l - tyi * I.ntx) * TX, tyi * TY,
-                                       lds, e_acc, g_acc, nf);
-    if (!REDUCE) continue;
-    ++run;
-    if (w + 1 < wb && a.tile_inst[a.work[w + 1]] == i) {
-      // the run of this member goes on: this tile's slot holds no part of the sum
-      if (tid == 0) {
-        double* p = a.partials + 4 * (long)g;
-        p[0] = 0.0;
-        p[1] = 0.0;
-        p[2] = 0.0;
-      }
-      continue;
-    }
+    double e_acc = 0.0, g_acc = 0.0;
+    int nf = 0;
+    for (int k = 0; k < U.n; ++k)
+      tile_body<T, TH, PASS, TX, TY, RY>(I.V, cur, arrest, nullptr, nullptr, 0, 0, U.tx * TX, (U.ty0 + k) * TY, lds,
+                                         e_acc, g_acc, nf);
+    if (!REDUCE) return;
     block_reduce3<NT>(e_acc, g_acc, nf, red);
     if (tid == 0) {
-      double* p = a.partials + 4 * (long)g;
+      double* p = a.partials + 4 * (long)u;
       p[0] = e_acc;
       p[1] = g_acc;
       p[2] = (double)nf;
       __threadfence();
-      const unsigned prev = atomicAdd(&st->counter, (unsigned)run);
-      is_last = (prev + (unsigned)run == (unsigned)I.ntiles);
+      const unsigned prev = atomicAdd(&st->counter, 1u);
+      is_last = (prev + 1u == (unsigned)I.nunits);
     }
-    e_acc = 0.0;
-    g_acc = 0.0;
-    nf = 0;
-    run = 0;
     __syncthreads();
     if (is_last) {
       __threadfence();
       double se = 0.0, sg = 0.0;
       int sn = 0;
-      for (int k = tid; k < I.ntiles; k += NT) {
-        const double* p = a.partials + 4 * (long)(I.tile0 + k);
+      for (int k = tid; k < I.nunits; k += NT) {
+        const double* p = a.partials + 4 * (long)(I.unit0 + k);
         se += __builtin_nontemporal_load(p);
         sg = fmax(sg, __builtin_nontemporal_load(p + 1));
         sn += (int)__builtin_nontemporal_load(p + 2);
@@ -1286,29 +1291,25 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
       if (tid == 0) finalise_status<PASS>(st, I.V.h * I.V.h * se, sg, sn);
     }
     __syncthreads();
-  }
+  });
 }
 
-// Fused stages 2-4 for the batch: the work list's tiles, each with its member's
+// Fused stages 2-4 for the batch: the work list's units, each with its member's
 // arrest flag and step parity (members that stopped are skipped).
 template <class T, int TH, int TX, int TY, int RY>
-__global__ void __launch_bounds__(TX*(TY / RY)) batch_pass_fused(BatchArgs<T> a) {
+__global__ void __launch_bounds__(TX*(TY / RY)) __attribute__((amdgpu_waves_per_eu(FusedWaves<T>::value)))
+batch_pass_fused(BatchArgs<T> a) {
   __shared__ __align__(16) T lds[FusedLds<T, TH, TX, TY>::value];
-  const int nwork = *a.nwork;
-  const int m = gridDim.x >> 3, xcd = blockIdx.x & 7, qb = blockIdx.x >> 3;
-  const int per = (nwork + 7) >> 3;
-  const int wend = min(nwork, (xcd + 1) * per);
-  for (int w = xcd * per + qb; w < wend; w += m) {
-    const int g = a.work[w];
-    const BatchInst<T>& I = a.inst[a.tile_inst[g]];
+  for_each_item(*a.nwork, [&](int w) {
+    const BatchUnit U = a.units[a.work[w]];
+    const BatchInst<T>& I = a.inst[U.inst];
     const DevStatus* __restrict__ st = I.st;
-    if (st->done) continue;
+    if (st->done) return;
     const int cur = int((st->step - 1) & 1);
     const bool arrest = st->arrest != 0;
-    const int l = g - I.tile0;
-    const int tyi = l / I.ntx;
-    tile_body_fused<T, TH, TX, TY, RY>(I.V, cur, arrest, (l - tyi * I.ntx) * TX, tyi * TY, lds);
-  }
+    for (int k = 0; k < U.n; ++k)
+      tile_body_fused<T, TH, TX, TY, RY>(I.V, cur, arrest, U.tx * TX, (U.ty0 + k) * TY, lds);
+  });
 }
 
 // Zero the velocity of every batch member whose last arrest test fired.
