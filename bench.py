@@ -202,9 +202,9 @@ def cpu_baseline(s, wl, params, window=1024, steps=10):
                       f"fixed halo), FP64, {dt:.1f} s"}
 
 
-def traffic_record(pass_name, wl_name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+def traffic_record(pass_name, wl_name, tile):
+    """HBM bytes per launch of a pass on a tile shape (index) from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -212,7 +212,7 @@ def traffic_record(pass_name, wl_name):
         rec = json.load(fh)
     if rec.get("kernel_source") != kernel_source_hash():
         return None
-    return rec.get(wl_name, {}).get(pass_name)
+    return rec.get(wl_name, {}).get(f"tile{tile}", {}).get(pass_name)
 
 
 def main():
@@ -284,7 +284,8 @@ def main():
     ach = passes[dom]["GBps"]
     step_sets = STEP_SETS if plan == 0 else STEP_SETS_FUSED
     step_gbps = step_sets * C * b * sites / (ms_step * 1e-3) / 1e9
-    tr = traffic_record(dom, args.workload)
+    import paper_2603_24370_amd as ss
+    tr = traffic_record(dom, args.workload, ss.ss_get_tile(s.ctx))
     tr_gb = tr["total_GB"] if tr else None
     kname = f"stage_pass {dom}" if dom != "P234" else "stage_pass_fused (stages 2-4)"
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -200,6 +200,8 @@ void launch_pass_t(int tile, const PassArgs<T>& a, int nlaunch, hipStream_t s) {
   }
 }
 
+// A pass; a reducing pass (P1, evaluation, check) is followed by its finalise
+// launch, which sums the workgroup partials and updates the status.
 template <class T, int PASS>
 void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   if (c->grad_mode == SS_GRAD_EXACT) {
@@ -208,10 +210,14 @@ void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
       hipLaunchKernelGGL((stage_pass_exact<T, 0, PASS>), dim3(c->L.nlaunch), dim3(kExTX, kExTY / kExRY), 0, s, a);
     else
       hipLaunchKernelGGL((stage_pass_exact<T, 1, PASS>), dim3(c->L.nlaunch), dim3(kExTX, kExTY / kExRY), 0, s, a);
-    return;
+  } else if (c->theory == SS_THEORY_AH) {
+    launch_pass_t<T, 0, PASS>(c->tile, a, c->L.nlaunch, s);
+  } else {
+    launch_pass_t<T, 1, PASS>(c->tile, a, c->L.nlaunch, s);
   }
-  if (c->theory == SS_THEORY_AH) launch_pass_t<T, 0, PASS>(c->tile, a, c->L.nlaunch, s);
-  else launch_pass_t<T, 1, PASS>(c->tile, a, c->L.nlaunch, s);
+  if constexpr (PASS == kP1 || PASS == kEval || PASS == kCheck)
+    hipLaunchKernelGGL((pass_finalise<PASS>), dim3(1), dim3(256), 0, s, a.st, (const double*)a.partials,
+                       c->L.nlaunch, a.cf.h);
 }
 
 // Fused stages 2-4 run on 64 x 16 tiles (tile 0) or 64 x 8 tiles (tile 1), two
@@ -1074,6 +1080,8 @@ void batch_launch(const ss_batch* b, hipStream_t s) {
   const int nlaunch = batch_nlaunch(b);
   if (b->theory == SS_THEORY_AH) batch_launch_t<T, 0, PASS>(b->tile, a, nlaunch, s);
   else batch_launch_t<T, 1, PASS>(b->tile, a, nlaunch, s);
+  if constexpr (PASS == kP1 || PASS == kCheck)
+    hipLaunchKernelGGL((batch_finalise<T, PASS>), dim3(b->n), dim3(256), 0, s, a.inst, (const double*)b->partials);
 }
 
 template <class T>

@@ -769,8 +769,8 @@ __device__ __forceinline__ void finalise_status(DevStatus* st, double E, double 
 }
 
 // Launch: gridDim.x is a multiple of 8; tiles are assigned by for_each_tile.
-// Each workgroup accumulates its tiles' reductions into one partial; the last
-// workgroup to finish sums the partials in a fixed order and updates the status.
+// Each workgroup accumulates its tiles' reductions into one partial;
+// pass_finalise sums the partials in a fixed order and updates the status.
 template <class T, int TH, int PASS, int TX, int TY, int RY>
 __global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
   constexpr int C = NComp<TH>::value;
@@ -796,33 +796,35 @@ __global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
   });
   if (!REDUCE) return;
 
-  // ---- two-level FP64 reduction with a deterministic last-workgroup finalise
-  const int tid = threadIdx.y * TX + threadIdx.x;
+  // ---- first level of the FP64 reduction: one partial per workgroup (the
+  // second level is pass_finalise, launched after the pass)
   block_reduce3<NT>(e_acc, g_acc, nf, red);
-  __shared__ int is_last;
-  if (tid == 0) {
+  if (threadIdx.y * TX + threadIdx.x == 0) {
     double* p = a.partials + 4 * (long)blockIdx.x;
     p[0] = e_acc;
     p[1] = g_acc;
     p[2] = (double)nf;
-    __threadfence();
-    const unsigned prev = atomicAdd(&st->counter, 1u);
-    is_last = (prev == (unsigned)(gridDim.x - 1));
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
+
+// Second level of a reducing pass (one workgroup of 256 threads): the nparts
+// workgroup partials summed in workgroup order, then the status update. Being a
+// launch of its own, it needs no fence or atomic inside the pass.
+template <int PASS>
+__global__ void __launch_bounds__(256) pass_finalise(DevStatus* st, const double* __restrict__ partials, int nparts,
+                                                     double h) {
+  if (PASS != kEval && st->done) return;
   double se = 0.0, sg = 0.0;
   int sn = 0;
-  for (int k = tid; k < (int)gridDim.x; k += NT) {
-    const double* p = a.partials + 4 * (long)k;
-    se += __builtin_nontemporal_load(p);
-    sg = fmax(sg, __builtin_nontemporal_load(p + 1));
-    sn += (int)__builtin_nontemporal_load(p + 2);
+  for (int k = threadIdx.x; k < nparts; k += 256) {
+    const double* p = partials + 4 * (long)k;
+    se += p[0];
+    sg = fmax(sg, p[1]);
+    sn += (int)p[2];
   }
-  __syncthreads();
-  block_reduce3<NT>(se, sg, sn, red);
-  if (tid == 0) finalise_status<PASS>(st, a.cf.h * a.cf.h * se, sg, sn);
+  __shared__ double red[3 * 4];
+  block_reduce3<256>(se, sg, sn, red);
+  if (threadIdx.x == 0) finalise_status<PASS>(st, h * h * se, sg, sn);
 }
 
 // ------------------------------------------------- fused stages 2-4 (EL gradient)
@@ -1169,32 +1171,13 @@ __global__ void __launch_bounds__(256) stage_pass_exact(PassArgs<T> a) {
                                  lds, e_acc, g_acc, nf);
   });
   if (!REDUCE) return;
-  const int tid = threadIdx.y * kExTX + threadIdx.x;
   block_reduce3<NT>(e_acc, g_acc, nf, red);
-  __shared__ int is_last;
-  if (tid == 0) {
+  if (threadIdx.y * kExTX + threadIdx.x == 0) {
     double* p = a.partials + 4 * (long)blockIdx.x;
     p[0] = e_acc;
     p[1] = g_acc;
     p[2] = (double)nf;
-    __threadfence();
-    const unsigned prev = atomicAdd(&st->counter, 1u);
-    is_last = (prev == (unsigned)(gridDim.x - 1));
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double se = 0.0, sg = 0.0;
-  int sn = 0;
-  for (int k = tid; k < (int)gridDim.x; k += NT) {
-    const double* p = a.partials + 4 * (long)k;
-    se += __builtin_nontemporal_load(p);
-    sg = fmax(sg, __builtin_nontemporal_load(p + 1));
-    sn += (int)__builtin_nontemporal_load(p + 2);
-  }
-  __syncthreads();
-  block_reduce3<NT>(se, sg, sn, red);
-  if (tid == 0) finalise_status<PASS>(st, a.cf.h * a.cf.h * se, sg, sn);
 }
 
 // ------------------------------------------------------------------ batching
@@ -1205,8 +1188,8 @@ __global__ void __launch_bounds__(256) stage_pass_exact(PassArgs<T> a) {
 // The launch walks the work list work[0 .. *nwork) (the units of the members
 // still running, rebuilt by the host between graph replays) as for_each_tile
 // walks one lattice. Reductions are per member: each unit writes its own
-// partial, and the workgroup finishing the member's last unit sums that
-// member's partials in unit order and updates the member's status.
+// partial, and batch_finalise (one workgroup per member, launched after the
+// pass) sums that member's partials in unit order and updates its status.
 template <class T>
 struct BatchInst {
   InstView<T> V;
@@ -1248,7 +1231,6 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
   constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
   __shared__ __align__(16) T lds[C * LY * LX];
   __shared__ double red[3 * (NT / 64)];
-  __shared__ int is_last;
   const int tid = threadIdx.y * TX + threadIdx.x;
   for_each_item(*a.nwork, [&](int w) {
     const int u = a.work[w];
@@ -1271,27 +1253,30 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
       p[0] = e_acc;
       p[1] = g_acc;
       p[2] = (double)nf;
-      __threadfence();
-      const unsigned prev = atomicAdd(&st->counter, 1u);
-      is_last = (prev + 1u == (unsigned)I.nunits);
-    }
-    __syncthreads();
-    if (is_last) {
-      __threadfence();
-      double se = 0.0, sg = 0.0;
-      int sn = 0;
-      for (int k = tid; k < I.nunits; k += NT) {
-        const double* p = a.partials + 4 * (long)(I.unit0 + k);
-        se += __builtin_nontemporal_load(p);
-        sg = fmax(sg, __builtin_nontemporal_load(p + 1));
-        sn += (int)__builtin_nontemporal_load(p + 2);
-      }
-      __syncthreads();
-      block_reduce3<NT>(se, sg, sn, red);
-      if (tid == 0) finalise_status<PASS>(st, I.V.h * I.V.h * se, sg, sn);
     }
     __syncthreads();
   });
+}
+
+// End of a batch reducing pass, one workgroup (256 threads) per member: the
+// member's unit partials summed in unit order, then its status update. Being
+// a launch of its own, it needs no fence or atomic inside the pass.
+template <class T, int PASS>
+__global__ void __launch_bounds__(256) batch_finalise(const BatchInst<T>* inst, const double* __restrict__ partials) {
+  const BatchInst<T>& I = inst[blockIdx.x];
+  DevStatus* __restrict__ st = I.st;
+  if (st->done) return;
+  double se = 0.0, sg = 0.0;
+  int sn = 0;
+  for (int k = threadIdx.x; k < I.nunits; k += 256) {
+    const double* p = partials + 4 * (long)(I.unit0 + k);
+    se += p[0];
+    sg = fmax(sg, p[1]);
+    sn += (int)p[2];
+  }
+  __shared__ double red[3 * 4];
+  block_reduce3<256>(se, sg, sn, red);
+  if (threadIdx.x == 0) finalise_status<PASS>(st, I.V.h * I.V.h * se, sg, sn);
 }
 
 // Fused stages 2-4 for the batch: the work list's units, each with its member's
