@@ -34,6 +34,7 @@ namespace ssn {
 typedef unsigned short bf16_t;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
 
 __device__ __forceinline__ float bf2f(bf16_t x) { return __uint_as_float(((unsigned)x) << 16); }
 
@@ -244,59 +245,97 @@ __global__ void __launch_bounds__(64 * WCO * WPX) conv3x3_tiled(ConvArgs a) {
 
 // Weight gradient: part[split][co][t][ci] = sum over this split's pixel chunks of
 // gz[pix][co] * x[pix + d_t][ci]. Block = 9 waves (one per tap), tile 32 co x 32 ci.
-// A chunk is cw pixels of one image row (cw = 64 or W); its gz rows and the
-// three x rows around it (cw + 2 pixels wide) are staged transposed in LDS.
-constexpr int kCW = 64;
+// A chunk is R image rows of cw pixels (R * cw <= kChunk): its gz pixels and the
+// R + 2 x rows around them (cw + 2 pixels wide) are read as 16-byte vectors of 8
+// channels and staged transposed in LDS, then every wave runs R * cw / 16 MFMAs
+// on them. Requires 16-byte aligned channel vectors (cs, coff, C multiples of 8),
+// cw % 16 == 0, W % cw == 0, H % R == 0 and (R + 2) * 32 * (cw + 8) <= kXLds.
+constexpr int kChunk = 256;         // pixels per chunk
+constexpr int kGP = kChunk + 8;     // gzT row pitch (elements)
+constexpr int kXLds = 13824;        // xT elements: (R + 2) * 32 rows of pitch cw + 8
 struct WgradArgs {
   TV gz;        // gradient w.r.t. the layer's pre-activation (C = Co)
   TV x;         // layer input (C = Ci)
   float* part;  // [nsplit][Co][9][Ci]
   int nsplit;
-  int cw;       // pixels per chunk (divides W, multiple of 16, <= kCW)
+  int cw;       // pixels per chunk row
+  int R;        // rows per chunk
 };
 
+// 8 channels (16 bytes, channel j in bits 16 (j % 2) of word j / 2)
+__device__ __forceinline__ u32x4 load_u32x4(const bf16_t* p) { return *reinterpret_cast<const u32x4*>(p); }
+
 __global__ void __launch_bounds__(576) conv3x3_wgrad(WgradArgs a) {
-  __shared__ __align__(16) bf16_t gzT[32][kCW + 8];      // [co][pix]
-  __shared__ __align__(16) bf16_t xT[3][32][kCW + 8 + 2]; // [row][ci][pix + 1]
+  __shared__ __align__(16) bf16_t gzT[32 * kGP];  // [co][pix]
+  __shared__ __align__(16) bf16_t xT[kXLds];      // [row][ci][pix + 1]
   const int lane = threadIdx.x & 63, tap = threadIdx.x >> 6;
   const int r = lane & 31, half = lane >> 5;
   const int ci0 = blockIdx.x * 32, co0 = blockIdx.y * 32, split = blockIdx.z;
-  const int H = a.x.H, W = a.x.W, Ci = a.x.C, Co = a.gz.C, cw = a.cw;
-  const int chunks_per_row = W / cw;
-  const long nchunks = (long)a.x.N * H * chunks_per_row;
+  const int H = a.x.H, W = a.x.W, Ci = a.x.C, Co = a.gz.C, cw = a.cw, R = a.R;
+  const int XP = cw + 8;
+  const int cpr = W / cw, rpi = H / R;
+  const long nchunks = (long)a.x.N * rpi * cpr;
   const int dy = tap / 3 - 1, dx = tap % 3 - 1;
   f32x16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
   for (long ch = split; ch < nchunks; ch += a.nsplit) {
-    const int n = (int)(ch / ((long)H * chunks_per_row));
-    const int rem = (int)(ch - (long)n * H * chunks_per_row);
-    const int y = rem / chunks_per_row, x0 = (rem - y * chunks_per_row) * cw;
-    // stage gz[pix][co0..co0+31] transposed
-    for (int e = threadIdx.x; e < cw * 32; e += 576) {
-      const int pix = e >> 5, c = e & 31;
-      gzT[c][pix] = (co0 + c < Co) ? a.gz.p[tv_at(a.gz, n, y, x0 + pix) + co0 + c] : (bf16_t)0;
+    const int n = (int)(ch / ((long)rpi * cpr));
+    const int rem = (int)(ch - (long)n * rpi * cpr);
+    const int y0 = (rem / cpr) * R, x0 = (rem - (rem / cpr) * cpr) * cw;
+    // gz: R * cw pixels, 4 vectors of 8 channels each
+    for (int e = threadIdx.x; e < R * cw * 4; e += 576) {
+      const int p = e >> 2, v = e & 3;
+      const int py = p / cw, px = p - py * cw;
+      u32x4 val = {0u, 0u, 0u, 0u};
+      if (co0 + 8 * v < Co) val = load_u32x4(a.gz.p + tv_at(a.gz, n, y0 + py, x0 + px) + co0 + 8 * v);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        gzT[(8 * v + 2 * j) * kGP + p] = (bf16_t)(val[j] & 0xffffu);
+        gzT[(8 * v + 2 * j + 1) * kGP + p] = (bf16_t)(val[j] >> 16);
+      }
     }
-    // stage x rows y-1..y+1, pixels x0-1..x0+cw, channels ci0..ci0+31, transposed
-    for (int e = threadIdx.x; e < 3 * (cw + 2) * 32; e += 576) {
-      const int c = e & 31, k = e >> 5;
-      const int row = k / (cw + 2), pix = k - row * (cw + 2);
-      const int yy = y + row - 1, xx = x0 + pix - 1;
-      bf16_t val = 0;
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W && ci0 + c < Ci) val = a.x.p[tv_at(a.x, n, yy, xx) + ci0 + c];
-      xT[row][c][pix] = val;
+    // x: rows y0 - 1 .. y0 + R, pixels x0 - 1 .. x0 + cw, 4 vectors of 8 channels each
+    for (int e = threadIdx.x; e < (R + 2) * (cw + 2) * 4; e += 576) {
+      const int v = e & 3, k = e >> 2;
+      const int rr = k / (cw + 2), px = k - rr * (cw + 2);
+      const int yy = y0 + rr - 1, xx = x0 + px - 1;
+      const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W && ci0 + 8 * v < Ci;
+      u32x4 val = {0u, 0u, 0u, 0u};
+      if (in) val = load_u32x4(a.x.p + tv_at(a.x, n, yy, xx) + ci0 + 8 * v);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        xT[(rr * 32 + 8 * v + 2 * j) * XP + px] = (bf16_t)(val[j] & 0xffffu);
+        xT[(rr * 32 + 8 * v + 2 * j + 1) * XP + px] = (bf16_t)(val[j] >> 16);
+      }
     }
     __syncthreads();
     if (tap < 9) {
-      for (int kk = 0; kk < cw; kk += 16) {
-        bf16x8 A, B;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int pix = kk + half * 8 + j;
-          A[j] = __builtin_bit_cast(__bf16, gzT[r][pix]);
-          B[j] = __builtin_bit_cast(__bf16, xT[dy + 1][r][pix + dx + 1]);
+      // B of tap (dy, dx) starts dx + 1 elements past a 16-byte boundary: it is
+      // read as two aligned 16-byte words and shifted by whole elements (LDS
+      // vector reads must be aligned)
+      const int sh = dx + 1;
+      for (int rr = 0; rr < R; ++rr) {
+        const u32x4* ap = reinterpret_cast<const u32x4*>(gzT + r * kGP + rr * cw + half * 8);
+        const u32x4* bp = reinterpret_cast<const u32x4*>(xT + ((rr + dy + 1) * 32 + r) * XP + half * 8);
+        for (int kk = 0; kk < cw; kk += 16) {
+          const u32x4 a4 = ap[kk >> 3];
+          const u32x4 w0 = bp[kk >> 3], w1 = bp[(kk >> 3) + 1];
+          u32x4 b4 = w0;
+          if (sh == 1) {
+            b4.x = __builtin_amdgcn_alignbit(w0.y, w0.x, 16);
+            b4.y = __builtin_amdgcn_alignbit(w0.z, w0.y, 16);
+            b4.z = __builtin_amdgcn_alignbit(w0.w, w0.z, 16);
+            b4.w = __builtin_amdgcn_alignbit(w1.x, w0.w, 16);
+          } else if (sh == 2) {
+            b4.x = w0.y;
+            b4.y = w0.z;
+            b4.z = w0.w;
+            b4.w = w1.x;
+          }
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a4), __builtin_bit_cast(bf16x8, b4),
+                                                         acc, 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc, 0, 0, 0);
       }
     }
     __syncthreads();
@@ -311,167 +350,287 @@ __global__ void __launch_bounds__(576) conv3x3_wgrad(WgradArgs a) {
   }
 }
 
-// out[k] = sum over s of part[s][k], in split order
-__global__ void reduce_splits(const float* __restrict__ part, int nsplit, long n, float* __restrict__ out) {
-  const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k >= n) return;
+// out[k] = sum over s of part[s][k]. A block takes 32 outputs; its 8 groups of
+// 32 lanes each sum a contiguous eighth of the splits in order, and the eight
+// sums are added in group order (fixed order: deterministic).
+__global__ void __launch_bounds__(256) reduce_splits(const float* __restrict__ part, int nsplit, long n,
+                                                     float* __restrict__ out) {
+  __shared__ float red[256];
+  const int kl = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const long k = blockIdx.x * 32L + kl;
+  const int per = (nsplit + 7) / 8;
+  const int s0 = min(nsplit, g * per), s1 = min(nsplit, s0 + per);
   float s = 0.0f;
-  for (int i = 0; i < nsplit; ++i) s += part[(long)i * n + k];
-  out[k] = s;
+  if (k < n)
+    for (int i = s0; i < s1; ++i) s += part[(long)i * n + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0 && k < n) {
+    float o = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) o += red[j * 32 + kl];
+    out[k] = o;
+  }
+}
+
+// 8 bf16 channels of a 16-byte vector as floats
+__device__ __forceinline__ void unpack8(const u32x4 v, float (&x)[8]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    x[2 * j] = bf2f((bf16_t)(v[j] & 0xffffu));
+    x[2 * j + 1] = bf2f((bf16_t)(v[j] >> 16));
+  }
 }
 
 // Per-block channel sums of an NHWC view (bf16 g, or fp32 gf with channel
 // stride gf_cs) into fp32 partials [nblk][C]. Block y takes channels
-// [256 y, 256 y + Cc), Cc = min(C - 256 y, 256); thread t sums channel t % Cc
-// over the pixels b0 + t / Cc, step 256 / Cc, of the block's pixel range, and
-// the lanes of each channel are then added in lane order (deterministic).
+// [256 y, 256 y + Cc), Cc = min(C - 256 y, 256). For g (Cc % 8 == 0) thread t
+// sums the 8-channel group t % G (G = Cc / 8) over the pixels b0 + t / G, step
+// 256 / G, of the block's pixel range; for gf, channel t % Cc over the pixels
+// b0 + t / Cc, step 256 / Cc. The lane sums of each channel are then added in
+// lane order (deterministic).
 __global__ void __launch_bounds__(256) channel_sums(TV g, const float* __restrict__ gf, int gf_cs, long npix, int C,
                                                     float* __restrict__ part) {
-  __shared__ float red[256];
+  __shared__ float red[256 * 8];
   const int t = threadIdx.x;
   const int c0 = 256 * blockIdx.y;
   const int Cc = min(C - c0, 256);
-  const int L = 256 / Cc;
-  const int c = t % Cc, l = t / Cc;
   const long per = (npix + gridDim.x - 1) / gridDim.x;
   const long b0 = blockIdx.x * per, b1 = std::min(npix, b0 + per);
-  float s = 0.0f;
-  if (l < L) {
-    if (gf)
+  if (gf) {
+    const int L = 256 / Cc;
+    const int c = t % Cc, l = t / Cc;
+    float s = 0.0f;
+    if (l < L)
       for (long p = b0 + l; p < b1; p += L) s += gf[p * gf_cs + c0 + c];
-    else
-      for (long p = b0 + l; p < b1; p += L) s += bf2f(g.p[p * g.cs + g.coff + c0 + c]);
+    red[t] = s;
+    __syncthreads();
+    if (t < Cc) {
+      float a = 0.0f;
+      for (int k = 0; k < L; ++k) a += red[k * Cc + t];
+      part[(long)blockIdx.x * C + c0 + t] = a;
+    }
+    return;
   }
-  red[t] = s;
+  const int G = Cc / 8, L = 256 / G;
+  const int e = t % G, l = t / G;
+  float s[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  if (l < L)
+    for (long p = b0 + l; p < b1; p += L) {
+      float v[8];
+      unpack8(load_u32x4(g.p + p * g.cs + g.coff + c0 + 8 * e), v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += v[j];
+    }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) red[t * 8 + j] = s[j];
   __syncthreads();
   if (t < Cc) {
     float a = 0.0f;
-    for (int k = 0; k < L; ++k) a += red[k * Cc + t];
+    for (int k = 0; k < L; ++k) a += red[(k * G + t / 8) * 8 + t % 8];
     part[(long)blockIdx.x * C + c0 + t] = a;
   }
 }
 
+// Pooling, upsampling and SiLU' on NHWC views, one 16-byte vector of 8
+// channels per work item (C, cs and coff multiples of 8); item k is channel
+// group k % (C / 8) of pixel k / (C / 8).
+__device__ __forceinline__ u32x4 pack8(const float (&x)[8]) {
+  u32x4 r;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r[j] = (unsigned)f2bf(x[2 * j]) | ((unsigned)f2bf(x[2 * j + 1]) << 16);
+  return r;
+}
+
+__device__ __forceinline__ void store_u32x4(bf16_t* p, const u32x4 v) { *reinterpret_cast<u32x4*>(p) = v; }
+
+// pixel (b, y, x) and first channel c of work item k of a view with C8 groups per pixel
+__device__ __forceinline__ void item_of(long k, const TV& t, int C8, int& b, int& y, int& x, int& c) {
+  c = 8 * (int)(k % C8);
+  long p = k / C8;
+  x = (int)(p % t.W);
+  p /= t.W;
+  y = (int)(p % t.H);
+  b = (int)(p / t.H);
+}
+
 __global__ void avgpool2_fwd(TV in, TV out) {
-  const long n = (long)out.N * out.H * out.W * out.C;
+  const int C8 = out.C / 8;
+  const long n = (long)out.N * out.H * out.W * C8;
   for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(k % out.C);
-    long p = k / out.C;
-    const int x = (int)(p % out.W);
-    p /= out.W;
-    const int y = (int)(p % out.H);
-    const int b = (int)(p / out.H);
-    float s = 0.0f;
+    int b, y, x, c;
+    item_of(k, out, C8, b, y, x, c);
+    float s[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     for (int j = 0; j < 2; ++j)
-      for (int i = 0; i < 2; ++i) s += bf2f(in.p[tv_at(in, b, 2 * y + j, 2 * x + i) + c]);
-    out.p[tv_at(out, b, y, x) + c] = f2bf(0.25f * s);
+      for (int i = 0; i < 2; ++i) {
+        float v[8];
+        unpack8(load_u32x4(in.p + tv_at(in, b, 2 * y + j, 2 * x + i) + c), v);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] += v[e];
+      }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] *= 0.25f;
+    store_u32x4(out.p + tv_at(out, b, y, x) + c, pack8(s));
   }
 }
 
 // gin (+)= gout / 4 spread over each 2x2 block
 __global__ void avgpool2_bwd(TV gout, TV gin, int accumulate) {
-  const long n = (long)gin.N * gin.H * gin.W * gin.C;
+  const int C8 = gin.C / 8;
+  const long n = (long)gin.N * gin.H * gin.W * C8;
   for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(k % gin.C);
-    long p = k / gin.C;
-    const int x = (int)(p % gin.W);
-    p /= gin.W;
-    const int y = (int)(p % gin.H);
-    const int b = (int)(p / gin.H);
-    float v = 0.25f * bf2f(gout.p[tv_at(gout, b, y >> 1, x >> 1) + c]);
+    int b, y, x, c;
+    item_of(k, gin, C8, b, y, x, c);
+    float v[8];
+    unpack8(load_u32x4(gout.p + tv_at(gout, b, y >> 1, x >> 1) + c), v);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] *= 0.25f;
     bf16_t* o = gin.p + tv_at(gin, b, y, x) + c;
-    if (accumulate) v += bf2f(*o);
-    *o = f2bf(v);
+    if (accumulate) {
+      float w[8];
+      unpack8(load_u32x4(o), w);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] += w[e];
+    }
+    store_u32x4(o, pack8(v));
   }
 }
 
 __global__ void upsample2_fwd(TV in, TV out) {
-  const long n = (long)out.N * out.H * out.W * out.C;
+  const int C8 = out.C / 8;
+  const long n = (long)out.N * out.H * out.W * C8;
   for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(k % out.C);
-    long p = k / out.C;
-    const int x = (int)(p % out.W);
-    p /= out.W;
-    const int y = (int)(p % out.H);
-    const int b = (int)(p / out.H);
-    out.p[tv_at(out, b, y, x) + c] = in.p[tv_at(in, b, y >> 1, x >> 1) + c];
+    int b, y, x, c;
+    item_of(k, out, C8, b, y, x, c);
+    store_u32x4(out.p + tv_at(out, b, y, x) + c, load_u32x4(in.p + tv_at(in, b, y >> 1, x >> 1) + c));
   }
 }
 
 // gin = sum of gout over each 2x2 block
 __global__ void upsample2_bwd(TV gout, TV gin) {
-  const long n = (long)gin.N * gin.H * gin.W * gin.C;
+  const int C8 = gin.C / 8;
+  const long n = (long)gin.N * gin.H * gin.W * C8;
   for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(k % gin.C);
-    long p = k / gin.C;
-    const int x = (int)(p % gin.W);
-    p /= gin.W;
-    const int y = (int)(p % gin.H);
-    const int b = (int)(p / gin.H);
-    float s = 0.0f;
+    int b, y, x, c;
+    item_of(k, gin, C8, b, y, x, c);
+    float s[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     for (int j = 0; j < 2; ++j)
-      for (int i = 0; i < 2; ++i) s += bf2f(gout.p[tv_at(gout, b, 2 * y + j, 2 * x + i) + c]);
-    gin.p[tv_at(gin, b, y, x) + c] = f2bf(s);
+      for (int i = 0; i < 2; ++i) {
+        float v[8];
+        unpack8(load_u32x4(gout.p + tv_at(gout, b, 2 * y + j, 2 * x + i) + c), v);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) s[e] += v[e];
+      }
+    store_u32x4(gin.p + tv_at(gin, b, y, x) + c, pack8(s));
   }
 }
 
 // g *= SiLU'(z) in place
 __global__ void silu_bwd_inplace(TV g, TV z) {
-  const long n = (long)g.N * g.H * g.W * g.C;
+  const int C8 = g.C / 8;
+  const long n = (long)g.N * g.H * g.W * C8;
   for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(k % g.C);
-    const long p = k / g.C;
+    const int c = 8 * (int)(k % C8);
+    const long p = k / C8;
     bf16_t* o = g.p + p * g.cs + g.coff + c;
-    *o = f2bf(bf2f(*o) * silu_grad_f(bf2f(z.p[p * z.cs + z.coff + c])));
+    float v[8], zz[8];
+    unpack8(load_u32x4(o), v);
+    unpack8(load_u32x4(z.p + p * z.cs + z.coff + c), zz);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] *= silu_grad_f(zz[e]);
+    store_u32x4(o, pack8(v));
   }
 }
 
-// head: out[pix][o] = sum_ci w[o][ci] a[pix][ci] + b[o]   (fp32 out, cout <= 8)
-__global__ void head_fwd(TV a, const float* __restrict__ w, const float* __restrict__ b, int cout,
-                         float* __restrict__ out, long npix) {
+// The 1x1 head (cout <= 8 outputs, C % 8 == 0 input channels): one pixel per
+// thread, channels moved as 16-byte vectors of 8 (load_u32x4).
+
+// head: out[pix][o] = b[o] + sum_ci w[o][ci] a[pix][ci] (fp32 out, ci ascending)
+__global__ void __launch_bounds__(256) head_fwd(TV a, const float* __restrict__ w, const float* __restrict__ b,
+                                                int cout, float* __restrict__ out, long npix) {
   const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (p >= npix) return;
   const bf16_t* ap = a.p + p * a.cs + a.coff;
-  for (int o = 0; o < cout; ++o) {
-    float s = b[o];
-    for (int c = 0; c < a.C; ++c) s += w[o * a.C + c] * bf2f(ap[c]);
-    out[p * cout + o] = s;
+  float s[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) s[o] = o < cout ? b[o] : 0.0f;
+  for (int c0 = 0; c0 < a.C; c0 += 8) {
+    float x[8];
+    unpack8(load_u32x4(ap + c0), x);
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+      if (o < cout) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[o] += w[o * a.C + c0 + j] * x[j];
+      }
   }
+  for (int o = 0; o < cout; ++o) out[p * cout + o] = s[o];
 }
 
 // head backward to its input, times SiLU'(z): ga[pix][ci] = SiLU'(z) sum_o gout[pix][o] w[o][ci]
-__global__ void head_bwd_data(const float* __restrict__ gout, const float* __restrict__ w, int cout, TV z, TV ga,
-                              long npix) {
+__global__ void __launch_bounds__(256) head_bwd_data(const float* __restrict__ gout, const float* __restrict__ w,
+                                                     int cout, TV z, TV ga, long npix) {
   const long p = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (p >= npix) return;
-  for (int c = 0; c < ga.C; ++c) {
-    float s = 0.0f;
-    for (int o = 0; o < cout; ++o) s += gout[p * cout + o] * w[o * ga.C + c];
-    s *= silu_grad_f(bf2f(z.p[p * z.cs + z.coff + c]));
-    ga.p[p * ga.cs + ga.coff + c] = f2bf(s);
+  float g[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) g[o] = o < cout ? gout[p * cout + o] : 0.0f;
+  const bf16_t* zp = z.p + p * z.cs + z.coff;
+  bf16_t* gp = ga.p + p * ga.cs + ga.coff;
+  const int C = ga.C;
+  for (int c0 = 0; c0 < C; c0 += 8) {
+    float zz[8];
+    unpack8(load_u32x4(zp + c0), zz);
+    u32x4 res;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float lo = 0.0f, hi = 0.0f;
+#pragma unroll
+      for (int o = 0; o < 8; ++o)
+        if (o < cout) {
+          lo += g[o] * w[o * C + c0 + 2 * j];
+          hi += g[o] * w[o * C + c0 + 2 * j + 1];
+        }
+      lo *= silu_grad_f(zz[2 * j]);
+      hi *= silu_grad_f(zz[2 * j + 1]);
+      res[j] = (unsigned)f2bf(lo) | ((unsigned)f2bf(hi) << 16);
+    }
+    *reinterpret_cast<u32x4*>(gp + c0) = res;
   }
 }
 
 // Per-block partials of gw[o][ci] = sum_pix gout[pix][o] a[pix][ci] ([nblk][cout * C],
-// cout * C <= 256): thread t takes entry k = t % K, K = cout * C, over the pixels
-// b0 + t / K, step 256 / K, of the block's range; lanes are added in order.
+// cout * C <= 256). Thread t takes the entries (o, 8 channels) e = t % E, E = cout * C / 8,
+// over the pixels b0 + t / E, step L = 256 / E, of the block's range; the L lane sums of
+// each entry are then added in lane order (deterministic).
 __global__ void __launch_bounds__(256) head_wgrad(const float* __restrict__ gout, TV a, int cout, long npix,
                                                   float* __restrict__ part) {
-  __shared__ float red[256];
+  __shared__ float red[256 * 8];
   const int t = threadIdx.x;
-  const int K = cout * a.C;
-  const int L = 256 / K;
-  const int k = t % K, l = t / K;
-  const int o = k / a.C, c = k - o * a.C;
+  const int C = a.C, C8 = C / 8, E = cout * C8, L = 256 / E, K = cout * C;
+  const int e = t % E, l = t / E;
+  const int o = e / C8, c0 = (e - o * C8) * 8;
   const long per = (npix + gridDim.x - 1) / gridDim.x;
   const long b0 = blockIdx.x * per, b1 = std::min(npix, b0 + per);
-  float s = 0.0f;
+  float s[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[j] = 0.0f;
   if (l < L)
-    for (long p = b0 + l; p < b1; p += L) s += gout[p * cout + o] * bf2f(a.p[p * a.cs + a.coff + c]);
-  red[t] = s;
+    for (long p = b0 + l; p < b1; p += L) {
+      const float g = gout[p * cout + o];
+      float x[8];
+      unpack8(load_u32x4(a.p + p * a.cs + a.coff + c0), x);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += g * x[j];
+    }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) red[t * 8 + j] = s[j];
   __syncthreads();
   if (t < K) {
+    const int oo = t / C, c = t - oo * C;
+    const int ee = oo * C8 + c / 8, jj = c % 8;
     float acc = 0.0f;
-    for (int q = 0; q < L; ++q) acc += red[q * K + t];
+    for (int q = 0; q < L; ++q) acc += red[(q * E + ee) * 8 + jj];
     part[(long)blockIdx.x * K + t] = acc;
   }
 }
@@ -779,11 +938,32 @@ void launch_conv_bwd_data(const ssn_net* n, const ConvL& c, TV gz, TV out, const
   launch_conv(n, ca, (long)gz.N * gz.H * gz.W, c.Ci);
 }
 
+// out[k] = sum over s < nsplit of part[s][k], k < nout
+void launch_reduce_splits(const ssn_net* n, const float* part, int nsplit, long nout, float* out) {
+  hipLaunchKernelGGL(reduce_splits, dim3((unsigned)((nout + 31) / 32)), dim3(256), 0, n->stream, part, nsplit, nout,
+                     out);
+}
+
+// Chunk geometry of the weight gradient for a W x H level: cw is the widest
+// multiple of 16 up to 64 that divides W; R the largest power of two with
+// R * cw <= kChunk, H % R == 0 and the x rows within kXLds.
+void wgrad_chunk(int W, int H, int& cw, int& R) {
+  cw = 16;
+  for (int c = 64; c >= 16; c -= 16)
+    if (W % c == 0) {
+      cw = c;
+      break;
+    }
+  R = 1;
+  while (2 * R * cw <= kChunk && H % (2 * R) == 0 && (2 * R + 2) * 32 * (cw + 8) <= kXLds) R *= 2;
+}
+
 void launch_wgrad(ssn_net* n, const ConvL& c, TV gz, TV x) {
-  const int cw = std::min(kCW, x.W);
-  const long nchunks = (long)x.N * x.H * (x.W / cw);
+  int cw = 16, R = 1;
+  wgrad_chunk(x.W, x.H, cw, R);
+  const long nchunks = (long)x.N * (x.H / R) * (x.W / cw);
   const int tci = (c.Ci + 31) / 32, tco = (c.Co + 31) / 32;
-  int nsplit = (int)std::max<long>(1, std::min<long>(nchunks, 256 / (tci * tco)));
+  int nsplit = (int)std::max<long>(1, std::min<long>(nchunks, 768 / (tci * tco)));
   while ((long)nsplit * c.Co * 9 * c.Ci > kWgradPartFloats) nsplit /= 2;
   WgradArgs wa;
   wa.gz = gz;
@@ -791,14 +971,14 @@ void launch_wgrad(ssn_net* n, const ConvL& c, TV gz, TV x) {
   wa.part = n->part;
   wa.nsplit = nsplit;
   wa.cw = cw;
+  wa.R = R;
   hipLaunchKernelGGL(conv3x3_wgrad, dim3(tci, tco, nsplit), dim3(576), 0, n->stream, wa);
   const long nw = (long)c.Co * 9 * c.Ci;
-  hipLaunchKernelGGL(reduce_splits, dim3(grid1(nw)), dim3(256), 0, n->stream, n->part, nsplit, nw, n->G + c.w_off);
+  launch_reduce_splits(n, n->part, nsplit, nw, n->G + c.w_off);
   // bias gradient: per-channel sums of gz
   hipLaunchKernelGGL(channel_sums, dim3(kPartBlocks, (c.Co + 255) / 256), dim3(256), 0, n->stream, gz,
                      (const float*)nullptr, 0, (long)gz.N * gz.H * gz.W, c.Co, n->cpart);
-  hipLaunchKernelGGL(reduce_splits, dim3(grid1(c.Co)), dim3(256), 0, n->stream, n->cpart, kPartBlocks, (long)c.Co,
-                     n->G + c.b_off);
+  launch_reduce_splits(n, n->cpart, kPartBlocks, (long)c.Co, n->G + c.b_off);
 }
 
 void pack_all(ssn_net* n) {
@@ -833,7 +1013,7 @@ int net_forward(ssn_net* n, const float* x, int nb) {
     TV skip = n->CAT[l].view(nb, cn, c);
     launch_conv_fwd(n, n->conv[enc_b(l)], n->AA[l].all(nb), n->ZB[l].all(nb), skip);
     TV pooled = n->Pin[l + 1].all(nb);
-    hipLaunchKernelGGL(avgpool2_fwd, dim3(grid1((long)nb * pooled.H * pooled.W * c)), dim3(256), 0, n->stream, skip,
+    hipLaunchKernelGGL(avgpool2_fwd, dim3(grid1((long)nb * pooled.H * pooled.W * c / 8)), dim3(256), 0, n->stream, skip,
                        pooled);
   }
   launch_conv_fwd(n, n->conv[mid_a(n)], n->Pin[L].all(nb), n->ZMa.all(nb), n->AMa.all(nb));
@@ -842,7 +1022,7 @@ int net_forward(ssn_net* n, const float* x, int nb) {
     const int cn = n->ch[l + 1];
     TV prev = l == L - 1 ? n->AMb.all(nb) : n->ADb[l + 1].all(nb);
     TV up = n->CAT[l].view(nb, 0, cn);
-    hipLaunchKernelGGL(upsample2_fwd, dim3(grid1((long)nb * up.H * up.W * cn)), dim3(256), 0, n->stream, prev, up);
+    hipLaunchKernelGGL(upsample2_fwd, dim3(grid1((long)nb * up.H * up.W * cn / 8)), dim3(256), 0, n->stream, prev, up);
     launch_conv_fwd(n, n->conv[dec_a(n, l)], n->CAT[l].all(nb), n->ZDa[l].all(nb), n->ADa[l].all(nb));
     launch_conv_fwd(n, n->conv[dec_b(n, l)], n->ADa[l].all(nb), n->ZDb[l].all(nb), n->ADb[l].all(nb));
   }
@@ -860,14 +1040,12 @@ int net_backward(ssn_net* n, const float* target, int nb, double* loss) {
   // head
   hipLaunchKernelGGL(head_wgrad, dim3(kPartBlocks), dim3(256), 0, n->stream, n->GOUT, n->ADb[0].all(nb), n->cout, npix,
                      n->cpart);
-  hipLaunchKernelGGL(reduce_splits, dim3(grid1((long)n->cout * n->ch[0])), dim3(256), 0, n->stream, n->cpart,
-                     kPartBlocks, (long)n->cout * n->ch[0], n->G + n->hw_off);
+  launch_reduce_splits(n, n->cpart, kPartBlocks, (long)n->cout * n->ch[0], n->G + n->hw_off);
   TV none;
   none.p = nullptr;
   hipLaunchKernelGGL(channel_sums, dim3(kPartBlocks), dim3(256), 0, n->stream, none, n->GOUT, n->cout, npix, n->cout,
                      n->cpart);
-  hipLaunchKernelGGL(reduce_splits, dim3(1), dim3(256), 0, n->stream, n->cpart, kPartBlocks, (long)n->cout,
-                     n->G + n->hb_off);
+  launch_reduce_splits(n, n->cpart, kPartBlocks, (long)n->cout, n->G + n->hb_off);
   hipLaunchKernelGGL(head_bwd_data, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, n->stream, n->GOUT,
                      n->P + n->hw_off, n->cout, n->ZDb[0].all(nb), n->gT1[0].all(nb), npix);
   // decoder, top level first
@@ -884,8 +1062,8 @@ int net_backward(ssn_net* n, const float* target, int nb, double* loss) {
     TV gup = n->gCAT[l].view(nb, 0, cn);
     TV dst = l == L - 1 ? n->gM2.all(nb) : n->gT1[l + 1].all(nb);
     TV zsrc = l == L - 1 ? n->ZMb.all(nb) : n->ZDb[l + 1].all(nb);
-    hipLaunchKernelGGL(upsample2_bwd, dim3(grid1((long)nb * dst.H * dst.W * cn)), dim3(256), 0, n->stream, gup, dst);
-    hipLaunchKernelGGL(silu_bwd_inplace, dim3(grid1((long)nb * dst.H * dst.W * cn)), dim3(256), 0, n->stream, dst,
+    hipLaunchKernelGGL(upsample2_bwd, dim3(grid1((long)nb * dst.H * dst.W * cn / 8)), dim3(256), 0, n->stream, gup, dst);
+    hipLaunchKernelGGL(silu_bwd_inplace, dim3(grid1((long)nb * dst.H * dst.W * cn / 8)), dim3(256), 0, n->stream, dst,
                        zsrc);
   }
   // bottleneck
@@ -902,9 +1080,9 @@ int net_backward(ssn_net* n, const float* target, int nb, double* loss) {
   for (int l = L - 1; l >= 0; --l) {
     const int c = n->ch[l], cn = n->ch[l + 1];
     TV gS = n->gCAT[l].view(nb, cn, c);
-    hipLaunchKernelGGL(avgpool2_bwd, dim3(grid1((long)nb * gS.H * gS.W * c)), dim3(256), 0, n->stream,
+    hipLaunchKernelGGL(avgpool2_bwd, dim3(grid1((long)nb * gS.H * gS.W * c / 8)), dim3(256), 0, n->stream,
                        n->gP[l + 1].all(nb), gS, 1);
-    hipLaunchKernelGGL(silu_bwd_inplace, dim3(grid1((long)nb * gS.H * gS.W * c)), dim3(256), 0, n->stream, gS,
+    hipLaunchKernelGGL(silu_bwd_inplace, dim3(grid1((long)nb * gS.H * gS.W * c / 8)), dim3(256), 0, n->stream, gS,
                        n->ZB[l].all(nb));
     const ConvL& cb = n->conv[enc_b(l)];
     const ConvL& ca = n->conv[enc_a(l)];
