@@ -312,8 +312,8 @@ __global__ void __launch_bounds__(576) conv3x3_wgrad(WgradArgs a) {
     __syncthreads();
     if (tap < 9) {
       // B of tap (dy, dx) starts dx + 1 elements past a 16-byte boundary: it is
-      // read as two aligned 16-byte words and shifted by whole elements (LDS
-      // vector reads must be aligned)
+      // read as two aligned 16-byte words and shifted by whole elements, so
+      // every vector LDS read is aligned
       const int sh = dx + 1;
       for (int rr = 0; rr < R; ++rr) {
         const u32x4* ap = reinterpret_cast<const u32x4*>(gzT + r * kGP + rr * cw + half * 8);
