@@ -214,23 +214,26 @@ __global__ void __launch_bounds__(64 * WCO * WPX) conv3x3_tiled(ConvArgs a) {
         for (int q = 0; q < R; ++q) {
           const bf16x8 B =
               *reinterpret_cast<const bf16x8*>(sin_ + ((q + dy) * PW + wj * 32 + r + dx) * kKP + ks + half * 8);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[q], 0, 0, 0);
+          // D = input x weights^T: rows are pixels, columns output channels
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(B, A, acc[q], 0, 0, 0);
         }
       }
     }
   }
-  // D[row][col]: lane holds col = r (pixel) and rows 8 (v / 4) + 4 half + v % 4 (channels)
-  const int x = x0 + wj * 32 + r;
+  // D[row][col]: lane holds col = r (output channel) and rows 8 (v / 4) + 4 half + v % 4
+  // (pixels), so each store of a row writes 32 neighbouring channels of one pixel
+  const int co = co0 + wi * 32 + r;
+  if (co >= a.Co) return;
+  const float bias = (a.mode == 0 && a.bias) ? a.bias[co] : 0.0f;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int y = y0 + q;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int co = co0 + wi * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
-      if (co >= a.Co) continue;
+      const int x = x0 + wj * 32 + (v >> 2) * 8 + half * 4 + (v & 3);
       float val = acc[q][v];
       if (a.mode == 0) {
-        const float z = val + (a.bias ? a.bias[co] : 0.0f);
+        const float z = val + bias;
         if (a.out_z.p) a.out_z.p[tv_at(a.out_z, n, y, x) + co] = f2bf(z);
         a.out.p[tv_at(a.out, n, y, x) + co] = f2bf(silu_f(z));
       } else {
