@@ -93,7 +93,7 @@ def run_unet(args, wl):
            "data": "synthetic", "config": {"workload": "unet256", **wl},
            "roofline": {"bound": "mfma", "achieved": round(tfl, 2), "peak": BF16_DENSE_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(tfl / BF16_DENSE_PEAK_TFLOPS, 4), "traffic": None,
-                        "kernel": "conv3x3_mfma + conv3x3_wgrad (whole training step)",
+                        "kernel": "conv3x3_tiled + conv3x3_mfma + conv3x3_wgrad (whole training step)",
                         "inference_TFLOPs": round(tfl_f, 2)},
            "cpu_baseline": None}
     print(json.dumps(out), flush=True)
