@@ -144,12 +144,13 @@ def time_to_target(solver, start, e_target, max_steps):
 
 
 def ab_compare(net, insts, tol=1e-6, sigmas=(3.0,), pin=0.0, ref_rel_e_tol=1e-9, ref_window=100,
-               ref_max_steps=50000, max_steps=50000, device="cuda:0", log=None):
+               ref_max_steps=50000, max_steps=50000, coarse_tols=(), device="cuda:0", log=None):
     """For each instance: a long ansatz-start run gives E_ref (its stalled energy);
     then the ansatz start and the learned start (for each envelope width sigma,
-    with the given pin radius) are flowed until E <= E_ref + tol |E_ref|. Returns
-    per-instance records; the learned start's time includes building the input
-    and running the network."""
+    with the given pin radius) are flowed until E <= E_ref + tol |E_ref|, and
+    again for each coarser tolerance in coarse_tols (keys suffixed "~tol").
+    Returns per-instance records; the learned start's time includes building the
+    input and running the network."""
     import torch
     m0 = insts[0]
     x = torch.empty((1, m0.Ny, m0.Nx, 2), dtype=torch.float32, device=device)
@@ -172,6 +173,10 @@ def ab_compare(net, insts, tol=1e-6, sigmas=(3.0,), pin=0.0, ref_rel_e_tol=1e-9,
         rec = {"kappa": m.kappa, "n_vortices": len(m.centres), "E_ref": E_ref, "ref_steps": ref["step"],
                "ansatz_s": ta, "ansatz_steps": ra["step"], "ansatz_reached": ra["reason"] == "target",
                "ansatz_E": ra["energy"], "ansatz_E0": s.energy_grad(want_grad=False)[0]}
+        for ct in coarse_tols:
+            tc, rc = time_to_target(s, ansatz_start, E_ref + ct * abs(E_ref), max_steps)
+            rec.update({f"ansatz_s~{ct:g}": tc, f"ansatz_steps~{ct:g}": rc["step"],
+                        f"ansatz_reached~{ct:g}": rc["reason"] == "target"})
         for sg in sigmas:
             def learned_start():
                 ss.ss_learned_input(s.ctx, m.centres, m.kappa, x.data_ptr())
@@ -183,6 +188,10 @@ def ab_compare(net, insts, tol=1e-6, sigmas=(3.0,), pin=0.0, ref_rel_e_tol=1e-9,
             rec.update({f"learned_s@{sg}": tl, f"learned_steps@{sg}": rl["step"],
                         f"learned_reached@{sg}": rl["reason"] == "target", f"learned_E@{sg}": rl["energy"],
                         f"learned_E0@{sg}": s.energy_grad(want_grad=False)[0]})
+            for ct in coarse_tols:
+                tc, rc = time_to_target(s, learned_start, E_ref + ct * abs(E_ref), max_steps)
+                rec.update({f"learned_s@{sg}~{ct:g}": tc, f"learned_steps@{sg}~{ct:g}": rc["step"],
+                            f"learned_reached@{sg}~{ct:g}": rc["reason"] == "target"})
         recs.append(rec)
         s.close()
         if log and (k + 1) % 8 == 0:
@@ -190,27 +199,32 @@ def ab_compare(net, insts, tol=1e-6, sigmas=(3.0,), pin=0.0, ref_rel_e_tol=1e-9,
     return recs
 
 
-def summarise(recs, sigma):
+def summarise(recs, sigma, tol=None, coarse=None):
     """Median time and step ratios (learned / ansatz) over the instances both starts
-    brought to the target, the win fraction, and the misses of the learned start."""
-    key = f"@{sigma}"
-    both = [r for r in recs if r["ansatz_reached"] and r["learned_reached" + key]]
-    ratio = [r["learned_s" + key] / r["ansatz_s"] for r in both]
-    sratio = [r["learned_steps" + key] / max(1, r["ansatz_steps"]) for r in both]
-    return {"sigma": sigma, "instances": len(recs), "both_reached": len(both),
+    brought to the target, the win fraction, and the misses of the learned start;
+    for a coarse tolerance of ab_compare when coarse is given."""
+    sfx = "" if coarse is None else f"~{coarse:g}"
+    key = f"@{sigma}" + sfx
+    both = [r for r in recs if r["ansatz_reached" + sfx] and r["learned_reached" + key]]
+    ratio = [r["learned_s" + key] / r["ansatz_s" + sfx] for r in both]
+    sratio = [r["learned_steps" + key] / max(1, r["ansatz_steps" + sfx]) for r in both]
+    return {"sigma": sigma, "tol": coarse if coarse is not None else tol, "instances": len(recs),
+            "both_reached": len(both),
             "learned_missed": sum(1 for r in recs if not r["learned_reached" + key]),
-            "ansatz_missed": sum(1 for r in recs if not r["ansatz_reached"]),
+            "ansatz_missed": sum(1 for r in recs if not r["ansatz_reached" + sfx]),
             "median_time_ratio": float(np.median(ratio)) if ratio else None,
             "median_step_ratio": float(np.median(sratio)) if sratio else None,
             "learned_win_fraction": float(np.mean([x < 1 for x in ratio])) if ratio else None,
-            "median_ansatz_s": float(np.median([r["ansatz_s"] for r in both])) if both else None,
+            "median_ansatz_steps": float(np.median([r["ansatz_steps" + sfx] for r in both])) if both else None,
+            "median_ansatz_s": float(np.median([r["ansatz_s" + sfx] for r in both])) if both else None,
             "median_learned_s": float(np.median([r["learned_s" + key] for r in both])) if both else None,
-            "total_ansatz_s": float(sum(r["ansatz_s"] for r in recs)),
+            "total_ansatz_s": float(sum(r["ansatz_s" + sfx] for r in recs)),
             "total_learned_s": float(sum(r["learned_s" + key] for r in recs))}
 
 
 def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20, batch=8, lr=1e-3, seed=0,
-                 tol=1e-6, sigmas=(0.0, 3.0), target_steps=150, pin=0.0, device="cuda:0", log=print):
+                 tol=1e-6, sigmas=(0.0, 3.0), target_steps=150, pin=0.0, coarse_tols=(), device="cuda:0",
+                 log=print):
     """Data -> training -> A/B on held-out instances; returns a summary dict."""
     import torch
     t0 = time.perf_counter()
@@ -238,8 +252,10 @@ def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20
         log(f"[infer] {infer_ms:.3f} ms per image at batch 1")
     del X, T
     torch.cuda.empty_cache()
-    recs = ab_compare(net, test_insts, tol=tol, sigmas=sigmas, pin=pin, device=device, log=log)
-    out = {"summary": [summarise(recs, sg) for sg in sigmas]}
+    recs = ab_compare(net, test_insts, tol=tol, sigmas=sigmas, pin=pin, coarse_tols=coarse_tols, device=device,
+                      log=log)
+    out = {"summary": [summarise(recs, sg, tol=tol) for sg in sigmas] +
+           [summarise(recs, sg, coarse=ct) for ct in coarse_tols for sg in sigmas]}
     out.update({"n_train": n_train, "n_test": n_test, "side": side, "levels": levels, "base": base,
                 "epochs": epochs, "batch": batch, "lr": lr, "data_s": t_data,
                 "data_median_steps": float(np.median(steps)), "train_s": t_train, "train_TFLOPs": tflops,
@@ -266,11 +282,14 @@ def main(argv=None):
     ap.add_argument("--target-steps", type=int, default=150, help="flow steps behind each training target")
     ap.add_argument("--pin", type=float, default=0.5, help="radius that pins the zeros of psi at the centres")
     ap.add_argument("--sigmas", default="3", help="envelope widths of the learned start (comma list)")
+    ap.add_argument("--coarse-tols", default="1e-3,1e-4",
+                    help="coarser relative energy tolerances also timed (comma list, may be empty)")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     a = ap.parse_args(argv)
     sig = tuple(float(v) for v in a.sigmas.split(","))
+    coarse = tuple(float(v) for v in a.coarse_tols.split(",") if v.strip())
     res = run_pipeline(a.n_train, a.n_test, a.side, a.levels, a.base, a.epochs, a.batch, a.lr, sigmas=sig,
-                       target_steps=a.target_steps, pin=a.pin, log=lambda m: print(m, flush=True))
+                       target_steps=a.target_steps, pin=a.pin, coarse_tols=coarse, log=lambda m: print(m, flush=True))
     brief = {k: v for k, v in res.items() if k not in ("records", "losses")}
     print(json.dumps(brief), flush=True)
     if a.out:
