@@ -149,14 +149,37 @@ def ss_tile(i):
 STAGE_SOURCES = ["ss_internal.hpp", "ss_theory.hpp", "ss_kernels.hpp", "ss_api.hip"]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank lines (a comment edit leaves the
+    kernels, and so their counters, unchanged)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        if text.startswith("//", i):
+            i = text.find("\n", i)
+            i = n if i < 0 else i
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif text[i] in "\"'":
+            j = i + 1
+            while j < n and text[j] != text[i]:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(text[i])
+            i += 1
+    return "\n".join(line.rstrip() for line in "".join(out).splitlines() if line.strip())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the sources the stage kernels are built from (traffic counters
-    taken on other sources are not reported)."""
+    """Hash of the code (comments stripped) the stage kernels are built from
+    (traffic counters taken on other code are not reported)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_24370_amd", "csrc")
     for f in STAGE_SOURCES:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -297,10 +297,11 @@ int ss_autotune(ss_ctx* ctx, int n_steps, double* ms_out);
 /* ------------------------------------------------------------ batching
  * Many independent minimisations (uneven lattices and couplings, one theory
  * and dtype) advanced together: each flow pass is one launch over a flat list
- * of the tiles of all members still running, with per-member reductions,
- * arrest tests and stop rules on the device. ss_batch_minimise replays a
- * captured HIP graph of stop->graph_steps steps and drops stopped members'
- * tiles from the list between replays. Each member is an ss_ctx carved from
+ * of work units (column segments of tiles) of all members still running,
+ * followed, for the reducing passes, by one launch that takes every member's
+ * reduction, arrest test and stop rules on the device. ss_batch_minimise
+ * replays a captured HIP graph of stop->graph_steps steps and drops stopped
+ * members' units from the list between replays. Each member is an ss_ctx carved from
  * the batch workspace (ss_batch_member): set its field with ss_set_field or
  * ss_init_ansatz and read results with the single-context calls; do not
  * destroy it separately. */

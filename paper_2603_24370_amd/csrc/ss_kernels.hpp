@@ -1,7 +1,8 @@
 // HIP kernels of the arrested-Newton-flow hot path (gfx950).
 //
 // One RK4 step (eq. (3), classical RK4 on (phi, phidot), dt = C h) is four
-// launches of stage_pass<..., P1..P4>. Each launch stages the stage point
+// launches of stage_pass<..., P1..P4> (or P1 and stage_pass_fused, which does
+// P2..P4 in one launch). Each launch stages the stage point
 // S = phi + c_v v + c_a a of a (TX + 4) x (TY + 4) tile (halo 2, Sec. 3.1) in
 // LDS, evaluates the Euler-Lagrange gradient with eq. (1)-(2) from LDS, and
 // writes only what the next pass needs:
@@ -14,9 +15,9 @@
 // chiral magnet every stage point is put back on the unit sphere and G is
 // projected on its tangent plane; phi' is renormalised and v' projected.
 // P1 also reduces E_h (FP64 from the stored values), max |G| and a non-finite
-// count; its last workgroup sums the per-workgroup partials in a fixed order,
-// applies the arrest test E > E_prev (strict) and the stop rules, and
-// advances the step counter, all on the device.
+// count to one partial per workgroup; pass_finalise, launched after it, sums
+// the partials in a fixed order, applies the arrest test E > E_prev (strict)
+// and the stop rules, and advances the step counter, all on the device.
 #pragma once
 
 #include "ss_internal.hpp"
