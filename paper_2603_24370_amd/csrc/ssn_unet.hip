@@ -153,19 +153,19 @@ __global__ void __launch_bounds__(64 * WB) conv3x3_mfma(ConvArgs a) {
 // image rows; wave (i, j) computes 32 output channels (co0 + 32 i ..) x 32 pixels
 // (x0 + 32 j ..) of each of the rows y0 .. y0 + R - 1. Input channels are taken
 // in chunks of 32: the chunk's input patch (R + 2 rows x (32 WPX + 2) pixels,
-// zero outside the image) and its weights (32 WCO rows x 9 taps) are staged in
-// LDS, each entry padded to kKP channels so that lanes reading neighbouring
-// pixels or rows fall in different banks; every MFMA takes both operands from
-// LDS and each weight fragment serves R rows. Requires W % (32 WPX) == 0,
-// H % R == 0, in.C % 16 == 0 and, for WCO = 2, Co % 64 == 0 (weight rows exist
-// up to gridDim.y * 32 WCO).
+// zero outside the image) is staged in LDS, each entry padded to kKP channels
+// so that lanes reading neighbouring pixels or rows fall in different banks.
+// The weight fragments (a few KB per layer, shared by every workgroup) are read
+// straight from global memory through the caches, which leaves LDS to the patch
+// (one more workgroup per CU than staging them); each serves R rows. Requires
+// W % (32 WPX) == 0, H % R == 0, in.C % 16 == 0 and, for WCO = 2, Co % 64 == 0
+// (weight rows exist up to gridDim.y * 32 WCO).
 constexpr int kKC = 32, kKP = 40;
 
 template <int WCO, int WPX, int R>
 __global__ void __launch_bounds__(64 * WCO * WPX) conv3x3_tiled(ConvArgs a) {
   constexpr int NT = 64 * WCO * WPX, PX = 32 * WPX, PW = PX + 2, CO = 32 * WCO, PR = R + 2;
   __shared__ __align__(16) bf16_t sin_[PR * PW * kKP];
-  __shared__ __align__(16) bf16_t sw[9 * CO * kKP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave / WPX, wj = wave - wi * WPX;
   const int r = lane & 31, half = lane >> 5;
@@ -198,18 +198,13 @@ __global__ void __launch_bounds__(64 * WCO * WPX) conv3x3_tiled(ConvArgs a) {
         val = *reinterpret_cast<const bf16x8*>(a.in.p + tv_at(a.in, n, yy, xx) + c0 + v * 8);
       *reinterpret_cast<bf16x8*>(sin_ + (row * PW + px) * kKP + v * 8) = val;
     }
-    for (int it = tid; it < CO * 9 * nv; it += NT) {
-      const int v = it % nv, q = it / nv;
-      const int t = q % 9, co = q / 9;
-      const bf16x8 val = *reinterpret_cast<const bf16x8*>(a.w + ((long)(co0 + co) * 9 + t) * Ci + c0 + v * 8);
-      *reinterpret_cast<bf16x8*>(sw + (t * CO + co) * kKP + v * 8) = val;
-    }
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int dy = t / 3, dx = t % 3;
       for (int ks = 0; ks < kc; ks += 16) {
-        const bf16x8 A = *reinterpret_cast<const bf16x8*>(sw + (t * CO + wi * 32 + r) * kKP + ks + half * 8);
+        const bf16x8 A =
+            *reinterpret_cast<const bf16x8*>(a.w + ((long)(co0 + wi * 32 + r) * 9 + t) * Ci + c0 + ks + half * 8);
 #pragma unroll
         for (int q = 0; q < R; ++q) {
           const bf16x8 B =
