@@ -977,10 +977,11 @@ int batch_nlaunch(const ss_batch* b) { return (int)std::min<long>(round_up(b->nu
 
 // (Re)build, for the batch's tile shape, the per-member tile and unit counts,
 // the units, the member descriptors and a full work list. Units are column
-// segments: seg is the tile count over the launch's workgroups (as for a single
-// lattice), and each member's tile columns are cut into ceil(nty / seg)
-// segments of near-equal length, so that units differ little in work. A
-// member's units are numbered row-major over (segment row, tile column).
+// segments: seg is half the tile count per workgroup of the launch (two or
+// more units per workgroup balance uneven members better than one; measured),
+// and each member's tile columns are cut into ceil(nty / seg) segments of
+// near-equal length, so that units differ little in work. A member's units are
+// numbered row-major over (segment row, tile column).
 int batch_build_tables(ss_batch* b) {
   b->ntiles_of.assign(b->n, 0);
   b->unit0_of.assign(b->n, 0);
@@ -996,7 +997,7 @@ int batch_build_tables(ss_batch* b) {
   if (tot > b->max_tiles) return fail(SS_EINVAL, "batch tile table overflow");
   b->ntiles_total = (int)tot;
   const long groups = std::min<long>(round_up(tot, 8), kMaxGroups);
-  const int seg = (int)std::max<long>(1, tot / groups);
+  const int seg = (int)std::max<long>(1, tot / (2 * groups));
   std::vector<BatchUnit> un;
   un.reserve(tot);
   for (int i = 0; i < b->n; ++i) {
