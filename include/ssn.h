@@ -61,17 +61,22 @@ int ssn_get_grads(ssn_net* net, float* host, long count);
 /* Forward pass of n <= N images x (n, H, W, cin); the output (n, H, W, cout)
  * is kept for ssn_backward and copied to out if out != NULL. */
 int ssn_forward(ssn_net* net, const float* x, int n, float* out);
-/* Gradients of the mean squared error between the last output and target
- * (n, H, W, cout); *loss (may be NULL) receives the loss (synchronises). */
 /* As ssn_forward (out required), but the forward pass is captured as a HIP
  * graph on the first call for a given (x, n, out) and replayed afterwards (one
  * launch instead of one per kernel); a call with other pointers or n captures
  * anew. The graph reads the weights at replay, so training between calls is
  * seen. For callers that repeat small forwards on fixed buffers. */
 int ssn_forward_graph(ssn_net* net, const float* x, int n, float* out);
+/* Gradients of the mean squared error between the last output and target
+ * (n, H, W, cout); *loss (may be NULL) receives the loss (synchronises). */
 int ssn_backward(ssn_net* net, const float* target, int n, double* loss);
 /* One Adam step (Kingma and Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. */
 int ssn_adam_step(ssn_net* net, float lr);
+/* Clip the gradient by its global L2 norm in every later ssn_adam_step: the
+ * step uses g * min(1, max_norm / |g|), |g| summed in FP64 in a fixed order on
+ * the device (no host synchronisation). max_norm = 0 (the default) turns it
+ * off; negative or non-finite values return SS_EINVAL. */
+int ssn_set_grad_clip(ssn_net* net, float max_norm);
 /* forward + backward + Adam. */
 int ssn_train_step(ssn_net* net, const float* x, const float* target, int n, float lr, double* loss);
 /* Multiply-add flops (2 per MAC) of one image's forward and backward passes. */

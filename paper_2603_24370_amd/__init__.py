@@ -78,7 +78,7 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_learned_targets", "ss_init_learned"]
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
-               "ssn_adam_step",
+               "ssn_adam_step", "ssn_set_grad_clip",
                "ssn_train_step", "ssn_flops", "ssn_last_error"]
 
 _lib = None
@@ -568,6 +568,7 @@ def _ssn_lib():
     L.ssn_forward_graph.argtypes = [vp, vp, i, vp]
     L.ssn_backward.argtypes = [vp, vp, i, dp]
     L.ssn_adam_step.argtypes = [vp, ctypes.c_float]
+    L.ssn_set_grad_clip.argtypes = [vp, ctypes.c_float]
     L.ssn_train_step.argtypes = [vp, vp, vp, i, ctypes.c_float, dp]
     L.ssn_flops.argtypes = [vp, dp, dp]
     L.ssn_last_error.argtypes = []
@@ -672,6 +673,10 @@ class Net:
 
     def adam_step(self, lr):
         _ncheck(_ssn_lib().ssn_adam_step(self.net, float(lr)))
+
+    def set_grad_clip(self, max_norm):
+        """Global L2-norm gradient clipping of later Adam steps (0 turns it off)."""
+        _ncheck(_ssn_lib().ssn_set_grad_clip(self.net, float(max_norm)))
 
     def train_step(self, x, target, lr, want_loss=True):
         x, t = self._dev(x), self._dev(target)

@@ -653,12 +653,47 @@ __global__ void __launch_bounds__(256) mse_fwd_bwd(const float* __restrict__ out
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// Adam (Kingma and Ba 2015) with bias correction; grads g, moments m, v, master p (fp32)
+// gradient clipping by global L2 norm: per-block partial sums of g^2 (FP64,
+// grid-stride ranges, tree order), then scale = min(1, max_norm / |g|)
+__global__ void __launch_bounds__(256) grad_sq_partials(const float* __restrict__ g, long n,
+                                                        double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < n; k += (long)gridDim.x * 256L) s += (double)g[k] * g[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) grad_clip_scale(const double* __restrict__ part, int nblk, float max_norm,
+                                                       float* __restrict__ scale) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += 256) s += part[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double norm = sqrt(red[0]);
+    *scale = norm > (double)max_norm ? (float)((double)max_norm / norm) : 1.0f;
+  }
+}
+
+// Adam (Kingma and Ba 2015) with bias correction on the gradient times *gscale
+// (gscale nullable: 1); grads g, moments m, v, master p (fp32)
 __global__ void adam_update(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                            const float* __restrict__ g, long n, float lr, float b1, float b2, float eps, float c1,
-                            float c2) {
+                            const float* __restrict__ g, const float* __restrict__ gscale, long n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+  const float sc = gscale ? *gscale : 1.0f;
   for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-    const float gk = g[k];
+    const float gk = g[k] * sc;
     const float mk = b1 * m[k] + (1.0f - b1) * gk;
     const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
     m[k] = mk;
@@ -759,6 +794,9 @@ struct ssn_net {
   HT gM1, gM2;
   float *OUT, *GOUT, *part, *cpart;
   double* lpart;
+  double* npart;   // per-block partial sums of the squared gradient
+  float* gscale;   // gradient scale of the clipped Adam step (device)
+  float clip = 0.0f;  // global L2 clipping norm of the Adam step (0: off)
   int adam_t;
   size_t bytes;
 };
@@ -814,6 +852,8 @@ size_t net_carve(ssn_net* n, char* base) {
   n->part = (float*)take(kWgradPartFloats * 4);
   n->cpart = (float*)take((size_t)kPartBlocks * 1024 * 4);
   n->lpart = (double*)take(256 * 8);
+  n->npart = (double*)take(kPartBlocks * 8);
+  n->gscale = (float*)take(256);
   return off;
 }
 
@@ -1277,10 +1317,22 @@ int ssn_adam_step(ssn_net* n, float lr) {
   n->adam_t += 1;
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.0f - std::pow(b1, (float)n->adam_t), c2 = 1.0f - std::pow(b2, (float)n->adam_t);
-  hipLaunchKernelGGL(adam_update, dim3(grid1(n->np)), dim3(256), 0, n->stream, n->P, n->M, n->V, n->G, n->np, lr, b1,
-                     b2, 1e-8f, c1, c2);
+  const float* gs = nullptr;
+  if (n->clip > 0.0f) {
+    hipLaunchKernelGGL(grad_sq_partials, dim3(kPartBlocks), dim3(256), 0, n->stream, n->G, n->np, n->npart);
+    hipLaunchKernelGGL(grad_clip_scale, dim3(1), dim3(256), 0, n->stream, n->npart, kPartBlocks, n->clip, n->gscale);
+    gs = n->gscale;
+  }
+  hipLaunchKernelGGL(adam_update, dim3(grid1(n->np)), dim3(256), 0, n->stream, n->P, n->M, n->V, n->G, gs, n->np, lr,
+                     b1, b2, 1e-8f, c1, c2);
   pack_all(n);
   SN_HIP(hipGetLastError());
+  return SS_OK;
+}
+
+int ssn_set_grad_clip(ssn_net* n, float max_norm) {
+  if (!n || !(max_norm >= 0.0f) || !std::isfinite(max_norm)) return nfail(SS_EINVAL, "bad clipping norm");
+  n->clip = max_norm;
   return SS_OK;
 }
 

@@ -101,11 +101,13 @@ def generate_dataset(insts, batch=64, rel_e_tol=0.0, window=0, max_steps=150, de
     return X, T, stats
 
 
-def train(net, X, T, epochs=10, batch=8, lr=1e-3, seed=0, log=None):
-    """Adam on the mean squared error; returns the per-epoch mean losses and the
-    achieved training rate (TFLOP/s of the MFMA convolutions)."""
+def train(net, X, T, epochs=10, batch=8, lr=1e-3, seed=0, clip=0.0, log=None):
+    """Adam on the mean squared error (gradient clipped to global L2 norm clip
+    if clip > 0); returns the per-epoch mean losses, the achieved training rate
+    (TFLOP/s of the MFMA convolutions) and the wall time."""
     import torch
     n = X.shape[0]
+    net.set_grad_clip(clip)
     rng = np.random.default_rng(seed)
     f_fwd, f_bwd = net.flops()
     losses = []
@@ -223,8 +225,8 @@ def summarise(recs, sigma, tol=None, coarse=None):
 
 
 def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20, batch=8, lr=1e-3, seed=0,
-                 tol=1e-6, sigmas=(0.0, 3.0), target_steps=150, pin=0.0, coarse_tols=(), device="cuda:0",
-                 log=print):
+                 tol=1e-6, sigmas=(0.0, 3.0), target_steps=150, pin=0.0, coarse_tols=(), clip=0.0,
+                 device="cuda:0", log=print):
     """Data -> training -> A/B on held-out instances; returns a summary dict."""
     import torch
     t0 = time.perf_counter()
@@ -237,7 +239,7 @@ def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20
         log(f"[data] target mean square {zero_mse:.4e} (the loss of predicting no correction)")
     net = ss.Net(levels=levels, base=base, cin=2, cout=4, N=batch, H=side, W=side, device=device)
     net.set_weights(init_weights(seed, levels, base, 2, 4))
-    losses, tflops, t_train = train(net, X, T, epochs=epochs, batch=batch, lr=lr, seed=seed, log=log)
+    losses, tflops, t_train = train(net, X, T, epochs=epochs, batch=batch, lr=lr, seed=seed, clip=clip, log=log)
     # network time of one learned start (batch of one image), after a warm-up
     x1 = X[:1].contiguous()
     o1 = torch.empty((1, side, side, 4), dtype=torch.float32, device=device)
@@ -260,7 +262,7 @@ def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20
                 "epochs": epochs, "batch": batch, "lr": lr, "data_s": t_data,
                 "data_median_steps": float(np.median(steps)), "train_s": t_train, "train_TFLOPs": tflops,
                 "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1], "losses": losses, "tol": tol,
-                "target_steps": target_steps, "target_mean_square": zero_mse, "pin": pin,
+                "target_steps": target_steps, "target_mean_square": zero_mse, "pin": pin, "clip": clip,
                 "inference_ms_batch1": infer_ms,
                 "records": recs})
     net.close()
@@ -282,6 +284,7 @@ def main(argv=None):
     ap.add_argument("--target-steps", type=int, default=150, help="flow steps behind each training target")
     ap.add_argument("--pin", type=float, default=0.5, help="radius that pins the zeros of psi at the centres")
     ap.add_argument("--sigmas", default="3", help="envelope widths of the learned start (comma list)")
+    ap.add_argument("--clip", type=float, default=1.0, help="global L2 gradient clipping norm (0: off)")
     ap.add_argument("--coarse-tols", default="1e-3,1e-4",
                     help="coarser relative energy tolerances also timed (comma list, may be empty)")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
@@ -289,7 +292,8 @@ def main(argv=None):
     sig = tuple(float(v) for v in a.sigmas.split(","))
     coarse = tuple(float(v) for v in a.coarse_tols.split(",") if v.strip())
     res = run_pipeline(a.n_train, a.n_test, a.side, a.levels, a.base, a.epochs, a.batch, a.lr, sigmas=sig,
-                       target_steps=a.target_steps, pin=a.pin, coarse_tols=coarse, log=lambda m: print(m, flush=True))
+                       target_steps=a.target_steps, pin=a.pin, coarse_tols=coarse, clip=a.clip,
+                       log=lambda m: print(m, flush=True))
     brief = {k: v for k, v in res.items() if k not in ("records", "losses")}
     print(json.dumps(brief), flush=True)
     if a.out:

@@ -134,6 +134,38 @@ def test_production_shape_matches_oracle(ss):
     net.close()
 
 
+@pytest.mark.parametrize("regime", ["clipped", "unclipped"])
+def test_adam_step_clips_the_global_gradient_norm(ss, regime):
+    """The first Adam step moves each weight by lr * g s / (|g s| + eps) with
+    s = min(1, max_norm / |g|): with max_norm far above |g| this is the plain
+    step; with max_norm so small that |g s| << eps the step is linear in s, which
+    checks the FP64 norm and the scale."""
+    P, x, t, net = _setup(ss, seed=2)
+    net.forward(x)
+    net.backward(t)
+    g = net.get_grads().astype(np.float64)
+    p0 = net.get_weights().astype(np.float64)
+    norm = float(np.linalg.norm(g))
+    assert norm > 0
+    print("[clip] gradient norm", norm, flush=True)
+    max_norm = 10.0 * norm if regime == "unclipped" else norm * 1e-10 / float(np.abs(g).max())
+    net.set_grad_clip(max_norm)
+    lr = 1e-3
+    net.adam_step(lr)
+    step = p0 - net.get_weights().astype(np.float64)
+    gs = g * min(1.0, max_norm / norm)
+    expect = lr * gs / (np.abs(gs) + 1e-8)
+    # the step is read back as a difference of FP32 weights: two ulps of each weight
+    ulp = np.spacing(np.abs(p0).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(step - expect) <= 1e-3 * np.abs(expect).max() + 2.0 * ulp)
+    if regime == "clipped":
+        assert np.abs(step).max() <= 0.011 * lr  # linear regime: far below the plain step's size lr
+    net.set_grad_clip(0.0)
+    with pytest.raises(Exception):
+        net.set_grad_clip(-1.0)
+    net.close()
+
+
 def test_forward_graph_replays_match_eager(ss):
     """The captured forward, replayed three times with training steps (eager work
     that changes the weights) in between, equals the eager forward bit for bit."""
