@@ -253,13 +253,18 @@ int ss_set_energy_target(ss_ctx* ctx, double e_target);
  *                       corrections near the vortices (sigma <= 0: env = 1); with
  *                       pin > 0 the psi correction is also multiplied by
  *                       prod_k (1 - exp(-r_k^2 / (2 pin^2))), which keeps the zeros
- *                       of psi at the centres (pin <= 0: factor 1). With sigma <= 0
- *                       and pin <= 0 ss_init_learned inverts ss_learned_targets.
+ *                       of psi at the centres (pin <= 0: factor 1). If noise_amp > 0
+ *                       every interior component then gets the seeded noise of
+ *                       ss_init_ansatz (same seed, generator and amplitude), so
+ *                       zero corrections with sigma <= 0 and pin <= 0 give
+ *                       ss_init_ansatz's field; without noise, sigma <= 0 and
+ *                       pin <= 0 ss_init_learned inverts ss_learned_targets.
+ *                       Negative or non-finite noise_amp returns SS_EINVAL.
  * The first two synchronise. */
 int ss_learned_input(ss_ctx* ctx, int n, const double* xy, double kappa, float* out);
 int ss_learned_targets(ss_ctx* ctx, int n, const double* xy, const double* w, float* out);
 int ss_init_learned(ss_ctx* ctx, int n, const double* xy, const double* w, const float* corr, double sigma,
-                    double pin);
+                    double pin, uint64_t seed, double noise_amp);
 
 /* Plans: how the four stages of an RK4 step (Sec. 3.2, eq. (3)) are launched.
  *   SS_PLAN_STAGES      one pass per stage, P1..P4 (17 field sets of HBM

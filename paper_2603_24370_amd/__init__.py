@@ -552,7 +552,7 @@ def _ssn_lib():
     L.ss_set_energy_target.argtypes = [vp, d]
     L.ss_learned_input.argtypes = [vp, i, dp, d, vp]
     L.ss_learned_targets.argtypes = [vp, i, dp, dp, vp]
-    L.ss_init_learned.argtypes = [vp, i, dp, dp, vp, d, d]
+    L.ss_init_learned.argtypes = [vp, i, dp, dp, vp, d, d, ctypes.c_uint64, d]
     L.ssn_param_count.argtypes = [i, i, i, i]
     L.ssn_param_count.restype = ctypes.c_long
     L.ssn_workspace_bytes.argtypes = [i, i, i, i, i, i, i, ctypes.POINTER(ctypes.c_size_t)]
@@ -597,10 +597,10 @@ def ss_learned_targets(ctx, centres, windings, out_ptr):
     _check(_ssn_lib().ss_learned_targets(ctx, len(flat) // 2, _darr(flat), _darr(windings), ctypes.c_void_p(out_ptr)))
 
 
-def ss_init_learned(ctx, centres, windings, corr_ptr, sigma=0.0, pin=0.0):
+def ss_init_learned(ctx, centres, windings, corr_ptr, sigma=0.0, pin=0.0, seed=0, noise_amp=0.0):
     flat = [float(v) for p in centres for v in p]
     _check(_ssn_lib().ss_init_learned(ctx, len(flat) // 2, _darr(flat), _darr(windings), ctypes.c_void_p(corr_ptr),
-                                      float(sigma), float(pin)))
+                                      float(sigma), float(pin), int(seed), float(noise_amp)))
 
 
 def ssn_param_count(levels, base, cin, cout):

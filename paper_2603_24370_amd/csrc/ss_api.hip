@@ -324,6 +324,21 @@ int reset_state(ss_ctx* c) {
 
 }  // namespace
 
+namespace {
+
+// Noise stream key of a seed: mix(seed * golden + stream), stream 1 = interior
+// noise; 0 (amplitude <= 0) marks "no noise".
+unsigned long long noise_key(uint64_t seed, double amp) {
+  if (!(amp > 0.0)) return 0ULL;
+  unsigned long long z = (unsigned long long)seed * 0x9E3779B97F4A7C15ULL + 1ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z ^= z >> 31;
+  return z ? z : 1ULL;
+}
+
+}  // namespace
+
 extern "C" {
 
 int ss_theory_id(const char* name) {
@@ -470,15 +485,7 @@ int ss_init_ansatz(ss_ctx* c, int kind, int n, const double* xy, const double* w
   ia.R = shape ? shape[0] : 0.0;
   ia.gamma = shape ? shape[1] : 0.0;
   ia.amp = noise_amp;
-  ia.key = 0ULL;
-  if (noise_amp > 0.0) {
-    // key = mix(seed * golden + stream), stream 1 = interior noise
-    unsigned long long z = (unsigned long long)seed * 0x9E3779B97F4A7C15ULL + 1ULL;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    ia.key = z ^ (z >> 31);
-    if (ia.key == 0ULL) ia.key = 1ULL;  // 0 marks "no noise"
-  }
+  ia.key = noise_key(seed, noise_amp);
   const long sites = (long)(c->Nx + 4) * (c->Ny + 4);
   const int nb = (int)((sites + 255) / 256);
   if (c->dtype == SS_F32)
@@ -853,9 +860,11 @@ int ss_learned_targets(ss_ctx* c, int n, const double* xy, const double* w, floa
 }
 
 int ss_init_learned(ss_ctx* c, int n, const double* xy, const double* w, const float* corr, double sigma,
-                    double pin) {
+                    double pin, uint64_t seed, double noise_amp) {
   if (!c || !corr) return fail(SS_EINVAL, "ctx or corrections are NULL");
   if (!std::isfinite(sigma) || !std::isfinite(pin)) return fail(SS_EINVAL, "sigma and pin must be finite");
+  if (!std::isfinite(noise_amp) || noise_amp < 0.0) return fail(SS_EINVAL, "noise_amp must be finite and >= 0");
+  const unsigned long long key = noise_key(seed, noise_amp);
   if (c->theory != SS_THEORY_AH) return fail(SS_EINVAL, "the learned start exists for the Abelian Higgs model only");
   double *dxy, *dw;
   int rc = stage_centres(c, n, xy, w, &dxy, &dw);
@@ -864,10 +873,10 @@ int ss_init_learned(ss_ctx* c, int n, const double* xy, const double* w, const f
   const dim3 g((unsigned)((sites + 255) / 256));
   if (c->dtype == SS_F32)
     hipLaunchKernelGGL((init_learned<float>), g, dim3(256), 0, c->stream, bufs_of<float>(c), coeffs_of(c),
-                       (const double*)dxy, (const double*)dw, n, corr, sigma, pin);
+                       (const double*)dxy, (const double*)dw, n, corr, sigma, pin, key, noise_amp);
   else
     hipLaunchKernelGGL((init_learned<double>), g, dim3(256), 0, c->stream, bufs_of<double>(c), coeffs_of(c),
-                       (const double*)dxy, (const double*)dw, n, corr, sigma, pin);
+                       (const double*)dxy, (const double*)dw, n, corr, sigma, pin, key, noise_amp);
   SS_HIP(hipGetLastError());
   return reset_state(c);
 }

@@ -1671,10 +1671,13 @@ __global__ void __launch_bounds__(256) learned_targets(Bufs<T> B, Coeffs cf, con
 //   pinf = prod_k (1 - exp(-r_k^2 / (2 pin^2)))        (pin <= 0: pinf = 1),
 // which keeps the zeros of psi at the given centres:
 //   psi = (f_ans + env pinf (c0 + i c1)) e^{i Theta},   A = A_ans + env (c2, c3)
-// on the interior; the halo gets the pure-gauge vacuum.
+// on the interior, plus (key != 0) the seeded uniform noise of init_ansatz
+// (same stream and amplitude, so zero corrections without envelope or pin
+// reproduce the noisy ansatz); the halo gets the pure-gauge vacuum.
 template <class T>
 __global__ void __launch_bounds__(256) init_learned(Bufs<T> B, Coeffs cf, const double* xy, const double* w, int n,
-                                                    const float* corr, double sigma, double pin) {
+                                                    const float* corr, double sigma, double pin,
+                                                    unsigned long long key, double amp) {
   const long W = B.Nx + 4, H = B.Ny + 4;
   const long k = blockIdx.x * 256L + threadIdx.x;
   if (k >= W * H) return;
@@ -1711,6 +1714,11 @@ __global__ void __launch_bounds__(256) init_learned(Bufs<T> B, Coeffs cf, const 
     out[1] = re * sn + im * cs;
     out[2] = ax + env * c[2];
     out[3] = ay + env * c[3];
+    if (key != 0ULL)
+      for (int cc = 0; cc < 4; ++cc) {
+        const unsigned long long q = ((unsigned long long)cc * B.Ny + j) * B.Nx + i;
+        out[cc] += amp * (2.0 * splitmix_u01(key, q) - 1.0);
+      }
   } else {
     double ph = 0.0, ax = 0.0, ay = 0.0;
     for (int v = 0; v < n; ++v) {

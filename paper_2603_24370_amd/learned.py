@@ -146,11 +146,14 @@ def time_to_target(solver, start, e_target, max_steps):
 
 
 def ab_compare(net, insts, tol=1e-6, sigmas=(3.0,), pin=0.0, ref_rel_e_tol=1e-9, ref_window=100,
-               ref_max_steps=50000, max_steps=50000, coarse_tols=(), device="cuda:0", log=None):
+               ref_max_steps=50000, max_steps=50000, coarse_tols=(), noise_amp=1e-3, learned_noise_amp=0.0,
+               device="cuda:0", log=None):
     """For each instance: a long ansatz-start run gives E_ref (its stalled energy);
     then the ansatz start and the learned start (for each envelope width sigma,
     with the given pin radius) are flowed until E <= E_ref + tol |E_ref|, and
     again for each coarser tolerance in coarse_tols (keys suffixed "~tol").
+    The ansatz start carries the instance's seeded noise of amplitude noise_amp,
+    the learned start the same noise at amplitude learned_noise_amp.
     Returns per-instance records; the learned start's time includes building the
     input and running the network."""
     import torch
@@ -161,14 +164,14 @@ def ab_compare(net, insts, tol=1e-6, sigmas=(3.0,), pin=0.0, ref_rel_e_tol=1e-9,
     recs = []
     for k, m in enumerate(insts):
         s = ss.Solver("abelian_higgs", m.Nx, m.Ny, m.h, m.params, dtype="f32", device=device)
-        s.init_vortices(m.centres, seed=m.seed, noise_amp=1e-3)
+        s.init_vortices(m.centres, seed=m.seed, noise_amp=noise_amp)
         ref = s.minimise(grad_tol=0.0, rel_e_tol=ref_rel_e_tol, window=ref_window, max_steps=ref_max_steps,
                          graph_steps=16)
         E_ref = ref["energy"]
         target = E_ref + tol * abs(E_ref)
 
         def ansatz_start():
-            s.init_vortices(m.centres, seed=m.seed, noise_amp=1e-3)
+            s.init_vortices(m.centres, seed=m.seed, noise_amp=noise_amp)
 
         ta, ra = time_to_target(s, ansatz_start, target, max_steps)
         ansatz_start()
@@ -183,7 +186,8 @@ def ab_compare(net, insts, tol=1e-6, sigmas=(3.0,), pin=0.0, ref_rel_e_tol=1e-9,
             def learned_start():
                 ss.ss_learned_input(s.ctx, m.centres, m.kappa, x.data_ptr())
                 net.forward(x, out=corr, graph=True)
-                ss.ss_init_learned(s.ctx, m.centres, None, corr.data_ptr(), sigma=sg, pin=pin)
+                ss.ss_init_learned(s.ctx, m.centres, None, corr.data_ptr(), sigma=sg, pin=pin, seed=m.seed,
+                                   noise_amp=learned_noise_amp)
 
             tl, rl = time_to_target(s, learned_start, target, max_steps)
             learned_start()
@@ -226,7 +230,7 @@ def summarise(recs, sigma, tol=None, coarse=None):
 
 def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20, batch=8, lr=1e-3, seed=0,
                  tol=1e-6, sigmas=(0.0, 3.0), target_steps=150, pin=0.0, coarse_tols=(), clip=0.0,
-                 device="cuda:0", log=print):
+                 learned_noise_amp=0.0, device="cuda:0", log=print):
     """Data -> training -> A/B on held-out instances; returns a summary dict."""
     import torch
     t0 = time.perf_counter()
@@ -254,8 +258,8 @@ def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20
         log(f"[infer] {infer_ms:.3f} ms per image at batch 1")
     del X, T
     torch.cuda.empty_cache()
-    recs = ab_compare(net, test_insts, tol=tol, sigmas=sigmas, pin=pin, coarse_tols=coarse_tols, device=device,
-                      log=log)
+    recs = ab_compare(net, test_insts, tol=tol, sigmas=sigmas, pin=pin, coarse_tols=coarse_tols,
+                      learned_noise_amp=learned_noise_amp, device=device, log=log)
     out = {"summary": [summarise(recs, sg, tol=tol) for sg in sigmas] +
            [summarise(recs, sg, coarse=ct) for ct in coarse_tols for sg in sigmas]}
     out.update({"n_train": n_train, "n_test": n_test, "side": side, "levels": levels, "base": base,
@@ -263,6 +267,7 @@ def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20
                 "data_median_steps": float(np.median(steps)), "train_s": t_train, "train_TFLOPs": tflops,
                 "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1], "losses": losses, "tol": tol,
                 "target_steps": target_steps, "target_mean_square": zero_mse, "pin": pin, "clip": clip,
+                "learned_noise_amp": learned_noise_amp,
                 "inference_ms_batch1": infer_ms,
                 "records": recs})
     net.close()
@@ -284,7 +289,9 @@ def main(argv=None):
     ap.add_argument("--target-steps", type=int, default=150, help="flow steps behind each training target")
     ap.add_argument("--pin", type=float, default=0.5, help="radius that pins the zeros of psi at the centres")
     ap.add_argument("--sigmas", default="3", help="envelope widths of the learned start (comma list)")
-    ap.add_argument("--clip", type=float, default=1.0, help="global L2 gradient clipping norm (0: off)")
+    ap.add_argument("--clip", type=float, default=0.0, help="global L2 gradient clipping norm (0: off)")
+    ap.add_argument("--learned-noise", type=float, default=0.0,
+                    help="amplitude of the instance's seeded noise added to the learned start (the ansatz start has 1e-3)")
     ap.add_argument("--coarse-tols", default="1e-3,1e-4",
                     help="coarser relative energy tolerances also timed (comma list, may be empty)")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
@@ -293,6 +300,7 @@ def main(argv=None):
     coarse = tuple(float(v) for v in a.coarse_tols.split(",") if v.strip())
     res = run_pipeline(a.n_train, a.n_test, a.side, a.levels, a.base, a.epochs, a.batch, a.lr, sigmas=sig,
                        target_steps=a.target_steps, pin=a.pin, coarse_tols=coarse, clip=a.clip,
+                       learned_noise_amp=a.learned_noise,
                        log=lambda m: print(m, flush=True))
     brief = {k: v for k, v in res.items() if k not in ("records", "losses")}
     print(json.dumps(brief), flush=True)

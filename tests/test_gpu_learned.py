@@ -275,6 +275,15 @@ def test_learned_input_and_targets(ss, orc):
     s.init_vortices(cen)
     ga = s.get_field().cpu().numpy()
     assert np.abs(g0 - ga).max() < 1e-12
+    # with the ansatz's seeded noise, zero corrections give the noisy ansatz
+    ss.ss_init_learned(s.ctx, cen, None, z.data_ptr(), seed=77, noise_amp=1e-3)
+    gn = s.get_field().cpu().numpy()
+    s.init_vortices(cen, seed=77, noise_amp=1e-3)
+    gan = s.get_field().cpu().numpy()
+    assert np.abs(gn - gan).max() < 1e-12 and np.abs(gn - ga).max() > 5e-4
+    with pytest.raises(Exception):
+        ss.ss_init_learned(s.ctx, cen, None, z.data_ptr(), seed=77, noise_amp=-1.0)
+    s.init_vortices(cen)
     # the envelope weights a unit correction of c0 by 1 - prod_k (1 - exp(-r_k^2 / 2 sigma^2))
     sigma = 1.5
     one = torch.zeros_like(t)
