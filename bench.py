@@ -225,6 +225,25 @@ def cpu_baseline(s, wl, params, window=1024, steps=10):
                       f"fixed halo), FP64, {dt:.1f} s"}
 
 
+def measured_copy_gbps(nbytes=1 << 30, reps=10):
+    """Bandwidth of a plain device-to-device copy (read + write bytes over the
+    mean time of `reps` copies of nbytes, HIP events): the practical ceiling
+    a streaming kernel is also compared with."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def traffic_record(pass_name, wl_name, tile):
     """HBM bytes per launch of a pass on a tile shape (index) from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
@@ -318,6 +337,10 @@ def main():
             "step_GBps": round(step_gbps, 1), "step_frac": round(step_gbps / HBM_PEAK_GBS, 4),
             "step_sets": step_sets,
             "passes": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in passes.items()}}
+
+    copy = measured_copy_gbps()
+    roof["copy_GBps"] = round(copy, 1)
+    roof["frac_of_copy"] = round(ach / copy, 4)
 
     cpu = None
     if not args.no_cpu:
