@@ -6,14 +6,18 @@
 // offsets (ky - 1, kx - 1). Master weights, Adam moments and gradients are FP32.
 //
 // Kernels:
-//   conv3x3_mfma   implicit GEMM, M = out channels, N = pixels, K = 9 * in channels,
-//                  v_mfma_f32_32x32x16_bf16; forward (bias + SiLU epilogue) and
+//   conv3x3_tiled  implicit GEMM for the larger layers, M = pixels, N = out
+//                  channels, K = 9 * in channels, v_mfma_f32_32x32x16_bf16, input
+//                  patch staged in LDS; forward (bias + SiLU epilogue) and
 //                  backward-data (the same GEMM with flipped, transposed weights;
 //                  optional SiLU' and accumulation epilogue);
+//   conv3x3_mfma   the same GEMM with operands read directly (M = out channels,
+//                  N = pixels), for small grids;
 //   conv3x3_wgrad  weight gradient, M = out channels, N = in channels per tap,
 //                  K = pixels, operands staged transposed in LDS, split over
 //                  pixel chunks with a fixed-order reduction (deterministic);
-//   pool / upsample / head 1x1 / SiLU' / MSE / bias sums / Adam: plain kernels.
+//   pool / upsample / head 1x1 / SiLU' / MSE / bias sums / Adam (optionally
+//   with global-norm gradient clipping): kernels on 8-channel vectors.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
