@@ -200,8 +200,9 @@ int ss_init_ansatz(ss_ctx* ctx, int kind, int n, const double* xy, const double*
 
 /* Mean device time per launch of each of the passes, measured with HIP events
  * on the context's stream over n_steps flow steps (the steps are real flow
- * steps). ms[0..3] = stage passes P1..P4, ms[4] = whole step; under a fused
- * plan ms[1] is the pass of stages 2-4 and ms[2] = ms[3] = 0. Synchronises. */
+ * steps). ms[0..3] = stage passes P1..P4 (P1 including the one-workgroup launch
+ * that finalises its reduction), ms[4] = whole step; under a fused plan ms[1]
+ * is the pass of stages 2-4 and ms[2] = ms[3] = 0. Synchronises. */
 int ss_time_passes(ss_ctx* ctx, int n_steps, double* ms);
 
 /* Copy the current field and (if velocity != NULL) velocity to device arrays. */
