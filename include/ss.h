@@ -292,8 +292,12 @@ int ss_get_plan(ss_ctx* ctx);
  * SS_NUM_PLANS * ss_tile_count() doubles, index plan * ss_tile_count() + tile;
  * -1 where a pair does not apply) and returns the chosen tile index (>= 0; the
  * plan is read with ss_get_plan). It overwrites the field: call ss_set_field
- * or ss_init_ansatz afterwards. The environment variable SS_TILE selects the
- * initial shape of new contexts. */
+ * or ss_init_ansatz afterwards. If the environment variable SS_AUTOTUNE_CACHE
+ * names a file, ss_autotune first looks the problem (theory, dtype, gradient
+ * form, Nx, Ny, compiled shapes) up there and, if found, applies the stored
+ * plan and tile without timing (ms_out all -1, the field untouched); otherwise
+ * it times as above and appends its choice to the file. The environment
+ * variable SS_TILE selects the initial shape of new contexts. */
 int ss_tile_count(void);
 int ss_tile_shape(int tile, int* tx, int* ty, int* ry);
 int ss_set_tile(ss_ctx* ctx, int tile);

@@ -758,6 +758,52 @@ int ss_tile_shape(int tile, int* tx, int* ty, int* ry) {
   return SS_OK;
 }
 
+namespace {
+
+// Autotune cache: a text file (path in SS_AUTOTUNE_CACHE) of lines
+// "theory dtype grad_mode Nx Ny tiles plan tile", one per tuned problem; the
+// last line for a problem wins. "tiles" is the number of compiled tile shapes,
+// so entries from a library with other shapes are not used.
+std::string tune_key(const ss_ctx* c) {
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "%d %d %d %d %d %d", c->theory, c->dtype, c->grad_mode, c->Nx, c->Ny, kNumTiles);
+  return buf;
+}
+
+bool tune_lookup(const ss_ctx* c, int* plan, int* tile) {
+  const char* path = std::getenv("SS_AUTOTUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  const std::string key = tune_key(c);
+  bool found = false;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    int th, dt, gm, nx, ny, nt, p, t;
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &th, &dt, &gm, &nx, &ny, &nt, &p, &t) != 8) continue;
+    char k[128];
+    std::snprintf(k, sizeof(k), "%d %d %d %d %d %d", th, dt, gm, nx, ny, nt);
+    if (key == k && p >= 0 && p < SS_NUM_PLANS && t >= 0 && t < kNumTiles) {
+      *plan = p;
+      *tile = t;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_store(const ss_ctx* c, int plan, int tile) {
+  const char* path = std::getenv("SS_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;  // an unwritable cache only costs the next run its timing
+  std::fprintf(f, "%s %d %d\n", tune_key(c).c_str(), plan, tile);
+  std::fclose(f);
+}
+
+}  // namespace
+
 int ss_autotune(ss_ctx* c, int n_steps, double* ms_out) {
   if (!c || n_steps <= 0) return fail(SS_EINVAL, "bad arguments");
   if (ms_out)
@@ -765,6 +811,14 @@ int ss_autotune(ss_ctx* c, int n_steps, double* ms_out) {
   if (c->grad_mode == SS_GRAD_EXACT) {
     if (ms_out) ms_out[0] = 0.0;
     return 0;
+  }
+  int cached_p = 0, cached_t = 0;
+  if (tune_lookup(c, &cached_p, &cached_t)) {
+    int rc = ss_set_plan(c, cached_p);
+    if (rc) return rc;
+    rc = ss_set_tile(c, cached_t);
+    if (rc) return rc;
+    return cached_t;  // nothing timed: ms_out stays -1 throughout
   }
   // a uniform vacuum (psi = 1, A = 0; n = e_3) keeps every pass finite
   const double zero[2] = {0.0, 0.0};
@@ -797,6 +851,7 @@ int ss_autotune(ss_ctx* c, int n_steps, double* ms_out) {
   if (rc) return rc;
   rc = ss_set_tile(c, best_t);
   if (rc) return rc;
+  tune_store(c, best_p, best_t);
   return reset_state(c) ? SS_EHIP : best_t;
 }
 

@@ -531,6 +531,36 @@ def test_autotune_picks_a_shape_and_leaves_a_usable_context(ss, orc):
     s.close()
 
 
+def test_autotune_cache_serves_the_stored_choice(ss, orc, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("SS_AUTOTUNE_CACHE", str(cache))
+    Nx, Ny, h = 160, 72, 0.2
+    f = _field(AH, Nx, Ny, h, seed=6).astype(np.float32).astype(np.float64)
+    s = _solver(ss, AH, f, h, "f32")
+    best, plan, ms = s.autotune(2)
+    assert all(m > 0 for row in ms for m in row)  # timed
+    assert cache.read_text().split()[-2:] == [str(plan), str(best)]
+    s.close()
+    # the same problem in a new context: stored plan and tile, nothing timed, field untouched
+    s2 = _solver(ss, AH, f, h, "f32")
+    s2.set_field(f)
+    s2.set_plan(1 - plan)
+    s2.set_tile((best + 1) % ss.ss_tile_count())
+    best2, plan2, ms2 = s2.autotune(2)
+    assert (best2, plan2) == (best, plan) and ss.ss_get_tile(s2.ctx) == best and s2.plan == plan
+    assert all(m == -1.0 for row in ms2 for m in row)
+    E, _, _ = s2.energy_grad(want_grad=False)
+    assert E == pytest.approx(orc.energy(AH, f, h, [1.0]), rel=1e-12)
+    s2.close()
+    # another lattice size is tuned and appended
+    g = _field(AH, Nx + 32, Ny, h, seed=6).astype(np.float32).astype(np.float64)
+    s3 = _solver(ss, AH, g, h, "f32")
+    _, _, ms3 = s3.autotune(1)
+    assert all(m > 0 for row in ms3 for m in row)
+    assert len(cache.read_text().strip().splitlines()) == 2
+    s3.close()
+
+
 # ------------------------------------------------ exact discrete gradient (SS_GRAD_EXACT)
 
 EXACT_SHAPES = [(150, 37), (8, 8), (129, 70), (64, 16)]
