@@ -208,6 +208,19 @@ int ss_time_passes(ss_ctx* ctx, int n_steps, double* ms);
 /* Copy the current field and (if velocity != NULL) velocity to device arrays. */
 int ss_get_field(ss_ctx* ctx, void* field, void* velocity);
 
+/* Checkpoint and resume. ss_get_state copies the current field and velocity
+ * into device buffers of the ss_get_field layout (both required) and the flow
+ * status into state, a host buffer of ss_state_bytes() bytes: step counter,
+ * the energies the arrest test compares, arrest flag and count, the energy
+ * history of the stall rule and the stop settings. ss_set_state on a context
+ * of the same theory, dtype, gradient form and lattice restores all of it, so
+ * that the flow continues exactly (bitwise) as it would have without the
+ * interruption. A blob from another problem returns SS_ESHAPE, a corrupt one
+ * SS_EINVAL. Both synchronise. */
+size_t ss_state_bytes(void);
+int ss_get_state(ss_ctx* ctx, void* field, void* velocity, void* state);
+int ss_set_state(ss_ctx* ctx, const void* field, const void* velocity, const void* state);
+
 /* E_h and gradient of a field: `field` (device, NULL = the current field).
  * If grad != NULL it receives G (device array, layout above, zero halo): the
  * gradient of the selected form; for the chiral magnet, at the normalised

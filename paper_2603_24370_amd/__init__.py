@@ -75,7 +75,7 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_batch_create",
            "ss_batch_destroy", "ss_batch_member", "ss_batch_size", "ss_batch_flow_step", "ss_batch_minimise",
            "ss_batch_set_tile", "ss_batch_autotune", "ss_batch_set_plan", "ss_batch_get_plan", "ss_set_energy_target", "ss_learned_input",
-           "ss_learned_targets", "ss_init_learned"]
+           "ss_learned_targets", "ss_init_learned", "ss_state_bytes", "ss_get_state", "ss_set_state"]
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
                "ssn_adam_step", "ssn_set_grad_clip",
@@ -101,6 +101,10 @@ def lib():
     L.ss_destroy.restype = None
     L.ss_set_field.argtypes = [vp, vp]
     L.ss_get_field.argtypes = [vp, vp, vp]
+    L.ss_state_bytes.argtypes = []
+    L.ss_state_bytes.restype = ctypes.c_size_t
+    L.ss_get_state.argtypes = [vp, vp, vp, vp]
+    L.ss_set_state.argtypes = [vp, vp, vp, vp]
     dp = ctypes.POINTER(d)
     L.ss_init_ansatz.argtypes = [vp, i, i, dp, dp, dp, ctypes.c_uint64, d]
     L.ss_time_passes.argtypes = [vp, i, dp]
@@ -215,6 +219,21 @@ def ss_time_passes(ctx, n_steps):
 
 def ss_get_field(ctx, field_ptr, vel_ptr=None):
     _check(lib().ss_get_field(ctx, ctypes.c_void_p(field_ptr), ctypes.c_void_p(vel_ptr or 0)))
+
+
+def ss_state_bytes() -> int:
+    return int(lib().ss_state_bytes())
+
+
+def ss_get_state(ctx, field_ptr, vel_ptr) -> bytes:
+    buf = ctypes.create_string_buffer(ss_state_bytes())
+    _check(lib().ss_get_state(ctx, ctypes.c_void_p(field_ptr), ctypes.c_void_p(vel_ptr), buf))
+    return buf.raw
+
+
+def ss_set_state(ctx, field_ptr, vel_ptr, state: bytes):
+    buf = ctypes.create_string_buffer(bytes(state), len(state))
+    _check(lib().ss_set_state(ctx, ctypes.c_void_p(field_ptr), ctypes.c_void_p(vel_ptr), buf))
 
 
 def ss_energy_grad(ctx, field_ptr=None, grad_ptr=None):
@@ -451,6 +470,21 @@ class Solver:
         v = self.torch.empty(self.shape, dtype=self.tdtype, device=self.device) if velocity else None
         ss_get_field(self.ctx, f.data_ptr(), v.data_ptr() if velocity else None)
         return (f, v) if velocity else f
+
+    def get_state(self):
+        """Checkpoint: (field, velocity, status bytes) of the flow."""
+        f = self.torch.empty(self.shape, dtype=self.tdtype, device=self.device)
+        v = self.torch.empty(self.shape, dtype=self.tdtype, device=self.device)
+        blob = ss_get_state(self.ctx, f.data_ptr(), v.data_ptr())
+        return f, v, blob
+
+    def set_state(self, state):
+        """Resume from a checkpoint of get_state (same theory, dtype and lattice)."""
+        f, v, blob = state
+        f, v = self._dev(f), self._dev(v)
+        if tuple(f.shape) != self.shape or tuple(v.shape) != self.shape:
+            raise ValueError(f"state shapes {tuple(f.shape)}, {tuple(v.shape)} != {self.shape}")
+        ss_set_state(self.ctx, f.data_ptr(), v.data_ptr(), blob)
 
     def energy_grad(self, field=None, want_grad=True):
         src = None if field is None else self._dev(field)

@@ -570,6 +570,64 @@ int ss_get_field(ss_ctx* c, void* field, void* velocity) {
   return SS_OK;
 }
 
+// Checkpoint blob: a header that names the problem, then the device status.
+struct StateBlob {
+  unsigned magic;
+  unsigned bytes;
+  int theory, dtype, grad_mode, Nx, Ny, pad_;
+  DevStatus st;
+};
+constexpr unsigned kStateMagic = 0x53535354u;  // "SSST"
+
+size_t ss_state_bytes(void) { return sizeof(StateBlob); }
+
+int ss_get_state(ss_ctx* c, void* field, void* velocity, void* state) {
+  if (!c || !field || !velocity || !state) return fail(SS_EINVAL, "ctx, field, velocity or state is NULL");
+  int rc = ss_get_field(c, field, velocity);
+  if (rc) return rc;
+  StateBlob b;
+  std::memset(&b, 0, sizeof(b));
+  b.magic = kStateMagic;
+  b.bytes = (unsigned)sizeof(StateBlob);
+  b.theory = c->theory;
+  b.dtype = c->dtype;
+  b.grad_mode = c->grad_mode;
+  b.Nx = c->Nx;
+  b.Ny = c->Ny;
+  rc = read_status(c, &b.st);
+  if (rc) return rc;
+  std::memcpy(state, &b, sizeof(b));
+  return SS_OK;
+}
+
+int ss_set_state(ss_ctx* c, const void* field, const void* velocity, const void* state) {
+  if (!c || !field || !velocity || !state) return fail(SS_EINVAL, "ctx, field, velocity or state is NULL");
+  StateBlob b;
+  std::memcpy(&b, state, sizeof(b));
+  if (b.magic != kStateMagic || b.bytes != (unsigned)sizeof(StateBlob)) return fail(SS_EINVAL, "not a state blob");
+  if (b.theory != c->theory || b.dtype != c->dtype || b.grad_mode != c->grad_mode || b.Nx != c->Nx ||
+      b.Ny != c->Ny)
+    return fail(SS_ESHAPE, "state was taken on another theory, dtype, gradient form or lattice");
+  if (b.st.counter != 0u || b.st.counter_obs != 0u) return fail(SS_EINVAL, "state blob is inconsistent");
+  // both ping-pong buffers get the field and the velocity (the halo of the
+  // buffer the next step writes must hold the boundary values too)
+  const size_t es = esize_of(c->dtype);
+  const size_t upitch = (size_t)(c->Nx + 4) * es;
+  const size_t uplane = upitch * (c->Ny + 4);
+  for (int buf = 0; buf < 2; ++buf)
+    for (int comp = 0; comp < c->C; ++comp) {
+      SS_HIP(hipMemcpy2DAsync((char*)c->phi[buf] + comp * c->L.plane * es, c->L.pitch * es,
+                              (const char*)field + comp * uplane, upitch, upitch, c->Ny + 4,
+                              hipMemcpyDeviceToDevice, c->stream));
+      SS_HIP(hipMemcpy2DAsync((char*)c->vel[buf] + comp * c->L.plane * es, c->L.pitch * es,
+                              (const char*)velocity + comp * uplane, upitch, upitch, c->Ny + 4,
+                              hipMemcpyDeviceToDevice, c->stream));
+    }
+  SS_HIP(hipMemcpyAsync(c->st, &b.st, sizeof(DevStatus), hipMemcpyHostToDevice, c->stream));
+  SS_HIP(hipStreamSynchronize(c->stream));
+  return SS_OK;
+}
+
 int ss_energy_grad(ss_ctx* c, const void* field, void* grad, double* energy, double* gnorm_inf) {
   if (!c) return fail(SS_EINVAL, "ctx is NULL");
   const size_t es = esize_of(c->dtype);

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions(header="ss.h", prefix="ss_"):
     src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = set(re.findall(r"^\s*(?:const\s+)?(?:int|void|double|long|char|ss_ctx)\s*\**\s*(" + prefix + r"\w+)\s*\(",
+    names = set(re.findall(r"^\s*(?:const\s+)?(?:int|void|double|long|char|size_t|ss_ctx)\s*\**\s*(" + prefix + r"\w+)\s*\(",
                            src, flags=re.M))
     return names
 
@@ -112,3 +112,10 @@ def test_status_strings_and_kappa_helper(L):
     assert ss.lib().ss_status_string(0) == b"ok"
     assert ss.lib().ss_status_string(-5) == b"non-finite value"
     assert ss.ss_gl_lambda_from_kappa(1 / 2 ** 0.5) == pytest.approx(1.0)
+
+
+def test_checkpoint_calls_validate_their_arguments(L):
+    assert ss.ss_state_bytes() > 0
+    buf = ctypes.create_string_buffer(ss.ss_state_bytes())
+    assert L.ss_get_state(None, None, None, buf) == -1
+    assert L.ss_set_state(None, None, None, buf) == -1

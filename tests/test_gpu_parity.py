@@ -531,6 +531,41 @@ def test_autotune_picks_a_shape_and_leaves_a_usable_context(ss, orc):
     s.close()
 
 
+@pytest.mark.parametrize("dtype,plan", [("f64", 0), ("f32", 1)])
+def test_checkpoint_resumes_the_flow_bitwise(ss, orc, dtype, plan):
+    Nx, Ny, h = 90, 70, 0.2
+    f = _field(AH, Nx, Ny, h, seed=8)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    s = _solver(ss, AH, f, h, dtype)
+    s.set_plan(plan)
+    s.set_field(f)
+    s.flow_step(7)
+    state = s.get_state()
+    s.flow_step(9)
+    a, va = s.get_field(velocity=True)
+    ia = s.info()
+    s2 = _solver(ss, AH, f, h, dtype)
+    s2.set_plan(plan)
+    s2.set_state(state)
+    assert s2.info()["step"] == 7
+    s2.flow_step(9)
+    b, vb = s2.get_field(velocity=True)
+    ib = s2.info()
+    assert bool((a == b).all()) and bool((va == vb).all())
+    assert (ia["step"], ia["n_arrests"], ia["energy"]) == (ib["step"], ib["n_arrests"], ib["energy"])
+    # the same flow in the oracle over all 16 steps
+    phi_r, _, E_r, na = orc.flow(AH, f, np.zeros_like(f), h, [1.0], 16)
+    rel = 1e-11 if dtype == "f64" else 1e-5
+    assert np.abs(_as_np(b) - phi_r).max() <= rel * np.abs(phi_r).max()
+    # a checkpoint of another lattice is refused
+    s3 = _solver(ss, AH, _field(AH, Nx + 2, Ny, h, seed=8), h, dtype)
+    with pytest.raises(Exception):
+        s3.set_state((state[0], state[1], state[2]))
+    for x in (s, s2, s3):
+        x.close()
+
+
 def test_autotune_cache_serves_the_stored_choice(ss, orc, tmp_path, monkeypatch):
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("SS_AUTOTUNE_CACHE", str(cache))
