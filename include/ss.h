@@ -354,6 +354,11 @@ int ss_batch_set_tile(ss_batch* batch, int tile);
  * with any other shape the batch runs separate stage passes. */
 int ss_batch_set_plan(ss_batch* batch, int plan);
 int ss_batch_get_plan(ss_batch* batch);
+/* Observables of every member (out: n entries, host), each as ss_observables
+ * gives it for one context. All members' observable passes are enqueued on the
+ * batch stream before the first read-back, which synchronises. SS_EINVAL if
+ * batch or out is NULL; after an error part of out may be filled. */
+int ss_batch_observables(ss_batch* batch, ss_obs* out);
 /* Times every plan with every tile shape it runs on over n_steps batch steps
  * (overwrites all fields with the vacuum), keeps the fastest pair, writes the
  * step times in ms_out (may be NULL, else SS_NUM_PLANS * ss_tile_count()

@@ -74,7 +74,7 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_set_tile", "ss_get_tile", "ss_autotune", "ss_set_plan", "ss_get_plan", "ss_batch_workspace_bytes",
            "ss_batch_create",
            "ss_batch_destroy", "ss_batch_member", "ss_batch_size", "ss_batch_flow_step", "ss_batch_minimise",
-           "ss_batch_set_tile", "ss_batch_autotune", "ss_batch_set_plan", "ss_batch_get_plan", "ss_set_energy_target", "ss_learned_input",
+           "ss_batch_set_tile", "ss_batch_autotune", "ss_batch_set_plan", "ss_batch_get_plan", "ss_batch_observables", "ss_set_energy_target", "ss_learned_input",
            "ss_learned_targets", "ss_init_learned", "ss_state_bytes", "ss_get_state", "ss_set_state"]
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
@@ -141,6 +141,7 @@ def lib():
     L.ss_batch_autotune.argtypes = [vp, i, dp]
     L.ss_batch_set_plan.argtypes = [vp, i]
     L.ss_batch_get_plan.argtypes = [vp]
+    L.ss_batch_observables.argtypes = [vp, ctypes.POINTER(ss_obs)]
     _lib = L
     return L
 
@@ -349,6 +350,12 @@ def ss_batch_size(batch) -> int:
     return _check_nonneg(lib().ss_batch_size(batch))
 
 
+def ss_batch_observables(batch, n_members):
+    out = (ss_obs * n_members)()
+    _check(lib().ss_batch_observables(batch, out))
+    return [x.as_dict() for x in out]
+
+
 def ss_batch_flow_step(batch, n_steps, n_members=None):
     infos = (ss_step_info * n_members)() if n_members else None
     _check(lib().ss_batch_flow_step(batch, int(n_steps), infos))
@@ -546,6 +553,9 @@ class Batch:
 
     def minimise(self, **kw):
         return ss_batch_minimise(self.batch, self.n, **kw)
+
+    def observables(self):
+        return ss_batch_observables(self.batch, self.n)
 
     def set_tile(self, tile):
         ss_batch_set_tile(self.batch, tile)

@@ -733,8 +733,8 @@ int ss_minimise(ss_ctx* c, const ss_stop* stop, ss_min_info* info) {
   return SS_OK;
 }
 
-int ss_observables(ss_ctx* c, ss_obs* out) {
-  if (!c || !out) return fail(SS_EINVAL, "ctx or out is NULL");
+// Observable passes of one context, enqueued on its stream; obs_collect reads them back.
+static int obs_enqueue(ss_ctx* c) {
   const int nobs = 1024;
   if (c->dtype == SS_F32) {
     Bufs<float> B = bufs_of<float>(c);
@@ -756,6 +756,10 @@ int ss_observables(ss_ctx* c, ss_obs* out) {
     }
   }
   SS_HIP(hipGetLastError());
+  return SS_OK;
+}
+
+static int obs_collect(ss_ctx* c, ss_obs* out) {
   DevStatus d;
   int rc = read_status(c, &d);
   if (rc) return rc;
@@ -774,6 +778,12 @@ int ss_observables(ss_ctx* c, ss_obs* out) {
     out->q_bl = d.obs[5] / (4.0 * M_PI);
   }
   return SS_OK;
+}
+
+int ss_observables(ss_ctx* c, ss_obs* out) {
+  if (!c || !out) return fail(SS_EINVAL, "ctx or out is NULL");
+  int rc = obs_enqueue(c);
+  return rc ? rc : obs_collect(c, out);
 }
 
 int ss_set_tile(ss_ctx* c, int tile) {
@@ -1422,6 +1432,21 @@ int ss_batch_set_plan(ss_batch* b, int plan) {
 }
 
 int ss_batch_get_plan(ss_batch* b) { return b ? b->plan : SS_EINVAL; }
+
+int ss_batch_observables(ss_batch* b, ss_obs* out) {
+  if (!b || !out) return fail(SS_EINVAL, "batch or out is NULL");
+  // Every member's passes go on the batch stream first, so the first read-back
+  // waits for all of them and the rest find their results ready.
+  for (ss_ctx* m : b->members) {
+    int rc = obs_enqueue(m);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < b->n; ++i) {
+    int rc = obs_collect(b->members[i], &out[i]);
+    if (rc) return rc;
+  }
+  return SS_OK;
+}
 
 int ss_batch_flow_step(ss_batch* b, int n_steps, ss_step_info* infos) {
   if (!b || n_steps < 0) return fail(SS_EINVAL, "bad arguments");

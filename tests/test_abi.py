@@ -119,3 +119,9 @@ def test_checkpoint_calls_validate_their_arguments(L):
     buf = ctypes.create_string_buffer(ss.ss_state_bytes())
     assert L.ss_get_state(None, None, None, buf) == -1
     assert L.ss_set_state(None, None, None, buf) == -1
+
+
+def test_batch_observables_rejects_null_arguments(L):
+    out = (ss.ss_obs * 2)()
+    assert L.ss_batch_observables(None, out) == -1
+    assert L.ss_batch_observables(None, None) == -1

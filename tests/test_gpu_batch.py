@@ -66,6 +66,16 @@ def test_batch_flow_matches_oracle_per_member(ss, orc, dtype, which):
         else:
             # energy of the member's own field (FP64 reduction of the stored values)
             assert infos[k]["energy"] == pytest.approx(orc.energy(AH, phi, m.h, m.params), rel=1e-12)
+    # observables of all members in one call: the oracle's on each member's own field,
+    # and bit for bit what the single-context call gives
+    obs = B.observables()
+    assert len(obs) == len(insts)
+    for k, (m, mem) in enumerate(zip(insts, B.members)):
+        r = orc.observables(AH, _np(mem.get_field()), m.h, m.params)
+        for k_gpu, k_ref in [("energy", "E"), ("flux", "flux"), ("n_rho", "N_rho"), ("bogo_r1", "R1"),
+                             ("bogo_r2", "R2"), ("n_wind", "N_wind")]:
+            assert obs[k][k_gpu] == pytest.approx(r[k_ref], rel=1e-11, abs=1e-11), (k, k_gpu)
+        assert obs[k] == mem.observables(), k
     B.close()
 
 
