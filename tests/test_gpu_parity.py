@@ -566,6 +566,32 @@ def test_checkpoint_resumes_the_flow_bitwise(ss, orc, dtype, plan):
         x.close()
 
 
+def test_checkpoint_resumes_a_minimisation(ss, orc):
+    """FP64: a minimisation resumed from a checkpoint in a fresh context stops at the
+    step, with the arrest count and field, of the one that was not interrupted, and
+    both stop where the oracle's flow from the start does."""
+    Nx, Ny, h = 48, 40, 0.2
+    f = _field(AH, Nx, Ny, h, seed=9)
+    s = _solver(ss, AH, f, h, "f64")
+    s.set_field(f)
+    s.flow_step(7)
+    state = s.get_state()
+    ra = s.minimise(grad_tol=2e-3, max_steps=3000, graph_steps=8)
+    a = s.get_field()
+    s2 = _solver(ss, AH, f, h, "f64")
+    s2.set_state(state)
+    rb = s2.minimise(grad_tol=2e-3, max_steps=3000, graph_steps=8)
+    b = s2.get_field()
+    assert (ra["step"], ra["n_arrests"], ra["reason"]) == (rb["step"], rb["n_arrests"], rb["reason"])
+    assert ra["reason"] == "grad"
+    assert bool((a == b).all())
+    phi_r, _, info_r = orc.minimise(AH, f, h, [1.0], grad_tol=2e-3, max_steps=3000)
+    assert ra["step"] == info_r["steps"] and ra["n_arrests"] == info_r["arrests"]
+    assert np.abs(_as_np(b) - phi_r).max() < 1e-9
+    s.close()
+    s2.close()
+
+
 def test_autotune_cache_serves_the_stored_choice(ss, orc, tmp_path, monkeypatch):
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("SS_AUTOTUNE_CACHE", str(cache))
