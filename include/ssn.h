@@ -37,6 +37,9 @@
 #define SSN_H
 
 #include <stddef.h>
+#include <stdint.h>
+
+#include "ss.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -79,6 +82,20 @@ int ssn_adam_step(ssn_net* net, float lr);
 int ssn_set_grad_clip(ssn_net* net, float max_norm);
 /* forward + backward + Adam. */
 int ssn_train_step(ssn_net* net, const float* x, const float* target, int n, float lr, double* loss);
+/* Learned start in one call, for a network made with cin = 2, cout = 4 and
+ * H = Ny, W = Nx of the Abelian Higgs context ctx: the input image of
+ * ss_learned_input (nv centres xy, kappa) is written to work, the network's
+ * forward pass maps it to corrections, and ss_init_learned (windings w, sigma,
+ * pin, seed, noise_amp as documented there) sets the field from them; the flow
+ * then starts from rest. The result equals those three calls made in turn.
+ * work: device memory of at least ssn_init_field_workspace_bytes(net) bytes,
+ * 256-byte aligned, owned by the caller. The network's last output is replaced.
+ * SS_EINVAL for NULL pointers, a network of other channel counts, another
+ * theory or a small or misaligned work; SS_ESHAPE if the network's image size
+ * is not the lattice's. Synchronises the network's and the context's streams. */
+size_t ssn_init_field_workspace_bytes(ssn_net* net);
+int ssn_init_field(ssn_net* net, ss_ctx* ctx, int nv, const double* xy, const double* w, double kappa, double sigma,
+                   double pin, uint64_t seed, double noise_amp, void* work, size_t work_bytes);
 /* Multiply-add flops (2 per MAC) of one image's forward and backward passes. */
 int ssn_flops(ssn_net* net, double* fwd, double* bwd);
 const char* ssn_last_error(void);

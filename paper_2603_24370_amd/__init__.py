@@ -79,7 +79,7 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
                "ssn_adam_step", "ssn_set_grad_clip",
-               "ssn_train_step", "ssn_flops", "ssn_last_error"]
+               "ssn_train_step", "ssn_flops", "ssn_init_field_workspace_bytes", "ssn_init_field", "ssn_last_error"]
 
 _lib = None
 
@@ -615,6 +615,9 @@ def _ssn_lib():
     L.ssn_set_grad_clip.argtypes = [vp, ctypes.c_float]
     L.ssn_train_step.argtypes = [vp, vp, vp, i, ctypes.c_float, dp]
     L.ssn_flops.argtypes = [vp, dp, dp]
+    L.ssn_init_field_workspace_bytes.argtypes = [vp]
+    L.ssn_init_field_workspace_bytes.restype = ctypes.c_size_t
+    L.ssn_init_field.argtypes = [vp, vp, i, dp, dp, d, d, d, ctypes.c_uint64, d, vp, ctypes.c_size_t]
     L.ssn_last_error.argtypes = []
     L.ssn_last_error.restype = ctypes.c_char_p
     L._ssn_ready = True
@@ -733,6 +736,16 @@ class Net:
         f, b = ctypes.c_double(0), ctypes.c_double(0)
         _ncheck(_ssn_lib().ssn_flops(self.net, ctypes.byref(f), ctypes.byref(b)))
         return f.value, b.value
+
+    def init_field(self, solver, centres, kappa, windings=None, sigma=0.0, pin=0.0, seed=0, noise_amp=0.0):
+        """Learned start of solver's lattice in one call (input image, forward, corrected ansatz)."""
+        L = _ssn_lib()
+        nbytes = L.ssn_init_field_workspace_bytes(self.net)
+        work = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        ptr = (work.data_ptr() + 255) // 256 * 256
+        flat = [float(v) for p in centres for v in p]
+        _ncheck(L.ssn_init_field(self.net, solver.ctx, len(flat) // 2, _darr(flat), _darr(windings), float(kappa),
+                                 float(sigma), float(pin), int(seed), float(noise_amp), ctypes.c_void_p(ptr), nbytes))
 
     def close(self):
         if getattr(self, "net", None) is not None:

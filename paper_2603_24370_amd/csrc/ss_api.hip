@@ -1033,6 +1033,18 @@ double ss_gl_lambda_from_kappa(double kappa) { return 2.0 * kappa * kappa; }
 
 }  // extern "C"
 
+// Lattice and theory of a context, for the network's one-call learned start
+// (C++ linkage: not part of the C interface).
+namespace ss_detail {
+int ctx_shape(const ss_ctx* c, int* Nx, int* Ny, int* theory) {
+  if (!c) return SS_EINVAL;
+  *Nx = c->Nx;
+  *Ny = c->Ny;
+  *theory = c->theory;
+  return SS_OK;
+}
+}  // namespace ss_detail
+
 // ======================================================================= batch
 
 struct ss_batch {

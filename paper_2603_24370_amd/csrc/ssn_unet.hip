@@ -1181,6 +1181,10 @@ int check_shape(int levels, int base, int cin, int cout, int N, int H, int W) {
 
 }  // namespace
 
+namespace ss_detail {
+int ctx_shape(const ss_ctx* c, int* Nx, int* Ny, int* theory);
+}
+
 extern "C" {
 
 long ssn_param_count(int levels, int base, int cin, int cout) {
@@ -1351,6 +1355,31 @@ int ssn_train_step(ssn_net* n, const float* x, const float* target, int nb, floa
 
 // Forward and backward multiply-add flops of one sample (2 flops per MAC),
 // counting the 3x3 and 1x1 convolutions at their real channel counts.
+size_t ssn_init_field_workspace_bytes(ssn_net* n) { return n ? (size_t)n->H * n->W * 2 * sizeof(float) : 0; }
+
+int ssn_init_field(ssn_net* n, ss_ctx* ctx, int nv, const double* xy, const double* w, double kappa, double sigma,
+                   double pin, uint64_t seed, double noise_amp, void* work, size_t work_bytes) {
+  if (!n || !ctx || !work) return nfail(SS_EINVAL, "net, ctx or work is NULL");
+  if (n->cin != 2 || n->cout != 4) return nfail(SS_EINVAL, "the learned start needs a network with 2 inputs and 4 outputs");
+  int Nx = 0, Ny = 0, theory = -1;
+  if (ss_detail::ctx_shape(ctx, &Nx, &Ny, &theory) != SS_OK) return nfail(SS_EINVAL, "ctx is NULL");
+  if (theory != SS_THEORY_AH) return nfail(SS_EINVAL, "the learned start exists for the Abelian Higgs model only");
+  if (Nx != n->W || Ny != n->H) return nfail(SS_ESHAPE, "the network's image size differs from the lattice");
+  if (work_bytes < ssn_init_field_workspace_bytes(n)) return nfail(SS_EINVAL, "work is too small");
+  if ((uintptr_t)work % 256) return nfail(SS_EINVAL, "work must be 256-byte aligned");
+  // input image on the context's stream (the call synchronises it)
+  int rc = ss_learned_input(ctx, nv, xy, kappa, (float*)work);
+  if (rc) return nfail(rc, std::string("input image: ") + ss_last_error());
+  rc = ssn_forward(n, (const float*)work, 1, nullptr);
+  if (rc) return rc;
+  // the corrections are read from the network's own output buffer on the
+  // context's stream, so the forward pass must have finished
+  SN_HIP(hipStreamSynchronize(n->stream));
+  rc = ss_init_learned(ctx, nv, xy, w, n->OUT, sigma, pin, seed, noise_amp);  // synchronises the context's stream
+  if (rc) return nfail(rc, std::string("corrected ansatz: ") + ss_last_error());
+  return SS_OK;
+}
+
 int ssn_flops(ssn_net* n, double* fwd, double* bwd) {
   if (!n) return nfail(SS_EINVAL, "net is NULL");
   double f = 0.0, b = 0.0;

@@ -125,3 +125,9 @@ def test_batch_observables_rejects_null_arguments(L):
     out = (ss.ss_obs * 2)()
     assert L.ss_batch_observables(None, out) == -1
     assert L.ss_batch_observables(None, None) == -1
+
+
+def test_one_call_learned_start_rejects_null_arguments(L):
+    N = ss._ssn_lib()
+    assert N.ssn_init_field_workspace_bytes(None) == 0
+    assert N.ssn_init_field(None, None, 0, None, None, 1.0, 0.0, 0.0, 0, 0.0, None, 0) == -1

@@ -362,3 +362,38 @@ def test_trained_network_starts_lower_in_energy(ss):
     assert np.median(el) < 0.25 * np.median(ea)
     assert sum(l < 0.5 * a for a, l in zip(ea, el)) >= 5
     net.close()
+
+
+def test_one_call_learned_start_equals_the_three_calls(ss):
+    """ssn_init_field gives, bit for bit, the field of ss_learned_input, the forward
+    pass and ss_init_learned made in turn, and refuses a lattice the network does
+    not fit."""
+    import torch
+    P, _, _, net = _setup(ss, seed=4)
+    N, h = H, 0.2
+    cen = [(1.1, -0.6), (-1.7, 1.4), (0.2, 2.1)]
+    s = ss.Solver("abelian_higgs", N, N, h, [2.0], dtype="f32")
+    kw = dict(sigma=3.0, pin=0.5, seed=5, noise_amp=1e-3)
+    net.init_field(s, cen, 1.3, **kw)
+    g1 = s.get_field().cpu().numpy()
+    assert s.info()["step"] == 0
+    x = torch.empty((1, N, N, 2), dtype=torch.float32, device="cuda:0")
+    ss.ss_learned_input(s.ctx, cen, 1.3, x.data_ptr())
+    corr = net.forward(x)
+    assert float(corr.abs().max()) > 1e-3  # the network really corrects the ansatz
+    ss.ss_init_learned(s.ctx, cen, None, corr.data_ptr(), **kw)
+    g2 = s.get_field().cpu().numpy()
+    assert np.array_equal(g1, g2)
+    s.init_vortices(cen, seed=5, noise_amp=1e-3)
+    assert np.abs(s.get_field().cpu().numpy() - g1).max() > 1e-4
+    s.close()
+    # another lattice size and another theory are refused before any work
+    s2 = ss.Solver("abelian_higgs", N + 16, N, h, [2.0], dtype="f32")
+    with pytest.raises(Exception):
+        net.init_field(s2, cen, 1.3)
+    s2.close()
+    s3 = ss.Solver("chiral_magnet", N, N, h, [1.0, 1.0, 0.1, 0.6], dtype="f32")
+    with pytest.raises(Exception):
+        net.init_field(s3, cen, 1.3)
+    s3.close()
+    net.close()
