@@ -8,8 +8,9 @@ FP32-rounded field). Tolerances:
     to 1e-12 relative on the same field; gradients are FP32 stencil
     arithmetic: each of the ~13/h^2-weighted stencil sums rounds at
     2^-24 relative, so |dG| <= 32 * 2^-24 * 13 * max|phi| / h^2 (derived in the
-    design notes); fields after a step agree to 1e-5 relative (the north
-    bound), since G enters the update with weight dt^2 / 6 = h^2 / 24.
+    design notes); fields after a step agree to 1e-5 relative (the stated
+    FP32 tolerance of the flow), since G enters the update with weight
+    dt^2 / 6 = h^2 / 24.
 """
 import math
 
@@ -531,13 +532,13 @@ def test_autotune_picks_a_shape_and_leaves_a_usable_context(ss, orc):
     s.close()
 
 
-@pytest.mark.parametrize("dtype,plan", [("f64", 0), ("f32", 1)])
-def test_checkpoint_resumes_the_flow_bitwise(ss, orc, dtype, plan):
+@pytest.mark.parametrize("theory,dtype,plan", [(AH, "f64", 0), (AH, "f32", 1), (CM, "f64", 0), (CM, "f32", 1)])
+def test_checkpoint_resumes_the_flow_bitwise(ss, orc, theory, dtype, plan):
     Nx, Ny, h = 90, 70, 0.2
-    f = _field(AH, Nx, Ny, h, seed=8)
+    f = _field(theory, Nx, Ny, h, seed=8)
     if dtype == "f32":
         f = f.astype(np.float32).astype(np.float64)
-    s = _solver(ss, AH, f, h, dtype)
+    s = _solver(ss, theory, f, h, dtype)
     s.set_plan(plan)
     s.set_field(f)
     s.flow_step(7)
@@ -545,7 +546,7 @@ def test_checkpoint_resumes_the_flow_bitwise(ss, orc, dtype, plan):
     s.flow_step(9)
     a, va = s.get_field(velocity=True)
     ia = s.info()
-    s2 = _solver(ss, AH, f, h, dtype)
+    s2 = _solver(ss, theory, f, h, dtype)
     s2.set_plan(plan)
     s2.set_state(state)
     assert s2.info()["step"] == 7
@@ -555,11 +556,16 @@ def test_checkpoint_resumes_the_flow_bitwise(ss, orc, dtype, plan):
     assert bool((a == b).all()) and bool((va == vb).all())
     assert (ia["step"], ia["n_arrests"], ia["energy"]) == (ib["step"], ib["n_arrests"], ib["energy"])
     # the same flow in the oracle over all 16 steps
-    phi_r, _, E_r, na = orc.flow(AH, f, np.zeros_like(f), h, [1.0], 16)
-    rel = 1e-11 if dtype == "f64" else 1e-5
-    assert np.abs(_as_np(b) - phi_r).max() <= rel * np.abs(phi_r).max()
+    phi_r, _, E_r, na = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), 16)
+    if dtype == "f64":
+        assert ib["n_arrests"] == na
+    # an FP32 run that arrests at other steps than the FP64 oracle follows
+    # another trajectory; the field comparison needs the same arrest pattern
+    if ib["n_arrests"] == na:
+        rel = 1e-11 if dtype == "f64" else 1e-5
+        assert np.abs(_as_np(b) - phi_r).max() <= rel * np.abs(phi_r).max()
     # a checkpoint of another lattice is refused
-    s3 = _solver(ss, AH, _field(AH, Nx + 2, Ny, h, seed=8), h, dtype)
+    s3 = _solver(ss, theory, _field(theory, Nx + 2, Ny, h, seed=8), h, dtype)
     with pytest.raises(Exception):
         s3.set_state((state[0], state[1], state[2]))
     for x in (s, s2, s3):
