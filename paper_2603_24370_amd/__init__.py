@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libss.so")
 
 SS_OK, SS_NOT_CONVERGED = 0, 1
+SS_EINVAL, SS_ETHEORY, SS_ESHAPE, SS_EHIP, SS_ENONFINITE, SS_ESTATE = -1, -2, -3, -4, -5, -6
 SS_F32, SS_F64 = 0, 1
 SS_GRAD_EL, SS_GRAD_EXACT = 0, 1
 SS_PLAN_STAGES, SS_PLAN_FUSED = 0, 1
@@ -233,7 +234,10 @@ def ss_get_state(ctx, field_ptr, vel_ptr) -> bytes:
 
 
 def ss_set_state(ctx, field_ptr, vel_ptr, state: bytes):
-    buf = ctypes.create_string_buffer(bytes(state), len(state))
+    state = bytes(state)
+    if len(state) != ss_state_bytes():
+        raise ValueError(f"a state blob has {ss_state_bytes()} bytes, not {len(state)}")
+    buf = ctypes.create_string_buffer(state, len(state))
     _check(lib().ss_set_state(ctx, ctypes.c_void_p(field_ptr), ctypes.c_void_p(vel_ptr), buf))
 
 

@@ -572,6 +572,32 @@ def test_checkpoint_resumes_the_flow_bitwise(ss, orc, theory, dtype, plan):
         x.close()
 
 
+def test_checkpoint_refuses_damaged_or_foreign_blobs(ss):
+    Nx, Ny, h = 40, 36, 0.2
+    f = _field(AH, Nx, Ny, h, seed=2)
+    s = _solver(ss, AH, f, h, "f64")
+    s.set_field(f)
+    s.flow_step(3)
+    fv, vv, blob = s.get_state()
+    s32 = _solver(ss, AH, f, h, "f32")
+    with pytest.raises(ss.SSError) as e:  # taken in FP64, offered to an FP32 context
+        s32.set_state((fv, vv, blob))
+    assert e.value.code == ss.SS_ESHAPE
+    bad = bytearray(blob)
+    bad[0] ^= 0xFF  # magic number
+    with pytest.raises(ss.SSError) as e:
+        s.set_state((fv, vv, bytes(bad)))
+    assert e.value.code == ss.SS_EINVAL
+    with pytest.raises(ValueError):  # truncated
+        s.set_state((fv, vv, blob[:-8]))
+    # the refused calls left the context as it was
+    assert s.info()["step"] == 3
+    s.set_state((fv, vv, blob))
+    assert s.info()["step"] == 3
+    s.close()
+    s32.close()
+
+
 def test_checkpoint_resumes_a_minimisation(ss, orc):
     """FP64: a minimisation resumed from a checkpoint in a fresh context stops at the
     step, with the arrest count and field, of the one that was not interrupted, and
