@@ -125,3 +125,44 @@ def test_batch_tiles_and_autotune(ss, orc):
             phi_r, _, _, _ = orc.flow(AH, f, np.zeros_like(f), m.h, m.params, 3)
             assert np.abs(_np(mem.get_field()) - phi_r).max() <= 1e-5 * np.abs(phi_r).max(), tile
     B.close()
+
+
+P_CM = [1.0, 1.0, 0.1, 0.6]
+
+
+@pytest.mark.parametrize("dtype,plan,tile", [("f64", 0, 0), ("f64", 1, 1), ("f32", 0, 0), ("f32", 1, 0)])
+def test_chiral_magnet_batch_matches_oracle_per_member(ss, orc, dtype, plan, tile):
+    """Chiral-magnet members (3 components, projected flow) of uneven sizes stepped
+    together: each member's field against the oracle, and the batch observables
+    (energy, both charges) against the oracle's on the member's own field."""
+    CM = "chiral_magnet"
+    h = 0.2
+    sides = [(40, 33), (71, 64), (96, 90), (33, 48)]
+    fields = []
+    for k, (Nx, Ny) in enumerate(sides):
+        f = I.cm_skyrmion_ansatz(Nx, Ny, h, R=min(Nx, Ny) * h / 8)
+        f = I.renormalise_interior(f + I.noise(30 + k, 3, Nx, Ny, 1e-3))
+        if dtype == "f32":
+            f = f.astype(np.float32).astype(np.float64)
+        fields.append(f)
+    B = ss.Batch(CM, [(Nx, Ny, h, P_CM) for Nx, Ny in sides], dtype=dtype)
+    B.set_plan(plan)
+    B.set_tile(tile)
+    for f, mem in zip(fields, B.members):
+        mem.set_field(f)
+    print(f"[case] CM batch {dtype} plan {plan} tile {tile}", flush=True)
+    infos = B.flow_step(5)
+    rel = 1e-11 if dtype == "f64" else 1e-5
+    obs = B.observables()
+    for k, (f, mem) in enumerate(zip(fields, B.members)):
+        phi_r, v_r, E_r, na = orc.flow(CM, f, np.zeros_like(f), h, P_CM, 5)
+        phi = _np(mem.get_field())
+        assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max(), k
+        assert infos[k]["step"] == 5 and infos[k]["n_arrests"] == na
+        nrm = np.sqrt((phi[:, 2:-2, 2:-2] ** 2).sum(0))
+        assert np.abs(nrm - 1).max() < (1e-14 if dtype == "f64" else 1e-6)
+        r = orc.observables(CM, phi, h, P_CM)
+        assert obs[k]["energy"] == pytest.approx(r["E"], rel=1e-11)
+        assert obs[k]["q_fd"] == pytest.approx(r["Q_fd"], rel=1e-11, abs=1e-12)
+        assert obs[k]["q_bl"] == pytest.approx(r["Q_bl"], abs=1e-9)
+    B.close()
