@@ -317,6 +317,29 @@ def test_device_skyrmion_ansatz_matches_input_module(ss, dtype):
     s.close()
 
 
+@pytest.mark.parametrize("dtype,tile", [("f32", 0), ("f32", 1), ("f64", 1)])
+def test_fused_pass_with_fewer_workgroups_than_tiles(ss, orc, dtype, tile):
+    """A ragged lattice with more tiles (342 on 64 x 16, 684 on 64 x 8) than the
+    fused launch has workgroups, so each workgroup walks several column segments:
+    every site against the oracle after 3 steps."""
+    Nx, Ny, h = 1100, 300, 0.2
+    print(f"[case] fused cap {dtype} tile {tile}", flush=True)
+    f = _field(AH, Nx, Ny, h, seed=17)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    s = _solver(ss, AH, f, h, dtype)
+    s.set_plan(ss.SS_PLAN_FUSED)
+    s.set_tile(tile)
+    s.set_field(f)
+    info = s.flow_step(3)
+    phi = _as_np(s.get_field())
+    phi_r, _, E_r, na = orc.flow(AH, f, np.zeros_like(f), h, [1.0], 3)
+    rel = 1e-11 if dtype == "f64" else 1e-5
+    assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max()
+    assert info["step"] == 3 and info["n_arrests"] == na
+    s.close()
+
+
 def test_large_lattice_sampled_parity(ss, orc):
     """The 4096^2 GL workload in the launch configuration the benchmark times:
     energy to 1e-9 relative (FP64 reduction of FP32 values vs the oracle's FP64
