@@ -170,11 +170,17 @@ int ss_workspace_bytes(const char* theory, int Nx, int Ny, int dtype, size_t* by
 int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype,
               void* workspace, size_t ws_bytes, void* stream, ss_ctx** out);
 
+/* Release a context: wait for its stream, destroy the HIP graph and the
+ * capture stream it created (Sec. 3.1: the simulation object owns its
+ * buffers; here the caller keeps the device memory and the library the host
+ * objects). The workspace may be freed by the caller afterwards. */
 void ss_destroy(ss_ctx* ctx);
 
 /* Copy the initial field (device array of the context's dtype and the layout
  * above; its halo holds the fixed boundary values) into the context, start
- * from rest (phidot = 0, Sec. 3.2) and reset step and arrest counters. */
+ * from rest (phidot = 0, Sec. 3.2) and reset step and arrest counters. The
+ * array is tightly packed (row pitch Nx + 4 elements); there is no pitch
+ * argument. */
 int ss_set_field(ss_ctx* ctx, const void* field);
 
 /* Initial field from an analytic ansatz, computed on the device (the paper's
@@ -205,7 +211,9 @@ int ss_init_ansatz(ss_ctx* ctx, int kind, int n, const double* xy, const double*
  * is the pass of stages 2-4 and ms[2] = ms[3] = 0. Synchronises. */
 int ss_time_passes(ss_ctx* ctx, int n_steps, double* ms);
 
-/* Copy the current field and (if velocity != NULL) velocity to device arrays. */
+/* Copy the current field and (if velocity != NULL) the fictitious velocity
+ * (Sec. 3.1 buffers, Sec. 3.2 first-order system) to device arrays of the
+ * layout above, halo included. Synchronises. */
 int ss_get_field(ss_ctx* ctx, void* field, void* velocity);
 
 /* Checkpoint and resume. ss_get_state copies the current field and velocity
@@ -221,7 +229,9 @@ size_t ss_state_bytes(void);
 int ss_get_state(ss_ctx* ctx, void* field, void* velocity, void* state);
 int ss_set_state(ss_ctx* ctx, const void* field, const void* velocity, const void* state);
 
-/* E_h and gradient of a field: `field` (device, NULL = the current field).
+/* E_h and gradient of a field (the force of eq. (3), Sec. 3.2; energy density of
+ * Tab. 1 / eq. (5) with the eq. (1) stencil): `field` (device, NULL = the
+ * current field).
  * If grad != NULL it receives G (device array, layout above, zero halo): the
  * gradient of the selected form; for the chiral magnet, at the normalised
  * field and projected on the tangent plane. Does not change the flow state.
@@ -233,14 +243,16 @@ int ss_energy_grad(ss_ctx* ctx, const void* field, void* grad, double* energy, d
  * If info != NULL the stream is synchronised and info filled. */
 int ss_flow_step(ss_ctx* ctx, int n_steps, ss_step_info* info);
 
-/* Flow until a stop rule holds, replaying a captured HIP graph of
+/* Arrested Newton flow (Sec. 3.2, eq. (3)-(4)) until a stop rule holds, replaying a captured HIP graph of
  * stop->graph_steps steps; each kernel skips its work once the device-side
  * stop flag is set, so the field stops exactly at the first state meeting a
  * rule. Returns SS_OK if converged, SS_NOT_CONVERGED at max_steps,
  * SS_ENONFINITE if a non-finite value appeared. */
 int ss_minimise(ss_ctx* ctx, const ss_stop* stop, ss_min_info* info);
 
-/* Observables of the current field. Synchronises. */
+/* Observables of the current field (ss_obs; the global quantities of Sec. 3.3:
+ * energy, topological charge, flux), reduced on the device in FP64.
+ * Synchronises. */
 int ss_observables(ss_ctx* ctx, ss_obs* out);
 
 /* Energy target of the minimise stop rule SS_STOP_TARGET (E <= e_target);

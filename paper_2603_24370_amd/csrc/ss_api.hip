@@ -394,6 +394,19 @@ unsigned long long noise_key(uint64_t seed, double amp) {
 
 }  // namespace
 
+namespace {
+// Theory, lattice and parameters of a problem, resolved and validated before
+// any device work (Sec. 3.1: parameters are resolved first, then packed).
+struct Problem {
+  int theory, dtype, grad_mode, C, nf_need;
+  double courant;
+  double p[4];
+};
+
+int resolve_problem(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype, Problem* pb);
+
+}  // namespace
+
 extern "C" {
 
 int ss_theory_id(const char* name) {
@@ -423,25 +436,23 @@ int ss_workspace_bytes(const char* theory, int Nx, int Ny, int dtype, size_t* by
   return SS_OK;
 }
 
-int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype, void* workspace,
-              size_t ws_bytes, void* stream, ss_ctx** out) {
-  if (!out) return fail(SS_EINVAL, "out is NULL");
-  *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+int resolve_problem(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype, Problem* pb) {
   const int th = ss_theory_id(theory);
   if (th < 0) return fail(SS_ETHEORY, std::string("unknown theory '") + (theory ? theory : "(null)") + "'");
-  size_t need = 0;
-  int rc = ss_workspace_bytes(theory, Nx, Ny, dtype, &need);
-  if (rc) return rc;
+  if (dtype != SS_F32 && dtype != SS_F64) return fail(SS_EINVAL, "dtype must be SS_F32 or SS_F64");
+  if (Nx < 8 || Ny < 8 || Nx > 65536 || Ny > 65536) return fail(SS_ESHAPE, "Nx, Ny must lie in [8, 65536]");
   if (!(h > 0.0) || !std::isfinite(h)) return fail(SS_EINVAL, "lattice spacing h must be positive and finite");
-  if (!workspace || ws_bytes < need) return fail(SS_EINVAL, "workspace missing or smaller than ss_workspace_bytes");
-  if (((uintptr_t)workspace) % 256 != 0) return fail(SS_EINVAL, "workspace must be 256-byte aligned");
   const int nf_need = th == SS_THEORY_AH ? 1 : 4;
   if (!params || !params->f || params->nf < nf_need || params->nf > nf_need + 1)
     return fail(SS_EINVAL, th == SS_THEORY_AH ? "abelian_higgs needs params.f = {lambda [, courant]}"
                                               : "chiral_magnet needs params.f = {J, D, K, B [, courant]}");
   for (int k = 0; k < params->nf; ++k)
     if (!std::isfinite(params->f[k])) return fail(SS_EINVAL, "non-finite parameter");
-  double courant = params->nf > nf_need ? params->f[nf_need] : 0.5;
+  const double courant = params->nf > nf_need ? params->f[nf_need] : 0.5;
   if (!(courant > 0.0 && courant < 1.0)) return fail(SS_EINVAL, "courant number C must lie in (0, 1)");
   int grad_mode = SS_GRAD_EL;
   if (params->ni > 0) {
@@ -449,18 +460,45 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
     grad_mode = params->i[0];
     if (grad_mode != SS_GRAD_EL && grad_mode != SS_GRAD_EXACT) return fail(SS_EINVAL, "unknown grad_mode");
   }
+  pb->theory = th;
+  pb->dtype = dtype;
+  pb->grad_mode = grad_mode;
+  pb->C = th == SS_THEORY_AH ? 4 : 3;
+  pb->nf_need = nf_need;
+  pb->courant = courant;
+  for (int k = 0; k < 4; ++k) pb->p[k] = k < nf_need ? params->f[k] : 0.0;
+  return SS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype, void* workspace,
+              size_t ws_bytes, void* stream, ss_ctx** out) {
+  if (!out) return fail(SS_EINVAL, "out is NULL");
+  *out = nullptr;
+  Problem pb;
+  int rc = resolve_problem(theory, Nx, Ny, h, params, dtype, &pb);
+  if (rc) return rc;
+  size_t need = 0;
+  rc = ss_workspace_bytes(theory, Nx, Ny, dtype, &need);
+  if (rc) return rc;
+  if (!workspace || ws_bytes < need) return fail(SS_EINVAL, "workspace missing or smaller than ss_workspace_bytes");
+  if (((uintptr_t)workspace) % 256 != 0) return fail(SS_EINVAL, "workspace must be 256-byte aligned");
+  const int th = pb.theory, grad_mode = pb.grad_mode;
 
   ss_ctx* c = new (std::nothrow) ss_ctx();
   if (!c) return fail(SS_EINVAL, "out of host memory");
   c->theory = th;
   c->dtype = dtype;
   c->grad_mode = grad_mode;
-  c->C = th == SS_THEORY_AH ? 4 : 3;
+  c->C = pb.C;
   c->Nx = Nx;
   c->Ny = Ny;
   c->h = h;
-  c->courant = courant;
-  for (int k = 0; k < 4; ++k) c->p[k] = k < nf_need ? params->f[k] : 0.0;
+  c->courant = pb.courant;
+  for (int k = 0; k < 4; ++k) c->p[k] = pb.p[k];
   c->stream = (hipStream_t)stream;
   c->ws = (char*)workspace;
   c->L = make_layout(c->C, Nx, Ny, (int)esize_of(dtype));
@@ -741,7 +779,7 @@ int ss_flow_step(ss_ctx* c, int n_steps, ss_step_info* info) {
 
 int ss_minimise(ss_ctx* c, const ss_stop* stop, ss_min_info* info) {
   if (!c || !stop) return fail(SS_EINVAL, "ctx or stop is NULL");
-  if (stop->window < 0 || stop->window > kHistLen) return fail(SS_EINVAL, "window must lie in [0, 128]");
+  if (stop->window < 0 || stop->window > kMaxWindow) return fail(SS_EINVAL, "window must lie in [0, 128]");
   if (stop->max_steps < 0) return fail(SS_EINVAL, "max_steps < 0");
   int K = stop->graph_steps > 0 ? stop->graph_steps : kDefaultGraphSteps;
   if (K % 2) ++K;
@@ -1540,7 +1578,7 @@ int ss_batch_flow_step(ss_batch* b, int n_steps, ss_step_info* infos) {
 
 int ss_batch_minimise(ss_batch* b, const ss_stop* stop, ss_min_info* infos) {
   if (!b || !stop) return fail(SS_EINVAL, "batch or stop is NULL");
-  if (stop->window < 0 || stop->window > kHistLen) return fail(SS_EINVAL, "window must lie in [0, 128]");
+  if (stop->window < 0 || stop->window > kMaxWindow) return fail(SS_EINVAL, "window must lie in [0, 128]");
   int K = stop->graph_steps > 0 ? stop->graph_steps : kDefaultGraphSteps;
   if (b->graph && b->graph_steps != K) {
     (void)hipGraphExecDestroy(b->graph);

@@ -7,7 +7,10 @@
 namespace ss {
 
 constexpr int kHalo = 2;          // Sec. 3.1: default halo width two
-constexpr int kHistLen = 128;     // ring of energies for the stall rule
+constexpr int kMaxWindow = 128;   // largest stall-rule window accepted by the API
+// Ring of energies for the stall rule. It is longer than the largest window, so
+// the entry of step s - W is never the slot that step s overwrites.
+constexpr int kHistLen = 2 * kMaxWindow;
 constexpr int kMaxComp = 4;
 
 // Device-resident state of one flow (written only by kernels, read by the host

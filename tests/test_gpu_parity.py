@@ -259,6 +259,26 @@ def test_max_steps_and_stall_rules(ss, orc):
     s.close()
 
 
+@pytest.mark.parametrize("rel_e_tol", [1e-6, 1e-3])
+def test_stall_rule_with_the_largest_window(ss, orc, rel_e_tol):
+    """window = 128 (the largest accepted): the energy of step s - 128 must be a
+    different ring entry from the one step s writes, else |E - E| = 0 would stop
+    the run at step 128. The stop step equals the oracle's (which keeps the
+    whole history): 223 and 177 steps here."""
+    Nx, Ny, h = 32, 32, 0.25
+    print(f"[case] stall window=128 tol={rel_e_tol}", flush=True)
+    f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.2, 0.1)]) + I.noise(8, 4, Nx, Ny, 1e-3)
+    s = _solver(ss, AH, f, h, "f64")
+    s.set_field(f)
+    res = s.minimise(grad_tol=0.0, rel_e_tol=rel_e_tol, window=128, max_steps=700, graph_steps=8)
+    _, _, info_r = orc.minimise(AH, f, h, [1.0], grad_tol=0.0, rel_e_tol=rel_e_tol, window=128, max_steps=700)
+    assert info_r["reason"] == 2 and info_r["steps"] > 128
+    assert res["reason"] == "stall"
+    assert res["step"] == info_r["steps"] and res["n_arrests"] == info_r["arrests"]
+    assert res["energy"] == pytest.approx(info_r["E"], rel=1e-12)
+    s.close()
+
+
 def test_nonfinite_is_reported(ss):
     Nx, Ny, h = 40, 24, 0.25
     f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.2, 0.1)])
