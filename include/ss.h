@@ -238,6 +238,25 @@ int ss_set_state(ss_ctx* ctx, const void* field, const void* velocity, const voi
  * Synchronises; energy and gnorm_inf (may be NULL) are host outputs. */
 int ss_energy_grad(ss_ctx* ctx, const void* field, void* grad, double* energy, double* gnorm_inf);
 
+/* Allocation-free ss_energy_grad, for callers that cannot allocate device
+ * memory (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc). Same result as ss_energy_grad on a context created with the same
+ * theory, lattice, h, params and dtype, from the same kernels, but without a
+ * context or workspace: field and grad (grad may be NULL) are device arrays of
+ * the tight layout above (pitch Nx + 4); energy and gnorm_inf are host outputs
+ * (may be NULL). The status block and the workgroup partials live in a
+ * file-scope device array of the library, one per GPU, of fixed size (a status
+ * block plus 2048 partials of 32 bytes, about 67 KB), kept until the process
+ * ends; every lattice the API accepts (8 <= Nx, Ny <= 65536) fits it, and a
+ * launch that would need more partials returns SS_ESHAPE. The call uses the
+ * calling thread's current device, which must be the device of field, grad
+ * and stream. It calls no hipMalloc or hipFree. Calls that overlap on one GPU
+ * (concurrent streams or threads) share the array and race; serialise them.
+ * The array keeps the last call's contents; nothing in it needs clearing,
+ * since every slot read is written first by the same call. Synchronises. */
+int ss_energy_grad_noalloc(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype,
+                           const void* field, void* grad, double* energy, double* gnorm_inf, void* stream);
+
 /* n_steps arrested-Newton-flow steps, then the arrest test of the final field
  * (so the state afterwards is that of eq. (4) applied after every step).
  * If info != NULL the stream is synchronised and info filled. */

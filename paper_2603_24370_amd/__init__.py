@@ -76,7 +76,8 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_batch_create",
            "ss_batch_destroy", "ss_batch_member", "ss_batch_size", "ss_batch_flow_step", "ss_batch_minimise",
            "ss_batch_set_tile", "ss_batch_autotune", "ss_batch_set_plan", "ss_batch_get_plan", "ss_batch_observables", "ss_set_energy_target", "ss_learned_input",
-           "ss_learned_targets", "ss_init_learned", "ss_state_bytes", "ss_get_state", "ss_set_state"]
+           "ss_learned_targets", "ss_init_learned", "ss_state_bytes", "ss_get_state", "ss_set_state",
+           "ss_energy_grad_noalloc"]
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
                "ssn_adam_step", "ssn_set_grad_clip",
@@ -110,6 +111,8 @@ def lib():
     L.ss_init_ansatz.argtypes = [vp, i, i, dp, dp, dp, ctypes.c_uint64, d]
     L.ss_time_passes.argtypes = [vp, i, dp]
     L.ss_energy_grad.argtypes = [vp, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d)]
+    L.ss_energy_grad_noalloc.argtypes = [cp, i, i, d, ctypes.POINTER(ss_params), i, vp, vp, ctypes.POINTER(d),
+                                         ctypes.POINTER(d), vp]
     L.ss_flow_step.argtypes = [vp, i, ctypes.POINTER(ss_step_info)]
     L.ss_minimise.argtypes = [vp, ctypes.POINTER(ss_stop), ctypes.POINTER(ss_min_info)]
     L.ss_observables.argtypes = [vp, ctypes.POINTER(ss_obs)]
@@ -245,6 +248,18 @@ def ss_energy_grad(ctx, field_ptr=None, grad_ptr=None):
     e, g = ctypes.c_double(0), ctypes.c_double(0)
     _check(lib().ss_energy_grad(ctx, ctypes.c_void_p(field_ptr or 0), ctypes.c_void_p(grad_ptr or 0),
                                 ctypes.byref(e), ctypes.byref(g)))
+    return e.value, g.value
+
+
+def ss_energy_grad_noalloc(theory, Nx, Ny, h, f_params, i_params, dtype, field_ptr, grad_ptr, stream_ptr):
+    """Allocation-free evaluation (no context, no workspace). Returns (E, max |G|)."""
+    fa = (ctypes.c_double * max(1, len(f_params)))(*f_params)
+    ia = (ctypes.c_int * max(1, len(i_params)))(*i_params)
+    p = ss_params(fa, len(f_params), ia, len(i_params))
+    e, g = ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib().ss_energy_grad_noalloc(_b(theory), int(Nx), int(Ny), float(h), ctypes.byref(p), int(dtype),
+                                        ctypes.c_void_p(field_ptr), ctypes.c_void_p(grad_ptr or 0), ctypes.byref(e),
+                                        ctypes.byref(g), ctypes.c_void_p(stream_ptr or 0)))
     return e.value, g.value
 
 

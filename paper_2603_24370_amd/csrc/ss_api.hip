@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -18,6 +19,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/ss.h"
 #include "ss_kernels.hpp"
@@ -757,6 +759,122 @@ int ss_energy_grad(ss_ctx* c, const void* field, void* grad, double* energy, dou
   if (energy) *energy = d.eval_E;
   if (gnorm_inf) *gnorm_inf = d.eval_gmax;
   if (d.nonfinite) return fail(SS_ENONFINITE, "non-finite energy or gradient");
+  return SS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free evaluation
+// ss_energy_grad_noalloc keeps its status block and workgroup partials in this
+// file-scope array instead of a caller's workspace. Every GPU holds its own
+// copy; the host reaches it only through the address hipGetSymbolAddress gives
+// on that device (the array's name is not a device address in host code).
+namespace {
+
+constexpr size_t kScratchStatus = (sizeof(DevStatus) + 255) / 256 * 256;
+constexpr size_t kScratchBytes = kScratchStatus + 4 * kMaxGroups * sizeof(double);
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Address of the calling thread's current device's copy of `scratch`, looked up
+// once per device.
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  SS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SS_EINVAL, "device index beyond the library's device table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    SS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(SS_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SS_OK;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) fill_zero(T* __restrict__ p, long n) {
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < n; k += (long)gridDim.x * 256L) p[k] = T(0);
+}
+
+template <class T>
+void enqueue_noalloc_eval(const ss_ctx* c, const void* field, void* grad, hipStream_t s) {
+  const long pitch = c->Nx + 4, plane = pitch * (c->Ny + 4);
+  if (grad) {
+    const long n = (long)c->C * plane;
+    const int nb = (int)std::min<long>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL((fill_zero<T>), dim3(nb), dim3(256), 0, s, (T*)grad, n);
+  }
+  PassArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  // the evaluation pass reads only the source field, here in the caller's layout
+  a.B.phi[0] = a.B.phi[1] = (T*)field;
+  a.B.pitch = pitch;
+  a.B.plane = plane;
+  a.B.Nx = c->Nx;
+  a.B.Ny = c->Ny;
+  a.cf = coeffs_of(c);
+  a.st = c->st;
+  a.partials = c->partials;
+  a.src = (const T*)field;
+  a.out = (T*)grad;
+  a.out_pitch = pitch;
+  a.out_plane = plane;
+  a.ntx = c->L.ntx;
+  a.nty = c->L.nty;
+  a.seg = c->L.seg;
+  launch_pass<T, kEval>(c, a, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_energy_grad_noalloc(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype,
+                           const void* field, void* grad, double* energy, double* gnorm_inf, void* stream) {
+  Problem pb;
+  int rc = resolve_problem(theory, Nx, Ny, h, params, dtype, &pb);
+  if (rc) return rc;
+  if (!field) return fail(SS_EINVAL, "field is NULL");
+  void* sp = nullptr;
+  rc = scratch_of_current_device(&sp);
+  if (rc) return rc;
+  // a host-side description of the problem; no workspace behind it
+  ss_ctx c;
+  std::memset(&c, 0, sizeof(c));
+  c.theory = pb.theory;
+  c.dtype = dtype;
+  c.grad_mode = pb.grad_mode;
+  c.C = pb.C;
+  c.Nx = Nx;
+  c.Ny = Ny;
+  c.h = h;
+  c.courant = pb.courant;
+  for (int k = 0; k < 4; ++k) c.p[k] = pb.p[k];
+  c.stream = (hipStream_t)stream;
+  c.tile = kDefaultTile;
+  set_tiles(c.L, Nx, Ny, c.tile);
+  if (c.L.nlaunch > kMaxGroups) return fail(SS_ESHAPE, "more workgroup partials than the scratch array holds");
+  c.st = (DevStatus*)sp;
+  c.partials = (double*)((char*)sp + kScratchStatus);
+  if (dtype == SS_F32) enqueue_noalloc_eval<float>(&c, field, grad, c.stream);
+  else enqueue_noalloc_eval<double>(&c, field, grad, c.stream);
+  SS_HIP(hipGetLastError());
+  static_assert(offsetof(DevStatus, eval_gmax) == offsetof(DevStatus, eval_E) + sizeof(double),
+                "eval_E and eval_gmax are read back as one pair");
+  double vals[2];
+  int nonfinite = 0;
+  SS_HIP(hipMemcpyAsync(vals, &c.st->eval_E, sizeof(vals), hipMemcpyDeviceToHost, c.stream));
+  SS_HIP(hipMemcpyAsync(&nonfinite, &c.st->nonfinite, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  SS_HIP(hipStreamSynchronize(c.stream));
+  if (energy) *energy = vals[0];
+  if (gnorm_inf) *gnorm_inf = vals[1];
+  if (nonfinite) return fail(SS_ENONFINITE, "non-finite energy or gradient");
   return SS_OK;
 }
 

@@ -208,7 +208,10 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
   auto stage_at = [&](int gi_, int gj_, T (&raw_p)[4], T (&raw_v)[4], T (&raw_a)[4], T (&S)[4]) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) raw_p[c] = raw_v[c] = raw_a[c] = S[c] = T(0);
-    if (gj_ > Ny + 1) return;
+    // Columns right of the padded lattice feed only discarded sites. The flow's
+    // own rows are long enough to read them; an evaluated field may come in a
+    // caller's tight layout (pitch Nx + 4), so there they are not read.
+    if (gj_ > Ny + 1 || (PASS == kEval && gi_ > Nx + 1)) return;
     const long off = (long)(gj_ + 2) * pitch + (gi_ + 2);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
