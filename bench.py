@@ -207,22 +207,56 @@ def make_solver(wl, autotune_steps=10):
     return s, params, tune
 
 
+def host_cores() -> int:
+    """Cores this process may use: its CPU affinity, capped by OMP_NUM_THREADS
+    where set (the host's share for one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
 def cpu_baseline(s, wl, params, window=1024, steps=10):
-    """The FP64 oracle (single thread) on a central window of the same field."""
+    """The FP64 oracle as it stands (one thread per call) on windows of the same
+    field: first one core on the central window, then every usable host core at
+    once, one window per thread (the oracle is a C library called through
+    ctypes, which releases the interpreter lock, so the threads run in parallel).
+    Each window keeps its neighbours as a fixed halo."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
     oracle.build(force=False)
     f = s.get_field().double().cpu().numpy()
     N = wl["N"]
     w = min(window, N)
-    a = (N - w) // 2
-    sub = np.ascontiguousarray(f[:, a:a + w + 4, a:a + w + 4])
+
+    def window_at(a, b):
+        return np.ascontiguousarray(f[:, a:a + w + 4, b:b + w + 4])
+
+    def run(sub):
+        oracle.flow(wl["theory"], sub, np.zeros_like(sub), wl["h"], params, steps)
+
+    c = (N - w) // 2
     t0 = time.perf_counter()
-    oracle.flow(wl["theory"], sub, np.zeros_like(sub), wl["h"], params, steps)
-    dt = time.perf_counter() - t0
-    return {"value": w * w * steps / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} RK4 steps of the central {w}x{w} window of the same field (its neighbours as a "
-                      f"fixed halo), FP64, {dt:.1f} s"}
+    run(window_at(c, c))
+    dt1 = time.perf_counter() - t0
+    cores = host_cores()
+    per = max(1, N // w)
+    origins = [((k // per) % per * w, k % per * w) for k in range(cores)]
+    subs = [window_at(min(a, N - w), min(b, N - w)) for a, b in origins]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(run, subs))
+    dtn = time.perf_counter() - t0
+    return {"value": cores * w * w * steps / dtn, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} threads, each {steps} RK4 steps of its own {w}x{w} window of the same field (its "
+                      f"neighbours as a fixed halo), FP64, {dtn:.1f} s wall",
+            "value_1core": w * w * steps / dt1,
+            "sample_1core": f"{steps} RK4 steps of the central {w}x{w} window on one core, {dt1:.1f} s"}
 
 
 def measured_copy_gbps(nbytes=1 << 30, reps=10):

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-THEORIES = {"abelian_higgs": 0, "chiral_magnet": 1, "toy_harmonic": 2}
+THEORIES = {"abelian_higgs": 0, "chiral_magnet": 1, "toy_harmonic": 2, "toy_offset": 3}
 COURANT = 0.5  # dt = C * h with the default C of Sec. 3.1
 GRAD_EXACT = 0  # G = h^-2 dE_h/dphi
 GRAD_EL = 1     # continuum Euler-Lagrange expression evaluated with eq. (1)-(2)

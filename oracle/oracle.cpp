@@ -48,13 +48,14 @@
 
 namespace {
 
-enum Theory { TH_AH = 0, TH_CM = 1, TH_TOY = 2 };
+enum Theory { TH_AH = 0, TH_CM = 1, TH_TOY = 2, TH_TOY_OFFSET = 3 };
 
 int n_components(int theory) {
   switch (theory) {
     case TH_AH: return 4;   // psi_1, psi_2, A_1, A_2
     case TH_CM: return 3;   // n_1, n_2, n_3
     case TH_TOY: return 1;  // one real scalar per site
+    case TH_TOY_OFFSET: return 1;
   }
   return -1;
 }
@@ -184,7 +185,9 @@ void cm_partials(const Jet<double>& Jt, double J, double D, double K, double Bz,
   F[0][3] = F[1][3] = 0.0;
 }
 
-// --- Harmonic toy theory (test of the integrator only): e = m2/2 phi^2 --------
+// --- Harmonic toy theories (tests of the integrator and stop rules only) ------
+// e = m2/2 phi^2, and e = m2/2 phi^2 + e0 (a floor under the energy, so that its
+// relative change over a window tends to zero and the stall rule can fire).
 template <class T>
 T toy_density(const Jet<T>& Jt, double m2) { return 0.5 * m2 * Jt.f[0] * Jt.f[0]; }
 
@@ -193,6 +196,7 @@ T density(int theory, const Jet<T>& Jt, const double* p) {
   switch (theory) {
     case TH_AH: return ah_density(Jt, p[0]);
     case TH_CM: return cm_density(Jt, p[0], p[1], p[2], p[3]);
+    case TH_TOY_OFFSET: return toy_density(Jt, p[0]) + p[1];
     default: return toy_density(Jt, p[0]);
   }
 }

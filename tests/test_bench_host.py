@@ -29,3 +29,23 @@ def test_traffic_record_is_keyed_by_tile_and_source():
     # either the committed counters match the current kernel code, or nothing is reported
     assert rec is None or (rec["total_GB"] > 0 and "kernel" in rec)
     assert bench.traffic_record("P234", "gl4096", 99) is None
+
+
+def test_cpu_baseline_runs_the_oracle_on_every_usable_core(monkeypatch):
+    """The CPU leg times the unchanged oracle on one core and on every usable
+    core (one window per thread); on a small field both figures are positive
+    and the reported core count is the usable count."""
+    import numpy as np
+    import torch
+    from paper_2603_24370_amd import inputs as I
+    monkeypatch.setenv("OMP_NUM_THREADS", "3")
+    f = I.ah_vortex_ansatz(64, 64, 0.2, [(0.5, -0.3)])
+
+    class FakeSolver:
+        def get_field(self):
+            return torch.as_tensor(f, dtype=torch.float32)
+
+    wl = dict(theory="abelian_higgs", N=64, h=0.2)
+    r = bench.cpu_baseline(FakeSolver(), wl, [1.0], window=32, steps=1)
+    assert r["cores"] == min(3, bench.host_cores()) and r["kind"] == "oracle"
+    assert r["value"] > 0 and r["value_1core"] > 0 and "32x32" in r["sample"]

@@ -380,6 +380,94 @@ def test_chiral_magnet_flow_keeps_unit_length(orc):
     assert np.abs((phi * v).sum(0)[2:-2, 2:-2]).max() < 1e-14
 
 
+def _toy_stop_prediction(m2, h, C, e0, x0, W, tol):
+    """Stop step and arrest count of arrested Newton flow on the one-site toy
+    e = m2/2 x^2 + e0 under the stall rule alone, from the closed-form RK4
+    amplification u -> R(-i w dt) u of u = x + i v / w (as in the test above)."""
+    w, dt = math.sqrt(m2), C * h
+    z = -1j * w * dt
+    R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    u, E, hist, arrests = x0 + 0j, h * h * (0.5 * m2 * x0 ** 2 + e0), [], 0
+    for s in range(100000):
+        hist.append(E)
+        if s >= W and abs(E - hist[s - W]) <= tol * abs(E):
+            return s, arrests
+        u = R * u
+        E_new = h * h * (0.5 * m2 * u.real ** 2 + e0)
+        if E_new > E:
+            u, arrests = u.real + 0j, arrests + 1
+        E = E_new
+    raise AssertionError("no stop")
+
+
+@pytest.mark.parametrize("W,tol,steps", [(5, 1e-3, 25), (8, 1e-4, 34), (3, 1e-2, 21), (20, 1e-6, 54)])
+def test_stall_rule_stops_where_the_closed_form_predicts(orc, W, tol, steps):
+    """The energy-stall rule |E(s) - E(s - W)| <= tol |E(s)| on a toy whose per-step
+    energies are known in closed form: the oracle stops at the predicted step with
+    the predicted number of arrests (a wrong window offset or comparison shifts it)."""
+    m2, h, C, e0, x0 = 1.0, 0.5, 0.5, 0.02, 1.0
+    s_ref, arrests_ref = _toy_stop_prediction(m2, h, C, e0, x0, W, tol)
+    assert s_ref == steps
+    phi = np.zeros((1, 5, 5))
+    phi[0, 2, 2] = x0
+    _, _, info = orc.minimise("toy_offset", phi, h, [m2, e0], grad_tol=0.0, rel_e_tol=tol, window=W,
+                              max_steps=100000)
+    assert info["reason"] == 2 and info["steps"] == s_ref and info["arrests"] == arrests_ref
+
+
+def test_cm_force_is_tangent_and_ignores_stage_point_length(orc):
+    """The chiral magnet's stage force (Sec. 3.2 projection in every stage) is taken at
+    the normalised stage point and projected on its tangent plane: it is orthogonal
+    to the normalised point, and scaling each interior site of the stage point by
+    its own positive factor leaves it unchanged."""
+    rng = np.random.default_rng(21)
+    Nx, Ny, h, p = 14, 11, 0.3, [1.3, 0.8, 0.2, 0.5]
+    n = _rand_field(rng, 3, Nx, Ny)
+    n[:, :2, :] = n[:, -2:, :] = n[:, :, :2] = n[:, :, -2:] = 0
+    n[2, :2, :] = n[2, -2:, :] = n[2, :, :2] = n[2, :, -2:] = 1
+    n = I.renormalise_interior(n)
+    a = orc.acceleration(CM, n, h, p)
+    scale = np.ones((Ny + 4, Nx + 4))
+    scale[2:-2, 2:-2] = rng.uniform(0.5, 2.0, size=(Ny, Nx))
+    a_scaled = orc.acceleration(CM, n * scale, h, p)
+    assert np.abs(a_scaled - a).max() <= 1e-13 * np.abs(a).max()
+    assert np.abs((a * n).sum(0)).max() <= 1e-13 * np.abs(a).max()
+    # the projection is not a no-op here: the raw force has a normal component
+    G = orc.gradient(CM, n, h, p)
+    assert np.abs((G * n).sum(0)[2:-2, 2:-2]).max() > 0.1
+
+
+def test_cm_flow_converges_to_the_constrained_pendulum(orc):
+    """With J = D = 0 every site is a spherical pendulum in V = K(1 - n3^2) + B(1 - n3).
+    Released from rest at tilt th0 it swings in a vertical plane,
+    th'' = -(2K sin th cos th + B sin th), solved here by scipy to 1e-13. The flow
+    (stage points normalised, forces projected, n' renormalised and v' projected)
+    converges to that motion at first order in dt: the stage force carries no
+    centripetal term -|v|^2 n, which only the end-of-step projection supplies, so
+    the velocity has an O(dt^2) local error. Halving dt halves both errors, and
+    the error constants fix the scheme: without the tangent projection of the
+    stage force they are four times larger."""
+    from scipy.integrate import solve_ivp
+    K, B, th0, T = 0.1, 0.6, 1.0, 1.2
+    r = solve_ivp(lambda t, y: [y[1], -(2 * K * math.sin(y[0]) * math.cos(y[0]) + B * math.sin(y[0]))],
+                  (0.0, T), [th0, 0.0], rtol=1e-13, atol=1e-14, method="DOP853")
+    th, om = r.y[0, -1], r.y[1, -1]
+    n_ex = np.array([math.sin(th), 0.0, math.cos(th)])
+    v_ex = om * np.array([math.cos(th), 0.0, -math.sin(th)])
+    phi = np.zeros((3, 12, 12))
+    phi[0], phi[2] = math.sin(th0), math.cos(th0)
+    errs = []
+    for C in (0.1, 0.05, 0.025, 0.0125):
+        # h = 1, dt = C: the sites are decoupled (no gradient terms), so h only sets dt
+        ph, v, _, na = orc.flow(CM, phi, np.zeros_like(phi), 1.0, [0.0, 0.0, K, B], int(round(T / C)), courant=C)
+        assert na == 0  # the pendulum only descends before T: no arrest
+        assert np.abs(ph[:, 2:-2, 2:-2] - ph[:, 5:6, 5:6]).max() == 0.0  # all sites alike
+        errs.append((np.abs(ph[:, 5, 5] - n_ex).max(), np.abs(v[:, 5, 5] - v_ex).max()))
+    for (en0, ev0), (en1, ev1) in zip(errs, errs[1:]):
+        assert 1.9 < en0 / en1 < 2.15 and 1.9 < ev0 / ev1 < 2.15
+    assert errs[-1][0] < 1.5e-4 and errs[-1][1] < 6e-4
+
+
 # ------------------------------------------------------------ topology/physics
 
 def test_berg_luscher_charge_is_integer_for_random_fields(orc):

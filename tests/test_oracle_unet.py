@@ -92,3 +92,32 @@ def test_adam_first_step_closed_form():
     want = np.array([1.0, -2.0, 0.5]) - 0.01 * G["w"] / (np.abs(G["w"]) + 1e-8)
     assert np.allclose(P["w"], want, rtol=0, atol=1e-15)
     assert st["t"] == 1
+
+
+def test_silu_hand_values():
+    """SiLU z / (1 + e^-z) (Elfwing, Uchibe and Doya 2018) at points worked by hand:
+    0 at 0; ln 2 / (1 + 1/2) at z = ln 2; -ln 2 / 3 at z = -ln 2 (e^{ln 2} = 2);
+    z -> z for large z, -> 0 for very negative z."""
+    ln2 = np.log(2.0)
+    z = np.array([0.0, ln2, -ln2, 50.0, -50.0])
+    want = np.array([0.0, ln2 / 1.5, -ln2 / 3.0, 50.0, 0.0])
+    got = U.silu(z)
+    assert np.abs(got - want).max() < 1e-15 * 50 + 1e-20
+    assert abs(got[4]) < 1e-19  # -50 e^-50
+    # derivative at 0 is 1/2 (s = 1/2, 1 + 0) and at ln 2: s = 2/3, 2/3 (1 + ln2/3)
+    assert U.silu_grad(np.array([0.0]))[0] == 0.5
+    assert U.silu_grad(np.array([ln2]))[0] == pytest.approx(2.0 / 3.0 * (1.0 + ln2 / 3.0), rel=1e-15)
+
+
+def test_avgpool_and_upsample_hand_values():
+    """2x2 average pooling and nearest upsampling of small arrays worked by hand."""
+    x = np.arange(16.0).reshape(1, 4, 4, 1)  # rows 0..3, 4..7, 8..11, 12..15
+    pooled = U.avgpool2(x)[0, :, :, 0]
+    assert pooled.tolist() == [[2.5, 4.5], [10.5, 12.5]]  # (0+1+4+5)/4, (2+3+6+7)/4, ...
+    # two channels pool independently
+    y = np.stack([x[..., 0], -2.0 * x[..., 0]], axis=-1)
+    assert U.avgpool2(y)[0, :, :, 1].tolist() == [[-5.0, -9.0], [-21.0, -25.0]]
+    up = U.upsample2(np.array([[1.0, 2.0], [3.0, 4.0]]).reshape(1, 2, 2, 1))[0, :, :, 0]
+    assert up.tolist() == [[1, 1, 2, 2], [1, 1, 2, 2], [3, 3, 4, 4], [3, 3, 4, 4]]
+    # pooling undoes upsampling
+    assert np.array_equal(U.avgpool2(U.upsample2(x)), x)
