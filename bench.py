@@ -33,7 +33,9 @@ HBM_PEAK_GBS = 8000.0
 #   P1 reads phi, writes a1; P2 reads phi, v, writes a2; P3 reads phi, v, a1, a2,
 #   writes q; P4 reads phi, v, a2, q, a1, writes phi', v'.
 #   P234 (fused stages 2-4) reads phi, v, a1, writes phi', v'.
-PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "P234": (3, 2)}
+#   VV (velocity Verlet, one pass) reads phi, v, a, writes phi', v', a';
+#   GF (gradient flow, one pass) reads phi, a, writes phi', a'.
+PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "P234": (3, 2), "VV": (3, 3), "GF": (2, 2)}
 STEP_SETS = 17          # separate stage passes
 STEP_SETS_FUSED = 7     # P1 + fused stages 2-4
 PLAN_NAMES = ["stages", "fused"]
@@ -183,13 +185,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def make_solver(wl, autotune_steps=10):
+INTEGRATOR_NAMES = {"rk4": "RK4 arrested Newton flow, dt = 0.5 h",
+                    "vv": "velocity Verlet arrested Newton flow (one pass per step), dt = 0.5 h",
+                    "gf": "gradient flow (one pass per step), tau = dt^2 / 2, dt = 0.5 h"}
+
+
+def make_solver(wl, autotune_steps=10, integrator="rk4"):
     import paper_2603_24370_amd as ss
     from paper_2603_24370_amd import inputs as I
     tune = None
     if wl["theory"] == "abelian_higgs":
         lam = I.gl_lambda_from_kappa(wl["kappa"])
         s = ss.Solver("abelian_higgs", wl["N"], wl["N"], wl["h"], [lam], dtype=wl["dtype"])
+        s.set_integrator(integrator)
         if autotune_steps:
             tune = s.autotune(autotune_steps)
         if wl["nv"] == 1:
@@ -201,6 +209,7 @@ def make_solver(wl, autotune_steps=10):
     else:
         params = [1.0, 1.0, 0.1, 0.6]
         s = ss.Solver("chiral_magnet", wl["N"], wl["N"], wl["h"], params, dtype=wl["dtype"])
+        s.set_integrator(integrator)
         if autotune_steps:
             tune = s.autotune(autotune_steps)
         s.init_skyrmion(R=2.0, gamma=-math.pi / 2, seed=wl["seed"], noise_amp=1e-3)
@@ -220,7 +229,7 @@ def host_cores() -> int:
     return max(1, n)
 
 
-def cpu_baseline(s, wl, params, window=1024, steps=10):
+def cpu_baseline(s, wl, params, window=1024, steps=10, scheme="rk4"):
     """The FP64 oracle as it stands (one thread per call) on windows of the same
     field: first one core on the central window, then every usable host core at
     once, one window per thread (the oracle is a C library called through
@@ -238,7 +247,7 @@ def cpu_baseline(s, wl, params, window=1024, steps=10):
         return np.ascontiguousarray(f[:, a:a + w + 4, b:b + w + 4])
 
     def run(sub):
-        oracle.flow(wl["theory"], sub, np.zeros_like(sub), wl["h"], params, steps)
+        oracle.flow(wl["theory"], sub, np.zeros_like(sub), wl["h"], params, steps, scheme=scheme)
 
     c = (N - w) // 2
     t0 = time.perf_counter()
@@ -253,10 +262,10 @@ def cpu_baseline(s, wl, params, window=1024, steps=10):
         list(ex.map(run, subs))
     dtn = time.perf_counter() - t0
     return {"value": cores * w * w * steps / dtn, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{cores} threads, each {steps} RK4 steps of its own {w}x{w} window of the same field (its "
+            "sample": f"{cores} threads, each {steps} {scheme} steps of its own {w}x{w} window of the same field (its "
                       f"neighbours as a fixed halo), FP64, {dtn:.1f} s wall",
             "value_1core": w * w * steps / dt1,
-            "sample_1core": f"{steps} RK4 steps of the central {w}x{w} window on one core, {dt1:.1f} s"}
+            "sample_1core": f"{steps} {scheme} steps of the central {w}x{w} window on one core, {dt1:.1f} s"}
 
 
 def measured_copy_gbps(nbytes=1 << 30, reps=10):
@@ -300,6 +309,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--autotune-steps", type=int, default=10, help="0 = keep the default tile shape")
+    ap.add_argument("--integrator", default="rk4", choices=sorted(INTEGRATOR_NAMES),
+                    help="rk4 (default), vv (velocity Verlet) or gf (gradient flow)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times), to scale HBM counters")
     args = ap.parse_args()
@@ -329,7 +340,7 @@ def main():
     if args.workload.startswith("unet"):
         run_unet(args, wl)
         return
-    s, params, tune = make_solver(wl, args.autotune_steps)
+    s, params, tune = make_solver(wl, args.autotune_steps, args.integrator)
     N = wl["N"]
     sites = N * N
     C = s.C
@@ -350,7 +361,10 @@ def main():
     # per-pass device time with HIP events on the library's stream
     plan = s.plan
     ms = s.time_passes(args.timing_steps)
-    names = ["P1", "P2", "P3", "P4"] if plan == 0 else ["P1", "P234"]
+    if args.integrator != "rk4":
+        names = [args.integrator.upper()]
+    else:
+        names = ["P1", "P2", "P3", "P4"] if plan == 0 else ["P1", "P234"]
     passes = {}
     for k, name in enumerate(names):
         r, w_ = PASS_SETS[name]
@@ -358,12 +372,16 @@ def main():
         passes[name] = {"ms": ms[k], "GB_per_launch": nbytes / 1e9, "GBps": nbytes / (ms[k] * 1e-3) / 1e9}
     dom = max(passes, key=lambda k: passes[k]["ms"])
     ach = passes[dom]["GBps"]
-    step_sets = STEP_SETS if plan == 0 else STEP_SETS_FUSED
+    if args.integrator != "rk4":
+        step_sets = sum(PASS_SETS[names[0]])
+    else:
+        step_sets = STEP_SETS if plan == 0 else STEP_SETS_FUSED
     step_gbps = step_sets * C * b * sites / (ms_step * 1e-3) / 1e9
     import paper_2603_24370_amd as ss
     tr = traffic_record(dom, args.workload, ss.ss_get_tile(s.ctx))
     tr_gb = tr["total_GB"] if tr else None
-    kname = f"stage_pass {dom}" if dom != "P234" else "stage_pass_fused (stages 2-4)"
+    kname = {"P234": "stage_pass_fused (stages 2-4)", "VV": "stage_pass (velocity Verlet step)",
+             "GF": "stage_pass (gradient-flow step)"}.get(dom, f"stage_pass {dom}")
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr_gb, "traffic_unit": "GB per launch (rocprofv3 "
             "FETCH_SIZE x2 + WRITE_SIZE x1, scaled on a plain copy)", "traffic_over_algorithmic": tr["ratio"] if tr else None,
@@ -378,7 +396,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(s, wl, params)
+        cpu = cpu_baseline(s, wl, params, scheme=args.integrator)
 
     out = {
         "metric": "site-updates/s",
@@ -395,9 +413,10 @@ def main():
         "data": "synthetic (seeded ansatz + noise)",
         "config": {"workload": args.workload, "theory": wl["theory"], "Nx": N, "Ny": N, "h": wl["h"],
                    "kappa": wl.get("kappa"), "vortices": wl.get("nv"), "grad_form": "euler-lagrange",
-                   "integrator": "RK4 arrested Newton flow, dt = 0.5 h", "parallelism": "single GPU"},
+                   "integrator": INTEGRATOR_NAMES[args.integrator], "parallelism": "single GPU"},
         "roofline": roof,
-        "tile": {"chosen": list(ss_tile(tune[0])) if tune else None, "plan": PLAN_NAMES[plan],
+        "tile": {"chosen": list(ss_tile(tune[0])) if tune else None,
+                 "plan": PLAN_NAMES[plan] if args.integrator == "rk4" else "one pass",
                  "step_ms_by_plan_and_tile": {PLAN_NAMES[p]: [round(x, 4) for x in row]
                                               for p, row in enumerate(tune[2])} if tune else None},
         "cpu_baseline": cpu,

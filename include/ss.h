@@ -107,7 +107,7 @@ typedef struct {
   double energy;      /* E_h of the current field (FP64 reduction) */
   double energy_prev; /* E_h compared against by the next arrest test */
   double gnorm_inf;   /* max |G| over interior sites and components */
-  int64_t step;       /* RK4 steps completed since ss_set_field */
+  int64_t step;       /* flow steps completed since ss_set_field */
   int64_t n_arrests;  /* arrests since ss_set_field */
   int32_t arrested;   /* 1 if the last arrest test fired */
   int32_t nonfinite;  /* number of non-finite values seen by the last test */
@@ -326,6 +326,29 @@ int ss_init_learned(ss_ctx* ctx, int n, const double* xy, const double* w, const
 #define SS_NUM_PLANS 2
 int ss_set_plan(ss_ctx* ctx, int plan);
 int ss_get_plan(ss_ctx* ctx);
+
+/* Integrators of the flow (Sec. 3.2: the second-order flow is integrated by an
+ * explicit scheme, RK4 for example, and contrasted with first-order descent).
+ *   SS_INTEG_RK4  classical RK4 on (phi, phidot), launched by the plan above
+ *                 (default);
+ *   SS_INTEG_VV   velocity Verlet, one pass per step that reads phi, v and the
+ *                 stored force a = -G(phi) and writes phi' = phi + dt v + dt^2/2 a,
+ *                 its force a' = -G(phi') and v' = v + dt/2 (a + a') (6 field
+ *                 sets of HBM traffic per site and step), with E_h(phi') reduced
+ *                 in the same pass, so the arrest test of eq. (4) for the next
+ *                 step is ready when that step starts;
+ *   SS_INTEG_GF   gradient flow phi' = phi + tau a with tau = dt^2/2 (the step
+ *                 velocity Verlet takes from rest), one pass reading phi and a,
+ *                 writing phi' and a' (4 field sets); no velocity, no arrest.
+ * dt = C h as for RK4. Every run of a one-pass integrator (ss_flow_step,
+ * ss_minimise) begins with one pass that tests the current field and stores
+ * its force. Chiral magnet: phi' is normalised before its force is taken and
+ * v' is projected on its tangent plane. Batches always use RK4. Synchronises. */
+#define SS_INTEG_RK4 0
+#define SS_INTEG_VV 1
+#define SS_INTEG_GF 2
+int ss_set_integrator(ss_ctx* ctx, int integ);
+int ss_get_integrator(ss_ctx* ctx);
 
 /* Tile shapes of the stage kernels. The library carries ss_tile_count()
  * compiled shapes (a workgroup covers TX x TY sites, each thread RY rows of

@@ -23,6 +23,8 @@ THEORIES = {"abelian_higgs": 0, "chiral_magnet": 1, "toy_harmonic": 2, "toy_offs
 COURANT = 0.5  # dt = C * h with the default C of Sec. 3.1
 GRAD_EXACT = 0  # G = h^-2 dE_h/dphi
 GRAD_EL = 1     # continuum Euler-Lagrange expression evaluated with eq. (1)-(2)
+# integrators of the flow: classical RK4, velocity Verlet, gradient flow
+SCHEMES = {"rk4": 0, "vv": 1, "gf": 2}
 
 
 def build(force: bool = True) -> str:
@@ -57,6 +59,8 @@ def lib():
         L.or_acceleration.argtypes = [i, i, i, i, d, dp, dp, dp]
         L.or_flow.argtypes = [i, i, i, i, d, dp, d, dp, dp, dp, i, ctypes.POINTER(ctypes.c_long)]
         L.or_minimise.argtypes = [i, i, i, i, d, dp, d, dp, dp, d, d, i, ctypes.c_long, dp]
+        L.or_flow_scheme.argtypes = [i, i, i, i, i, d, dp, d, dp, dp, dp, i, ctypes.POINTER(ctypes.c_long)]
+        L.or_minimise_scheme.argtypes = [i, i, i, i, i, d, dp, d, dp, dp, d, d, i, ctypes.c_long, dp]
         L.or_observables_ah.argtypes = [i, i, d, dp, dp, dp]
         L.or_observables_cm.argtypes = [i, i, d, dp, dp, dp]
         _lib = L
@@ -129,28 +133,29 @@ def acceleration(theory, phi, h, params, mode=GRAD_EL) -> np.ndarray:
     return a
 
 
-def flow(theory, phi, v, h, params, n_steps, E_cur=None, courant=COURANT, mode=GRAD_EL):
-    """n_steps of arrested Newton flow. Returns (phi, v, E, n_arrests) (new arrays)."""
+def flow(theory, phi, v, h, params, n_steps, E_cur=None, courant=COURANT, mode=GRAD_EL, scheme="rk4"):
+    """n_steps of the flow (arrested Newton flow by RK4 or velocity Verlet, or gradient
+    flow: scheme "rk4", "vv", "gf"). Returns (phi, v, E, n_arrests) (new arrays)."""
     phi, v, p = _arr(phi).copy(), _arr(v).copy(), _arr(params)
     Nx, Ny = _dims(phi)
     if E_cur is None:
         E_cur = energy(theory, phi, h, params)
     E = ctypes.c_double(E_cur)
     na = ctypes.c_long(0)
-    lib().or_flow(_tid(theory), int(mode), Nx, Ny, h, _p(p), courant, _p(phi), _p(v), ctypes.byref(E), int(n_steps),
-                  ctypes.byref(na))
+    lib().or_flow_scheme(_tid(theory), int(mode), SCHEMES[scheme], Nx, Ny, h, _p(p), courant, _p(phi), _p(v),
+                         ctypes.byref(E), int(n_steps), ctypes.byref(na))
     return phi, v, E.value, na.value
 
 
 def minimise(theory, phi, h, params, grad_tol=1e-6, rel_e_tol=0.0, window=0, max_steps=100000,
-             v=None, courant=COURANT, mode=GRAD_EL):
-    """Arrested Newton flow to a stop criterion. Returns (phi, v, info dict)."""
+             v=None, courant=COURANT, mode=GRAD_EL, scheme="rk4"):
+    """The flow (scheme as in flow) to a stop criterion. Returns (phi, v, info dict)."""
     phi, p = _arr(phi).copy(), _arr(params)
     v = np.zeros_like(phi) if v is None else _arr(v).copy()
     Nx, Ny = _dims(phi)
     info = np.zeros(6)
-    lib().or_minimise(_tid(theory), int(mode), Nx, Ny, h, _p(p), courant, _p(phi), _p(v), grad_tol, rel_e_tol,
-                      int(window), int(max_steps), _p(info))
+    lib().or_minimise_scheme(_tid(theory), int(mode), SCHEMES[scheme], Nx, Ny, h, _p(p), courant, _p(phi), _p(v),
+                             grad_tol, rel_e_tol, int(window), int(max_steps), _p(info))
     return phi, v, {"E": info[0], "gmax": info[1], "steps": int(info[2]), "arrests": int(info[3]),
                     "converged": bool(info[4]), "reason": int(info[5])}
 
@@ -168,4 +173,4 @@ def observables(theory, phi, h, params) -> dict:
 
 
 __all__ = ["build", "lib", "energy", "energy_density", "energy_complex", "gradient", "acceleration",
-           "flow", "minimise", "observables", "deriv_at", "THEORIES", "COURANT", "GRAD_EXACT", "GRAD_EL"]
+           "flow", "minimise", "observables", "deriv_at", "THEORIES", "COURANT", "GRAD_EXACT", "GRAD_EL", "SCHEMES"]

@@ -395,6 +395,48 @@ void rk4_step(int theory, int mode, const Lat& L, const double* p, double dt, do
   }
 }
 
+// The other integrators of the flow (Sec. 3.2 names RK4 as one choice of explicit
+// integrator and contrasts the method with first-order descent):
+//   scheme 1, velocity Verlet (Stoermer-Verlet) of phi'' = a(phi):
+//       phi' = phi + dt v + dt^2/2 a(phi),   v' = v + dt/2 (a(phi) + a(phi'));
+//   scheme 2, gradient flow phi' = -G(phi) by explicit Euler with step tau = dt^2/2,
+//       the step velocity Verlet takes from rest (after an arrest):
+//       phi' = phi + tau a(phi)   (the velocity stays zero).
+// For the chiral magnet the force is the projected one of acceleration(); phi' is
+// renormalised before a(phi') is taken, and v' is projected on the tangent plane
+// at phi', as after an RK4 step.
+enum Scheme { SCHEME_RK4 = 0, SCHEME_VV = 1, SCHEME_GF = 2 };
+
+void one_pass_step(int theory, int mode, int scheme, const Lat& L, const double* p, double dt, double* phi,
+                   double* v) {
+  int C = n_components(theory);
+  long n = (long)C * L.plane();
+  std::vector<double> a0(n), a1(n);
+  acceleration(theory, mode, L, p, phi, a0.data());
+  for (int c = 0; c < C; ++c)
+    for (int j = 0; j < L.Ny; ++j)
+      for (int i = 0; i < L.Nx; ++i) {
+        long k = L.at(c, j, i);
+        if (scheme == SCHEME_VV) phi[k] += dt * v[k] + 0.5 * dt * dt * a0[k];
+        else phi[k] += 0.5 * dt * dt * a0[k];
+      }
+  if (theory == TH_CM) normalise_interior(L, phi);
+  if (scheme != SCHEME_VV) return;
+  acceleration(theory, mode, L, p, phi, a1.data());
+  for (int c = 0; c < C; ++c)
+    for (int j = 0; j < L.Ny; ++j)
+      for (int i = 0; i < L.Nx; ++i) {
+        long k = L.at(c, j, i);
+        v[k] += 0.5 * dt * (a0[k] + a1[k]);
+      }
+  if (theory == TH_CM) tangent_project(L, phi, v);
+}
+
+void step_scheme(int theory, int mode, int scheme, const Lat& L, const double* p, double dt, double* phi, double* v) {
+  if (scheme == SCHEME_RK4) rk4_step(theory, mode, L, p, dt, phi, v);
+  else one_pass_step(theory, mode, scheme, L, p, dt, phi, v);
+}
+
 double wrap_angle(double a) {
   const double pi = 3.14159265358979323846;
   while (a > pi) a -= 2.0 * pi;
@@ -457,19 +499,20 @@ void or_acceleration(int theory, int mode, int Nx, int Ny, double h, const doubl
   acceleration(theory, mode, Lat(Nx, Ny, h), p, phi, a);
 }
 
-// n_steps of arrested Newton flow, eq. (3)-(4). On entry *E_cur = E_h(phi).
-// After every RK4 step: E' = E_h(phi'); if E' > *E_cur the velocity is zeroed
-// (*n_arrests incremented); then *E_cur = E'.
-void or_flow(int theory, int mode, int Nx, int Ny, double h, const double* p, double courant, double* phi,
-             double* v, double* E_cur, int n_steps, long* n_arrests) {
+// n_steps of the flow with the given integrator (0 = RK4, 1 = velocity Verlet,
+// 2 = gradient flow). On entry *E_cur = E_h(phi). After every step: E' = E_h(phi');
+// for the second-order schemes, if E' > *E_cur the velocity is zeroed (*n_arrests
+// incremented; eq. (4)); then *E_cur = E'. Gradient flow has no velocity to arrest.
+void or_flow_scheme(int theory, int mode, int scheme, int Nx, int Ny, double h, const double* p, double courant,
+                    double* phi, double* v, double* E_cur, int n_steps, long* n_arrests) {
   Lat L(Nx, Ny, h);
   int C = n_components(theory);
   long n = (long)C * L.plane();
   double dt = courant * h;
   for (int s = 0; s < n_steps; ++s) {
-    rk4_step(theory, mode, L, p, dt, phi, v);
+    step_scheme(theory, mode, scheme, L, p, dt, phi, v);
     double E = energy(theory, L, p, phi);
-    if (E > *E_cur) {
+    if (scheme != SCHEME_GF && E > *E_cur) {
       for (long k = 0; k < n; ++k) v[k] = 0.0;
       ++*n_arrests;
     }
@@ -477,14 +520,20 @@ void or_flow(int theory, int mode, int Nx, int Ny, double h, const double* p, do
   }
 }
 
-// Minimise by arrested Newton flow from (phi, v). Stops at the first state whose
+// n_steps of arrested Newton flow, eq. (3)-(4), integrated by RK4.
+void or_flow(int theory, int mode, int Nx, int Ny, double h, const double* p, double courant, double* phi,
+             double* v, double* E_cur, int n_steps, long* n_arrests) {
+  or_flow_scheme(theory, mode, SCHEME_RK4, Nx, Ny, h, p, courant, phi, v, E_cur, n_steps, n_arrests);
+}
+
+// Minimise from (phi, v) with the given integrator (as or_flow_scheme). Stops at the first state whose
 // (projected) gradient satisfies max|G| < grad_tol, or whose energy changed by at
 // most rel_e_tol * |E| over the last `window` steps (window > 0), or after
 // max_steps steps. info = {E, gmax, steps, arrests, converged(1/0), reason}
 // with reason 1 = gradient, 2 = energy stall, 0 = max steps.
-void or_minimise(int theory, int mode, int Nx, int Ny, double h, const double* p, double courant,
-                 double* phi, double* v, double grad_tol, double rel_e_tol, int window,
-                 long max_steps, double* info) {
+void or_minimise_scheme(int theory, int mode, int scheme, int Nx, int Ny, double h, const double* p,
+                        double courant, double* phi, double* v, double grad_tol, double rel_e_tol, int window,
+                        long max_steps, double* info) {
   Lat L(Nx, Ny, h);
   int C = n_components(theory);
   long n = (long)C * L.plane();
@@ -503,15 +552,22 @@ void or_minimise(int theory, int mode, int Nx, int Ny, double h, const double* p
     if (window > 0 && step >= window &&
         std::fabs(E - hist[step - window]) <= rel_e_tol * std::fabs(E)) { reason = 2; break; }
     if (step >= max_steps) break;
-    rk4_step(theory, mode, L, p, dt, phi, v);
+    step_scheme(theory, mode, scheme, L, p, dt, phi, v);
     double En = energy(theory, L, p, phi);
-    if (En > E) { for (long k = 0; k < n; ++k) v[k] = 0.0; ++arrests; }
+    if (scheme != SCHEME_GF && En > E) { for (long k = 0; k < n; ++k) v[k] = 0.0; ++arrests; }
     E = En;
   }
   info[2] = (double)step;
   info[3] = (double)arrests;
   info[4] = reason != 0 ? 1.0 : 0.0;
   info[5] = (double)reason;
+}
+
+// Minimise by arrested Newton flow integrated by RK4.
+void or_minimise(int theory, int mode, int Nx, int Ny, double h, const double* p, double courant, double* phi,
+                 double* v, double grad_tol, double rel_e_tol, int window, long max_steps, double* info) {
+  or_minimise_scheme(theory, mode, SCHEME_RK4, Nx, Ny, h, p, courant, phi, v, grad_tol, rel_e_tol, window,
+                     max_steps, info);
 }
 
 // Observables of the Abelian Higgs field.

@@ -22,6 +22,11 @@ void or_flow(int theory, int mode, int Nx, int Ny, double h, const double* p, do
              double* v, double* E_cur, int n_steps, long* n_arrests);
 void or_minimise(int theory, int mode, int Nx, int Ny, double h, const double* p, double courant, double* phi,
                  double* v, double grad_tol, double rel_e_tol, int window, long max_steps, double* info);
+void or_flow_scheme(int theory, int mode, int scheme, int Nx, int Ny, double h, const double* p, double courant,
+                    double* phi, double* v, double* E_cur, int n_steps, long* n_arrests);
+void or_minimise_scheme(int theory, int mode, int scheme, int Nx, int Ny, double h, const double* p,
+                        double courant, double* phi, double* v, double grad_tol, double rel_e_tol, int window,
+                        long max_steps, double* info);
 void or_observables_ah(int Nx, int Ny, double h, const double* p, const double* phi, double* out);
 void or_observables_cm(int Nx, int Ny, double h, const double* p, const double* phi, double* out);
 }
@@ -65,6 +70,14 @@ int check_theory(int theory, const double* p, int Nx, int Ny) {
     std::vector<double> f3 = phi, v3(phi.size(), 0.0);
     or_minimise(theory, mode, Nx, Ny, h, p, 0.5, f3.data(), v3.data(), 0.0, 1e-3, 2, 6, info.data());
     acc += G[G.size() / 2] + a[a.size() / 3] + E + info[0];
+    for (int scheme = 1; scheme < 3; ++scheme) {
+      std::vector<double> f4 = phi, v4(phi.size(), 0.0), f5 = phi, v5(phi.size(), 0.0);
+      double E4 = or_energy(theory, Nx, Ny, h, p, f4.data());
+      or_flow_scheme(theory, mode, scheme, Nx, Ny, h, p, 0.5, f4.data(), v4.data(), &E4, 3, &na);
+      or_minimise_scheme(theory, mode, scheme, Nx, Ny, h, p, 0.5, f5.data(), v5.data(), 0.0, 1e-3, 2, 6,
+                         info.data());
+      acc += E4 + info[0];
+    }
   }
   if (theory == 0) or_observables_ah(Nx, Ny, h, p, phi.data(), out.data());
   if (theory == 1) or_observables_cm(Nx, Ny, h, p, phi.data(), out.data());

@@ -20,6 +20,8 @@ SS_EINVAL, SS_ETHEORY, SS_ESHAPE, SS_EHIP, SS_ENONFINITE, SS_ESTATE = -1, -2, -3
 SS_F32, SS_F64 = 0, 1
 SS_GRAD_EL, SS_GRAD_EXACT = 0, 1
 SS_PLAN_STAGES, SS_PLAN_FUSED = 0, 1
+SS_INTEG_RK4, SS_INTEG_VV, SS_INTEG_GF = 0, 1, 2
+INTEGRATORS = {"rk4": SS_INTEG_RK4, "vv": SS_INTEG_VV, "gf": SS_INTEG_GF}
 SS_NUM_PLANS = 2
 SS_THEORY_AH, SS_THEORY_CM = 0, 1
 SS_ANSATZ_VORTICES, SS_ANSATZ_SKYRMION = 0, 1
@@ -77,7 +79,7 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_batch_destroy", "ss_batch_member", "ss_batch_size", "ss_batch_flow_step", "ss_batch_minimise",
            "ss_batch_set_tile", "ss_batch_autotune", "ss_batch_set_plan", "ss_batch_get_plan", "ss_batch_observables", "ss_set_energy_target", "ss_learned_input",
            "ss_learned_targets", "ss_init_learned", "ss_state_bytes", "ss_get_state", "ss_set_state",
-           "ss_energy_grad_noalloc"]
+           "ss_energy_grad_noalloc", "ss_set_integrator", "ss_get_integrator"]
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
                "ssn_adam_step", "ssn_set_grad_clip",
@@ -130,6 +132,8 @@ def lib():
     L.ss_get_tile.argtypes = [vp]
     L.ss_autotune.argtypes = [vp, i, dp]
     L.ss_set_plan.argtypes = [vp, i]
+    L.ss_set_integrator.argtypes = [vp, i]
+    L.ss_get_integrator.argtypes = [vp]
     L.ss_get_plan.argtypes = [vp]
     ins = ctypes.POINTER(ss_instance)
     L.ss_batch_workspace_bytes.argtypes = [cp, i, ins, i, ctypes.POINTER(ctypes.c_size_t)]
@@ -316,6 +320,14 @@ def ss_get_plan(ctx) -> int:
     return _check_nonneg(lib().ss_get_plan(ctx))
 
 
+def ss_set_integrator(ctx, integ):
+    _check(lib().ss_set_integrator(ctx, INTEGRATORS.get(integ, integ)))
+
+
+def ss_get_integrator(ctx) -> int:
+    return _check_nonneg(lib().ss_get_integrator(ctx))
+
+
 def ss_autotune(ctx, n_steps=10):
     """Returns (tile, plan, ms) with ms[plan][tile] the mean step time (-1: not timed)."""
     nt = ss_tile_count()
@@ -477,6 +489,14 @@ class Solver:
     @property
     def plan(self):
         return ss_get_plan(self.ctx)
+
+    def set_integrator(self, integ):
+        """"rk4" (default), "vv" (velocity Verlet, one pass) or "gf" (gradient flow, one pass)."""
+        ss_set_integrator(self.ctx, integ)
+
+    @property
+    def integrator(self):
+        return ss_get_integrator(self.ctx)
 
     def set_energy_target(self, e_target):
         ss_set_energy_target(self.ctx, e_target)

@@ -139,7 +139,8 @@ struct ss_ctx {
   hipGraphExec_t graph;
   int graph_steps;
   int tile;
-  int plan;  // SS_PLAN_*: how stages 2-4 of a step are launched
+  int plan;   // SS_PLAN_*: how stages 2-4 of a step are launched
+  int integ;  // SS_INTEG_*: the flow's integrator
 };
 
 namespace {
@@ -216,7 +217,7 @@ template <class T, int TH, int PASS, int CFG>
 int launch_cfg(const PassArgs<T>& a, int nlaunch, hipStream_t s) {
   constexpr TileCfg tc = kTiles[CFG];
   PassArgs<T> b = a;
-  if constexpr (PASS == kP1) {
+  if constexpr (PASS == kP1 || PASS == kPrime || PASS == kVV || PASS == kGF) {
     const long r = resident_groups<T, TH, PASS, tc.TX, tc.TY, tc.RY>();
     if (nlaunch > r) {
       nlaunch = (int)r;
@@ -254,7 +255,7 @@ void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   } else {
     groups = launch_pass_t<T, 1, PASS>(c->tile, a, groups, s);
   }
-  if constexpr (PASS == kP1 || PASS == kEval || PASS == kCheck)
+  if constexpr (reduces(PASS))
     hipLaunchKernelGGL((pass_finalise<PASS>), dim3(1), dim3(256), 0, s, a.st, (const double*)a.partials, groups,
                        a.cf.h);
 }
@@ -314,6 +315,14 @@ void launch_fused(const ss_ctx* c, hipStream_t s) {
 template <class T>
 void enqueue_steps(const ss_ctx* c, int n, hipStream_t s) {
   PassArgs<T> a = pass_args<T>(c);
+  if (c->integ != SS_INTEG_RK4) {
+    // one pass (and its finalise) per step
+    for (int k = 0; k < n; ++k) {
+      if (c->integ == SS_INTEG_VV) launch_pass<T, kVV>(c, a, s);
+      else launch_pass<T, kGF>(c, a, s);
+    }
+    return;
+  }
   for (int k = 0; k < n; ++k) {
     launch_pass<T, kP1>(c, a, s);
     if (c->plan != SS_PLAN_STAGES) {
@@ -343,9 +352,30 @@ void enqueue_check_any(const ss_ctx* c, hipStream_t s) {
   else enqueue_check<double>(c, s);
 }
 
+// Start of a run of a one-pass integrator: the arrest test of the current field
+// (as a check pass) and its force stored in the buffer of the step's parity.
+void enqueue_prime_any(const ss_ctx* c, hipStream_t s) {
+  if (c->dtype == SS_F32) launch_pass<float, kPrime>(c, pass_args<float>(c), s);
+  else launch_pass<double, kPrime>(c, pass_args<double>(c), s);
+}
+
+// End of a run of steps: the arrest test of the final field where the
+// integrator has not taken it already, then the velocity zeroed if it fired.
+void enqueue_end_of_run_any(const ss_ctx* c, hipStream_t s);
+
 template <class T>
 void enqueue_apply_arrest(const ss_ctx* c, hipStream_t s) {
   hipLaunchKernelGGL((apply_arrest<T>), dim3(1024), dim3(256), 0, s, bufs_of<T>(c), c->st, c->C);
+}
+
+void enqueue_end_of_run_any(const ss_ctx* c, hipStream_t s) {
+  if (c->integ == SS_INTEG_RK4) {
+    enqueue_check_any(c, s);
+  } else if (c->dtype == SS_F32) {
+    enqueue_apply_arrest<float>(c, s);
+  } else {
+    enqueue_apply_arrest<double>(c, s);
+  }
 }
 
 int read_status(ss_ctx* c, DevStatus* out) {
@@ -518,6 +548,7 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   if (grad_mode == SS_GRAD_EXACT) c->tile = 0;
   set_tiles(c->L, Nx, Ny, c->tile);
   c->plan = (grad_mode == SS_GRAD_EL && dtype == SS_F32) ? kDefaultPlanF32 : SS_PLAN_STAGES;
+  c->integ = SS_INTEG_RK4;
   hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete c;
@@ -597,9 +628,14 @@ int ss_time_passes(ss_ctx* c, int n_steps, double* ms) {
   for (int k = 0; k < 5; ++k) SS_HIP(hipEventCreate(&ev[k]));
   double acc[5] = {0, 0, 0, 0, 0};
   hipLaunchKernelGGL(arm_status, dim3(1), dim3(64), 0, c->stream, c->st, 0, 0.0, 0.0, 0, 0LL);
+  if (c->integ != SS_INTEG_RK4) enqueue_prime_any(c, c->stream);
   for (int s = 0; s < n_steps; ++s) {
     SS_HIP(hipEventRecord(ev[0], c->stream));
-    if (c->plan != SS_PLAN_STAGES) {
+    if (c->integ != SS_INTEG_RK4) {
+      // one pass per step: its time (with its finalise) in ms[0]
+      enqueue_steps_any(c, 1, c->stream);
+      for (int k = 1; k < 5; ++k) SS_HIP(hipEventRecord(ev[k], c->stream));
+    } else if (c->plan != SS_PLAN_STAGES) {
       // stages 2-4 in one pass: its time in ms[1], zero in ms[2] and ms[3]
       if (c->dtype == SS_F32) {
         PassArgs<float> a = pass_args<float>(c);
@@ -636,7 +672,7 @@ int ss_time_passes(ss_ctx* c, int n_steps, double* ms) {
     SS_HIP(hipEventElapsedTime(&t, ev[0], ev[4]));
     acc[4] += t;
   }
-  enqueue_check_any(c, c->stream);
+  enqueue_end_of_run_any(c, c->stream);
   SS_HIP(hipStreamSynchronize(c->stream));
   for (int k = 0; k < 5; ++k) {
     ms[k] = acc[k] / n_steps;
@@ -882,8 +918,9 @@ int ss_flow_step(ss_ctx* c, int n_steps, ss_step_info* info) {
   if (!c) return fail(SS_EINVAL, "ctx is NULL");
   if (n_steps < 0) return fail(SS_EINVAL, "n_steps < 0");
   hipLaunchKernelGGL(arm_status, dim3(1), dim3(64), 0, c->stream, c->st, 0, 0.0, 0.0, 0, 0LL);
+  if (c->integ != SS_INTEG_RK4) enqueue_prime_any(c, c->stream);
   enqueue_steps_any(c, n_steps, c->stream);
-  enqueue_check_any(c, c->stream);
+  enqueue_end_of_run_any(c, c->stream);
   SS_HIP(hipGetLastError());
   if (info) {
     DevStatus d;
@@ -921,6 +958,8 @@ int ss_minimise(ss_ctx* c, const ss_stop* stop, ss_min_info* info) {
   }
   hipLaunchKernelGGL(arm_status, dim3(1), dim3(64), 0, c->stream, c->st, 1, stop->grad_tol, stop->rel_e_tol,
                      stop->window, (long long)stop->max_steps);
+  // a one-pass run starts by testing the current field and storing its force
+  if (c->integ != SS_INTEG_RK4) enqueue_prime_any(c, c->stream);
   SS_HIP(hipGetLastError());
   DevStatus d;
   for (;;) {
@@ -1027,6 +1066,21 @@ int ss_set_plan(ss_ctx* c, int plan) {
 
 int ss_get_plan(ss_ctx* c) { return c ? c->plan : SS_EINVAL; }
 
+int ss_set_integrator(ss_ctx* c, int integ) {
+  if (!c) return fail(SS_EINVAL, "ctx is NULL");
+  if (integ != SS_INTEG_RK4 && integ != SS_INTEG_VV && integ != SS_INTEG_GF)
+    return fail(SS_EINVAL, "unknown integrator");
+  SS_HIP(hipStreamSynchronize(c->stream));
+  c->integ = integ;
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return SS_OK;
+}
+
+int ss_get_integrator(ss_ctx* c) { return c ? c->integ : SS_EINVAL; }
+
 int ss_tile_count(void) { return kNumTiles; }
 
 int ss_tile_shape(int tile, int* tx, int* ty, int* ry) {
@@ -1042,12 +1096,13 @@ int ss_tile_shape(int tile, int* tx, int* ty, int* ry) {
 namespace {
 
 // Autotune cache: a text file (path in SS_AUTOTUNE_CACHE) of lines
-// "theory dtype grad_mode Nx Ny tiles plan tile", one per tuned problem; the
+// "theory dtype grad_mode Nx Ny tiles integrator plan tile", one per tuned problem; the
 // last line for a problem wins. "tiles" is the number of compiled tile shapes,
 // so entries from a library with other shapes are not used.
 std::string tune_key(const ss_ctx* c) {
   char buf[128];
-  std::snprintf(buf, sizeof(buf), "%d %d %d %d %d %d", c->theory, c->dtype, c->grad_mode, c->Nx, c->Ny, kNumTiles);
+  std::snprintf(buf, sizeof(buf), "%d %d %d %d %d %d %d", c->theory, c->dtype, c->grad_mode, c->Nx, c->Ny, kNumTiles,
+                c->integ);
   return buf;
 }
 
@@ -1060,10 +1115,10 @@ bool tune_lookup(const ss_ctx* c, int* plan, int* tile) {
   bool found = false;
   char line[256];
   while (std::fgets(line, sizeof(line), f)) {
-    int th, dt, gm, nx, ny, nt, p, t;
-    if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &th, &dt, &gm, &nx, &ny, &nt, &p, &t) != 8) continue;
+    int th, dt, gm, nx, ny, nt, ig, p, t;
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d", &th, &dt, &gm, &nx, &ny, &nt, &ig, &p, &t) != 9) continue;
     char k[128];
-    std::snprintf(k, sizeof(k), "%d %d %d %d %d %d", th, dt, gm, nx, ny, nt);
+    std::snprintf(k, sizeof(k), "%d %d %d %d %d %d %d", th, dt, gm, nx, ny, nt, ig);
     if (key == k && p >= 0 && p < SS_NUM_PLANS && t >= 0 && t < kNumTiles) {
       *plan = p;
       *tile = t;

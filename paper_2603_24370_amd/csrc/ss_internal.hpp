@@ -67,7 +67,20 @@ enum Pass : int {
   kP4 = 3,     // stage 4: a4 = -G(phi + dt v + dt^2/2 a2); phi', v'
   kEval = 4,   // G and E of a given field; flow state untouched
   kCheck = 5,  // arrest test of the current field only (after a run of steps)
+  // one-pass integrators, which keep the force a = -G of the current field in
+  // one of two force buffers (a1, a2 by step parity):
+  kPrime = 6,  // arrest test of the current field, as kCheck, and its force stored
+  kVV = 7,     // velocity Verlet: phi' = phi + dt v + dt^2/2 a, a' = -G(phi'),
+               //   v' = v + dt/2 (a + a'), E_h(phi'); then the arrest test of phi'
+  kGF = 8,     // gradient flow: phi' = phi + dt^2/2 a, a' = -G(phi'), E_h(phi')
 };
+
+// The pass writes a new field and tests it (its finalise advances the step first).
+constexpr bool advances_first(int pass) { return pass == kVV || pass == kGF; }
+// The pass reduces energy, max |G| and a non-finite count.
+constexpr bool reduces(int pass) {
+  return pass == kP1 || pass == kEval || pass == kCheck || pass == kPrime || pass == kVV || pass == kGF;
+}
 
 // Map a launched workgroup id to a tile so that the workgroups one XCD receives
 // (ids congruent mod 8 go to the same XCD) cover a contiguous range of tiles

@@ -156,6 +156,35 @@ __device__ __forceinline__ InstView<T> view_of(const Bufs<T>& B, const Coeffs& c
   return V;
 }
 
+// Epilogue of the one-pass integrators at one site: the stage point S is the new
+// field phi' (normalised for the chiral magnet). Stores phi', its force
+// a' = -G(phi') and, for velocity Verlet, v' = v + dt/2 (a + a'), with v = 0
+// after an arrest and, for the chiral magnet, v' projected on the tangent plane
+// at phi'. a is the current field's force, read by the pass.
+template <class T, int TH, int PASS>
+__device__ __forceinline__ void one_pass_epilogue(bool arrest, T dt, const T (&v)[4], const T (&a)[4],
+                                                  const T (&S)[4], const T (&G)[4], T* __restrict__ phn,
+                                                  T* __restrict__ vn, T* __restrict__ an, long plane, long off) {
+  constexpr int C = NComp<TH>::value;
+  if (PASS == kVV) {
+    T vnew[4];
+#pragma unroll
+    for (int c = 0; c < C; ++c) vnew[c] = (arrest ? T(0) : v[c]) + (T(0.5) * dt) * (a[c] - G[c]);
+    if (TH == 1) {
+      const T vd = vnew[0] * S[0] + vnew[1] * S[1] + vnew[2] * S[2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vnew[c] -= vd * S[c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) __builtin_nontemporal_store(vnew[c], &vn[c * plane + off]);
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    __builtin_nontemporal_store(S[c], &phn[c * plane + off]);
+    __builtin_nontemporal_store(-G[c], &an[c * plane + off]);
+  }
+}
+
 template <int TH, int TX, int TY>
 struct TileLds {
   static constexpr int C = NComp<TH>::value;
@@ -176,9 +205,11 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
   constexpr int LX = TX + 4, LY = TY + 4;
   constexpr int NT = TX * (TY / RY);
   constexpr int NRING = 4 * LX + 4 * TY;
-  constexpr bool REDUCE = (PASS == kP1 || PASS == kEval || PASS == kCheck);
-  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
-  constexpr bool WITH_A = (PASS == kP3 || PASS == kP4);
+  constexpr bool REDUCE = reduces(PASS);
+  constexpr bool ONEPASS = advances_first(PASS);  // the stage point is the new field
+  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4 || ONEPASS);
+  constexpr bool WITH_V = STAGED && PASS != kGF;
+  constexpr bool WITH_A = (PASS == kP3 || PASS == kP4 || ONEPASS);
   T* s[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) s[c] = lds + c * (LY * LX);
@@ -189,12 +220,17 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
   // (that would place V in private scratch memory)
   const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : (cur ? V.phi[1] : V.phi[0]);
   const T* __restrict__ vv = cur ? V.vel[1] : V.vel[0];
-  const T* __restrict__ aa = (PASS == kP3) ? V.a1 : V.a2;
+  // force buffers: RK4 stages read a1 (P3) or a2 (P4); the one-pass integrators
+  // read the current field's force from the buffer of the step's parity and
+  // write the new field's force to the other one
+  const T* __restrict__ aa = ONEPASS ? (cur ? V.a2 : V.a1) : (PASS == kP3) ? V.a1 : V.a2;
+  T* __restrict__ a_store = (PASS == kP1) ? V.a1 : (PASS == kPrime) ? (cur ? V.a2 : V.a1) : (cur ? V.a1 : V.a2);
   const T dt = (T)V.dt;
   T cv = T(0), ca = T(0);
   if (PASS == kP2) cv = T(0.5) * dt;
   if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
-  if (PASS == kP4) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (PASS == kP4 || PASS == kVV) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (PASS == kGF) ca = T(0.5) * dt * dt;
   if (arrest) cv = T(0);
   const double h = V.h;
   const T c1 = T(1.0 / (12.0 * h)), c2 = T(1.0 / (12.0 * h * h));
@@ -218,7 +254,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
       raw_p[c] = ph[c * plane + off];
       T x = raw_p[c];
       if (STAGED) {
-        raw_v[c] = vv[c * plane + off];
+        if (WITH_V) raw_v[c] = vv[c * plane + off];
         x += cv * raw_v[c];
         if (WITH_A) {
           raw_a[c] = aa[c * plane + off];
@@ -235,14 +271,14 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
     }
   };
 
-  // ---- own sites: raw inputs kept in registers, stage point to LDS
-  T rp[RY][4], rv[RY][4], ra[RY][4];
+  // ---- own sites: raw inputs kept in registers, stage point to LDS (and, for
+  // the one-pass integrators, in registers: it is the new field that is stored)
+  T rp[RY][4], rv[RY][4], ra[RY][4], so[RY][4];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    T S[4];
-    stage_at(gi, y0 + ly0 - 2 + r, rp[r], rv[r], ra[r], S);
+    stage_at(gi, y0 + ly0 - 2 + r, rp[r], rv[r], ra[r], so[r]);
 #pragma unroll
-    for (int c = 0; c < C; ++c) s[c][(ly0 + r) * LX + lx] = S[c];
+    for (int c = 0; c < C; ++c) s[c][(ly0 + r) * LX + lx] = so[r][c];
   }
   // ---- halo ring of the tile
   for (int idx = tid; idx < NRING; idx += NT) {
@@ -355,9 +391,11 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
         if (!isfinite(G[c])) ++nf;
       }
     }
-    if (PASS == kP1) {
+    if (PASS == kP1 || PASS == kPrime) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) __builtin_nontemporal_store(-G[c], &V.a1[c * plane + off]);
+      for (int c = 0; c < C; ++c) __builtin_nontemporal_store(-G[c], &a_store[c * plane + off]);
+    } else if (ONEPASS) {
+      one_pass_epilogue<T, TH, PASS>(arrest, dt, rv[r], ra[r], so[r], G, phn, vn, a_store, plane, off);
     } else if (PASS == kEval) {
       if (out != nullptr) {
         const long o = (long)(gj + 2) * out_pitch + (gi + 2);
@@ -461,9 +499,11 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   constexpr int NRING = 8 * LX + 8 * TY;
   constexpr int FXW = TX + 4, NXF = TY * FXW, NYF = (TY + 4) * TX;
   constexpr int KX = (NXF + NT - 1) / NT, KY = (NYF + NT - 1) / NT;
-  constexpr bool REDUCE = (PASS == kP1 || PASS == kEval || PASS == kCheck);
-  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
-  constexpr bool WITH_A = (PASS == kP3 || PASS == kP4);
+  constexpr bool REDUCE = reduces(PASS);
+  constexpr bool ONEPASS = advances_first(PASS);  // the stage point is the new field
+  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4 || ONEPASS);
+  constexpr bool WITH_V = STAGED && PASS != kGF;
+  constexpr bool WITH_A = (PASS == kP3 || PASS == kP4 || ONEPASS);
   T* s[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) s[c] = lds + (c < C ? c : 0) * (LY * LX);
@@ -474,12 +514,17 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   const long pitch = V.pitch, plane = V.plane;
   const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : (cur ? V.phi[1] : V.phi[0]);
   const T* __restrict__ vv = cur ? V.vel[1] : V.vel[0];
-  const T* __restrict__ aa = (PASS == kP3) ? V.a1 : V.a2;
+  // force buffers: RK4 stages read a1 (P3) or a2 (P4); the one-pass integrators
+  // read the current field's force from the buffer of the step's parity and
+  // write the new field's force to the other one
+  const T* __restrict__ aa = ONEPASS ? (cur ? V.a2 : V.a1) : (PASS == kP3) ? V.a1 : V.a2;
+  T* __restrict__ a_store = (PASS == kP1) ? V.a1 : (PASS == kPrime) ? (cur ? V.a2 : V.a1) : (cur ? V.a1 : V.a2);
   const T dt = (T)V.dt;
   T cv = T(0), ca = T(0);
   if (PASS == kP2) cv = T(0.5) * dt;
   if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
-  if (PASS == kP4) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (PASS == kP4 || PASS == kVV) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (PASS == kGF) ca = T(0.5) * dt * dt;
   if (arrest) cv = T(0);
   const double h = V.h;
   const T c1 = T(1.0 / (12.0 * h));
@@ -497,7 +542,7 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
       raw_p[c] = ph[c * plane + off];
       T x = raw_p[c];
       if (STAGED) {
-        raw_v[c] = vv[c * plane + off];
+        if (WITH_V) raw_v[c] = vv[c * plane + off];
         x += cv * raw_v[c];
         if (WITH_A) {
           raw_a[c] = aa[c * plane + off];
@@ -514,15 +559,14 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
     }
   };
 
-  // ---- stage: own sites (raw inputs kept), then the halo-4 frame
-  T rp[RY][4], rv[RY][4], ra[RY][4];
+  // ---- stage: own sites (raw inputs and stage point kept), then the halo-4 frame
+  T rp[RY][4], rv[RY][4], ra[RY][4], so[RY][4];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    T S[4];
     const int ly = 4 + threadIdx.y * RY + r;
-    stage_at(gi, y0 + ly - 4, rp[r], rv[r], ra[r], S);
+    stage_at(gi, y0 + ly - 4, rp[r], rv[r], ra[r], so[r]);
 #pragma unroll
-    for (int c = 0; c < C; ++c) s[c][ly * LX + 4 + threadIdx.x] = S[c];
+    for (int c = 0; c < C; ++c) s[c][ly * LX + 4 + threadIdx.x] = so[r][c];
   }
   for (int idx = tid; idx < NRING; idx += NT) {
     int ly, lx;
@@ -690,9 +734,11 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
         if (!isfinite(G[c])) ++nf;
       }
     }
-    if (PASS == kP1) {
+    if (PASS == kP1 || PASS == kPrime) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) __builtin_nontemporal_store(-G[c], &V.a1[c * plane + off]);
+      for (int c = 0; c < C; ++c) __builtin_nontemporal_store(-G[c], &a_store[c * plane + off]);
+    } else if (ONEPASS) {
+      one_pass_epilogue<T, TH, PASS>(arrest, dt, rv[r], ra[r], so[r], G, phn, vn, a_store, plane, off);
     } else if (PASS == kEval) {
       if (out != nullptr) {
         const long o = (long)(gj + 2) * out_pitch + (gi + 2);
@@ -749,14 +795,18 @@ __device__ __forceinline__ void finalise_status(DevStatus* st, double E, double 
     st->nonfinite = nfin;
     return;
   }
-  const int arr = (E > st->E_prev) ? 1 : 0;
+  // a one-pass step has written the new field: it becomes the current one, and
+  // the tests below are those of the new field
+  long long s0 = st->step;
+  if (advances_first(PASS)) st->step = ++s0;
+  // gradient flow has no velocity, hence no arrest
+  const int arr = (PASS != kGF && E > st->E_prev) ? 1 : 0;
   st->arrest = arr;
   if (arr) st->n_arrests += 1;
   st->E_prev = E;
   st->E = E;
   st->gmax = gmax;
   st->nonfinite = nfin;
-  const long long s0 = st->step;
   st->hist[s0 % kHistLen] = E;
   int done = 0;
   if (nfin > 0) {
@@ -780,16 +830,19 @@ __global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
   constexpr int C = NComp<TH>::value;
   constexpr int LX = TX + 4, LY = TY + 4;
   constexpr int NT = TX * (TY / RY);
-  constexpr bool REDUCE = (PASS == kP1 || PASS == kEval || PASS == kCheck);
-  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  constexpr bool REDUCE = reduces(PASS);
+  // stages 2-4 of RK4 run after P1 advanced the step counter; the one-pass
+  // integrators read the current field and advance it in their finalise
+  constexpr bool AFTER_P1 = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  constexpr bool USES_ARREST = AFTER_P1 || PASS == kVV;
   __shared__ __align__(16) T lds[C * LY * LX];
   __shared__ double red[3 * (NT / 64)];
 
   DevStatus* __restrict__ st = a.st;
   if (PASS != kEval && st->done) return;
   const long long step = st->step;
-  const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
-  const bool arrest = STAGED ? (st->arrest != 0) : false;
+  const int cur = AFTER_P1 ? int((step - 1) & 1) : int(step & 1);
+  const bool arrest = USES_ARREST ? (st->arrest != 0) : false;
   const InstView<T> V = view_of<T>(a.B, a.cf);
 
   double e_acc = 0.0, g_acc = 0.0;
@@ -1157,16 +1210,17 @@ __global__ void __launch_bounds__(256) stage_pass_exact(PassArgs<T> a) {
   constexpr int NFL = 3 * (kExTY * (kExTX + 4) + (kExTY + 4) * kExTX);
   constexpr int NLDS = C * LY * LX > NFL ? C * LY * LX : NFL;
   constexpr int NT = 256;
-  constexpr bool REDUCE = (PASS == kP1 || PASS == kEval || PASS == kCheck);
-  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  constexpr bool REDUCE = reduces(PASS);
+  constexpr bool AFTER_P1 = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  constexpr bool USES_ARREST = AFTER_P1 || PASS == kVV;
   __shared__ __align__(16) T lds[NLDS];
   __shared__ double red[3 * (NT / 64)];
 
   DevStatus* __restrict__ st = a.st;
   if (PASS != kEval && st->done) return;
   const long long step = st->step;
-  const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
-  const bool arrest = STAGED ? (st->arrest != 0) : false;
+  const int cur = AFTER_P1 ? int((step - 1) & 1) : int(step & 1);
+  const bool arrest = USES_ARREST ? (st->arrest != 0) : false;
   const InstView<T> V = view_of<T>(a.B, a.cf);
   double e_acc = 0.0, g_acc = 0.0;
   int nf = 0;

@@ -1,0 +1,196 @@
+"""The one-pass integrators (velocity Verlet arrested Newton flow, gradient flow)
+through the C ABI against the FP64 oracle's flows of the same scheme.
+
+Tolerances as for the RK4 plans: FP64 fields to 1e-11 relative (rounding order
+only), FP32 fields to 1e-5 relative (the FP32 tolerance of the flow), energies
+of the device's own field to 1e-12 against the oracle, arrests and steps exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2603_24370_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+AH, CM = "abelian_higgs", "chiral_magnet"
+P_CM = [1.0, 1.0, 0.1, 0.6]
+
+
+@pytest.fixture(scope="module")
+def ss():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2603_24370_amd as m
+    m.lib()
+    return m
+
+
+def _params(theory):
+    return [1.0] if theory == AH else P_CM
+
+
+def _field(theory, Nx, Ny, h, seed):
+    if theory == AH:
+        cen = I.uniform_centres(seed, 3, 0.3 * min(Nx, Ny) * h)
+        return I.ah_vortex_ansatz(Nx, Ny, h, cen) + I.noise(seed, 4, Nx, Ny, 1e-3)
+    f = I.cm_skyrmion_ansatz(Nx, Ny, h, R=min(Nx, Ny) * h / 8)
+    return I.renormalise_interior(f + I.noise(seed, 3, Nx, Ny, 1e-3))
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+SHAPES = [(150, 37), (64, 16), (129, 70)]
+
+
+@pytest.mark.parametrize("integ", ["vv", "gf"])
+@pytest.mark.parametrize("theory", [AH, CM])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_one_pass_flow_tracks_the_oracle(ss, orc, integ, theory, dtype, shape):
+    Nx, Ny = shape
+    h = 0.17
+    print(f"[case] one-pass {integ} {theory} {dtype} {shape}", flush=True)
+    f = _field(theory, Nx, Ny, h, seed=Nx + 5 * Ny)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    s = ss.Solver(theory, Nx, Ny, h, _params(theory), dtype=dtype)
+    s.set_integrator(integ)
+    assert s.integrator == ss.INTEGRATORS[integ]
+    s.set_field(f)
+    n = 6
+    info = s.flow_step(n)
+    phi, vel = s.get_field(velocity=True)
+    phi, vel = _np(phi), _np(vel)
+    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), n, scheme=integ)
+    rel = 1e-11 if dtype == "f64" else 1e-5
+    assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max()
+    assert np.abs(vel - v_r).max() <= rel * max(np.abs(phi_r).max(), 1.0)
+    if integ == "gf":
+        assert not vel.any() and na_r == 0
+    assert info["step"] == n and info["n_arrests"] == na_r
+    assert info["energy"] == pytest.approx(orc.energy(theory, phi, h, _params(theory)), rel=1e-12, abs=1e-12)
+    if dtype == "f64":
+        assert info["energy"] == pytest.approx(E_r, rel=1e-12)
+    # max |G| reported is that of the final field
+    a_ref = orc.acceleration(theory, phi, h, _params(theory))
+    assert info["gnorm_inf"] == pytest.approx(np.abs(a_ref).max(), rel=1e-9 if dtype == "f64" else 1e-3)
+    assert np.array_equal(phi[:, :2, :], f[:, :2, :]) and np.array_equal(phi[:, :, -2:], f[:, :, -2:])
+    s.close()
+
+
+@pytest.mark.parametrize("integ", ["vv", "gf"])
+@pytest.mark.parametrize("theory", [AH, CM])
+def test_one_pass_exact_gradient_tracks_the_oracle(ss, orc, integ, theory):
+    """The one-pass passes also run with the exact gradient h^-2 dE_h/dphi."""
+    Nx, Ny, h = 70, 45, 0.2
+    print(f"[case] one-pass exact {integ} {theory}", flush=True)
+    f = _field(theory, Nx, Ny, h, seed=11)
+    s = ss.Solver(theory, Nx, Ny, h, _params(theory), dtype="f64", grad_mode=ss.SS_GRAD_EXACT)
+    s.set_integrator(integ)
+    s.set_field(f)
+    info = s.flow_step(5)
+    phi, vel = (_np(x) for x in s.get_field(velocity=True))
+    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), 5, scheme=integ,
+                                     mode=orc.GRAD_EXACT)
+    assert np.abs(phi - phi_r).max() <= 1e-11 * np.abs(phi_r).max()
+    assert np.abs(vel - v_r).max() <= 1e-11 * max(np.abs(phi_r).max(), 1.0)
+    assert info["n_arrests"] == na_r and info["energy"] == pytest.approx(E_r, rel=1e-12)
+    s.close()
+
+
+def test_runs_compose_and_switch_integrators(ss, orc):
+    """Each run starts with a pass that tests the current field and stores its
+    force, so 3 + 4 steps equal 7 steps bit for bit, and a run of RK4 followed by
+    velocity Verlet equals the oracle's RK4 then velocity Verlet."""
+    Nx, Ny, h = 96, 40, 0.2
+    f = _field(AH, Nx, Ny, h, seed=3)
+    a = ss.Solver(AH, Nx, Ny, h, [1.0], dtype="f64")
+    b = ss.Solver(AH, Nx, Ny, h, [1.0], dtype="f64")
+    for s in (a, b):
+        s.set_integrator("vv")
+        s.set_field(f)
+    a.flow_step(3)
+    ia = a.flow_step(4)
+    ib = b.flow_step(7)
+    assert np.array_equal(_np(a.get_field()), _np(b.get_field()))
+    assert ia["energy"] == ib["energy"] and ia["n_arrests"] == ib["n_arrests"] and ia["step"] == 7
+    a.set_integrator("rk4")
+    a.set_field(f)
+    a.flow_step(3)
+    a.set_integrator("vv")
+    info = a.flow_step(4)
+    p1, v1, E1, n1 = orc.flow(AH, f, np.zeros_like(f), h, [1.0], 3)
+    p2, v2, E2, n2 = orc.flow(AH, p1, v1, h, [1.0], 4, E_cur=E1, scheme="vv")
+    assert np.abs(_np(a.get_field()) - p2).max() <= 1e-11 * np.abs(p2).max()
+    assert info["n_arrests"] == n1 + n2 and info["step"] == 7
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("integ", ["vv", "gf"])
+def test_one_pass_arrests_and_stops_like_the_oracle(ss, orc, integ):
+    """A long FP64 run: arrests fire at the oracle's steps, and the stall and
+    gradient stop rules end the run at the oracle's step."""
+    Nx, Ny, h = 48, 40, 0.25
+    f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.3, -0.2), (-1.1, 0.9)]) + I.noise(5, 4, Nx, Ny, 1e-3)
+    s = ss.Solver(AH, Nx, Ny, h, [1.0], dtype="f64")
+    s.set_integrator(integ)
+    s.set_field(f)
+    phi_r, v_r, E, total = f, np.zeros_like(f), None, 0
+    for _ in range(4):
+        info = s.flow_step(50)
+        phi_r, v_r, E, na = orc.flow(AH, phi_r, v_r, h, [1.0], 50, E_cur=E, scheme=integ)
+        total += na
+        assert info["n_arrests"] == total
+    assert np.abs(_np(s.get_field()) - phi_r).max() <= 1e-10 * np.abs(phi_r).max()
+    if integ == "vv":
+        assert total > 0
+    s.set_field(f)
+    res = s.minimise(grad_tol=0.0, rel_e_tol=1e-4, window=20, max_steps=5000, graph_steps=8)
+    _, _, ref = orc.minimise(AH, f, h, [1.0], grad_tol=0.0, rel_e_tol=1e-4, window=20, max_steps=5000,
+                             scheme=integ)
+    assert res["reason"] == "stall" and ref["reason"] == 2
+    assert res["step"] == ref["steps"] and res["n_arrests"] == ref["arrests"]
+    assert res["energy"] == pytest.approx(ref["E"], rel=1e-12)
+    s.set_field(f)
+    res = s.minimise(grad_tol=2e-2, max_steps=5000, graph_steps=8)
+    _, _, ref = orc.minimise(AH, f, h, [1.0], grad_tol=2e-2, max_steps=5000, scheme=integ)
+    assert res["reason"] == "grad" and ref["reason"] == 1 and res["step"] == ref["steps"]
+    s.set_field(f)
+    res = s.minimise(grad_tol=0.0, max_steps=37, graph_steps=8)
+    assert res["reason"] == "max_steps" and res["step"] == 37
+    s.close()
+
+
+@pytest.mark.parametrize("integ", ["vv", "gf"])
+def test_large_lattice_one_pass_step_sampled_parity(ss, orc, integ):
+    """One step of the 4096^2 GL workload with a one-pass integrator, as the
+    benchmark times it, on sampled windows: the oracle steps a window whose outer
+    ring of M >= 4 sites (two radius-2 stencils per step) is held fixed."""
+    N, h, M, S = 4096, 0.2, 6, 64
+    print(f"[case] gl4096 one-pass {integ}", flush=True)
+    inst = I.gl_large_instance(N, h)
+    lam = I.gl_lambda_from_kappa(1.5)
+    s = ss.Solver(AH, N, N, h, [lam], dtype="f32")
+    s.set_integrator(integ)
+    s.init_vortices(inst.centres, seed=4, noise_amp=1e-3)
+    f0 = s.get_field().double().cpu().numpy()
+    info = s.flow_step(1)
+    assert info["step"] == 1 and info["nonfinite"] == 0
+    f1, v1 = (x.double().cpu().numpy() for x in s.get_field(velocity=True))
+    rng = np.random.default_rng(2)
+    origins = [tuple(rng.integers(M, N - S - M, size=2)) for _ in range(5)] + [(0, 0), (N - S, N - S)]
+    for j0, i0 in origins:
+        ja, jb = max(j0 - M, 0), min(j0 + S + M, N)
+        ia, ib = max(i0 - M, 0), min(i0 + S + M, N)
+        win = np.ascontiguousarray(f0[:, ja:jb + 4, ia:ib + 4])
+        w1, wv, _, _ = orc.flow(AH, win, np.zeros_like(win), h, [lam], 1, scheme=integ)
+        sl = (slice(None), slice(j0 - ja + 2, j0 - ja + S + 2), slice(i0 - ia + 2, i0 - ia + S + 2))
+        got = (slice(None), slice(j0 + 2, j0 + S + 2), slice(i0 + 2, i0 + S + 2))
+        assert np.abs(f1[got] - w1[sl]).max() <= 1e-5 * max(np.abs(w1[sl]).max(), 1.0), (j0, i0)
+        assert np.abs(v1[got] - wv[sl]).max() <= 1e-5 * max(np.abs(w1[sl]).max(), 1.0), (j0, i0)
+    s.close()

@@ -415,6 +415,88 @@ def test_stall_rule_stops_where_the_closed_form_predicts(orc, W, tol, steps):
     assert info["reason"] == 2 and info["steps"] == s_ref and info["arrests"] == arrests_ref
 
 
+def _one_pass_matrix(scheme, w, dt):
+    """Closed-form map of (x, v) for one step of x'' = -w^2 x, with s = (w dt)^2:
+    velocity Verlet x' = (1 - s/2) x + dt v, v' = v - dt w^2 (x + x') / 2;
+    gradient flow x' = (1 - s/2) x with v kept at zero (velocity Verlet from rest)."""
+    s = (w * dt) ** 2
+    if scheme == "vv":
+        return np.array([[1.0 - s / 2, dt], [-0.5 * w * w * dt * (2.0 - s / 2), 1.0 - s / 2]])
+    return np.array([[1.0 - s / 2, 0.0], [0.0, 0.0]])
+
+
+@pytest.mark.parametrize("scheme", ["vv", "gf"])
+def test_one_pass_step_matches_closed_form(orc, scheme):
+    m2, h, C = 2.3, 0.4, 0.5
+    w, dt = math.sqrt(m2), C * h
+    rng = np.random.default_rng(5)
+    phi = _rand_field(rng, 1, 6, 3)
+    v = _rand_field(rng, 1, 6, 3) if scheme == "vv" else np.zeros_like(phi)
+    v[:, :2, :] = v[:, -2:, :] = 0
+    v[:, :, :2] = v[:, :, -2:] = 0
+    p1, v1, _, na = orc.flow("toy_harmonic", phi, v, h, [m2], 1, E_cur=1e300, scheme=scheme)
+    M = _one_pass_matrix(scheme, w, dt)
+    sl = (0, slice(2, -2), slice(2, -2))
+    assert na == 0
+    assert np.abs(p1[sl] - (M[0, 0] * phi[sl] + M[0, 1] * v[sl])).max() < 1e-14
+    assert np.abs(v1[sl] - (M[1, 0] * phi[sl] + M[1, 1] * v[sl])).max() < 1e-14
+    assert np.array_equal(p1[:, :2], phi[:, :2])
+    if scheme == "vv":  # symplectic: the one-step map preserves area
+        assert np.linalg.det(M) == pytest.approx(1.0, abs=1e-15)
+
+
+def test_velocity_verlet_arrest_on_the_new_energy(orc):
+    """eq. (4) with the velocity Verlet step: after each step the energy of the
+    new field is compared with the old one; on a rise v is zeroed, phi kept."""
+    m2, h, C = 1.0, 0.5, 0.5
+    w, dt = 1.0, C * h
+    M = _one_pass_matrix("vv", w, dt)
+    phi = np.zeros((1, 5, 5))
+    phi[0, 2, 2] = 1.0
+    v = np.zeros_like(phi)
+    E = orc.energy("toy_harmonic", phi, h, [m2])
+    y = np.array([1.0, 0.0])
+    E_ref = 0.5 * m2 * h * h
+    arrests = 0
+    for _ in range(30):
+        phi, v, E, na = orc.flow("toy_harmonic", phi, v, h, [m2], 1, E_cur=E, scheme="vv")
+        y = M @ y
+        E_new = 0.5 * m2 * h * h * y[0] ** 2
+        if E_new > E_ref:
+            y[1] = 0.0
+            arrests += 1
+            assert na == 1 and v[0, 2, 2] == 0.0
+        else:
+            assert na == 0
+        E_ref = E_new
+        assert phi[0, 2, 2] == pytest.approx(y[0], abs=1e-14)
+        assert v[0, 2, 2] == pytest.approx(y[1], abs=1e-14)
+    assert arrests >= 1
+
+
+@pytest.mark.parametrize("scheme,W,tol", [("vv", 5, 1e-3), ("vv", 20, 1e-6), ("gf", 5, 1e-3), ("gf", 10, 1e-5)])
+def test_one_pass_stall_stop_from_closed_form(orc, scheme, W, tol):
+    """The stall rule under the one-pass integrators, predicted from the closed-form
+    step map on the toy with an energy floor (as for RK4 above)."""
+    m2, h, C, e0, x0 = 1.0, 0.5, 0.5, 0.02, 1.0
+    M = _one_pass_matrix(scheme, math.sqrt(m2), C * h)
+    y, E, hist, arrests = np.array([x0, 0.0]), h * h * (0.5 * m2 * x0 ** 2 + e0), [], 0
+    for s_ref in range(100000):
+        hist.append(E)
+        if s_ref >= W and abs(E - hist[s_ref - W]) <= tol * abs(E):
+            break
+        y = M @ y
+        E_new = h * h * (0.5 * m2 * y[0] ** 2 + e0)
+        if scheme == "vv" and E_new > E:
+            y[1], arrests = 0.0, arrests + 1
+        E = E_new
+    phi = np.zeros((1, 5, 5))
+    phi[0, 2, 2] = x0
+    _, _, info = orc.minimise("toy_offset", phi, h, [m2, e0], grad_tol=0.0, rel_e_tol=tol, window=W,
+                              max_steps=100000, scheme=scheme)
+    assert info["reason"] == 2 and info["steps"] == s_ref and info["arrests"] == arrests
+
+
 def test_cm_force_is_tangent_and_ignores_stage_point_length(orc):
     """The chiral magnet's stage force (Sec. 3.2 projection in every stage) is taken at
     the normalised stage point and projected on its tangent plane: it is orthogonal
