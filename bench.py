@@ -143,6 +143,56 @@ def run_batch(args, wl):
     B.close()
 
 
+CONVERGE_CASES = [
+    # (name, theory, N, h, params, grad_mode, integrator, courant, grad_tol)
+    ("ah128 EL", "abelian_higgs", 128, 0.1, [1.0], 0, "rk4", 0.5, 1e-6),
+    ("ah128 EL", "abelian_higgs", 128, 0.1, [1.0], 0, "vv", 0.5, 1e-6),
+    ("ah128 EL", "abelian_higgs", 128, 0.1, [1.0], 0, "gf", 0.5, 1e-6),
+    ("ah128 EL", "abelian_higgs", 128, 0.1, [1.0], 0, "gf", 0.6, 1e-6),
+    ("cm128 EL", "chiral_magnet", 128, 0.1, [1.0, 1.0, 0.1, 0.6], 0, "rk4", 0.5, 1e-6),
+    ("cm128 EL", "chiral_magnet", 128, 0.1, [1.0, 1.0, 0.1, 0.6], 0, "vv", 0.5, 1e-6),
+    ("cm128 EL", "chiral_magnet", 128, 0.1, [1.0, 1.0, 0.1, 0.6], 0, "gf", 0.5, 1e-6),
+    ("cm128 exact", "chiral_magnet", 128, 0.1, [1.0, 1.0, 0.1, 0.6], 1, "rk4", 0.5, 1e-6),
+    ("cm128 exact", "chiral_magnet", 128, 0.1, [1.0, 1.0, 0.1, 0.6], 1, "vv", 0.5, 1e-6),
+    ("cm128 exact", "chiral_magnet", 128, 0.1, [1.0, 1.0, 0.1, 0.6], 1, "gf", 0.5, 1e-6),
+]
+
+
+def run_converge(args):
+    """Flow steps and wall time to ||G||_inf < tol (FP64) for each integrator:
+    the critical vortex of 128^2 at h = 0.1 (one vortex at the origin, seeded noise
+    1e-3, seed 1) and a Belavin-Polyakov skyrmion of radius 2 on 128^2 at h = 0.1
+    (seed 2) with both gradient forms. Tests whether the arrested second-order flow
+    beats first-order descent (gradient flow with tau = (C h)^2 / 2)."""
+    import torch
+    import paper_2603_24370_amd as ss
+    rows = []
+    for name, theory, N, h, params, gm, integ, C, tol in CONVERGE_CASES:
+        s = ss.Solver(theory, N, N, h, params, dtype="f64", grad_mode=gm, courant=C)
+        s.set_integrator(integ)
+        if theory == "abelian_higgs":
+            s.init_vortices([(0.0, 0.0)], seed=1, noise_amp=1e-3)
+        else:
+            s.init_skyrmion(R=2.0, gamma=-math.pi / 2, seed=2, noise_amp=1e-3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = s.minimise(grad_tol=tol, max_steps=args.converge_max_steps, graph_steps=64)
+        el = time.perf_counter() - t0
+        obs = s.observables()
+        rows.append({"case": name, "integrator": integ, "courant": C, "steps": res["step"],
+                     "arrests": res["n_arrests"], "reason": res["reason"], "gnorm_inf": res["gnorm_inf"],
+                     "energy": res["energy"], "wall_s": round(el, 3),
+                     "q": obs["n_wind"] if theory == "abelian_higgs" else obs["q_bl"]})
+        print(json.dumps(rows[-1]), flush=True)
+        s.close()
+    out = {"metric": "flow steps and wall time to ||G||_inf < 1e-6", "value": None, "unit": "s", "n_gpus": 1,
+           "steps": None, "warmup": 0, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic (seeded ansatz + noise)",
+           "config": {"workload": "converge", "max_steps": args.converge_max_steps}, "results": rows,
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def ss_tile(i):
     import paper_2603_24370_amd as ss
     return ss.ss_tile_shape(i)
@@ -305,10 +355,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="gl4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="gl4096", choices=sorted(WORKLOADS) + ["converge"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--autotune-steps", type=int, default=10, help="0 = keep the default tile shape")
+    ap.add_argument("--converge-max-steps", type=int, default=400000)
     ap.add_argument("--integrator", default="rk4", choices=sorted(INTEGRATOR_NAMES),
                     help="rk4 (default), vv (velocity Verlet) or gf (gradient flow)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -333,6 +384,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "converge":
+        run_converge(args)
+        return
     wl = WORKLOADS[args.workload]
     if args.workload.startswith("batch"):
         run_batch(args, wl)
