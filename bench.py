@@ -4,9 +4,13 @@ Workload (default): the large Ginzburg-Landau lattice, 4096 x 4096 interior
 sites, kappa = 1.5 (lambda = 2 kappa^2 = 4.5), h = 0.2, 256 unit vortices at
 seeded Poisson-disc positions (minimum separation 3) inside the centred square
 of side 0.6 L, U(+-1e-3) noise, FP32 fields with FP64 reductions. A "step" is
-one full RK4 flow step: the first stage pass (gradient, FP64 energy, arrest
-test, stop rules) and either one fused pass for stages 2-4 and the update or
-three separate stage passes, whichever plan the autotuner picks.
+one full step of arrested Newton flow. By default it is integrated by velocity
+Verlet in one pass per step (read phi, v and the stored force, write the new
+ones, reduce the new field's FP64 energy for the arrest test of eq. (4)); with
+--integrator rk4 it is one classical RK4 step (the first stage pass with the
+energy and arrest test, then one fused pass for stages 2-4 or three separate
+stage passes, whichever plan the autotuner picks); --integrator gf times plain
+gradient flow.
 
 Prints one JSON line: site-updates/s over K timed steps (inputs resident in
 HBM), the roofline of the dominant pass (algorithmic bytes per launch over its
@@ -360,8 +364,9 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--autotune-steps", type=int, default=10, help="0 = keep the default tile shape")
     ap.add_argument("--converge-max-steps", type=int, default=400000)
-    ap.add_argument("--integrator", default="rk4", choices=sorted(INTEGRATOR_NAMES),
-                    help="rk4 (default), vv (velocity Verlet) or gf (gradient flow)")
+    ap.add_argument("--integrator", default="vv", choices=sorted(INTEGRATOR_NAMES),
+                    help="vv (velocity Verlet arrested Newton flow, default), rk4 (RK4 arrested Newton flow) or "
+                         "gf (gradient flow)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times), to scale HBM counters")
     args = ap.parse_args()

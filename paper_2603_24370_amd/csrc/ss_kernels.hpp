@@ -825,8 +825,19 @@ __device__ __forceinline__ void finalise_status(DevStatus* st, double E, double 
 // Launch: gridDim.x is a multiple of 8; tiles are assigned by for_each_tile.
 // Each workgroup accumulates its tiles' reductions into one partial;
 // pass_finalise sums the partials in a fixed order and updates the status.
+// Waves per SIMD a stage pass is compiled for. The Abelian-Higgs one-pass
+// integrators in FP32 on two-row tiles are held to 128 VGPRs (four waves; 160
+// uncapped), so that two 512-thread workgroups share a CU, without spills; the
+// chiral magnet and four-row tiles would spill under that cap, and the other
+// passes fit it uncapped.
+template <class T, int TH, int PASS, int RY>
+struct StageWaves {
+  static constexpr int value = (sizeof(T) == 4 && TH == 0 && RY == 2 && advances_first(PASS)) ? 4 : 1;
+};
+
 template <class T, int TH, int PASS, int TX, int TY, int RY>
-__global__ void __launch_bounds__(TX*(TY / RY)) stage_pass(PassArgs<T> a) {
+__global__ void __launch_bounds__(TX*(TY / RY))
+__attribute__((amdgpu_waves_per_eu(StageWaves<T, TH, PASS, RY>::value))) stage_pass(PassArgs<T> a) {
   constexpr int C = NComp<TH>::value;
   constexpr int LX = TX + 4, LY = TY + 4;
   constexpr int NT = TX * (TY / RY);

@@ -7,8 +7,11 @@ csv -o run`) and the bench line of the same tree, and writes
                                     its roofline while the stage-kernel sources
                                     (comments stripped) are unchanged.
 
-    python profile_report.py --stats D1 --fetch D2 --write D3 --valu D4 --lds D5 --bench LOG
+    python profile_report.py --stats D1 --fetch D2 --write D3 --valu D4 --lds D5 --bench LOG \
+        [--stats D1' --fetch D2' --write D3' --valu D4' --lds D5' --bench LOG' ...]
 
+One set of directories per integrator run of bench.py (`--integrator rk4`, `vv`,
+`gf`), given in the same order for every option; kernels of all runs are merged.
 D1: `rocprofv3 --kernel-trace --stats` of bench.py; D2, D3: `--pmc FETCH_SIZE`,
 `--pmc WRITE_SIZE`; D4: `--pmc SQ_INSTS_VALU SQ_WAVES SQ_WAIT_INST_ANY
 SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU`; D5: `--pmc SQ_INSTS_LDS
@@ -39,7 +42,10 @@ DEFAULT_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 # field sets read and written per site by each pass (stage passes P1..P4 and
 # the fused pass of stages 2-4)
-ALG_SETS = {"P1": (1, 1), "P234": (3, 2), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2)}
+ALG_SETS = {"P1": (1, 1), "P234": (3, 2), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "VV": (3, 3), "GF": (2, 2)}
+PASS_INDEX = {"P1": 0, "P2": 1, "P3": 2, "P4": 3, "VV": 7, "GF": 8}  # the kernels' pass template argument
+# passes each integrator launches every step
+INTEG_PASSES = {"rk4": ("P1", "P234"), "vv": ("VV",), "gf": ("GF",)}
 TILES = [(64, 16, 2), (64, 8, 2), (64, 16, 4), (64, 32, 4)]  # (TX, TY, rows per thread)
 FUSED_TILES = 2  # the fused pass exists for the first two tile shapes
 
@@ -48,20 +54,27 @@ def kernel_name(p, t):
     TX, TY, RY = TILES[t]
     if p == "P234":
         return f"ss::stage_pass_fused<float, 0, {TX}, {TY}, {RY}>"
-    return f"ss::stage_pass<float, 0, {['P1', 'P2', 'P3', 'P4'].index(p)}, {TX}, {TY}, {RY}>"
+    return f"ss::stage_pass<float, 0, {PASS_INDEX[p]}, {TX}, {TY}, {RY}>"
 
 
 def _short(name):
     return name.split("(")[0].replace("void ", "")
 
 
-def counters(d):
-    """{kernel: {counter: [values per dispatch]}} of one --pmc run."""
+def counters(dirs):
+    """{kernel: {counter: [values per dispatch]}} of one or more --pmc runs."""
     out = collections.defaultdict(lambda: collections.defaultdict(list))
-    with open(os.path.join(d, "run_counter_collection.csv")) as fh:
-        for r in csv.DictReader(fh):
-            out[_short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    for d in [dirs] if isinstance(dirs, str) else dirs:
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            for r in csv.DictReader(fh):
+                out[_short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
     return out
+
+
+def integrator_of(line):
+    """rk4, vv or gf from a bench line's integrator description."""
+    text = line.get("config", {}).get("integrator", "RK4")
+    return "vv" if "Verlet" in text else "gf" if "gradient flow" in text else "rk4"
 
 
 def medians(c):
@@ -77,7 +90,7 @@ def copy_scale(d, counter, mib):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     for a in ("stats", "fetch", "write", "valu", "lds", "bench"):
-        ap.add_argument("--" + a, required=True)
+        ap.add_argument("--" + a, required=True, action="append")
     ap.add_argument("--copy-fetch")
     ap.add_argument("--copy-write")
     ap.add_argument("--copy-mib", type=int, default=1024)
@@ -96,15 +109,23 @@ def main(argv=None):
         scale_text = (f"Counter scaling (default; no copy runs given): read bytes = {fs:g} x FETCH_SIZE, written "
                       f"bytes = {ws:g} x WRITE_SIZE.")
     F, W = counters(args.fetch), counters(args.write)
-    with open(os.path.join(args.stats, "run_kernel_stats.csv")) as fh:
-        stats = {_short(r["Name"]): r for r in csv.DictReader(fh)}
-    with open(args.bench) as fh:
-        line = json.loads(fh.read().strip().split("\n")[-1])
-    chosen = line["tile"]["chosen"]
+    stats = {}
+    for d in args.stats:
+        with open(os.path.join(d, "run_kernel_stats.csv")) as fh:
+            stats.update({_short(r["Name"]): r for r in csv.DictReader(fh)})
+    chosen_of, integs = {}, []
+    for b in args.bench:
+        with open(b) as fh:
+            line = json.loads(fh.read().strip().split("\n")[-1])
+        ig = integrator_of(line)
+        integs.append(ig)
+        for p in INTEG_PASSES[ig]:
+            chosen_of[p] = line["tile"]["chosen"]
+    chosen = chosen_of.get("P1", next(iter(chosen_of.values())))
 
     rows, traffic = [], {}
     for t in range(len(TILES)):
-        for p in ("P1", "P234", "P2", "P3", "P4"):
+        for p in ("P1", "P234", "P2", "P3", "P4", "VV", "GF"):
             if p == "P234" and t >= FUSED_TILES:
                 continue
             k = kernel_name(p, t)
@@ -115,7 +136,7 @@ def main(argv=None):
             nr, nw = ALG_SETS[p]
             ar, aw = SITES * C * ELEM * nr / 1e9, SITES * C * ELEM * nw / 1e9
             us = float(stats[k]["AverageNs"]) / 1e3
-            sel = list(TILES[t]) == chosen and p in ("P1", "P234")
+            sel = p in chosen_of and list(TILES[t]) == chosen_of[p]
             label = f"{p} (tile {TILES[t][0]}x{TILES[t][1]}, {TILES[t][2]} rows/thread{'; chosen' if sel else ''})"
             rows.append((label, k, int(stats[k]["Calls"]), us, ar, rd, aw, wr, (ar + aw) / (us * 1e-6) / 1e3, sel))
             traffic.setdefault(f"tile{t}", {})[p] = {
@@ -123,26 +144,33 @@ def main(argv=None):
                 "algorithmic_GB": round(ar + aw, 4), "ratio": round((rd + wr) / (ar + aw), 3), "kernel": k}
     rows.sort(key=lambda r: (not r[9], r[0]))
 
-    bench_args = "python3 bench.py --steps 3 --warmup 1 --no-cpu --timing-steps 2 --autotune-steps 2"
-    cmd_stats = (f"rocprofv3 --kernel-trace --stats --output-format csv -d {args.stats} -o run -- "
-                 "python3 bench.py --steps 50 --warmup 5 --no-cpu --timing-steps 5")
-    cmd_f = f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {args.fetch} -o run -- {bench_args}"
-    cmd_w = f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {args.write} -o run -- {bench_args}"
+    def bench_args(ig):
+        return ("python3 bench.py --steps 3 --warmup 1 --no-cpu --timing-steps 2 --autotune-steps 2"
+                + ("" if ig == "rk4" else f" --integrator {ig}"))
+
+    cmd_stats = [f"rocprofv3 --kernel-trace --stats --output-format csv -d {d} -o run -- python3 bench.py --steps 50 "
+                 f"--warmup 5 --no-cpu --timing-steps 5" + ("" if ig == "rk4" else f" --integrator {ig}")
+                 for d, ig in zip(args.stats, integs)]
+    cmd_f = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d} -o run -- {bench_args(ig)}"
+             for d, ig in zip(args.fetch, integs)]
+    cmd_w = [f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d} -o run -- {bench_args(ig)}"
+             for d, ig in zip(args.write, integs)]
     cmd_cf = (f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {args.copy_fetch or '<copy_fetch_dir>'} -o run -- "
               f"python3 bench.py --calibrate-copy-mib {args.copy_mib}")
     cmd_cw = (f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {args.copy_write or '<copy_write_dir>'} -o run -- "
               f"python3 bench.py --calibrate-copy-mib {args.copy_mib}")
-    cmd_v = (f"rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES SQ_WAIT_INST_ANY SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU "
-             f"--output-format csv -d {args.valu} -o run -- {bench_args}")
-    cmd_l = (f"rocprofv3 --pmc SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_INSTS_SALU SQ_WAVE_CYCLES "
-             f"--output-format csv -d {args.lds} -o run -- {bench_args}")
+    cmd_v = [f"rocprofv3 --pmc SQ_INSTS_VALU SQ_WAVES SQ_WAIT_INST_ANY SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU "
+             f"--output-format csv -d {d} -o run -- {bench_args(ig)}" for d, ig in zip(args.valu, integs)]
+    cmd_l = [f"rocprofv3 --pmc SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_INSTS_SALU SQ_WAVE_CYCLES "
+             f"--output-format csv -d {d} -o run -- {bench_args(ig)}" for d, ig in zip(args.lds, integs)]
     md = ["# Stage kernels on the 4096^2 GL lattice (FP32 fields): kernel times, HBM traffic, issue counters", "",
           "Workload: `bench.py` default (GL 4096^2, kappa = 1.5, h = 0.2, 256 vortices, FP32 fields, FP64",
-          f"reductions). The autotuner picked the fused plan on {chosen[0]}x{chosen[1]} tiles (P1 and the fused "
-          "pass); the other",
+          f"reductions), run once per integrator ({', '.join(integs)}). For RK4 the autotuner picked the fused "
+          f"plan on {chosen[0]}x{chosen[1]} tiles",
+          "(P1 and the fused pass); the kernels each integrator's autotuner chose are marked, the other",
           "plans' and tiles' kernels run during autotuning and are listed for comparison.", "",
           "Commands (repository root, MI355X), summarised by `python profile_report.py` with the same",
-          "directories:", "", "```", cmd_stats, cmd_f, cmd_w, cmd_cf, cmd_cw, cmd_v, cmd_l, "```", "",
+          "directories:", "", "```", *cmd_stats, *cmd_f, *cmd_w, cmd_cf, cmd_cw, *cmd_v, *cmd_l, "```", "",
           scale_text, "",
           "| pass | kernel | calls | mean us | algorithmic read GB | measured read GB | algorithmic write GB | "
           "measured write GB | algorithmic TB/s |",
@@ -176,7 +204,7 @@ def main(argv=None):
     with open(args.out_md, "w") as fh:
         fh.write("\n".join(md) + "\n")
     rec = {"kernel_source": bench.kernel_source_hash(), "scale": {"FETCH_SIZE": fs, "WRITE_SIZE": ws},
-           "commands": [cmd_f, cmd_w, cmd_cf, cmd_cw], "gl4096": traffic}
+           "commands": [*cmd_f, *cmd_w, cmd_cf, cmd_cw], "gl4096": traffic}
     with open(args.out_json, "w") as fh:
         fh.write(json.dumps(rec, indent=1) + "\n")
     print(rec["kernel_source"])
