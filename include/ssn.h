@@ -96,6 +96,29 @@ int ssn_train_step(ssn_net* net, const float* x, const float* target, int n, flo
 size_t ssn_init_field_workspace_bytes(ssn_net* net);
 int ssn_init_field(ssn_net* net, ss_ctx* ctx, int nv, const double* xy, const double* w, double kappa, double sigma,
                    double pin, uint64_t seed, double noise_amp, void* work, size_t work_bytes);
+/* Read-back of the network's internal BF16 tensors (as floats, host array of
+ * (n, H, W, C)) for inspection and per-layer checks: for 3x3 layer `layer` (the
+ * order of the parameter exchange; 0 .. 4 levels - 1),
+ *   SSN_T_INPUT        its input (for a decoder "a" layer the concatenation
+ *                      [upsampled, skip]; for layer 0 the BF16 image, its
+ *                      channels padded with zeros to 16),
+ *   SSN_T_PREACT       its pre-activation z = conv + bias (rounded to BF16),
+ *   SSN_T_OUTPUT       its output SiLU(z) (rounded from the FP32 z),
+ *   SSN_T_GRAD_PREACT  the loss gradient at z, and
+ *   SSN_T_GRAD_DATA    what its backward-data pass wrote: for an "a" layer the
+ *                      gradient at its input (none for layer 0), for a "b" layer
+ *                      the gradient at the "a" layer's z (the product with
+ *                      SiLU'(z_a) is fused),
+ * as the last ssn_forward / ssn_backward left them. ssn_tensor_shape gives
+ * H, W, C of a tensor. count must be n * H * W * C. Synchronises. */
+#define SSN_T_INPUT 0
+#define SSN_T_PREACT 1
+#define SSN_T_OUTPUT 2
+#define SSN_T_GRAD_PREACT 3
+#define SSN_T_GRAD_DATA 4
+int ssn_tensor_shape(ssn_net* net, int kind, int layer, int* H, int* W, int* C);
+int ssn_read_tensor(ssn_net* net, int kind, int layer, int n, float* host, long count);
+
 /* Multiply-add flops (2 per MAC) of one image's forward and backward passes. */
 int ssn_flops(ssn_net* net, double* fwd, double* bwd);
 const char* ssn_last_error(void);

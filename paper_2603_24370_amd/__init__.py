@@ -83,7 +83,9 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
                "ssn_adam_step", "ssn_set_grad_clip",
-               "ssn_train_step", "ssn_flops", "ssn_init_field_workspace_bytes", "ssn_init_field", "ssn_last_error"]
+               "ssn_train_step", "ssn_flops", "ssn_init_field_workspace_bytes", "ssn_init_field", "ssn_last_error",
+               "ssn_tensor_shape", "ssn_read_tensor"]
+SSN_T_INPUT, SSN_T_PREACT, SSN_T_OUTPUT, SSN_T_GRAD_PREACT, SSN_T_GRAD_DATA = 0, 1, 2, 3, 4
 
 _lib = None
 
@@ -659,6 +661,9 @@ def _ssn_lib():
     L.ssn_init_field.argtypes = [vp, vp, i, dp, dp, d, d, d, ctypes.c_uint64, d, vp, ctypes.c_size_t]
     L.ssn_last_error.argtypes = []
     L.ssn_last_error.restype = ctypes.c_char_p
+    ip = ctypes.POINTER(i)
+    L.ssn_tensor_shape.argtypes = [vp, i, i, ip, ip, ip]
+    L.ssn_read_tensor.argtypes = [vp, i, i, i, fp, ctypes.c_long]
     L._ssn_ready = True
     return L
 
@@ -749,6 +754,18 @@ class Net:
             out = self.torch.empty((n, self.H, self.W, self.cout), dtype=self.torch.float32, device=self.device)
         fn = _ssn_lib().ssn_forward_graph if graph else _ssn_lib().ssn_forward
         _ncheck(fn(self.net, ctypes.c_void_p(x.data_ptr()), n, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def read_tensor(self, kind, layer, n=None):
+        """An internal BF16 tensor (SSN_T_*) of 3x3 layer `layer` as float32 (n, H, W, C)."""
+        import numpy as np
+        H, W, C = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _ncheck(_ssn_lib().ssn_tensor_shape(self.net, kind, layer, ctypes.byref(H), ctypes.byref(W),
+                                            ctypes.byref(C)))
+        n = self.N if n is None else n
+        out = np.empty((n, H.value, W.value, C.value), dtype=np.float32)
+        _ncheck(_ssn_lib().ssn_read_tensor(self.net, kind, layer, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                           out.size))
         return out
 
     def backward(self, target):

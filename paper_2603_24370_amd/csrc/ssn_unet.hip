@@ -794,7 +794,7 @@ struct ssn_net {
   HT ZMa, AMa, ZMb, AMb;
   std::vector<HT> ZDa, ADa, ZDb, ADb;
   // gradients
-  std::vector<HT> gCAT, gT1, gT2, gP;
+  std::vector<HT> gCAT, gT1, gT2, gT3, gP;  // gT3[l]: gradient at the pre-activation of dec_a(l)
   HT gM1, gM2;
   float *OUT, *GOUT, *part, *cpart;
   double* lpart;
@@ -834,13 +834,15 @@ size_t net_carve(ssn_net* n, char* base) {
   n->ZA.assign(L, HT()); n->AA.assign(L, HT()); n->ZB.assign(L, HT()); n->CAT.assign(L, HT());
   n->Pin.assign(L + 1, HT());
   n->ZDa.assign(L, HT()); n->ADa.assign(L, HT()); n->ZDb.assign(L, HT()); n->ADb.assign(L, HT());
-  n->gCAT.assign(L, HT()); n->gT1.assign(L, HT()); n->gT2.assign(L, HT()); n->gP.assign(L + 1, HT());
+  n->gCAT.assign(L, HT()); n->gT1.assign(L, HT()); n->gT2.assign(L, HT()); n->gT3.assign(L, HT());
+  n->gP.assign(L + 1, HT());
   for (int l = 0; l < L; ++l) {
     const int H = n->H >> l, W = n->W >> l, c = n->ch[l], cn = n->ch[l + 1];
     tensor(n->ZA[l], H, W, c); tensor(n->AA[l], H, W, c); tensor(n->ZB[l], H, W, c);
     tensor(n->CAT[l], H, W, cn + c);
     tensor(n->ZDa[l], H, W, c); tensor(n->ADa[l], H, W, c); tensor(n->ZDb[l], H, W, c); tensor(n->ADb[l], H, W, c);
     tensor(n->gCAT[l], H, W, cn + c); tensor(n->gT1[l], H, W, c); tensor(n->gT2[l], H, W, c);
+    tensor(n->gT3[l], H, W, c);
     if (l >= 1) {
       tensor(n->Pin[l], H, W, n->ch[l - 1]);
       tensor(n->gP[l], H, W, n->ch[l - 1]);
@@ -1098,9 +1100,9 @@ int net_backward(ssn_net* n, const float* target, int nb, double* loss) {
     const ConvL& ca = n->conv[dec_a(n, l)];
     launch_wgrad(n, cb, n->gT1[l].all(nb), n->ADa[l].all(nb));
     TV za = n->ZDa[l].all(nb);
-    launch_conv_bwd_data(n, cb, n->gT1[l].all(nb), n->gT2[l].all(nb), &za);
-    launch_wgrad(n, ca, n->gT2[l].all(nb), n->CAT[l].all(nb));
-    launch_conv_bwd_data(n, ca, n->gT2[l].all(nb), n->gCAT[l].all(nb), nullptr);
+    launch_conv_bwd_data(n, cb, n->gT1[l].all(nb), n->gT3[l].all(nb), &za);
+    launch_wgrad(n, ca, n->gT3[l].all(nb), n->CAT[l].all(nb));
+    launch_conv_bwd_data(n, ca, n->gT3[l].all(nb), n->gCAT[l].all(nb), nullptr);
     // the upsampled half of the concatenation feeds back to the level below
     TV gup = n->gCAT[l].view(nb, 0, cn);
     TV dst = l == L - 1 ? n->gM2.all(nb) : n->gT1[l + 1].all(nb);
@@ -1271,6 +1273,98 @@ static int copy_out(ssn_net* n, const float* dev, float* host, long count) {
 
 int ssn_get_weights(ssn_net* n, float* host, long count) { return copy_out(n, n ? n->P : nullptr, host, count); }
 int ssn_get_grads(ssn_net* n, float* host, long count) { return copy_out(n, n ? n->G : nullptr, host, count); }
+
+}  // extern "C"
+
+namespace {
+
+// The BF16 tensor of kind `kind` of 3x3 layer k (layer order of the parameter
+// exchange), as the last forward and backward passes left it.
+bool layer_tensor(const ssn_net* n, int kind, int k, int nb, TV* out) {
+  const int L = n->L;
+  const int nconv = (int)n->conv.size();
+  if (k < 0 || k >= nconv) return false;
+  // locate the layer: encoder level l (a/b), bottleneck, or decoder level l (a/b)
+  int l = -1, part = 0;  // part: 0 enc, 1 mid, 2 dec
+  bool second = (k & 1) != 0;
+  if (k < 2 * L) { l = k / 2; part = 0; }
+  else if (k < 2 * L + 2) { part = 1; }
+  else { l = L - 1 - (k - 2 * L - 2) / 2; part = 2; }
+  const int c = l >= 0 ? n->ch[l] : n->ch[L], cn = l >= 0 ? n->ch[l + 1] : 0;
+  TV t;
+  t.p = nullptr;
+  switch (kind) {
+    case SSN_T_INPUT:
+      if (part == 0) t = second ? n->AA[l].all(nb) : (l == 0 ? n->X0.all(nb) : n->Pin[l].all(nb));
+      else if (part == 1) t = second ? n->AMa.all(nb) : n->Pin[L].all(nb);
+      else t = second ? n->ADa[l].all(nb) : n->CAT[l].all(nb);
+      break;
+    case SSN_T_PREACT:
+      if (part == 0) t = second ? n->ZB[l].all(nb) : n->ZA[l].all(nb);
+      else if (part == 1) t = second ? n->ZMb.all(nb) : n->ZMa.all(nb);
+      else t = second ? n->ZDb[l].all(nb) : n->ZDa[l].all(nb);
+      break;
+    case SSN_T_OUTPUT:
+      if (part == 0) t = second ? n->CAT[l].view(nb, cn, c) : n->AA[l].all(nb);
+      else if (part == 1) t = second ? n->AMb.all(nb) : n->AMa.all(nb);
+      else t = second ? n->ADb[l].all(nb) : n->ADa[l].all(nb);
+      break;
+    case SSN_T_GRAD_PREACT:
+      if (part == 0) t = second ? n->gCAT[l].view(nb, cn, c) : n->gT2[l].all(nb);
+      else if (part == 1) t = second ? n->gM2.all(nb) : n->gM1.all(nb);
+      else t = second ? n->gT1[l].all(nb) : n->gT3[l].all(nb);
+      break;
+    case SSN_T_GRAD_DATA:
+      if (part == 0) {
+        if (second) t = n->gT2[l].all(nb);
+        else if (l > 0) t = n->gP[l].all(nb);
+        else return false;  // the first layer's input gradient is not formed
+      } else if (part == 1) {
+        t = second ? n->gM1.all(nb) : n->gP[L].all(nb);
+      } else {
+        t = second ? n->gT3[l].all(nb) : n->gCAT[l].all(nb);
+      }
+      break;
+    default:
+      return false;
+  }
+  *out = t;
+  return t.p != nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ssn_tensor_shape(ssn_net* n, int kind, int layer, int* H, int* W, int* C) {
+  if (!n || !H || !W || !C) return nfail(SS_EINVAL, "NULL argument");
+  TV t;
+  if (!layer_tensor(n, kind, layer, 1, &t)) return nfail(SS_EINVAL, "no such tensor");
+  *H = t.H;
+  *W = t.W;
+  *C = t.C;
+  return SS_OK;
+}
+
+int ssn_read_tensor(ssn_net* n, int kind, int layer, int nb, float* host, long count) {
+  if (!n || !host) return nfail(SS_EINVAL, "NULL argument");
+  if (nb < 1 || nb > n->Ncap) return nfail(SS_EINVAL, "image count out of range");
+  TV t;
+  if (!layer_tensor(n, kind, layer, nb, &t)) return nfail(SS_EINVAL, "no such tensor");
+  const long npix = (long)nb * t.H * t.W;
+  if (count != npix * t.C) return nfail(SS_EINVAL, "count must be n * H * W * C of the tensor");
+  std::vector<bf16_t> raw((size_t)npix * t.cs);
+  SN_HIP(hipMemcpyAsync(raw.data(), t.p, raw.size() * sizeof(bf16_t), hipMemcpyDeviceToHost, n->stream));
+  SN_HIP(hipStreamSynchronize(n->stream));
+  for (long p = 0; p < npix; ++p)
+    for (int ch = 0; ch < t.C; ++ch) {
+      const unsigned u = ((unsigned)raw[(size_t)p * t.cs + t.coff + ch]) << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      host[p * t.C + ch] = f;
+    }
+  return SS_OK;
+}
 
 int ssn_forward(ssn_net* n, const float* x, int nb, float* out) {
   if (!n || !x || nb < 1 || nb > n->Ncap) return nfail(SS_EINVAL, "bad forward arguments");

@@ -1,5 +1,7 @@
 """Learned initialiser on the GPU: the BF16-MFMA U-Net against the FP64 oracle
-network, and the solver-side input / target / reconstruction kernels.
+network end to end, and the solver-side input / target / reconstruction kernels.
+(Element-by-element parity of every layer, each on its own BF16 inputs, is in
+test_gpu_unet_layers.py; the checks here cover the composed network.)
 
 Tolerances (BF16, 8 significant bits): every 3x3 layer rounds its activation
 and pre-activation to BF16 (relative 2^-9) and its weights are BF16 copies of
