@@ -26,6 +26,10 @@
  *       C = 3 components (n_1, n_2, n_3), |n| = 1, bulk DMI d_k = e_k,
  *       e = J/2 |grad n|^2 + D sum_k e_k.(n x d_k n) + K (1 - n_3^2) + B (1 - n_3).
  *       params.f = {J, D, K, B [, courant]}.
+ *   "baby_skyrme" (aliases "Baby Skyrme", "BS"):
+ *       C = 3 components (m_1, m_2, m_3), |m| = 1, the standard potential,
+ *       e = 1/2 |grad m|^2 + kappa^2/4 sum_ij |d_i m x d_j m|^2 + mu^2 (1 - m_3).
+ *       params.f = {kappa, mu^2 [, courant]}. Single contexts only (no batches).
  *   params.i (optional) = {grad_mode}: SS_GRAD_EL (default) evaluates the
  *   continuum Euler-Lagrange derivative with eq. (1)-(2); SS_GRAD_EXACT uses
  *   h^-2 dE_h/dphi, the exact derivative of the discrete energy.
@@ -77,6 +81,7 @@ extern "C" {
 /* theories */
 #define SS_THEORY_AH 0
 #define SS_THEORY_CM 1
+#define SS_THEORY_BS 2
 
 /* gradient forms */
 #define SS_GRAD_EL 0
@@ -192,7 +197,7 @@ int ss_set_field(ss_ctx* ctx, const void* field);
  *       A   = sum_k w_k (1 - exp(-r_k^2)) / r_k^2 (-(y - y_k), x - x_k);
  *     the halo holds the pure-gauge vacuum psi = exp(i sum w_k theta_k),
  *     A = sum_k w_k grad theta_k.
- *   Chiral magnet, kind SS_ANSATZ_SKYRMION: n = 1, xy = centre, shape = {R, gamma}:
+ *   Chiral magnet and Baby Skyrme, kind SS_ANSATZ_SKYRMION: n = 1, xy = centre, shape = {R, gamma}:
  *       n = (sin T cos(theta + gamma), sin T sin(theta + gamma), cos T),
  *       T = 2 atan(R / r) (Belavin-Polyakov); halo n = e_3.
  * Noise: if noise_amp > 0, every interior component gets noise_amp * (2u - 1),

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-THEORIES = {"abelian_higgs": 0, "chiral_magnet": 1, "toy_harmonic": 2, "toy_offset": 3}
+THEORIES = {"abelian_higgs": 0, "chiral_magnet": 1, "toy_harmonic": 2, "toy_offset": 3, "baby_skyrme": 4}
 COURANT = 0.5  # dt = C * h with the default C of Sec. 3.1
 GRAD_EXACT = 0  # G = h^-2 dE_h/dphi
 GRAD_EL = 1     # continuum Euler-Lagrange expression evaluated with eq. (1)-(2)
@@ -63,6 +63,7 @@ def lib():
         L.or_minimise_scheme.argtypes = [i, i, i, i, i, d, dp, d, dp, dp, d, d, i, ctypes.c_long, dp]
         L.or_observables_ah.argtypes = [i, i, d, dp, dp, dp]
         L.or_observables_cm.argtypes = [i, i, d, dp, dp, dp]
+        L.or_observables_unit.argtypes = [i, i, i, d, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -168,7 +169,7 @@ def observables(theory, phi, h, params) -> dict:
         lib().or_observables_ah(Nx, Ny, h, _p(p), _p(phi), _p(out))
         return {"E": out[0], "flux": out[1], "N_rho": out[2], "N_wind": out[3], "R1": out[4], "R2": out[5]}
     out = np.zeros(3)
-    lib().or_observables_cm(Nx, Ny, h, _p(p), _p(phi), _p(out))
+    lib().or_observables_unit(_tid(theory), Nx, Ny, h, _p(p), _p(phi), _p(out))
     return {"E": out[0], "Q_fd": out[1], "Q_bl": out[2]}
 
 

@@ -48,7 +48,7 @@
 
 namespace {
 
-enum Theory { TH_AH = 0, TH_CM = 1, TH_TOY = 2, TH_TOY_OFFSET = 3 };
+enum Theory { TH_AH = 0, TH_CM = 1, TH_TOY = 2, TH_TOY_OFFSET = 3, TH_BS = 4 };
 
 int n_components(int theory) {
   switch (theory) {
@@ -56,6 +56,7 @@ int n_components(int theory) {
     case TH_CM: return 3;   // n_1, n_2, n_3
     case TH_TOY: return 1;  // one real scalar per site
     case TH_TOY_OFFSET: return 1;
+    case TH_BS: return 3;   // m_1, m_2, m_3
   }
   return -1;
 }
@@ -185,6 +186,46 @@ void cm_partials(const Jet<double>& Jt, double J, double D, double K, double Bz,
   F[0][3] = F[1][3] = 0.0;
 }
 
+// --- Baby Skyrme (Tab. 1, standard potential) --------------------------------
+// e = 1/2 sum_k |D_k m|^2 + kappa^2/4 sum_{i,j} |D_i m x D_j m|^2 + mu2 (1 - m_3);
+// the double sum has the two equal terms (i, j) = (1, 2), (2, 1), so the Skyrme term
+// is kappa^2/2 |D_1 m x D_2 m|^2.
+template <class T>
+void cross(const T* a, const T* b, T* out) {
+  out[0] = a[1] * b[2] - a[2] * b[1];
+  out[1] = a[2] * b[0] - a[0] * b[2];
+  out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <class T>
+T bs_density(const Jet<T>& Jt, double kappa, double mu2) {
+  T s[3];
+  cross(Jt.d[0], Jt.d[1], s);
+  T grad2 = 0.0, skyrme = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    grad2 += Jt.d[0][c] * Jt.d[0][c] + Jt.d[1][c] * Jt.d[1][c];
+    skyrme += s[c] * s[c];
+  }
+  return 0.5 * grad2 + 0.5 * kappa * kappa * skyrme + mu2 * (1.0 - Jt.f[2]);
+}
+
+// de/dm = -mu2 e_3;  de/d(D_1 m) = D_1 m + kappa^2 D_2 m x s;  de/d(D_2 m) = D_2 m + kappa^2 s x D_1 m,
+// with s = D_1 m x D_2 m (d|s|^2/2 = s . (dD_1 m x D_2 m) = dD_1 m . (D_2 m x s), likewise for D_2 m).
+void bs_partials(const Jet<double>& Jt, double kappa, double mu2, double g[4], double F[2][4]) {
+  double s[3], ws[3], su[3];
+  cross(Jt.d[0], Jt.d[1], s);
+  cross(Jt.d[1], s, ws);
+  cross(s, Jt.d[0], su);
+  const double k2 = kappa * kappa;
+  for (int c = 0; c < 3; ++c) {
+    g[c] = 0.0;
+    F[0][c] = Jt.d[0][c] + k2 * ws[c];
+    F[1][c] = Jt.d[1][c] + k2 * su[c];
+  }
+  g[2] = -mu2;
+  g[3] = F[0][3] = F[1][3] = 0.0;
+}
+
 // --- Harmonic toy theories (tests of the integrator and stop rules only) ------
 // e = m2/2 phi^2, and e = m2/2 phi^2 + e0 (a floor under the energy, so that its
 // relative change over a window tends to zero and the stall rule can fire).
@@ -197,6 +238,7 @@ T density(int theory, const Jet<T>& Jt, const double* p) {
     case TH_AH: return ah_density(Jt, p[0]);
     case TH_CM: return cm_density(Jt, p[0], p[1], p[2], p[3]);
     case TH_TOY_OFFSET: return toy_density(Jt, p[0]) + p[1];
+    case TH_BS: return bs_density(Jt, p[0], p[1]);
     default: return toy_density(Jt, p[0]);
   }
 }
@@ -206,6 +248,7 @@ void partials(int theory, const Jet<double>& Jt, const double* p, double g[4], d
   switch (theory) {
     case TH_AH: ah_partials(Jt, p[0], g, F); break;
     case TH_CM: cm_partials(Jt, p[0], p[1], p[2], p[3], g, F); break;
+    case TH_BS: bs_partials(Jt, p[0], p[1], g, F); break;
     default: g[0] = p[0] * Jt.f[0]; break;
   }
 }
@@ -268,6 +311,38 @@ void cm_el(const ELJet& Jt, double J, double D, double K, double Bz, double G[4]
   G[3] = 0.0;
 }
 
+// Baby Skyrme: G = de/dm - d_1 [de/d(d_1 m)] - d_2 [de/d(d_2 m)] with
+//   d_1 [d_1 m + k^2 d_2 m x s] = m_xx + k^2 (m_xy x s + d_2 m x s_x),  s_x = m_xx x d_2 m + d_1 m x m_xy,
+//   d_2 [d_2 m + k^2 s x d_1 m] = m_yy + k^2 (s_y x d_1 m + s x m_xy),  s_y = m_xy x d_2 m + d_1 m x m_yy.
+void bs_el(const ELJet& J, double kappa, double mu2, double G[4]) {
+  const double* u = J.d[0];
+  const double* w = J.d[1];
+  const double* mxx = J.dd[0];
+  const double* myy = J.dd[1];
+  const double* mxy = J.dxy;
+  double s[3], sx[3], sy[3], t1[3], t2[3];
+  cross(u, w, s);
+  cross(mxx, w, t1);
+  cross(u, mxy, t2);
+  for (int c = 0; c < 3; ++c) sx[c] = t1[c] + t2[c];
+  cross(mxy, w, t1);
+  cross(u, myy, t2);
+  for (int c = 0; c < 3; ++c) sy[c] = t1[c] + t2[c];
+  double a1[3], a2[3], b1[3], b2[3];
+  cross(mxy, s, a1);
+  cross(w, sx, a2);
+  cross(sy, u, b1);
+  cross(s, mxy, b2);
+  const double k2 = kappa * kappa;
+  for (int c = 0; c < 3; ++c) {
+    const double d1F1 = mxx[c] + k2 * (a1[c] + a2[c]);
+    const double d2F2 = myy[c] + k2 * (b1[c] + b2[c]);
+    G[c] = -d1F1 - d2F2;
+  }
+  G[2] -= mu2;
+  G[3] = 0.0;
+}
+
 void gradient_el(int theory, const Lat& L, const double* p, const double* phi, double* G) {
   int C = n_components(theory);
   std::memset(G, 0, sizeof(double) * C * L.plane());
@@ -277,6 +352,7 @@ void gradient_el(int theory, const Lat& L, const double* p, const double* phi, d
       double g[4] = {0.0, 0.0, 0.0, 0.0};
       if (theory == TH_AH) ah_el(J, p[0], g);
       else if (theory == TH_CM) cm_el(J, p[0], p[1], p[2], p[3], g);
+      else if (theory == TH_BS) bs_el(J, p[0], p[1], g);
       else g[0] = p[0] * J.f[0];
       for (int c = 0; c < C; ++c) G[L.at(c, j, i)] = g[c];
     }
@@ -342,6 +418,9 @@ void tangent_project(const Lat& L, const double* n, double* X) {
     }
 }
 
+// Theories of a unit-vector field (chiral magnet, Baby Skyrme).
+bool unit_theory(int theory) { return theory == TH_CM || theory == TH_BS; }
+
 // The force used by the flow: -G at the stage point; for the chiral magnet the
 // stage point is first put back on the unit sphere and -G is projected onto its
 // tangent plane.
@@ -349,10 +428,10 @@ void acceleration(int theory, int mode, const Lat& L, const double* p, const dou
   int C = n_components(theory);
   long n = (long)C * L.plane();
   std::vector<double> s(stage, stage + n);
-  if (theory == TH_CM) normalise_interior(L, s.data());
+  if (unit_theory(theory)) normalise_interior(L, s.data());
   if (mode == 0) gradient(theory, L, p, s.data(), a);
   else gradient_el(theory, L, p, s.data(), a);
-  if (theory == TH_CM) tangent_project(L, s.data(), a);
+  if (unit_theory(theory)) tangent_project(L, s.data(), a);
   for (long k = 0; k < n; ++k) a[k] = -a[k];
 }
 
@@ -389,7 +468,7 @@ void rk4_step(int theory, int mode, const Lat& L, const double* p, double dt, do
         phi[k] += dt / 6.0 * (k1p[k] + 2.0 * k2p[k] + 2.0 * k3p[k] + k4p[k]);
         v[k] += dt / 6.0 * (k1v[k] + 2.0 * k2v[k] + 2.0 * k3v[k] + k4v[k]);
       }
-  if (theory == TH_CM) {
+  if (unit_theory(theory)) {
     normalise_interior(L, phi);
     tangent_project(L, phi, v);
   }
@@ -420,7 +499,7 @@ void one_pass_step(int theory, int mode, int scheme, const Lat& L, const double*
         if (scheme == SCHEME_VV) phi[k] += dt * v[k] + 0.5 * dt * dt * a0[k];
         else phi[k] += 0.5 * dt * dt * a0[k];
       }
-  if (theory == TH_CM) normalise_interior(L, phi);
+  if (unit_theory(theory)) normalise_interior(L, phi);
   if (scheme != SCHEME_VV) return;
   acceleration(theory, mode, L, p, phi, a1.data());
   for (int c = 0; c < C; ++c)
@@ -429,7 +508,7 @@ void one_pass_step(int theory, int mode, int scheme, const Lat& L, const double*
         long k = L.at(c, j, i);
         v[k] += 0.5 * dt * (a0[k] + a1[k]);
       }
-  if (theory == TH_CM) tangent_project(L, phi, v);
+  if (unit_theory(theory)) tangent_project(L, phi, v);
 }
 
 void step_scheme(int theory, int mode, int scheme, const Lat& L, const double* p, double dt, double* phi, double* v) {
@@ -626,14 +705,21 @@ void or_observables_ah(int Nx, int Ny, double h, const double* p, const double* 
 //          a=(i,j), b=(i+1,j), c=(i+1,j+1), d=(i,j+1)) the signed solid angles of the
 //          triangles (a,b,c) and (a,c,d), each 2 atan2(a.(b x c), 1 + a.b + b.c + c.a),
 //          summed and divided by 4 pi.
+void or_observables_unit(int theory, int Nx, int Ny, double h, const double* p, const double* phi, double* out);
+
 void or_observables_cm(int Nx, int Ny, double h, const double* p, const double* phi, double* out) {
+  or_observables_unit(TH_CM, Nx, Ny, h, p, phi, out);
+}
+
+// Observables of a unit-vector field of either theory (as for the chiral magnet).
+void or_observables_unit(int theory, int Nx, int Ny, double h, const double* p, const double* phi, double* out) {
   Lat L(Nx, Ny, h);
   const double pi = 3.14159265358979323846;
   KSum sE, sQ, sBL;
   for (int j = 0; j < Ny; ++j)
     for (int i = 0; i < Nx; ++i) {
       Jet<double> J = jet_at(phi, L, 3, j, i);
-      sE.add(cm_density(J, p[0], p[1], p[2], p[3]));
+      sE.add(density(theory, J, p));
       const double* n = J.f;
       const double* u = J.d[0];
       const double* w = J.d[1];

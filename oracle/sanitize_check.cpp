@@ -29,6 +29,7 @@ void or_minimise_scheme(int theory, int mode, int scheme, int Nx, int Ny, double
                         long max_steps, double* info);
 void or_observables_ah(int Nx, int Ny, double h, const double* p, const double* phi, double* out);
 void or_observables_cm(int Nx, int Ny, double h, const double* p, const double* phi, double* out);
+void or_observables_unit(int theory, int Nx, int Ny, double h, const double* p, const double* phi, double* out);
 }
 
 namespace {
@@ -54,7 +55,8 @@ std::vector<double> field(int C, int Nx, int Ny, bool unit) {
 int check_theory(int theory, const double* p, int Nx, int Ny) {
   const int C = or_components(theory);
   const double h = 0.3;
-  std::vector<double> phi = field(C, Nx, Ny, theory == 1), zero(phi.size(), 0.0), G(phi.size()), a(phi.size());
+  const bool unit = theory == 1 || theory == 4;
+  std::vector<double> phi = field(C, Nx, Ny, unit), zero(phi.size(), 0.0), G(phi.size()), a(phi.size());
   std::vector<double> dens((size_t)Nx * Ny), out(8), info(6);
   double acc = or_energy(theory, Nx, Ny, h, p, phi.data());
   or_energy_density(theory, Nx, Ny, h, p, phi.data(), dens.data());
@@ -81,6 +83,7 @@ int check_theory(int theory, const double* p, int Nx, int Ny) {
   }
   if (theory == 0) or_observables_ah(Nx, Ny, h, p, phi.data(), out.data());
   if (theory == 1) or_observables_cm(Nx, Ny, h, p, phi.data(), out.data());
+  if (theory == 4) or_observables_unit(4, Nx, Ny, h, p, phi.data(), out.data());
   acc += out[0];
   return std::isfinite(acc) ? 0 : 1;
 }
@@ -88,12 +91,13 @@ int check_theory(int theory, const double* p, int Nx, int Ny) {
 }  // namespace
 
 int main() {
-  const double p_ah[1] = {0.8}, p_cm[4] = {1.1, 0.9, 0.2, 0.5}, p_toy[2] = {1.3, 0.1};
+  const double p_ah[1] = {0.8}, p_cm[4] = {1.1, 0.9, 0.2, 0.5}, p_toy[2] = {1.3, 0.1}, p_bs[2] = {0.9, 0.2};
   int bad = 0;
   bad += check_theory(0, p_ah, 9, 7);
   bad += check_theory(1, p_cm, 8, 10);
   bad += check_theory(2, p_toy, 5, 6);
   bad += check_theory(3, p_toy, 6, 5);
+  bad += check_theory(4, p_bs, 7, 8);
   if (bad) {
     std::printf("non-finite result\n");
     return 1;

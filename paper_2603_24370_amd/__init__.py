@@ -23,7 +23,7 @@ SS_PLAN_STAGES, SS_PLAN_FUSED = 0, 1
 SS_INTEG_RK4, SS_INTEG_VV, SS_INTEG_GF = 0, 1, 2
 INTEGRATORS = {"rk4": SS_INTEG_RK4, "vv": SS_INTEG_VV, "gf": SS_INTEG_GF}
 SS_NUM_PLANS = 2
-SS_THEORY_AH, SS_THEORY_CM = 0, 1
+SS_THEORY_AH, SS_THEORY_CM, SS_THEORY_BS = 0, 1, 2
 SS_ANSATZ_VORTICES, SS_ANSATZ_SKYRMION = 0, 1
 STOP_REASONS = {0: "none", 1: "grad", 2: "stall", 3: "max_steps", 4: "nonfinite", 5: "target"}
 

@@ -247,13 +247,17 @@ void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   if (c->grad_mode == SS_GRAD_EXACT) {
     // exact-gradient passes: one tile shape (64 x 16), the layout of tile 0
     if (c->theory == SS_THEORY_AH)
-      hipLaunchKernelGGL((stage_pass_exact<T, 0, PASS>), dim3(groups), dim3(kExTX, kExTY / kExRY), 0, s, a);
+      hipLaunchKernelGGL((stage_pass_exact<T, kAH, PASS>), dim3(groups), dim3(kExTX, kExTY / kExRY), 0, s, a);
+    else if (c->theory == SS_THEORY_CM)
+      hipLaunchKernelGGL((stage_pass_exact<T, kCM, PASS>), dim3(groups), dim3(kExTX, kExTY / kExRY), 0, s, a);
     else
-      hipLaunchKernelGGL((stage_pass_exact<T, 1, PASS>), dim3(groups), dim3(kExTX, kExTY / kExRY), 0, s, a);
+      hipLaunchKernelGGL((stage_pass_exact<T, kBS, PASS>), dim3(groups), dim3(kExTX, kExTY / kExRY), 0, s, a);
   } else if (c->theory == SS_THEORY_AH) {
-    groups = launch_pass_t<T, 0, PASS>(c->tile, a, groups, s);
+    groups = launch_pass_t<T, kAH, PASS>(c->tile, a, groups, s);
+  } else if (c->theory == SS_THEORY_CM) {
+    groups = launch_pass_t<T, kCM, PASS>(c->tile, a, groups, s);
   } else {
-    groups = launch_pass_t<T, 1, PASS>(c->tile, a, groups, s);
+    groups = launch_pass_t<T, kBS, PASS>(c->tile, a, groups, s);
   }
   if constexpr (reduces(PASS))
     hipLaunchKernelGGL((pass_finalise<PASS>), dim3(1), dim3(256), 0, s, a.st, (const double*)a.partials, groups,
@@ -308,8 +312,9 @@ void launch_fused(const ss_ctx* c, hipStream_t s) {
   a.ntx = L.ntx;
   a.nty = L.nty;
   a.seg = L.seg;
-  if (c->theory == SS_THEORY_AH) launch_fused_t<T, 0>(lt, a, L.nlaunch, s);
-  else launch_fused_t<T, 1>(lt, a, L.nlaunch, s);
+  if (c->theory == SS_THEORY_AH) launch_fused_t<T, kAH>(lt, a, L.nlaunch, s);
+  else if (c->theory == SS_THEORY_CM) launch_fused_t<T, kCM>(lt, a, L.nlaunch, s);
+  else launch_fused_t<T, kBS>(lt, a, L.nlaunch, s);
 }
 
 template <class T>
@@ -445,10 +450,13 @@ int ss_theory_id(const char* name) {
   if (!name) return SS_ETHEORY;
   static const char* ah[] = {"abelian_higgs", "abelian higgs", "ginzburg-landau", "gl", "ah", "ginzburg landau"};
   static const char* cm[] = {"chiral_magnet", "chiral magnet", "cm"};
+  static const char* bs[] = {"baby_skyrme", "baby skyrme", "bs"};
   for (const char* a : ah)
     if (lower_eq(name, a)) return SS_THEORY_AH;
   for (const char* a : cm)
     if (lower_eq(name, a)) return SS_THEORY_CM;
+  for (const char* a : bs)
+    if (lower_eq(name, a)) return SS_THEORY_BS;
   return SS_ETHEORY;
 }
 
@@ -478,10 +486,11 @@ int resolve_problem(const char* theory, int Nx, int Ny, double h, const ss_param
   if (dtype != SS_F32 && dtype != SS_F64) return fail(SS_EINVAL, "dtype must be SS_F32 or SS_F64");
   if (Nx < 8 || Ny < 8 || Nx > 65536 || Ny > 65536) return fail(SS_ESHAPE, "Nx, Ny must lie in [8, 65536]");
   if (!(h > 0.0) || !std::isfinite(h)) return fail(SS_EINVAL, "lattice spacing h must be positive and finite");
-  const int nf_need = th == SS_THEORY_AH ? 1 : 4;
+  const int nf_need = th == SS_THEORY_AH ? 1 : th == SS_THEORY_CM ? 4 : 2;
   if (!params || !params->f || params->nf < nf_need || params->nf > nf_need + 1)
-    return fail(SS_EINVAL, th == SS_THEORY_AH ? "abelian_higgs needs params.f = {lambda [, courant]}"
-                                              : "chiral_magnet needs params.f = {J, D, K, B [, courant]}");
+    return fail(SS_EINVAL, th == SS_THEORY_AH   ? "abelian_higgs needs params.f = {lambda [, courant]}"
+                           : th == SS_THEORY_CM ? "chiral_magnet needs params.f = {J, D, K, B [, courant]}"
+                                                : "baby_skyrme needs params.f = {kappa, mu^2 [, courant]}");
   for (int k = 0; k < params->nf; ++k)
     if (!std::isfinite(params->f[k])) return fail(SS_EINVAL, "non-finite parameter");
   const double courant = params->nf > nf_need ? params->f[nf_need] : 0.5;
@@ -983,31 +992,40 @@ int ss_minimise(ss_ctx* c, const ss_stop* stop, ss_min_info* info) {
   return SS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
 // Observable passes of one context, enqueued on its stream; obs_collect reads them back.
-static int obs_enqueue(ss_ctx* c) {
-  const int nobs = 1024;
-  if (c->dtype == SS_F32) {
-    Bufs<float> B = bufs_of<float>(c);
-    if (c->theory == SS_THEORY_AH) {
-      hipLaunchKernelGGL((obs_sites<float, 0>), dim3(nobs), dim3(256), 0, c->stream, B, coeffs_of(c), c->st, c->partials, nobs);
-      hipLaunchKernelGGL((obs_winding<float>), dim3(1), dim3(256), 0, c->stream, B, c->st);
-    } else {
-      hipLaunchKernelGGL((obs_sites<float, 1>), dim3(nobs), dim3(256), 0, c->stream, B, coeffs_of(c), c->st, c->partials, nobs);
-      hipLaunchKernelGGL((obs_berg_luscher<float>), dim3(nobs), dim3(256), 0, c->stream, B, c->st, c->partials, nobs);
-    }
-  } else {
-    Bufs<double> B = bufs_of<double>(c);
-    if (c->theory == SS_THEORY_AH) {
-      hipLaunchKernelGGL((obs_sites<double, 0>), dim3(nobs), dim3(256), 0, c->stream, B, coeffs_of(c), c->st, c->partials, nobs);
-      hipLaunchKernelGGL((obs_winding<double>), dim3(1), dim3(256), 0, c->stream, B, c->st);
-    } else {
-      hipLaunchKernelGGL((obs_sites<double, 1>), dim3(nobs), dim3(256), 0, c->stream, B, coeffs_of(c), c->st, c->partials, nobs);
-      hipLaunchKernelGGL((obs_berg_luscher<double>), dim3(nobs), dim3(256), 0, c->stream, B, c->st, c->partials, nobs);
-    }
+template <class T>
+void obs_enqueue_t(ss_ctx* c, int nobs) {
+  Bufs<T> B = bufs_of<T>(c);
+  if (c->theory == SS_THEORY_AH) {
+    hipLaunchKernelGGL((obs_sites<T, kAH>), dim3(nobs), dim3(256), 0, c->stream, B, coeffs_of(c), c->st, c->partials,
+                       nobs);
+    hipLaunchKernelGGL((obs_winding<T>), dim3(1), dim3(256), 0, c->stream, B, c->st);
+    return;
   }
+  if (c->theory == SS_THEORY_CM)
+    hipLaunchKernelGGL((obs_sites<T, kCM>), dim3(nobs), dim3(256), 0, c->stream, B, coeffs_of(c), c->st, c->partials,
+                       nobs);
+  else
+    hipLaunchKernelGGL((obs_sites<T, kBS>), dim3(nobs), dim3(256), 0, c->stream, B, coeffs_of(c), c->st, c->partials,
+                       nobs);
+  hipLaunchKernelGGL((obs_berg_luscher<T>), dim3(nobs), dim3(256), 0, c->stream, B, c->st, c->partials, nobs);
+}
+
+int obs_enqueue(ss_ctx* c) {
+  const int nobs = 1024;
+  if (c->dtype == SS_F32) obs_enqueue_t<float>(c, nobs);
+  else obs_enqueue_t<double>(c, nobs);
   SS_HIP(hipGetLastError());
   return SS_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 static int obs_collect(ss_ctx* c, ss_obs* out) {
   DevStatus d;
@@ -1610,6 +1628,7 @@ int ss_batch_create(const char* theory, int n, const ss_instance* inst, int dtyp
   if (rc) return rc;
   if (!workspace || ws_bytes < need) return fail(SS_EINVAL, "workspace missing or smaller than ss_batch_workspace_bytes");
   if (((uintptr_t)workspace) % 256 != 0) return fail(SS_EINVAL, "workspace must be 256-byte aligned");
+  if (ss_theory_id(theory) == SS_THEORY_BS) return fail(SS_ETHEORY, "batches run the abelian_higgs and chiral_magnet theories");
   ss_batch* b = new (std::nothrow) ss_batch();
   if (!b) return fail(SS_EINVAL, "out of host memory");
   b->theory = ss_theory_id(theory);
@@ -1817,7 +1836,7 @@ int ss_batch_autotune(ss_batch* b, int n_steps, double* ms_out) {
   for (ss_ctx* c : b->members) {
     int rc = c->theory == SS_THEORY_AH ? ss_init_ansatz(c, SS_ANSATZ_VORTICES, 0, nullptr, nullptr, nullptr, 0, 0.0)
                                        : 0;
-    if (c->theory == SS_THEORY_CM) {
+    if (c->theory != SS_THEORY_AH) {
       const double zero[2] = {0.0, 0.0}, shape[2] = {0.0, 0.0};
       rc = ss_init_ansatz(c, SS_ANSATZ_SKYRMION, 1, zero, nullptr, shape, 0, 0.0);
     }

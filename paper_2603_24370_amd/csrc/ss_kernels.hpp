@@ -31,6 +31,8 @@ template <>
 struct NComp<0> { static constexpr int value = 4; };
 template <>
 struct NComp<1> { static constexpr int value = 3; };
+template <>
+struct NComp<2> { static constexpr int value = 3; };
 
 // Jets of one component for RY consecutive rows of one LDS column (rows
 // ly0 .. ly0 + RY - 1, column lx), by eq. (1) and eq. (2); the mixed derivative
@@ -170,7 +172,7 @@ __device__ __forceinline__ void one_pass_epilogue(bool arrest, T dt, const T (&v
     T vnew[4];
 #pragma unroll
     for (int c = 0; c < C; ++c) vnew[c] = (arrest ? T(0) : v[c]) + (T(0.5) * dt) * (a[c] - G[c]);
-    if (TH == 1) {
+    if (unit_field(TH)) {
       const T vd = vnew[0] * S[0] + vnew[1] * S[1] + vnew[2] * S[2];
 #pragma unroll
       for (int c = 0; c < 3; ++c) vnew[c] -= vd * S[c];
@@ -263,7 +265,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
       }
       S[c] = x;
     }
-    if (TH == 1 && STAGED && gi_ >= 0 && gi_ < Nx && gj_ >= 0 && gj_ < Ny) {
+    if (unit_field(TH) && STAGED && gi_ >= 0 && gi_ < Nx && gj_ >= 0 && gj_ < Ny) {
       const T inv = T(1) / sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
       S[0] *= inv;
       S[1] *= inv;
@@ -318,9 +320,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
           Jd[c].y = ey[c][r];
           Jd[c].xx = Jd[c].yy = Jd[c].xy = 0.0;
         }
-        double e;
-        if (TH == 0) e = ah_density<double>(Jd, V.p[0]);
-        else e = cm_density<double>(Jd, V.p[0], V.p[1], V.p[2], V.p[3]);
+        const double e = density<TH>(Jd, V.p);
         e_acc += e;
         if (!isfinite(e)) ++nf;
       }
@@ -332,15 +332,15 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
     double dx_[C][RY], dy_[C][RY];
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      column_jets<T, LX, RY, TH == 0, false>(s[c], lx, ly0, c1, c2, d1, J[c], dx_[c], dy_[c]);
+      column_jets<T, LX, RY, el_mixed(TH), false>(s[c], lx, ly0, c1, c2, d1, J[c], dx_[c], dy_[c]);
   }
 
   // The chiral magnet needs E_h before the stage point is normalised in LDS;
   // the Abelian Higgs energy is formed after the epilogue, so that the FP64
   // energy and the FP32 gradient do not hold registers at the same time.
   if (REDUCE) {
-    if (TH == 1) energy_density();
-    if (TH == 1) {
+    if (unit_field(TH)) energy_density();
+    if (unit_field(TH)) {
       // the flow evaluates G at the normalised field
       __syncthreads();
       for (int idx = tid; idx < LX * LY; idx += NT) {
@@ -358,7 +358,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
       double dx_[C][RY], dy_[C][RY];
 #pragma unroll
       for (int c = 0; c < C; ++c)
-        column_jets<T, LX, RY, false, false>(s[c], lx, ly0, c1, c2, d1, J[c], dx_[c], dy_[c]);
+        column_jets<T, LX, RY, el_mixed(TH), false>(s[c], lx, ly0, c1, c2, d1, J[c], dx_[c], dy_[c]);
     }
   }
 
@@ -375,10 +375,8 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
 #pragma unroll
     for (int c = 0; c < C; ++c) Js[c] = J[c][r];
     T G[4];
-    if (TH == 0) {
-      ah_el_gradient<T>(Js, (T)V.p[0], G);
-    } else {
-      cm_el_gradient<T>(Js, (T)V.p[0], (T)V.p[1], (T)V.p[2], (T)V.p[3], G);
+    el_gradient<T, TH>(Js, V.p, G);
+    if (unit_field(TH)) {
       const T gn = G[0] * Js[0].f + G[1] * Js[1].f + G[2] * Js[2].f;
 #pragma unroll
       for (int c = 0; c < 3; ++c) G[c] -= gn * Js[c].f;
@@ -422,7 +420,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
         pn[c] = rp[r][c] + dt * v0 + (dt * dt / T(12)) * (qq + __builtin_nontemporal_load(&V.a1[k]));
         vnew[c] = v0 + (dt / T(6)) * (qq - G[c]);
       }
-      if (TH == 1) {
+      if (unit_field(TH)) {
         const T inv = T(1) / sqrt(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) pn[c] *= inv;
@@ -474,6 +472,16 @@ __device__ __forceinline__ void site_fluxes(T* const (&s)[4], int ly, int lx, T 
     if (xdir) { F[0] = dxp + ax * q; F[1] = dxq - ax * p; }
     else { F[0] = dyp + ay * q; F[1] = dyq - ay * p; }
     F[2] = dxa2 - dya1;
+  } else if (TH == kBS) {
+    // F_x = u + kappa^2 w x (u x w) = u + kappa^2 (u |w|^2 - w (u.w)),
+    // F_y = w + kappa^2 (u x w) x u = w + kappa^2 (w |u|^2 - u (u.w))
+    const T k2 = (T)(V.p[0] * V.p[0]);
+    T u[3], w[3];
+    for (int c = 0; c < 3; ++c) lds_dxdy<T, LX>(s[c], ly, lx, c1, u[c], w[c]);
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2], ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    const T uw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+    for (int c = 0; c < 3; ++c)
+      F[c] = xdir ? u[c] + k2 * (u[c] * ww - w[c] * uw) : w[c] + k2 * (w[c] * uu - u[c] * uw);
   } else {
     const T J = (T)V.p[0], Dm = (T)V.p[1];
     const int o = ly * LX + lx;
@@ -551,7 +559,7 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
       }
       S[c] = x;
     }
-    if (TH == 1 && STAGED && gi_ >= 0 && gi_ < Nx && gj_ >= 0 && gj_ < Ny) {
+    if (unit_field(TH) && STAGED && gi_ >= 0 && gi_ < Nx && gj_ >= 0 && gj_ < Ny) {
       const T inv = T(1) / sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
       S[0] *= inv;
       S[1] *= inv;
@@ -603,12 +611,12 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
           Jd[c].y = d1 * (((double)q[-2 * LX] - (double)q[2 * LX]) + 8.0 * ((double)q[LX] - (double)q[-LX]));
           Jd[c].xx = Jd[c].yy = Jd[c].xy = 0.0;
         }
-        const double e = TH == 0 ? ah_density<double>(Jd, V.p[0]) : cm_density<double>(Jd, V.p[0], V.p[1], V.p[2], V.p[3]);
+        const double e = density<TH>(Jd, V.p);
         e_acc += e;
         if (!isfinite(e)) ++nf;
       }
     }
-    if (TH == 1) {
+    if (unit_field(TH)) {
       __syncthreads();
       for (int idx = tid; idx < LX * LY; idx += NT) {
         const int ly = idx / LX, lx = idx - ly * LX;
@@ -648,6 +656,8 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
       g[r][1] = (ax * P1 + ay * P2) - T(0.5) * lam * Wm * q;
       g[r][2] = P1 * q - Q1 * p;
       g[r][3] = P2 * q - Q2 * p;
+    } else if (TH == kBS) {
+      g[r][2] = -(T)V.p[1];  // d/dm of mu^2 (1 - m_z); the other terms are fluxes
     } else {
       const T Dm = (T)V.p[1], K = (T)V.p[2], Bz = (T)V.p[3];
       g[r][0] = -Dm * dy[2];
@@ -764,7 +774,7 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
         pn[c] = rp[r][c] + dt * v0 + (dt * dt / T(12)) * (qq + __builtin_nontemporal_load(&V.a1[k]));
         vnew[c] = v0 + (dt / T(6)) * (qq - G[c]);
       }
-      if (TH == 1) {
+      if (unit_field(TH)) {
         const T inv = T(1) / sqrt(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) pn[c] *= inv;
@@ -935,10 +945,8 @@ __device__ __forceinline__ void site_jet(const T* __restrict__ s, int ly, int lx
 // G at one site from its jets (the chiral magnet's G is projected at the site).
 template <class T, int TH>
 __device__ __forceinline__ void site_gradient(const Jet<T> (&Js)[4], const InstView<T>& V, T (&G)[4]) {
-  if (TH == 0) {
-    ah_el_gradient<T>(Js, (T)V.p[0], G);
-  } else {
-    cm_el_gradient<T>(Js, (T)V.p[0], (T)V.p[1], (T)V.p[2], (T)V.p[3], G);
+  el_gradient<T, TH>(Js, V.p, G);
+  if (unit_field(TH)) {
     const T gn = G[0] * Js[0].f + G[1] * Js[1].f + G[2] * Js[2].f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) G[c] -= gn * Js[c].f;
@@ -963,7 +971,7 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
   constexpr int NT = TX * (TY / RY);
   constexpr int NRB = NB - TX * TY;         // ring of B around the tile
   constexpr int KRB = (NRB + NT - 1) / NT;
-  constexpr bool MIXED = (TH == 0);
+  constexpr bool MIXED = el_mixed(TH);
   // LDS: A [C][AY][AX] | a2 [C][BY][BX] | phi [C][BY][BX] | v [C][BY][BX] | a1 [C][BY][BX]
   T* sa[4];
   T* s2[4];
@@ -1015,7 +1023,7 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
         if (inb) A1[c] = a1p[c * plane + o];
         S[c] = P[c] + cv2 * W[c];
       }
-      if (TH == 1 && inside(x, y)) unit3(S);
+      if (unit_field(TH) && inside(x, y)) unit3(S);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) sa[c][idx] = S[c];
@@ -1101,7 +1109,7 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
       T S[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int c = 0; c < C; ++c) S[c] = sp[c][ib] + cv * sv[c][ib] + ca * acc[c][ib];
-      if (TH == 1 && inside(x0 - 2 + bx, y0 - 2 + by)) unit3(S);
+      if (unit_field(TH) && inside(x0 - 2 + bx, y0 - 2 + by)) unit3(S);
 #pragma unroll
       for (int c = 0; c < C; ++c) sa[c][(by + 2) * AX + bx + 2] = S[c];
     }
@@ -1167,7 +1175,7 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
         pn[c] = sp[c][ib] + dt * v0 + (dt * dt / T(12)) * (qo[r][c] + s1[c][ib]);
         vnew[c] = v0 + (dt / T(6)) * (qo[r][c] - G[c]);
       }
-      if (TH == 1) {
+      if (unit_field(TH)) {
         unit3(pn);
         const T vd = vnew[0] * pn[0] + vnew[1] * pn[1] + vnew[2] * pn[2];
 #pragma unroll
@@ -1505,12 +1513,15 @@ __global__ void __launch_bounds__(256) obs_sites(Bufs<T> B, Coeffs cf, DevStatus
       v[3] += r1r * r1r + r1i * r1i;
       v[4] += r2 * r2;
     } else {
-      const double cx = dy[2], cy = -dx[2], cz = dx[1] - dy[0];
-      double ex = 0.0;
-      for (int c = 0; c < 3; ++c) ex += dx[c] * dx[c] + dy[c] * dy[c];
-      v[0] += 0.5 * cf.p[0] * ex - cf.p[1] * (f[0] * cx + f[1] * cy + f[2] * cz) + cf.p[2] * (1.0 - f[2] * f[2]) +
-              cf.p[3] * (1.0 - f[2]);
-      // n . (d_x n x d_y n)
+      // unit-vector theories: energy density and n . (d_x n x d_y n)
+      Jet<double> Jd[4];
+      for (int c = 0; c < 4; ++c) {
+        Jd[c].f = c < 3 ? f[c] : 0.0;
+        Jd[c].x = c < 3 ? dx[c] : 0.0;
+        Jd[c].y = c < 3 ? dy[c] : 0.0;
+        Jd[c].xx = Jd[c].yy = Jd[c].xy = 0.0;
+      }
+      v[0] += density<TH>(Jd, cf.p);
       const double tx = dx[1] * dy[2] - dx[2] * dy[1], ty = dx[2] * dy[0] - dx[0] * dy[2],
                    tz = dx[0] * dy[1] - dx[1] * dy[0];
       v[1] += f[0] * tx + f[1] * ty + f[2] * tz;

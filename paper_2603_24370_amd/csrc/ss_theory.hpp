@@ -72,4 +72,61 @@ __device__ __forceinline__ double cm_density(const Jet<T> (&J)[4], double Jx, do
   return 0.5 * Jx * ex - Dm * (nx * cx + ny * cy + nz * cz) + K * (1.0 - nz * nz) + Bz * (1.0 - nz);
 }
 
+// Baby Skyrme model (Tab. 1) with the standard potential, unit field m:
+//   e = 1/2 (|u|^2 + |w|^2) + kappa^2/2 |u x w|^2 + mu^2 (1 - m_z),   u = d_x m, w = d_y m
+// (kappa^2/4 sum_ij |d_i m x d_j m|^2 = kappa^2/2 |u x w|^2). The Euler-Lagrange
+// derivative, with the Skyrme term's cross products expanded into dot products:
+//   G = -lap m - mu^2 e_z - kappa^2 [ m_xx |w|^2 + m_yy |u|^2 - 2 m_xy (u.w)
+//         - w (w.m_xx) - u (u.m_yy) + u (w.m_xy) + w (u.m_xy) ]   (before projection).
+template <class T>
+__device__ __forceinline__ void bs_el_gradient(const Jet<T> (&J)[4], T kappa2, T mu2, T (&G)[4]) {
+  T u[3], w[3], mxx[3], myy[3], mxy[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    u[c] = J[c].x; w[c] = J[c].y; mxx[c] = J[c].xx; myy[c] = J[c].yy; mxy[c] = J[c].xy;
+  }
+  auto dot = [](const T (&a)[3], const T (&b)[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+  const T uu = dot(u, u), ww = dot(w, w), uw = dot(u, w);
+  const T w_xx = dot(w, mxx), u_yy = dot(u, myy), w_xy = dot(w, mxy), u_xy = dot(u, mxy);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T sk = mxx[c] * ww + myy[c] * uu - T(2) * mxy[c] * uw - w[c] * w_xx - u[c] * u_yy + u[c] * w_xy + w[c] * u_xy;
+    G[c] = -(mxx[c] + myy[c]) - kappa2 * sk;
+  }
+  G[2] -= mu2;
+  G[3] = T(0);
+}
+
+template <class T>
+__device__ __forceinline__ double bs_density(const Jet<T> (&J)[4], double kappa2, double mu2) {
+  double uu = 0.0, ww = 0.0, uw = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    uu += (double)J[c].x * J[c].x;
+    ww += (double)J[c].y * J[c].y;
+    uw += (double)J[c].x * J[c].y;
+  }
+  return 0.5 * (uu + ww) + 0.5 * kappa2 * (uu * ww - uw * uw) + mu2 * (1.0 - (double)J[2].f);
+}
+
+// Theory ids of the kernels' template argument, and what each needs.
+constexpr int kAH = 0, kCM = 1, kBS = 2;
+constexpr bool unit_field(int TH) { return TH != kAH; }     // |m| = 1, projected forces
+constexpr bool el_mixed(int TH) { return TH != kCM; }       // the EL form uses d_x d_y
+
+// Euler-Lagrange gradient and FP64 energy density of theory TH (p: theory parameters).
+template <class T, int TH>
+__device__ __forceinline__ void el_gradient(const Jet<T> (&J)[4], const double (&p)[4], T (&G)[4]) {
+  if (TH == kAH) ah_el_gradient<T>(J, (T)p[0], G);
+  else if (TH == kCM) cm_el_gradient<T>(J, (T)p[0], (T)p[1], (T)p[2], (T)p[3], G);
+  else bs_el_gradient<T>(J, (T)(p[0] * p[0]), (T)p[1], G);
+}
+
+template <int TH>
+__device__ __forceinline__ double density(const Jet<double> (&J)[4], const double (&p)[4]) {
+  if (TH == kAH) return ah_density<double>(J, p[0]);
+  if (TH == kCM) return cm_density<double>(J, p[0], p[1], p[2], p[3]);
+  return bs_density<double>(J, p[0] * p[0], p[1]);
+}
+
 }  // namespace ss

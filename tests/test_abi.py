@@ -61,8 +61,10 @@ def test_theory_registry_names_and_aliases(L):
         assert ss.ss_theory_id(name) == ss.SS_THEORY_AH
     for name in ["chiral_magnet", "Chiral magnet", "CM"]:
         assert ss.ss_theory_id(name) == ss.SS_THEORY_CM
-    assert ss.ss_theory_id("baby_skyrme") < 0
-    assert ss.ss_components("GL") == 4 and ss.ss_components("CM") == 3
+    for name in ["baby_skyrme", "Baby Skyrme", "BS"]:
+        assert ss.ss_theory_id(name) == ss.SS_THEORY_BS
+    assert ss.ss_theory_id("bose_einstein") < 0
+    assert ss.ss_components("GL") == 4 and ss.ss_components("CM") == 3 and ss.ss_components("BS") == 3
 
 
 def test_workspace_bytes_grow_with_size_and_dtype(L):

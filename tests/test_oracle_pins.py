@@ -13,9 +13,10 @@ import pytest
 
 from paper_2603_24370_amd import inputs as I
 
-AH, CM = "abelian_higgs", "chiral_magnet"
+AH, CM, BS = "abelian_higgs", "chiral_magnet", "baby_skyrme"
 P_AH = [1.0]
 P_CM = [1.0, 1.0, 0.1, 0.6]
+P_BS = [1.0, 0.1]  # kappa, mu^2
 
 
 def _rand_field(rng, C, Nx, Ny, scale=1.0):
@@ -204,9 +205,61 @@ def test_cm_energy_converges_to_continuum(orc):
     assert errs[0] / errs[1] > 12.0, errs
 
 
+def test_bs_energy_converges_to_continuum(orc):
+    """E_h of a smooth unit texture tends to the continuum Baby Skyrme energy of Tab. 1
+    (standard potential) at O(h^4); the Skyrme term is written here as
+    kappa^2/4 sum_ij |d_i m x d_j m|^2 over both orders of i, j."""
+    kappa, mu2 = 1.0, 0.1
+
+    def fld(x, y, sp):
+        r2 = x * x + y * y
+        g = 2 * sp.exp(-r2 / 2)
+        m1, m2, m3 = x * g, y * g + 0.3 * sp.exp(-r2), 1 - 2 * sp.exp(-r2)
+        mn = sp.sqrt(m1 ** 2 + m2 ** 2 + m3 ** 2)
+        n = [m1 / mn, m2 / mn, m3 / mn]
+        d = [[sp.diff(c, v) for c in n] for v in (x, y)]
+        sk = 0
+        for i in range(2):
+            for j in range(2):
+                cr = sp.Matrix(d[i]).cross(sp.Matrix(d[j]))
+                sk += cr.dot(cr)
+        grad2 = sum(v * v for row in d for v in row)
+        return n, grad2 / 2 + kappa ** 2 / 4 * sk + mu2 * (1 - n[2])
+
+    box = 10.0
+    cont, phis = _continuum_energy(BS, [80, 160], box, fld)
+    errs = [abs(orc.energy(BS, p, box / (p.shape[2] - 4), [kappa, mu2]) - cont) for p in phis]
+    assert errs[1] < 2e-4 * abs(cont)
+    assert errs[0] / errs[1] > 12.0, errs
+
+
+def test_bs_isospin_and_quarter_turn_invariance(orc):
+    """The Baby Skyrme energy is invariant under a rotation of m about e_3 (the standard
+    potential depends on m_3 only) and under a quarter turn of the lattice alone."""
+    rng = np.random.default_rng(12)
+    n = I.renormalise_interior(_rand_field(rng, 3, 11, 11))
+    E = orc.energy(BS, n, 0.3, P_BS)
+    a = 0.7
+    r = n.copy()
+    r[0], r[1] = math.cos(a) * n[0] - math.sin(a) * n[1], math.sin(a) * n[0] + math.cos(a) * n[1]
+    assert orc.energy(BS, r, 0.3, P_BS) == pytest.approx(E, rel=1e-12)
+    assert orc.energy(BS, np.ascontiguousarray(np.rot90(n, 1, axes=(1, 2))), 0.3, P_BS) == pytest.approx(E, rel=1e-12)
+
+
+def test_bs_energy_bounds_the_charge(orc):
+    """For unit fields 1/2 |D m|^2 >= |m . (D_1 m x D_2 m)| at every site, and the Skyrme
+    term and the potential are non-negative, so E_h >= 4 pi |Q_FD|; the skyrmion
+    ansatz carries an integer Berg-Luescher charge."""
+    n = I.renormalise_interior(I.cm_skyrmion_ansatz(64, 64, 0.2, R=1.5, gamma=0.0) + I.noise(4, 3, 64, 64, 1e-2))
+    obs = orc.observables(BS, n, 0.2, P_BS)
+    assert abs(obs["Q_bl"] - round(obs["Q_bl"])) < 1e-12 and abs(round(obs["Q_bl"])) == 1
+    assert obs["E"] >= 4 * math.pi * abs(obs["Q_fd"])
+    assert obs["E"] == pytest.approx(orc.energy(BS, n, 0.2, P_BS), rel=1e-13)
+
+
 # ----------------------------------------------------------------- gradients
 
-@pytest.mark.parametrize("theory,C,params", [(AH, 4, [0.7]), (CM, 3, [1.3, 0.8, 0.1, 0.6])])
+@pytest.mark.parametrize("theory,C,params", [(AH, 4, [0.7]), (CM, 3, [1.3, 0.8, 0.1, 0.6]), (BS, 3, [1.3, 0.4])])
 def test_exact_gradient_matches_complex_step(orc, theory, C, params):
     """G = h^-2 dE_h/dphi at every interior site and component (complex step, eps = 1e-30)."""
     rng = np.random.default_rng(1)
@@ -223,7 +276,7 @@ def test_exact_gradient_matches_complex_step(orc, theory, C, params):
                 assert abs(g - G[c, j + 2, i + 2]) <= 1e-13 * scale
 
 
-@pytest.mark.parametrize("theory,C,params", [(AH, 4, [1.0]), (CM, 3, P_CM)])
+@pytest.mark.parametrize("theory,C,params", [(AH, 4, [1.0]), (CM, 3, P_CM), (BS, 3, [0.8, 0.2])])
 def test_exact_gradient_matches_central_differences(orc, theory, C, params):
     rng = np.random.default_rng(2)
     Nx, Ny, h, eps = 6, 6, 0.25, 1e-6
@@ -257,6 +310,23 @@ def _sympy_el(theory, params):
         B = dx[3] - dy[2]
         W = 1 - s[0] ** 2 - s[1] ** 2
         e = (P1 ** 2 + Q1 ** 2 + P2 ** 2 + Q2 ** 2) / 2 + B ** 2 / 2 + lam / 8 * W ** 2
+    elif theory == BS:
+        kappa, mu2 = params
+        n1 = 0.3 + 0.4 * x - 0.1 * y ** 2 + 0.02 * x ** 3 * y
+        n2 = -0.2 + 0.3 * y + 0.1 * x * y - 0.03 * x ** 4
+        n3 = 0.8 - 0.05 * x ** 2 + 0.04 * y ** 3 + 0.01 * x * y ** 3
+        comps = [n1, n2, n3]
+        s = sp.symbols("s0:3")
+        dx = sp.symbols("dx0:3")
+        dy = sp.symbols("dy0:3")
+        # Tab. 1: 1/2 |grad m|^2 + kappa^2/4 sum_ij |d_i m x d_j m|^2 + mu^2 (1 - m_3)
+        d = [dx, dy]
+        sk = 0
+        for i in range(2):
+            for j in range(2):
+                cr = sp.Matrix(d[i]).cross(sp.Matrix(d[j]))
+                sk += cr.dot(cr)
+        e = sum(v * v for v in dx) / 2 + sum(v * v for v in dy) / 2 + kappa ** 2 / 4 * sk + mu2 * (1 - s[2])
     else:
         J, D, K, Bz = params
         n1 = 0.3 + 0.4 * x - 0.1 * y ** 2 + 0.02 * x ** 3 * y
@@ -283,7 +353,7 @@ def _sympy_el(theory, params):
     return [sp.lambdify((x, y), c, "numpy") for c in comps], el
 
 
-@pytest.mark.parametrize("theory,params", [(AH, [0.9]), (CM, [1.2, 0.7, 0.15, 0.4])])
+@pytest.mark.parametrize("theory,params", [(AH, [0.9]), (CM, [1.2, 0.7, 0.15, 0.4]), (BS, [1.1, 0.3])])
 def test_el_gradient_equals_continuum_functional_derivative(orc, theory, params):
     """For fields of degree <= 4 in each variable the stencils of eq. (1)-(2) are
     exact, so the Euler-Lagrange form must equal the continuum functional
