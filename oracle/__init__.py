@@ -19,7 +19,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-THEORIES = {"abelian_higgs": 0, "chiral_magnet": 1, "toy_harmonic": 2, "toy_offset": 3, "baby_skyrme": 4}
+THEORIES = {"abelian_higgs": 0, "chiral_magnet": 1, "toy_harmonic": 2, "toy_offset": 3, "baby_skyrme": 4,
+            # chiral magnet with a second DMI coefficient and demagnetisation:
+            # params {J, D, K, B, Dy, mu_d} (Dy = D bulk, -D Heusler; mu_d = 0: no demagnetisation)
+            "chiral_magnet_ext": 5}
 COURANT = 0.5  # dt = C * h with the default C of Sec. 3.1
 GRAD_EXACT = 0  # G = h^-2 dE_h/dphi
 GRAD_EL = 1     # continuum Euler-Lagrange expression evaluated with eq. (1)-(2)
@@ -64,6 +67,7 @@ def lib():
         L.or_observables_ah.argtypes = [i, i, d, dp, dp, dp]
         L.or_observables_cm.argtypes = [i, i, d, dp, dp, dp]
         L.or_observables_unit.argtypes = [i, i, i, d, dp, dp, dp]
+        L.or_poisson.argtypes = [i, i, d, dp, dp]
         _lib = L
     return _lib
 
@@ -161,6 +165,16 @@ def minimise(theory, phi, h, params, grad_tol=1e-6, rel_e_tol=0.0, window=0, max
                     "converged": bool(info[4]), "reason": int(info[5])}
 
 
+def poisson(rhs, h) -> np.ndarray:
+    """psi with Laplace_h psi = rhs on the interior ((Ny, Nx) arrays), eq. (2) Laplacian,
+    psi = 0 outside the interior (conjugate gradients to 1e-14)."""
+    rhs = _arr(rhs)
+    Ny, Nx = rhs.shape
+    out = np.zeros_like(rhs)
+    lib().or_poisson(Nx, Ny, h, _p(rhs), _p(out))
+    return out
+
+
 def observables(theory, phi, h, params) -> dict:
     phi, p = _arr(phi), _arr(params)
     Nx, Ny = _dims(phi)
@@ -174,4 +188,4 @@ def observables(theory, phi, h, params) -> dict:
 
 
 __all__ = ["build", "lib", "energy", "energy_density", "energy_complex", "gradient", "acceleration",
-           "flow", "minimise", "observables", "deriv_at", "THEORIES", "COURANT", "GRAD_EXACT", "GRAD_EL", "SCHEMES"]
+           "flow", "minimise", "observables", "deriv_at", "poisson", "THEORIES", "COURANT", "GRAD_EXACT", "GRAD_EL", "SCHEMES"]

@@ -48,7 +48,7 @@
 
 namespace {
 
-enum Theory { TH_AH = 0, TH_CM = 1, TH_TOY = 2, TH_TOY_OFFSET = 3, TH_BS = 4 };
+enum Theory { TH_AH = 0, TH_CM = 1, TH_TOY = 2, TH_TOY_OFFSET = 3, TH_BS = 4, TH_CMX = 5 };
 
 int n_components(int theory) {
   switch (theory) {
@@ -57,6 +57,7 @@ int n_components(int theory) {
     case TH_TOY: return 1;  // one real scalar per site
     case TH_TOY_OFFSET: return 1;
     case TH_BS: return 3;   // m_1, m_2, m_3
+    case TH_CMX: return 3;  // chiral magnet with a general DMI and demagnetisation
   }
   return -1;
 }
@@ -156,33 +157,34 @@ void ah_partials(const Jet<double>& J, double lambda, double g[4], double F[2][4
   F[1][0] = Re2; F[1][1] = Im2; F[1][2] = -B;  F[1][3] = 0.0;
 }
 
-// --- Chiral magnet (eq. (5) without the demagnetising term) -----------------
-// e = J/2 sum_k |D_k n|^2 + D sum_k e_k . (n x D_k n) + K (1 - n_3^2) + B (1 - n_3),
-// bulk DMI vectors d_k = e_k for k = 1, 2 (there is no z-derivative in 2-D).
+// --- Chiral magnet (eq. (5); the demagnetising term is added below) --------
+// e = J/2 sum_k |D_k n|^2 + D sum_k d_k . (n x D_k n) + K (1 - n_3^2) + B (1 - n_3),
+// DMI vectors for k = 1, 2 (there is no z-derivative in 2-D): bulk d_k = e_k, or the
+// Heusler (D_2d) pair d_1 = e_1, d_2 = -e_2; Dy is D times the sign of d_2 . e_2.
 template <class T>
-T cm_density(const Jet<T>& Jt, double J, double D, double K, double Bz) {
+T cm_density(const Jet<T>& Jt, double J, double D, double K, double Bz, double Dy) {
   const T* n = Jt.f;
   T ex = 0.0;
   for (int k = 0; k < 2; ++k)
     for (int c = 0; c < 3; ++c) ex += Jt.d[k][c] * Jt.d[k][c];
   // e_1 . (n x d_1 n) = n_2 d_1 n_3 - n_3 d_1 n_2;  e_2 . (n x d_2 n) = n_3 d_2 n_1 - n_1 d_2 n_3
-  T dmi = (n[1] * Jt.d[0][2] - n[2] * Jt.d[0][1]) + (n[2] * Jt.d[1][0] - n[0] * Jt.d[1][2]);
-  return 0.5 * J * ex + D * dmi + K * (1.0 - n[2] * n[2]) + Bz * (1.0 - n[2]);
+  T dmi = D * (n[1] * Jt.d[0][2] - n[2] * Jt.d[0][1]) + Dy * (n[2] * Jt.d[1][0] - n[0] * Jt.d[1][2]);
+  return 0.5 * J * ex + dmi + K * (1.0 - n[2] * n[2]) + Bz * (1.0 - n[2]);
 }
 
-void cm_partials(const Jet<double>& Jt, double J, double D, double K, double Bz, double g[4],
+void cm_partials(const Jet<double>& Jt, double J, double D, double K, double Bz, double Dy, double g[4],
                  double F[2][4]) {
   const double* n = Jt.f;
-  g[0] = -D * Jt.d[1][2];
+  g[0] = -Dy * Jt.d[1][2];
   g[1] = D * Jt.d[0][2];
-  g[2] = -D * Jt.d[0][1] + D * Jt.d[1][0] - 2.0 * K * n[2] - Bz;
+  g[2] = -D * Jt.d[0][1] + Dy * Jt.d[1][0] - 2.0 * K * n[2] - Bz;
   g[3] = 0.0;
   F[0][0] = J * Jt.d[0][0];
   F[0][1] = J * Jt.d[0][1] - D * n[2];
   F[0][2] = J * Jt.d[0][2] + D * n[1];
-  F[1][0] = J * Jt.d[1][0] + D * n[2];
+  F[1][0] = J * Jt.d[1][0] + Dy * n[2];
   F[1][1] = J * Jt.d[1][1];
-  F[1][2] = J * Jt.d[1][2] - D * n[0];
+  F[1][2] = J * Jt.d[1][2] - Dy * n[0];
   F[0][3] = F[1][3] = 0.0;
 }
 
@@ -236,7 +238,8 @@ template <class T>
 T density(int theory, const Jet<T>& Jt, const double* p) {
   switch (theory) {
     case TH_AH: return ah_density(Jt, p[0]);
-    case TH_CM: return cm_density(Jt, p[0], p[1], p[2], p[3]);
+    case TH_CM: return cm_density(Jt, p[0], p[1], p[2], p[3], p[1]);
+    case TH_CMX: return cm_density(Jt, p[0], p[1], p[2], p[3], p[4]);
     case TH_TOY_OFFSET: return toy_density(Jt, p[0]) + p[1];
     case TH_BS: return bs_density(Jt, p[0], p[1]);
     default: return toy_density(Jt, p[0]);
@@ -247,7 +250,8 @@ void partials(int theory, const Jet<double>& Jt, const double* p, double g[4], d
   for (int c = 0; c < 4; ++c) g[c] = F[0][c] = F[1][c] = 0.0;
   switch (theory) {
     case TH_AH: ah_partials(Jt, p[0], g, F); break;
-    case TH_CM: cm_partials(Jt, p[0], p[1], p[2], p[3], g, F); break;
+    case TH_CM: cm_partials(Jt, p[0], p[1], p[2], p[3], p[1], g, F); break;
+    case TH_CMX: cm_partials(Jt, p[0], p[1], p[2], p[3], p[4], g, F); break;
     case TH_BS: bs_partials(Jt, p[0], p[1], g, F); break;
     default: g[0] = p[0] * Jt.f[0]; break;
   }
@@ -300,14 +304,14 @@ void ah_el(const ELJet& J, double lambda, double G[4]) {
   G[3] = P2 * p2 - Q2 * p1 - (J.dd[0][3] - J.dxy[2]);
 }
 
-// Chiral magnet: G = -J lap n + 2 D sum_k (d_k n x e_k) - (2 K n3 + B) e3.
-void cm_el(const ELJet& Jt, double J, double D, double K, double Bz, double G[4]) {
+// Chiral magnet: G = -J lap n + 2 sum_k D_k (d_k n x e_k) - (2 K n3 + B) e3, D_1 = D, D_2 = Dy.
+void cm_el(const ELJet& Jt, double J, double D, double K, double Bz, double Dy, double G[4]) {
   double lap[3];
   for (int c = 0; c < 3; ++c) lap[c] = Jt.dd[0][c] + Jt.dd[1][c];
   // d_1 n x e_1 = (0, d1n3, -d1n2);  d_2 n x e_2 = (-d2n3, 0, d2n1)
-  G[0] = -J * lap[0] + 2.0 * D * (-Jt.d[1][2]);
+  G[0] = -J * lap[0] + 2.0 * Dy * (-Jt.d[1][2]);
   G[1] = -J * lap[1] + 2.0 * D * (Jt.d[0][2]);
-  G[2] = -J * lap[2] + 2.0 * D * (-Jt.d[0][1] + Jt.d[1][0]) - 2.0 * K * Jt.f[2] - Bz;
+  G[2] = -J * lap[2] + 2.0 * (-D * Jt.d[0][1] + Dy * Jt.d[1][0]) - 2.0 * K * Jt.f[2] - Bz;
   G[3] = 0.0;
 }
 
@@ -343,21 +347,6 @@ void bs_el(const ELJet& J, double kappa, double mu2, double G[4]) {
   G[3] = 0.0;
 }
 
-void gradient_el(int theory, const Lat& L, const double* p, const double* phi, double* G) {
-  int C = n_components(theory);
-  std::memset(G, 0, sizeof(double) * C * L.plane());
-  for (int j = 0; j < L.Ny; ++j)
-    for (int i = 0; i < L.Nx; ++i) {
-      ELJet J = el_jet_at(phi, L, C, j, i);
-      double g[4] = {0.0, 0.0, 0.0, 0.0};
-      if (theory == TH_AH) ah_el(J, p[0], g);
-      else if (theory == TH_CM) cm_el(J, p[0], p[1], p[2], p[3], g);
-      else if (theory == TH_BS) bs_el(J, p[0], p[1], g);
-      else g[0] = p[0] * J.f[0];
-      for (int c = 0; c < C; ++c) G[L.at(c, j, i)] = g[c];
-    }
-}
-
 // Neumaier-compensated sum.
 struct KSum {
   double s = 0.0, c = 0.0;
@@ -369,12 +358,144 @@ struct KSum {
   double value() const { return s + c; }
 };
 
+// --- Demagnetisation (eq. (5)-(6)) ------------------------------------------
+// In units where mu_0 M_s^2 is the coefficient mu_d, the magnetostatic potential psi
+// solves Laplace(psi) = div n (the in-plane divergence; no z-dependence in 2-D) with
+// psi = 0 outside the interior, and the energy gains mu_d/2 |grad psi|^2 per site.
+// Discretely: div and grad by eq. (1), the Laplacian by eq. (2) along each axis.
+
+// One plane of scalars on the padded lattice (component 0 of a 1-component layout).
+struct Plane {
+  Lat L;
+  std::vector<double> v;
+  explicit Plane(const Lat& l) : L(l), v(l.plane(), 0.0) {}
+  double& at(int j, int i) { return v[L.at(0, j, i)]; }
+  double at(int j, int i) const { return v[L.at(0, j, i)]; }
+};
+
+// eq. (1) derivative of a plane along an axis at an interior site (the plane is zero outside).
+double plane_deriv(const Plane& P, int j, int i, int axis) { return deriv(P.v.data(), P.L, 0, j, i, axis); }
+
+// y = -Laplace_h(x) on the interior (x zero outside), eq. (2) along both axes.
+void neg_laplacian(const Plane& x, Plane& y) {
+  for (int j = 0; j < x.L.Ny; ++j)
+    for (int i = 0; i < x.L.Nx; ++i)
+      y.at(j, i) = -(deriv2(x.v.data(), x.L, 0, j, i, 0) + deriv2(x.v.data(), x.L, 0, j, i, 1));
+}
+
+double dot_interior(const Plane& a, const Plane& b) {
+  KSum s;
+  for (int j = 0; j < a.L.Ny; ++j)
+    for (int i = 0; i < a.L.Nx; ++i) s.add(a.at(j, i) * b.at(j, i));
+  return s.value();
+}
+
+// Solve Laplace_h(psi) = rhs by conjugate gradients on the symmetric positive
+// definite -Laplace_h (zero outside the interior), to a relative residual of 1e-14.
+void poisson_solve(const Plane& rhs, Plane& psi) {
+  const Lat& L = rhs.L;
+  Plane r(L), d(L), Ad(L);
+  std::fill(psi.v.begin(), psi.v.end(), 0.0);
+  for (int j = 0; j < L.Ny; ++j)
+    for (int i = 0; i < L.Nx; ++i) r.at(j, i) = -rhs.at(j, i);  // b of  (-Laplace) psi = -rhs
+  d = r;
+  double rr = dot_interior(r, r);
+  const double stop = 1e-28 * rr;
+  for (long it = 0; it < 20L * (L.Nx + L.Ny) + 1000 && rr > stop && rr > 0.0; ++it) {
+    neg_laplacian(d, Ad);
+    const double alpha = rr / dot_interior(d, Ad);
+    for (int j = 0; j < L.Ny; ++j)
+      for (int i = 0; i < L.Nx; ++i) {
+        psi.at(j, i) += alpha * d.at(j, i);
+        r.at(j, i) -= alpha * Ad.at(j, i);
+      }
+    const double rr1 = dot_interior(r, r);
+    for (int j = 0; j < L.Ny; ++j)
+      for (int i = 0; i < L.Nx; ++i) d.at(j, i) = r.at(j, i) + (rr1 / rr) * d.at(j, i);
+    rr = rr1;
+  }
+}
+
+// psi of a field n: Laplace_h psi = d_x n_1 + d_y n_2 (the halo of n holds the boundary values).
+void demag_potential(const Lat& L, const double* n, Plane& psi) {
+  Plane rhs(L);
+  for (int j = 0; j < L.Ny; ++j)
+    for (int i = 0; i < L.Nx; ++i) rhs.at(j, i) = deriv(n, L, 0, j, i, 0) + deriv(n, L, 1, j, i, 1);
+  poisson_solve(rhs, psi);
+}
+
+// mu_d / 2 h^2 sum |grad psi|^2
+double demag_energy(const Lat& L, double mu_d, const double* n) {
+  Plane psi(L);
+  demag_potential(L, n, psi);
+  KSum s;
+  for (int j = 0; j < L.Ny; ++j)
+    for (int i = 0; i < L.Nx; ++i) {
+      const double gx = plane_deriv(psi, j, i, 0), gy = plane_deriv(psi, j, i, 1);
+      s.add(gx * gx + gy * gy);
+    }
+  return 0.5 * mu_d * L.h * L.h * s.value();
+}
+
+bool has_demag(int theory, const double* p) { return theory == TH_CMX && p[5] != 0.0; }
+
+// Euler-Lagrange demagnetising force: mu_d (d_x psi, d_y psi, 0) added to G.
+void add_demag_el(const Lat& L, double mu_d, const double* n, double* G) {
+  Plane psi(L);
+  demag_potential(L, n, psi);
+  for (int j = 0; j < L.Ny; ++j)
+    for (int i = 0; i < L.Nx; ++i) {
+      G[L.at(0, j, i)] += mu_d * plane_deriv(psi, j, i, 0);
+      G[L.at(1, j, i)] += mu_d * plane_deriv(psi, j, i, 1);
+    }
+}
+
+// Exact derivative of the discrete demagnetising energy: with B_c the eq. (1)
+// derivatives restricted to the interior (antisymmetric), L the eq. (2) Laplacian and
+// M = B_x^T B_x + B_y^T B_y, E_d = mu_d/2 h^2 psi^T M psi and psi = L^-1 (B_x n_1 + B_y n_2),
+// so h^-2 dE_d/dn_c = mu_d B_c^T L^-1 M psi = -mu_d B_c chi with L chi = M psi.
+void add_demag_exact(const Lat& L, double mu_d, const double* n, double* G) {
+  Plane psi(L), gx(L), gy(L), Mpsi(L), chi(L);
+  demag_potential(L, n, psi);
+  for (int j = 0; j < L.Ny; ++j)
+    for (int i = 0; i < L.Nx; ++i) {
+      gx.at(j, i) = plane_deriv(psi, j, i, 0);
+      gy.at(j, i) = plane_deriv(psi, j, i, 1);
+    }
+  for (int j = 0; j < L.Ny; ++j)
+    for (int i = 0; i < L.Nx; ++i) Mpsi.at(j, i) = -(plane_deriv(gx, j, i, 0) + plane_deriv(gy, j, i, 1));
+  poisson_solve(Mpsi, chi);
+  for (int j = 0; j < L.Ny; ++j)
+    for (int i = 0; i < L.Nx; ++i) {
+      G[L.at(0, j, i)] += -mu_d * plane_deriv(chi, j, i, 0);
+      G[L.at(1, j, i)] += -mu_d * plane_deriv(chi, j, i, 1);
+    }
+}
+
+void gradient_el(int theory, const Lat& L, const double* p, const double* phi, double* G) {
+  int C = n_components(theory);
+  std::memset(G, 0, sizeof(double) * C * L.plane());
+  for (int j = 0; j < L.Ny; ++j)
+    for (int i = 0; i < L.Nx; ++i) {
+      ELJet J = el_jet_at(phi, L, C, j, i);
+      double g[4] = {0.0, 0.0, 0.0, 0.0};
+      if (theory == TH_AH) ah_el(J, p[0], g);
+      else if (theory == TH_CM) cm_el(J, p[0], p[1], p[2], p[3], p[1], g);
+      else if (theory == TH_CMX) cm_el(J, p[0], p[1], p[2], p[3], p[4], g);
+      else if (theory == TH_BS) bs_el(J, p[0], p[1], g);
+      else g[0] = p[0] * J.f[0];
+      for (int c = 0; c < C; ++c) G[L.at(c, j, i)] = g[c];
+    }
+  if (has_demag(theory, p)) add_demag_el(L, p[5], phi, G);
+}
+
 double energy(int theory, const Lat& L, const double* p, const double* phi) {
   int C = n_components(theory);
   KSum s;
   for (int j = 0; j < L.Ny; ++j)
     for (int i = 0; i < L.Nx; ++i) s.add(density(theory, jet_at(phi, L, C, j, i), p));
-  return L.h * L.h * s.value();
+  const double e_demag = has_demag(theory, p) ? demag_energy(L, p[5], phi) : 0.0;
+  return L.h * L.h * s.value() + e_demag;
 }
 
 // G = h^-2 dE_h/dphi on interior sites (halo entries set to 0). Scatter form:
@@ -397,6 +518,7 @@ void gradient(int theory, const Lat& L, const double* p, const double* phi, doub
         }
       }
     }
+  if (has_demag(theory, p)) add_demag_exact(L, p[5], phi, G);
 }
 
 void normalise_interior(const Lat& L, double* n) {
@@ -419,7 +541,7 @@ void tangent_project(const Lat& L, const double* n, double* X) {
 }
 
 // Theories of a unit-vector field (chiral magnet, Baby Skyrme).
-bool unit_theory(int theory) { return theory == TH_CM || theory == TH_BS; }
+bool unit_theory(int theory) { return theory == TH_CM || theory == TH_BS || theory == TH_CMX; }
 
 // The force used by the flow: -G at the stage point; for the chiral magnet the
 // stage point is first put back on the unit sphere and -G is projected onto its
@@ -537,6 +659,18 @@ double or_deriv_at(const double* phi, int Nx, int Ny, double h, int C, int c, in
 
 double or_energy(int theory, int Nx, int Ny, double h, const double* p, const double* phi) {
   return energy(theory, Lat(Nx, Ny, h), p, phi);
+}
+
+// Solve Laplace_h psi = rhs (eq. (2) along each axis, psi = 0 outside the interior);
+// rhs and psi are (Ny, Nx) arrays of the interior.
+void or_poisson(int Nx, int Ny, double h, const double* rhs, double* psi) {
+  Lat L(Nx, Ny, h);
+  Plane r(L), x(L);
+  for (int j = 0; j < Ny; ++j)
+    for (int i = 0; i < Nx; ++i) r.at(j, i) = rhs[(long)j * Nx + i];
+  poisson_solve(r, x);
+  for (int j = 0; j < Ny; ++j)
+    for (int i = 0; i < Nx; ++i) psi[(long)j * Nx + i] = x.at(j, i);
 }
 
 // Energy density e at every interior site, written to dens[(Ny, Nx)].

@@ -17,6 +17,7 @@ AH, CM, BS = "abelian_higgs", "chiral_magnet", "baby_skyrme"
 P_AH = [1.0]
 P_CM = [1.0, 1.0, 0.1, 0.6]
 P_BS = [1.0, 0.1]  # kappa, mu^2
+CMX = "chiral_magnet_ext"  # {J, D, K, B, Dy, mu_d}: second DMI coefficient and demagnetisation
 
 
 def _rand_field(rng, C, Nx, Ny, scale=1.0):
@@ -259,7 +260,8 @@ def test_bs_energy_bounds_the_charge(orc):
 
 # ----------------------------------------------------------------- gradients
 
-@pytest.mark.parametrize("theory,C,params", [(AH, 4, [0.7]), (CM, 3, [1.3, 0.8, 0.1, 0.6]), (BS, 3, [1.3, 0.4])])
+@pytest.mark.parametrize("theory,C,params", [(AH, 4, [0.7]), (CM, 3, [1.3, 0.8, 0.1, 0.6]), (BS, 3, [1.3, 0.4]),
+                                            (CMX, 3, [1.3, 0.8, 0.1, 0.6, -0.8, 0.0])])
 def test_exact_gradient_matches_complex_step(orc, theory, C, params):
     """G = h^-2 dE_h/dphi at every interior site and component (complex step, eps = 1e-30)."""
     rng = np.random.default_rng(1)
@@ -276,7 +278,9 @@ def test_exact_gradient_matches_complex_step(orc, theory, C, params):
                 assert abs(g - G[c, j + 2, i + 2]) <= 1e-13 * scale
 
 
-@pytest.mark.parametrize("theory,C,params", [(AH, 4, [1.0]), (CM, 3, P_CM), (BS, 3, [0.8, 0.2])])
+@pytest.mark.parametrize("theory,C,params", [(AH, 4, [1.0]), (CM, 3, P_CM), (BS, 3, [0.8, 0.2]),
+                                            (CMX, 3, [1.1, 0.9, 0.2, 0.5, -0.9, 0.0]),
+                                            (CMX, 3, [1.1, 0.9, 0.2, 0.5, -0.9, 1.3])])
 def test_exact_gradient_matches_central_differences(orc, theory, C, params):
     rng = np.random.default_rng(2)
     Nx, Ny, h, eps = 6, 6, 0.25, 1e-6
@@ -328,7 +332,8 @@ def _sympy_el(theory, params):
                 sk += cr.dot(cr)
         e = sum(v * v for v in dx) / 2 + sum(v * v for v in dy) / 2 + kappa ** 2 / 4 * sk + mu2 * (1 - s[2])
     else:
-        J, D, K, Bz = params
+        J, D, K, Bz = params[:4]
+        Dy = params[4] if len(params) > 4 else D
         n1 = 0.3 + 0.4 * x - 0.1 * y ** 2 + 0.02 * x ** 3 * y
         n2 = -0.2 + 0.3 * y + 0.1 * x * y - 0.03 * x ** 4
         n3 = 0.8 - 0.05 * x ** 2 + 0.04 * y ** 3 + 0.01 * x * y ** 3
@@ -337,8 +342,10 @@ def _sympy_el(theory, params):
         dx = sp.symbols("dx0:3")
         dy = sp.symbols("dy0:3")
         ex = sum(d * d for d in dx) + sum(d * d for d in dy)
-        dmi = (s[1] * dx[2] - s[2] * dx[1]) + (s[2] * dy[0] - s[0] * dy[2])
-        e = J / 2 * ex + D * dmi + K * (1 - s[2] ** 2) + Bz * (1 - s[2])
+        # sum_k D_k d_k . (n x d_k n) with d_1 = e_1 and d_2 = +-e_2 (D_2 = Dy)
+        n = sp.Matrix(s)
+        dmi = D * sp.Matrix([1, 0, 0]).dot(n.cross(sp.Matrix(dx))) + Dy * sp.Matrix([0, 1, 0]).dot(n.cross(sp.Matrix(dy)))
+        e = J / 2 * ex + dmi + K * (1 - s[2] ** 2) + Bz * (1 - s[2])
     sub = {}
     for k, c in enumerate(comps):
         sub[s[k]] = c
@@ -353,7 +360,8 @@ def _sympy_el(theory, params):
     return [sp.lambdify((x, y), c, "numpy") for c in comps], el
 
 
-@pytest.mark.parametrize("theory,params", [(AH, [0.9]), (CM, [1.2, 0.7, 0.15, 0.4]), (BS, [1.1, 0.3])])
+@pytest.mark.parametrize("theory,params", [(AH, [0.9]), (CM, [1.2, 0.7, 0.15, 0.4]), (BS, [1.1, 0.3]),
+                                           (CMX, [1.2, 0.7, 0.15, 0.4, -0.7, 0.0])])
 def test_el_gradient_equals_continuum_functional_derivative(orc, theory, params):
     """For fields of degree <= 4 in each variable the stencils of eq. (1)-(2) are
     exact, so the Euler-Lagrange form must equal the continuum functional
@@ -379,6 +387,108 @@ def test_el_and_exact_gradients_agree_to_fourth_order(orc):
         # compare away from the boundary layer where the exact form drops halo fluxes
         diffs.append(np.abs(ge - gl)[:, 8:-8, 8:-8].max())
     assert diffs[0] / diffs[1] > 12.0, diffs
+
+
+def test_poisson_solve_converges_at_fourth_order(orc):
+    """Laplace_h psi = Laplace(psi_exact) for a Gaussian psi_exact (zero to e^-36 at the
+    box edge): the discrete solution converges to psi_exact at O(h^4) (eq. (2))."""
+    errs = []
+    for N in (48, 96):
+        h = 12.0 / N
+        X, Y = I.grid(N, N, h)
+        X, Y = X[2:-2, 2:-2], Y[2:-2, 2:-2]
+        r2 = X * X + Y * Y
+        psi_ex = np.exp(-r2)
+        lap = (4 * r2 - 4) * np.exp(-r2)
+        errs.append(np.abs(orc.poisson(lap, h) - psi_ex).max())
+    assert errs[1] < 1e-4 and errs[0] / errs[1] > 14.0, errs
+
+
+def _eq1(f, axis, h):
+    """eq. (1) derivative of a plane (valid two sites in from its edges)."""
+    out = np.zeros_like(f)
+    if axis == 0:
+        out[:, 2:-2] = (f[:, :-4] - f[:, 4:] + 8 * (f[:, 3:-1] - f[:, 1:-3])) / (12 * h)
+    else:
+        out[2:-2, :] = (f[:-4, :] - f[4:, :] + 8 * (f[3:-1, :] - f[1:-3, :])) / (12 * h)
+    return out
+
+
+def test_demagnetisation_vanishes_for_divergence_free_fields(orc):
+    """n_1 = -D_y f, n_2 = D_x f has zero discrete divergence (the eq. (1) stencils
+    commute), so the potential and the demagnetising energy vanish; a texture with
+    divergence pays a positive energy."""
+    N, h, mu = 40, 0.25, 1.7
+    X, Y = I.grid(N + 4, N + 4, h)  # two more rings, so D f is known on the halo
+    fpl = np.exp(-(X * X + (Y - 0.3) ** 2) / 2.0)
+    n = np.zeros((3, N + 4, N + 4))
+    n[0] = -_eq1(fpl, 1, h)[2:-2, 2:-2]
+    n[1] = _eq1(fpl, 0, h)[2:-2, 2:-2]
+    n[2] = 1.0
+    p0, p1 = [1.0, 0.8, 0.1, 0.3, 0.8, 0.0], [1.0, 0.8, 0.1, 0.3, 0.8, mu]
+    E0, E1 = orc.energy(CMX, n, h, p0), orc.energy(CMX, n, h, p1)
+    assert abs(E1 - E0) <= 1e-12 * abs(E0)
+    m = n.copy()
+    m[0], m[1] = n[1], -n[0]  # the same field turned by 90 degrees: all divergence
+    assert orc.energy(CMX, m, h, p1) - orc.energy(CMX, m, h, p0) > 1e-3
+
+
+def test_demagnetising_force_euler_lagrange_agrees_with_exact_to_fourth_order(orc):
+    """mu_d grad psi (the Euler-Lagrange form) against the exact derivative of the discrete
+    demagnetising energy (pinned by central differences above) on a smooth Neel texture:
+    the difference tends to zero as h -> 0. It does so at about O(h^2.5), not O(h^4): the
+    potential is global, and the two Laplacians (eq. (2), against eq. (1) applied twice)
+    differ in the boundary layer, where the texture's dipole potential (~ 1/r) is not
+    small. A wrong sign or factor of the force would leave an O(1) difference."""
+    diffs, scale = [], []
+    p = [0.0, 0.0, 0.0, 0.0, 0.0, 1.0]  # demagnetisation alone
+    for N in (40, 80):
+        h = 10.0 / N
+        n = I.renormalise_interior(I.cm_skyrmion_ansatz(N, N, h, R=1.5, gamma=0.0, profile="gauss"))
+        ge = orc.gradient(CMX, n, h, p, mode=orc.GRAD_EXACT)
+        gl = orc.gradient(CMX, n, h, p, mode=orc.GRAD_EL)
+        diffs.append(np.abs(ge - gl)[:, 8:-8, 8:-8].max())
+        scale.append(np.abs(gl).max())
+    assert diffs[0] / diffs[1] > 4.0, diffs
+    assert diffs[1] < 1e-2 * scale[1], (diffs, scale)
+
+
+def test_bloch_and_neel_textures_under_demagnetisation(orc):
+    """A Bloch skyrmion (gamma = +-pi/2) has zero divergence in the continuum, so its
+    demagnetising energy is small (O(h^4) stencil residue); a Neel skyrmion (gamma = 0)
+    carries magnetic charge and pays for it."""
+    N, h = 80, 0.125
+    p0, p1 = [1.0, 0.0, 0.0, 0.0, 0.0, 0.0], [1.0, 0.0, 0.0, 0.0, 0.0, 1.0]
+    ed = {}
+    for name, g in (("bloch", math.pi / 2), ("neel", 0.0)):
+        n = I.renormalise_interior(I.cm_skyrmion_ansatz(N, N, h, R=1.5, gamma=g, profile="gauss"))
+        ed[name] = orc.energy(CMX, n, h, p1) - orc.energy(CMX, n, h, p0)
+    assert ed["neel"] > 0.5 and 0.0 <= ed["bloch"] < 1e-6 * ed["neel"], ed
+
+
+def test_heusler_dmi_favours_the_antiskyrmion(orc):
+    """With d_1 = e_1, d_2 = -e_2 (Dy = -D) the DMI energy of an antiskyrmion (vorticity -1,
+    helicity chosen below) is negative and equals the bulk DMI energy of the Bloch
+    skyrmion, while the skyrmion's Heusler DMI energy vanishes by symmetry."""
+    N, h, R = 96, 0.1, 2.0
+    D = 1.0
+    only_bulk, only_heusler = [0.0, D, 0.0, 0.0, D, 0.0], [0.0, D, 0.0, 0.0, -D, 0.0]
+    sk = I.renormalise_interior(I.cm_skyrmion_ansatz(N, N, h, R=R, gamma=-math.pi / 2))
+    X, Y = I.grid(N, N, h)
+    r, th = np.hypot(X, Y), np.arctan2(Y, X)
+    T = 2 * np.arctan2(R, r)
+    g = -math.pi / 2  # the lower-energy helicity (pi/2 gives +|E|)
+    anti = np.stack([np.sin(T) * np.cos(-th + g), np.sin(T) * np.sin(-th + g), np.cos(T)])
+    anti[:, :2, :] = anti[:, -2:, :] = anti[:, :, :2] = anti[:, :, -2:] = 0
+    anti[2, :2, :] = anti[2, -2:, :] = anti[2, :, :2] = anti[2, :, -2:] = 1
+    e_sk_bulk = orc.energy(CMX, sk, h, only_bulk)
+    e_sk_heus = orc.energy(CMX, sk, h, only_heusler)
+    e_anti_heus = orc.energy(CMX, anti, h, only_heusler)
+    assert e_sk_bulk < -1.0
+    assert abs(e_sk_heus) < 1e-9 * abs(e_sk_bulk)
+    assert e_anti_heus == pytest.approx(e_sk_bulk, rel=1e-3)
+    q = orc.observables(CMX, anti, h, only_heusler)["Q_bl"]
+    assert abs(q - round(q)) < 1e-10 and round(q) == 1
 
 
 # ---------------------------------------------------------------- integrator
