@@ -17,22 +17,34 @@
  *   - reductions: energy, convergence norm and observables are reduced on the
  *     GPU (Sec. 3.3), here entirely on the device in FP64.
  *
- * Theories (Tab. 1; eq. (5) without demagnetisation):
+ * Theories (Tab. 1; eq. (5)-(6)):
  *   "abelian_higgs" (aliases "Abelian Higgs", "Ginzburg-Landau", "GL", "AH"):
  *       C = 4 components (psi_1, psi_2, A_1, A_2), u = e = 1, D = grad - iA,
  *       e = 1/2 |D psi|^2 + 1/2 (d_1 A_2 - d_2 A_1)^2 + lambda/8 (1 - |psi|^2)^2.
  *       params.f = {lambda [, courant]}.
  *   "chiral_magnet" (aliases "Chiral magnet", "CM"):
- *       C = 3 components (n_1, n_2, n_3), |n| = 1, bulk DMI d_k = e_k,
- *       e = J/2 |grad n|^2 + D sum_k e_k.(n x d_k n) + K (1 - n_3^2) + B (1 - n_3).
- *       params.f = {J, D, K, B [, courant]}.
+ *       C = 3 components (n_1, n_2, n_3), |n| = 1, DMI vectors d_1 = e_1 and
+ *       d_2 = e_2 (SS_DMI_BULK) or d_2 = -e_2 (SS_DMI_HEUSLER, Sec. 4.2),
+ *       e = J/2 |grad n|^2 + D sum_k d_k.(n x d_k n) + K (1 - n_3^2) + B (1 - n_3)
+ *           [+ mu_d/2 |grad psi|^2 with demagnetisation].
+ *       params.f = {J, D, K, B [, courant]}, or {J, D, K, B, mu_d [, courant]}
+ *       with demagnetisation. The demagnetising potential psi of a field n
+ *       (eq. (6), in units where mu_0 M_s^2 is mu_d) solves
+ *       Laplace_h psi = d_x n_1 + d_y n_2 with psi = 0 outside the interior
+ *       (eq. (1) divergence, eq. (2) Laplacian); it is solved on the device by
+ *       multigrid-preconditioned conjugate gradients for every field the flow
+ *       evaluates (see ss_set_demag_iters). Demagnetisation needs the
+ *       Euler-Lagrange gradient and the SS_PLAN_STAGES launch plan, single
+ *       contexts (no batches), and the workspace of ss_workspace_bytes_for.
  *   "baby_skyrme" (aliases "Baby Skyrme", "BS"):
  *       C = 3 components (m_1, m_2, m_3), |m| = 1, the standard potential,
  *       e = 1/2 |grad m|^2 + kappa^2/4 sum_ij |d_i m x d_j m|^2 + mu^2 (1 - m_3).
  *       params.f = {kappa, mu^2 [, courant]}. Single contexts only (no batches).
- *   params.i (optional) = {grad_mode}: SS_GRAD_EL (default) evaluates the
- *   continuum Euler-Lagrange derivative with eq. (1)-(2); SS_GRAD_EXACT uses
- *   h^-2 dE_h/dphi, the exact derivative of the discrete energy.
+ *   params.i (optional, ni <= 3) = {grad_mode, dmi_kind, demag}:
+ *   grad_mode SS_GRAD_EL (default) evaluates the continuum Euler-Lagrange
+ *   derivative with eq. (1)-(2); SS_GRAD_EXACT uses h^-2 dE_h/dphi, the exact
+ *   derivative of the discrete energy. dmi_kind SS_DMI_BULK (default) or
+ *   SS_DMI_HEUSLER, and demag 0 (default) or 1, apply to the chiral magnet only.
  *
  * Memory layout of every field array passed in or out: planar, component
  * major, rows of x fastest, shape (C, Ny + 4, Nx + 4) including the halo,
@@ -86,6 +98,10 @@ extern "C" {
 /* gradient forms */
 #define SS_GRAD_EL 0
 #define SS_GRAD_EXACT 1
+
+/* DMI vectors of the chiral magnet (params.i[1]) */
+#define SS_DMI_BULK 0
+#define SS_DMI_HEUSLER 1
 
 /* stop reasons reported by ss_minimise */
 #define SS_STOP_NONE 0
@@ -165,13 +181,21 @@ int ss_theory_id(const char* name);
 /* Number of field components of a theory, or SS_ETHEORY. */
 int ss_components(const char* theory);
 
-/* Workspace bytes ss_create needs for this theory, grid and dtype. */
+/* Workspace bytes ss_create needs for this theory, grid and dtype, without
+ * demagnetisation. */
 int ss_workspace_bytes(const char* theory, int Nx, int Ny, int dtype, size_t* bytes);
 
+/* Workspace bytes ss_create needs for these parameters: ss_workspace_bytes
+ * plus, with demagnetisation, the solver's stage point (C planes of the
+ * dtype) and its FP64 planes (seven on the lattice, three per coarser level;
+ * about 75 bytes per site in all for FP32). Validates params as ss_create
+ * does. */
+int ss_workspace_bytes_for(const char* theory, int Nx, int Ny, const ss_params* params, int dtype, size_t* bytes);
+
 /* Create a context. Parameters are validated and resolved before any device
- * work (Sec. 3.1). workspace: device memory of at least ss_workspace_bytes,
- * 256-byte aligned. stream: a hipStream_t or NULL. Requires 8 <= Nx, Ny <=
- * 65536 and h > 0. */
+ * work (Sec. 3.1). workspace: device memory of at least ss_workspace_bytes_for
+ * (= ss_workspace_bytes without demagnetisation), 256-byte aligned. stream: a
+ * hipStream_t or NULL. Requires 8 <= Nx, Ny <= 65536 and h > 0. */
 int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype,
               void* workspace, size_t ws_bytes, void* stream, ss_ctx** out);
 
@@ -197,8 +221,10 @@ int ss_set_field(ss_ctx* ctx, const void* field);
  *       A   = sum_k w_k (1 - exp(-r_k^2)) / r_k^2 (-(y - y_k), x - x_k);
  *     the halo holds the pure-gauge vacuum psi = exp(i sum w_k theta_k),
  *     A = sum_k w_k grad theta_k.
- *   Chiral magnet and Baby Skyrme, kind SS_ANSATZ_SKYRMION: n = 1, xy = centre, shape = {R, gamma}:
- *       n = (sin T cos(theta + gamma), sin T sin(theta + gamma), cos T),
+ *   Chiral magnet and Baby Skyrme, kind SS_ANSATZ_SKYRMION: n = 1, xy = centre, shape = {R, gamma},
+ *     w = {m} (vorticity, a nonzero integer; NULL = 1; m = -1 is the
+ *     antiskyrmion of Sec. 4.2):
+ *       n = (sin T cos(m theta + gamma), sin T sin(m theta + gamma), cos T),
  *       T = 2 atan(R / r) (Belavin-Polyakov); halo n = e_3.
  * Noise: if noise_amp > 0, every interior component gets noise_amp * (2u - 1),
  * u the SplitMix64 counter draw of (seed, c, j, i) (same generator as the
@@ -355,6 +381,15 @@ int ss_get_plan(ss_ctx* ctx);
 int ss_set_integrator(ss_ctx* ctx, int integ);
 int ss_get_integrator(ss_ctx* ctx);
 
+/* Conjugate-gradient iterations per solve of the demagnetising potential
+ * (Sec. 4.2, eq. (6)): iters_flow for every field a flow step evaluates (the
+ * solve starts from the last potential, so a few iterations track the slowly
+ * moving field; default 2), iters_eval for ss_energy_grad and ss_observables
+ * (default 40; each iteration lowers the residual about five-fold). Each
+ * iteration is one multigrid V-cycle and one operator application. Only for
+ * contexts with demagnetisation (else SS_EINVAL); values in [1, 1000]. */
+int ss_set_demag_iters(ss_ctx* ctx, int iters_flow, int iters_eval);
+
 /* Tile shapes of the stage kernels. The library carries ss_tile_count()
  * compiled shapes (a workgroup covers TX x TY sites, each thread RY rows of
  * one column); under a fused plan the shape applies to P1. ss_set_tile selects
@@ -366,7 +401,7 @@ int ss_get_integrator(ss_ctx* ctx);
  * plan is read with ss_get_plan). It overwrites the field: call ss_set_field
  * or ss_init_ansatz afterwards. If the environment variable SS_AUTOTUNE_CACHE
  * names a file, ss_autotune first looks the problem (theory, dtype, gradient
- * form, Nx, Ny, compiled shapes) up there and, if found, applies the stored
+ * form, Nx, Ny, compiled shapes, integrator, demagnetisation) up there and, if found, applies the stored
  * plan and tile without timing (ms_out all -1, the field untouched); otherwise
  * it times as above and appends its choice to the file. The environment
  * variable SS_TILE selects the initial shape of new contexts. */

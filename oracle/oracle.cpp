@@ -877,7 +877,8 @@ void or_observables_unit(int theory, int Nx, int Ny, double h, const double* p, 
       sBL.add(tri(a, b, c));
       sBL.add(tri(a, c, d));
     }
-  out[0] = h * h * sE.value();
+  // the energy is that of eq. (5), demagnetising term included
+  out[0] = h * h * sE.value() + (has_demag(theory, p) ? demag_energy(L, p[5], phi) : 0.0);
   out[1] = h * h * sQ.value() / (4.0 * pi);
   out[2] = sBL.value() / (4.0 * pi);
 }

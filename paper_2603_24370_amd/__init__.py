@@ -19,6 +19,8 @@ SS_OK, SS_NOT_CONVERGED = 0, 1
 SS_EINVAL, SS_ETHEORY, SS_ESHAPE, SS_EHIP, SS_ENONFINITE, SS_ESTATE = -1, -2, -3, -4, -5, -6
 SS_F32, SS_F64 = 0, 1
 SS_GRAD_EL, SS_GRAD_EXACT = 0, 1
+SS_DMI_BULK, SS_DMI_HEUSLER = 0, 1
+DMI_KINDS = {"bulk": SS_DMI_BULK, "heusler": SS_DMI_HEUSLER}
 SS_PLAN_STAGES, SS_PLAN_FUSED = 0, 1
 SS_INTEG_RK4, SS_INTEG_VV, SS_INTEG_GF = 0, 1, 2
 INTEGRATORS = {"rk4": SS_INTEG_RK4, "vv": SS_INTEG_VV, "gf": SS_INTEG_GF}
@@ -79,7 +81,8 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_batch_destroy", "ss_batch_member", "ss_batch_size", "ss_batch_flow_step", "ss_batch_minimise",
            "ss_batch_set_tile", "ss_batch_autotune", "ss_batch_set_plan", "ss_batch_get_plan", "ss_batch_observables", "ss_set_energy_target", "ss_learned_input",
            "ss_learned_targets", "ss_init_learned", "ss_state_bytes", "ss_get_state", "ss_set_state",
-           "ss_energy_grad_noalloc", "ss_set_integrator", "ss_get_integrator"]
+           "ss_energy_grad_noalloc", "ss_set_integrator", "ss_get_integrator", "ss_workspace_bytes_for",
+           "ss_set_demag_iters"]
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
                "ssn_adam_step", "ssn_set_grad_clip",
@@ -102,6 +105,8 @@ def lib():
     L.ss_theory_id.argtypes = [cp]
     L.ss_components.argtypes = [cp]
     L.ss_workspace_bytes.argtypes = [cp, i, i, i, ctypes.POINTER(ctypes.c_size_t)]
+    L.ss_workspace_bytes_for.argtypes = [cp, i, i, ctypes.POINTER(ss_params), i, ctypes.POINTER(ctypes.c_size_t)]
+    L.ss_set_demag_iters.argtypes = [vp, i, i]
     L.ss_create.argtypes = [cp, i, i, d, ctypes.POINTER(ss_params), i, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.ss_destroy.argtypes = [vp]
     L.ss_destroy.restype = None
@@ -188,6 +193,19 @@ def ss_workspace_bytes(theory: str, Nx: int, Ny: int, dtype: int) -> int:
     n = ctypes.c_size_t(0)
     _check(lib().ss_workspace_bytes(_b(theory), Nx, Ny, dtype, ctypes.byref(n)))
     return n.value
+
+
+def ss_workspace_bytes_for(theory: str, Nx: int, Ny: int, f_params, i_params, dtype: int) -> int:
+    fa = (ctypes.c_double * max(1, len(f_params)))(*f_params)
+    ia = (ctypes.c_int * max(1, len(i_params)))(*i_params)
+    p = ss_params(fa, len(f_params), ia, len(i_params))
+    n = ctypes.c_size_t(0)
+    _check(lib().ss_workspace_bytes_for(_b(theory), Nx, Ny, ctypes.byref(p), dtype, ctypes.byref(n)))
+    return n.value
+
+
+def ss_set_demag_iters(ctx, iters_flow, iters_eval):
+    _check(lib().ss_set_demag_iters(ctx, int(iters_flow), int(iters_eval)))
 
 
 def ss_create(theory, Nx, Ny, h, f_params, i_params, dtype, workspace_ptr, ws_bytes, stream_ptr):
@@ -434,7 +452,9 @@ class Solver:
     """One library context plus its torch-allocated workspace on a CUDA/HIP device."""
 
     def __init__(self, theory, Nx, Ny, h, params, dtype="f32", grad_mode=SS_GRAD_EL, courant=None,
-                 device="cuda:0", stream=None, _ctx=None):
+                 device="cuda:0", stream=None, _ctx=None, dmi="bulk", demag=False):
+        """Chiral magnet options: dmi "bulk" or "heusler" (d_2 = -e_2); demag=True
+        adds the demagnetising term, with params = (J, D, K, B, mu_d)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libss needs a HIP GPU; none is available")
@@ -457,12 +477,15 @@ class Solver:
         self.C = ss_components(theory)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        nbytes = ss_workspace_bytes(theory, self.Nx, self.Ny, self.dtype_code)
+        f = list(params) + ([courant] if courant is not None else [])
+        ip = [grad_mode]
+        if dmi != "bulk" or demag:
+            ip += [DMI_KINDS[dmi], int(bool(demag))]
+        nbytes = ss_workspace_bytes_for(theory, self.Nx, self.Ny, f, ip, self.dtype_code)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
-        f = list(params) + ([courant] if courant is not None else [])
-        self.ctx = ss_create(theory, self.Nx, self.Ny, self.h, f, [grad_mode], self.dtype_code, self._ws_ptr,
+        self.ctx = ss_create(theory, self.Nx, self.Ny, self.h, f, ip, self.dtype_code, self._ws_ptr,
                              nbytes, self.stream.cuda_stream)
 
     @property
@@ -476,8 +499,13 @@ class Solver:
     def init_vortices(self, centres, windings=None, seed=0, noise_amp=0.0):
         ss_init_ansatz(self.ctx, SS_ANSATZ_VORTICES, centres, windings, None, seed, noise_amp)
 
-    def init_skyrmion(self, R=2.0, gamma=-1.5707963267948966, centre=(0.0, 0.0), seed=0, noise_amp=0.0):
-        ss_init_ansatz(self.ctx, SS_ANSATZ_SKYRMION, [centre], None, [R, gamma], seed, noise_amp)
+    def init_skyrmion(self, R=2.0, gamma=-1.5707963267948966, centre=(0.0, 0.0), seed=0, noise_amp=0.0,
+                      vorticity=1):
+        """Belavin-Polyakov ansatz; vorticity -1 gives the antiskyrmion."""
+        ss_init_ansatz(self.ctx, SS_ANSATZ_SKYRMION, [centre], [float(vorticity)], [R, gamma], seed, noise_amp)
+
+    def set_demag_iters(self, iters_flow, iters_eval):
+        ss_set_demag_iters(self.ctx, iters_flow, iters_eval)
 
     def autotune(self, n_steps=10):
         return ss_autotune(self.ctx, n_steps)

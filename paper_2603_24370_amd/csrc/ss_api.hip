@@ -23,6 +23,7 @@
 
 #include "../../include/ss.h"
 #include "ss_kernels.hpp"
+#include "ss_demag.hpp"
 
 using namespace ss;
 
@@ -124,7 +125,7 @@ struct ss_batch;
 struct ss_ctx {
   int theory, dtype, grad_mode, C, Nx, Ny;
   double h, courant;
-  double p[4];
+  double p[kNumParams];
   hipStream_t stream;
   hipStream_t cap_stream;
   char* ws;
@@ -141,6 +142,16 @@ struct ss_ctx {
   int tile;
   int plan;   // SS_PLAN_*: how stages 2-4 of a step are launched
   int integ;  // SS_INTEG_*: the flow's integrator
+  size_t ws_total;  // bytes of the workspace in use
+  // demagnetising potential (chiral magnet with params.i[2] = 1)
+  struct Demag {
+    int on;
+    int iters_flow, iters_eval;  // conjugate-gradient iterations per solve
+    void* S;                     // stage point (C planes, flow layout)
+    DmVecs v;
+    int nlev;
+    DmLevel lv[kDmMaxLevels];
+  } dm;
 };
 
 namespace {
@@ -159,6 +170,8 @@ Bufs<T> bufs_of(const ss_ctx* c) {
   B.plane = c->L.plane;
   B.Nx = c->Nx;
   B.Ny = c->Ny;
+  B.psi = c->dm.on ? c->dm.v.x : nullptr;
+  B.psi_pitch = c->Nx + 4;
   return B;
 }
 
@@ -166,7 +179,7 @@ Coeffs coeffs_of(const ss_ctx* c) {
   Coeffs cf;
   cf.h = c->h;
   cf.dt = c->courant * c->h;
-  for (int k = 0; k < 4; ++k) cf.p[k] = c->p[k];
+  for (int k = 0; k < kNumParams; ++k) cf.p[k] = c->p[k];
   return cf;
 }
 
@@ -239,10 +252,68 @@ int launch_pass_t(int tile, const PassArgs<T>& a, int nlaunch, hipStream_t s) {
   }
 }
 
+int dm_groups(long n) { return (int)std::max<long>(1, std::min<long>((n + 255) / 256, 4096)); }
+
+// One V-cycle from level l (the level's psi and rhs are set): smoothing, the
+// residual restricted to the next level, its correction, smoothing; on the
+// coarsest level an even number of sweeps from zero.
+void dm_vcycle(const ss_ctx::Demag& d, int l, const DevStatus* skip, hipStream_t s) {
+  const DmLevel& L = d.lv[l];
+  const int g = dm_groups((long)L.Nx * L.Ny);
+  auto sweeps = [&](int n) {
+    for (int k = 0; k < n; k += 2) {
+      hipLaunchKernelGGL(dm_jacobi, dim3(g), dim3(256), 0, s, L, (const double*)L.psi, L.tmp, skip);
+      hipLaunchKernelGGL(dm_jacobi, dim3(g), dim3(256), 0, s, L, (const double*)L.tmp, L.psi, skip);
+    }
+  };
+  if (l == d.nlev - 1) {
+    hipLaunchKernelGGL(dm_coarse_solve, dim3(1), dim3(256), 0, s, L, skip);
+    return;
+  }
+  const DmLevel& Cl = d.lv[l + 1];
+  sweeps(kDmSmooth);
+  hipLaunchKernelGGL(dm_residual, dim3(g), dim3(256), 0, s, L, skip);
+  hipLaunchKernelGGL(dm_restrict, dim3(dm_groups((long)Cl.Nx * Cl.Ny)), dim3(256), 0, s, L, Cl, skip);
+  dm_vcycle(d, l + 1, skip, s);
+  hipLaunchKernelGGL(dm_prolong, dim3(g), dim3(256), 0, s, Cl, L, skip);
+  sweeps(kDmSmooth);
+}
+
+// Demagnetising potential of the stage point of pass PASS (Sec. 4.2, eq. (6)),
+// queued before the pass: the stage point, then `iters` iterations of
+// multigrid-preconditioned conjugate gradients from the last potential. A flow's
+// solves stop with the flow (its status block); an evaluation's always run.
+template <class T, int PASS>
+void demag_solve(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
+  const ss_ctx::Demag& d = c->dm;
+  const DevStatus* skip = PASS == kEval ? nullptr : c->st;
+  const int iters = PASS == kEval ? d.iters_eval : d.iters_flow;
+  const DmLevel& L0 = d.lv[0];
+  Bufs<T> B = a.B;
+  T* S = (T*)d.S;
+  hipLaunchKernelGGL((dm_stage_point<T, PASS>), dim3(dm_groups((long)(c->Nx + 4) * (c->Ny + 4))), dim3(256), 0, s, B,
+                     a.cf, (const DevStatus*)c->st, a.src, S);
+  const int g = dm_groups((long)c->Nx * c->Ny);
+  hipLaunchKernelGGL((dm_begin<T>), dim3(g), dim3(256), 0, s, B, (const T*)S, L0, d.v, skip);
+  for (int it = 0; it < iters; ++it) {
+    const int first = it == 0 ? 1 : 0;
+    dm_vcycle(d, 0, skip, s);
+    hipLaunchKernelGGL(dm_dot, dim3(kDmRedGroups), dim3(256), 0, s, L0, (const double*)d.v.r, (const double*)L0.psi,
+                       d.v.part, skip);
+    hipLaunchKernelGGL(dm_beta, dim3(1), dim3(64), 0, s, (const double*)d.v.part, d.v.sc, first, skip);
+    hipLaunchKernelGGL(dm_dir, dim3(g), dim3(256), 0, s, L0, d.v, first, skip);
+    hipLaunchKernelGGL(dm_matvec, dim3(kDmRedGroups), dim3(256), 0, s, L0, d.v, skip);
+    hipLaunchKernelGGL(dm_alpha, dim3(1), dim3(64), 0, s, d.v, skip);
+    hipLaunchKernelGGL(dm_update, dim3(g), dim3(256), 0, s, L0, d.v, skip);
+  }
+}
+
 // A pass; a reducing pass (P1, evaluation, check) is followed by its finalise
-// launch, which sums the workgroup partials and updates the status.
+// launch, which sums the workgroup partials and updates the status. With
+// demagnetisation the pass is preceded by the solve for its stage point.
 template <class T, int PASS>
 void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
+  if (c->dm.on) demag_solve<T, PASS>(c, a, s);
   int groups = c->L.nlaunch;  // workgroups launched = partials written
   if (c->grad_mode == SS_GRAD_EXACT) {
     // exact-gradient passes: one tile shape (64 x 16), the layout of tile 0
@@ -404,6 +475,9 @@ size_t esize_of(int dtype) { return dtype == SS_F32 ? 4 : 8; }
 // Start from rest (Sec. 3.2): zero velocity and stage arrays, reset counters.
 int reset_state(ss_ctx* c) {
   SS_HIP(hipMemsetAsync(c->ws + 2 * c->L.set_bytes, 0, 5 * c->L.set_bytes, c->stream));
+  // the demagnetising potential (warm start of the solves) restarts from zero
+  if (c->dm.on)
+    SS_HIP(hipMemsetAsync(c->dm.v.x, 0, (size_t)(c->Nx + 4) * (c->Ny + 4) * sizeof(double), c->stream));
   DevStatus s;
   std::memset(&s, 0, sizeof(s));
   s.E = s.E_prev = std::numeric_limits<double>::infinity();
@@ -436,8 +510,9 @@ namespace {
 // any device work (Sec. 3.1: parameters are resolved first, then packed).
 struct Problem {
   int theory, dtype, grad_mode, C, nf_need;
+  int dmi_kind, demag;  // chiral magnet: SS_DMI_*, demagnetisation on/off
   double courant;
-  double p[4];
+  double p[kNumParams];
 };
 
 int resolve_problem(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype, Problem* pb);
@@ -486,34 +561,119 @@ int resolve_problem(const char* theory, int Nx, int Ny, double h, const ss_param
   if (dtype != SS_F32 && dtype != SS_F64) return fail(SS_EINVAL, "dtype must be SS_F32 or SS_F64");
   if (Nx < 8 || Ny < 8 || Nx > 65536 || Ny > 65536) return fail(SS_ESHAPE, "Nx, Ny must lie in [8, 65536]");
   if (!(h > 0.0) || !std::isfinite(h)) return fail(SS_EINVAL, "lattice spacing h must be positive and finite");
-  const int nf_need = th == SS_THEORY_AH ? 1 : th == SS_THEORY_CM ? 4 : 2;
-  if (!params || !params->f || params->nf < nf_need || params->nf > nf_need + 1)
-    return fail(SS_EINVAL, th == SS_THEORY_AH   ? "abelian_higgs needs params.f = {lambda [, courant]}"
-                           : th == SS_THEORY_CM ? "chiral_magnet needs params.f = {J, D, K, B [, courant]}"
-                                                : "baby_skyrme needs params.f = {kappa, mu^2 [, courant]}");
+  if (!params) return fail(SS_EINVAL, "params is NULL");
+  // integer options: {grad_mode, dmi_kind, demag}
+  int opt[3] = {SS_GRAD_EL, SS_DMI_BULK, 0};
+  if (params->ni > 3) return fail(SS_EINVAL, "params.i holds at most {grad_mode, dmi_kind, demag}");
+  if (params->ni > 0) {
+    if (!params->i) return fail(SS_EINVAL, "params.i is NULL with ni > 0");
+    for (int k = 0; k < params->ni; ++k) opt[k] = params->i[k];
+  }
+  const int grad_mode = opt[0], dmi_kind = opt[1], demag = opt[2];
+  if (grad_mode != SS_GRAD_EL && grad_mode != SS_GRAD_EXACT) return fail(SS_EINVAL, "unknown grad_mode");
+  if (dmi_kind != SS_DMI_BULK && dmi_kind != SS_DMI_HEUSLER) return fail(SS_EINVAL, "unknown dmi_kind");
+  if (demag != 0 && demag != 1) return fail(SS_EINVAL, "demag must be 0 or 1");
+  if (th != SS_THEORY_CM && (dmi_kind != SS_DMI_BULK || demag))
+    return fail(SS_EINVAL, "DMI variants and demagnetisation belong to the chiral magnet");
+  if (demag && grad_mode != SS_GRAD_EL)
+    return fail(SS_EINVAL, "the demagnetising term runs with the Euler-Lagrange gradient (grad_mode SS_GRAD_EL)");
+  const int nf_need = th == SS_THEORY_AH ? 1 : th == SS_THEORY_CM ? 4 + demag : 2;
+  if (!params->f || params->nf < nf_need || params->nf > nf_need + 1)
+    return fail(SS_EINVAL, th == SS_THEORY_AH ? "abelian_higgs needs params.f = {lambda [, courant]}"
+                           : th == SS_THEORY_CM
+                               ? (demag ? "chiral_magnet with demagnetisation needs params.f = {J, D, K, B, mu_d [, courant]}"
+                                        : "chiral_magnet needs params.f = {J, D, K, B [, courant]}")
+                               : "baby_skyrme needs params.f = {kappa, mu^2 [, courant]}");
   for (int k = 0; k < params->nf; ++k)
     if (!std::isfinite(params->f[k])) return fail(SS_EINVAL, "non-finite parameter");
   const double courant = params->nf > nf_need ? params->f[nf_need] : 0.5;
   if (!(courant > 0.0 && courant < 1.0)) return fail(SS_EINVAL, "courant number C must lie in (0, 1)");
-  int grad_mode = SS_GRAD_EL;
-  if (params->ni > 0) {
-    if (!params->i) return fail(SS_EINVAL, "params.i is NULL with ni > 0");
-    grad_mode = params->i[0];
-    if (grad_mode != SS_GRAD_EL && grad_mode != SS_GRAD_EXACT) return fail(SS_EINVAL, "unknown grad_mode");
-  }
+  if (demag && !(params->f[4] > 0.0)) return fail(SS_EINVAL, "mu_d must be positive");
   pb->theory = th;
   pb->dtype = dtype;
   pb->grad_mode = grad_mode;
+  pb->dmi_kind = dmi_kind;
+  pb->demag = demag;
   pb->C = th == SS_THEORY_AH ? 4 : 3;
   pb->nf_need = nf_need;
   pb->courant = courant;
-  for (int k = 0; k < 4; ++k) pb->p[k] = k < nf_need ? params->f[k] : 0.0;
+  for (int k = 0; k < kNumParams; ++k) pb->p[k] = 0.0;
+  for (int k = 0; k < std::min(nf_need, 4); ++k) pb->p[k] = params->f[k];
+  if (th == SS_THEORY_CM) {
+    // d_1 = e_1 always; d_2 = e_2 (bulk) or -e_2 (Heusler): the y-derivative DMI coefficient
+    pb->p[4] = dmi_kind == SS_DMI_HEUSLER ? -params->f[1] : params->f[1];
+    pb->p[5] = demag ? params->f[4] : 0.0;
+  }
   return SS_OK;
+}
+
+// Demagnetisation region of a workspace (after the flow's own buffers): the
+// stage point, level 0 of the solver (x, r, d, Ad and the V-cycle's psi, tmp,
+// rhs), three planes per coarser level, the reduction partials and scalars.
+// With base == nullptr only the size is computed.
+size_t demag_region(int Nx, int Ny, double h, const Layout& L, int esize, char* base, ss_ctx::Demag* d) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (size_t)round_up((long)bytes, 256);
+    return p;
+  };
+  char* S = take(L.set_bytes);
+  if (d) d->S = S ? S + L.col0 * esize : nullptr;
+  int nx = Nx, ny = Ny, nlev = 0;
+  double hl = h;
+  for (;;) {
+    const size_t pb = (size_t)(nx + 4) * (ny + 4) * sizeof(double);
+    DmLevel lv;
+    lv.Nx = nx;
+    lv.Ny = ny;
+    lv.pitch = nx + 4;
+    lv.h = hl;
+    if (nlev == 0) {
+      double* x = (double*)take(pb);
+      double* r = (double*)take(pb);
+      double* dd = (double*)take(pb);
+      double* ad = (double*)take(pb);
+      if (d) {
+        d->v.x = x;
+        d->v.r = r;
+        d->v.d = dd;
+        d->v.Ad = ad;
+      }
+    }
+    lv.psi = (double*)take(pb);
+    lv.tmp = (double*)take(pb);
+    lv.rhs = (double*)take(pb);
+    if (d) d->lv[nlev] = lv;
+    ++nlev;
+    if (std::min(nx, ny) < 8 || nlev == kDmMaxLevels) break;
+    nx = (nx + 1) / 2;
+    ny = (ny + 1) / 2;
+    hl *= 2.0;
+  }
+  double* part = (double*)take(kDmRedGroups * sizeof(double));
+  double* sc = (double*)take(8 * sizeof(double));
+  if (d) {
+    d->nlev = nlev;
+    d->v.part = part;
+    d->v.sc = sc;
+  }
+  return off;
 }
 
 }  // namespace
 
 extern "C" {
+
+int ss_workspace_bytes_for(const char* theory, int Nx, int Ny, const ss_params* params, int dtype, size_t* bytes) {
+  Problem pb;
+  int rc = resolve_problem(theory, Nx, Ny, 1.0, params, dtype, &pb);
+  if (rc) return rc;
+  if (!bytes) return fail(SS_EINVAL, "bytes is NULL");
+  const Layout L = make_layout(pb.C, Nx, Ny, (int)esize_of(dtype));
+  *bytes = L.total + (pb.demag ? demag_region(Nx, Ny, 1.0, L, (int)esize_of(dtype), nullptr, nullptr) : 0);
+  return SS_OK;
+}
 
 int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* params, int dtype, void* workspace,
               size_t ws_bytes, void* stream, ss_ctx** out) {
@@ -523,7 +683,7 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   int rc = resolve_problem(theory, Nx, Ny, h, params, dtype, &pb);
   if (rc) return rc;
   size_t need = 0;
-  rc = ss_workspace_bytes(theory, Nx, Ny, dtype, &need);
+  rc = ss_workspace_bytes_for(theory, Nx, Ny, params, dtype, &need);
   if (rc) return rc;
   if (!workspace || ws_bytes < need) return fail(SS_EINVAL, "workspace missing or smaller than ss_workspace_bytes");
   if (((uintptr_t)workspace) % 256 != 0) return fail(SS_EINVAL, "workspace must be 256-byte aligned");
@@ -539,7 +699,7 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   c->Ny = Ny;
   c->h = h;
   c->courant = pb.courant;
-  for (int k = 0; k < 4; ++k) c->p[k] = pb.p[k];
+  for (int k = 0; k < kNumParams; ++k) c->p[k] = pb.p[k];
   c->stream = (hipStream_t)stream;
   c->ws = (char*)workspace;
   c->L = make_layout(c->C, Nx, Ny, (int)esize_of(dtype));
@@ -556,15 +716,23 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   }
   if (grad_mode == SS_GRAD_EXACT) c->tile = 0;
   set_tiles(c->L, Nx, Ny, c->tile);
-  c->plan = (grad_mode == SS_GRAD_EL && dtype == SS_F32) ? kDefaultPlanF32 : SS_PLAN_STAGES;
+  c->plan = (grad_mode == SS_GRAD_EL && dtype == SS_F32 && !pb.demag) ? kDefaultPlanF32 : SS_PLAN_STAGES;
   c->integ = SS_INTEG_RK4;
+  c->ws_total = need;
+  std::memset(&c->dm, 0, sizeof(c->dm));
+  if (pb.demag) {
+    c->dm.on = 1;
+    c->dm.iters_flow = 2;
+    c->dm.iters_eval = 40;
+    demag_region(Nx, Ny, h, c->L, (int)esize_of(dtype), c->ws + c->L.total, &c->dm);
+  }
   hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete c;
     return fail(SS_EHIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
   }
   // zero the whole workspace once: halos of velocity and stage arrays stay 0
-  e = hipMemsetAsync(c->ws, 0, c->L.total, c->stream);
+  e = hipMemsetAsync(c->ws, 0, c->ws_total, c->stream);
   if (e != hipSuccess) {
     (void)hipStreamDestroy(c->cap_stream);
     delete c;
@@ -603,6 +771,8 @@ int ss_init_ansatz(ss_ctx* c, int kind, int n, const double* xy, const double* w
     return fail(SS_EINVAL, "ansatz kind does not match the theory");
   if (n < 0 || n > kMaxVortices || (n > 0 && !xy)) return fail(SS_EINVAL, "bad vortex list");
   if (kind == SS_ANSATZ_SKYRMION && (n != 1 || !shape)) return fail(SS_EINVAL, "skyrmion needs n = 1 and shape");
+  if (kind == SS_ANSATZ_SKYRMION && w && !(w[0] != 0.0 && w[0] == std::nearbyint(w[0]) && std::fabs(w[0]) <= 64.0))
+    return fail(SS_EINVAL, "skyrmion vorticity w[0] must be a nonzero integer");
   if (!(noise_amp >= 0.0) || !std::isfinite(noise_amp)) return fail(SS_EINVAL, "bad noise amplitude");
   std::vector<double> host(3 * (size_t)std::max(n, 1), 0.0);
   for (int k = 0; k < n; ++k) {
@@ -886,6 +1056,7 @@ int ss_energy_grad_noalloc(const char* theory, int Nx, int Ny, double h, const s
   int rc = resolve_problem(theory, Nx, Ny, h, params, dtype, &pb);
   if (rc) return rc;
   if (!field) return fail(SS_EINVAL, "field is NULL");
+  if (pb.demag) return fail(SS_EINVAL, "the demagnetising term needs a context's workspace (use ss_energy_grad)");
   void* sp = nullptr;
   rc = scratch_of_current_device(&sp);
   if (rc) return rc;
@@ -900,7 +1071,7 @@ int ss_energy_grad_noalloc(const char* theory, int Nx, int Ny, double h, const s
   c.Ny = Ny;
   c.h = h;
   c.courant = pb.courant;
-  for (int k = 0; k < 4; ++k) c.p[k] = pb.p[k];
+  for (int k = 0; k < kNumParams; ++k) c.p[k] = pb.p[k];
   c.stream = (hipStream_t)stream;
   c.tile = kDefaultTile;
   set_tiles(c.L, Nx, Ny, c.tile);
@@ -1006,9 +1177,12 @@ void obs_enqueue_t(ss_ctx* c, int nobs) {
     hipLaunchKernelGGL((obs_winding<T>), dim3(1), dim3(256), 0, c->stream, B, c->st);
     return;
   }
-  if (c->theory == SS_THEORY_CM)
+  if (c->theory == SS_THEORY_CM) {
+    // the potential of the current field, for the demagnetising energy
+    if (c->dm.on) demag_solve<T, kEval>(c, pass_args<T>(c), c->stream);
     hipLaunchKernelGGL((obs_sites<T, kCM>), dim3(nobs), dim3(256), 0, c->stream, B, coeffs_of(c), c->st, c->partials,
                        nobs);
+  }
   else
     hipLaunchKernelGGL((obs_sites<T, kBS>), dim3(nobs), dim3(256), 0, c->stream, B, coeffs_of(c), c->st, c->partials,
                        nobs);
@@ -1073,6 +1247,8 @@ int ss_set_plan(ss_ctx* c, int plan) {
   if (plan < 0 || plan >= SS_NUM_PLANS) return fail(SS_EINVAL, "unknown plan");
   if (plan != SS_PLAN_STAGES && c->grad_mode != SS_GRAD_EL)
     return fail(SS_EINVAL, "the fused plans evaluate the Euler-Lagrange gradient only");
+  if (plan != SS_PLAN_STAGES && c->dm.on)
+    return fail(SS_EINVAL, "demagnetisation runs with SS_PLAN_STAGES (one solve per stage point)");
   SS_HIP(hipStreamSynchronize(c->stream));
   c->plan = plan;
   if (c->graph) {
@@ -1099,6 +1275,21 @@ int ss_set_integrator(ss_ctx* c, int integ) {
 
 int ss_get_integrator(ss_ctx* c) { return c ? c->integ : SS_EINVAL; }
 
+int ss_set_demag_iters(ss_ctx* c, int iters_flow, int iters_eval) {
+  if (!c) return fail(SS_EINVAL, "ctx is NULL");
+  if (!c->dm.on) return fail(SS_EINVAL, "the context has no demagnetising term");
+  if (iters_flow < 1 || iters_flow > 1000 || iters_eval < 1 || iters_eval > 1000)
+    return fail(SS_EINVAL, "iteration counts must lie in [1, 1000]");
+  SS_HIP(hipStreamSynchronize(c->stream));
+  c->dm.iters_flow = iters_flow;
+  c->dm.iters_eval = iters_eval;
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return SS_OK;
+}
+
 int ss_tile_count(void) { return kNumTiles; }
 
 int ss_tile_shape(int tile, int* tx, int* ty, int* ry) {
@@ -1119,8 +1310,8 @@ namespace {
 // so entries from a library with other shapes are not used.
 std::string tune_key(const ss_ctx* c) {
   char buf[128];
-  std::snprintf(buf, sizeof(buf), "%d %d %d %d %d %d %d", c->theory, c->dtype, c->grad_mode, c->Nx, c->Ny, kNumTiles,
-                c->integ);
+  std::snprintf(buf, sizeof(buf), "%d %d %d %d %d %d %d %d", c->theory, c->dtype, c->grad_mode, c->Nx, c->Ny,
+                kNumTiles, c->integ, c->dm.on);
   return buf;
 }
 
@@ -1133,10 +1324,11 @@ bool tune_lookup(const ss_ctx* c, int* plan, int* tile) {
   bool found = false;
   char line[256];
   while (std::fgets(line, sizeof(line), f)) {
-    int th, dt, gm, nx, ny, nt, ig, p, t;
-    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d", &th, &dt, &gm, &nx, &ny, &nt, &ig, &p, &t) != 9) continue;
+    int th, dt, gm, nx, ny, nt, ig, dm, p, t;
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &th, &dt, &gm, &nx, &ny, &nt, &ig, &dm, &p, &t) != 10)
+      continue;
     char k[128];
-    std::snprintf(k, sizeof(k), "%d %d %d %d %d %d %d", th, dt, gm, nx, ny, nt, ig);
+    std::snprintf(k, sizeof(k), "%d %d %d %d %d %d %d %d", th, dt, gm, nx, ny, nt, ig, dm);
     if (key == k && p >= 0 && p < SS_NUM_PLANS && t >= 0 && t < kNumTiles) {
       *plan = p;
       *tile = t;
@@ -1184,7 +1376,8 @@ int ss_autotune(ss_ctx* c, int n_steps, double* ms_out) {
   if (rc) return rc;
   int best_t = c->tile, best_p = c->plan;
   double best_ms = 1e300;
-  for (int p = 0; p < SS_NUM_PLANS; ++p) {
+  const int nplans = c->dm.on ? 1 : SS_NUM_PLANS;
+  for (int p = 0; p < nplans; ++p) {
     rc = ss_set_plan(c, p);
     if (rc) return rc;
     for (int t = 0; t < kNumTiles; ++t) {
@@ -1397,7 +1590,9 @@ BatchInst<T> batch_inst_of(const ss_ctx* c, int unit0, int nunits) {
   I.V.pitch = B.pitch; I.V.plane = B.plane;
   I.V.Nx = B.Nx; I.V.Ny = B.Ny;
   I.V.h = cf.h; I.V.dt = cf.dt;
-  for (int k = 0; k < 4; ++k) I.V.p[k] = cf.p[k];
+  for (int k = 0; k < kNumParams; ++k) I.V.p[k] = cf.p[k];
+  I.V.psi = nullptr;  // batches run local theories only
+  I.V.psi_pitch = 0;
   I.st = c->st;
   I.unit0 = unit0;
   I.nunits = nunits;

@@ -1,0 +1,321 @@
+// Demagnetising potential of the chiral magnet (Sec. 4.2, eq. (5)-(6)).
+//
+// In units where mu_0 M_s^2 is the coefficient mu_d, the potential psi of a field
+// n solves Laplace_h psi = d_x n_1 + d_y n_2 on the interior, with psi = 0 outside
+// it: the divergence by eq. (1), the Laplacian by eq. (2) along each axis. The
+// energy density gains mu_d/2 |grad_h psi|^2 and the Euler-Lagrange gradient
+// mu_d grad_h psi (eq. (1) derivatives of psi); the stage passes add both terms
+// from the potential of the stage point they evaluate, solved just before.
+//
+// Solver: conjugate gradients on the symmetric positive definite A = -Laplace_h,
+// preconditioned by one multigrid V-cycle, all in FP64. The hierarchy coarsens
+// by two per axis (a coarse cell covers two fine sites, N_c = ceil(N / 2)) down
+// to a level with fewer than eight sites along an axis; each level rediscretises
+// eq. (2) at its spacing 2^l h with a zero halo of width two. The V-cycle is
+// symmetric, as the preconditioner of conjugate gradients must be: two weighted
+// Jacobi sweeps before and after the coarse correction, bilinear prolongation P
+// (weights 3/4 and 1/4 per axis), restriction P^T / 4, and an even number of
+// Jacobi sweeps from zero on the coarsest level. A solve runs a fixed number of
+// iterations, warm-started from the last potential (stage points change little
+// from one pass to the next), so that it can be captured in a graph. Dot
+// products are summed per workgroup and then in workgroup order (deterministic).
+#pragma once
+
+#include "ss_internal.hpp"
+
+namespace ss {
+
+constexpr int kDmMaxLevels = 20;
+constexpr int kDmRedGroups = 256;  // workgroups of the dot-product launches
+constexpr double kDmOmega = 0.8;   // Jacobi weight (stable below 15/16 for this operator)
+constexpr int kDmSmooth = 2;       // sweeps before and after the coarse correction
+constexpr int kDmCoarse = 40;      // sweeps on the coarsest level (even)
+
+// One level of the hierarchy: padded planes of (Ny + 4) rows of pitch = Nx + 4 doubles.
+struct DmLevel {
+  double* psi;  // solution (the preconditioned residual z on level 0)
+  double* tmp;  // Jacobi partner of psi; holds the residual before a restriction
+  double* rhs;
+  int Nx, Ny;
+  long pitch;
+  double h;
+};
+
+// Level-0 vectors of conjugate gradients, the reduction partials and the scalars
+// {r.z, beta, alpha, d.Ad}.
+struct DmVecs {
+  double* x;  // the potential psi
+  double* r;
+  double* d;
+  double* Ad;
+  double* part;
+  double* sc;
+};
+
+__device__ __forceinline__ bool dm_skip(const DevStatus* st) { return st != nullptr && st->done != 0; }
+
+__device__ __forceinline__ long dm_at(const DmLevel& L, int j, int i) { return (long)(j + 2) * L.pitch + (i + 2); }
+
+// Laplace_h of a padded plane at interior site (j, i): eq. (2) along both axes.
+__device__ __forceinline__ double dm_lap(const double* __restrict__ x, long p, int j, int i, double h) {
+  const double* c = x + (long)(j + 2) * p + (i + 2);
+  const double sx = -(c[-2] + c[2]) + 16.0 * (c[-1] + c[1]);
+  const double sy = -(c[-2 * p] + c[2 * p]) + 16.0 * (c[-p] + c[p]);
+  return (sx + sy - 60.0 * c[0]) / (12.0 * h * h);
+}
+
+#define DM_SITES(L)                                                                        \
+  for (long k_ = blockIdx.x * 256L + threadIdx.x; k_ < (long)(L).Nx * (L).Ny;              \
+       k_ += (long)gridDim.x * 256L)
+
+// Weighted Jacobi: dst = src - omega h^2/5 (rhs - Laplace_h src) (the operator's
+// diagonal is -5/h^2). Only interior sites are written; halos stay zero.
+__global__ void __launch_bounds__(256) dm_jacobi(DmLevel L, const double* __restrict__ src, double* __restrict__ dst,
+                                                 const DevStatus* st) {
+  if (dm_skip(st)) return;
+  const double s = kDmOmega * L.h * L.h / 5.0;
+  DM_SITES(L) {
+    const int j = (int)(k_ / L.Nx), i = (int)(k_ - (long)j * L.Nx);
+    const long o = dm_at(L, j, i);
+    dst[o] = src[o] - s * (L.rhs[o] - dm_lap(src, L.pitch, j, i, L.h));
+  }
+}
+
+// The coarsest level: kDmCoarse Jacobi sweeps (psi -> tmp -> psi ...) from the
+// zero start the restriction left, in one workgroup, with a barrier between sweeps
+// (one launch instead of kDmCoarse). Global memory is coherent within a workgroup
+// across the barrier.
+__global__ void __launch_bounds__(256) dm_coarse_solve(DmLevel L, const DevStatus* st) {
+  if (dm_skip(st)) return;
+  const double s = kDmOmega * L.h * L.h / 5.0;
+  const long n = (long)L.Nx * L.Ny;
+  for (int sweep = 0; sweep < kDmCoarse; ++sweep) {
+    const double* __restrict__ src = (sweep & 1) ? L.tmp : L.psi;
+    double* __restrict__ dst = (sweep & 1) ? L.psi : L.tmp;
+    for (long k = threadIdx.x; k < n; k += 256) {
+      const int j = (int)(k / L.Nx), i = (int)(k - (long)j * L.Nx);
+      const long o = dm_at(L, j, i);
+      dst[o] = src[o] - s * (L.rhs[o] - dm_lap(src, L.pitch, j, i, L.h));
+    }
+    __syncthreads();
+  }
+}
+
+// tmp = rhs - Laplace_h psi
+__global__ void __launch_bounds__(256) dm_residual(DmLevel L, const DevStatus* st) {
+  if (dm_skip(st)) return;
+  DM_SITES(L) {
+    const int j = (int)(k_ / L.Nx), i = (int)(k_ - (long)j * L.Nx);
+    const long o = dm_at(L, j, i);
+    L.tmp[o] = L.rhs[o] - dm_lap(L.psi, L.pitch, j, i, L.h);
+  }
+}
+
+// 1-D weight of fine index f in coarse cell J (transpose of the prolongation):
+// f = 2J - 1 and 2J + 2 carry 1/4, f = 2J and 2J + 1 carry 3/4.
+__device__ __forceinline__ double dm_w(int f, int J) {
+  const int d = f - 2 * J;
+  return (d == 0 || d == 1) ? 0.75 : 0.25;
+}
+
+// Coarse right-hand side = P^T (fine residual) / 4; coarse psi = 0.
+__global__ void __launch_bounds__(256) dm_restrict(DmLevel F, DmLevel C, const DevStatus* st) {
+  if (dm_skip(st)) return;
+  DM_SITES(C) {
+    const int J = (int)(k_ / C.Nx), I = (int)(k_ - (long)J * C.Nx);
+    double acc = 0.0;
+    for (int j = max(2 * J - 1, 0); j <= min(2 * J + 2, F.Ny - 1); ++j) {
+      double row = 0.0;
+      for (int i = max(2 * I - 1, 0); i <= min(2 * I + 2, F.Nx - 1); ++i) row += dm_w(i, I) * F.tmp[dm_at(F, j, i)];
+      acc += dm_w(j, J) * row;
+    }
+    const long o = dm_at(C, J, I);
+    C.rhs[o] = 0.25 * acc;
+    C.psi[o] = 0.0;
+  }
+}
+
+// Fine psi += P (coarse psi): bilinear in cell-centred positions; coarse cells
+// outside the level count as zero.
+__global__ void __launch_bounds__(256) dm_prolong(DmLevel C, DmLevel F, const DevStatus* st) {
+  if (dm_skip(st)) return;
+  DM_SITES(F) {
+    const int j = (int)(k_ / F.Nx), i = (int)(k_ - (long)j * F.Nx);
+    const int J = j >> 1, I = i >> 1;
+    const int J2 = J + ((j & 1) ? 1 : -1), I2 = I + ((i & 1) ? 1 : -1);
+    auto cv = [&](int jj, int ii) -> double {
+      return (ii >= 0 && ii < C.Nx && jj >= 0 && jj < C.Ny) ? C.psi[dm_at(C, jj, ii)] : 0.0;
+    };
+    F.psi[dm_at(F, j, i)] += 0.5625 * cv(J, I) + 0.1875 * (cv(J, I2) + cv(J2, I)) + 0.0625 * cv(J2, I2);
+  }
+}
+
+// Start of a solve for the stage point S (C planes in the flow's layout):
+// r = b - A x with b = -(d_x S_1 + d_y S_2) and A = -Laplace_h, then the
+// V-cycle's input on level 0: rhs = -r, psi = 0 (it solves Laplace_h z = -r).
+template <class T>
+__global__ void __launch_bounds__(256) dm_begin(Bufs<T> B, const T* __restrict__ S, DmLevel L0, DmVecs D,
+                                                const DevStatus* st) {
+  if (dm_skip(st)) return;
+  const double c1 = 1.0 / (12.0 * L0.h);
+  const long p = B.pitch;
+  DM_SITES(L0) {
+    const int j = (int)(k_ / L0.Nx), i = (int)(k_ - (long)j * L0.Nx);
+    const T* s1 = S + (long)(j + 2) * p + (i + 2);
+    const T* s2 = s1 + B.plane;
+    const double dx = c1 * (((double)s1[-2] - (double)s1[2]) + 8.0 * ((double)s1[1] - (double)s1[-1]));
+    const double dy = c1 * (((double)s2[-2 * p] - (double)s2[2 * p]) + 8.0 * ((double)s2[p] - (double)s2[-p]));
+    const long o = dm_at(L0, j, i);
+    const double r = -(dx + dy) + dm_lap(D.x, L0.pitch, j, i, L0.h);
+    D.r[o] = r;
+    L0.rhs[o] = -r;
+    L0.psi[o] = 0.0;
+  }
+}
+
+// Sum of 256 threads' values in a fixed order; valid in thread 0.
+__device__ __forceinline__ double dm_block_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// part[block] = sum over the block's sites of a . b (level-0 planes)
+__global__ void __launch_bounds__(256) dm_dot(DmLevel L0, const double* __restrict__ a, const double* __restrict__ b,
+                                              double* __restrict__ part, const DevStatus* st) {
+  if (dm_skip(st)) return;
+  __shared__ double red[4];
+  double acc = 0.0;
+  DM_SITES(L0) {
+    const int j = (int)(k_ / L0.Nx), i = (int)(k_ - (long)j * L0.Nx);
+    const long o = dm_at(L0, j, i);
+    acc += a[o] * b[o];
+  }
+  const double s = dm_block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// rz = sum of the partials; beta = rz / rz_previous (0 on the first iteration or
+// once rz_previous is 0).
+__global__ void __launch_bounds__(64) dm_beta(const double* __restrict__ part, double* sc, int first,
+                                              const DevStatus* st) {
+  if (dm_skip(st) || threadIdx.x != 0) return;
+  double rz = 0.0;
+  for (int k = 0; k < kDmRedGroups; ++k) rz += part[k];
+  sc[1] = (first || sc[0] == 0.0) ? 0.0 : rz / sc[0];
+  sc[0] = rz;
+}
+
+// d = z (first iteration) or z + beta d
+__global__ void __launch_bounds__(256) dm_dir(DmLevel L0, DmVecs D, int first, const DevStatus* st) {
+  if (dm_skip(st)) return;
+  const double beta = D.sc[1];
+  DM_SITES(L0) {
+    const int j = (int)(k_ / L0.Nx), i = (int)(k_ - (long)j * L0.Nx);
+    const long o = dm_at(L0, j, i);
+    D.d[o] = first ? L0.psi[o] : L0.psi[o] + beta * D.d[o];
+  }
+}
+
+// Ad = -Laplace_h d and part[block] = sum of d . Ad over the block's sites
+__global__ void __launch_bounds__(256) dm_matvec(DmLevel L0, DmVecs D, const DevStatus* st) {
+  if (dm_skip(st)) return;
+  __shared__ double red[4];
+  double acc = 0.0;
+  DM_SITES(L0) {
+    const int j = (int)(k_ / L0.Nx), i = (int)(k_ - (long)j * L0.Nx);
+    const long o = dm_at(L0, j, i);
+    const double ad = -dm_lap(D.d, L0.pitch, j, i, L0.h);
+    D.Ad[o] = ad;
+    acc += D.d[o] * ad;
+  }
+  const double s = dm_block_sum(acc, red);
+  if (threadIdx.x == 0) D.part[blockIdx.x] = s;
+}
+
+// alpha = r.z / d.Ad (0 once d.Ad is 0: the residual has vanished)
+__global__ void __launch_bounds__(64) dm_alpha(DmVecs D, const DevStatus* st) {
+  if (dm_skip(st) || threadIdx.x != 0) return;
+  double dad = 0.0;
+  for (int k = 0; k < kDmRedGroups; ++k) dad += D.part[k];
+  D.sc[3] = dad;
+  D.sc[2] = dad > 0.0 ? D.sc[0] / dad : 0.0;
+}
+
+// x += alpha d, r -= alpha Ad, and the next V-cycle's input (rhs = -r, psi = 0)
+__global__ void __launch_bounds__(256) dm_update(DmLevel L0, DmVecs D, const DevStatus* st) {
+  if (dm_skip(st)) return;
+  const double alpha = D.sc[2];
+  DM_SITES(L0) {
+    const int j = (int)(k_ / L0.Nx), i = (int)(k_ - (long)j * L0.Nx);
+    const long o = dm_at(L0, j, i);
+    D.x[o] += alpha * D.d[o];
+    const double r = D.r[o] - alpha * D.Ad[o];
+    D.r[o] = r;
+    L0.rhs[o] = -r;
+    L0.psi[o] = 0.0;
+  }
+}
+
+// The stage point a pass evaluates, formed as the pass forms it (phi + cv v + ca a,
+// put on the unit sphere at interior sites when the pass moves the field), over
+// the whole padded lattice, into `out` (the flow's layout). For an evaluation the
+// field is `src` or, when that is null, the current field. Skipped once a flow
+// has stopped, as the pass itself is.
+template <class T, int PASS>
+__global__ void __launch_bounds__(256) dm_stage_point(Bufs<T> B, Coeffs cf, const DevStatus* st,
+                                                      const T* __restrict__ src, T* __restrict__ out) {
+  if (PASS != kEval && st->done) return;
+  constexpr bool ONEPASS = advances_first(PASS);
+  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4 || ONEPASS);
+  constexpr bool WITH_V = STAGED && PASS != kGF;
+  constexpr bool WITH_A = (PASS == kP3 || PASS == kP4 || ONEPASS);
+  constexpr bool AFTER_P1 = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  constexpr bool USES_ARREST = AFTER_P1 || PASS == kVV;
+  const long long step = st->step;
+  const int cur = AFTER_P1 ? int((step - 1) & 1) : int(step & 1);
+  const bool arrest = USES_ARREST ? (st->arrest != 0) : false;
+  const T dt = (T)cf.dt;
+  T cv = T(0), ca = T(0);
+  if (PASS == kP2) cv = T(0.5) * dt;
+  if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
+  if (PASS == kP4 || PASS == kVV) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (PASS == kGF) ca = T(0.5) * dt * dt;
+  if (arrest) cv = T(0);
+  const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : (cur ? B.phi[1] : B.phi[0]);
+  const T* __restrict__ vv = cur ? B.vel[1] : B.vel[0];
+  const T* __restrict__ aa = ONEPASS ? (cur ? B.a2 : B.a1) : (PASS == kP3) ? B.a1 : B.a2;
+  const long W = B.Nx + 4, H = B.Ny + 4;
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < W * H; k += (long)gridDim.x * 256L) {
+    const int jj = (int)(k / W), ii = (int)(k - (long)jj * W);
+    const long o = (long)jj * B.pitch + ii;
+    T S[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T x = ph[c * B.plane + o];
+      if (STAGED) {
+        if (WITH_V) x += cv * vv[c * B.plane + o];
+        if (WITH_A) x += ca * aa[c * B.plane + o];
+      }
+      S[c] = x;
+    }
+    if (STAGED && ii >= 2 && ii < B.Nx + 2 && jj >= 2 && jj < B.Ny + 2) {
+      const T inv = T(1) / sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) S[c] *= inv;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c * B.plane + o] = S[c];
+  }
+}
+
+// Zero-fill of n doubles (the hierarchy's planes at set-up, and the potential
+// when a new field is set).
+__global__ void __launch_bounds__(256) dm_fill_zero(double* p, long n) {
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < n; k += (long)gridDim.x * 256L) p[k] = 0.0;
+}
+
+#undef DM_SITES
+
+}  // namespace ss

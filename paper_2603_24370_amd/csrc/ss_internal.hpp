@@ -12,6 +12,7 @@ constexpr int kMaxWindow = 128;   // largest stall-rule window accepted by the A
 // the entry of step s - W is never the slot that step s overwrites.
 constexpr int kHistLen = 2 * kMaxWindow;
 constexpr int kMaxComp = 4;
+constexpr int kNumParams = 6;  // theory parameters packed for the kernels
 
 // Device-resident state of one flow (written only by kernels, read by the host
 // through a stream-ordered copy).
@@ -51,12 +52,17 @@ struct Bufs {
   long pitch;
   long plane;
   int Nx, Ny;
+  // demagnetising potential of the stage point a pass evaluates (FP64, padded
+  // plane of row length psi_pitch = Nx + 4, zero outside the interior); null
+  // when the theory has no demagnetising term
+  const double* psi;
+  long psi_pitch;
 };
 
 // Theory constants packed for the kernels.
 struct Coeffs {
   double h, dt;
-  double p[4];  // AH: {lambda}; CM: {J, D, K, B}
+  double p[kNumParams];  // AH: {lambda}; CM: {J, D, K, B, Dy, mu_d}; BS: {kappa, mu^2}
 };
 
 // Passes of one RK4 step and the single-evaluation variants.

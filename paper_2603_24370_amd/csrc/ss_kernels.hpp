@@ -131,6 +131,15 @@ __device__ __forceinline__ void vstore_lds(T* p, const T (&x)[16 / sizeof(T)]) {
   *reinterpret_cast<V*>(p) = v;
 }
 
+// eq. (1) gradient of the demagnetising potential at interior site (gi, gj) of a
+// padded FP64 plane of row length pp (zero outside the interior); d1 = 1/(12h).
+__device__ __forceinline__ void psi_gradient(const double* __restrict__ psi, long pp, int gi, int gj, double d1,
+                                             double& gx, double& gy) {
+  const double* c = psi + (long)(gj + 2) * pp + (gi + 2);
+  gx = d1 * ((c[-2] - c[2]) + 8.0 * (c[1] - c[-1]));
+  gy = d1 * ((c[-2 * pp] - c[2 * pp]) + 8.0 * (c[pp] - c[-pp]));
+}
+
 // One lattice as the stage passes see it (single context or one batch member).
 template <class T>
 struct InstView {
@@ -142,7 +151,9 @@ struct InstView {
   long pitch, plane;
   int Nx, Ny;
   double h, dt;
-  double p[4];
+  double p[kNumParams];
+  const double* psi;  // demagnetising potential of the stage point (null: none)
+  long psi_pitch;
 };
 
 template <class T>
@@ -154,7 +165,9 @@ __device__ __forceinline__ InstView<T> view_of(const Bufs<T>& B, const Coeffs& c
   V.pitch = B.pitch; V.plane = B.plane;
   V.Nx = B.Nx; V.Ny = B.Ny;
   V.h = cf.h; V.dt = cf.dt;
-  for (int k = 0; k < 4; ++k) V.p[k] = cf.p[k];
+  for (int k = 0; k < kNumParams; ++k) V.p[k] = cf.p[k];
+  V.psi = B.psi;
+  V.psi_pitch = B.psi_pitch;
   return V;
 }
 
@@ -320,7 +333,12 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
           Jd[c].y = ey[c][r];
           Jd[c].xx = Jd[c].yy = Jd[c].xy = 0.0;
         }
-        const double e = density<TH>(Jd, V.p);
+        double e = density<TH>(Jd, V.p);
+        if (TH == kCM && V.psi != nullptr) {
+          double px, py;
+          psi_gradient(V.psi, V.psi_pitch, gi, gj, d1, px, py);
+          e += 0.5 * V.p[5] * (px * px + py * py);
+        }
         e_acc += e;
         if (!isfinite(e)) ++nf;
       }
@@ -376,6 +394,13 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
     for (int c = 0; c < C; ++c) Js[c] = J[c][r];
     T G[4];
     el_gradient<T, TH>(Js, V.p, G);
+    if (TH == kCM && V.psi != nullptr) {
+      // demagnetising force mu_d grad psi (Euler-Lagrange form)
+      double px, py;
+      psi_gradient(V.psi, V.psi_pitch, gi, gj, d1, px, py);
+      G[0] += (T)(V.p[5] * px);
+      G[1] += (T)(V.p[5] * py);
+    }
     if (unit_field(TH)) {
       const T gn = G[0] * Js[0].f + G[1] * Js[1].f + G[2] * Js[2].f;
 #pragma unroll
@@ -448,7 +473,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
 // the stage point with halo 4, forms the fluxes on the tile plus a ring of 2
 // and then G on the tile. Fluxes (3 per direction):
 //   Abelian Higgs  x: (P1, Q1, B)   y: (P2, Q2, B)     with D_k psi = P_k + i Q_k
-//   chiral magnet  x: J D_x n + D (0, -n3, n2)   y: J D_y n + D (n3, 0, -n1)
+//   chiral magnet  x: J D_x n + D (0, -n3, n2)   y: J D_y n + Dy (n3, 0, -n1)   (Dy = D bulk, -D Heusler)
 constexpr int kExTX = 64, kExTY = 16, kExRY = 4;
 
 template <class T, int LX>
@@ -483,7 +508,7 @@ __device__ __forceinline__ void site_fluxes(T* const (&s)[4], int ly, int lx, T 
     for (int c = 0; c < 3; ++c)
       F[c] = xdir ? u[c] + k2 * (u[c] * ww - w[c] * uw) : w[c] + k2 * (w[c] * uu - u[c] * uw);
   } else {
-    const T J = (T)V.p[0], Dm = (T)V.p[1];
+    const T J = (T)V.p[0], Dm = (T)V.p[1], Dy = (T)V.p[4];
     const int o = ly * LX + lx;
     T d[3];
     for (int c = 0; c < 3; ++c) {
@@ -493,7 +518,7 @@ __device__ __forceinline__ void site_fluxes(T* const (&s)[4], int ly, int lx, T 
     }
     const T n0 = s[0][o], n1 = s[1][o], n2 = s[2][o];
     if (xdir) { F[0] = J * d[0]; F[1] = J * d[1] - Dm * n2; F[2] = J * d[2] + Dm * n1; }
-    else { F[0] = J * d[0] + Dm * n2; F[1] = J * d[1]; F[2] = J * d[2] - Dm * n0; }
+    else { F[0] = J * d[0] + Dy * n2; F[1] = J * d[1]; F[2] = J * d[2] - Dy * n0; }
   }
 }
 
@@ -659,10 +684,10 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
     } else if (TH == kBS) {
       g[r][2] = -(T)V.p[1];  // d/dm of mu^2 (1 - m_z); the other terms are fluxes
     } else {
-      const T Dm = (T)V.p[1], K = (T)V.p[2], Bz = (T)V.p[3];
-      g[r][0] = -Dm * dy[2];
+      const T Dm = (T)V.p[1], K = (T)V.p[2], Bz = (T)V.p[3], Dy = (T)V.p[4];
+      g[r][0] = -Dy * dy[2];
       g[r][1] = Dm * dx[2];
-      g[r][2] = Dm * (dy[0] - dx[1]) - (T(2) * K * cen[r][2] + Bz);
+      g[r][2] = Dy * dy[0] - Dm * dx[1] - (T(2) * K * cen[r][2] + Bz);
     }
   }
 
@@ -1522,6 +1547,11 @@ __global__ void __launch_bounds__(256) obs_sites(Bufs<T> B, Coeffs cf, DevStatus
         Jd[c].xx = Jd[c].yy = Jd[c].xy = 0.0;
       }
       v[0] += density<TH>(Jd, cf.p);
+      if (TH == kCM && B.psi != nullptr) {
+        double px, py;
+        psi_gradient(B.psi, B.psi_pitch, i, j, c1, px, py);
+        v[0] += 0.5 * cf.p[5] * (px * px + py * py);
+      }
       const double tx = dx[1] * dy[2] - dx[2] * dy[1], ty = dx[2] * dy[0] - dx[0] * dy[2],
                    tz = dx[0] * dy[1] - dx[1] * dy[0];
       v[1] += f[0] * tx + f[1] * ty + f[2] * tz;
@@ -1659,8 +1689,9 @@ __global__ void __launch_bounds__(256) init_ansatz(Bufs<T> B, Coeffs cf, InitArg
       const double dx = x - ia.xy[0], dy = y - ia.xy[1];
       const double r = sqrt(dx * dx + dy * dy), th = atan2(dy, dx);
       const double Th = 2.0 * atan2(ia.R, r);
-      out[0] = sin(Th) * cos(th + ia.gamma);
-      out[1] = sin(Th) * sin(th + ia.gamma);
+      const double az = ia.w[0] * th + ia.gamma;  // vorticity w[0] (-1: antiskyrmion)
+      out[0] = sin(Th) * cos(az);
+      out[1] = sin(Th) * sin(az);
       out[2] = cos(Th);
     } else {
       out[2] = 1.0;

@@ -48,28 +48,29 @@ __device__ __forceinline__ double ah_density(const Jet<T> (&J)[4], double lambda
   return 0.5 * (rx * rx + ix * ix + ry * ry + iy * iy) + 0.5 * B * B + 0.125 * lambda * W * W;
 }
 
-// Chiral magnet (eq. (5), local terms, bulk DMI d_k = e_k), unit field n.
-// With curl n = (d_y n_z, -d_x n_z, d_x n_y - d_y n_x) in the plane:
-//   e = J/2 |grad n|^2 - D n . curl n + K (1 - n_z^2) + B (1 - n_z),
-//   G = -J lap n - 2 D curl n - (2 K n_z + B) e_z   (before projection).
+// Chiral magnet (eq. (5), local terms), unit field n, DMI vectors d_1 = e_1 and
+// d_2 = e_2 (bulk, Dy = D) or d_2 = -e_2 (Heusler, Dy = -D):
+//   e = J/2 |grad n|^2 + D e_1.(n x d_x n) + Dy e_2.(n x d_y n) + K (1 - n_z^2) + B (1 - n_z),
+//   G = -J lap n + 2 D (d_x n x e_1) + 2 Dy (d_y n x e_2) - (2 K n_z + B) e_z   (before projection),
+// with d_x n x e_1 = (0, d_x n_z, -d_x n_y) and d_y n x e_2 = (-d_y n_z, 0, d_y n_x). For the
+// bulk case the DMI force is -2 D curl n.
 template <class T>
-__device__ __forceinline__ void cm_el_gradient(const Jet<T> (&J)[4], T Jx, T Dm, T K, T Bz, T (&G)[4]) {
-  const T cx = J[2].y, cy = -J[2].x, cz = J[1].x - J[0].y;
-  G[0] = -Jx * (J[0].xx + J[0].yy) - T(2) * Dm * cx;
-  G[1] = -Jx * (J[1].xx + J[1].yy) - T(2) * Dm * cy;
-  G[2] = -Jx * (J[2].xx + J[2].yy) - T(2) * Dm * cz - (T(2) * K * J[2].f + Bz);
+__device__ __forceinline__ void cm_el_gradient(const Jet<T> (&J)[4], T Jx, T Dm, T K, T Bz, T Dy, T (&G)[4]) {
+  G[0] = -Jx * (J[0].xx + J[0].yy) - T(2) * Dy * J[2].y;
+  G[1] = -Jx * (J[1].xx + J[1].yy) + T(2) * Dm * J[2].x;
+  G[2] = -Jx * (J[2].xx + J[2].yy) + T(2) * (Dy * J[0].y - Dm * J[1].x) - (T(2) * K * J[2].f + Bz);
   G[3] = T(0);
 }
 
 template <class T>
-__device__ __forceinline__ double cm_density(const Jet<T> (&J)[4], double Jx, double Dm, double K,
-                                             double Bz) {
+__device__ __forceinline__ double cm_density(const Jet<T> (&J)[4], double Jx, double Dm, double K, double Bz,
+                                             double Dy) {
   double ex = 0.0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) ex += (double)J[c].x * J[c].x + (double)J[c].y * J[c].y;
   const double nx = J[0].f, ny = J[1].f, nz = J[2].f;
-  const double cx = J[2].y, cy = -(double)J[2].x, cz = (double)J[1].x - (double)J[0].y;
-  return 0.5 * Jx * ex - Dm * (nx * cx + ny * cy + nz * cz) + K * (1.0 - nz * nz) + Bz * (1.0 - nz);
+  const double dmi = Dm * (ny * (double)J[2].x - nz * (double)J[1].x) + Dy * (nz * (double)J[0].y - nx * (double)J[2].y);
+  return 0.5 * Jx * ex + dmi + K * (1.0 - nz * nz) + Bz * (1.0 - nz);
 }
 
 // Baby Skyrme model (Tab. 1) with the standard potential, unit field m:
@@ -116,16 +117,16 @@ constexpr bool el_mixed(int TH) { return TH != kCM; }       // the EL form uses 
 
 // Euler-Lagrange gradient and FP64 energy density of theory TH (p: theory parameters).
 template <class T, int TH>
-__device__ __forceinline__ void el_gradient(const Jet<T> (&J)[4], const double (&p)[4], T (&G)[4]) {
+__device__ __forceinline__ void el_gradient(const Jet<T> (&J)[4], const double (&p)[kNumParams], T (&G)[4]) {
   if (TH == kAH) ah_el_gradient<T>(J, (T)p[0], G);
-  else if (TH == kCM) cm_el_gradient<T>(J, (T)p[0], (T)p[1], (T)p[2], (T)p[3], G);
+  else if (TH == kCM) cm_el_gradient<T>(J, (T)p[0], (T)p[1], (T)p[2], (T)p[3], (T)p[4], G);
   else bs_el_gradient<T>(J, (T)(p[0] * p[0]), (T)p[1], G);
 }
 
 template <int TH>
-__device__ __forceinline__ double density(const Jet<double> (&J)[4], const double (&p)[4]) {
+__device__ __forceinline__ double density(const Jet<double> (&J)[4], const double (&p)[kNumParams]) {
   if (TH == kAH) return ah_density<double>(J, p[0]);
-  if (TH == kCM) return cm_density<double>(J, p[0], p[1], p[2], p[3]);
+  if (TH == kCM) return cm_density<double>(J, p[0], p[1], p[2], p[3], p[4]);
   return bs_density<double>(J, p[0] * p[0], p[1]);
 }
 

@@ -144,8 +144,9 @@ def ah_vortex_ansatz(Nx: int, Ny: int, h: float, centres, windings=None,
 
 def cm_skyrmion_ansatz(Nx: int, Ny: int, h: float, R: float = 2.0,
                        gamma: float = -math.pi / 2, centre=(0.0, 0.0),
-                       profile: str = "bp") -> np.ndarray:
-    """n = (sin T cos(th+gamma), sin T sin(th+gamma), cos T), halo n = e_3.
+                       profile: str = "bp", vorticity: int = 1) -> np.ndarray:
+    """n = (sin T cos(m th+gamma), sin T sin(m th+gamma), cos T), halo n = e_3,
+    m the vorticity (-1: antiskyrmion).
 
     ``profile='bp'``: T = 2 arctan(R / r) (Belavin-Polyakov).
     ``profile='gauss'``: T = pi exp(-(r/R)^2), a fast-decaying test texture.
@@ -161,7 +162,8 @@ def cm_skyrmion_ansatz(Nx: int, Ny: int, h: float, R: float = 2.0,
         T = math.pi * np.exp(-(r / R) ** 2)
     else:
         raise ValueError(profile)
-    out = np.stack([np.sin(T) * np.cos(th + gamma), np.sin(T) * np.sin(th + gamma), np.cos(T)])
+    az = vorticity * th + gamma
+    out = np.stack([np.sin(T) * np.cos(az), np.sin(T) * np.sin(az), np.cos(T)])
     m = ~interior_mask(Nx, Ny)
     out[0][m] = 0.0
     out[1][m] = 0.0

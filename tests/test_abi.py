@@ -133,3 +133,31 @@ def test_one_call_learned_start_rejects_null_arguments(L):
     N = ss._ssn_lib()
     assert N.ssn_init_field_workspace_bytes(None) == 0
     assert N.ssn_init_field(None, None, 0, None, None, 1.0, 0.0, 0.0, 0, 0.0, None, 0) == -1
+
+
+def _wsf(theory, f, i, Nx=64, Ny=48, dtype=None):
+    fa = (ctypes.c_double * max(1, len(f)))(*f)
+    ia = (ctypes.c_int * max(1, len(i)))(*i)
+    p = ss.ss_params(fa, len(f), ia, len(i))
+    n = ctypes.c_size_t(0)
+    rc = ss.lib().ss_workspace_bytes_for(theory.encode(), Nx, Ny, ctypes.byref(p),
+                                         ss.SS_F32 if dtype is None else dtype, ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_for_demagnetisation_and_dmi_options(L):
+    base = ss.ss_workspace_bytes("CM", 64, 48, ss.SS_F32)
+    assert _wsf("CM", [1, 1, 0.1, 0.6], []) == (0, base)
+    assert _wsf("CM", [1, 1, 0.1, 0.6], [0, ss.SS_DMI_HEUSLER]) == (0, base)  # Heusler DMI is local
+    rc, n = _wsf("CM", [1, 1, 2.0, 0.0, 1.057], [0, ss.SS_DMI_HEUSLER, 1])
+    # stage point (3 FP32 planes) + 7 FP64 planes on the lattice + 3 per coarser level
+    site = (64 + 4) * (48 + 4)
+    assert rc == 0 and n - base >= 10 * 8 * site and n - base < 3 * base
+    assert _wsf("AH", [1.0], [0, 0, 1])[0] == -1          # demagnetisation is the chiral magnet's
+    assert _wsf("AH", [1.0], [0, ss.SS_DMI_HEUSLER])[0] == -1
+    assert _wsf("CM", [1, 1, 2, 0, 1.0], [1, 0, 1])[0] == -1  # exact gradient with demagnetisation
+    assert _wsf("CM", [1, 1, 2, 0, 0.0], [0, 0, 1])[0] == -1  # mu_d must be positive
+    assert _wsf("CM", [1, 1, 2, 0], [0, 0, 1])[0] == -1       # mu_d missing
+    assert _wsf("CM", [1, 1, 2, 0, 1.0], [0, 0, 1, 0])[0] == -1  # ni > 3
+    assert _wsf("CM", [1, 1, 2, 0], [0, 2])[0] == -1          # unknown dmi_kind
+    assert L.ss_set_demag_iters(None, 2, 40) == -1

@@ -491,6 +491,25 @@ def test_heusler_dmi_favours_the_antiskyrmion(orc):
     assert abs(q - round(q)) < 1e-10 and round(q) == 1
 
 
+def test_observables_energy_includes_the_demagnetising_term(orc):
+    """The observables' energy is E_h of eq. (5) with its demagnetising term: equal to
+    the energy function's value, and above the local energy by mu_d/2 h^2 sum |grad psi|^2
+    of the oracle's own Poisson solution (a divergence-carrying Neel texture)."""
+    N, h = 40, 0.2
+    n = I.renormalise_interior(I.cm_skyrmion_ansatz(N, N, h, R=1.2, gamma=0.0) + I.noise(4, 3, N, N, 1e-3))
+    p1 = [1.0, 1.0, 0.3, 0.2, -1.0, 0.9]
+    p0 = p1[:5] + [0.0]
+    o1, o0 = orc.observables(CMX, n, h, p1), orc.observables(CMX, n, h, p0)
+    assert o1["E"] == pytest.approx(orc.energy(CMX, n, h, p1), rel=1e-13)
+    div = _eq1(n[0], 0, h) + _eq1(n[1], 1, h)  # d_x n_1 + d_y n_2
+    psi = np.pad(orc.poisson(div[2:-2, 2:-2], h), 2)  # zero outside the interior
+    gx, gy = _eq1(psi, 0, h)[2:-2, 2:-2], _eq1(psi, 1, h)[2:-2, 2:-2]
+    ed = 0.5 * 0.9 * h * h * float((gx * gx + gy * gy).sum())
+    assert ed > 1e-2
+    assert o1["E"] - o0["E"] == pytest.approx(ed, rel=1e-10)
+    assert o1["Q_bl"] == o0["Q_bl"]
+
+
 # ---------------------------------------------------------------- integrator
 
 def test_rk4_step_matches_closed_form_amplification(orc):
