@@ -22,7 +22,10 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 THEORIES = {"abelian_higgs": 0, "chiral_magnet": 1, "toy_harmonic": 2, "toy_offset": 3, "baby_skyrme": 4,
             # chiral magnet with a second DMI coefficient and demagnetisation:
             # params {J, D, K, B, Dy, mu_d} (Dy = D bulk, -D Heusler; mu_d = 0: no demagnetisation)
-            "chiral_magnet_ext": 5}
+            "chiral_magnet_ext": 5,
+            # rotating trapped BEC in trap units, params {g, Omega, N}; the flow holds
+            # the atom number N = h^2 sum |psi|^2 fixed
+            "bec": 6}
 COURANT = 0.5  # dt = C * h with the default C of Sec. 3.1
 GRAD_EXACT = 0  # G = h^-2 dE_h/dphi
 GRAD_EL = 1     # continuum Euler-Lagrange expression evaluated with eq. (1)-(2)
@@ -67,6 +70,7 @@ def lib():
         L.or_observables_ah.argtypes = [i, i, d, dp, dp, dp]
         L.or_observables_cm.argtypes = [i, i, d, dp, dp, dp]
         L.or_observables_unit.argtypes = [i, i, i, d, dp, dp, dp]
+        L.or_observables_bec.argtypes = [i, i, d, dp, dp, dp]
         L.or_poisson.argtypes = [i, i, d, dp, dp]
         _lib = L
     return _lib
@@ -178,6 +182,10 @@ def poisson(rhs, h) -> np.ndarray:
 def observables(theory, phi, h, params) -> dict:
     phi, p = _arr(phi), _arr(params)
     Nx, Ny = _dims(phi)
+    if _tid(theory) == 6:
+        out = np.zeros(3)
+        lib().or_observables_bec(Nx, Ny, h, _p(p), _p(phi), _p(out))
+        return {"E": out[0], "N": out[1], "Lz": out[2]}
     if _tid(theory) == 0:
         out = np.zeros(6)
         lib().or_observables_ah(Nx, Ny, h, _p(p), _p(phi), _p(out))

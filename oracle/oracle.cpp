@@ -48,7 +48,7 @@
 
 namespace {
 
-enum Theory { TH_AH = 0, TH_CM = 1, TH_TOY = 2, TH_TOY_OFFSET = 3, TH_BS = 4, TH_CMX = 5 };
+enum Theory { TH_AH = 0, TH_CM = 1, TH_TOY = 2, TH_TOY_OFFSET = 3, TH_BS = 4, TH_CMX = 5, TH_BEC = 6 };
 
 int n_components(int theory) {
   switch (theory) {
@@ -58,6 +58,7 @@ int n_components(int theory) {
     case TH_TOY_OFFSET: return 1;
     case TH_BS: return 3;   // m_1, m_2, m_3
     case TH_CMX: return 3;  // chiral magnet with a general DMI and demagnetisation
+    case TH_BEC: return 2;  // Re psi, Im psi
   }
   return -1;
 }
@@ -114,11 +115,18 @@ template <class T>
 struct Jet {
   T f[4];
   T d[2][4];  // d[axis][component]
+  double x, y;  // position of the site (for the BEC's trap and rotation)
 };
+
+// Site coordinates: cell-centred, the origin at the lattice centre.
+double site_x(const Lat& L, int i) { return (i - 0.5 * (L.Nx - 1)) * L.h; }
+double site_y(const Lat& L, int j) { return (j - 0.5 * (L.Ny - 1)) * L.h; }
 
 template <class T>
 Jet<T> jet_at(const T* phi, const Lat& L, int C, int j, int i) {
   Jet<T> J;
+  J.x = site_x(L, i);
+  J.y = site_y(L, j);
   for (int c = 0; c < C; ++c) {
     J.f[c] = phi[L.at(c, j, i)];
     J.d[0][c] = deriv(phi, L, c, j, i, 0);
@@ -228,6 +236,34 @@ void bs_partials(const Jet<double>& Jt, double kappa, double mu2, double g[4], d
   g[3] = F[0][3] = F[1][3] = 0.0;
 }
 
+// --- Rotating trapped Bose-Einstein condensate (Sec. 4.3) --------------------
+// Trap units (hbar = m = omega = 1), psi = u + i w:
+//   e = 1/2 |grad psi|^2 + 1/2 r^2 |psi|^2 + g/2 |psi|^4 - Omega Re(psi* L_z psi),
+//   L_z = -i (x d_y - y d_x), so Re(psi* L_z psi) = u (x w_y - y w_x) - w (x u_y - y u_x)
+//   (the imaginary part is a total derivative). p = {g, Omega, N}; N = h^2 sum |psi|^2
+// is held fixed by the flow.
+template <class T>
+T bec_density(const Jet<T>& J, double g, double Om) {
+  const T u = J.f[0], w = J.f[1];
+  const T ux = J.d[0][0], uy = J.d[1][0], wx = J.d[0][1], wy = J.d[1][1];
+  const T rho = u * u + w * w;
+  const double r2 = J.x * J.x + J.y * J.y;
+  const T lz = u * (J.x * wy - J.y * wx) - w * (J.x * uy - J.y * ux);
+  return 0.5 * (ux * ux + uy * uy + wx * wx + wy * wy) + 0.5 * r2 * rho + 0.5 * g * rho * rho - Om * lz;
+}
+
+void bec_partials(const Jet<double>& J, double g, double Om, double gg[4], double F[2][4]) {
+  const double u = J.f[0], w = J.f[1];
+  const double ux = J.d[0][0], uy = J.d[1][0], wx = J.d[0][1], wy = J.d[1][1];
+  const double rho = u * u + w * w, r2 = J.x * J.x + J.y * J.y, x = J.x, y = J.y;
+  gg[0] = r2 * u + 2.0 * g * rho * u - Om * (x * wy - y * wx);
+  gg[1] = r2 * w + 2.0 * g * rho * w + Om * (x * uy - y * ux);
+  F[0][0] = ux - Om * y * w;
+  F[1][0] = uy + Om * x * w;
+  F[0][1] = wx + Om * y * u;
+  F[1][1] = wy - Om * x * u;
+}
+
 // --- Harmonic toy theories (tests of the integrator and stop rules only) ------
 // e = m2/2 phi^2, and e = m2/2 phi^2 + e0 (a floor under the energy, so that its
 // relative change over a window tends to zero and the stall rule can fire).
@@ -242,6 +278,7 @@ T density(int theory, const Jet<T>& Jt, const double* p) {
     case TH_CMX: return cm_density(Jt, p[0], p[1], p[2], p[3], p[4]);
     case TH_TOY_OFFSET: return toy_density(Jt, p[0]) + p[1];
     case TH_BS: return bs_density(Jt, p[0], p[1]);
+    case TH_BEC: return bec_density(Jt, p[0], p[1]);
     default: return toy_density(Jt, p[0]);
   }
 }
@@ -253,6 +290,7 @@ void partials(int theory, const Jet<double>& Jt, const double* p, double g[4], d
     case TH_CM: cm_partials(Jt, p[0], p[1], p[2], p[3], p[1], g, F); break;
     case TH_CMX: cm_partials(Jt, p[0], p[1], p[2], p[3], p[4], g, F); break;
     case TH_BS: bs_partials(Jt, p[0], p[1], g, F); break;
+    case TH_BEC: bec_partials(Jt, p[0], p[1], g, F); break;
     default: g[0] = p[0] * Jt.f[0]; break;
   }
 }
@@ -267,10 +305,13 @@ struct ELJet {
   double d[2][4];   // first derivatives d[axis][c]
   double dd[2][4];  // pure second derivatives dd[axis][c]
   double dxy[4];    // mixed derivative
+  double x, y;      // site position
 };
 
 ELJet el_jet_at(const double* phi, const Lat& L, int C, int j, int i) {
   ELJet J;
+  J.x = site_x(L, i);
+  J.y = site_y(L, j);
   for (int c = 0; c < 4; ++c) {
     J.f[c] = J.d[0][c] = J.d[1][c] = J.dd[0][c] = J.dd[1][c] = J.dxy[c] = 0.0;
   }
@@ -345,6 +386,18 @@ void bs_el(const ELJet& J, double kappa, double mu2, double G[4]) {
   }
   G[2] -= mu2;
   G[3] = 0.0;
+}
+
+// BEC: G_u = -lap u + r^2 u + 2 g |psi|^2 u - 2 Omega (x d_y - y d_x) w,
+//      G_w = -lap w + r^2 w + 2 g |psi|^2 w + 2 Omega (x d_y - y d_x) u
+// (the rotation term's two parts, from the density and from its flux, are equal).
+void bec_el(const ELJet& J, double g, double Om, double G[4]) {
+  const double u = J.f[0], w = J.f[1], x = J.x, y = J.y;
+  const double rho = u * u + w * w, r2 = x * x + y * y;
+  const double Dw = x * J.d[1][1] - y * J.d[0][1], Du = x * J.d[1][0] - y * J.d[0][0];
+  G[0] = -(J.dd[0][0] + J.dd[1][0]) + r2 * u + 2.0 * g * rho * u - 2.0 * Om * Dw;
+  G[1] = -(J.dd[0][1] + J.dd[1][1]) + r2 * w + 2.0 * g * rho * w + 2.0 * Om * Du;
+  G[2] = G[3] = 0.0;
 }
 
 // Neumaier-compensated sum.
@@ -483,6 +536,7 @@ void gradient_el(int theory, const Lat& L, const double* p, const double* phi, d
       else if (theory == TH_CM) cm_el(J, p[0], p[1], p[2], p[3], p[1], g);
       else if (theory == TH_CMX) cm_el(J, p[0], p[1], p[2], p[3], p[4], g);
       else if (theory == TH_BS) bs_el(J, p[0], p[1], g);
+      else if (theory == TH_BEC) bec_el(J, p[0], p[1], g);
       else g[0] = p[0] * J.f[0];
       for (int c = 0; c < C; ++c) G[L.at(c, j, i)] = g[c];
     }
@@ -543,17 +597,51 @@ void tangent_project(const Lat& L, const double* n, double* X) {
 // Theories of a unit-vector field (chiral magnet, Baby Skyrme).
 bool unit_theory(int theory) { return theory == TH_CM || theory == TH_BS || theory == TH_CMX; }
 
+// Theories whose flow holds a global norm fixed: the BEC's atom number
+// N = h^2 sum |psi|^2 (Sec. 4.3), p[2] = N.
+bool norm_theory(int theory) { return theory == TH_BEC; }
+
+// Interior sum of a . b over all components.
+double interior_dot(const Lat& L, int C, const double* a, const double* b) {
+  KSum s;
+  for (int c = 0; c < C; ++c)
+    for (int j = 0; j < L.Ny; ++j)
+      for (int i = 0; i < L.Nx; ++i) s.add(a[L.at(c, j, i)] * b[L.at(c, j, i)]);
+  return s.value();
+}
+
+// Scale the interior so that h^2 sum |phi|^2 = N (the halo keeps its values).
+void normalise_global(const Lat& L, int C, double N, double* phi) {
+  const double c = std::sqrt(N / (L.h * L.h * interior_dot(L, C, phi, phi)));
+  for (int cc = 0; cc < C; ++cc)
+    for (int j = 0; j < L.Ny; ++j)
+      for (int i = 0; i < L.Nx; ++i) phi[L.at(cc, j, i)] *= c;
+}
+
+// Remove from X its component along phi in the interior inner product (the
+// tangent space of the sphere h^2 sum |phi|^2 = N).
+void project_global(const Lat& L, int C, const double* phi, double* X) {
+  const double m = interior_dot(L, C, phi, X) / interior_dot(L, C, phi, phi);
+  for (int c = 0; c < C; ++c)
+    for (int j = 0; j < L.Ny; ++j)
+      for (int i = 0; i < L.Nx; ++i) X[L.at(c, j, i)] -= m * phi[L.at(c, j, i)];
+}
+
 // The force used by the flow: -G at the stage point; for the chiral magnet the
 // stage point is first put back on the unit sphere and -G is projected onto its
-// tangent plane.
+// tangent plane; for the BEC the stage point is scaled to the atom number N and
+// -G is projected onto the tangent space of that sphere (the chemical potential
+// mu = <phi, G> / <phi, phi> is the multiplier of the constraint).
 void acceleration(int theory, int mode, const Lat& L, const double* p, const double* stage, double* a) {
   int C = n_components(theory);
   long n = (long)C * L.plane();
   std::vector<double> s(stage, stage + n);
   if (unit_theory(theory)) normalise_interior(L, s.data());
+  if (norm_theory(theory)) normalise_global(L, C, p[2], s.data());
   if (mode == 0) gradient(theory, L, p, s.data(), a);
   else gradient_el(theory, L, p, s.data(), a);
   if (unit_theory(theory)) tangent_project(L, s.data(), a);
+  if (norm_theory(theory)) project_global(L, C, s.data(), a);
   for (long k = 0; k < n; ++k) a[k] = -a[k];
 }
 
@@ -594,6 +682,10 @@ void rk4_step(int theory, int mode, const Lat& L, const double* p, double dt, do
     normalise_interior(L, phi);
     tangent_project(L, phi, v);
   }
+  if (norm_theory(theory)) {
+    normalise_global(L, C, p[2], phi);
+    project_global(L, C, phi, v);
+  }
 }
 
 // The other integrators of the flow (Sec. 3.2 names RK4 as one choice of explicit
@@ -622,6 +714,7 @@ void one_pass_step(int theory, int mode, int scheme, const Lat& L, const double*
         else phi[k] += 0.5 * dt * dt * a0[k];
       }
   if (unit_theory(theory)) normalise_interior(L, phi);
+  if (norm_theory(theory)) normalise_global(L, C, p[2], phi);
   if (scheme != SCHEME_VV) return;
   acceleration(theory, mode, L, p, phi, a1.data());
   for (int c = 0; c < C; ++c)
@@ -631,6 +724,7 @@ void one_pass_step(int theory, int mode, int scheme, const Lat& L, const double*
         v[k] += 0.5 * dt * (a0[k] + a1[k]);
       }
   if (unit_theory(theory)) tangent_project(L, phi, v);
+  if (norm_theory(theory)) project_global(L, C, phi, v);
 }
 
 void step_scheme(int theory, int mode, int scheme, const Lat& L, const double* p, double dt, double* phi, double* v) {
@@ -881,6 +975,24 @@ void or_observables_unit(int theory, int Nx, int Ny, double h, const double* p, 
   out[0] = h * h * sE.value() + (has_demag(theory, p) ? demag_energy(L, p[5], phi) : 0.0);
   out[1] = h * h * sQ.value() / (4.0 * pi);
   out[2] = sBL.value() / (4.0 * pi);
+}
+
+// BEC observables (Sec. 4.3): out = {E_h, N = h^2 sum |psi|^2, L = h^2 sum Re(psi* L_z psi)}
+// with L_z = -i (x d_y - y d_x) and eq. (1) derivatives.
+void or_observables_bec(int Nx, int Ny, double h, const double* p, const double* phi, double* out) {
+  Lat L(Nx, Ny, h);
+  KSum sE, sN, sL;
+  for (int j = 0; j < Ny; ++j)
+    for (int i = 0; i < Nx; ++i) {
+      Jet<double> J = jet_at(phi, L, 2, j, i);
+      sE.add(bec_density(J, p[0], p[1]));
+      const double u = J.f[0], w = J.f[1];
+      sN.add(u * u + w * w);
+      sL.add(u * (J.x * J.d[1][1] - J.y * J.d[0][1]) - w * (J.x * J.d[1][0] - J.y * J.d[0][0]));
+    }
+  out[0] = h * h * sE.value();
+  out[1] = h * h * sN.value();
+  out[2] = h * h * sL.value();
 }
 
 }  // extern "C"

@@ -30,6 +30,8 @@ void or_minimise_scheme(int theory, int mode, int scheme, int Nx, int Ny, double
 void or_observables_ah(int Nx, int Ny, double h, const double* p, const double* phi, double* out);
 void or_observables_cm(int Nx, int Ny, double h, const double* p, const double* phi, double* out);
 void or_observables_unit(int theory, int Nx, int Ny, double h, const double* p, const double* phi, double* out);
+void or_observables_bec(int Nx, int Ny, double h, const double* p, const double* phi, double* out);
+void or_poisson(int Nx, int Ny, double h, const double* rhs, double* psi);
 }
 
 namespace {
@@ -55,7 +57,7 @@ std::vector<double> field(int C, int Nx, int Ny, bool unit) {
 int check_theory(int theory, const double* p, int Nx, int Ny) {
   const int C = or_components(theory);
   const double h = 0.3;
-  const bool unit = theory == 1 || theory == 4;
+  const bool unit = theory == 1 || theory == 4 || theory == 5;
   std::vector<double> phi = field(C, Nx, Ny, unit), zero(phi.size(), 0.0), G(phi.size()), a(phi.size());
   std::vector<double> dens((size_t)Nx * Ny), out(8), info(6);
   double acc = or_energy(theory, Nx, Ny, h, p, phi.data());
@@ -83,7 +85,8 @@ int check_theory(int theory, const double* p, int Nx, int Ny) {
   }
   if (theory == 0) or_observables_ah(Nx, Ny, h, p, phi.data(), out.data());
   if (theory == 1) or_observables_cm(Nx, Ny, h, p, phi.data(), out.data());
-  if (theory == 4) or_observables_unit(4, Nx, Ny, h, p, phi.data(), out.data());
+  if (theory == 4 || theory == 5) or_observables_unit(theory, Nx, Ny, h, p, phi.data(), out.data());
+  if (theory == 6) or_observables_bec(Nx, Ny, h, p, phi.data(), out.data());
   acc += out[0];
   return std::isfinite(acc) ? 0 : 1;
 }
@@ -98,6 +101,12 @@ int main() {
   bad += check_theory(2, p_toy, 5, 6);
   bad += check_theory(3, p_toy, 6, 5);
   bad += check_theory(4, p_bs, 7, 8);
+  const double p_cmx[6] = {1.0, 0.9, 0.3, 0.1, -0.9, 0.7}, p_bec[3] = {1.2, 0.6, 2.0};
+  bad += check_theory(5, p_cmx, 9, 8);
+  bad += check_theory(6, p_bec, 8, 9);
+  std::vector<double> rhs(7 * 6, 0.3), psi(7 * 6, 0.0);
+  or_poisson(7, 6, 0.3, rhs.data(), psi.data());
+  if (!std::isfinite(psi[20])) ++bad;
   if (bad) {
     std::printf("non-finite result\n");
     return 1;

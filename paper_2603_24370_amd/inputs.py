@@ -171,6 +171,29 @@ def cm_skyrmion_ansatz(Nx: int, Ny: int, h: float, R: float = 2.0,
     return out
 
 
+# ---------------------------------------------------------------------------
+# Rotating trapped BEC: Gaussian cloud with optional vortices (psi = u + i w)
+# ---------------------------------------------------------------------------
+
+def bec_ansatz(Nx: int, Ny: int, h: float, R: float = 1.0, centres=(), windings=None,
+               xi: float = 1.0) -> np.ndarray:
+    """psi = exp(-r^2 / (2 R^2)) / (sqrt(pi) R) * prod_k tanh(r_k / xi) exp(i n_k theta_k)
+    on the interior, psi = 0 on the halo. Returns float64 of shape (2, Ny+4, Nx+4)."""
+    centres = np.asarray(centres, dtype=np.float64).reshape(-1, 2)
+    if windings is None:
+        windings = np.ones(len(centres), dtype=np.float64)
+    X, Y = grid(Nx, Ny, h)
+    amp = np.exp(-(X * X + Y * Y) / (2.0 * R * R)) / (math.sqrt(math.pi) * R)
+    phase = np.zeros_like(X)
+    for (xk, yk), nk in zip(centres, np.asarray(windings, dtype=np.float64)):
+        dx, dy = X - xk, Y - yk
+        amp = amp * np.tanh(np.hypot(dx, dy) / xi)
+        phase = phase + nk * np.arctan2(dy, dx)
+    out = np.stack([amp * np.cos(phase), amp * np.sin(phase)])
+    out[:, ~interior_mask(Nx, Ny)] = 0.0
+    return out
+
+
 def renormalise_interior(n: np.ndarray) -> np.ndarray:
     """Rescale each interior 3-vector to unit length (input preparation only)."""
     Ny, Nx = n.shape[1] - 2 * HALO, n.shape[2] - 2 * HALO

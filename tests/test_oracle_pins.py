@@ -18,6 +18,7 @@ P_AH = [1.0]
 P_CM = [1.0, 1.0, 0.1, 0.6]
 P_BS = [1.0, 0.1]  # kappa, mu^2
 CMX = "chiral_magnet_ext"  # {J, D, K, B, Dy, mu_d}: second DMI coefficient and demagnetisation
+BEC = "bec"  # rotating trapped condensate in trap units, {g, Omega, N}
 
 
 def _rand_field(rng, C, Nx, Ny, scale=1.0):
@@ -261,7 +262,8 @@ def test_bs_energy_bounds_the_charge(orc):
 # ----------------------------------------------------------------- gradients
 
 @pytest.mark.parametrize("theory,C,params", [(AH, 4, [0.7]), (CM, 3, [1.3, 0.8, 0.1, 0.6]), (BS, 3, [1.3, 0.4]),
-                                            (CMX, 3, [1.3, 0.8, 0.1, 0.6, -0.8, 0.0])])
+                                            (CMX, 3, [1.3, 0.8, 0.1, 0.6, -0.8, 0.0]),
+                                            (BEC, 2, [2.3, 0.7, 1.0])])
 def test_exact_gradient_matches_complex_step(orc, theory, C, params):
     """G = h^-2 dE_h/dphi at every interior site and component (complex step, eps = 1e-30)."""
     rng = np.random.default_rng(1)
@@ -280,7 +282,8 @@ def test_exact_gradient_matches_complex_step(orc, theory, C, params):
 
 @pytest.mark.parametrize("theory,C,params", [(AH, 4, [1.0]), (CM, 3, P_CM), (BS, 3, [0.8, 0.2]),
                                             (CMX, 3, [1.1, 0.9, 0.2, 0.5, -0.9, 0.0]),
-                                            (CMX, 3, [1.1, 0.9, 0.2, 0.5, -0.9, 1.3])])
+                                            (CMX, 3, [1.1, 0.9, 0.2, 0.5, -0.9, 1.3]),
+                                            (BEC, 2, [1.7, 0.6, 1.0])])
 def test_exact_gradient_matches_central_differences(orc, theory, C, params):
     rng = np.random.default_rng(2)
     Nx, Ny, h, eps = 6, 6, 0.25, 1e-6
@@ -331,6 +334,21 @@ def _sympy_el(theory, params):
                 cr = sp.Matrix(d[i]).cross(sp.Matrix(d[j]))
                 sk += cr.dot(cr)
         e = sum(v * v for v in dx) / 2 + sum(v * v for v in dy) / 2 + kappa ** 2 / 4 * sk + mu2 * (1 - s[2])
+    elif theory == BEC:
+        g, Om = params[:2]
+        u0 = 0.3 + 0.4 * x - 0.1 * y ** 2 + 0.02 * x ** 3 * y - 0.01 * x ** 4
+        w0 = -0.2 + 0.3 * y + 0.1 * x * y - 0.03 * x ** 2 * y ** 2 + 0.015 * y ** 4
+        comps = [u0, w0]
+        s = sp.symbols("s0:2", real=True)
+        dx = sp.symbols("dx0:2", real=True)
+        dy = sp.symbols("dy0:2", real=True)
+        # Sec. 4.3 in trap units: 1/2 |grad psi|^2 + 1/2 r^2 |psi|^2 + g/2 |psi|^4 - Omega Re(psi* L_z psi),
+        # L_z psi = -i (x d_y psi - y d_x psi), formed with sympy's complex arithmetic
+        psi_c = s[0] - sp.I * s[1]
+        lz_psi = -sp.I * (x * (dy[0] + sp.I * dy[1]) - y * (dx[0] + sp.I * dx[1]))
+        rho = s[0] ** 2 + s[1] ** 2
+        e = (sum(v * v for v in dx) + sum(v * v for v in dy)) / 2 + (x ** 2 + y ** 2) / 2 * rho \
+            + g / 2 * rho ** 2 - Om * sp.re(sp.expand(psi_c * lz_psi))
     else:
         J, D, K, Bz = params[:4]
         Dy = params[4] if len(params) > 4 else D
@@ -361,7 +379,7 @@ def _sympy_el(theory, params):
 
 
 @pytest.mark.parametrize("theory,params", [(AH, [0.9]), (CM, [1.2, 0.7, 0.15, 0.4]), (BS, [1.1, 0.3]),
-                                           (CMX, [1.2, 0.7, 0.15, 0.4, -0.7, 0.0])])
+                                           (CMX, [1.2, 0.7, 0.15, 0.4, -0.7, 0.0]), (BEC, [1.9, 0.8, 1.0])])
 def test_el_gradient_equals_continuum_functional_derivative(orc, theory, params):
     """For fields of degree <= 4 in each variable the stencils of eq. (1)-(2) are
     exact, so the Euler-Lagrange form must equal the continuum functional
@@ -508,6 +526,100 @@ def test_observables_energy_includes_the_demagnetising_term(orc):
     assert ed > 1e-2
     assert o1["E"] - o0["E"] == pytest.approx(ed, rel=1e-10)
     assert o1["Q_bl"] == o0["Q_bl"]
+
+
+# ---------------------------------------------------------------- BEC (Sec. 4.3)
+
+def _bec_oscillator_state(N, h, m):
+    """psi = r^|m| e^{i m theta} e^{-r^2/2} / sqrt(pi |m|!): the 2-D oscillator state of
+    angular momentum m (trap units), with integral |psi|^2 = 1; zero on the halo."""
+    X, Y = I.grid(N, N, h)
+    r, th = np.hypot(X, Y), np.arctan2(Y, X)
+    amp = r ** abs(m) * np.exp(-r * r / 2) / math.sqrt(math.pi * math.factorial(abs(m)))
+    f = np.stack([amp * np.cos(m * th), amp * np.sin(m * th)])
+    f[:, ~I.interior_mask(N, N)] = 0.0
+    return f
+
+
+@pytest.mark.parametrize("m", [0, 1, -1])
+def test_bec_oscillator_states_have_closed_form_energies(orc, m):
+    """Without interaction the density's kinetic + trap part has the oscillator energy
+    |m| + 1 per atom and the rotation term -Omega m: E = |m| + 1 - Omega m,
+    L_z = m, N = 1 (a wrong sign of the rotation term would swap m = +-1). The
+    errors fall at fourth order in h."""
+    Om = 0.6
+    errs = []
+    for N, h in [(40, 0.3), (80, 0.15)]:
+        f = _bec_oscillator_state(N, h, m)
+        o = orc.observables(BEC, f, h, [0.0, Om, 1.0])
+        assert o["E"] == pytest.approx(orc.energy(BEC, f, h, [0.0, Om, 1.0]), rel=1e-14)
+        assert o["N"] == pytest.approx(1.0, abs=1e-9)
+        errs.append(abs(o["E"] - (abs(m) + 1 - Om * m)))
+        assert o["Lz"] == pytest.approx(m, abs=5e-3)
+    assert errs[1] < 5e-4 and errs[0] / errs[1] > 12.0, errs
+
+
+@pytest.mark.parametrize("m", [0, 1])
+def test_bec_oscillator_states_are_stationary(orc, m):
+    """The Euler-Lagrange gradient of an oscillator state at g = 0 is 2 (|m| + 1 - Omega m)
+    psi (G is twice the Gross-Pitaevskii operator in real components), to O(h^4): the
+    constrained force, G minus its projection on psi, vanishes."""
+    Om, N, h = 0.4, 60, 0.2
+    f = _bec_oscillator_state(N, h, m)
+    G = orc.gradient(BEC, f, h, [0.0, Om, 1.0], mode=orc.GRAD_EL)
+    mu2 = 2 * (abs(m) + 1 - Om * m)
+    assert np.abs(G - mu2 * f)[:, 2:-2, 2:-2].max() < 2e-3 * np.abs(mu2 * f).max()
+    a = orc.acceleration(BEC, f, h, [0.0, Om, 1.0])
+    assert np.abs(a).max() < 2e-3 * np.abs(mu2 * f).max()
+
+
+def test_bec_flow_holds_the_atom_number(orc):
+    """Every step of each integrator ends with h^2 sum |psi|^2 = N and the velocity
+    orthogonal to psi (the tangent space of the constraint)."""
+    N, h, Nat = 32, 0.3, 3.0
+    f = I.bec_ansatz(N, N, h, R=1.3, centres=[(0.4, -0.2)]) + I.noise(7, 2, N, N, 1e-2)
+    for scheme in ("rk4", "vv", "gf"):
+        phi, v = f, np.zeros_like(f)
+        for _ in range(4):
+            phi, v, _, _ = orc.flow(BEC, phi, v, h, [1.5, 0.5, Nat], 1, scheme=scheme)
+            assert h * h * float((phi[:, 2:-2, 2:-2] ** 2).sum()) == pytest.approx(Nat, rel=1e-13)
+            dot = float((phi[:, 2:-2, 2:-2] * v[:, 2:-2, 2:-2]).sum())
+            assert abs(dot) <= 1e-12 * max(1.0, float(np.abs(v).max())) * phi.size
+        assert np.array_equal(phi[:, :2, :], f[:, :2, :])  # the halo is never written
+
+
+def test_bec_minimum_without_interaction_is_the_oscillator_ground_state(orc):
+    """From a displaced, noisy cloud the arrested flow reaches the ground state at
+    g = 0, Omega = 0.5 < 1: E = N (one trap quantum per atom; the rotation term
+    vanishes for L_z = 0) up to the O(h^4) discretisation error (5e-4 at h = 0.25).
+    The minimum lies below the discrete energy of the sampled analytic ground state
+    scaled to N (variational), and above it by no more than O(h^8)."""
+    N, h, Nat = 48, 0.25, 2.0
+    f = I.bec_ansatz(N, N, h, R=1.6, centres=[]) * 1.3 + I.noise(3, 2, N, N, 1e-2)
+    phi, _, info = orc.minimise(BEC, f, h, [0.0, 0.5, Nat], grad_tol=1e-8, max_steps=20000)
+    assert info["reason"] == 1, info
+    o = orc.observables(BEC, phi, h, [0.0, 0.5, Nat])
+    assert o["N"] == pytest.approx(Nat, rel=1e-12)
+    assert o["E"] == pytest.approx(Nat, rel=1e-3)
+    g0 = _bec_oscillator_state(N, h, 0)
+    g0 *= math.sqrt(Nat / (h * h * float((g0 ** 2).sum())))
+    e0 = orc.energy(BEC, g0, h, [0.0, 0.5, Nat])
+    assert e0 - 1e-6 * Nat < o["E"] <= e0 + 1e-12
+    assert abs(o["Lz"]) < 1e-6
+
+
+def test_bec_thomas_fermi_limit(orc):
+    """Strong interaction, no rotation: the minimum approaches the Thomas-Fermi energy
+    E_TF = 2/3 mu N with mu = sqrt(g N / pi) (2-D, trap units; the kinetic energy is
+    dropped), from above, within a few percent for g N = 200."""
+    N, h, Nat, g = 64, 0.25, 1.0, 200.0
+    mu = math.sqrt(g * Nat / math.pi)
+    f = I.bec_ansatz(N, N, h, R=3.0)
+    phi, _, info = orc.minimise(BEC, f, h, [g, 0.0, Nat], grad_tol=1e-6, max_steps=40000)
+    assert info["reason"] == 1, info
+    E = orc.energy(BEC, phi, h, [g, 0.0, Nat])
+    E_tf = 2.0 / 3.0 * mu * Nat
+    assert E_tf < E < 1.05 * E_tf, (E, E_tf)
 
 
 # ---------------------------------------------------------------- integrator
