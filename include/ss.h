@@ -40,6 +40,18 @@
  *       C = 3 components (m_1, m_2, m_3), |m| = 1, the standard potential,
  *       e = 1/2 |grad m|^2 + kappa^2/4 sum_ij |d_i m x d_j m|^2 + mu^2 (1 - m_3).
  *       params.f = {kappa, mu^2 [, courant]}. Single contexts only (no batches).
+ *   "bec" (aliases "bose_einstein", "Bose-Einstein condensate", "BEC"):
+ *       the rotating trapped condensate of Sec. 4.3 in trap units (hbar = m = omega = 1),
+ *       C = 2 components (Re psi, Im psi), sites at x_i = (i - (Nx-1)/2) h,
+ *       e = 1/2 |grad psi|^2 + 1/2 r^2 |psi|^2 + g/2 |psi|^4 - Omega Re(psi* L_z psi),
+ *       L_z = -i (x d_y - y d_x). params.f = {g, Omega, N [, courant]}: the flow
+ *       holds the atom number N = h^2 sum |psi|^2 fixed (every stage point is
+ *       scaled to N and the force projected on the tangent space of that sphere,
+ *       with the chemical potential as multiplier; after each step the field is
+ *       scaled and the velocity projected). Euler-Lagrange gradient, RK4,
+ *       SS_PLAN_STAGES and single contexts only; ss_energy_grad returns the
+ *       projected gradient at the field scaled to N and the energy of the field as
+ *       given.
  *   params.i (optional, ni <= 3) = {grad_mode, dmi_kind, demag}:
  *   grad_mode SS_GRAD_EL (default) evaluates the continuum Euler-Lagrange
  *   derivative with eq. (1)-(2); SS_GRAD_EXACT uses h^-2 dE_h/dphi, the exact
@@ -94,6 +106,7 @@ extern "C" {
 #define SS_THEORY_AH 0
 #define SS_THEORY_CM 1
 #define SS_THEORY_BS 2
+#define SS_THEORY_BEC 3
 
 /* gradient forms */
 #define SS_GRAD_EL 0
@@ -162,7 +175,10 @@ typedef struct {
  * counter-clockwise; bogo_r1 = h^2 sum |(P1 - Q2) + i (Q1 + P2)|^2,
  * bogo_r2 = h^2 sum (B - W/2)^2. Chiral magnet: q_fd = h^2/(4 pi) sum
  * n.(D1 n x D2 n); q_bl = Berg-Luescher solid-angle charge over all plaquettes
- * of the padded lattice. Fields that do not apply are 0. */
+ * of the padded lattice (also the Baby Skyrme model). BEC (Sec. 4.3): atoms and
+ * lz below. energy includes every term of the theory (with the chiral magnet's
+ * demagnetising term, from a fresh solve of the current field). Fields that do
+ * not apply are 0. */
 typedef struct {
   double energy;
   double flux;
@@ -173,6 +189,8 @@ typedef struct {
   double q_fd;
   double q_bl;
   double gnorm_inf;
+  double atoms; /* BEC: N = h^2 sum |psi|^2 */
+  double lz;    /* BEC: h^2 sum Re(psi* L_z psi), eq. (1) derivatives */
 } ss_obs;
 
 /* Canonical theory id of a name or alias (Sec. 2.3 registry), or SS_ETHEORY. */
@@ -221,6 +239,9 @@ int ss_set_field(ss_ctx* ctx, const void* field);
  *       A   = sum_k w_k (1 - exp(-r_k^2)) / r_k^2 (-(y - y_k), x - x_k);
  *     the halo holds the pure-gauge vacuum psi = exp(i sum w_k theta_k),
  *     A = sum_k w_k grad theta_k.
+ *   BEC, kind SS_ANSATZ_BEC: shape = {R, xi}, n >= 0 vortices at xy with windings
+ *     w (NULL = all +1): psi = exp(-r^2 / (2 R^2)) / (sqrt(pi) R) prod_k tanh(r_k / xi)
+ *     exp(i w_k theta_k) in the interior, psi = 0 on the halo (the flow scales it to N).
  *   Chiral magnet and Baby Skyrme, kind SS_ANSATZ_SKYRMION: n = 1, xy = centre, shape = {R, gamma},
  *     w = {m} (vorticity, a nonzero integer; NULL = 1; m = -1 is the
  *     antiskyrmion of Sec. 4.2):
@@ -232,6 +253,7 @@ int ss_set_field(ss_ctx* ctx, const void* field);
  * Synchronises. */
 #define SS_ANSATZ_VORTICES 0
 #define SS_ANSATZ_SKYRMION 1
+#define SS_ANSATZ_BEC 2
 int ss_init_ansatz(ss_ctx* ctx, int kind, int n, const double* xy, const double* w, const double* shape,
                    uint64_t seed, double noise_amp);
 

@@ -25,8 +25,8 @@ SS_PLAN_STAGES, SS_PLAN_FUSED = 0, 1
 SS_INTEG_RK4, SS_INTEG_VV, SS_INTEG_GF = 0, 1, 2
 INTEGRATORS = {"rk4": SS_INTEG_RK4, "vv": SS_INTEG_VV, "gf": SS_INTEG_GF}
 SS_NUM_PLANS = 2
-SS_THEORY_AH, SS_THEORY_CM, SS_THEORY_BS = 0, 1, 2
-SS_ANSATZ_VORTICES, SS_ANSATZ_SKYRMION = 0, 1
+SS_THEORY_AH, SS_THEORY_CM, SS_THEORY_BS, SS_THEORY_BEC = 0, 1, 2, 3
+SS_ANSATZ_VORTICES, SS_ANSATZ_SKYRMION, SS_ANSATZ_BEC = 0, 1, 2
 STOP_REASONS = {0: "none", 1: "grad", 2: "stall", 3: "max_steps", 4: "nonfinite", 5: "target"}
 
 
@@ -55,7 +55,8 @@ class ss_min_info(ctypes.Structure):
 
 class ss_obs(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
-                ("energy", "flux", "n_rho", "n_wind", "bogo_r1", "bogo_r2", "q_fd", "q_bl", "gnorm_inf")]
+                ("energy", "flux", "n_rho", "n_wind", "bogo_r1", "bogo_r2", "q_fd", "q_bl", "gnorm_inf", "atoms",
+                 "lz")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -503,6 +504,10 @@ class Solver:
                       vorticity=1):
         """Belavin-Polyakov ansatz; vorticity -1 gives the antiskyrmion."""
         ss_init_ansatz(self.ctx, SS_ANSATZ_SKYRMION, [centre], [float(vorticity)], [R, gamma], seed, noise_amp)
+
+    def init_bec(self, R=1.0, xi=1.0, centres=(), windings=None, seed=0, noise_amp=0.0):
+        """Gaussian cloud of radius R with vortices (core width xi) at the centres."""
+        ss_init_ansatz(self.ctx, SS_ANSATZ_BEC, list(centres), windings, [R, xi], seed, noise_amp)
 
     def set_demag_iters(self, iters_flow, iters_eval):
         ss_set_demag_iters(self.ctx, iters_flow, iters_eval)

@@ -24,6 +24,7 @@
 #include "../../include/ss.h"
 #include "ss_kernels.hpp"
 #include "ss_demag.hpp"
+#include "ss_bec.hpp"
 
 using namespace ss;
 
@@ -118,6 +119,18 @@ Layout make_layout(int C, int Nx, int Ny, int esize) {
   return L;
 }
 
+// BEC work region (after the flow's buffers): stage point and gradient sets,
+// kBecGroups * 4 partials and eight scalars. With base == nullptr only the size.
+size_t bec_region(const Layout& L, char* base, void** ptrs) {
+  const size_t sizes[4] = {L.set_bytes, L.set_bytes, (size_t)round_up(kBecGroups * 4 * 8, 256), 256};
+  size_t off = 0;
+  for (int k = 0; k < 4; ++k) {
+    if (ptrs) ptrs[k] = base + off;
+    off += sizes[k];
+  }
+  return off;
+}
+
 }  // namespace
 
 struct ss_batch;
@@ -152,6 +165,11 @@ struct ss_ctx {
     int nlev;
     DmLevel lv[kDmMaxLevels];
   } dm;
+  // BEC work buffers (theory SS_THEORY_BEC): stage point, gradient, partials, scalars
+  void* bec_S;
+  void* bec_G;
+  double* bec_part;
+  double* bec_sc;
 };
 
 namespace {
@@ -308,11 +326,46 @@ void demag_solve(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   }
 }
 
+// A BEC pass (RK4 stages, the check and the evaluation): the stage point and its
+// norm, its scale to the atom number, G and the sums for mu, mu, the force and the
+// pass's update; P4 ends with the step's constraint, a reducing pass with the
+// status update.
+template <class T, int PASS>
+void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
+  static_assert(PASS == kP1 || PASS == kP2 || PASS == kP3 || PASS == kP4 || PASS == kEval || PASS == kCheck,
+                "the BEC runs the RK4 stages");
+  BecBufs<T> W;
+  W.S = (T*)c->bec_S;
+  W.G = (T*)c->bec_G;
+  W.part = c->bec_part;
+  W.sc = c->bec_sc;
+  const int flow = PASS == kEval ? 0 : 1;
+  const dim3 g(kBecGroups), b(256), b1(64);
+  hipLaunchKernelGGL((bec_stage<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, a.src, W);
+  hipLaunchKernelGGL(bec_scale, dim3(1), b1, 0, s, (const double*)W.part, W.sc, a.cf, (const DevStatus*)c->st, flow);
+  hipLaunchKernelGGL((bec_grad<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, W, (const double*)W.sc);
+  hipLaunchKernelGGL(bec_mu, dim3(1), b1, 0, s, (const double*)W.part, W.sc, a.cf, (const DevStatus*)c->st, flow);
+  hipLaunchKernelGGL((bec_apply<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, W, (const double*)W.sc,
+                     a.out, a.out_pitch, a.out_plane);
+  if constexpr (PASS == kP4) {
+    hipLaunchKernelGGL(bec_fix_scalars, dim3(1), b1, 0, s, (const double*)W.part, W.sc, a.cf,
+                       (const DevStatus*)c->st);
+    hipLaunchKernelGGL((bec_fix<T>), g, b, 0, s, a.B, (const DevStatus*)c->st, (const double*)W.sc);
+  }
+  if constexpr (reduces(PASS))
+    hipLaunchKernelGGL((bec_finalise<PASS>), dim3(1), b1, 0, s, c->st, (const double*)W.part, (const double*)W.sc);
+}
+
 // A pass; a reducing pass (P1, evaluation, check) is followed by its finalise
 // launch, which sums the workgroup partials and updates the status. With
 // demagnetisation the pass is preceded by the solve for its stage point.
 template <class T, int PASS>
 void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
+  if (c->theory == SS_THEORY_BEC) {
+    if constexpr (PASS == kP1 || PASS == kP2 || PASS == kP3 || PASS == kP4 || PASS == kEval || PASS == kCheck)
+      bec_pass<T, PASS>(c, a, s);
+    return;
+  }
   if (c->dm.on) demag_solve<T, PASS>(c, a, s);
   int groups = c->L.nlaunch;  // workgroups launched = partials written
   if (c->grad_mode == SS_GRAD_EXACT) {
@@ -526,19 +579,23 @@ int ss_theory_id(const char* name) {
   static const char* ah[] = {"abelian_higgs", "abelian higgs", "ginzburg-landau", "gl", "ah", "ginzburg landau"};
   static const char* cm[] = {"chiral_magnet", "chiral magnet", "cm"};
   static const char* bs[] = {"baby_skyrme", "baby skyrme", "bs"};
+  static const char* bec[] = {"bec", "bose_einstein", "bose-einstein condensate", "bose einstein condensate",
+                              "rotating bec"};
   for (const char* a : ah)
     if (lower_eq(name, a)) return SS_THEORY_AH;
   for (const char* a : cm)
     if (lower_eq(name, a)) return SS_THEORY_CM;
   for (const char* a : bs)
     if (lower_eq(name, a)) return SS_THEORY_BS;
+  for (const char* a : bec)
+    if (lower_eq(name, a)) return SS_THEORY_BEC;
   return SS_ETHEORY;
 }
 
 int ss_components(const char* theory) {
   const int t = ss_theory_id(theory);
   if (t < 0) return t;
-  return t == SS_THEORY_AH ? 4 : 3;
+  return t == SS_THEORY_AH ? 4 : t == SS_THEORY_BEC ? 2 : 3;
 }
 
 int ss_workspace_bytes(const char* theory, int Nx, int Ny, int dtype, size_t* bytes) {
@@ -547,7 +604,8 @@ int ss_workspace_bytes(const char* theory, int Nx, int Ny, int dtype, size_t* by
   if (dtype != SS_F32 && dtype != SS_F64) return fail(SS_EINVAL, "dtype must be SS_F32 or SS_F64");
   if (Nx < 8 || Ny < 8 || Nx > 65536 || Ny > 65536) return fail(SS_ESHAPE, "Nx, Ny must lie in [8, 65536]");
   if (!bytes) return fail(SS_EINVAL, "bytes is NULL");
-  *bytes = make_layout(C, Nx, Ny, (int)esize_of(dtype)).total;
+  const Layout L = make_layout(C, Nx, Ny, (int)esize_of(dtype));
+  *bytes = L.total + (ss_theory_id(theory) == SS_THEORY_BEC ? bec_region(L, nullptr, nullptr) : 0);
   return SS_OK;
 }
 
@@ -577,28 +635,32 @@ int resolve_problem(const char* theory, int Nx, int Ny, double h, const ss_param
     return fail(SS_EINVAL, "DMI variants and demagnetisation belong to the chiral magnet");
   if (demag && grad_mode != SS_GRAD_EL)
     return fail(SS_EINVAL, "the demagnetising term runs with the Euler-Lagrange gradient (grad_mode SS_GRAD_EL)");
-  const int nf_need = th == SS_THEORY_AH ? 1 : th == SS_THEORY_CM ? 4 + demag : 2;
+  if (th == SS_THEORY_BEC && grad_mode != SS_GRAD_EL)
+    return fail(SS_EINVAL, "the BEC runs with the Euler-Lagrange gradient (grad_mode SS_GRAD_EL)");
+  const int nf_need = th == SS_THEORY_AH ? 1 : th == SS_THEORY_CM ? 4 + demag : th == SS_THEORY_BEC ? 3 : 2;
   if (!params->f || params->nf < nf_need || params->nf > nf_need + 1)
     return fail(SS_EINVAL, th == SS_THEORY_AH ? "abelian_higgs needs params.f = {lambda [, courant]}"
                            : th == SS_THEORY_CM
                                ? (demag ? "chiral_magnet with demagnetisation needs params.f = {J, D, K, B, mu_d [, courant]}"
                                         : "chiral_magnet needs params.f = {J, D, K, B [, courant]}")
-                               : "baby_skyrme needs params.f = {kappa, mu^2 [, courant]}");
+                           : th == SS_THEORY_BEC ? "bec needs params.f = {g, Omega, N [, courant]}"
+                                                 : "baby_skyrme needs params.f = {kappa, mu^2 [, courant]}");
   for (int k = 0; k < params->nf; ++k)
     if (!std::isfinite(params->f[k])) return fail(SS_EINVAL, "non-finite parameter");
   const double courant = params->nf > nf_need ? params->f[nf_need] : 0.5;
   if (!(courant > 0.0 && courant < 1.0)) return fail(SS_EINVAL, "courant number C must lie in (0, 1)");
   if (demag && !(params->f[4] > 0.0)) return fail(SS_EINVAL, "mu_d must be positive");
+  if (th == SS_THEORY_BEC && !(params->f[2] > 0.0)) return fail(SS_EINVAL, "the atom number N must be positive");
   pb->theory = th;
   pb->dtype = dtype;
   pb->grad_mode = grad_mode;
   pb->dmi_kind = dmi_kind;
   pb->demag = demag;
-  pb->C = th == SS_THEORY_AH ? 4 : 3;
+  pb->C = th == SS_THEORY_AH ? 4 : th == SS_THEORY_BEC ? 2 : 3;
   pb->nf_need = nf_need;
   pb->courant = courant;
   for (int k = 0; k < kNumParams; ++k) pb->p[k] = 0.0;
-  for (int k = 0; k < std::min(nf_need, 4); ++k) pb->p[k] = params->f[k];
+  for (int k = 0; k < std::min(nf_need, 4); ++k) pb->p[k] = params->f[k];  // BEC: {g, Omega, N}
   if (th == SS_THEORY_CM) {
     // d_1 = e_1 always; d_2 = e_2 (bulk) or -e_2 (Heusler): the y-derivative DMI coefficient
     pb->p[4] = dmi_kind == SS_DMI_HEUSLER ? -params->f[1] : params->f[1];
@@ -671,7 +733,8 @@ int ss_workspace_bytes_for(const char* theory, int Nx, int Ny, const ss_params* 
   if (rc) return rc;
   if (!bytes) return fail(SS_EINVAL, "bytes is NULL");
   const Layout L = make_layout(pb.C, Nx, Ny, (int)esize_of(dtype));
-  *bytes = L.total + (pb.demag ? demag_region(Nx, Ny, 1.0, L, (int)esize_of(dtype), nullptr, nullptr) : 0);
+  *bytes = L.total + (pb.demag ? demag_region(Nx, Ny, 1.0, L, (int)esize_of(dtype), nullptr, nullptr) : 0) +
+           (pb.theory == SS_THEORY_BEC ? bec_region(L, nullptr, nullptr) : 0);
   return SS_OK;
 }
 
@@ -716,10 +779,21 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   }
   if (grad_mode == SS_GRAD_EXACT) c->tile = 0;
   set_tiles(c->L, Nx, Ny, c->tile);
-  c->plan = (grad_mode == SS_GRAD_EL && dtype == SS_F32 && !pb.demag) ? kDefaultPlanF32 : SS_PLAN_STAGES;
+  c->plan = (grad_mode == SS_GRAD_EL && dtype == SS_F32 && !pb.demag && th != SS_THEORY_BEC) ? kDefaultPlanF32
+                                                                                          : SS_PLAN_STAGES;
   c->integ = SS_INTEG_RK4;
   c->ws_total = need;
   std::memset(&c->dm, 0, sizeof(c->dm));
+  c->bec_S = c->bec_G = nullptr;
+  c->bec_part = c->bec_sc = nullptr;
+  if (th == SS_THEORY_BEC) {
+    void* ptrs[4];
+    bec_region(c->L, c->ws + c->L.total, ptrs);
+    c->bec_S = (char*)ptrs[0] + c->L.col0 * esize_of(dtype);
+    c->bec_G = (char*)ptrs[1] + c->L.col0 * esize_of(dtype);
+    c->bec_part = (double*)ptrs[2];
+    c->bec_sc = (double*)ptrs[3];
+  }
   if (pb.demag) {
     c->dm.on = 1;
     c->dm.iters_flow = 2;
@@ -766,9 +840,12 @@ int ss_set_field(ss_ctx* c, const void* field) {
 int ss_init_ansatz(ss_ctx* c, int kind, int n, const double* xy, const double* w, const double* shape,
                    uint64_t seed, double noise_amp) {
   if (!c) return fail(SS_EINVAL, "ctx is NULL");
-  if ((kind == SS_ANSATZ_VORTICES) != (c->theory == SS_THEORY_AH) ||
-      (kind != SS_ANSATZ_VORTICES && kind != SS_ANSATZ_SKYRMION))
-    return fail(SS_EINVAL, "ansatz kind does not match the theory");
+  const int want = c->theory == SS_THEORY_AH    ? SS_ANSATZ_VORTICES
+                   : c->theory == SS_THEORY_BEC ? SS_ANSATZ_BEC
+                                                : SS_ANSATZ_SKYRMION;
+  if (kind != want) return fail(SS_EINVAL, "ansatz kind does not match the theory");
+  if (kind == SS_ANSATZ_BEC && (!shape || !(shape[0] > 0.0) || !(shape[1] > 0.0)))
+    return fail(SS_EINVAL, "the BEC ansatz needs shape = {R > 0, xi > 0}");
   if (n < 0 || n > kMaxVortices || (n > 0 && !xy)) return fail(SS_EINVAL, "bad vortex list");
   if (kind == SS_ANSATZ_SKYRMION && (n != 1 || !shape)) return fail(SS_EINVAL, "skyrmion needs n = 1 and shape");
   if (kind == SS_ANSATZ_SKYRMION && w && !(w[0] != 0.0 && w[0] == std::nearbyint(w[0]) && std::fabs(w[0]) <= 64.0))
@@ -783,7 +860,7 @@ int ss_init_ansatz(ss_ctx* c, int kind, int n, const double* xy, const double* w
   double* dev = (double*)(c->ws + c->L.init_off);
   SS_HIP(hipMemcpyAsync(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   InitArgs ia;
-  ia.kind = kind == SS_ANSATZ_VORTICES ? 0 : 1;
+  ia.kind = kind == SS_ANSATZ_VORTICES ? 0 : kind == SS_ANSATZ_SKYRMION ? 1 : 2;
   ia.n = n;
   ia.xy = dev;
   ia.w = dev + 2 * (size_t)n;
@@ -1057,6 +1134,7 @@ int ss_energy_grad_noalloc(const char* theory, int Nx, int Ny, double h, const s
   if (rc) return rc;
   if (!field) return fail(SS_EINVAL, "field is NULL");
   if (pb.demag) return fail(SS_EINVAL, "the demagnetising term needs a context's workspace (use ss_energy_grad)");
+  if (pb.theory == SS_THEORY_BEC) return fail(SS_EINVAL, "the BEC's constraint needs a context's workspace (use ss_energy_grad)");
   void* sp = nullptr;
   rc = scratch_of_current_device(&sp);
   if (rc) return rc;
@@ -1177,6 +1255,10 @@ void obs_enqueue_t(ss_ctx* c, int nobs) {
     hipLaunchKernelGGL((obs_winding<T>), dim3(1), dim3(256), 0, c->stream, B, c->st);
     return;
   }
+  if (c->theory == SS_THEORY_BEC) {
+    hipLaunchKernelGGL((bec_obs<T>), dim3(nobs), dim3(256), 0, c->stream, B, coeffs_of(c), c->st, c->partials, nobs);
+    return;
+  }
   if (c->theory == SS_THEORY_CM) {
     // the potential of the current field, for the demagnetising energy
     if (c->dm.on) demag_solve<T, kEval>(c, pass_args<T>(c), c->stream);
@@ -1209,7 +1291,10 @@ static int obs_collect(ss_ctx* c, ss_obs* out) {
   std::memset(out, 0, sizeof(*out));
   out->energy = h2 * d.obs[0];
   out->gnorm_inf = d.gmax;
-  if (c->theory == SS_THEORY_AH) {
+  if (c->theory == SS_THEORY_BEC) {
+    out->atoms = h2 * d.obs[1];
+    out->lz = h2 * d.obs[2];
+  } else if (c->theory == SS_THEORY_AH) {
     out->flux = h2 * d.obs[1];
     out->n_rho = h2 * d.obs[2];
     out->bogo_r1 = h2 * d.obs[3];
@@ -1249,6 +1334,8 @@ int ss_set_plan(ss_ctx* c, int plan) {
     return fail(SS_EINVAL, "the fused plans evaluate the Euler-Lagrange gradient only");
   if (plan != SS_PLAN_STAGES && c->dm.on)
     return fail(SS_EINVAL, "demagnetisation runs with SS_PLAN_STAGES (one solve per stage point)");
+  if (plan != SS_PLAN_STAGES && c->theory == SS_THEORY_BEC)
+    return fail(SS_EINVAL, "the BEC runs with SS_PLAN_STAGES (its constraint needs whole-lattice sums per stage)");
   SS_HIP(hipStreamSynchronize(c->stream));
   c->plan = plan;
   if (c->graph) {
@@ -1264,6 +1351,8 @@ int ss_set_integrator(ss_ctx* c, int integ) {
   if (!c) return fail(SS_EINVAL, "ctx is NULL");
   if (integ != SS_INTEG_RK4 && integ != SS_INTEG_VV && integ != SS_INTEG_GF)
     return fail(SS_EINVAL, "unknown integrator");
+  if (integ != SS_INTEG_RK4 && c->theory == SS_THEORY_BEC)
+    return fail(SS_EINVAL, "the BEC runs with the RK4 integrator");
   SS_HIP(hipStreamSynchronize(c->stream));
   c->integ = integ;
   if (c->graph) {
@@ -1356,7 +1445,7 @@ int ss_autotune(ss_ctx* c, int n_steps, double* ms_out) {
   if (!c || n_steps <= 0) return fail(SS_EINVAL, "bad arguments");
   if (ms_out)
     for (int k = 0; k < SS_NUM_PLANS * kNumTiles; ++k) ms_out[k] = -1.0;
-  if (c->grad_mode == SS_GRAD_EXACT) {
+  if (c->grad_mode == SS_GRAD_EXACT || c->theory == SS_THEORY_BEC) {
     if (ms_out) ms_out[0] = 0.0;
     return 0;
   }
@@ -1823,7 +1912,8 @@ int ss_batch_create(const char* theory, int n, const ss_instance* inst, int dtyp
   if (rc) return rc;
   if (!workspace || ws_bytes < need) return fail(SS_EINVAL, "workspace missing or smaller than ss_batch_workspace_bytes");
   if (((uintptr_t)workspace) % 256 != 0) return fail(SS_EINVAL, "workspace must be 256-byte aligned");
-  if (ss_theory_id(theory) == SS_THEORY_BS) return fail(SS_ETHEORY, "batches run the abelian_higgs and chiral_magnet theories");
+  if (ss_theory_id(theory) == SS_THEORY_BS || ss_theory_id(theory) == SS_THEORY_BEC)
+    return fail(SS_ETHEORY, "batches run the abelian_higgs and chiral_magnet theories");
   ss_batch* b = new (std::nothrow) ss_batch();
   if (!b) return fail(SS_EINVAL, "out of host memory");
   b->theory = ss_theory_id(theory);

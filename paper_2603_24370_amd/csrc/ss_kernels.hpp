@@ -1646,7 +1646,7 @@ struct InitArgs {
   int kind, n;
   const double* xy;  // device copy of the centres
   const double* w;   // device copy of the windings
-  double R, gamma;
+  double R, gamma;  // skyrmion: radius and helicity; BEC: cloud radius and vortex core width
   unsigned long long key;  // noise stream key (0 = no noise)
   double amp;
 };
@@ -1663,7 +1663,20 @@ __global__ void __launch_bounds__(256) init_ansatz(Bufs<T> B, Coeffs cf, InitArg
   const double x = (i - 0.5 * (B.Nx - 1)) * cf.h, y = (j - 0.5 * (B.Ny - 1)) * cf.h;
   double out[4] = {0.0, 0.0, 0.0, 0.0};
   int C = 3;
-  if (ia.kind == 0) {
+  if (ia.kind == 2) {
+    // BEC: Gaussian cloud of radius R with vortices of core width xi; psi = 0 on the halo
+    C = 2;
+    if (inner) {
+      double amp = exp(-(x * x + y * y) / (2.0 * ia.R * ia.R)) / (sqrt(M_PI) * ia.R), ph = 0.0;
+      for (int v = 0; v < ia.n; ++v) {
+        const double dx = x - ia.xy[2 * v], dy = y - ia.xy[2 * v + 1];
+        amp *= tanh(sqrt(dx * dx + dy * dy) / ia.gamma);
+        ph += ia.w[v] * atan2(dy, dx);
+      }
+      out[0] = amp * cos(ph);
+      out[1] = amp * sin(ph);
+    }
+  } else if (ia.kind == 0) {
     C = 4;
     double mod = 1.0, ph = 0.0, ax = 0.0, ay = 0.0;
     for (int v = 0; v < ia.n; ++v) {
@@ -1702,7 +1715,7 @@ __global__ void __launch_bounds__(256) init_ansatz(Bufs<T> B, Coeffs cf, InitArg
       const unsigned long long n = ((unsigned long long)c * B.Ny + j) * B.Nx + i;
       out[c] += ia.amp * (2.0 * splitmix_u01(ia.key, n) - 1.0);
     }
-    if (ia.kind == 1) {
+    if (ia.kind == 1) {  // unit vectors are renormalised after the noise
       const double r = sqrt(out[0] * out[0] + out[1] * out[1] + out[2] * out[2]);
       for (int c = 0; c < 3; ++c) out[c] /= r;
     }

@@ -63,8 +63,11 @@ def test_theory_registry_names_and_aliases(L):
         assert ss.ss_theory_id(name) == ss.SS_THEORY_CM
     for name in ["baby_skyrme", "Baby Skyrme", "BS"]:
         assert ss.ss_theory_id(name) == ss.SS_THEORY_BS
-    assert ss.ss_theory_id("bose_einstein") < 0
+    for name in ["bec", "Bose-Einstein condensate", "bose_einstein"]:
+        assert ss.ss_theory_id(name) == ss.SS_THEORY_BEC
+    assert ss.ss_theory_id("liquid_crystal") < 0
     assert ss.ss_components("GL") == 4 and ss.ss_components("CM") == 3 and ss.ss_components("BS") == 3
+    assert ss.ss_components("BEC") == 2
 
 
 def test_workspace_bytes_grow_with_size_and_dtype(L):

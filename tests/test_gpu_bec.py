@@ -1,0 +1,211 @@
+"""The rotating trapped BEC (Sec. 4.3) on the device, through the C ABI, against
+the FP64 oracle's "bec" theory {g, Omega, N}: energy and constrained gradient,
+RK4 trajectories with the atom-number constraint, minima and observables.
+
+Tolerances. FP64: energies 1e-12, gradients 1e-10 of max|G|, fields after a few
+steps 1e-11. FP32 gradients: each term's rounding bounded separately, with M =
+max|psi| and r the largest site radius: the eq. (2) Laplacian 32 * 2^-24 * 13 M / h^2
+(as for the other theories), the trap 8 * 2^-24 r^2 M, the interaction
+16 * 2^-24 g M^3, the rotation 16 * 2^-24 Omega r (3 M / (2 h)), the scale to N
+(one FP32 rounding of c, relative 2^-24, times the operator's largest entry
+~ (10.7 / h^2 + r^2 + 2 Omega r 1.4 / h) M) and the projection |mu| M 8 * 2^-24.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2603_24370_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+BEC = "bec"
+EPS32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def ss():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2603_24370_amd as m
+    m.lib()
+    return m
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _field(Nx, Ny, h, seed, R=None, n_vort=3):
+    R = R if R is not None else 0.25 * min(Nx, Ny) * h
+    cen = I.uniform_centres(seed, n_vort, 0.5 * R)
+    return I.bec_ansatz(Nx, Ny, h, R=R, centres=cen, windings=[1, -1, 1][:n_vort]) + I.noise(seed, 2, Nx, Ny, 1e-3)
+
+
+def _f32_tol(f, h, p, mu):
+    g, Om, _ = p
+    M = np.abs(f).max()
+    Nx, Ny = f.shape[2] - 4, f.shape[1] - 4
+    r = math.hypot(0.5 * (Nx - 1) * h, 0.5 * (Ny - 1) * h)
+    op = 10.7 / h ** 2 + r * r + 2 * Om * r * 1.4 / h
+    return EPS32 * (32 * 13 * M / h ** 2 + 8 * r * r * M + 16 * g * M ** 3 + 16 * Om * r * 1.5 * M / h + op * M
+                    + 8 * abs(mu) * M)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(64, 48), (77, 61), (150, 37), (8, 8)])
+def test_energy_and_constrained_gradient(ss, orc, dtype, shape):
+    Nx, Ny = shape
+    h = 0.15
+    p = [1.7, 0.6, 2.5]
+    print(f"[case] bec energy_grad {dtype} {shape}", flush=True)
+    f = _field(Nx, Ny, h, seed=Nx + 2 * Ny)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    s = ss.Solver(BEC, Nx, Ny, h, p, dtype=dtype)
+    s.set_field(f)
+    E, gmax, G = s.energy_grad()
+    assert E == pytest.approx(orc.energy(BEC, f, h, p), rel=1e-12, abs=1e-14)
+    G_ref = -orc.acceleration(BEC, f, h, p)  # at the field scaled to N, projected
+    scale = np.abs(G_ref).max()
+    if dtype == "f64":
+        tol = 1e-10 * scale
+    else:
+        Gfull = orc.gradient(BEC, f, h, p, mode=orc.GRAD_EL)
+        mu = float((f * Gfull).sum() / (f * f).sum())
+        tol = _f32_tol(f * math.sqrt(p[2] / (h * h * (f[:, 2:-2, 2:-2] ** 2).sum())), h, p, mu)
+    assert np.abs(_np(G) - G_ref).max() <= tol
+    assert gmax == pytest.approx(np.abs(G_ref[:, 2:-2, 2:-2]).max(), rel=1e-9 if dtype == "f64" else 1e-3)
+    o = s.observables()
+    ref = orc.observables(BEC, f, h, p)
+    assert o["energy"] == pytest.approx(ref["E"], rel=1e-12, abs=1e-14)
+    assert o["atoms"] == pytest.approx(ref["N"], rel=1e-12)
+    assert o["lz"] == pytest.approx(ref["Lz"], rel=1e-10, abs=1e-12)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_flow_tracks_the_oracle_and_holds_the_atom_number(ss, orc, dtype):
+    Nx, Ny, h = 96, 70, 0.15
+    p = [2.0, 0.7, 3.0]
+    print(f"[case] bec flow {dtype}", flush=True)
+    f = _field(Nx, Ny, h, seed=21)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    s = ss.Solver(BEC, Nx, Ny, h, p, dtype=dtype)
+    s.set_field(f)
+    n = 8
+    info = s.flow_step(n)
+    phi, vel = (_np(x) for x in s.get_field(velocity=True))
+    phi_r, v_r, E_r, na_r = orc.flow(BEC, f, np.zeros_like(f), h, p, n)
+    rel = 1e-11 if dtype == "f64" else 2e-5
+    assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max()
+    assert np.abs(vel - v_r).max() <= rel * max(np.abs(v_r).max(), np.abs(phi_r).max())
+    assert info["step"] == n and info["n_arrests"] == na_r
+    if dtype == "f64":
+        assert info["energy"] == pytest.approx(E_r, rel=1e-12)
+    atoms = h * h * float((phi[:, 2:-2, 2:-2] ** 2).sum())
+    assert atoms == pytest.approx(p[2], rel=1e-13 if dtype == "f64" else 2e-6)
+    dot = h * h * float((phi[:, 2:-2, 2:-2] * vel[:, 2:-2, 2:-2]).sum())
+    assert abs(dot) <= (1e-12 if dtype == "f64" else 1e-5) * math.sqrt(p[2]) * max(1.0, np.abs(vel).max())
+    assert np.array_equal(phi[:, :2, :], f[:, :2, :]) and np.array_equal(phi[:, :, -2:], f[:, :, -2:])
+    s.close()
+
+
+def test_ground_state_without_interaction(ss, orc):
+    """FP64, g = 0, Omega = 0.5: the minimum is the oscillator ground state, E = N to
+    the O(h^4) error; the stop step and arrest count equal the oracle's. The stop
+    tolerance 1e-5 keeps the energy change per step (~dt^2 |G|^2 ~ 1e-12) far above
+    the energy's rounding (~1e-16 E), so every arrest decision is determined."""
+    N, h, Nat = 48, 0.25, 2.0
+    p = [0.0, 0.5, Nat]
+    f = I.bec_ansatz(N, N, h, R=1.6) * 1.3 + I.noise(3, 2, N, N, 1e-2)
+    s = ss.Solver(BEC, N, N, h, p, dtype="f64")
+    s.set_field(f)
+    res = s.minimise(grad_tol=1e-5, max_steps=20000, graph_steps=16)
+    phi_r, _, ref = orc.minimise(BEC, f, h, p, grad_tol=1e-5, max_steps=20000)
+    print(f"[bec] ground state: steps {res['step']} (oracle {ref['steps']}), E {res['energy']:.12f}", flush=True)
+    assert res["reason"] == "grad" and ref["reason"] == 1
+    assert res["step"] == ref["steps"] and res["n_arrests"] == ref["arrests"]
+    phi = _np(s.get_field())
+    assert np.abs(phi - phi_r).max() <= 1e-9
+    o = s.observables()
+    assert o["energy"] == pytest.approx(Nat, rel=1e-3)
+    assert o["atoms"] == pytest.approx(Nat, rel=1e-12)
+    assert abs(o["lz"]) < 1e-4
+    s.close()
+
+
+def _vortex_count(phi, h, frac=0.75):
+    """Plaquettes whose phase winds by +-2 pi, among those whose centre lies within
+    frac R of the cloud's centre, R = sqrt(3 <r^2>) (the radius of a Thomas-Fermi
+    disc with that second moment): a test-side analysis of the returned field."""
+    th = np.arctan2(phi[1], phi[0])[2:-2, 2:-2]
+    rho = (phi[0] ** 2 + phi[1] ** 2)[2:-2, 2:-2]
+    Ny, Nx = rho.shape
+    X, Y = I.grid(Nx, Ny, h)
+    X, Y = X[2:-2, 2:-2], Y[2:-2, 2:-2]
+    R = math.sqrt(3.0 * float((rho * (X * X + Y * Y)).sum() / rho.sum()))
+    wrap = lambda a: (a + np.pi) % (2 * np.pi) - np.pi
+    a, b, c, d = th[:-1, :-1], th[:-1, 1:], th[1:, 1:], th[1:, :-1]
+    w = wrap(b - a) + wrap(c - b) + wrap(d - c) + wrap(a - d)
+    xc, yc = X[:-1, :-1] + 0.5 * h, Y[:-1, :-1] + 0.5 * h
+    inside = xc * xc + yc * yc < (frac * R) ** 2
+    n = np.rint(w / (2 * np.pi))[inside]
+    return int((n > 0).sum()), int((n < 0).sum())
+
+
+def test_rotating_cloud_relaxes_to_a_vortex_state(ss, orc):
+    """FP32, Omega = 0.9, g N = 60 (Thomas-Fermi radius ~4.5), from a cloud seeded
+    with seven +1 vortices and noise: the relaxed state keeps same-sign vortices
+    only (the rotation term favours L_z > 0) in its dense core, L_z per atom exceeds
+    2, the atom number is held, and the device field is a stationary point of the
+    oracle's constrained flow: its projected gradient there is below twice the stop
+    tolerance. (Measured: 7523 steps to |G| < 2e-3, 7 vortices, L_z/N = 4.9.)"""
+    N, h = 128, 0.125
+    p = [0.06, 0.9, 1000.0]  # g N = 60
+    s = ss.Solver(BEC, N, N, h, p, dtype="f32")
+    cen = [(0.0, 0.0)] + [(1.8 * math.cos(k * math.pi / 3), 1.8 * math.sin(k * math.pi / 3)) for k in range(6)]
+    s.init_bec(R=4.0, xi=0.5, centres=cen, seed=5, noise_amp=0.2)
+    tol = 2e-3
+    res = s.minimise(grad_tol=tol, rel_e_tol=1e-9, window=128, max_steps=200000, graph_steps=32)
+    phi = _np(s.get_field())
+    o = s.observables()
+    npos, nneg = _vortex_count(phi, h)
+    a = orc.acceleration(BEC, phi, h, p)
+    print(f"[bec] rotating: {res['reason']} after {res['step']} steps, E {o['energy']:.6f}, "
+          f"Lz/N {o['lz'] / p[2]:.3f}, vortices +{npos} -{nneg}, oracle |G| {np.abs(a).max():.3e}", flush=True)
+    assert res["reason"] in ("grad", "stall")
+    assert o["atoms"] == pytest.approx(p[2], rel=2e-6)
+    assert npos >= 4 and nneg == 0
+    assert o["lz"] / p[2] > 2.0
+    if res["reason"] == "grad":
+        assert np.abs(a).max() <= 2 * tol
+    assert o["energy"] == pytest.approx(orc.energy(BEC, phi, h, p), rel=1e-10)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_device_bec_ansatz_matches_input_module(ss, dtype):
+    Nx, Ny, h = 70, 45, 0.2
+    s = ss.Solver(BEC, Nx, Ny, h, [1.0, 0.5, 1.0], dtype=dtype)
+    cen = [(0.4, -0.3), (-1.0, 0.8)]
+    s.init_bec(R=2.0, xi=0.7, centres=cen, windings=[1, -1])
+    want = I.bec_ansatz(Nx, Ny, h, R=2.0, centres=cen, windings=[1, -1], xi=0.7)
+    tol = 1e-13 if dtype == "f64" else 1e-7
+    assert np.abs(_np(s.get_field()) - want).max() <= tol
+    s.close()
+
+
+def test_bec_refuses_what_it_cannot_run(ss):
+    s = ss.Solver(BEC, 32, 32, 0.2, [1.0, 0.5, 1.0], dtype="f32")
+    assert s.plan == ss.SS_PLAN_STAGES
+    with pytest.raises(ss.SSError):
+        s.set_plan(ss.SS_PLAN_FUSED)
+    with pytest.raises(ss.SSError):
+        s.set_integrator("vv")
+    with pytest.raises(ss.SSError):
+        s.init_skyrmion()
+    s.close()
+    with pytest.raises(ss.SSError):
+        ss.Batch(BEC, [(32, 32, 0.2, [1.0, 0.5, 1.0])], dtype="f64")
