@@ -101,10 +101,19 @@ def generate_dataset(insts, batch=64, rel_e_tol=0.0, window=0, max_steps=150, de
     return X, T, stats
 
 
-def train(net, X, T, epochs=10, batch=8, lr=1e-3, seed=0, clip=0.0, log=None):
+def lr_at(step, total, lr, warmup=0, per_step=False, steps_per_epoch=1):
+    """Learning rate of an Adam step: a linear warm-up over the first `warmup`
+    steps, then a cosine decay from lr to 0, evaluated per step (per_step) or
+    held constant within each epoch."""
+    w = min(1.0, (step + 1) / warmup) if warmup > 0 else 1.0
+    x = step / max(1, total) if per_step else (step // steps_per_epoch) * steps_per_epoch / max(1, total)
+    return lr * w * 0.5 * (1.0 + math.cos(math.pi * x))
+
+
+def train(net, X, T, epochs=10, batch=8, lr=1e-3, seed=0, clip=0.0, warmup=0, per_step=False, log=None):
     """Adam on the mean squared error (gradient clipped to global L2 norm clip
-    if clip > 0); returns the per-epoch mean losses, the achieved training rate
-    (TFLOP/s of the MFMA convolutions) and the wall time."""
+    if clip > 0, learning rate from lr_at); returns the per-epoch mean losses, the
+    achieved training rate (TFLOP/s of the MFMA convolutions) and the wall time."""
     import torch
     n = X.shape[0]
     net.set_grad_clip(clip)
@@ -114,13 +123,15 @@ def train(net, X, T, epochs=10, batch=8, lr=1e-3, seed=0, clip=0.0, log=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps = 0
+    per_epoch = n // batch
+    total = per_epoch * epochs
     for ep in range(epochs):
         perm = rng.permutation(n)
         tot, cnt = 0.0, 0
         for b0 in range(0, n - batch + 1, batch):
             idx = torch.as_tensor(perm[b0:b0 + batch], device=X.device)
             loss = net.train_step(X.index_select(0, idx), T.index_select(0, idx),
-                                  lr * 0.5 * (1 + math.cos(math.pi * ep / max(1, epochs))))
+                                  lr_at(steps, total, lr, warmup, per_step, per_epoch))
             tot += loss
             cnt += 1
             steps += 1
@@ -230,22 +241,35 @@ def summarise(recs, sigma, tol=None, coarse=None):
 
 def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20, batch=8, lr=1e-3, seed=0,
                  tol=1e-6, sigmas=(0.0, 3.0), target_steps=150, pin=0.0, coarse_tols=(), clip=0.0,
-                 learned_noise_amp=0.0, device="cuda:0", log=print):
-    """Data -> training -> A/B on held-out instances; returns a summary dict."""
+                 learned_noise_amp=0.0, warmup=0, per_step=False, test_offset=0, save_weights=None,
+                 load_weights=None, device="cuda:0", log=print):
+    """Data -> training -> A/B on held-out instances test_offset .. test_offset +
+    n_test - 1; returns a summary dict. With load_weights the data and training
+    steps are skipped and the stored network is evaluated; save_weights stores the
+    trained network (flat fp32, exchange order, .npy)."""
     import torch
     t0 = time.perf_counter()
-    train_insts = [learned_instance(i, 5_000_000, side) for i in range(n_train)]
-    test_insts = [learned_instance(j, 6_000_000, side) for j in range(n_test)]
-    X, T, steps = generate_dataset(train_insts, batch=64, max_steps=target_steps, device=device, log=log)
-    t_data = time.perf_counter() - t0
-    zero_mse = float(T.pow(2).mean().item())
-    if log:
-        log(f"[data] target mean square {zero_mse:.4e} (the loss of predicting no correction)")
+    test_insts = [learned_instance(test_offset + j, 6_000_000, side) for j in range(n_test)]
     net = ss.Net(levels=levels, base=base, cin=2, cout=4, N=batch, H=side, W=side, device=device)
-    net.set_weights(init_weights(seed, levels, base, 2, 4))
-    losses, tflops, t_train = train(net, X, T, epochs=epochs, batch=batch, lr=lr, seed=seed, clip=clip, log=log)
+    losses, tflops, t_train, t_data, steps, zero_mse = [], 0.0, 0.0, 0.0, [0], 0.0
+    if load_weights:
+        net.set_weights(np.load(load_weights).astype(np.float32))
+    else:
+        train_insts = [learned_instance(i, 5_000_000, side) for i in range(n_train)]
+        X, T, steps = generate_dataset(train_insts, batch=64, max_steps=target_steps, device=device, log=log)
+        t_data = time.perf_counter() - t0
+        zero_mse = float(T.pow(2).mean().item())
+        if log:
+            log(f"[data] target mean square {zero_mse:.4e} (the loss of predicting no correction)")
+        net.set_weights(init_weights(seed, levels, base, 2, 4))
+        losses, tflops, t_train = train(net, X, T, epochs=epochs, batch=batch, lr=lr, seed=seed, clip=clip,
+                                        warmup=warmup, per_step=per_step, log=log)
+        if save_weights:
+            np.save(save_weights, net.get_weights())
+        del X, T
+        torch.cuda.empty_cache()
     # network time of one learned start (batch of one image), after a warm-up
-    x1 = X[:1].contiguous()
+    x1 = torch.zeros((1, side, side, 2), dtype=torch.float32, device=device)  # the time does not depend on values
     o1 = torch.empty((1, side, side, 4), dtype=torch.float32, device=device)
     net.forward(x1, out=o1, graph=True)
     torch.cuda.synchronize()
@@ -256,8 +280,6 @@ def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20
     infer_ms = (time.perf_counter() - t1) / 20 * 1e3
     if log:
         log(f"[infer] {infer_ms:.3f} ms per image at batch 1")
-    del X, T
-    torch.cuda.empty_cache()
     recs = ab_compare(net, test_insts, tol=tol, sigmas=sigmas, pin=pin, coarse_tols=coarse_tols,
                       learned_noise_amp=learned_noise_amp, device=device, log=log)
     out = {"summary": [summarise(recs, sg, tol=tol) for sg in sigmas] +
@@ -265,13 +287,37 @@ def run_pipeline(n_train=2048, n_test=64, side=256, levels=4, base=32, epochs=20
     out.update({"n_train": n_train, "n_test": n_test, "side": side, "levels": levels, "base": base,
                 "epochs": epochs, "batch": batch, "lr": lr, "data_s": t_data,
                 "data_median_steps": float(np.median(steps)), "train_s": t_train, "train_TFLOPs": tflops,
-                "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1], "losses": losses, "tol": tol,
+                "loss_first_epoch": losses[0] if losses else None, "loss_last_epoch": losses[-1] if losses else None,
+                "losses": losses, "tol": tol,
                 "target_steps": target_steps, "target_mean_square": zero_mse, "pin": pin, "clip": clip,
-                "learned_noise_amp": learned_noise_amp,
-                "inference_ms_batch1": infer_ms,
+                "learned_noise_amp": learned_noise_amp, "warmup": warmup, "per_step": per_step,
+                "test_offset": test_offset, "inference_ms_batch1": infer_ms,
                 "records": recs})
     net.close()
     return out
+
+
+def merge_runs(paths, out=None):
+    """Summaries over the records of several runs of the same network (held-out
+    chunks): the per-instance records are concatenated and summarised again."""
+    import json
+    runs = [json.load(open(p)) for p in paths]
+    recs = [r for run in runs for r in run["records"]]
+    first = runs[0]
+    sigmas = sorted({s["sigma"] for s in first["summary"]})
+    coarse = sorted({s["tol"] for s in first["summary"] if s["tol"] != first["tol"]}, reverse=True)
+    res = {"summary": [summarise(recs, sg, tol=first["tol"]) for sg in sigmas] +
+           [summarise(recs, sg, coarse=ct) for ct in coarse for sg in sigmas],
+           "n_test": len(recs), "parts": [p for p in paths],
+           "train": {k: first.get(k) for k in ("n_train", "epochs", "lr", "warmup", "per_step", "clip",
+                                               "loss_last_epoch", "losses", "train_s", "train_TFLOPs",
+                                               "target_mean_square", "data_s")},
+           "inference_ms_batch1": first.get("inference_ms_batch1")}
+    print(json.dumps({k: v for k, v in res.items() if k != "train"}), flush=True)
+    if out:
+        with open(out, "w") as f:
+            json.dump(res, f, indent=1)
+    return 0
 
 
 def main(argv=None):
@@ -294,13 +340,23 @@ def main(argv=None):
                     help="amplitude of the instance's seeded noise added to the learned start (the ansatz start has 1e-3)")
     ap.add_argument("--coarse-tols", default="1e-3,1e-4",
                     help="coarser relative energy tolerances also timed (comma list, may be empty)")
+    ap.add_argument("--warmup", type=int, default=0, help="linear learning-rate warm-up steps")
+    ap.add_argument("--per-step-cosine", action="store_true", help="cosine decay per step (default: per epoch)")
+    ap.add_argument("--test-offset", type=int, default=0, help="first held-out instance")
+    ap.add_argument("--save-weights", default=None, help="store the trained network here (.npy)")
+    ap.add_argument("--load-weights", default=None, help="evaluate this stored network (no data, no training)")
+    ap.add_argument("--merge", nargs="+", default=None,
+                    help="summarise the records of several --out files (held-out chunks) and exit")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     a = ap.parse_args(argv)
+    if a.merge:
+        return merge_runs(a.merge, a.out)
     sig = tuple(float(v) for v in a.sigmas.split(","))
     coarse = tuple(float(v) for v in a.coarse_tols.split(",") if v.strip())
     res = run_pipeline(a.n_train, a.n_test, a.side, a.levels, a.base, a.epochs, a.batch, a.lr, sigmas=sig,
                        target_steps=a.target_steps, pin=a.pin, coarse_tols=coarse, clip=a.clip,
-                       learned_noise_amp=a.learned_noise,
+                       learned_noise_amp=a.learned_noise, warmup=a.warmup, per_step=a.per_step_cosine,
+                       test_offset=a.test_offset, save_weights=a.save_weights, load_weights=a.load_weights,
                        log=lambda m: print(m, flush=True))
     brief = {k: v for k, v in res.items() if k not in ("records", "losses")}
     print(json.dumps(brief), flush=True)

@@ -333,14 +333,16 @@ def test_energy_target_stop_rule(ss):
 
 
 @pytest.mark.slow
-def test_trained_network_starts_lower_in_energy(ss):
+def test_trained_network_starts_lower_and_needs_fewer_steps(ss):
     """What the trained network gains over the ansatz start, with a reduced budget
-    (1024 training fields at 256^2, 24 epochs; the full pipeline uses 4096 and
-    32): on held-out instances the learned start's energy excess over the relaxed
-    energy is, at the median, well under the ansatz start's, and on most of them
-    under half of it. Fewer flow steps to the 1e-6 tolerance is not asserted: at
-    this budget the learned start still takes more steps on most instances, and
-    the step and time comparison belongs to the full A/B run."""
+    (1024 training fields at 256^2, 24 epochs, the schedule of the full run: Adam
+    lr 3e-4, 200 warm-up steps, per-step cosine, clipping at 1; the full run uses
+    10,000 fields, 32 epochs and 512 held-out instances). On 8 held-out instances
+    the learned start's energy excess over the relaxed energy is, at the median,
+    well under the ansatz start's, and it needs fewer flow steps to the 1e-3
+    tolerance (median step ratio below 0.9; 0.59 in the full run). Wall time is not
+    asserted: on 256^2 lattices the network costs about as much as the steps it
+    saves (median time ratio 0.97-1.02 in the full run)."""
     from paper_2603_24370_amd import learned as L
     side = 256
     train = [L.learned_instance(i, 5_000_000, side) for i in range(1024)]
@@ -348,21 +350,26 @@ def test_trained_network_starts_lower_in_energy(ss):
     X, T, _ = L.generate_dataset(train, batch=64, max_steps=150)
     net = ss.Net(levels=4, base=32, cin=2, cout=4, N=8, H=side, W=side)
     net.set_weights(L.init_weights(0, 4, 32, 2, 4))
-    losses, _, _ = L.train(net, X, T, epochs=24, batch=8, lr=1e-3)
+    losses, _, _ = L.train(net, X, T, epochs=24, batch=8, lr=3e-4, clip=1.0, warmup=200, per_step=True)
     zero = float(T.pow(2).mean())
     print("[learned] loss", losses[-1], "zero", zero, flush=True)
     assert losses[-1] < 0.2 * zero
     del X, T
-    recs = L.ab_compare(net, test, sigmas=(3.0,), pin=0.5, ref_max_steps=20000, max_steps=20000)
+    recs = L.ab_compare(net, test, sigmas=(3.0,), pin=0.5, ref_max_steps=20000, max_steps=20000,
+                        coarse_tols=(1e-3,))
     ea, el = [], []
     for r in recs:
         ea.append((r["ansatz_E0"] - r["E_ref"]) / abs(r["E_ref"]))
         el.append((r["learned_E0@3.0"] - r["E_ref"]) / abs(r["E_ref"]))
         print("[learned]", r["n_vortices"], round(r["kappa"], 2), f"{ea[-1]:.1e} {el[-1]:.1e}",
-              r["ansatz_steps"], r["learned_steps@3.0"], flush=True)
+              r["ansatz_steps~0.001"], r["learned_steps@3.0~0.001"], flush=True)
     assert min(ea) > 0 and min(el) > 0  # both starts lie above the relaxed energy
     assert np.median(el) < 0.25 * np.median(ea)
     assert sum(l < 0.5 * a for a, l in zip(ea, el)) >= 5
+    coarse = L.summarise(recs, 3.0, coarse=1e-3)
+    print("[learned] 1e-3:", coarse, flush=True)
+    assert coarse["both_reached"] == len(test)
+    assert coarse["median_step_ratio"] < 0.9
     net.close()
 
 
