@@ -283,12 +283,13 @@ def host_cores() -> int:
     return max(1, n)
 
 
-def cpu_baseline(s, wl, params, window=1024, steps=10, scheme="rk4"):
+def cpu_baseline(s, wl, params, window=1024, steps=None, scheme="rk4", target_s=3.0):
     """The FP64 oracle as it stands (one thread per call) on windows of the same
     field: first one core on the central window, then every usable host core at
     once, one window per thread (the oracle is a C library called through
     ctypes, which releases the interpreter lock, so the threads run in parallel).
-    Each window keeps its neighbours as a fixed halo."""
+    Each window keeps its neighbours as a fixed halo. Without a step count, two
+    calibration steps set it so that the one-core run takes about target_s."""
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
     import oracle
@@ -304,6 +305,11 @@ def cpu_baseline(s, wl, params, window=1024, steps=10, scheme="rk4"):
         oracle.flow(wl["theory"], sub, np.zeros_like(sub), wl["h"], params, steps, scheme=scheme)
 
     c = (N - w) // 2
+    if steps is None:
+        t0 = time.perf_counter()
+        oracle.flow(wl["theory"], window_at(c, c), np.zeros_like(window_at(c, c)), wl["h"], params, 2,
+                    scheme=scheme)
+        steps = int(min(100000, max(10, math.ceil(target_s / max((time.perf_counter() - t0) / 2, 1e-9)))))
     t0 = time.perf_counter()
     run(window_at(c, c))
     dt1 = time.perf_counter() - t0
