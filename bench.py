@@ -50,6 +50,13 @@ WORKLOADS = {
     "ah128": dict(theory="abelian_higgs", N=128, h=0.1, kappa=2 ** -0.5, nv=1, seed=1, dtype="f64"),
     "batch256": dict(theory="abelian_higgs", n=256, base_seed=3000, h=0.2, dtype="f32"),
     "unet256": dict(levels=4, base=32, cin=2, cout=4, N=8, H=256, W=256),
+    # the other theories (context lines, with their own step models below)
+    "heusler_demag512": dict(theory="chiral_magnet", N=512, h=0.05, dtype="f32", integrator="vv", seed=5,
+                             params=[1.0, 1.0, 2.0, 0.0, 1.057], dmi="heusler", demag=True),
+    "bec256": dict(theory="bec", N=256, h=0.1, dtype="f32", integrator="rk4", seed=6, params=[0.038, 0.99, 1000.0]),
+    # the Skyrme term stiffens the flow where |grad m| is large: C = 0.25 keeps dt^2 times the
+    # largest stiffness below the velocity Verlet limit for this skyrmion size
+    "bs512": dict(theory="baby_skyrme", N=512, h=0.1, dtype="f32", integrator="vv", seed=7, params=[1.0, 0.1, 0.25]),
 }
 
 BF16_DENSE_PEAK_TFLOPS = 2500.0
@@ -104,6 +111,74 @@ def run_unet(args, wl):
            "cpu_baseline": None}
     print(json.dumps(out), flush=True)
     net.close()
+
+
+def other_theory_bytes(name, wl, demag_iters=2, nlev=1):
+    """Bytes per interior site and step that the kernels of a step read and write
+    (FP32 fields, FP64 solver planes; halo re-reads not counted):
+      heusler_demag512, velocity Verlet: the pass reads phi, v, a and writes phi', v',
+        a' (6 x 3 x 4 B); the solve forms the stage point (reads 3 sets, writes one:
+        48 B), starts conjugate gradients (reads S_1, S_2 and x, writes r, rhs, psi:
+        40 B) and per iteration moves about 312 B on the lattice (V-cycle 144 B, the
+        coarser levels a third of that, the conjugate-gradient kernels 120 B);
+      bec256, RK4 with the atom-number constraint: stage points 104 B, gradients 64 B,
+        forces and updates 152 B, the end-of-step scaling 32 B (two components);
+      bs512, velocity Verlet: 6 x 3 x 4 B."""
+    if name == "heusler_demag512":
+        return 72 + 48 + 40 + demag_iters * 312
+    if name == "bec256":
+        return 352
+    return 72
+
+
+def run_other(args, name, wl):
+    """A flow of one of the other theories, timed over graph replays of ss_minimise
+    (no stop rule fires: grad_tol = 0, max_steps = warm-up + steps)."""
+    import torch
+    import paper_2603_24370_amd as ss
+    N, h = wl["N"], wl["h"]
+    kw = {}
+    if wl.get("demag") or wl.get("dmi", "bulk") != "bulk":
+        kw = {"dmi": wl.get("dmi", "bulk"), "demag": wl.get("demag", False)}
+    s = ss.Solver(wl["theory"], N, N, h, wl["params"], dtype=wl["dtype"], **kw)
+    s.set_integrator(wl["integrator"])
+    if wl["theory"] == "bec":
+        R = 7.0  # about the Thomas-Fermi radius of these parameters
+        cen = [(2.0 * math.cos(k * math.pi / 3), 2.0 * math.sin(k * math.pi / 3)) for k in range(6)]
+        s.init_bec(R=R, xi=0.5, centres=cen, seed=wl["seed"], noise_amp=0.05)
+    elif wl.get("dmi") == "heusler":
+        s.init_skyrmion(R=0.6, gamma=-math.pi / 2, seed=wl["seed"], noise_amp=1e-3, vorticity=-1)
+    else:
+        s.init_skyrmion(R=2.0, gamma=0.0, seed=wl["seed"], noise_amp=1e-3)
+    s.minimise(grad_tol=0.0, max_steps=args.warmup, graph_steps=16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = s.minimise(grad_tol=0.0, max_steps=args.warmup + args.steps, graph_steps=16)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    done = res["step"] - args.warmup
+    sites = N * N
+    ms_step = 1e3 * el / max(done, 1)
+    per_site = other_theory_bytes(name, wl)
+    gbps = per_site * sites / (ms_step * 1e-3) / 1e9
+    obs = s.observables()
+    out = {"metric": "site-updates/s", "value": sites * done / el, "unit": "site-updates/s", "n_gpus": 1,
+           "steps": done, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 fields, f64 reductions" + (
+               " and f64 solver" if wl.get("demag") else ""),
+           "data": "synthetic (seeded ansatz + noise)",
+           "config": {"workload": name, "theory": wl["theory"], "Nx": N, "Ny": N, "h": h, "params": wl["params"],
+                      "dmi": wl.get("dmi"), "demag": wl.get("demag", False),
+                      "integrator": INTEGRATOR_NAMES[wl["integrator"]], "parallelism": "single GPU"},
+           "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "whole step (every kernel of the step; bytes per site from the step model)",
+                        "step_bytes_per_site": per_site},
+           "cpu_baseline": None,
+           "state": {"energy": obs["energy"], "step": res["step"], "n_arrests": res["n_arrests"],
+                     "atoms": obs.get("atoms"), "q_bl": obs.get("q_bl")}}
+    print(json.dumps(out), flush=True)
+    s.close()
 
 
 def run_batch(args, wl):
@@ -399,6 +474,9 @@ def main():
         run_converge(args)
         return
     wl = WORKLOADS[args.workload]
+    if args.workload in ("heusler_demag512", "bec256", "bs512"):
+        run_other(args, args.workload, wl)
+        return
     if args.workload.startswith("batch"):
         run_batch(args, wl)
         return

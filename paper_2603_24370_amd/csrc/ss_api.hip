@@ -277,6 +277,15 @@ int dm_groups(long n) { return (int)std::max<long>(1, std::min<long>((n + 255) /
 // coarsest level an even number of sweeps from zero.
 void dm_vcycle(const ss_ctx::Demag& d, int l, const DevStatus* skip, hipStream_t s) {
   const DmLevel& L = d.lv[l];
+  const long small = dm_small_bytes(d.lv, d.nlev, l);
+  if (small <= kDmSmallLds) {
+    // this level and the coarser ones in one workgroup, in LDS
+    DmHierarchy H;
+    for (int k = 0; k < d.nlev; ++k) H.lv[k] = d.lv[k];
+    H.nlev = d.nlev;
+    hipLaunchKernelGGL(dm_vcycle_small, dim3(1), dim3(256), (unsigned)small, s, H, l, skip);
+    return;
+  }
   const int g = dm_groups((long)L.Nx * L.Ny);
   auto sweeps = [&](int n) {
     for (int k = 0; k < n; k += 2) {
@@ -318,10 +327,10 @@ void demag_solve(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
     dm_vcycle(d, 0, skip, s);
     hipLaunchKernelGGL(dm_dot, dim3(kDmRedGroups), dim3(256), 0, s, L0, (const double*)d.v.r, (const double*)L0.psi,
                        d.v.part, skip);
-    hipLaunchKernelGGL(dm_beta, dim3(1), dim3(64), 0, s, (const double*)d.v.part, d.v.sc, first, skip);
+    hipLaunchKernelGGL(dm_beta, dim3(1), dim3(256), 0, s, (const double*)d.v.part, d.v.sc, first, skip);
     hipLaunchKernelGGL(dm_dir, dim3(g), dim3(256), 0, s, L0, d.v, first, skip);
     hipLaunchKernelGGL(dm_matvec, dim3(kDmRedGroups), dim3(256), 0, s, L0, d.v, skip);
-    hipLaunchKernelGGL(dm_alpha, dim3(1), dim3(64), 0, s, d.v, skip);
+    hipLaunchKernelGGL(dm_alpha, dim3(1), dim3(256), 0, s, d.v, skip);
     hipLaunchKernelGGL(dm_update, dim3(g), dim3(256), 0, s, L0, d.v, skip);
   }
 }
@@ -340,7 +349,7 @@ void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   W.part = c->bec_part;
   W.sc = c->bec_sc;
   const int flow = PASS == kEval ? 0 : 1;
-  const dim3 g(kBecGroups), b(256), b1(64);
+  const dim3 g(kBecGroups), b(256), b1(256);
   hipLaunchKernelGGL((bec_stage<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, a.src, W);
   hipLaunchKernelGGL(bec_scale, dim3(1), b1, 0, s, (const double*)W.part, W.sc, a.cf, (const DevStatus*)c->st, flow);
   hipLaunchKernelGGL((bec_grad<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, W, (const double*)W.sc);

@@ -46,6 +46,16 @@ __device__ __forceinline__ double bec_block_sum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
+// Sum over the kBecGroups partials part[k * stride + off] by one workgroup of 256
+// threads in a fixed order (strided per thread, then in wave order); valid in
+// thread 0.
+__device__ __forceinline__ double bec_partials_sum(const double* __restrict__ part, int stride, int off,
+                                                   double* red) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < kBecGroups; k += 256) acc += part[(long)k * stride + off];
+  return bec_block_sum(acc, red);
+}
+
 __device__ __forceinline__ double bec_block_max(double v, double* red) {
   v = wave_max(v);
   __syncthreads();
@@ -96,12 +106,12 @@ __global__ void __launch_bounds__(256) bec_stage(Bufs<T> B, Coeffs cf, const Dev
 }
 
 // c = sqrt(N / (h^2 sum S^2)): the scale of the stage point onto the sphere of atom number N.
-__global__ void __launch_bounds__(64) bec_scale(const double* __restrict__ part, double* sc, Coeffs cf,
-                                                const DevStatus* __restrict__ st, int flow) {
-  if ((flow && st->done) || threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int k = 0; k < kBecGroups; ++k) s += part[k];
-  sc[0] = sqrt(cf.p[2] / (cf.h * cf.h * s));
+__global__ void __launch_bounds__(256) bec_scale(const double* __restrict__ part, double* sc, Coeffs cf,
+                                                 const DevStatus* __restrict__ st, int flow) {
+  if (flow && st->done) return;
+  __shared__ double red[4];
+  const double s = bec_partials_sum(part, 1, 0, red);
+  if (threadIdx.x == 0) sc[0] = sqrt(cf.p[2] / (cf.h * cf.h * s));
 }
 
 // Value of the scaled stage point at padded (jj, ii): c S inside the interior, S on the halo.
@@ -184,20 +194,19 @@ __global__ void __launch_bounds__(256) bec_grad(Bufs<T> B, Coeffs cf, const DevS
 }
 
 // mu = <psi, G> / <psi, psi>, E h^2 and the non-finite count of the stage.
-__global__ void __launch_bounds__(64) bec_mu(const double* __restrict__ part, double* sc, Coeffs cf,
-                                             const DevStatus* __restrict__ st, int flow) {
-  if ((flow && st->done) || threadIdx.x != 0) return;
-  double sG = 0.0, ss = 0.0, se = 0.0, nf = 0.0;
-  for (int k = 0; k < kBecGroups; ++k) {
-    const double* p = part + 4 * (long)k;
-    sG += p[0];
-    ss += p[1];
-    se += p[2];
-    nf += p[3];
+__global__ void __launch_bounds__(256) bec_mu(const double* __restrict__ part, double* sc, Coeffs cf,
+                                              const DevStatus* __restrict__ st, int flow) {
+  if (flow && st->done) return;
+  __shared__ double red[4];
+  const double sG = bec_partials_sum(part, 4, 0, red);
+  const double ss = bec_partials_sum(part, 4, 1, red);
+  const double se = bec_partials_sum(part, 4, 2, red);
+  const double nf = bec_partials_sum(part, 4, 3, red);
+  if (threadIdx.x == 0) {
+    sc[1] = sG / ss;
+    sc[2] = cf.h * cf.h * se;
+    sc[3] = nf;
   }
-  sc[1] = sG / ss;
-  sc[2] = cf.h * cf.h * se;
-  sc[3] = nf;
 }
 
 // The force a = -(G - mu psi) at the scaled stage point and the pass's update; a
@@ -282,26 +291,28 @@ __global__ void __launch_bounds__(256) bec_apply(Bufs<T> B, Coeffs cf, const Dev
 // Status update of a reducing BEC pass: the stage's energy and non-finite count
 // (bec_mu) and the max of the constrained force, through the common finalise.
 template <int PASS>
-__global__ void __launch_bounds__(64) bec_finalise(DevStatus* st, const double* __restrict__ part,
-                                                   const double* __restrict__ sc) {
-  if ((PASS != kEval && st->done) || threadIdx.x != 0) return;
+__global__ void __launch_bounds__(256) bec_finalise(DevStatus* st, const double* __restrict__ part,
+                                                    const double* __restrict__ sc) {
+  if (PASS != kEval && st->done) return;
+  __shared__ double red[4];
   double gm = 0.0;
-  for (int k = 0; k < kBecGroups; ++k) gm = fmax(gm, part[k]);
-  finalise_status<PASS>(st, sc[2], gm, (int)sc[3]);
+  for (int k = threadIdx.x; k < kBecGroups; k += 256) gm = fmax(gm, part[k]);
+  gm = bec_block_max(gm, red);
+  if (threadIdx.x == 0) finalise_status<PASS>(st, sc[2], gm, (int)sc[3]);
 }
 
 // End of a step: phi' scaled to N, v' projected on the tangent space at phi'
 // (the projection uses the unscaled phi'; the coefficient is scale-free).
-__global__ void __launch_bounds__(64) bec_fix_scalars(const double* __restrict__ part, double* sc, Coeffs cf,
-                                                      const DevStatus* __restrict__ st) {
-  if (st->done || threadIdx.x != 0) return;
-  double pp = 0.0, pv = 0.0;
-  for (int k = 0; k < kBecGroups; ++k) {
-    pp += part[2 * (long)k];
-    pv += part[2 * (long)k + 1];
+__global__ void __launch_bounds__(256) bec_fix_scalars(const double* __restrict__ part, double* sc, Coeffs cf,
+                                                       const DevStatus* __restrict__ st) {
+  if (st->done) return;
+  __shared__ double red[4];
+  const double pp = bec_partials_sum(part, 2, 0, red);
+  const double pv = bec_partials_sum(part, 2, 1, red);
+  if (threadIdx.x == 0) {
+    sc[4] = sqrt(cf.p[2] / (cf.h * cf.h * pp));
+    sc[5] = pv / pp;
   }
-  sc[4] = sqrt(cf.p[2] / (cf.h * cf.h * pp));
-  sc[5] = pv / pp;
 }
 
 template <class T>

@@ -26,7 +26,7 @@
 namespace ss {
 
 constexpr int kDmMaxLevels = 20;
-constexpr int kDmRedGroups = 256;  // workgroups of the dot-product launches
+constexpr int kDmRedGroups = 256;  // workgroups of the dot-product launches (one partial per thread of the sum)
 constexpr double kDmOmega = 0.8;   // Jacobi weight (stable below 15/16 for this operator)
 constexpr int kDmSmooth = 2;       // sweeps before and after the coarse correction
 constexpr int kDmCoarse = 40;      // sweeps on the coarsest level (even)
@@ -101,6 +101,143 @@ __global__ void __launch_bounds__(256) dm_coarse_solve(DmLevel L, const DevStatu
   }
 }
 
+// 1-D weight of fine index f in coarse cell J (transpose of the prolongation):
+// f = 2J - 1 and 2J + 2 carry 1/4, f = 2J and 2J + 1 carry 3/4.
+__device__ __forceinline__ double dm_w(int f, int J) {
+  const int d = f - 2 * J;
+  return (d == 0 || d == 1) ? 0.75 : 0.25;
+}
+
+// ---- the small levels of a V-cycle in one workgroup, in LDS
+// The coarse levels of a V-cycle cost a few microseconds per launch and almost
+// nothing to compute. From the first level whose planes and those of every
+// coarser level fit in kDmSmallLds bytes, the V-cycle down to the coarsest level
+// and back up runs in one workgroup on LDS copies of those planes, phase by phase
+// with a barrier between phases: the same updates in the same order of phases as
+// the per-level launches, so the result is the same bit for bit. The level's rhs
+// and psi are read from global memory at the start and psi written back at the end.
+constexpr int kDmSmallLds = 64 * 1024;
+
+struct DmHierarchy {
+  DmLevel lv[kDmMaxLevels];
+  int nlev;
+};
+
+// LDS bytes of levels l .. nlev - 1 (three padded planes each)
+__host__ __device__ inline long dm_small_bytes(const DmLevel* lv, int nlev, int l) {
+  long n = 0;
+  for (int k = l; k < nlev; ++k) n += 3L * (lv[k].Nx + 4) * (lv[k].Ny + 4);
+  return 8 * n;
+}
+
+__device__ __forceinline__ void dm_wg_jacobi(const DmLevel& L, const double* __restrict__ src,
+                                             double* __restrict__ dst) {
+  const double s = kDmOmega * L.h * L.h / 5.0;
+  const long n = (long)L.Nx * L.Ny;
+  for (long k = threadIdx.x; k < n; k += 256) {
+    const int j = (int)(k / L.Nx), i = (int)(k - (long)j * L.Nx);
+    const long o = dm_at(L, j, i);
+    dst[o] = src[o] - s * (L.rhs[o] - dm_lap(src, L.pitch, j, i, L.h));
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) dm_vcycle_small(DmHierarchy H, int l0, const DevStatus* st) {
+  if (dm_skip(st)) return;
+  extern __shared__ double smem[];
+  const int last = H.nlev - 1;
+  // the LDS copy of level l (its planes follow those of levels l0 .. l - 1); a
+  // value built per use, so that no array of levels is indexed at run time
+  auto lds_level = [&](int l) {
+    long off = 0;
+    for (int k = l0; k < l; ++k) off += 3L * (H.lv[k].Nx + 4) * (H.lv[k].Ny + 4);
+    DmLevel L = H.lv[l];
+    const long pl = (long)(L.Nx + 4) * (L.Ny + 4);
+    L.psi = smem + off;
+    L.tmp = smem + off + pl;
+    L.rhs = smem + off + 2 * pl;
+    return L;
+  };
+  // every plane zero (halos included) before the interior of level l0 is read in
+  const long total = dm_small_bytes(H.lv, H.nlev, l0) / 8;
+  for (long k = threadIdx.x; k < total; k += 256) smem[k] = 0.0;
+  __syncthreads();
+  const DmLevel L0 = lds_level(l0);
+  {
+    const DmLevel& G = H.lv[l0];
+    const long n = (long)G.Nx * G.Ny;
+    for (long k = threadIdx.x; k < n; k += 256) {
+      const int j = (int)(k / G.Nx), i = (int)(k - (long)j * G.Nx);
+      const long o = dm_at(G, j, i);
+      L0.rhs[o] = G.rhs[o];
+      L0.psi[o] = G.psi[o];
+    }
+    __syncthreads();
+  }
+  for (int l = l0; l < last; ++l) {
+    const DmLevel F = lds_level(l);
+    const DmLevel C = lds_level(l + 1);
+    for (int k = 0; k < kDmSmooth; k += 2) {
+      dm_wg_jacobi(F, F.psi, F.tmp);
+      dm_wg_jacobi(F, F.tmp, F.psi);
+    }
+    const long nf = (long)F.Nx * F.Ny;
+    for (long k = threadIdx.x; k < nf; k += 256) {
+      const int j = (int)(k / F.Nx), i = (int)(k - (long)j * F.Nx);
+      const long o = dm_at(F, j, i);
+      F.tmp[o] = F.rhs[o] - dm_lap(F.psi, F.pitch, j, i, F.h);
+    }
+    __syncthreads();
+    const long nc = (long)C.Nx * C.Ny;
+    for (long k = threadIdx.x; k < nc; k += 256) {
+      const int J = (int)(k / C.Nx), I = (int)(k - (long)J * C.Nx);
+      double acc = 0.0;
+      for (int j = max(2 * J - 1, 0); j <= min(2 * J + 2, F.Ny - 1); ++j) {
+        double row = 0.0;
+        for (int i = max(2 * I - 1, 0); i <= min(2 * I + 2, F.Nx - 1); ++i) row += dm_w(i, I) * F.tmp[dm_at(F, j, i)];
+        acc += dm_w(j, J) * row;
+      }
+      const long o = dm_at(C, J, I);
+      C.rhs[o] = 0.25 * acc;
+      C.psi[o] = 0.0;
+    }
+    __syncthreads();
+  }
+  const DmLevel B = lds_level(last);
+  for (int k = 0; k < kDmCoarse; k += 2) {
+    dm_wg_jacobi(B, B.psi, B.tmp);
+    dm_wg_jacobi(B, B.tmp, B.psi);
+  }
+  for (int l = last - 1; l >= l0; --l) {
+    const DmLevel F = lds_level(l);
+    const DmLevel C = lds_level(l + 1);
+    const long nf = (long)F.Nx * F.Ny;
+    for (long k = threadIdx.x; k < nf; k += 256) {
+      const int j = (int)(k / F.Nx), i = (int)(k - (long)j * F.Nx);
+      const int J = j >> 1, I = i >> 1;
+      const int J2 = J + ((j & 1) ? 1 : -1), I2 = I + ((i & 1) ? 1 : -1);
+      auto cv = [&](int jj, int ii) -> double {
+        return (ii >= 0 && ii < C.Nx && jj >= 0 && jj < C.Ny) ? C.psi[dm_at(C, jj, ii)] : 0.0;
+      };
+      F.psi[dm_at(F, j, i)] += 0.5625 * cv(J, I) + 0.1875 * (cv(J, I2) + cv(J2, I)) + 0.0625 * cv(J2, I2);
+    }
+    __syncthreads();
+    for (int k = 0; k < kDmSmooth; k += 2) {
+      dm_wg_jacobi(F, F.psi, F.tmp);
+      dm_wg_jacobi(F, F.tmp, F.psi);
+    }
+  }
+  {
+    const DmLevel& G = H.lv[l0];
+    const long n = (long)G.Nx * G.Ny;
+    for (long k = threadIdx.x; k < n; k += 256) {
+      const int j = (int)(k / G.Nx), i = (int)(k - (long)j * G.Nx);
+      const long o = dm_at(G, j, i);
+      G.psi[o] = L0.psi[o];
+    }
+  }
+}
+
 // tmp = rhs - Laplace_h psi
 __global__ void __launch_bounds__(256) dm_residual(DmLevel L, const DevStatus* st) {
   if (dm_skip(st)) return;
@@ -109,13 +246,6 @@ __global__ void __launch_bounds__(256) dm_residual(DmLevel L, const DevStatus* s
     const long o = dm_at(L, j, i);
     L.tmp[o] = L.rhs[o] - dm_lap(L.psi, L.pitch, j, i, L.h);
   }
-}
-
-// 1-D weight of fine index f in coarse cell J (transpose of the prolongation):
-// f = 2J - 1 and 2J + 2 carry 1/4, f = 2J and 2J + 1 carry 3/4.
-__device__ __forceinline__ double dm_w(int f, int J) {
-  const int d = f - 2 * J;
-  return (d == 0 || d == 1) ? 0.75 : 0.25;
 }
 
 // Coarse right-hand side = P^T (fine residual) / 4; coarse psi = 0.
@@ -198,11 +328,12 @@ __global__ void __launch_bounds__(256) dm_dot(DmLevel L0, const double* __restri
 
 // rz = sum of the partials; beta = rz / rz_previous (0 on the first iteration or
 // once rz_previous is 0).
-__global__ void __launch_bounds__(64) dm_beta(const double* __restrict__ part, double* sc, int first,
-                                              const DevStatus* st) {
-  if (dm_skip(st) || threadIdx.x != 0) return;
-  double rz = 0.0;
-  for (int k = 0; k < kDmRedGroups; ++k) rz += part[k];
+__global__ void __launch_bounds__(256) dm_beta(const double* __restrict__ part, double* sc, int first,
+                                               const DevStatus* st) {
+  if (dm_skip(st)) return;
+  __shared__ double red[4];
+  const double rz = dm_block_sum(part[threadIdx.x], red);  // kDmRedGroups == 256 partials
+  if (threadIdx.x != 0) return;
   sc[1] = (first || sc[0] == 0.0) ? 0.0 : rz / sc[0];
   sc[0] = rz;
 }
@@ -235,10 +366,11 @@ __global__ void __launch_bounds__(256) dm_matvec(DmLevel L0, DmVecs D, const Dev
 }
 
 // alpha = r.z / d.Ad (0 once d.Ad is 0: the residual has vanished)
-__global__ void __launch_bounds__(64) dm_alpha(DmVecs D, const DevStatus* st) {
-  if (dm_skip(st) || threadIdx.x != 0) return;
-  double dad = 0.0;
-  for (int k = 0; k < kDmRedGroups; ++k) dad += D.part[k];
+__global__ void __launch_bounds__(256) dm_alpha(DmVecs D, const DevStatus* st) {
+  if (dm_skip(st)) return;
+  __shared__ double red[4];
+  const double dad = dm_block_sum(D.part[threadIdx.x], red);
+  if (threadIdx.x != 0) return;
   D.sc[3] = dad;
   D.sc[2] = dad > 0.0 ? D.sc[0] / dad : 0.0;
 }
