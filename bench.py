@@ -62,6 +62,46 @@ WORKLOADS = {
 BF16_DENSE_PEAK_TFLOPS = 2500.0
 
 
+def unet_step_bytes(wl):
+    """Bytes one training step of the U-Net reads and writes in its activation
+    tensors (BF16), layer by layer, per pixel of the layer's level: forward reads
+    the input (C_in) and writes the pre-activation and the activation (2 C_out);
+    backward reads the output gradient and the pre-activation (2 C_out) and the input
+    (C_in) and writes the input gradient (C_in); the weight gradient reads the
+    input and the output gradient again (C_in + C_out). Weights, pooling,
+    upsampling and the head are small beside these and are left out."""
+    from paper_2603_24370_amd.learned import unet_param_shapes
+    total = 0
+    for name, shp in unet_param_shapes(wl["levels"], wl["base"], wl["cin"], wl["cout"]):
+        if not name.endswith(".w") or len(shp) != 4:
+            continue
+        cout, cin = shp[0], shp[3]
+        level = 0 if name.startswith("head") else int(name[3]) if name[:3] in ("enc", "dec") else wl["levels"] - 1
+        pixels = wl["N"] * (wl["H"] >> level) * (wl["W"] >> level)
+        total += pixels * 2 * ((cin + 2 * cout) + (2 * cout + 2 * cin) + (cin + cout))
+    return total
+
+
+def unet_roofline(tflops, step_bytes, step_flops, step_s, infer_tflops):
+    """Roofline of the U-Net training step. Its arithmetic intensity (flops over the
+    activation bytes of unet_step_bytes) lies below the BF16 ridge (2.5 PFLOP/s over
+    8 TB/s = 312 flop/B), so HBM bounds it: achieved = those bytes over the step
+    time, against 8 TB/s."""
+    intensity = step_flops / step_bytes
+    gbps = step_bytes / step_s / 1e9
+    ridge = BF16_DENSE_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    bound = "hbm" if intensity < ridge else "mfma"
+    if bound == "hbm":
+        ach, peak, unit = gbps, HBM_PEAK_GBS, "GB/s"
+    else:
+        ach, peak, unit = tflops, BF16_DENSE_PEAK_TFLOPS, "TFLOP/s"
+    return {"bound": bound, "achieved": round(ach, 2), "peak": peak, "unit": unit, "frac": round(ach / peak, 4),
+            "traffic": None, "kernel": "conv3x3_tiled + conv3x3_mfma + conv3x3_wgrad (whole training step)",
+            "intensity_flop_per_B": round(intensity, 1), "ridge_flop_per_B": round(ridge, 1),
+            "TFLOPs": round(tflops, 2), "frac_of_bf16_peak": round(tflops / BF16_DENSE_PEAK_TFLOPS, 4),
+            "step_GB": round(step_bytes / 1e9, 4), "inference_TFLOPs": round(infer_tflops, 2)}
+
+
 def run_unet(args, wl):
     """Training throughput of the learned initialiser's U-Net (BF16 MFMA, FP32
     accumulate): forward + backward + Adam on batches of 8 images of 256^2."""
@@ -92,6 +132,7 @@ def run_unet(args, wl):
     el = time.perf_counter() - t0
     f_fwd, f_bwd = net.flops()
     tfl = args.steps * wl["N"] * (f_fwd + f_bwd) / el / 1e12
+    step_bytes = unet_step_bytes(wl)
     # inference alone
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -104,10 +145,7 @@ def run_unet(args, wl):
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)",
            "data": "synthetic", "config": {"workload": "unet256", **wl},
-           "roofline": {"bound": "mfma", "achieved": round(tfl, 2), "peak": BF16_DENSE_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(tfl / BF16_DENSE_PEAK_TFLOPS, 4), "traffic": None,
-                        "kernel": "conv3x3_tiled + conv3x3_mfma + conv3x3_wgrad (whole training step)",
-                        "inference_TFLOPs": round(tfl_f, 2)},
+           "roofline": unet_roofline(tfl, step_bytes, wl["N"] * (f_fwd + f_bwd), el / args.steps, tfl_f),
            "cpu_baseline": None}
     print(json.dumps(out), flush=True)
     net.close()
@@ -319,13 +357,14 @@ INTEGRATOR_NAMES = {"rk4": "RK4 arrested Newton flow, dt = 0.5 h",
                     "gf": "gradient flow (one pass per step), tau = dt^2 / 2, dt = 0.5 h"}
 
 
-def make_solver(wl, autotune_steps=10, integrator="rk4"):
+def make_solver(wl, autotune_steps=10, integrator="rk4", grad="el"):
     import paper_2603_24370_amd as ss
     from paper_2603_24370_amd import inputs as I
     tune = None
+    gm = ss.SS_GRAD_EXACT if grad == "exact" else ss.SS_GRAD_EL
     if wl["theory"] == "abelian_higgs":
         lam = I.gl_lambda_from_kappa(wl["kappa"])
-        s = ss.Solver("abelian_higgs", wl["N"], wl["N"], wl["h"], [lam], dtype=wl["dtype"])
+        s = ss.Solver("abelian_higgs", wl["N"], wl["N"], wl["h"], [lam], dtype=wl["dtype"], grad_mode=gm)
         s.set_integrator(integrator)
         if autotune_steps:
             tune = s.autotune(autotune_steps)
@@ -337,7 +376,7 @@ def make_solver(wl, autotune_steps=10, integrator="rk4"):
         params = [lam]
     else:
         params = [1.0, 1.0, 0.1, 0.6]
-        s = ss.Solver("chiral_magnet", wl["N"], wl["N"], wl["h"], params, dtype=wl["dtype"])
+        s = ss.Solver("chiral_magnet", wl["N"], wl["N"], wl["h"], params, dtype=wl["dtype"], grad_mode=gm)
         s.set_integrator(integrator)
         if autotune_steps:
             tune = s.autotune(autotune_steps)
@@ -358,7 +397,7 @@ def host_cores() -> int:
     return max(1, n)
 
 
-def cpu_baseline(s, wl, params, window=1024, steps=None, scheme="rk4", target_s=3.0):
+def cpu_baseline(s, wl, params, window=1024, steps=None, scheme="rk4", target_s=3.0, grad="el"):
     """The FP64 oracle as it stands (one thread per call) on windows of the same
     field: first one core on the central window, then every usable host core at
     once, one window per thread (the oracle is a C library called through
@@ -376,14 +415,16 @@ def cpu_baseline(s, wl, params, window=1024, steps=None, scheme="rk4", target_s=
     def window_at(a, b):
         return np.ascontiguousarray(f[:, a:a + w + 4, b:b + w + 4])
 
+    mode = oracle.GRAD_EXACT if grad == "exact" else oracle.GRAD_EL
+
     def run(sub):
-        oracle.flow(wl["theory"], sub, np.zeros_like(sub), wl["h"], params, steps, scheme=scheme)
+        oracle.flow(wl["theory"], sub, np.zeros_like(sub), wl["h"], params, steps, scheme=scheme, mode=mode)
 
     c = (N - w) // 2
     if steps is None:
         t0 = time.perf_counter()
         oracle.flow(wl["theory"], window_at(c, c), np.zeros_like(window_at(c, c)), wl["h"], params, 2,
-                    scheme=scheme)
+                    scheme=scheme, mode=mode)
         steps = int(min(100000, max(10, math.ceil(target_s / max((time.perf_counter() - t0) / 2, 1e-9)))))
     t0 = time.perf_counter()
     run(window_at(c, c))
@@ -445,6 +486,8 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=20)
     ap.add_argument("--autotune-steps", type=int, default=10, help="0 = keep the default tile shape")
     ap.add_argument("--converge-max-steps", type=int, default=400000)
+    ap.add_argument("--grad", default="el", choices=["el", "exact"],
+                    help="gradient form: the Euler-Lagrange expression (default) or the exact h^-2 dE_h/dphi")
     ap.add_argument("--integrator", default="vv", choices=sorted(INTEGRATOR_NAMES),
                     help="vv (velocity Verlet arrested Newton flow, default), rk4 (RK4 arrested Newton flow) or "
                          "gf (gradient flow)")
@@ -483,7 +526,7 @@ def main():
     if args.workload.startswith("unet"):
         run_unet(args, wl)
         return
-    s, params, tune = make_solver(wl, args.autotune_steps, args.integrator)
+    s, params, tune = make_solver(wl, args.autotune_steps, args.integrator, args.grad)
     N = wl["N"]
     sites = N * N
     C = s.C
@@ -521,10 +564,13 @@ def main():
         step_sets = STEP_SETS if plan == 0 else STEP_SETS_FUSED
     step_gbps = step_sets * C * b * sites / (ms_step * 1e-3) / 1e9
     import paper_2603_24370_amd as ss
-    tr = traffic_record(dom, args.workload, ss.ss_get_tile(s.ctx))
+    # the counter record covers the Euler-Lagrange kernels only
+    tr = traffic_record(dom, args.workload, ss.ss_get_tile(s.ctx)) if args.grad == "el" else None
     tr_gb = tr["total_GB"] if tr else None
     kname = {"P234": "stage_pass_fused (stages 2-4)", "VV": "stage_pass (velocity Verlet step)",
              "GF": "stage_pass (gradient-flow step)"}.get(dom, f"stage_pass {dom}")
+    if args.grad == "exact":
+        kname = f"stage_pass_exact {dom}"
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr_gb, "traffic_unit": "GB per launch (rocprofv3 "
             "FETCH_SIZE x2 + WRITE_SIZE x1, scaled on a plain copy)", "traffic_over_algorithmic": tr["ratio"] if tr else None,
@@ -539,7 +585,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(s, wl, params, scheme=args.integrator)
+        cpu = cpu_baseline(s, wl, params, scheme=args.integrator, grad=args.grad)
 
     out = {
         "metric": "site-updates/s",
@@ -555,7 +601,8 @@ def main():
         "dtype": "f32 fields, f64 reductions" if wl["dtype"] == "f32" else "f64",
         "data": "synthetic (seeded ansatz + noise)",
         "config": {"workload": args.workload, "theory": wl["theory"], "Nx": N, "Ny": N, "h": wl["h"],
-                   "kappa": wl.get("kappa"), "vortices": wl.get("nv"), "grad_form": "euler-lagrange",
+                   "kappa": wl.get("kappa"), "vortices": wl.get("nv"),
+                   "grad_form": "euler-lagrange" if args.grad == "el" else "exact",
                    "integrator": INTEGRATOR_NAMES[args.integrator], "parallelism": "single GPU"},
         "roofline": roof,
         "tile": {"chosen": list(ss_tile(tune[0])) if tune else None,
