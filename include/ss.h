@@ -48,8 +48,8 @@
  *       holds the atom number N = h^2 sum |psi|^2 fixed (every stage point is
  *       scaled to N and the force projected on the tangent space of that sphere,
  *       with the chemical potential as multiplier; after each step the field is
- *       scaled and the velocity projected). Euler-Lagrange gradient, RK4,
- *       SS_PLAN_STAGES and single contexts only; ss_energy_grad returns the
+ *       scaled and the velocity projected). Euler-Lagrange gradient,
+ *       SS_PLAN_STAGES and single contexts only (every integrator); ss_energy_grad returns the
  *       projected gradient at the field scaled to N and the energy of the field as
  *       given.
  *   params.i (optional, ni <= 3) = {grad_mode, dmi_kind, demag}:

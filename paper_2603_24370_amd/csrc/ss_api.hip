@@ -335,14 +335,13 @@ void demag_solve(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   }
 }
 
-// A BEC pass (RK4 stages, the check and the evaluation): the stage point and its
-// norm, its scale to the atom number, G and the sums for mu, mu, the force and the
-// pass's update; P4 ends with the step's constraint, a reducing pass with the
+// A BEC pass (RK4 stages, the one-pass steps, the check, the prime pass and the
+// evaluation): the stage point and its norm, its scale to the atom number, G and
+// the sums for mu, mu, the force and the pass's update; P4 ends with the step's
+// constraint, velocity Verlet with the projection of v', a reducing pass with the
 // status update.
 template <class T, int PASS>
 void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
-  static_assert(PASS == kP1 || PASS == kP2 || PASS == kP3 || PASS == kP4 || PASS == kEval || PASS == kCheck,
-                "the BEC runs the RK4 stages");
   BecBufs<T> W;
   W.S = (T*)c->bec_S;
   W.G = (T*)c->bec_G;
@@ -356,10 +355,13 @@ void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   hipLaunchKernelGGL(bec_mu, dim3(1), b1, 0, s, (const double*)W.part, W.sc, a.cf, (const DevStatus*)c->st, flow);
   hipLaunchKernelGGL((bec_apply<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, W, (const double*)W.sc,
                      a.out, a.out_pitch, a.out_plane);
-  if constexpr (PASS == kP4) {
+  if constexpr (PASS == kP4 || PASS == kVV) {
     hipLaunchKernelGGL(bec_fix_scalars, dim3(1), b1, 0, s, (const double*)W.part, W.sc, a.cf,
                        (const DevStatus*)c->st);
-    hipLaunchKernelGGL((bec_fix<T>), g, b, 0, s, a.B, (const DevStatus*)c->st, (const double*)W.sc);
+    if constexpr (PASS == kP4)
+      hipLaunchKernelGGL((bec_fix<T>), g, b, 0, s, a.B, (const DevStatus*)c->st, (const double*)W.sc);
+    else
+      hipLaunchKernelGGL((bec_vproj<T>), g, b, 0, s, a.B, (const DevStatus*)c->st, (const double*)W.sc);
   }
   if constexpr (reduces(PASS))
     hipLaunchKernelGGL((bec_finalise<PASS>), dim3(1), b1, 0, s, c->st, (const double*)W.part, (const double*)W.sc);
@@ -371,8 +373,7 @@ void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
 template <class T, int PASS>
 void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   if (c->theory == SS_THEORY_BEC) {
-    if constexpr (PASS == kP1 || PASS == kP2 || PASS == kP3 || PASS == kP4 || PASS == kEval || PASS == kCheck)
-      bec_pass<T, PASS>(c, a, s);
+    bec_pass<T, PASS>(c, a, s);
     return;
   }
   if (c->dm.on) demag_solve<T, PASS>(c, a, s);
@@ -1360,8 +1361,6 @@ int ss_set_integrator(ss_ctx* c, int integ) {
   if (!c) return fail(SS_EINVAL, "ctx is NULL");
   if (integ != SS_INTEG_RK4 && integ != SS_INTEG_VV && integ != SS_INTEG_GF)
     return fail(SS_EINVAL, "unknown integrator");
-  if (integ != SS_INTEG_RK4 && c->theory == SS_THEORY_BEC)
-    return fail(SS_EINVAL, "the BEC runs with the RK4 integrator");
   SS_HIP(hipStreamSynchronize(c->stream));
   c->integ = integ;
   if (c->graph) {

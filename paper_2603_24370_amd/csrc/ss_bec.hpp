@@ -71,19 +71,23 @@ __global__ void __launch_bounds__(256) bec_stage(Bufs<T> B, Coeffs cf, const Dev
                                                  const T* __restrict__ src, BecBufs<T> W) {
   if (PASS != kEval && st->done) return;
   __shared__ double red[4];
-  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  constexpr bool AFTER_P1 = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  constexpr bool ONEPASS = advances_first(PASS);
+  constexpr bool STAGED = AFTER_P1 || ONEPASS;
   const long long step = st->step;
-  const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
-  const bool arrest = STAGED ? (st->arrest != 0) : false;
+  const int cur = AFTER_P1 ? int((step - 1) & 1) : int(step & 1);
+  const bool arrest = (AFTER_P1 || PASS == kVV) ? (st->arrest != 0) : false;
   const T dt = (T)cf.dt;
   T cv = T(0), ca = T(0);
   if (PASS == kP2) cv = T(0.5) * dt;
   if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
-  if (PASS == kP4) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (PASS == kP4 || PASS == kVV) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (PASS == kGF) ca = T(0.5) * dt * dt;
   if (arrest) cv = T(0);
   const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : (cur ? B.phi[1] : B.phi[0]);
   const T* __restrict__ vv = cur ? B.vel[1] : B.vel[0];
-  const T* __restrict__ aa = (PASS == kP3) ? B.a1 : B.a2;
+  // one-pass integrators: the current field's force in the buffer of the step's parity
+  const T* __restrict__ aa = ONEPASS ? (cur ? B.a2 : B.a1) : (PASS == kP3) ? B.a1 : B.a2;
   const long Wd = B.Nx + 4, H = B.Ny + 4;
   double acc = 0.0;
   BEC_SITES(Wd * H) {
@@ -94,7 +98,7 @@ __global__ void __launch_bounds__(256) bec_stage(Bufs<T> B, Coeffs cf, const Dev
     for (int c = 0; c < 2; ++c) {
       T x = ph[c * B.plane + o];
       if (STAGED) {
-        x += cv * vv[c * B.plane + o];
+        if (PASS != kGF) x += cv * vv[c * B.plane + o];
         if (PASS != kP2) x += ca * aa[c * B.plane + o];
       }
       W.S[c * B.plane + o] = x;
@@ -122,8 +126,9 @@ __device__ __forceinline__ T bec_at(const T* __restrict__ S, long pitch, int Nx,
 }
 
 // G at the scaled stage point; partials {psi.G, psi.psi, energy density sum,
-// non-finite count}. The energy is that of the stage point as stored (unscaled),
-// in FP64, as the energy of the other theories.
+// non-finite count}. The energy is that of the field the pass tests, in FP64: the
+// stage point as stored (unscaled) for an evaluation, a check or the first stage of
+// RK4; the scaled stage point, which becomes the new field, for a one-pass step.
 template <class T, int PASS>
 __global__ void __launch_bounds__(256) bec_grad(Bufs<T> B, Coeffs cf, const DevStatus* __restrict__ st,
                                                 BecBufs<T> W, const double* __restrict__ sc) {
@@ -153,7 +158,9 @@ __global__ void __launch_bounds__(256) bec_grad(Bufs<T> B, Coeffs cf, const DevS
       dy[comp] = c1 * ((ym2 - yp2) + T(8) * (yp1 - ym1));
       lap[comp] = c2 * ((-(xm2 + xp2) + T(16) * (xm1 + xp1)) + (-(ym2 + yp2) + T(16) * (ym1 + yp1)) - T(60) * x0);
       if (REDUCE) {
-        auto raw = [&](int dj, int di) { return (double)Sc[(long)(jj + dj) * B.pitch + (ii + di)]; };
+        auto raw = [&](int dj, int di) {
+          return advances_first(PASS) ? (double)at(dj, di) : (double)Sc[(long)(jj + dj) * B.pitch + (ii + di)];
+        };
         fd[comp] = raw(0, 0);
         dxd[comp] = d1 * ((raw(0, -2) - raw(0, 2)) + 8.0 * (raw(0, 1) - raw(0, -1)));
         dyd[comp] = d1 * ((raw(-2, 0) - raw(2, 0)) + 8.0 * (raw(1, 0) - raw(-1, 0)));
@@ -222,8 +229,11 @@ __global__ void __launch_bounds__(256) bec_apply(Bufs<T> B, Coeffs cf, const Dev
   constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
   const long long step = st->step;
   const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
-  const bool arrest = STAGED ? (st->arrest != 0) : false;
+  const bool arrest = (STAGED || PASS == kVV) ? (st->arrest != 0) : false;
   const T c = (T)sc[0], mu = (T)sc[1];
+  // one-pass integrators: current force (read) and new force (written) by parity
+  const T* __restrict__ a_cur = cur ? B.a2 : B.a1;
+  T* __restrict__ a_new = cur ? B.a1 : B.a2;
   const T dt = (T)cf.dt;
   const T* __restrict__ ph = cur ? B.phi[1] : B.phi[0];
   const T* __restrict__ vv = cur ? B.vel[1] : B.vel[0];
@@ -251,6 +261,27 @@ __global__ void __launch_bounds__(256) bec_apply(Bufs<T> B, Coeffs cf, const Dev
     } else if (PASS == kP1) {
       B.a1[o] = a[0];
       B.a1[B.plane + o] = a[1];
+    } else if (PASS == kPrime) {
+      // the current field's force, in the buffer of the step's parity
+      T* __restrict__ as = cur ? B.a2 : B.a1;
+      as[o] = a[0];
+      as[B.plane + o] = a[1];
+    } else if (PASS == kVV || PASS == kGF) {
+      // the scaled stage point is the new field; velocity Verlet also forms
+      // v' = v + dt/2 (a + a'), projected by bec_vproj after the sums below
+#pragma unroll
+      for (int comp = 0; comp < 2; ++comp) {
+        const long k = comp * B.plane + o;
+        const T pn = c * W.S[k];
+        phn[k] = pn;
+        a_new[k] = a[comp];
+        spp += (double)pn * (double)pn;
+        if (PASS == kVV) {
+          const T vnew = (arrest ? T(0) : vv[k]) + (T(0.5) * dt) * (a_cur[k] + a[comp]);
+          vn[k] = vnew;
+          spv += (double)pn * (double)vnew;
+        }
+      }
     } else if (PASS == kP2) {
       B.a2[o] = a[0];
       B.a2[B.plane + o] = a[1];
@@ -275,16 +306,15 @@ __global__ void __launch_bounds__(256) bec_apply(Bufs<T> B, Coeffs cf, const Dev
       }
     }
   }
-  if (PASS == kP4) {
-    const double a0 = bec_block_sum(spp, red);
-    const double a1 = bec_block_sum(spv, red);
-    if (threadIdx.x == 0) {
-      W.part[2 * (long)blockIdx.x] = a0;
-      W.part[2 * (long)blockIdx.x + 1] = a1;
-    }
-  } else if (reduces(PASS)) {
-    const double m = bec_block_max(gm, red);
-    if (threadIdx.x == 0) W.part[blockIdx.x] = m;
+  // partials, four per workgroup: {max |G - mu psi|, phi'.phi', phi'.v', unused}
+  const double m = reduces(PASS) ? bec_block_max(gm, red) : 0.0;
+  const double a1 = (PASS == kP4 || PASS == kVV) ? bec_block_sum(spp, red) : 0.0;
+  const double a2 = (PASS == kP4 || PASS == kVV) ? bec_block_sum(spv, red) : 0.0;
+  if (threadIdx.x == 0) {
+    double* p = W.part + 4 * (long)blockIdx.x;
+    p[0] = m;
+    p[1] = a1;
+    p[2] = a2;
   }
 }
 
@@ -296,7 +326,7 @@ __global__ void __launch_bounds__(256) bec_finalise(DevStatus* st, const double*
   if (PASS != kEval && st->done) return;
   __shared__ double red[4];
   double gm = 0.0;
-  for (int k = threadIdx.x; k < kBecGroups; k += 256) gm = fmax(gm, part[k]);
+  for (int k = threadIdx.x; k < kBecGroups; k += 256) gm = fmax(gm, part[4 * (long)k]);
   gm = bec_block_max(gm, red);
   if (threadIdx.x == 0) finalise_status<PASS>(st, sc[2], gm, (int)sc[3]);
 }
@@ -307,8 +337,8 @@ __global__ void __launch_bounds__(256) bec_fix_scalars(const double* __restrict_
                                                        const DevStatus* __restrict__ st) {
   if (st->done) return;
   __shared__ double red[4];
-  const double pp = bec_partials_sum(part, 2, 0, red);
-  const double pv = bec_partials_sum(part, 2, 1, red);
+  const double pp = bec_partials_sum(part, 4, 1, red);
+  const double pv = bec_partials_sum(part, 4, 2, red);
   if (threadIdx.x == 0) {
     sc[4] = sqrt(cf.p[2] / (cf.h * cf.h * pp));
     sc[5] = pv / pp;
@@ -333,6 +363,28 @@ __global__ void __launch_bounds__(256) bec_fix(Bufs<T> B, const DevStatus* __res
       const T p = ph[k];
       v[k] = v[k] - m * p;
       ph[k] = cs * p;
+    }
+  }
+}
+
+// Velocity Verlet: v' projected on the tangent space at the new field (which the
+// pass wrote into the buffer of the other parity; the step counter advances after).
+template <class T>
+__global__ void __launch_bounds__(256) bec_vproj(Bufs<T> B, const DevStatus* __restrict__ st,
+                                                 const double* __restrict__ sc) {
+  if (st->done) return;
+  const int nxt = 1 - int(st->step & 1);
+  const T* __restrict__ ph = nxt ? B.phi[1] : B.phi[0];
+  T* __restrict__ v = nxt ? B.vel[1] : B.vel[0];
+  const T m = (T)sc[5];
+  const long n = (long)B.Nx * B.Ny;
+  BEC_SITES(n) {
+    const int j = (int)(k_ / B.Nx), i = (int)(k_ - (long)j * B.Nx);
+    const long o = (long)(j + 2) * B.pitch + (i + 2);
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+      const long k = comp * B.plane + o;
+      v[k] = v[k] - m * ph[k];
     }
   }
 }

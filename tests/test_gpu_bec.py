@@ -1,6 +1,7 @@
 """The rotating trapped BEC (Sec. 4.3) on the device, through the C ABI, against
 the FP64 oracle's "bec" theory {g, Omega, N}: energy and constrained gradient,
-RK4 trajectories with the atom-number constraint, minima and observables.
+RK4, velocity Verlet and gradient-flow trajectories with the atom-number
+constraint, minima and observables.
 
 Tolerances. FP64: energies 1e-12, gradients 1e-10 of max|G|, fields after a few
 steps 1e-11. FP32 gradients: each term's rounding bounded separately, with M =
@@ -85,19 +86,22 @@ def test_energy_and_constrained_gradient(ss, orc, dtype, shape):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_flow_tracks_the_oracle_and_holds_the_atom_number(ss, orc, dtype):
+@pytest.mark.parametrize("scheme", ["rk4", "vv", "gf"])
+def test_flow_tracks_the_oracle_and_holds_the_atom_number(ss, orc, dtype, scheme):
     Nx, Ny, h = 96, 70, 0.15
     p = [2.0, 0.7, 3.0]
-    print(f"[case] bec flow {dtype}", flush=True)
+    print(f"[case] bec flow {scheme} {dtype}", flush=True)
     f = _field(Nx, Ny, h, seed=21)
     if dtype == "f32":
         f = f.astype(np.float32).astype(np.float64)
     s = ss.Solver(BEC, Nx, Ny, h, p, dtype=dtype)
+    if scheme != "rk4":
+        s.set_integrator(scheme)
     s.set_field(f)
     n = 8
     info = s.flow_step(n)
     phi, vel = (_np(x) for x in s.get_field(velocity=True))
-    phi_r, v_r, E_r, na_r = orc.flow(BEC, f, np.zeros_like(f), h, p, n)
+    phi_r, v_r, E_r, na_r = orc.flow(BEC, f, np.zeros_like(f), h, p, n, scheme=scheme)
     rel = 1e-11 if dtype == "f64" else 2e-5
     assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max()
     assert np.abs(vel - v_r).max() <= rel * max(np.abs(v_r).max(), np.abs(phi_r).max())
@@ -112,7 +116,8 @@ def test_flow_tracks_the_oracle_and_holds_the_atom_number(ss, orc, dtype):
     s.close()
 
 
-def test_ground_state_without_interaction(ss, orc):
+@pytest.mark.parametrize("scheme", ["rk4", "vv"])
+def test_ground_state_without_interaction(ss, orc, scheme):
     """FP64, g = 0, Omega = 0.5: the minimum is the oscillator ground state, E = N to
     the O(h^4) error; the stop step and arrest count equal the oracle's. The stop
     tolerance 1e-5 keeps the energy change per step (~dt^2 |G|^2 ~ 1e-12) far above
@@ -121,9 +126,11 @@ def test_ground_state_without_interaction(ss, orc):
     p = [0.0, 0.5, Nat]
     f = I.bec_ansatz(N, N, h, R=1.6) * 1.3 + I.noise(3, 2, N, N, 1e-2)
     s = ss.Solver(BEC, N, N, h, p, dtype="f64")
+    if scheme != "rk4":
+        s.set_integrator(scheme)
     s.set_field(f)
     res = s.minimise(grad_tol=1e-5, max_steps=20000, graph_steps=16)
-    phi_r, _, ref = orc.minimise(BEC, f, h, p, grad_tol=1e-5, max_steps=20000)
+    phi_r, _, ref = orc.minimise(BEC, f, h, p, grad_tol=1e-5, max_steps=20000, scheme=scheme)
     print(f"[bec] ground state: steps {res['step']} (oracle {ref['steps']}), E {res['energy']:.12f}", flush=True)
     assert res["reason"] == "grad" and ref["reason"] == 1
     assert res["step"] == ref["steps"] and res["n_arrests"] == ref["arrests"]
@@ -202,8 +209,6 @@ def test_bec_refuses_what_it_cannot_run(ss):
     assert s.plan == ss.SS_PLAN_STAGES
     with pytest.raises(ss.SSError):
         s.set_plan(ss.SS_PLAN_FUSED)
-    with pytest.raises(ss.SSError):
-        s.set_integrator("vv")
     with pytest.raises(ss.SSError):
         s.init_skyrmion()
     s.close()
