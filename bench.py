@@ -227,6 +227,7 @@ def run_batch(args, wl):
     from paper_2603_24370_amd import inputs as I
     insts = [I.gl_batch_instance(b, wl["base_seed"], wl["h"]) for b in range(wl["n"])]
     B = ss.Batch("abelian_higgs", [(m.Nx, m.Ny, m.h, m.params) for m in insts], dtype=wl["dtype"])
+    B.set_integrator(args.integrator)
     tune = B.autotune(args.autotune_steps) if args.autotune_steps else None
     for m, mem in zip(insts, B.members):
         mem.init_vortices(m.centres, seed=m.seed, noise_amp=1e-3)
@@ -239,20 +240,27 @@ def run_batch(args, wl):
     el = time.perf_counter() - t0
     ms_step = 1e3 * el / args.steps
     batch_plan = B.plan
-    step_sets = STEP_SETS_FUSED if batch_plan == 1 else STEP_SETS
+    one_pass = args.integrator != "rk4"
+    if one_pass:
+        step_sets = sum(PASS_SETS[args.integrator.upper()])
+        kname = f"batch_pass ({args.integrator.upper()} step)"
+    else:
+        step_sets = STEP_SETS_FUSED if batch_plan == 1 else STEP_SETS
+        kname = ("batch_pass + batch_pass_fused (whole step)" if step_sets == STEP_SETS_FUSED
+                 else "batch_pass (whole step)")
     step_gbps = step_sets * 4 * 4 * sites / (ms_step * 1e-3) / 1e9
     out = {"metric": "site-updates/s", "value": sites * args.steps / el, "unit": "site-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32 fields, f64 reductions",
            "data": "synthetic (seeded ansatz + noise)",
            "config": {"workload": "batch256", "members": wl["n"], "interior_sites": sites, "h": wl["h"],
-                      "grad_form": "euler-lagrange", "parallelism": "single GPU, one launch per pass"},
+                      "grad_form": "euler-lagrange", "integrator": INTEGRATOR_NAMES[args.integrator],
+                      "parallelism": "single GPU, one launch per pass"},
            "roofline": {"bound": "hbm", "achieved": round(step_gbps, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(step_gbps / HBM_PEAK_GBS, 4), "traffic": None, "step_sets": step_sets,
-                        "kernel": "batch_pass + batch_pass_fused (whole step)" if step_sets == STEP_SETS_FUSED
-                        else "batch_pass (whole step)"},
+                        "kernel": kname},
            "tile": {"chosen": list(ss_tile(tune[0])) if tune else None,
-                    "plan": PLAN_NAMES[batch_plan],
+                    "plan": "one pass" if one_pass else PLAN_NAMES[batch_plan],
                     "step_ms_by_plan_and_tile": {PLAN_NAMES[p]: [round(x, 4) for x in row]
                                                  for p, row in enumerate(tune[2])} if tune else None},
            "cpu_baseline": None}

@@ -396,7 +396,8 @@ int ss_get_plan(ss_ctx* ctx);
  * dt = C h as for RK4. Every run of a one-pass integrator (ss_flow_step,
  * ss_minimise) begins with one pass that tests the current field and stores
  * its force. Chiral magnet: phi' is normalised before its force is taken and
- * v' is projected on its tangent plane. Batches always use RK4. Synchronises. */
+ * v' is projected on its tangent plane. Batches: ss_batch_set_integrator.
+ * Synchronises. */
 #define SS_INTEG_RK4 0
 #define SS_INTEG_VV 1
 #define SS_INTEG_GF 2
@@ -470,6 +471,13 @@ int ss_batch_set_tile(ss_batch* batch, int tile);
  * with any other shape the batch runs separate stage passes. */
 int ss_batch_set_plan(ss_batch* batch, int plan);
 int ss_batch_get_plan(ss_batch* batch);
+/* Integrator of the batch's steps (SS_INTEG_*, default SS_INTEG_RK4; Sec. 3.2),
+ * as ss_set_integrator for one context: with velocity Verlet or gradient flow
+ * every step is one batched pass (the plan does not apply), and each run starts
+ * with one pass that tests every member's field and stores its force.
+ * Synchronises. */
+int ss_batch_set_integrator(ss_batch* batch, int integ);
+int ss_batch_get_integrator(ss_batch* batch);
 /* Observables of every member (out: n entries, host), each as ss_observables
  * gives it for one context. All members' observable passes are enqueued on the
  * batch stream before the first read-back, which synchronises. SS_EINVAL if

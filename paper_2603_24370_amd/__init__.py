@@ -83,7 +83,7 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_batch_set_tile", "ss_batch_autotune", "ss_batch_set_plan", "ss_batch_get_plan", "ss_batch_observables", "ss_set_energy_target", "ss_learned_input",
            "ss_learned_targets", "ss_init_learned", "ss_state_bytes", "ss_get_state", "ss_set_state",
            "ss_energy_grad_noalloc", "ss_set_integrator", "ss_get_integrator", "ss_workspace_bytes_for",
-           "ss_set_demag_iters"]
+           "ss_set_demag_iters", "ss_batch_set_integrator", "ss_batch_get_integrator"]
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
                "ssn_adam_step", "ssn_set_grad_clip",
@@ -157,6 +157,8 @@ def lib():
     L.ss_batch_autotune.argtypes = [vp, i, dp]
     L.ss_batch_set_plan.argtypes = [vp, i]
     L.ss_batch_get_plan.argtypes = [vp]
+    L.ss_batch_set_integrator.argtypes = [vp, i]
+    L.ss_batch_get_integrator.argtypes = [vp]
     L.ss_batch_observables.argtypes = [vp, ctypes.POINTER(ss_obs)]
     _lib = L
     return L
@@ -434,6 +436,14 @@ def ss_batch_set_plan(batch, plan: int):
     _check(lib().ss_batch_set_plan(batch, plan))
 
 
+def ss_batch_set_integrator(batch, integ):
+    _check(lib().ss_batch_set_integrator(batch, INTEGRATORS.get(integ, integ)))
+
+
+def ss_batch_get_integrator(batch) -> int:
+    return _check_nonneg(lib().ss_batch_get_integrator(batch))
+
+
 def ss_batch_get_plan(batch) -> int:
     return _check_nonneg(lib().ss_batch_get_plan(batch))
 
@@ -643,6 +653,14 @@ class Batch:
     @property
     def plan(self):
         return ss_batch_get_plan(self.batch)
+
+    def set_integrator(self, integ):
+        """"rk4" (default), "vv" or "gf", as Solver.set_integrator."""
+        ss_batch_set_integrator(self.batch, integ)
+
+    @property
+    def integrator(self):
+        return ss_batch_get_integrator(self.batch)
 
     def close(self):
         if getattr(self, "batch", None) is not None:

@@ -1627,7 +1627,8 @@ int ctx_shape(const ss_ctx* c, int* Nx, int* Ny, int* theory) {
 
 struct ss_batch {
   int theory, dtype, C, n, tile;
-  int plan;  // SS_PLAN_*; the fused pass runs on tiles 0 and 1 only (see batch_fused)
+  int plan;   // SS_PLAN_*; the fused pass runs on tiles 0 and 1 only (see batch_fused)
+  int integ;  // SS_INTEG_*
   hipStream_t stream;
   hipStream_t cap_stream;
   std::vector<ss_ctx*> members;
@@ -1805,7 +1806,7 @@ void batch_launch(const ss_batch* b, hipStream_t s) {
   const int nlaunch = batch_nlaunch(b);
   if (b->theory == SS_THEORY_AH) batch_launch_t<T, 0, PASS>(b->tile, a, nlaunch, s);
   else batch_launch_t<T, 1, PASS>(b->tile, a, nlaunch, s);
-  if constexpr (PASS == kP1 || PASS == kCheck)
+  if constexpr (reduces(PASS))
     hipLaunchKernelGGL((batch_finalise<T, PASS>), dim3(b->n), dim3(256), 0, s, a.inst, (const double*)b->partials);
 }
 
@@ -1841,6 +1842,14 @@ void batch_launch_fused(const ss_batch* b, hipStream_t s) {
 
 template <class T>
 void batch_enqueue_steps(const ss_batch* b, int n, hipStream_t s) {
+  if (b->integ != SS_INTEG_RK4) {
+    // one pass (and the members' finalise) per step
+    for (int k = 0; k < n; ++k) {
+      if (b->integ == SS_INTEG_VV) batch_launch<T, kVV>(b, s);
+      else batch_launch<T, kGF>(b, s);
+    }
+    return;
+  }
   const bool fused = batch_fused<T>(b);
   for (int k = 0; k < n; ++k) {
     batch_launch<T, kP1>(b, s);
@@ -1859,7 +1868,22 @@ void batch_enqueue_steps_any(const ss_batch* b, int n, hipStream_t s) {
   else batch_enqueue_steps<double>(b, n, s);
 }
 
+// First pass of a one-pass run: each member's current field tested and its force stored.
+void batch_enqueue_prime(const ss_batch* b, hipStream_t s) {
+  if (b->integ == SS_INTEG_RK4) return;
+  if (b->dtype == SS_F32) batch_launch<float, kPrime>(b, s);
+  else batch_launch<double, kPrime>(b, s);
+}
+
+void batch_enqueue_apply_arrest(const ss_batch* b, hipStream_t s);
+
+// End of a run: RK4 tests the last field (the check pass); the one-pass
+// integrators have tested it already. Then a pending arrest zeroes the velocity.
 void batch_enqueue_check(const ss_batch* b, hipStream_t s) {
+  if (b->integ != SS_INTEG_RK4) {
+    batch_enqueue_apply_arrest(b, s);
+    return;
+  }
   if (b->dtype == SS_F32) {
     batch_launch<float, kCheck>(b, s);
     hipLaunchKernelGGL((batch_apply_arrest<float>), dim3(b->n), dim3(256), 0, s,
@@ -1930,6 +1954,7 @@ int ss_batch_create(const char* theory, int n, const ss_instance* inst, int dtyp
   b->n = n;
   b->tile = kDefaultTile;
   b->plan = SS_PLAN_FUSED;
+  b->integ = SS_INTEG_RK4;
   b->stream = (hipStream_t)stream;
   b->graph = nullptr;
   b->graph_steps = 0;
@@ -2027,6 +2052,21 @@ int ss_batch_set_plan(ss_batch* b, int plan) {
 
 int ss_batch_get_plan(ss_batch* b) { return b ? b->plan : SS_EINVAL; }
 
+int ss_batch_set_integrator(ss_batch* b, int integ) {
+  if (!b) return fail(SS_EINVAL, "batch is NULL");
+  if (integ != SS_INTEG_RK4 && integ != SS_INTEG_VV && integ != SS_INTEG_GF)
+    return fail(SS_EINVAL, "unknown integrator");
+  SS_HIP(hipStreamSynchronize(b->stream));
+  b->integ = integ;
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  return SS_OK;
+}
+
+int ss_batch_get_integrator(ss_batch* b) { return b ? b->integ : SS_EINVAL; }
+
 int ss_batch_observables(ss_batch* b, ss_obs* out) {
   if (!b || !out) return fail(SS_EINVAL, "batch or out is NULL");
   // Every member's passes go on the batch stream first, so the first read-back
@@ -2049,6 +2089,7 @@ int ss_batch_flow_step(ss_batch* b, int n_steps, ss_step_info* infos) {
   std::vector<int> none(b->n, 0);
   int rc = batch_compact(b, none);
   if (rc) return rc;
+  batch_enqueue_prime(b, b->stream);
   batch_enqueue_steps_any(b, n_steps, b->stream);
   batch_enqueue_check(b, b->stream);
   SS_HIP(hipGetLastError());
@@ -2088,6 +2129,7 @@ int ss_batch_minimise(ss_batch* b, const ss_stop* stop, ss_min_info* infos) {
   }
   hipLaunchKernelGGL(batch_arm, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->st_ptrs, b->n, 1,
                      stop->grad_tol, stop->rel_e_tol, stop->window, (long long)stop->max_steps);
+  batch_enqueue_prime(b, b->stream);
   SS_HIP(hipGetLastError());
   int ndone = 0;
   for (;;) {
@@ -2154,6 +2196,7 @@ int ss_batch_autotune(ss_batch* b, int n_steps, double* ms_out) {
       if (rc) return rc;
       hipLaunchKernelGGL(batch_arm, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->st_ptrs, b->n, 0, 0.0,
                          0.0, 0, 0LL);
+      batch_enqueue_prime(b, b->stream);
       batch_enqueue_steps_any(b, 2, b->stream);
       SS_HIP(hipEventRecord(e0, b->stream));
       batch_enqueue_steps_any(b, n_steps, b->stream);

@@ -1325,12 +1325,16 @@ __device__ __forceinline__ void for_each_item(int nwork, F&& body) {
 }
 
 template <class T, int TH, int PASS, int TX, int TY, int RY>
-__global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
+__global__ void __launch_bounds__(TX*(TY / RY))
+__attribute__((amdgpu_waves_per_eu(StageWaves<T, TH, PASS, RY>::value))) batch_pass(BatchArgs<T> a) {
   constexpr int C = NComp<TH>::value;
   constexpr int LX = TX + 4, LY = TY + 4;
   constexpr int NT = TX * (TY / RY);
-  constexpr bool REDUCE = (PASS == kP1 || PASS == kCheck);
+  constexpr bool REDUCE = reduces(PASS);
+  // stages 2-4 of RK4 run after P1 advanced the member's step counter; the
+  // one-pass integrators read the current field (and velocity Verlet the arrest)
   constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
+  constexpr bool USES_ARREST = STAGED || PASS == kVV;
   __shared__ __align__(16) T lds[C * LY * LX];
   __shared__ double red[3 * (NT / 64)];
   const int tid = threadIdx.y * TX + threadIdx.x;
@@ -1342,7 +1346,7 @@ __global__ void __launch_bounds__(TX*(TY / RY)) batch_pass(BatchArgs<T> a) {
     if (st->done) return;
     const long long step = st->step;
     const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
-    const bool arrest = STAGED ? (st->arrest != 0) : false;
+    const bool arrest = USES_ARREST ? (st->arrest != 0) : false;
     double e_acc = 0.0, g_acc = 0.0;
     int nf = 0;
     for (int k = 0; k < U.n; ++k)

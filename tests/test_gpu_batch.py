@@ -166,3 +166,58 @@ def test_chiral_magnet_batch_matches_oracle_per_member(ss, orc, dtype, plan, til
         assert obs[k]["q_fd"] == pytest.approx(r["Q_fd"], rel=1e-11, abs=1e-12)
         assert obs[k]["q_bl"] == pytest.approx(r["Q_bl"], abs=1e-9)
     B.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("scheme", ["vv", "gf"])
+@pytest.mark.parametrize("tile", [0, 1])
+def test_one_pass_batch_flow_matches_oracle_per_member(ss, orc, dtype, scheme, tile):
+    """Velocity Verlet and gradient flow in batched launches (one pass per step for
+    every member, after one prime pass): each member's trajectory is the oracle's."""
+    insts = _members(20, 5, sides=[40, 71, 96, 33, 64])
+    B = ss.Batch(AH, [(m.Nx, m.Ny, m.h, m.params) for m in insts], dtype=dtype)
+    B.set_integrator(scheme)
+    B.set_tile(tile)
+    assert B.integrator == ss.INTEGRATORS[scheme]
+    fields = []
+    for m, mem in zip(insts, B.members):
+        f = m.field()
+        if dtype == "f32":
+            f = f.astype(np.float32).astype(np.float64)
+        mem.set_field(f)
+        fields.append(f)
+    n = 6
+    infos = B.flow_step(n)
+    rel = 1e-11 if dtype == "f64" else 1e-5
+    for k, (m, mem, f) in enumerate(zip(insts, B.members, fields)):
+        phi_r, v_r, E_r, na = orc.flow(AH, f, np.zeros_like(f), m.h, m.params, n, scheme=scheme)
+        phi, vel = (_np(x) for x in mem.get_field(velocity=True))
+        assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max(), k
+        assert np.abs(vel - v_r).max() <= rel * max(np.abs(phi_r).max(), 1.0), k
+        assert infos[k]["step"] == n and infos[k]["n_arrests"] == na, k
+        if dtype == "f64":
+            assert infos[k]["energy"] == pytest.approx(E_r, rel=1e-12)
+    B.close()
+
+
+def test_velocity_verlet_batch_minimise_stops_each_member_where_the_oracle_does(ss, orc):
+    """FP64 velocity Verlet: every member stops at the oracle's step with its arrest
+    count, across graph replays and work-list compaction."""
+    insts = _members(30, 5, sides=[32, 48, 40, 56, 36])
+    B = ss.Batch(AH, [(m.Nx, m.Ny, m.h, m.params) for m in insts], dtype="f64")
+    B.set_integrator("vv")
+    fields = [m.field() for m in insts]
+    for f, mem in zip(fields, B.members):
+        mem.set_field(f)
+    rc, infos = B.minimise(grad_tol=2e-3, max_steps=3000, graph_steps=8)
+    steps = set()
+    for k, (m, f) in enumerate(zip(insts, fields)):
+        phi_r, v_r, info_r = orc.minimise(AH, f, m.h, m.params, grad_tol=2e-3, max_steps=3000, scheme="vv")
+        assert infos[k]["step"] == info_r["steps"], k
+        assert infos[k]["n_arrests"] == info_r["arrests"], k
+        assert infos[k]["reason"] == {1: "grad", 2: "stall", 0: "max_steps"}[info_r["reason"]]
+        phi = _np(B.members[k].get_field())
+        assert np.abs(phi - phi_r).max() < 1e-9, k
+        steps.add(info_r["steps"])
+    assert len(steps) > 1
+    B.close()
