@@ -49,3 +49,25 @@ def test_cpu_baseline_runs_the_oracle_on_every_usable_core(monkeypatch):
     r = bench.cpu_baseline(FakeSolver(), wl, [1.0], window=32, steps=1)
     assert r["cores"] == min(3, bench.host_cores()) and r["kind"] == "oracle"
     assert r["value"] > 0 and r["value_1core"] > 0 and "32x32" in r["sample"]
+
+
+def test_unet_step_bytes_and_roofline_bound():
+    """The U-Net step model counts (4 C_in + 5 C_out) BF16 values per pixel and conv
+    layer; with one level and base 16 (enc... none, mid.a 2->16, mid.b 16->16 at full
+    resolution) that is 2 * N * H * W * ((4*2 + 5*16) + (4*16 + 5*16)) bytes. The
+    roofline names HBM below the BF16 ridge (312.5 flop/B) and MFMA above it."""
+    import bench
+    wl = dict(levels=1, base=16, cin=2, cout=4, N=2, H=8, W=8)
+    want = 2 * 2 * 8 * 8 * ((4 * 2 + 5 * 16) + (4 * 16 + 5 * 16))
+    assert bench.unet_step_bytes(wl) == want
+    r = bench.unet_roofline(100.0, 1e9, 1e11, 1e-3, 50.0)  # 100 flop/B
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["achieved"] == 1000.0 and r["peak"] == 8000.0
+    r = bench.unet_roofline(100.0, 1e9, 1e12, 1e-3, 50.0)  # 1000 flop/B
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["achieved"] == 100.0
+
+
+def test_other_theory_step_models():
+    import bench
+    assert bench.other_theory_bytes("bs512", {}) == 72
+    assert bench.other_theory_bytes("bec256", {}) == 352
+    assert bench.other_theory_bytes("heusler_demag512", {}, demag_iters=2) == 72 + 48 + 40 + 2 * 312
