@@ -39,7 +39,9 @@ HBM_PEAK_GBS = 8000.0
 #   P234 (fused stages 2-4) reads phi, v, a1, writes phi', v'.
 #   VV (velocity Verlet, one pass) reads phi, v, a, writes phi', v', a';
 #   GF (gradient flow, one pass) reads phi, a, writes phi', a'.
-PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "P234": (3, 2), "VV": (3, 3), "GF": (2, 2)}
+# field sets (C components of one lattice) read and written per launch; velocity
+# Verlet in kick-drift-kick form reads phi and u and writes phi' and u'
+PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "P234": (3, 2), "VV": (2, 2), "GF": (2, 2)}
 STEP_SETS = 17          # separate stage passes
 STEP_SETS_FUSED = 7     # P1 + fused stages 2-4
 PLAN_NAMES = ["stages", "fused"]
@@ -154,19 +156,20 @@ def run_unet(args, wl):
 def other_theory_bytes(name, wl, demag_iters=2, nlev=1):
     """Bytes per interior site and step that the kernels of a step read and write
     (FP32 fields, FP64 solver planes; halo re-reads not counted):
-      heusler_demag512, velocity Verlet: the pass reads phi, v, a and writes phi', v',
-        a' (6 x 3 x 4 B); the solve forms the stage point (reads 3 sets, writes one:
-        48 B), starts conjugate gradients (reads S_1, S_2 and x, writes r, rhs, psi:
-        40 B) and per iteration moves about 312 B on the lattice (V-cycle 144 B, the
-        coarser levels a third of that, the conjugate-gradient kernels 120 B);
+      heusler_demag512, velocity Verlet (kick-drift-kick): the pass reads phi and u and
+        writes phi', u' (4 x 3 x 4 B); the solve forms the stage point (reads 2 sets,
+        writes one: 36 B), starts conjugate gradients (reads S_1, S_2 and x, writes r,
+        rhs, psi: 40 B) and per iteration moves about 312 B on the lattice (V-cycle
+        144 B, the coarser levels a third of that, the conjugate-gradient kernels 120 B);
       bec256, RK4 with the atom-number constraint: stage points 104 B, gradients 64 B,
         forces and updates 152 B, the end-of-step scaling 32 B (two components);
-      bs512, velocity Verlet: 6 x 3 x 4 B."""
+      bs512, velocity Verlet (kick-drift-kick): 4 x 3 x 4 B.
+    The restart pass after an arrest (reads phi, writes u) is not counted."""
     if name == "heusler_demag512":
-        return 72 + 48 + 40 + demag_iters * 312
+        return 48 + 36 + 40 + demag_iters * 312
     if name == "bec256":
         return 352
-    return 72
+    return 48
 
 
 def run_other(args, name, wl):

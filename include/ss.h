@@ -259,9 +259,12 @@ int ss_init_ansatz(ss_ctx* ctx, int kind, int n, const double* xy, const double*
 
 /* Mean device time per launch of each of the passes, measured with HIP events
  * on the context's stream over n_steps flow steps (the steps are real flow
- * steps). ms[0..3] = stage passes P1..P4 (P1 including the one-workgroup launch
- * that finalises its reduction), ms[4] = whole step; under a fused plan ms[1]
- * is the pass of stages 2-4 and ms[2] = ms[3] = 0. Synchronises. */
+ * steps). RK4: ms[0..3] = stage passes P1..P4 (P1 including the one-workgroup
+ * launch that finalises its reduction), ms[4] = whole step; under a fused plan
+ * ms[1] is the pass of stages 2-4 and ms[2] = ms[3] = 0. One-pass integrators:
+ * ms[0] = the step's pass with its finalise, ms[1] = velocity Verlet's restart
+ * pass (the force of an arrested field; a launch that returns at once on the
+ * other steps), ms[2] = ms[3] = 0. Synchronises. */
 int ss_time_passes(ss_ctx* ctx, int n_steps, double* ms);
 
 /* Copy the current field and (if velocity != NULL) the fictitious velocity
@@ -384,20 +387,26 @@ int ss_get_plan(ss_ctx* ctx);
  * explicit scheme, RK4 for example, and contrasted with first-order descent).
  *   SS_INTEG_RK4  classical RK4 on (phi, phidot), launched by the plan above
  *                 (default);
- *   SS_INTEG_VV   velocity Verlet, one pass per step that reads phi, v and the
- *                 stored force a = -G(phi) and writes phi' = phi + dt v + dt^2/2 a,
- *                 its force a' = -G(phi') and v' = v + dt/2 (a + a') (6 field
- *                 sets of HBM traffic per site and step), with E_h(phi') reduced
- *                 in the same pass, so the arrest test of eq. (4) for the next
- *                 step is ready when that step starts;
+ *   SS_INTEG_VV   velocity Verlet, phi' = phi + dt v + dt^2/2 a, a' = -G(phi'),
+ *                 v' = v + dt/2 (a + a'), with E_h(phi') reduced in the pass that
+ *                 forms phi', so the arrest test of eq. (4) for the next step is
+ *                 ready when that step starts. On the lattice theories it runs
+ *                 in kick-drift-kick form: within a run the velocity buffer
+ *                 holds u = v + dt/2 a, and one pass per step reads phi and u
+ *                 and writes phi' = phi + dt u and u' = v' + dt/2 a' (4 field
+ *                 sets of HBM traffic per site and step); a step after an
+ *                 arrest (v = 0) is preceded by a pass that sets u = dt/2 a
+ *                 from the field. The BEC keeps v and a between steps (6 sets);
  *   SS_INTEG_GF   gradient flow phi' = phi + tau a with tau = dt^2/2 (the step
  *                 velocity Verlet takes from rest), one pass reading phi and a,
  *                 writing phi' and a' (4 field sets); no velocity, no arrest.
  * dt = C h as for RK4. Every run of a one-pass integrator (ss_flow_step,
  * ss_minimise) begins with one pass that tests the current field and stores
- * its force. Chiral magnet: phi' is normalised before its force is taken and
- * v' is projected on its tangent plane. Batches: ss_batch_set_integrator.
- * Synchronises. */
+ * its force (velocity Verlet on the lattice theories: forms u) and ends with
+ * the velocity of the last field (v = u - dt/2 a, or 0 after an arrest), so
+ * between runs the velocity buffer holds v. Chiral magnet: phi' is normalised
+ * before its force is taken and v' is projected on its tangent plane.
+ * Batches: ss_batch_set_integrator. Synchronises. */
 #define SS_INTEG_RK4 0
 #define SS_INTEG_VV 1
 #define SS_INTEG_GF 2

@@ -248,7 +248,7 @@ template <class T, int TH, int PASS, int CFG>
 int launch_cfg(const PassArgs<T>& a, int nlaunch, hipStream_t s) {
   constexpr TileCfg tc = kTiles[CFG];
   PassArgs<T> b = a;
-  if constexpr (PASS == kP1 || PASS == kPrime || PASS == kVV || PASS == kGF) {
+  if constexpr (PASS == kP1 || PASS == kPrime || PASS == kVV || PASS == kGF || vv_in_place(PASS)) {
     const long r = resident_groups<T, TH, PASS, tc.TX, tc.TY, tc.RY>();
     if (nlaunch > r) {
       nlaunch = (int)r;
@@ -372,11 +372,15 @@ void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
 // demagnetisation the pass is preceded by the solve for its stage point.
 template <class T, int PASS>
 void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
-  if (c->theory == SS_THEORY_BEC) {
-    bec_pass<T, PASS>(c, a, s);
-    return;
+  if constexpr (!vv_in_place(PASS)) {
+    if (c->theory == SS_THEORY_BEC) {
+      bec_pass<T, PASS>(c, a, s);
+      return;
+    }
   }
-  if (c->dm.on) demag_solve<T, PASS>(c, a, s);
+  // velocity Verlet's restart and end of run evaluate the current field, whose
+  // potential the step that made it has solved for
+  if (c->dm.on && PASS != kVVRestart && PASS != kVVEnd) demag_solve<T, PASS>(c, a, s);
   int groups = c->L.nlaunch;  // workgroups launched = partials written
   if (c->grad_mode == SS_GRAD_EXACT) {
     // exact-gradient passes: one tile shape (64 x 16), the layout of tile 0
@@ -386,6 +390,18 @@ void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
       hipLaunchKernelGGL((stage_pass_exact<T, kCM, PASS>), dim3(groups), dim3(kExTX, kExTY / kExRY), 0, s, a);
     else
       hipLaunchKernelGGL((stage_pass_exact<T, kBS, PASS>), dim3(groups), dim3(kExTX, kExTY / kExRY), 0, s, a);
+  } else if constexpr (vv_in_place(PASS)) {
+    // once per run, or after an arrest: one tile shape (64 x 16) whatever the
+    // context's tile
+    PassArgs<T> b = a;
+    Layout L = c->L;
+    set_tiles(L, c->Nx, c->Ny, 0);
+    b.ntx = L.ntx;
+    b.nty = L.nty;
+    b.seg = L.seg;
+    if (c->theory == SS_THEORY_AH) groups = launch_cfg<T, kAH, PASS, 0>(b, L.nlaunch, s);
+    else if (c->theory == SS_THEORY_CM) groups = launch_cfg<T, kCM, PASS, 0>(b, L.nlaunch, s);
+    else groups = launch_cfg<T, kBS, PASS, 0>(b, L.nlaunch, s);
   } else if (c->theory == SS_THEORY_AH) {
     groups = launch_pass_t<T, kAH, PASS>(c->tile, a, groups, s);
   } else if (c->theory == SS_THEORY_CM) {
@@ -451,14 +467,23 @@ void launch_fused(const ss_ctx* c, hipStream_t s) {
   else launch_fused_t<T, kBS>(lt, a, L.nlaunch, s);
 }
 
+// Velocity Verlet in kick-drift-kick form (the lattice theories; the BEC keeps
+// v and the force a between steps).
+bool vv_kdk(const ss_ctx* c) { return c->integ == SS_INTEG_VV && c->theory != SS_THEORY_BEC; }
+
 template <class T>
 void enqueue_steps(const ss_ctx* c, int n, hipStream_t s) {
   PassArgs<T> a = pass_args<T>(c);
   if (c->integ != SS_INTEG_RK4) {
-    // one pass (and its finalise) per step
+    // one pass (and its finalise) per step; velocity Verlet's restart pass
+    // before it returns at once unless the last step was arrested
     for (int k = 0; k < n; ++k) {
-      if (c->integ == SS_INTEG_VV) launch_pass<T, kVV>(c, a, s);
-      else launch_pass<T, kGF>(c, a, s);
+      if (c->integ == SS_INTEG_GF) {
+        launch_pass<T, kGF>(c, a, s);
+      } else {
+        if (vv_kdk(c)) launch_pass<T, kVVRestart>(c, a, s);
+        launch_pass<T, kVV>(c, a, s);
+      }
     }
     return;
   }
@@ -492,29 +517,42 @@ void enqueue_check_any(const ss_ctx* c, hipStream_t s) {
 }
 
 // Start of a run of a one-pass integrator: the arrest test of the current field
-// (as a check pass) and its force stored in the buffer of the step's parity.
+// (as a check pass) and its force stored in the buffer of the step's parity, or
+// for velocity Verlet in kick-drift-kick form u = v + dt/2 a in place of v.
 void enqueue_prime_any(const ss_ctx* c, hipStream_t s) {
+  if (vv_kdk(c)) {
+    if (c->dtype == SS_F32) launch_pass<float, kVVStart>(c, pass_args<float>(c), s);
+    else launch_pass<double, kVVStart>(c, pass_args<double>(c), s);
+    return;
+  }
   if (c->dtype == SS_F32) launch_pass<float, kPrime>(c, pass_args<float>(c), s);
   else launch_pass<double, kPrime>(c, pass_args<double>(c), s);
 }
-
-// End of a run of steps: the arrest test of the final field where the
-// integrator has not taken it already, then the velocity zeroed if it fired.
-void enqueue_end_of_run_any(const ss_ctx* c, hipStream_t s);
 
 template <class T>
 void enqueue_apply_arrest(const ss_ctx* c, hipStream_t s) {
   hipLaunchKernelGGL((apply_arrest<T>), dim3(1024), dim3(256), 0, s, bufs_of<T>(c), c->st, c->C);
 }
 
-void enqueue_end_of_run_any(const ss_ctx* c, hipStream_t s) {
-  if (c->integ == SS_INTEG_RK4) {
-    enqueue_check_any(c, s);
+// End of a run of a one-pass integrator: the velocity of the current field,
+// zero if the last test arrested the flow (kick-drift-kick velocity Verlet
+// turns u back into v).
+void enqueue_settle_any(const ss_ctx* c, hipStream_t s) {
+  if (vv_kdk(c)) {
+    if (c->dtype == SS_F32) launch_pass<float, kVVEnd>(c, pass_args<float>(c), s);
+    else launch_pass<double, kVVEnd>(c, pass_args<double>(c), s);
   } else if (c->dtype == SS_F32) {
     enqueue_apply_arrest<float>(c, s);
   } else {
     enqueue_apply_arrest<double>(c, s);
   }
+}
+
+// End of a run of steps: the arrest test of the final field where the
+// integrator has not taken it already, then the velocity zeroed if it fired.
+void enqueue_end_of_run_any(const ss_ctx* c, hipStream_t s) {
+  if (c->integ == SS_INTEG_RK4) enqueue_check_any(c, s);
+  else enqueue_settle_any(c, s);
 }
 
 int read_status(ss_ctx* c, DevStatus* out) {
@@ -898,9 +936,22 @@ int ss_time_passes(ss_ctx* c, int n_steps, double* ms) {
   for (int s = 0; s < n_steps; ++s) {
     SS_HIP(hipEventRecord(ev[0], c->stream));
     if (c->integ != SS_INTEG_RK4) {
-      // one pass per step: its time (with its finalise) in ms[0]
-      enqueue_steps_any(c, 1, c->stream);
-      for (int k = 1; k < 5; ++k) SS_HIP(hipEventRecord(ev[k], c->stream));
+      // one pass per step: its time (with its finalise) in ms[0]; velocity
+      // Verlet's restart pass (timed as launched, also where it returns at
+      // once) in ms[1]
+      if (vv_kdk(c)) {
+        if (c->dtype == SS_F32) launch_pass<float, kVVRestart>(c, pass_args<float>(c), c->stream);
+        else launch_pass<double, kVVRestart>(c, pass_args<double>(c), c->stream);
+      }
+      SS_HIP(hipEventRecord(ev[1], c->stream));
+      if (c->dtype == SS_F32) {
+        if (c->integ == SS_INTEG_GF) launch_pass<float, kGF>(c, pass_args<float>(c), c->stream);
+        else launch_pass<float, kVV>(c, pass_args<float>(c), c->stream);
+      } else {
+        if (c->integ == SS_INTEG_GF) launch_pass<double, kGF>(c, pass_args<double>(c), c->stream);
+        else launch_pass<double, kVV>(c, pass_args<double>(c), c->stream);
+      }
+      for (int k = 2; k < 5; ++k) SS_HIP(hipEventRecord(ev[k], c->stream));
     } else if (c->plan != SS_PLAN_STAGES) {
       // stages 2-4 in one pass: its time in ms[1], zero in ms[2] and ms[3]
       if (c->dtype == SS_F32) {
@@ -932,7 +983,9 @@ int ss_time_passes(ss_ctx* c, int n_steps, double* ms) {
     for (int k = 0; k < 4; ++k) {
       float t = 0.f;
       SS_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
-      acc[k] += t;
+      // one-pass: the step's pass runs between events 1 and 2, the restart before
+      const int slot = c->integ == SS_INTEG_RK4 ? k : k == 0 ? 1 : k == 1 ? 0 : k;
+      acc[slot] += t;
     }
     float t = 0.f;
     SS_HIP(hipEventElapsedTime(&t, ev[0], ev[4]));
@@ -1237,8 +1290,12 @@ int ss_minimise(ss_ctx* c, const ss_stop* stop, ss_min_info* info) {
     if (rc) return rc;
     if (d.done) break;
   }
-  if (c->dtype == SS_F32) enqueue_apply_arrest<float>(c, c->stream);
-  else enqueue_apply_arrest<double>(c, c->stream);
+  if (c->integ == SS_INTEG_RK4) {
+    if (c->dtype == SS_F32) enqueue_apply_arrest<float>(c, c->stream);
+    else enqueue_apply_arrest<double>(c, c->stream);
+  } else {
+    enqueue_settle_any(c, c->stream);
+  }
   int rc = read_status(c, &d);
   if (rc) return rc;
   if (info) {
@@ -1843,10 +1900,15 @@ void batch_launch_fused(const ss_batch* b, hipStream_t s) {
 template <class T>
 void batch_enqueue_steps(const ss_batch* b, int n, hipStream_t s) {
   if (b->integ != SS_INTEG_RK4) {
-    // one pass (and the members' finalise) per step
+    // one pass (and the members' finalise) per step; velocity Verlet (in
+    // kick-drift-kick form, as for one lattice) restarts the arrested members first
     for (int k = 0; k < n; ++k) {
-      if (b->integ == SS_INTEG_VV) batch_launch<T, kVV>(b, s);
-      else batch_launch<T, kGF>(b, s);
+      if (b->integ == SS_INTEG_VV) {
+        batch_launch<T, kVVRestart>(b, s);
+        batch_launch<T, kVV>(b, s);
+      } else {
+        batch_launch<T, kGF>(b, s);
+      }
     }
     return;
   }
@@ -1868,20 +1930,39 @@ void batch_enqueue_steps_any(const ss_batch* b, int n, hipStream_t s) {
   else batch_enqueue_steps<double>(b, n, s);
 }
 
-// First pass of a one-pass run: each member's current field tested and its force stored.
+// First pass of a one-pass run: each member's current field tested and its
+// force stored (velocity Verlet: u formed).
 void batch_enqueue_prime(const ss_batch* b, hipStream_t s) {
   if (b->integ == SS_INTEG_RK4) return;
+  if (b->integ == SS_INTEG_VV) {
+    if (b->dtype == SS_F32) batch_launch<float, kVVStart>(b, s);
+    else batch_launch<double, kVVStart>(b, s);
+    return;
+  }
   if (b->dtype == SS_F32) batch_launch<float, kPrime>(b, s);
   else batch_launch<double, kPrime>(b, s);
 }
 
 void batch_enqueue_apply_arrest(const ss_batch* b, hipStream_t s);
 
+// End of a one-pass run: each member's velocity (velocity Verlet turns u back
+// into v, or 0 after an arrest; gradient flow has none). The work list must
+// hold every member's units.
+void batch_enqueue_settle(const ss_batch* b, hipStream_t s) {
+  if (b->integ != SS_INTEG_VV) {
+    batch_enqueue_apply_arrest(b, s);
+  } else if (b->dtype == SS_F32) {
+    batch_launch<float, kVVEnd>(b, s);
+  } else {
+    batch_launch<double, kVVEnd>(b, s);
+  }
+}
+
 // End of a run: RK4 tests the last field (the check pass); the one-pass
 // integrators have tested it already. Then a pending arrest zeroes the velocity.
 void batch_enqueue_check(const ss_batch* b, hipStream_t s) {
   if (b->integ != SS_INTEG_RK4) {
-    batch_enqueue_apply_arrest(b, s);
+    batch_enqueue_settle(b, s);
     return;
   }
   if (b->dtype == SS_F32) {
@@ -2146,9 +2227,10 @@ int ss_batch_minimise(ss_batch* b, const ss_stop* stop, ss_min_info* infos) {
       ndone = nd;
     }
   }
-  batch_enqueue_apply_arrest(b, b->stream);
   rc = batch_compact(b, std::vector<int>(b->n, 0));
   if (rc) return rc;
+  if (b->integ == SS_INTEG_RK4) batch_enqueue_apply_arrest(b, b->stream);
+  else batch_enqueue_settle(b, b->stream);
   int worst = SS_OK;
   for (int i = 0; i < b->n; ++i) {
     DevStatus d;
@@ -2201,6 +2283,7 @@ int ss_batch_autotune(ss_batch* b, int n_steps, double* ms_out) {
       SS_HIP(hipEventRecord(e0, b->stream));
       batch_enqueue_steps_any(b, n_steps, b->stream);
       SS_HIP(hipEventRecord(e1, b->stream));
+      if (b->integ != SS_INTEG_RK4) batch_enqueue_settle(b, b->stream);
       SS_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       SS_HIP(hipEventElapsedTime(&ms, e0, e1));

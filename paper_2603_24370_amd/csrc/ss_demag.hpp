@@ -400,21 +400,16 @@ __global__ void __launch_bounds__(256) dm_stage_point(Bufs<T> B, Coeffs cf, cons
                                                       const T* __restrict__ src, T* __restrict__ out) {
   if (PASS != kEval && st->done) return;
   constexpr bool ONEPASS = advances_first(PASS);
-  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4 || ONEPASS);
-  constexpr bool WITH_V = STAGED && PASS != kGF;
-  constexpr bool WITH_A = (PASS == kP3 || PASS == kP4 || ONEPASS);
+  constexpr bool STAGED = staged(PASS);
+  constexpr bool WITH_V = stage_reads_v(PASS);
+  constexpr bool WITH_A = stage_reads_a(PASS);
   constexpr bool AFTER_P1 = (PASS == kP2 || PASS == kP3 || PASS == kP4);
-  constexpr bool USES_ARREST = AFTER_P1 || PASS == kVV;
   const long long step = st->step;
   const int cur = AFTER_P1 ? int((step - 1) & 1) : int(step & 1);
-  const bool arrest = USES_ARREST ? (st->arrest != 0) : false;
+  const bool arrest = uses_arrest(PASS) ? (st->arrest != 0) : false;
   const T dt = (T)cf.dt;
-  T cv = T(0), ca = T(0);
-  if (PASS == kP2) cv = T(0.5) * dt;
-  if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
-  if (PASS == kP4 || PASS == kVV) { cv = dt; ca = T(0.5) * dt * dt; }
-  if (PASS == kGF) ca = T(0.5) * dt * dt;
-  if (arrest) cv = T(0);
+  T cv, ca;
+  stage_coeffs<T, PASS>(dt, arrest, cv, ca);
   const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : (cur ? B.phi[1] : B.phi[0]);
   const T* __restrict__ vv = cur ? B.vel[1] : B.vel[0];
   const T* __restrict__ aa = ONEPASS ? (cur ? B.a2 : B.a1) : (PASS == kP3) ? B.a1 : B.a2;

@@ -103,7 +103,7 @@ __device__ __forceinline__ void for_each_tile(int ntx, int nty, int seg, F&& bod
   for (int u = xcd * per + q; u < uend; u += m) {
     const int sg = u / ntx, tx = u - sg * ntx;
     const int ty1 = min(nty, (sg + 1) * seg);
-    for (int ty = sg * seg; ty < ty1; ++ty) body(tx, ty);
+    for (int ty = sg * seg; ty < ty1; ++ty) body(tx, ty, ty - sg * seg);
   }
 }
 
@@ -176,34 +176,74 @@ __device__ __forceinline__ InstView<T> view_of(const Bufs<T>& B, const Coeffs& c
 // a' = -G(phi') and, for velocity Verlet, v' = v + dt/2 (a + a'), with v = 0
 // after an arrest and, for the chiral magnet, v' projected on the tangent plane
 // at phi'. a is the current field's force, read by the pass.
+// Epilogue of a one-pass step at one site: S is the new field, G = G(S), u the
+// half-step velocity read by the step (velocity Verlet). Velocity Verlet writes
+// the new field and u' = v' - dt/2 G with v' = u - dt/2 G (tangent to S for
+// unit fields); gradient flow writes the new field and its force -G.
 template <class T, int TH, int PASS>
-__device__ __forceinline__ void one_pass_epilogue(bool arrest, T dt, const T (&v)[4], const T (&a)[4],
-                                                  const T (&S)[4], const T (&G)[4], T* __restrict__ phn,
-                                                  T* __restrict__ vn, T* __restrict__ an, long plane, long off) {
+__device__ __forceinline__ void one_pass_epilogue(T dt, const T (&u)[4], const T (&S)[4], const T (&G)[4],
+                                                  T* __restrict__ phn, T* __restrict__ vn, T* __restrict__ an,
+                                                  long plane, long off) {
   constexpr int C = NComp<TH>::value;
   if (PASS == kVV) {
+    const T hd = T(0.5) * dt;
     T vnew[4];
 #pragma unroll
-    for (int c = 0; c < C; ++c) vnew[c] = (arrest ? T(0) : v[c]) + (T(0.5) * dt) * (a[c] - G[c]);
+    for (int c = 0; c < C; ++c) vnew[c] = u[c] - hd * G[c];
     if (unit_field(TH)) {
       const T vd = vnew[0] * S[0] + vnew[1] * S[1] + vnew[2] * S[2];
 #pragma unroll
       for (int c = 0; c < 3; ++c) vnew[c] -= vd * S[c];
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) __builtin_nontemporal_store(vnew[c], &vn[c * plane + off]);
-  }
+    for (int c = 0; c < C; ++c) {
+      __builtin_nontemporal_store(S[c], &phn[c * plane + off]);
+      __builtin_nontemporal_store(vnew[c] - hd * G[c], &vn[c * plane + off]);
+    }
+  } else {
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    __builtin_nontemporal_store(S[c], &phn[c * plane + off]);
-    __builtin_nontemporal_store(-G[c], &an[c * plane + off]);
+    for (int c = 0; c < C; ++c) {
+      __builtin_nontemporal_store(S[c], &phn[c * plane + off]);
+      __builtin_nontemporal_store(-G[c], &an[c * plane + off]);
+    }
   }
 }
 
-template <int TH, int TX, int TY>
+// Epilogue of the velocity Verlet passes around the steps at one site of the
+// current field, whose velocity buffer vc is updated in place (G = G(phi)):
+// start u = v - dt/2 G, restart u = -dt/2 G, end v = u + dt/2 G (0 after an
+// arrest).
+template <class T, int TH, int PASS>
+__device__ __forceinline__ void vv_in_place_epilogue(T dt, bool arrest, const T (&G)[4], T* __restrict__ vc,
+                                                     long plane, long off) {
+  constexpr int C = NComp<TH>::value;
+  const T hd = T(0.5) * dt;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const long k = c * plane + off;
+    T x;
+    if (PASS == kVVStart) x = vc[k] - hd * G[c];
+    else if (PASS == kVVRestart) x = -hd * G[c];
+    else x = arrest ? T(0) : vc[k] + hd * G[c];
+    vc[k] = x;
+  }
+}
+
+// LDS of one tile of a stage pass, in elements of T: the stage point on the
+// tile and its halo of 2 (C planes of LY x LX). The one-pass integrators walk
+// a unit's tiles downwards and carry the overlap from one tile to the next: the
+// last four stage rows (C x 4 x LX), and for velocity Verlet the partial
+// update v0 + (dt/2) a of the two bottom halo rows, which are the next tile's
+// first own rows (2 parities x 2 rows x C x TX).
+template <class T, int TH, int PASS, int TX, int TY>
 struct TileLds {
   static constexpr int C = NComp<TH>::value;
   static constexpr int LX = TX + 4, LY = TY + 4;
+  static constexpr bool CARRY = (PASS == kVV || PASS == kGF);
+  static constexpr int STAGE = C * LY * LX;
+  static constexpr int ROWS = CARRY ? C * 4 * LX : 0;
+  static constexpr int RAW = (PASS == kVV) ? 2 * 2 * C * TX : 0;
+  static constexpr int size = STAGE + ROWS + RAW;
 };
 
 // One tile of one pass. Thread (tx, ty) owns column tx and rows ty*RY ..
@@ -212,19 +252,28 @@ struct TileLds {
 // point to LDS; the halo ring of the tile is loaded cooperatively. Reduction
 // contributions (energy, max |G|, non-finite count) are added to the caller's
 // accumulators. Ends with a barrier (LDS is reused by the next tile).
+// k is the tile's place in its workgroup's walk down a unit (0 = the unit's top
+// tile). For the one-pass integrators a tile with k > 0 takes the four stage
+// rows it shares with the tile above, and the raw inputs of its first two own
+// rows, from LDS (see TileLds) instead of reading them again: the values are
+// the ones stage_at formed for the tile above, so the result is bitwise the
+// same, and each array is read about once plus its x halo.
 template <class T, int TH, int PASS, int TX, int TY, int RY>
 __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool arrest, const T* __restrict__ src,
-                                          T* __restrict__ out, long out_pitch, long out_plane, int x0, int y0,
+                                          T* __restrict__ out, long out_pitch, long out_plane, int x0, int y0, int k,
                                           T* __restrict__ lds, double& e_acc, double& g_acc, int& nf) {
   constexpr int C = NComp<TH>::value;
   constexpr int LX = TX + 4, LY = TY + 4;
   constexpr int NT = TX * (TY / RY);
   constexpr int NRING = 4 * LX + 4 * TY;
+  typedef TileLds<T, TH, PASS, TX, TY> TL;
+  constexpr bool CARRY = TL::CARRY;
+  static_assert(TY >= 4, "a carried tile takes four rows from the one above");
   constexpr bool REDUCE = reduces(PASS);
   constexpr bool ONEPASS = advances_first(PASS);  // the stage point is the new field
-  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4 || ONEPASS);
-  constexpr bool WITH_V = STAGED && PASS != kGF;
-  constexpr bool WITH_A = (PASS == kP3 || PASS == kP4 || ONEPASS);
+  constexpr bool STAGED = staged(PASS);
+  constexpr bool WITH_V = stage_reads_v(PASS);
+  constexpr bool WITH_A = stage_reads_a(PASS);
   T* s[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) s[c] = lds + c * (LY * LX);
@@ -235,24 +284,23 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
   // (that would place V in private scratch memory)
   const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : (cur ? V.phi[1] : V.phi[0]);
   const T* __restrict__ vv = cur ? V.vel[1] : V.vel[0];
-  // force buffers: RK4 stages read a1 (P3) or a2 (P4); the one-pass integrators
-  // read the current field's force from the buffer of the step's parity and
-  // write the new field's force to the other one
+  // force buffers: RK4 stages read a1 (P3) or a2 (P4); gradient flow reads the
+  // current field's force from the buffer of the step's parity and writes the
+  // new field's force to the other one
   const T* __restrict__ aa = ONEPASS ? (cur ? V.a2 : V.a1) : (PASS == kP3) ? V.a1 : V.a2;
   T* __restrict__ a_store = (PASS == kP1) ? V.a1 : (PASS == kPrime) ? (cur ? V.a2 : V.a1) : (cur ? V.a1 : V.a2);
   const T dt = (T)V.dt;
-  T cv = T(0), ca = T(0);
-  if (PASS == kP2) cv = T(0.5) * dt;
-  if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
-  if (PASS == kP4 || PASS == kVV) { cv = dt; ca = T(0.5) * dt * dt; }
-  if (PASS == kGF) ca = T(0.5) * dt * dt;
-  if (arrest) cv = T(0);
+  T cv, ca;
+  stage_coeffs<T, PASS>(dt, arrest, cv, ca);
   const double h = V.h;
   const T c1 = T(1.0 / (12.0 * h)), c2 = T(1.0 / (12.0 * h * h));
   const double d1 = 1.0 / (12.0 * h);
   const int tid = threadIdx.y * TX + threadIdx.x;
   const int lx = threadIdx.x + 2;
-  const int ly0 = threadIdx.y * RY + 2;
+  // a 64-wide tile row is one wavefront, so the row index is wave-uniform and
+  // can live in a scalar register
+  const int wy = (TX == 64) ? __builtin_amdgcn_readfirstlane((int)threadIdx.y) : (int)threadIdx.y;
+  const int ly0 = wy * RY + 2;
   const int gi = x0 + threadIdx.x;
 
   // stage point of padded element (gi, gj) (interior coordinates), and its raw inputs
@@ -286,19 +334,57 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
     }
   };
 
+  // ---- carried rows: stage rows 0-3 from the tile above
+  T* __restrict__ cs = lds + TL::STAGE;  // C x 4 x LX
+  T* __restrict__ cr = cs + TL::ROWS;    // [parity][row][C][TX]
+  const bool carried = CARRY && k > 0;
+  const int par = k & 1;
+  if (carried) {
+    for (int idx = tid; idx < C * 4 * LX; idx += NT) {
+      const int c = idx / (4 * LX);
+      s[c][idx - c * 4 * LX] = cs[idx];
+    }
+  }
+
   // ---- own sites: raw inputs kept in registers, stage point to LDS (and, for
   // the one-pass integrators, in registers: it is the new field that is stored)
   T rp[RY][4], rv[RY][4], ra[RY][4], so[RY][4];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    stage_at(gi, y0 + ly0 - 2 + r, rp[r], rv[r], ra[r], so[r]);
+    const int ly = ly0 + r;
+    if (carried && ly < 4) {
+      const T* __restrict__ q = cr + ((par ^ 1) * 2 + (ly - 2)) * C * TX + threadIdx.x;
 #pragma unroll
-    for (int c = 0; c < C; ++c) s[c][(ly0 + r) * LX + lx] = so[r][c];
+      for (int c = 0; c < 4; ++c) {
+        rp[r][c] = rv[r][c] = ra[r][c] = so[r][c] = T(0);
+        if (c < C) {
+          so[r][c] = cs[(c * 4 + ly) * LX + lx];
+          if (PASS == kVV) rv[r][c] = q[c * TX];
+        }
+      }
+    } else {
+      stage_at(gi, y0 + ly - 2, rp[r], rv[r], ra[r], so[r]);
+#pragma unroll
+      for (int c = 0; c < C; ++c) s[c][ly * LX + lx] = so[r][c];
+    }
   }
-  // ---- halo ring of the tile
-  for (int idx = tid; idx < NRING; idx += NT) {
+  // ---- halo ring of the tile: all of it, or for a carried tile the x halo of
+  // rows 4 .. TY+1 and the two bottom rows
+  const int nring = carried ? 2 * LX + 4 * (TY - 2) : NRING;
+  for (int idx = tid; idx < nring; idx += NT) {
     int ly, lxr;
-    if (idx < 4 * LX) {
+    if (carried) {
+      if (idx < 2 * LX) {
+        const int rr = idx / LX;
+        ly = LY - 2 + rr;
+        lxr = idx - rr * LX;
+      } else {
+        const int j = idx - 2 * LX;
+        ly = 4 + (j >> 2);
+        const int cc = j & 3;
+        lxr = cc < 2 ? cc : LX - 4 + cc;
+      }
+    } else if (idx < 4 * LX) {
       const int rr = idx / LX;
       ly = rr < 2 ? rr : LY - 4 + rr;
       lxr = idx - rr * LX;
@@ -312,8 +398,22 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
     stage_at(x0 - 2 + lxr, y0 - 2 + ly, d0, d1v, d2, S);
 #pragma unroll
     for (int c = 0; c < C; ++c) s[c][ly * LX + lxr] = S[c];
+    if (PASS == kVV && ly >= LY - 2 && lxr >= 2 && lxr < LX - 2) {
+      // the next tile's first own rows: keep their u
+      T* __restrict__ q = cr + (par * 2 + (ly - (LY - 2))) * C * TX + (lxr - 2);
+#pragma unroll
+      for (int c = 0; c < C; ++c) q[c * TX] = d1v[c];
+    }
   }
   __syncthreads();
+  if (CARRY) {
+    // stage rows TY .. TY+3 are the next tile's rows 0-3; saved before any
+    // in-place change of the stage point below
+    for (int idx = tid; idx < C * 4 * LX; idx += NT) {
+      const int c = idx / (4 * LX);
+      cs[idx] = s[c][(LY - 4) * LX + idx - c * 4 * LX];
+    }
+  }
 
   // E_h density in FP64 from the stored (unnormalised) values in LDS, own sites
   auto energy_density = [&]() {
@@ -385,6 +485,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
   // that L2 keeps the staged arrays whose halo rows neighbouring tiles re-read.
   T* __restrict__ phn = cur ? V.phi[0] : V.phi[1];
   T* __restrict__ vn = cur ? V.vel[0] : V.vel[1];
+  T* vcur = cur ? V.vel[1] : V.vel[0];  // the velocity Verlet passes around the steps
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int gj = y0 + ly0 - 2 + r;
@@ -418,7 +519,9 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
 #pragma unroll
       for (int c = 0; c < C; ++c) __builtin_nontemporal_store(-G[c], &a_store[c * plane + off]);
     } else if (ONEPASS) {
-      one_pass_epilogue<T, TH, PASS>(arrest, dt, rv[r], ra[r], so[r], G, phn, vn, a_store, plane, off);
+      one_pass_epilogue<T, TH, PASS>(dt, rv[r], so[r], G, phn, vn, a_store, plane, off);
+    } else if (vv_in_place(PASS)) {
+      vv_in_place_epilogue<T, TH, PASS>(dt, arrest, G, vcur, plane, off);
     } else if (PASS == kEval) {
       if (out != nullptr) {
         const long o = (long)(gj + 2) * out_pitch + (gi + 2);
@@ -534,9 +637,9 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   constexpr int KX = (NXF + NT - 1) / NT, KY = (NYF + NT - 1) / NT;
   constexpr bool REDUCE = reduces(PASS);
   constexpr bool ONEPASS = advances_first(PASS);  // the stage point is the new field
-  constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4 || ONEPASS);
-  constexpr bool WITH_V = STAGED && PASS != kGF;
-  constexpr bool WITH_A = (PASS == kP3 || PASS == kP4 || ONEPASS);
+  constexpr bool STAGED = staged(PASS);
+  constexpr bool WITH_V = stage_reads_v(PASS);
+  constexpr bool WITH_A = stage_reads_a(PASS);
   T* s[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) s[c] = lds + (c < C ? c : 0) * (LY * LX);
@@ -547,18 +650,14 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   const long pitch = V.pitch, plane = V.plane;
   const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : (cur ? V.phi[1] : V.phi[0]);
   const T* __restrict__ vv = cur ? V.vel[1] : V.vel[0];
-  // force buffers: RK4 stages read a1 (P3) or a2 (P4); the one-pass integrators
-  // read the current field's force from the buffer of the step's parity and
-  // write the new field's force to the other one
+  // force buffers: RK4 stages read a1 (P3) or a2 (P4); gradient flow reads the
+  // current field's force from the buffer of the step's parity and writes the
+  // new field's force to the other one
   const T* __restrict__ aa = ONEPASS ? (cur ? V.a2 : V.a1) : (PASS == kP3) ? V.a1 : V.a2;
   T* __restrict__ a_store = (PASS == kP1) ? V.a1 : (PASS == kPrime) ? (cur ? V.a2 : V.a1) : (cur ? V.a1 : V.a2);
   const T dt = (T)V.dt;
-  T cv = T(0), ca = T(0);
-  if (PASS == kP2) cv = T(0.5) * dt;
-  if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
-  if (PASS == kP4 || PASS == kVV) { cv = dt; ca = T(0.5) * dt * dt; }
-  if (PASS == kGF) ca = T(0.5) * dt * dt;
-  if (arrest) cv = T(0);
+  T cv, ca;
+  stage_coeffs<T, PASS>(dt, arrest, cv, ca);
   const double h = V.h;
   const T c1 = T(1.0 / (12.0 * h));
   const double d1 = 1.0 / (12.0 * h);
@@ -734,6 +833,7 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   // ---- G = de/dphi - D_x F_x - D_y F_y, then the pass epilogue
   T* __restrict__ phn = cur ? V.phi[0] : V.phi[1];
   T* __restrict__ vn = cur ? V.vel[0] : V.vel[1];
+  T* vcur = cur ? V.vel[1] : V.vel[0];  // the velocity Verlet passes around the steps
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int tr = threadIdx.y * RY + r;
@@ -773,7 +873,9 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
 #pragma unroll
       for (int c = 0; c < C; ++c) __builtin_nontemporal_store(-G[c], &a_store[c * plane + off]);
     } else if (ONEPASS) {
-      one_pass_epilogue<T, TH, PASS>(arrest, dt, rv[r], ra[r], so[r], G, phn, vn, a_store, plane, off);
+      one_pass_epilogue<T, TH, PASS>(dt, rv[r], so[r], G, phn, vn, a_store, plane, off);
+    } else if (vv_in_place(PASS)) {
+      vv_in_place_epilogue<T, TH, PASS>(dt, arrest, G, vcur, plane, off);
     } else if (PASS == kEval) {
       if (out != nullptr) {
         const long o = (long)(gj + 2) * out_pitch + (gi + 2);
@@ -880,21 +982,24 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<T, TH, PASS, RY>::value))) stage_p
   // stages 2-4 of RK4 run after P1 advanced the step counter; the one-pass
   // integrators read the current field and advance it in their finalise
   constexpr bool AFTER_P1 = (PASS == kP2 || PASS == kP3 || PASS == kP4);
-  constexpr bool USES_ARREST = AFTER_P1 || PASS == kVV;
-  __shared__ __align__(16) T lds[C * LY * LX];
+  __shared__ __align__(16) T lds[TileLds<T, TH, PASS, TX, TY>::size];
   __shared__ double red[3 * (NT / 64)];
 
   DevStatus* __restrict__ st = a.st;
-  if (PASS != kEval && st->done) return;
+  // a finished flow skips its remaining passes; velocity Verlet's end of run
+  // converts the velocity whatever the status, and its restart runs only after
+  // an arrest
+  if (PASS != kEval && PASS != kVVEnd && st->done) return;
+  if (PASS == kVVRestart && !st->arrest) return;
   const long long step = st->step;
   const int cur = AFTER_P1 ? int((step - 1) & 1) : int(step & 1);
-  const bool arrest = USES_ARREST ? (st->arrest != 0) : false;
+  const bool arrest = uses_arrest(PASS) ? (st->arrest != 0) : false;
   const InstView<T> V = view_of<T>(a.B, a.cf);
 
   double e_acc = 0.0, g_acc = 0.0;
   int nf = 0;
-  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty) {
-    tile_body<T, TH, PASS, TX, TY, RY>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane, tx * TX, ty * TY,
+  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty, int k) {
+    tile_body<T, TH, PASS, TX, TY, RY>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane, tx * TX, ty * TY, k,
                                        lds, e_acc, g_acc, nf);
   });
   if (!REDUCE) return;
@@ -1241,7 +1346,7 @@ stage_pass_fused(PassArgs<T> a) {
   const int cur = int((st->step - 1) & 1);
   const bool arrest = st->arrest != 0;
   const InstView<T> V = view_of<T>(a.B, a.cf);
-  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty) {
+  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty, int) {
     tile_body_fused<T, TH, TX, TY, RY>(V, cur, arrest, tx * TX, ty * TY, lds);
   });
 }
@@ -1256,19 +1361,19 @@ __global__ void __launch_bounds__(256) stage_pass_exact(PassArgs<T> a) {
   constexpr int NT = 256;
   constexpr bool REDUCE = reduces(PASS);
   constexpr bool AFTER_P1 = (PASS == kP2 || PASS == kP3 || PASS == kP4);
-  constexpr bool USES_ARREST = AFTER_P1 || PASS == kVV;
   __shared__ __align__(16) T lds[NLDS];
   __shared__ double red[3 * (NT / 64)];
 
   DevStatus* __restrict__ st = a.st;
-  if (PASS != kEval && st->done) return;
+  if (PASS != kEval && PASS != kVVEnd && st->done) return;
+  if (PASS == kVVRestart && !st->arrest) return;
   const long long step = st->step;
   const int cur = AFTER_P1 ? int((step - 1) & 1) : int(step & 1);
-  const bool arrest = USES_ARREST ? (st->arrest != 0) : false;
+  const bool arrest = uses_arrest(PASS) ? (st->arrest != 0) : false;
   const InstView<T> V = view_of<T>(a.B, a.cf);
   double e_acc = 0.0, g_acc = 0.0;
   int nf = 0;
-  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty) {
+  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty, int) {
     tile_body_exact<T, TH, PASS>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane, tx * kExTX, ty * kExTY,
                                  lds, e_acc, g_acc, nf);
   });
@@ -1332,10 +1437,9 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<T, TH, PASS, RY>::value))) batch_p
   constexpr int NT = TX * (TY / RY);
   constexpr bool REDUCE = reduces(PASS);
   // stages 2-4 of RK4 run after P1 advanced the member's step counter; the
-  // one-pass integrators read the current field (and velocity Verlet the arrest)
+  // one-pass integrators read the current field
   constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
-  constexpr bool USES_ARREST = STAGED || PASS == kVV;
-  __shared__ __align__(16) T lds[C * LY * LX];
+  __shared__ __align__(16) T lds[TileLds<T, TH, PASS, TX, TY>::size];
   __shared__ double red[3 * (NT / 64)];
   const int tid = threadIdx.y * TX + threadIdx.x;
   for_each_item(*a.nwork, [&](int w) {
@@ -1343,15 +1447,16 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<T, TH, PASS, RY>::value))) batch_p
     const BatchUnit U = a.units[u];
     const BatchInst<T>& I = a.inst[U.inst];
     DevStatus* __restrict__ st = I.st;
-    if (st->done) return;
+    if (PASS != kVVEnd && st->done) return;
+    if (PASS == kVVRestart && !st->arrest) return;
     const long long step = st->step;
     const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
-    const bool arrest = USES_ARREST ? (st->arrest != 0) : false;
+    const bool arrest = uses_arrest(PASS) ? (st->arrest != 0) : false;
     double e_acc = 0.0, g_acc = 0.0;
     int nf = 0;
     for (int k = 0; k < U.n; ++k)
-      tile_body<T, TH, PASS, TX, TY, RY>(I.V, cur, arrest, nullptr, nullptr, 0, 0, U.tx * TX, (U.ty0 + k) * TY, lds,
-                                         e_acc, g_acc, nf);
+      tile_body<T, TH, PASS, TX, TY, RY>(I.V, cur, arrest, nullptr, nullptr, 0, 0, U.tx * TX, (U.ty0 + k) * TY, k,
+                                         lds, e_acc, g_acc, nf);
     if (!REDUCE) return;
     block_reduce3<NT>(e_acc, g_acc, nf, red);
     if (tid == 0) {

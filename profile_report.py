@@ -40,9 +40,9 @@ SITES = 4096 * 4096
 C, ELEM = 4, 4  # field components, bytes per FP32 element
 DEFAULT_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
-# field sets read and written per site by each pass (stage passes P1..P4 and
-# the fused pass of stages 2-4)
-ALG_SETS = {"P1": (1, 1), "P234": (3, 2), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "VV": (3, 3), "GF": (2, 2)}
+# field sets read and written per site by each pass (stage passes P1..P4, the
+# fused pass of stages 2-4, velocity Verlet in kick-drift-kick form, gradient flow)
+ALG_SETS = {"P1": (1, 1), "P234": (3, 2), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "VV": (2, 2), "GF": (2, 2)}
 PASS_INDEX = {"P1": 0, "P2": 1, "P3": 2, "P4": 3, "VV": 7, "GF": 8}  # the kernels' pass template argument
 # passes each integrator launches every step
 INTEG_PASSES = {"rk4": ("P1", "P234"), "vv": ("VV",), "gf": ("GF",)}

@@ -103,9 +103,11 @@ def test_one_pass_exact_gradient_tracks_the_oracle(ss, orc, integ, theory):
 
 
 def test_runs_compose_and_switch_integrators(ss, orc):
-    """Each run starts with a pass that tests the current field and stores its
-    force, so 3 + 4 steps equal 7 steps bit for bit, and a run of RK4 followed by
-    velocity Verlet equals the oracle's RK4 then velocity Verlet."""
+    """Each run starts with a pass that tests the current field and forms the
+    half-step velocity u = v + dt/2 a, and ends with v = u - dt/2 a, so 3 + 4 steps
+    equal 7 steps up to the rounding of that round trip (the arrests are the
+    same), and a run of RK4 followed by velocity Verlet equals the oracle's RK4
+    then velocity Verlet."""
     Nx, Ny, h = 96, 40, 0.2
     f = _field(AH, Nx, Ny, h, seed=3)
     a = ss.Solver(AH, Nx, Ny, h, [1.0], dtype="f64")
@@ -116,8 +118,10 @@ def test_runs_compose_and_switch_integrators(ss, orc):
     a.flow_step(3)
     ia = a.flow_step(4)
     ib = b.flow_step(7)
-    assert np.array_equal(_np(a.get_field()), _np(b.get_field()))
-    assert ia["energy"] == ib["energy"] and ia["n_arrests"] == ib["n_arrests"] and ia["step"] == 7
+    pa, pb = _np(a.get_field()), _np(b.get_field())
+    assert np.abs(pa - pb).max() <= 1e-14 * np.abs(pb).max()
+    assert ia["energy"] == pytest.approx(ib["energy"], rel=1e-14)
+    assert ia["n_arrests"] == ib["n_arrests"] and ia["step"] == 7
     a.set_integrator("rk4")
     a.set_field(f)
     a.flow_step(3)
@@ -193,4 +197,34 @@ def test_large_lattice_one_pass_step_sampled_parity(ss, orc, integ):
         got = (slice(None), slice(j0 + 2, j0 + S + 2), slice(i0 + 2, i0 + S + 2))
         assert np.abs(f1[got] - w1[sl]).max() <= 1e-5 * max(np.abs(w1[sl]).max(), 1.0), (j0, i0)
         assert np.abs(v1[got] - wv[sl]).max() <= 1e-5 * max(np.abs(w1[sl]).max(), 1.0), (j0, i0)
+    s.close()
+
+
+@pytest.mark.parametrize("integ,theory,dtype", [("vv", AH, "f32"), ("vv", AH, "f64"), ("gf", AH, "f32"),
+                                                ("vv", CM, "f32"), ("gf", CM, "f64")])
+def test_one_pass_units_of_several_tiles(ss, orc, integ, theory, dtype):
+    """A ragged lattice with 6174 tiles of 64 x 8 (18 x 343), over three times the
+    2048 workgroups of a stage launch, so each workgroup walks units of three
+    tiles and the second and third take their top rows, and the velocity Verlet
+    partial update of their first rows, from LDS: every site against the oracle
+    after 3 steps."""
+    Nx, Ny, h = 1100, 2740, 0.2
+    print(f"[case] one-pass units {integ} {theory} {dtype}", flush=True)
+    f = _field(theory, Nx, Ny, h, seed=23)
+    if dtype == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    s = ss.Solver(theory, Nx, Ny, h, _params(theory), dtype=dtype)
+    s.set_integrator(integ)
+    s.set_tile(1)
+    s.set_field(f)
+    n = 3
+    info = s.flow_step(n)
+    phi, vel = (_np(x) for x in s.get_field(velocity=True))
+    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), n, scheme=integ)
+    rel = 1e-11 if dtype == "f64" else 1e-5
+    assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max()
+    assert np.abs(vel - v_r).max() <= rel * max(np.abs(phi_r).max(), 1.0)
+    assert info["step"] == n and info["n_arrests"] == na_r
+    if dtype == "f64":
+        assert info["energy"] == pytest.approx(E_r, rel=1e-12)
     s.close()
