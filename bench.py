@@ -40,8 +40,10 @@ HBM_PEAK_GBS = 8000.0
 #   VV (velocity Verlet, one pass) reads phi, v, a, writes phi', v', a';
 #   GF (gradient flow, one pass) reads phi, a, writes phi', a'.
 # field sets (C components of one lattice) read and written per launch; velocity
-# Verlet in kick-drift-kick form reads phi and u and writes phi' and u'
-PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "P234": (3, 2), "VV": (2, 2), "GF": (2, 2)}
+# Verlet in kick-drift-kick form (VV) reads phi and u and writes phi' and u', in
+# its stored-force form (VVA) reads phi, v, a and writes phi', v', a'
+PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "P234": (3, 2), "VV": (2, 2), "VVA": (3, 3),
+             "GF": (2, 2)}
 STEP_SETS = 17          # separate stage passes
 STEP_SETS_FUSED = 7     # P1 + fused stages 2-4
 PLAN_NAMES = ["stages", "fused"]
@@ -153,23 +155,25 @@ def run_unet(args, wl):
     net.close()
 
 
-def other_theory_bytes(name, wl, demag_iters=2, nlev=1):
+def other_theory_bytes(name, wl, demag_iters=2, nlev=1, half_step=False):
     """Bytes per interior site and step that the kernels of a step read and write
     (FP32 fields, FP64 solver planes; halo re-reads not counted):
-      heusler_demag512, velocity Verlet (kick-drift-kick): the pass reads phi and u and
-        writes phi', u' (4 x 3 x 4 B); the solve forms the stage point (reads 2 sets,
-        writes one: 36 B), starts conjugate gradients (reads S_1, S_2 and x, writes r,
+      heusler_demag512, velocity Verlet: the pass reads phi, v, a and writes phi', v',
+        a' (6 x 3 x 4 B; in the half-step form phi and u in and out, 4 x 3 x 4 B); the
+        solve forms the stage point (reads 3 sets, writes one: 48 B; half-step form
+        2 and one, 36 B), starts conjugate gradients (reads S_1, S_2 and x, writes r,
         rhs, psi: 40 B) and per iteration moves about 312 B on the lattice (V-cycle
         144 B, the coarser levels a third of that, the conjugate-gradient kernels 120 B);
       bec256, RK4 with the atom-number constraint: stage points 104 B, gradients 64 B,
         forces and updates 152 B, the end-of-step scaling 32 B (two components);
-      bs512, velocity Verlet (kick-drift-kick): 4 x 3 x 4 B.
-    The restart pass after an arrest (reads phi, writes u) is not counted."""
+      bs512, velocity Verlet: 6 x 3 x 4 B (half-step form 4 x 3 x 4 B).
+    The half-step form's restart pass after an arrest (reads phi, writes u) is not
+    counted."""
     if name == "heusler_demag512":
-        return 48 + 36 + 40 + demag_iters * 312
+        return (48 + 36 if half_step else 72 + 48) + 40 + demag_iters * 312
     if name == "bec256":
         return 352
-    return 48
+    return 48 if half_step else 72
 
 
 def run_other(args, name, wl):
@@ -200,7 +204,8 @@ def run_other(args, name, wl):
     done = res["step"] - args.warmup
     sites = N * N
     ms_step = 1e3 * el / max(done, 1)
-    per_site = other_theory_bytes(name, wl)
+    half = wl["integrator"] == "vv" and s.vv_form == ss.SS_VV_HALF_STEP
+    per_site = other_theory_bytes(name, wl, half_step=half)
     gbps = per_site * sites / (ms_step * 1e-3) / 1e9
     obs = s.observables()
     out = {"metric": "site-updates/s", "value": sites * done / el, "unit": "site-updates/s", "n_gpus": 1,
@@ -558,7 +563,11 @@ def main():
     # per-pass device time with HIP events on the library's stream
     plan = s.plan
     ms = s.time_passes(args.timing_steps)
-    if args.integrator != "rk4":
+    import paper_2603_24370_amd as ss
+    half_step = args.integrator == "vv" and s.vv_form == ss.SS_VV_HALF_STEP
+    if args.integrator == "vv":
+        names = ["VV" if half_step else "VVA"]
+    elif args.integrator != "rk4":
         names = [args.integrator.upper()]
     else:
         names = ["P1", "P2", "P3", "P4"] if plan == 0 else ["P1", "P234"]
@@ -569,16 +578,22 @@ def main():
         passes[name] = {"ms": ms[k], "GB_per_launch": nbytes / 1e9, "GBps": nbytes / (ms[k] * 1e-3) / 1e9}
     dom = max(passes, key=lambda k: passes[k]["ms"])
     ach = passes[dom]["GBps"]
+    if half_step:
+        # the restart pass that follows an arrest (reads phi, writes u): its mean
+        # time per step, over steps where it works and steps where it returns at once
+        st = s.info()
+        passes["VV restart"] = {"ms": ms[1], "GB_per_launch": sites * C * b * 2 / 1e9,
+                                "arrest_fraction": st["n_arrests"] / max(st["step"], 1)}
     if args.integrator != "rk4":
         step_sets = sum(PASS_SETS[names[0]])
     else:
         step_sets = STEP_SETS if plan == 0 else STEP_SETS_FUSED
     step_gbps = step_sets * C * b * sites / (ms_step * 1e-3) / 1e9
-    import paper_2603_24370_amd as ss
     # the counter record covers the Euler-Lagrange kernels only
     tr = traffic_record(dom, args.workload, ss.ss_get_tile(s.ctx)) if args.grad == "el" else None
     tr_gb = tr["total_GB"] if tr else None
-    kname = {"P234": "stage_pass_fused (stages 2-4)", "VV": "stage_pass (velocity Verlet step)",
+    kname = {"P234": "stage_pass_fused (stages 2-4)", "VV": "stage_pass (velocity Verlet step, half-step form)",
+             "VVA": "stage_pass (velocity Verlet step, stored force)",
              "GF": "stage_pass (gradient-flow step)"}.get(dom, f"stage_pass {dom}")
     if args.grad == "exact":
         kname = f"stage_pass_exact {dom}"

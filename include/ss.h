@@ -390,21 +390,22 @@ int ss_get_plan(ss_ctx* ctx);
  *   SS_INTEG_VV   velocity Verlet, phi' = phi + dt v + dt^2/2 a, a' = -G(phi'),
  *                 v' = v + dt/2 (a + a'), with E_h(phi') reduced in the pass that
  *                 forms phi', so the arrest test of eq. (4) for the next step is
- *                 ready when that step starts. On the lattice theories it runs
- *                 in kick-drift-kick form: within a run the velocity buffer
- *                 holds u = v + dt/2 a, and one pass per step reads phi and u
- *                 and writes phi' = phi + dt u and u' = v' + dt/2 a' (4 field
- *                 sets of HBM traffic per site and step); a step after an
- *                 arrest (v = 0) is preceded by a pass that sets u = dt/2 a
- *                 from the field. The BEC keeps v and a between steps (6 sets);
+ *                 ready when that step starts. One pass per step reads phi, v
+ *                 and the stored force a and writes phi', v', a' (6 field sets
+ *                 of HBM traffic per site and step), or, in kick-drift-kick
+ *                 form (ss_set_vv_form), keeps u = v + dt/2 a in the velocity
+ *                 buffer within a run and reads phi and u and writes
+ *                 phi' = phi + dt u and u' = v' + dt/2 a' (4 sets); there a
+ *                 step after an arrest (v = 0) is preceded by a pass that sets
+ *                 u = dt/2 a from the field;
  *   SS_INTEG_GF   gradient flow phi' = phi + tau a with tau = dt^2/2 (the step
  *                 velocity Verlet takes from rest), one pass reading phi and a,
  *                 writing phi' and a' (4 field sets); no velocity, no arrest.
  * dt = C h as for RK4. Every run of a one-pass integrator (ss_flow_step,
  * ss_minimise) begins with one pass that tests the current field and stores
- * its force (velocity Verlet on the lattice theories: forms u) and ends with
- * the velocity of the last field (v = u - dt/2 a, or 0 after an arrest), so
- * between runs the velocity buffer holds v. Chiral magnet: phi' is normalised
+ * its force (kick-drift-kick: forms u) and ends with the velocity of the last
+ * field (0 after an arrest; kick-drift-kick: v = u - dt/2 a), so between runs
+ * the velocity buffer holds v. Chiral magnet: phi' is normalised
  * before its force is taken and v' is projected on its tangent plane.
  * Batches: ss_batch_set_integrator. Synchronises. */
 #define SS_INTEG_RK4 0
@@ -412,6 +413,26 @@ int ss_get_plan(ss_ctx* ctx);
 #define SS_INTEG_GF 2
 int ss_set_integrator(ss_ctx* ctx, int integ);
 int ss_get_integrator(ss_ctx* ctx);
+
+/* How velocity Verlet (SS_INTEG_VV, Sec. 3.2) keeps its state between steps;
+ * both forms take the same steps up to rounding, and between runs the velocity
+ * buffer holds v either way.
+ *   SS_VV_STORED_FORCE  v and a = -G(phi) (6 field sets per step, no extra launch);
+ *   SS_VV_HALF_STEP     kick-drift-kick: u = v + dt/2 a (4 field sets per step,
+ *                       plus a restart pass launched every step that works only
+ *                       after an arrest);
+ *   SS_VV_AUTO          (default) the half-step form on lattices of at least
+ *                       2^20 interior sites, where bytes outweigh the extra
+ *                       launch, the stored force below. The BEC always keeps the
+ *                       stored force (SS_EINVAL for SS_VV_HALF_STEP).
+ * ss_get_vv_form returns the form the context's runs use (never SS_VV_AUTO).
+ * Batches always use the half-step form (one restart launch serves every
+ * member). Synchronises. */
+#define SS_VV_AUTO 0
+#define SS_VV_STORED_FORCE 1
+#define SS_VV_HALF_STEP 2
+int ss_set_vv_form(ss_ctx* ctx, int form);
+int ss_get_vv_form(ss_ctx* ctx);
 
 /* Conjugate-gradient iterations per solve of the demagnetising potential
  * (Sec. 4.2, eq. (6)): iters_flow for every field a flow step evaluates (the

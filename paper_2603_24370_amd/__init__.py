@@ -24,6 +24,8 @@ DMI_KINDS = {"bulk": SS_DMI_BULK, "heusler": SS_DMI_HEUSLER}
 SS_PLAN_STAGES, SS_PLAN_FUSED = 0, 1
 SS_INTEG_RK4, SS_INTEG_VV, SS_INTEG_GF = 0, 1, 2
 INTEGRATORS = {"rk4": SS_INTEG_RK4, "vv": SS_INTEG_VV, "gf": SS_INTEG_GF}
+SS_VV_AUTO, SS_VV_STORED_FORCE, SS_VV_HALF_STEP = 0, 1, 2
+VV_FORMS = {"auto": SS_VV_AUTO, "stored_force": SS_VV_STORED_FORCE, "half_step": SS_VV_HALF_STEP}
 SS_NUM_PLANS = 2
 SS_THEORY_AH, SS_THEORY_CM, SS_THEORY_BS, SS_THEORY_BEC = 0, 1, 2, 3
 SS_ANSATZ_VORTICES, SS_ANSATZ_SKYRMION, SS_ANSATZ_BEC = 0, 1, 2
@@ -83,7 +85,8 @@ EXPORTS = ["ss_theory_id", "ss_components", "ss_workspace_bytes", "ss_create", "
            "ss_batch_set_tile", "ss_batch_autotune", "ss_batch_set_plan", "ss_batch_get_plan", "ss_batch_observables", "ss_set_energy_target", "ss_learned_input",
            "ss_learned_targets", "ss_init_learned", "ss_state_bytes", "ss_get_state", "ss_set_state",
            "ss_energy_grad_noalloc", "ss_set_integrator", "ss_get_integrator", "ss_workspace_bytes_for",
-           "ss_set_demag_iters", "ss_batch_set_integrator", "ss_batch_get_integrator"]
+           "ss_set_demag_iters", "ss_batch_set_integrator", "ss_batch_get_integrator", "ss_set_vv_form",
+           "ss_get_vv_form"]
 SSN_EXPORTS = ["ssn_param_count", "ssn_workspace_bytes", "ssn_create", "ssn_destroy", "ssn_num_params",
                "ssn_set_weights", "ssn_get_weights", "ssn_get_grads", "ssn_forward", "ssn_forward_graph", "ssn_backward",
                "ssn_adam_step", "ssn_set_grad_clip",
@@ -142,6 +145,8 @@ def lib():
     L.ss_set_plan.argtypes = [vp, i]
     L.ss_set_integrator.argtypes = [vp, i]
     L.ss_get_integrator.argtypes = [vp]
+    L.ss_set_vv_form.argtypes = [vp, i]
+    L.ss_get_vv_form.argtypes = [vp]
     L.ss_get_plan.argtypes = [vp]
     ins = ctypes.POINTER(ss_instance)
     L.ss_batch_workspace_bytes.argtypes = [cp, i, ins, i, ctypes.POINTER(ctypes.c_size_t)]
@@ -351,6 +356,14 @@ def ss_get_integrator(ctx) -> int:
     return _check_nonneg(lib().ss_get_integrator(ctx))
 
 
+def ss_set_vv_form(ctx, form):
+    _check(lib().ss_set_vv_form(ctx, VV_FORMS.get(form, form)))
+
+
+def ss_get_vv_form(ctx) -> int:
+    return _check_nonneg(lib().ss_get_vv_form(ctx))
+
+
 def ss_autotune(ctx, n_steps=10):
     """Returns (tile, plan, ms) with ms[plan][tile] the mean step time (-1: not timed)."""
     nt = ss_tile_count()
@@ -542,6 +555,15 @@ class Solver:
     @property
     def integrator(self):
         return ss_get_integrator(self.ctx)
+
+    def set_vv_form(self, form):
+        """Velocity Verlet's state between steps: "auto" (default), "stored_force" or "half_step"."""
+        ss_set_vv_form(self.ctx, form)
+
+    @property
+    def vv_form(self):
+        """The form this context's velocity Verlet runs use (SS_VV_STORED_FORCE or SS_VV_HALF_STEP)."""
+        return ss_get_vv_form(self.ctx)
 
     def set_energy_target(self, e_target):
         ss_set_energy_target(self.ctx, e_target)

@@ -155,6 +155,7 @@ struct ss_ctx {
   int tile;
   int plan;   // SS_PLAN_*: how stages 2-4 of a step are launched
   int integ;  // SS_INTEG_*: the flow's integrator
+  int vv_form;  // SS_VV_*: how velocity Verlet keeps its state between steps
   size_t ws_total;  // bytes of the workspace in use
   // demagnetising potential (chiral magnet with params.i[2] = 1)
   struct Demag {
@@ -248,7 +249,7 @@ template <class T, int TH, int PASS, int CFG>
 int launch_cfg(const PassArgs<T>& a, int nlaunch, hipStream_t s) {
   constexpr TileCfg tc = kTiles[CFG];
   PassArgs<T> b = a;
-  if constexpr (PASS == kP1 || PASS == kPrime || PASS == kVV || PASS == kGF || vv_in_place(PASS)) {
+  if constexpr (PASS == kP1 || PASS == kPrime || advances_first(PASS) || vv_in_place(PASS)) {
     const long r = resident_groups<T, TH, PASS, tc.TX, tc.TY, tc.RY>();
     if (nlaunch > r) {
       nlaunch = (int)r;
@@ -355,7 +356,7 @@ void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   hipLaunchKernelGGL(bec_mu, dim3(1), b1, 0, s, (const double*)W.part, W.sc, a.cf, (const DevStatus*)c->st, flow);
   hipLaunchKernelGGL((bec_apply<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, W, (const double*)W.sc,
                      a.out, a.out_pitch, a.out_plane);
-  if constexpr (PASS == kP4 || PASS == kVV) {
+  if constexpr (PASS == kP4 || PASS == kVVA) {
     hipLaunchKernelGGL(bec_fix_scalars, dim3(1), b1, 0, s, (const double*)W.part, W.sc, a.cf,
                        (const DevStatus*)c->st);
     if constexpr (PASS == kP4)
@@ -467,9 +468,17 @@ void launch_fused(const ss_ctx* c, hipStream_t s) {
   else launch_fused_t<T, kBS>(lt, a, L.nlaunch, s);
 }
 
-// Velocity Verlet in kick-drift-kick form (the lattice theories; the BEC keeps
-// v and the force a between steps).
-bool vv_kdk(const ss_ctx* c) { return c->integ == SS_INTEG_VV && c->theory != SS_THEORY_BEC; }
+// Velocity Verlet's form (SS_VV_AUTO): kick-drift-kick from kKdkMinSites
+// interior sites up, where its two fewer field sets per step outweigh the
+// launch of its restart pass (about 3 us whether or not it works); the stored
+// force below, and always for the BEC.
+constexpr long kKdkMinSites = 1L << 20;
+bool vv_kdk_form(const ss_ctx* c) {
+  if (c->theory == SS_THEORY_BEC) return false;
+  if (c->vv_form != SS_VV_AUTO) return c->vv_form == SS_VV_HALF_STEP;
+  return (long)c->Nx * c->Ny >= kKdkMinSites;
+}
+bool vv_kdk(const ss_ctx* c) { return c->integ == SS_INTEG_VV && vv_kdk_form(c); }
 
 template <class T>
 void enqueue_steps(const ss_ctx* c, int n, hipStream_t s) {
@@ -480,9 +489,11 @@ void enqueue_steps(const ss_ctx* c, int n, hipStream_t s) {
     for (int k = 0; k < n; ++k) {
       if (c->integ == SS_INTEG_GF) {
         launch_pass<T, kGF>(c, a, s);
-      } else {
-        if (vv_kdk(c)) launch_pass<T, kVVRestart>(c, a, s);
+      } else if (vv_kdk(c)) {
+        launch_pass<T, kVVRestart>(c, a, s);
         launch_pass<T, kVV>(c, a, s);
+      } else {
+        launch_pass<T, kVVA>(c, a, s);
       }
     }
     return;
@@ -830,6 +841,7 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   c->plan = (grad_mode == SS_GRAD_EL && dtype == SS_F32 && !pb.demag && th != SS_THEORY_BEC) ? kDefaultPlanF32
                                                                                           : SS_PLAN_STAGES;
   c->integ = SS_INTEG_RK4;
+  c->vv_form = SS_VV_AUTO;
   c->ws_total = need;
   std::memset(&c->dm, 0, sizeof(c->dm));
   c->bec_S = c->bec_G = nullptr;
@@ -946,10 +958,12 @@ int ss_time_passes(ss_ctx* c, int n_steps, double* ms) {
       SS_HIP(hipEventRecord(ev[1], c->stream));
       if (c->dtype == SS_F32) {
         if (c->integ == SS_INTEG_GF) launch_pass<float, kGF>(c, pass_args<float>(c), c->stream);
-        else launch_pass<float, kVV>(c, pass_args<float>(c), c->stream);
+        else if (vv_kdk(c)) launch_pass<float, kVV>(c, pass_args<float>(c), c->stream);
+        else launch_pass<float, kVVA>(c, pass_args<float>(c), c->stream);
       } else {
         if (c->integ == SS_INTEG_GF) launch_pass<double, kGF>(c, pass_args<double>(c), c->stream);
-        else launch_pass<double, kVV>(c, pass_args<double>(c), c->stream);
+        else if (vv_kdk(c)) launch_pass<double, kVV>(c, pass_args<double>(c), c->stream);
+        else launch_pass<double, kVVA>(c, pass_args<double>(c), c->stream);
       }
       for (int k = 2; k < 5; ++k) SS_HIP(hipEventRecord(ev[k], c->stream));
     } else if (c->plan != SS_PLAN_STAGES) {
@@ -1428,6 +1442,26 @@ int ss_set_integrator(ss_ctx* c, int integ) {
 }
 
 int ss_get_integrator(ss_ctx* c) { return c ? c->integ : SS_EINVAL; }
+
+int ss_set_vv_form(ss_ctx* c, int form) {
+  if (!c) return fail(SS_EINVAL, "ctx is NULL");
+  if (form != SS_VV_AUTO && form != SS_VV_STORED_FORCE && form != SS_VV_HALF_STEP)
+    return fail(SS_EINVAL, "unknown velocity Verlet form");
+  if (form == SS_VV_HALF_STEP && c->theory == SS_THEORY_BEC)
+    return fail(SS_EINVAL, "the BEC runs velocity Verlet in its stored-force form");
+  SS_HIP(hipStreamSynchronize(c->stream));
+  c->vv_form = form;
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return SS_OK;
+}
+
+int ss_get_vv_form(ss_ctx* c) {
+  if (!c) return SS_EINVAL;
+  return vv_kdk_form(c) ? SS_VV_HALF_STEP : SS_VV_STORED_FORCE;
+}
 
 int ss_set_demag_iters(ss_ctx* c, int iters_flow, int iters_eval) {
   if (!c) return fail(SS_EINVAL, "ctx is NULL");

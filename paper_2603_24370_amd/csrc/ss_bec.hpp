@@ -76,12 +76,12 @@ __global__ void __launch_bounds__(256) bec_stage(Bufs<T> B, Coeffs cf, const Dev
   constexpr bool STAGED = AFTER_P1 || ONEPASS;
   const long long step = st->step;
   const int cur = AFTER_P1 ? int((step - 1) & 1) : int(step & 1);
-  const bool arrest = (AFTER_P1 || PASS == kVV) ? (st->arrest != 0) : false;
+  const bool arrest = (AFTER_P1 || PASS == kVVA) ? (st->arrest != 0) : false;
   const T dt = (T)cf.dt;
   T cv = T(0), ca = T(0);
   if (PASS == kP2) cv = T(0.5) * dt;
   if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
-  if (PASS == kP4 || PASS == kVV) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (PASS == kP4 || PASS == kVVA) { cv = dt; ca = T(0.5) * dt * dt; }
   if (PASS == kGF) ca = T(0.5) * dt * dt;
   if (arrest) cv = T(0);
   const T* __restrict__ ph = (PASS == kEval && src != nullptr) ? src : (cur ? B.phi[1] : B.phi[0]);
@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(256) bec_apply(Bufs<T> B, Coeffs cf, const Dev
   constexpr bool STAGED = (PASS == kP2 || PASS == kP3 || PASS == kP4);
   const long long step = st->step;
   const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
-  const bool arrest = (STAGED || PASS == kVV) ? (st->arrest != 0) : false;
+  const bool arrest = (STAGED || PASS == kVVA) ? (st->arrest != 0) : false;
   const T c = (T)sc[0], mu = (T)sc[1];
   // one-pass integrators: current force (read) and new force (written) by parity
   const T* __restrict__ a_cur = cur ? B.a2 : B.a1;
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(256) bec_apply(Bufs<T> B, Coeffs cf, const Dev
       T* __restrict__ as = cur ? B.a2 : B.a1;
       as[o] = a[0];
       as[B.plane + o] = a[1];
-    } else if (PASS == kVV || PASS == kGF) {
+    } else if (PASS == kVVA || PASS == kGF) {
       // the scaled stage point is the new field; velocity Verlet also forms
       // v' = v + dt/2 (a + a'), projected by bec_vproj after the sums below
 #pragma unroll
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(256) bec_apply(Bufs<T> B, Coeffs cf, const Dev
         phn[k] = pn;
         a_new[k] = a[comp];
         spp += (double)pn * (double)pn;
-        if (PASS == kVV) {
+        if (PASS == kVVA) {
           const T vnew = (arrest ? T(0) : vv[k]) + (T(0.5) * dt) * (a_cur[k] + a[comp]);
           vn[k] = vnew;
           spv += (double)pn * (double)vnew;
@@ -308,8 +308,8 @@ __global__ void __launch_bounds__(256) bec_apply(Bufs<T> B, Coeffs cf, const Dev
   }
   // partials, four per workgroup: {max |G - mu psi|, phi'.phi', phi'.v', unused}
   const double m = reduces(PASS) ? bec_block_max(gm, red) : 0.0;
-  const double a1 = (PASS == kP4 || PASS == kVV) ? bec_block_sum(spp, red) : 0.0;
-  const double a2 = (PASS == kP4 || PASS == kVV) ? bec_block_sum(spv, red) : 0.0;
+  const double a1 = (PASS == kP4 || PASS == kVVA) ? bec_block_sum(spp, red) : 0.0;
+  const double a2 = (PASS == kP4 || PASS == kVVA) ? bec_block_sum(spv, red) : 0.0;
   if (threadIdx.x == 0) {
     double* p = W.part + 4 * (long)blockIdx.x;
     p[0] = m;

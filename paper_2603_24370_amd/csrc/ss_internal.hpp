@@ -73,11 +73,13 @@ enum Pass : int {
   kP4 = 3,     // stage 4: a4 = -G(phi + dt v + dt^2/2 a2); phi', v'
   kEval = 4,   // G and E of a given field; flow state untouched
   kCheck = 5,  // arrest test of the current field only (after a run of steps)
-  // Gradient flow keeps the force a = -G of the current field in one of two
-  // force buffers (a1, a2 by step parity):
+  // Gradient flow, and velocity Verlet in its stored-force form, keep the force
+  // a = -G of the current field in one of two force buffers (a1, a2 by step parity):
   kPrime = 6,  // arrest test of the current field, as kCheck, and its force stored
   kGF = 8,     // gradient flow: phi' = phi + dt^2/2 a, a' = -G(phi'), E_h(phi')
-  // Velocity Verlet on the lattice theories runs in kick-drift-kick form: within
+  kVVA = 12,   // velocity Verlet: phi' = phi + dt v + dt^2/2 a, a' = -G(phi'),
+               //   v' = v + dt/2 (a + a'), E_h(phi'); then the arrest test of phi'
+  // Velocity Verlet in kick-drift-kick form (large lattices and batches): within
   // a run the velocity buffer holds u = v + dt/2 a of the current field (the
   // next half-step velocity), so a step reads and writes the field and u only.
   kVV = 7,          // phi' = phi + dt u, G' = G(phi'), v' = u - dt/2 G' (tangent
@@ -90,34 +92,37 @@ enum Pass : int {
 };
 
 // The pass writes a new field and tests it (its finalise advances the step first).
-constexpr bool advances_first(int pass) { return pass == kVV || pass == kGF; }
+constexpr bool advances_first(int pass) { return pass == kVV || pass == kVVA || pass == kGF; }
 // The pass reduces energy, max |G| and a non-finite count.
 constexpr bool reduces(int pass) {
-  return pass == kP1 || pass == kEval || pass == kCheck || pass == kPrime || pass == kVV || pass == kGF ||
+  return pass == kP1 || pass == kEval || pass == kCheck || pass == kPrime || advances_first(pass) ||
          pass == kVVStart;
 }
 // The pass evaluates G at a stage point phi + cv v + ca a (stage_coeffs) rather
 // than at the current field.
 constexpr bool staged(int pass) { return pass == kP2 || pass == kP3 || pass == kP4 || advances_first(pass); }
 constexpr bool stage_reads_v(int pass) { return staged(pass) && pass != kGF; }
-constexpr bool stage_reads_a(int pass) { return pass == kP3 || pass == kP4 || pass == kGF; }
-// The pass reads the arrest flag: RK4 stages 2-4 start from rest after an
-// arrest, and velocity Verlet's end of run sets v = 0.
-constexpr bool uses_arrest(int pass) { return pass == kP2 || pass == kP3 || pass == kP4 || pass == kVVEnd; }
+constexpr bool stage_reads_a(int pass) { return pass == kP3 || pass == kP4 || pass == kGF || pass == kVVA; }
+// The pass reads the arrest flag: RK4 stages 2-4 and the stored-force velocity
+// Verlet step start from rest after an arrest, and the kick-drift-kick end of
+// run sets v = 0.
+constexpr bool uses_arrest(int pass) {
+  return pass == kP2 || pass == kP3 || pass == kP4 || pass == kVVA || pass == kVVEnd;
+}
 // The pass writes the velocity buffer of the current field in place (each site
 // by the thread that reads it): the velocity Verlet passes around the steps.
 constexpr bool vv_in_place(int pass) { return pass == kVVStart || pass == kVVRestart || pass == kVVEnd; }
 
 // Coefficients of the stage point phi + cv v + ca a of a pass. After an arrest
-// the RK4 stages 2-4 start from rest (cv = 0); velocity Verlet's u already
-// carries the arrest (kVVRestart).
+// the RK4 stages 2-4 and the stored-force velocity Verlet step start from rest
+// (cv = 0); the kick-drift-kick u already carries the arrest (kVVRestart).
 template <class T, int PASS>
 __device__ __forceinline__ void stage_coeffs(T dt, bool arrest, T& cv, T& ca) {
   cv = T(0);
   ca = T(0);
   if (PASS == kP2) cv = T(0.5) * dt;
   if (PASS == kP3) { cv = T(0.5) * dt; ca = T(0.25) * dt * dt; }
-  if (PASS == kP4) { cv = dt; ca = T(0.5) * dt * dt; }
+  if (PASS == kP4 || PASS == kVVA) { cv = dt; ca = T(0.5) * dt * dt; }
   if (PASS == kVV) cv = dt;
   if (PASS == kGF) ca = T(0.5) * dt * dt;
   if (arrest) cv = T(0);

@@ -103,7 +103,7 @@ __device__ __forceinline__ void for_each_tile(int ntx, int nty, int seg, F&& bod
   for (int u = xcd * per + q; u < uend; u += m) {
     const int sg = u / ntx, tx = u - sg * ntx;
     const int ty1 = min(nty, (sg + 1) * seg);
-    for (int ty = sg * seg; ty < ty1; ++ty) body(tx, ty, ty - sg * seg);
+    for (int ty = sg * seg; ty < ty1; ++ty) body(tx, ty, ty - sg * seg, ty + 1 < ty1);
   }
 }
 
@@ -176,16 +176,26 @@ __device__ __forceinline__ InstView<T> view_of(const Bufs<T>& B, const Coeffs& c
 // a' = -G(phi') and, for velocity Verlet, v' = v + dt/2 (a + a'), with v = 0
 // after an arrest and, for the chiral magnet, v' projected on the tangent plane
 // at phi'. a is the current field's force, read by the pass.
-// Epilogue of a one-pass step at one site: S is the new field, G = G(S), u the
-// half-step velocity read by the step (velocity Verlet). Velocity Verlet writes
-// the new field and u' = v' - dt/2 G with v' = u - dt/2 G (tangent to S for
-// unit fields); gradient flow writes the new field and its force -G.
+// w = v0 + dt/2 a: the part of the stored-force velocity Verlet update known
+// before the force at the new field (v0 = 0 after an arrest); formed when the
+// inputs are read, so that a thread holds one value per component, not two.
+template <class T>
+__device__ __forceinline__ T vv_partial(bool arrest, T dt, T v, T a) {
+  return (arrest ? T(0) : v) + (T(0.5) * dt) * a;
+}
+
+// Epilogue of a one-pass step at one site: S is the new field, G = G(S), and u
+// the part of the new velocity known before G: the half-step velocity read by
+// the kick-drift-kick step, or w = v0 + dt/2 a of the stored-force step. Both
+// velocity Verlet forms take v' = u - dt/2 G (tangent to S for unit fields);
+// kick-drift-kick writes the new field and u' = v' - dt/2 G, the stored-force
+// form the new field, v' and the force -G, gradient flow the new field and -G.
 template <class T, int TH, int PASS>
 __device__ __forceinline__ void one_pass_epilogue(T dt, const T (&u)[4], const T (&S)[4], const T (&G)[4],
                                                   T* __restrict__ phn, T* __restrict__ vn, T* __restrict__ an,
                                                   long plane, long off) {
   constexpr int C = NComp<TH>::value;
-  if (PASS == kVV) {
+  if (PASS == kVV || PASS == kVVA) {
     const T hd = T(0.5) * dt;
     T vnew[4];
 #pragma unroll
@@ -198,7 +208,12 @@ __device__ __forceinline__ void one_pass_epilogue(T dt, const T (&u)[4], const T
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       __builtin_nontemporal_store(S[c], &phn[c * plane + off]);
-      __builtin_nontemporal_store(vnew[c] - hd * G[c], &vn[c * plane + off]);
+      if (PASS == kVV) {
+        __builtin_nontemporal_store(vnew[c] - hd * G[c], &vn[c * plane + off]);
+      } else {
+        __builtin_nontemporal_store(vnew[c], &vn[c * plane + off]);
+        __builtin_nontemporal_store(-G[c], &an[c * plane + off]);
+      }
     }
   } else {
 #pragma unroll
@@ -230,19 +245,20 @@ __device__ __forceinline__ void vv_in_place_epilogue(T dt, bool arrest, const T 
 }
 
 // LDS of one tile of a stage pass, in elements of T: the stage point on the
-// tile and its halo of 2 (C planes of LY x LX). The one-pass integrators walk
-// a unit's tiles downwards and carry the overlap from one tile to the next: the
-// last four stage rows (C x 4 x LX), and for velocity Verlet the partial
-// update v0 + (dt/2) a of the two bottom halo rows, which are the next tile's
-// first own rows (2 parities x 2 rows x C x TX).
+// tile and its halo of 2 (C planes of LY x LX). The one-pass integrators (and
+// velocity Verlet's passes around the steps) walk a unit's tiles downwards and
+// carry the overlap from one tile to the next: the
+// last four stage rows (C x 4 x LX), and for velocity Verlet the part of the
+// new velocity known before the force (u, or w = v0 + dt/2 a) of the two bottom
+// halo rows, which are the next tile's first own rows (2 parities x 2 rows x C x TX).
 template <class T, int TH, int PASS, int TX, int TY>
 struct TileLds {
   static constexpr int C = NComp<TH>::value;
   static constexpr int LX = TX + 4, LY = TY + 4;
-  static constexpr bool CARRY = (PASS == kVV || PASS == kGF);
+  static constexpr bool CARRY = advances_first(PASS) || vv_in_place(PASS);
   static constexpr int STAGE = C * LY * LX;
   static constexpr int ROWS = CARRY ? C * 4 * LX : 0;
-  static constexpr int RAW = (PASS == kVV) ? 2 * 2 * C * TX : 0;
+  static constexpr int RAW = (PASS == kVV || PASS == kVVA) ? 2 * 2 * C * TX : 0;
   static constexpr int size = STAGE + ROWS + RAW;
 };
 
@@ -253,15 +269,16 @@ struct TileLds {
 // contributions (energy, max |G|, non-finite count) are added to the caller's
 // accumulators. Ends with a barrier (LDS is reused by the next tile).
 // k is the tile's place in its workgroup's walk down a unit (0 = the unit's top
-// tile). For the one-pass integrators a tile with k > 0 takes the four stage
+// tile). For the one-pass passes (TileLds::CARRY) a tile with k > 0 takes the four stage
 // rows it shares with the tile above, and the raw inputs of its first two own
 // rows, from LDS (see TileLds) instead of reading them again: the values are
 // the ones stage_at formed for the tile above, so the result is bitwise the
-// same, and each array is read about once plus its x halo.
+// same, and each array is read about once plus its x halo. more = another tile
+// of the unit follows (only then is the overlap kept).
 template <class T, int TH, int PASS, int TX, int TY, int RY>
 __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool arrest, const T* __restrict__ src,
                                           T* __restrict__ out, long out_pitch, long out_plane, int x0, int y0, int k,
-                                          T* __restrict__ lds, double& e_acc, double& g_acc, int& nf) {
+                                          bool more, T* __restrict__ lds, double& e_acc, double& g_acc, int& nf) {
   constexpr int C = NComp<TH>::value;
   constexpr int LX = TX + 4, LY = TY + 4;
   constexpr int NT = TX * (TY / RY);
@@ -359,11 +376,16 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
         rp[r][c] = rv[r][c] = ra[r][c] = so[r][c] = T(0);
         if (c < C) {
           so[r][c] = cs[(c * 4 + ly) * LX + lx];
-          if (PASS == kVV) rv[r][c] = q[c * TX];
+          if (PASS == kVV || PASS == kVVA) rv[r][c] = q[c * TX];
         }
       }
     } else {
       stage_at(gi, y0 + ly - 2, rp[r], rv[r], ra[r], so[r]);
+      // the stored-force step keeps w = v0 + dt/2 a in rv (the epilogue's u)
+      if (PASS == kVVA) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rv[r][c] = vv_partial(arrest, dt, rv[r][c], ra[r][c]);
+      }
 #pragma unroll
       for (int c = 0; c < C; ++c) s[c][ly * LX + lx] = so[r][c];
     }
@@ -398,15 +420,15 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
     stage_at(x0 - 2 + lxr, y0 - 2 + ly, d0, d1v, d2, S);
 #pragma unroll
     for (int c = 0; c < C; ++c) s[c][ly * LX + lxr] = S[c];
-    if (PASS == kVV && ly >= LY - 2 && lxr >= 2 && lxr < LX - 2) {
-      // the next tile's first own rows: keep their u
+    if ((PASS == kVV || PASS == kVVA) && more && ly >= LY - 2 && lxr >= 2 && lxr < LX - 2) {
+      // the next tile's first own rows: keep their u (or w)
       T* __restrict__ q = cr + (par * 2 + (ly - (LY - 2))) * C * TX + (lxr - 2);
 #pragma unroll
-      for (int c = 0; c < C; ++c) q[c * TX] = d1v[c];
+      for (int c = 0; c < C; ++c) q[c * TX] = PASS == kVV ? d1v[c] : vv_partial(arrest, dt, d1v[c], d2[c]);
     }
   }
   __syncthreads();
-  if (CARRY) {
+  if (CARRY && more) {
     // stage rows TY .. TY+3 are the next tile's rows 0-3; saved before any
     // in-place change of the stage point below
     for (int idx = tid; idx < C * 4 * LX; idx += NT) {
@@ -697,6 +719,11 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   for (int r = 0; r < RY; ++r) {
     const int ly = 4 + threadIdx.y * RY + r;
     stage_at(gi, y0 + ly - 4, rp[r], rv[r], ra[r], so[r]);
+    // the stored-force step keeps w = v0 + dt/2 a in rv (the epilogue's u)
+    if (PASS == kVVA) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) rv[r][c] = vv_partial(arrest, dt, rv[r][c], ra[r][c]);
+    }
 #pragma unroll
     for (int c = 0; c < C; ++c) s[c][ly * LX + 4 + threadIdx.x] = so[r][c];
   }
@@ -998,9 +1025,9 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<T, TH, PASS, RY>::value))) stage_p
 
   double e_acc = 0.0, g_acc = 0.0;
   int nf = 0;
-  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty, int k) {
+  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty, int k, bool more) {
     tile_body<T, TH, PASS, TX, TY, RY>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane, tx * TX, ty * TY, k,
-                                       lds, e_acc, g_acc, nf);
+                                       more, lds, e_acc, g_acc, nf);
   });
   if (!REDUCE) return;
 
@@ -1346,7 +1373,7 @@ stage_pass_fused(PassArgs<T> a) {
   const int cur = int((st->step - 1) & 1);
   const bool arrest = st->arrest != 0;
   const InstView<T> V = view_of<T>(a.B, a.cf);
-  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty, int) {
+  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty, int, bool) {
     tile_body_fused<T, TH, TX, TY, RY>(V, cur, arrest, tx * TX, ty * TY, lds);
   });
 }
@@ -1373,7 +1400,7 @@ __global__ void __launch_bounds__(256) stage_pass_exact(PassArgs<T> a) {
   const InstView<T> V = view_of<T>(a.B, a.cf);
   double e_acc = 0.0, g_acc = 0.0;
   int nf = 0;
-  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty, int) {
+  for_each_tile(a.ntx, a.nty, a.seg, [&](int tx, int ty, int, bool) {
     tile_body_exact<T, TH, PASS>(V, cur, arrest, a.src, a.out, a.out_pitch, a.out_plane, tx * kExTX, ty * kExTY,
                                  lds, e_acc, g_acc, nf);
   });
@@ -1456,7 +1483,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<T, TH, PASS, RY>::value))) batch_p
     int nf = 0;
     for (int k = 0; k < U.n; ++k)
       tile_body<T, TH, PASS, TX, TY, RY>(I.V, cur, arrest, nullptr, nullptr, 0, 0, U.tx * TX, (U.ty0 + k) * TY, k,
-                                         lds, e_acc, g_acc, nf);
+                                         k + 1 < U.n, lds, e_acc, g_acc, nf);
     if (!REDUCE) return;
     block_reduce3<NT>(e_acc, g_acc, nf, red);
     if (tid == 0) {

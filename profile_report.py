@@ -42,8 +42,11 @@ DEFAULT_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 # field sets read and written per site by each pass (stage passes P1..P4, the
 # fused pass of stages 2-4, velocity Verlet in kick-drift-kick form, gradient flow)
-ALG_SETS = {"P1": (1, 1), "P234": (3, 2), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "VV": (2, 2), "GF": (2, 2)}
-PASS_INDEX = {"P1": 0, "P2": 1, "P3": 2, "P4": 3, "VV": 7, "GF": 8}  # the kernels' pass template argument
+ALG_SETS = {"P1": (1, 1), "P234": (3, 2), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "VV": (2, 2), "VVA": (3, 3),
+            "GF": (2, 2)}
+# the kernels' pass template argument (VV: velocity Verlet in kick-drift-kick form,
+# VVR: its restart pass, VVA: velocity Verlet with the stored force)
+PASS_INDEX = {"P1": 0, "P2": 1, "P3": 2, "P4": 3, "VV": 7, "GF": 8, "VVR": 10, "VVA": 12}
 # passes each integrator launches every step
 INTEG_PASSES = {"rk4": ("P1", "P234"), "vv": ("VV",), "gf": ("GF",)}
 TILES = [(64, 16, 2), (64, 8, 2), (64, 16, 4), (64, 32, 4)]  # (TX, TY, rows per thread)
@@ -75,6 +78,35 @@ def integrator_of(line):
     """rk4, vv or gf from a bench line's integrator description."""
     text = line.get("config", {}).get("integrator", "RK4")
     return "vv" if "Verlet" in text else "gf" if "gradient flow" in text else "rk4"
+
+
+def restart_summary(stats_dirs, F, W, fs, ws):
+    """Velocity Verlet's restart pass (64 x 16 tiles): it works only after an
+    arrest and returns at once otherwise, so its figures are those of the
+    dispatches that worked (more than a fifth of the longest duration or of the
+    largest counter reading)."""
+    k = kernel_name("VVR", 0)
+    durs = []
+    for d in stats_dirs:
+        path = os.path.join(d, "run_kernel_trace.csv")
+        if not os.path.exists(path):
+            continue
+        with open(path) as fh:
+            durs += [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in csv.DictReader(fh)
+                     if _short(r["Kernel_Name"]) == k]
+    if not durs or k not in F or k not in W:
+        return None
+    work = [x for x in durs if x > 0.2 * max(durs)]
+    idle = [x for x in durs if x <= 0.2 * max(durs)]
+    fv, wv = F[k]["FETCH_SIZE"], W[k]["WRITE_SIZE"]
+    rd = wr = None  # no arrest in the counter runs: no working dispatch to read
+    if max(fv) > 0 and max(wv) > 0:
+        rd = fs * statistics.median([v for v in fv if v > 0.2 * max(fv)]) * KIB / 1e9
+        wr = ws * statistics.median([v for v in wv if v > 0.2 * max(wv)]) * KIB / 1e9
+    alg = SITES * C * ELEM / 1e9
+    return {"kernel": k, "dispatches": len(durs), "working": len(work), "us_working": statistics.mean(work),
+            "us_idle": statistics.mean(idle) if idle else 0.0, "read_GB": rd, "write_GB": wr, "alg_read_GB": alg,
+            "alg_write_GB": alg}
 
 
 def medians(c):
@@ -125,7 +157,7 @@ def main(argv=None):
 
     rows, traffic = [], {}
     for t in range(len(TILES)):
-        for p in ("P1", "P234", "P2", "P3", "P4", "VV", "GF"):
+        for p in ("P1", "P234", "P2", "P3", "P4", "VV", "VVA", "GF"):
             if p == "P234" and t >= FUSED_TILES:
                 continue
             k = kernel_name(p, t)
@@ -194,6 +226,24 @@ def main(argv=None):
         md.append(f"| {label} | `{k}` | {64 * a['SQ_INSTS_VALU'] / SITES:.0f} | {busy:.2f} | "
                   f"{64 * c['SQ_INSTS_LDS'] / SITES:.0f} | {c['SQ_LDS_BANK_CONFLICT'] / max(c['SQ_INSTS_LDS'], 1):.2f} | "
                   f"{64 * c['SQ_INSTS_SALU'] / SITES:.1f} | {a['SQ_WAIT_INST_ANY'] / a['SQ_WAVE_CYCLES']:.2f} |")
+
+    rs = restart_summary(args.stats, F, W, fs, ws)
+    if rs is not None:
+        md += ["", f"Velocity Verlet's restart pass `{rs['kernel']}` (reads phi, writes u = dt/2 a after an arrest; "
+               "returns at once on", f"the other steps): {rs['working']} of {rs['dispatches']} dispatches in the "
+               f"stats run worked, {rs['us_working']:.1f} us each (the others {rs['us_idle']:.1f} us)."]
+        if rs["read_GB"] is None:
+            md += ["No arrest fired in the counter runs, so its traffic was not counted."]
+        else:
+            md += [f"A working dispatch reads {rs['read_GB']:.3f} GB (algorithmic {rs['alg_read_GB']:.3f}) and "
+                   f"writes {rs['write_GB']:.3f} GB (algorithmic {rs['alg_write_GB']:.3f})."]
+    if rs is not None and rs["read_GB"] is not None:
+        traffic.setdefault("tile0", {})["VVR"] = {
+            "read_GB": round(rs["read_GB"], 4), "write_GB": round(rs["write_GB"], 4),
+            "total_GB": round(rs["read_GB"] + rs["write_GB"], 4),
+            "algorithmic_GB": round(rs["alg_read_GB"] + rs["alg_write_GB"], 4),
+            "ratio": round((rs["read_GB"] + rs["write_GB"]) / (rs["alg_read_GB"] + rs["alg_write_GB"]), 3),
+            "kernel": rs["kernel"]}
 
     fin = stats.get("ss::pass_finalise<0>")
     if fin is not None:

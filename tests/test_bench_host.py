@@ -68,6 +68,8 @@ def test_unet_step_bytes_and_roofline_bound():
 
 def test_other_theory_step_models():
     import bench
-    assert bench.other_theory_bytes("bs512", {}) == 48
+    assert bench.other_theory_bytes("bs512", {}) == 72
+    assert bench.other_theory_bytes("bs512", {}, half_step=True) == 48
     assert bench.other_theory_bytes("bec256", {}) == 352
-    assert bench.other_theory_bytes("heusler_demag512", {}, demag_iters=2) == 48 + 36 + 40 + 2 * 312
+    assert bench.other_theory_bytes("heusler_demag512", {}, demag_iters=2) == 72 + 48 + 40 + 2 * 312
+    assert bench.other_theory_bytes("heusler_demag512", {}, demag_iters=2, half_step=True) == 48 + 36 + 40 + 2 * 312

@@ -66,7 +66,7 @@ def test_energy_and_gradient(ss, orc, dtype, mode, shape):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("how", ["stages", "fused", "vv", "gf"])
+@pytest.mark.parametrize("how", ["stages", "fused", "vv", "vv_half", "gf"])
 def test_flow_tracks_the_oracle(ss, orc, dtype, how):
     Nx, Ny, h = 96, 45, 0.2
     print(f"[case] baby skyrme flow {how} {dtype}", flush=True)
@@ -75,9 +75,11 @@ def test_flow_tracks_the_oracle(ss, orc, dtype, how):
         f = f.astype(np.float32).astype(np.float64)
     s = ss.Solver(BS, Nx, Ny, h, P, dtype=dtype)
     scheme = "rk4"
-    if how in ("vv", "gf"):
-        s.set_integrator(how)
-        scheme = how
+    if how in ("vv", "vv_half", "gf"):
+        scheme = "gf" if how == "gf" else "vv"
+        s.set_integrator(scheme)
+        if how == "vv_half":
+            s.set_vv_form("half_step")
     else:
         s.set_plan(ss.SS_PLAN_STAGES if how == "stages" else ss.SS_PLAN_FUSED)
     s.set_field(f)

@@ -211,6 +211,14 @@ def test_bec_refuses_what_it_cannot_run(ss):
         s.set_plan(ss.SS_PLAN_FUSED)
     with pytest.raises(ss.SSError):
         s.init_skyrmion()
+    # velocity Verlet keeps the stored force on the BEC
+    s.set_integrator("vv")
+    with pytest.raises(ss.SSError):
+        s.set_vv_form("half_step")
+    s.set_vv_form("stored_force")
+    assert s.vv_form == ss.SS_VV_STORED_FORCE
+    with pytest.raises(ss.SSError):
+        s.set_vv_form(7)
     s.close()
     with pytest.raises(ss.SSError):
         ss.Batch(BEC, [(32, 32, 0.2, [1.0, 0.5, 1.0])], dtype="f64")

@@ -132,24 +132,27 @@ def test_demag_solver_converges_geometrically(ss, orc):
     assert errs[40] <= 1e-11 * abs(E_ref)
 
 
-@pytest.mark.parametrize("how", ["rk4", "vv", "gf"])
+@pytest.mark.parametrize("how", ["rk4", "vv", "vv_half", "gf"])
 def test_demag_flow_tracks_the_oracle(ss, orc, how):
     """With converged solves (30 iterations per stage point) the FP64 flow is the
     oracle's to 1e-9; the stage points of RK4 and of the one-pass integrators get
-    their own potentials."""
+    their own potentials (velocity Verlet in both of its forms: the half-step
+    form's restart and end passes reuse the potential of the field they read)."""
     Nx, Ny, h = 64, 40, 0.15
     print(f"[case] demag flow {how}", flush=True)
     f = _anti(Nx, Ny, h, seed=9)
     s = _solver(ss, Nx, Ny, h, "f64", "heusler", True)
     s.set_demag_iters(30, 40)
     if how != "rk4":
-        s.set_integrator(how)
+        s.set_integrator("vv" if how == "vv_half" else how)
+    if how == "vv_half":
+        s.set_vv_form("half_step")
     s.set_field(f)
     n = 6
     info = s.flow_step(n)
     phi, vel = (_np(x) for x in s.get_field(velocity=True))
     p = _oracle_params("heusler", True)
-    phi_r, v_r, E_r, na_r = orc.flow(CMX, f, np.zeros_like(f), h, p, n, scheme=how)
+    phi_r, v_r, E_r, na_r = orc.flow(CMX, f, np.zeros_like(f), h, p, n, scheme="vv" if how == "vv_half" else how)
     assert np.abs(phi - phi_r).max() <= 1e-9
     assert np.abs(vel - v_r).max() <= 1e-9
     assert info["step"] == n and info["n_arrests"] == na_r

@@ -43,10 +43,28 @@ def _np(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
+# integrators under test: velocity Verlet in the form its context picks (the
+# stored force on these small lattices), forced into the kick-drift-kick
+# (half-step) form, and gradient flow; the oracle's scheme of each
+INTEGS = ["vv", "vv_half", "gf"]
+
+
+def _set_integ(s, integ):
+    s.set_integrator("gf" if integ == "gf" else "vv")
+    if integ == "vv_half":
+        s.set_vv_form("half_step")
+    elif integ == "vv_stored":
+        s.set_vv_form("stored_force")
+
+
+def _scheme(integ):
+    return "gf" if integ == "gf" else "vv"
+
+
 SHAPES = [(150, 37), (64, 16), (129, 70)]
 
 
-@pytest.mark.parametrize("integ", ["vv", "gf"])
+@pytest.mark.parametrize("integ", INTEGS)
 @pytest.mark.parametrize("theory", [AH, CM])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("shape", SHAPES)
@@ -58,14 +76,16 @@ def test_one_pass_flow_tracks_the_oracle(ss, orc, integ, theory, dtype, shape):
     if dtype == "f32":
         f = f.astype(np.float32).astype(np.float64)
     s = ss.Solver(theory, Nx, Ny, h, _params(theory), dtype=dtype)
-    s.set_integrator(integ)
-    assert s.integrator == ss.INTEGRATORS[integ]
+    _set_integ(s, integ)
+    assert s.integrator == ss.INTEGRATORS[_scheme(integ)]
+    if integ != "gf":
+        assert s.vv_form == (ss.SS_VV_HALF_STEP if integ == "vv_half" else ss.SS_VV_STORED_FORCE)
     s.set_field(f)
     n = 6
     info = s.flow_step(n)
     phi, vel = s.get_field(velocity=True)
     phi, vel = _np(phi), _np(vel)
-    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), n, scheme=integ)
+    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), n, scheme=_scheme(integ))
     rel = 1e-11 if dtype == "f64" else 1e-5
     assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max()
     assert np.abs(vel - v_r).max() <= rel * max(np.abs(phi_r).max(), 1.0)
@@ -82,7 +102,7 @@ def test_one_pass_flow_tracks_the_oracle(ss, orc, integ, theory, dtype, shape):
     s.close()
 
 
-@pytest.mark.parametrize("integ", ["vv", "gf"])
+@pytest.mark.parametrize("integ", INTEGS)
 @pytest.mark.parametrize("theory", [AH, CM])
 def test_one_pass_exact_gradient_tracks_the_oracle(ss, orc, integ, theory):
     """The one-pass passes also run with the exact gradient h^-2 dE_h/dphi."""
@@ -90,11 +110,11 @@ def test_one_pass_exact_gradient_tracks_the_oracle(ss, orc, integ, theory):
     print(f"[case] one-pass exact {integ} {theory}", flush=True)
     f = _field(theory, Nx, Ny, h, seed=11)
     s = ss.Solver(theory, Nx, Ny, h, _params(theory), dtype="f64", grad_mode=ss.SS_GRAD_EXACT)
-    s.set_integrator(integ)
+    _set_integ(s, integ)
     s.set_field(f)
     info = s.flow_step(5)
     phi, vel = (_np(x) for x in s.get_field(velocity=True))
-    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), 5, scheme=integ,
+    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), 5, scheme=_scheme(integ),
                                      mode=orc.GRAD_EXACT)
     assert np.abs(phi - phi_r).max() <= 1e-11 * np.abs(phi_r).max()
     assert np.abs(vel - v_r).max() <= 1e-11 * max(np.abs(phi_r).max(), 1.0)
@@ -102,25 +122,30 @@ def test_one_pass_exact_gradient_tracks_the_oracle(ss, orc, integ, theory):
     s.close()
 
 
-def test_runs_compose_and_switch_integrators(ss, orc):
-    """Each run starts with a pass that tests the current field and forms the
-    half-step velocity u = v + dt/2 a, and ends with v = u - dt/2 a, so 3 + 4 steps
-    equal 7 steps up to the rounding of that round trip (the arrests are the
-    same), and a run of RK4 followed by velocity Verlet equals the oracle's RK4
-    then velocity Verlet."""
+@pytest.mark.parametrize("integ", ["vv", "vv_half"])
+def test_runs_compose_and_switch_integrators(ss, orc, integ):
+    """Each run starts with a pass that tests the current field and stores its
+    force, so with the stored force 3 + 4 steps equal 7 steps bit for bit; in
+    the half-step form that pass forms u = v + dt/2 a and the run ends with
+    v = u - dt/2 a, so they are equal up to the rounding of that round trip
+    (the arrests are the same). A run of RK4 followed by velocity Verlet equals
+    the oracle's RK4 then velocity Verlet."""
     Nx, Ny, h = 96, 40, 0.2
     f = _field(AH, Nx, Ny, h, seed=3)
     a = ss.Solver(AH, Nx, Ny, h, [1.0], dtype="f64")
     b = ss.Solver(AH, Nx, Ny, h, [1.0], dtype="f64")
     for s in (a, b):
-        s.set_integrator("vv")
+        _set_integ(s, integ)
         s.set_field(f)
     a.flow_step(3)
     ia = a.flow_step(4)
     ib = b.flow_step(7)
     pa, pb = _np(a.get_field()), _np(b.get_field())
-    assert np.abs(pa - pb).max() <= 1e-14 * np.abs(pb).max()
-    assert ia["energy"] == pytest.approx(ib["energy"], rel=1e-14)
+    if integ == "vv":
+        assert np.array_equal(pa, pb) and ia["energy"] == ib["energy"]
+    else:
+        assert np.abs(pa - pb).max() <= 1e-14 * np.abs(pb).max()
+        assert ia["energy"] == pytest.approx(ib["energy"], rel=1e-14)
     assert ia["n_arrests"] == ib["n_arrests"] and ia["step"] == 7
     a.set_integrator("rk4")
     a.set_field(f)
@@ -135,34 +160,34 @@ def test_runs_compose_and_switch_integrators(ss, orc):
     b.close()
 
 
-@pytest.mark.parametrize("integ", ["vv", "gf"])
+@pytest.mark.parametrize("integ", INTEGS)
 def test_one_pass_arrests_and_stops_like_the_oracle(ss, orc, integ):
     """A long FP64 run: arrests fire at the oracle's steps, and the stall and
     gradient stop rules end the run at the oracle's step."""
     Nx, Ny, h = 48, 40, 0.25
     f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.3, -0.2), (-1.1, 0.9)]) + I.noise(5, 4, Nx, Ny, 1e-3)
     s = ss.Solver(AH, Nx, Ny, h, [1.0], dtype="f64")
-    s.set_integrator(integ)
+    _set_integ(s, integ)
     s.set_field(f)
     phi_r, v_r, E, total = f, np.zeros_like(f), None, 0
     for _ in range(4):
         info = s.flow_step(50)
-        phi_r, v_r, E, na = orc.flow(AH, phi_r, v_r, h, [1.0], 50, E_cur=E, scheme=integ)
+        phi_r, v_r, E, na = orc.flow(AH, phi_r, v_r, h, [1.0], 50, E_cur=E, scheme=_scheme(integ))
         total += na
         assert info["n_arrests"] == total
     assert np.abs(_np(s.get_field()) - phi_r).max() <= 1e-10 * np.abs(phi_r).max()
-    if integ == "vv":
+    if integ != "gf":
         assert total > 0
     s.set_field(f)
     res = s.minimise(grad_tol=0.0, rel_e_tol=1e-4, window=20, max_steps=5000, graph_steps=8)
     _, _, ref = orc.minimise(AH, f, h, [1.0], grad_tol=0.0, rel_e_tol=1e-4, window=20, max_steps=5000,
-                             scheme=integ)
+                             scheme=_scheme(integ))
     assert res["reason"] == "stall" and ref["reason"] == 2
     assert res["step"] == ref["steps"] and res["n_arrests"] == ref["arrests"]
     assert res["energy"] == pytest.approx(ref["E"], rel=1e-12)
     s.set_field(f)
     res = s.minimise(grad_tol=2e-2, max_steps=5000, graph_steps=8)
-    _, _, ref = orc.minimise(AH, f, h, [1.0], grad_tol=2e-2, max_steps=5000, scheme=integ)
+    _, _, ref = orc.minimise(AH, f, h, [1.0], grad_tol=2e-2, max_steps=5000, scheme=_scheme(integ))
     assert res["reason"] == "grad" and ref["reason"] == 1 and res["step"] == ref["steps"]
     s.set_field(f)
     res = s.minimise(grad_tol=0.0, max_steps=37, graph_steps=8)
@@ -170,7 +195,7 @@ def test_one_pass_arrests_and_stops_like_the_oracle(ss, orc, integ):
     s.close()
 
 
-@pytest.mark.parametrize("integ", ["vv", "gf"])
+@pytest.mark.parametrize("integ", ["vv", "vv_stored", "gf"])
 def test_large_lattice_one_pass_step_sampled_parity(ss, orc, integ):
     """One step of the 4096^2 GL workload with a one-pass integrator, as the
     benchmark times it, on sampled windows: the oracle steps a window whose outer
@@ -180,7 +205,9 @@ def test_large_lattice_one_pass_step_sampled_parity(ss, orc, integ):
     inst = I.gl_large_instance(N, h)
     lam = I.gl_lambda_from_kappa(1.5)
     s = ss.Solver(AH, N, N, h, [lam], dtype="f32")
-    s.set_integrator(integ)
+    _set_integ(s, integ)
+    if integ == "vv":
+        assert s.vv_form == ss.SS_VV_HALF_STEP  # the form a lattice of this size picks
     s.init_vortices(inst.centres, seed=4, noise_amp=1e-3)
     f0 = s.get_field().double().cpu().numpy()
     info = s.flow_step(1)
@@ -192,7 +219,7 @@ def test_large_lattice_one_pass_step_sampled_parity(ss, orc, integ):
         ja, jb = max(j0 - M, 0), min(j0 + S + M, N)
         ia, ib = max(i0 - M, 0), min(i0 + S + M, N)
         win = np.ascontiguousarray(f0[:, ja:jb + 4, ia:ib + 4])
-        w1, wv, _, _ = orc.flow(AH, win, np.zeros_like(win), h, [lam], 1, scheme=integ)
+        w1, wv, _, _ = orc.flow(AH, win, np.zeros_like(win), h, [lam], 1, scheme=_scheme(integ))
         sl = (slice(None), slice(j0 - ja + 2, j0 - ja + S + 2), slice(i0 - ia + 2, i0 - ia + S + 2))
         got = (slice(None), slice(j0 + 2, j0 + S + 2), slice(i0 + 2, i0 + S + 2))
         assert np.abs(f1[got] - w1[sl]).max() <= 1e-5 * max(np.abs(w1[sl]).max(), 1.0), (j0, i0)
@@ -201,7 +228,7 @@ def test_large_lattice_one_pass_step_sampled_parity(ss, orc, integ):
 
 
 @pytest.mark.parametrize("integ,theory,dtype", [("vv", AH, "f32"), ("vv", AH, "f64"), ("gf", AH, "f32"),
-                                                ("vv", CM, "f32"), ("gf", CM, "f64")])
+                                                ("vv", CM, "f32"), ("gf", CM, "f64"), ("vv_stored", AH, "f32")])
 def test_one_pass_units_of_several_tiles(ss, orc, integ, theory, dtype):
     """A ragged lattice with 6174 tiles of 64 x 8 (18 x 343), over three times the
     2048 workgroups of a stage launch, so each workgroup walks units of three
@@ -214,13 +241,13 @@ def test_one_pass_units_of_several_tiles(ss, orc, integ, theory, dtype):
     if dtype == "f32":
         f = f.astype(np.float32).astype(np.float64)
     s = ss.Solver(theory, Nx, Ny, h, _params(theory), dtype=dtype)
-    s.set_integrator(integ)
+    _set_integ(s, integ)
     s.set_tile(1)
     s.set_field(f)
     n = 3
     info = s.flow_step(n)
     phi, vel = (_np(x) for x in s.get_field(velocity=True))
-    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), n, scheme=integ)
+    phi_r, v_r, E_r, na_r = orc.flow(theory, f, np.zeros_like(f), h, _params(theory), n, scheme=_scheme(integ))
     rel = 1e-11 if dtype == "f64" else 1e-5
     assert np.abs(phi - phi_r).max() <= rel * np.abs(phi_r).max()
     assert np.abs(vel - v_r).max() <= rel * max(np.abs(phi_r).max(), 1.0)
