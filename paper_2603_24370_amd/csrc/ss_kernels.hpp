@@ -508,6 +508,8 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
   T* __restrict__ phn = cur ? V.phi[0] : V.phi[1];
   T* __restrict__ vn = cur ? V.vel[0] : V.vel[1];
   T* vcur = cur ? V.vel[1] : V.vel[0];  // the velocity Verlet passes around the steps
+  // max |G| of the thread's sites in T (exact), folded into the FP64 accumulator once
+  T gmx = T(0);
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int gj = y0 + ly0 - 2 + r;
@@ -533,7 +535,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
     if (REDUCE) {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        g_acc = fmax(g_acc, fabs((double)G[c]));
+        gmx = fmax(gmx, fabs(G[c]));
         if (!isfinite(G[c])) ++nf;
       }
     }
@@ -586,6 +588,7 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
       }
     }
   }
+  if (REDUCE) g_acc = fmax(g_acc, (double)gmx);
   if (REDUCE && TH == 0) energy_density();
   __syncthreads();
 }
@@ -861,6 +864,8 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   T* __restrict__ phn = cur ? V.phi[0] : V.phi[1];
   T* __restrict__ vn = cur ? V.vel[0] : V.vel[1];
   T* vcur = cur ? V.vel[1] : V.vel[0];  // the velocity Verlet passes around the steps
+  // max |G| of the thread's sites in T (exact), folded into the FP64 accumulator once
+  T gmx = T(0);
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     const int tr = threadIdx.y * RY + r;
@@ -892,7 +897,7 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
     if (REDUCE) {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        g_acc = fmax(g_acc, fabs((double)G[c]));
+        gmx = fmax(gmx, fabs(G[c]));
         if (!isfinite(G[c])) ++nf;
       }
     }
@@ -944,6 +949,7 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
       }
     }
   }
+  if (REDUCE) g_acc = fmax(g_acc, (double)gmx);
   __syncthreads();
 }
 
@@ -1157,6 +1163,8 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
   const T c1 = T(1.0 / (12.0 * h)), c2 = T(1.0 / (12.0 * h * h));
   const int tid = threadIdx.y * TX + threadIdx.x;
   const int gi = x0 + threadIdx.x;
+  // a 64-wide tile row is one wavefront: its row index is wave-uniform
+  const int wy = (TX == 64) ? __builtin_amdgcn_readfirstlane((int)threadIdx.y) : (int)threadIdx.y;
   auto inside = [&](int x, int y) { return x >= 0 && x < Nx && y >= 0 && y < Ny; };
   // site (x, y) of the padded lattice (x, y in [-2, N + 1]) as an element offset
   auto offs = [&](int x, int y) { return (long)(y + 2) * pitch + (x + 2); };
@@ -1212,7 +1220,7 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
     double dx_[C][RY], dy_[C][RY];
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      column_jets<T, AX, RY, MIXED, false>(sa[c], 4 + threadIdx.x, 4 + threadIdx.y * RY, c1, c2, 0.0, J[c], dx_[c],
+      column_jets<T, AX, RY, MIXED, false>(sa[c], 4 + threadIdx.x, 4 + wy * RY, c1, c2, 0.0, J[c], dx_[c],
                                            dy_[c]);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -1221,8 +1229,8 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
       for (int c = 0; c < C; ++c) Js[c] = J[c][r];
       T G[4] = {T(0), T(0), T(0), T(0)};
       site_gradient<T, TH>(Js, V, G);
-      const bool in = inside(gi, y0 + threadIdx.y * RY + r);
-      const int ib = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
+      const bool in = inside(gi, y0 + wy * RY + r);
+      const int ib = (2 + wy * RY + r) * BX + 2 + threadIdx.x;
 #pragma unroll
       for (int c = 0; c < C; ++c) s2[c][ib] = in ? -G[c] : T(0);
     }
@@ -1283,7 +1291,7 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
     double dx_[C][RY], dy_[C][RY];
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      column_jets<T, AX, RY, MIXED, false>(sa[c], 4 + threadIdx.x, 4 + threadIdx.y * RY, c1, c2, 0.0, J[c], dx_[c],
+      column_jets<T, AX, RY, MIXED, false>(sa[c], 4 + threadIdx.x, 4 + wy * RY, c1, c2, 0.0, J[c], dx_[c],
                                            dy_[c]);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -1292,7 +1300,7 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
       for (int c = 0; c < C; ++c) Js[c] = J[c][r];
       T G[4] = {T(0), T(0), T(0), T(0)};
       site_gradient<T, TH>(Js, V, G);
-      const int ib = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
+      const int ib = (2 + wy * RY + r) * BX + 2 + threadIdx.x;
 #pragma unroll
       for (int c = 0; c < 4; ++c) qo[r][c] = T(0);
 #pragma unroll
@@ -1313,18 +1321,18 @@ __device__ __forceinline__ void tile_body_fused(const InstView<T>& V, int cur, b
     double dx_[C][RY], dy_[C][RY];
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      column_jets<T, AX, RY, MIXED, false>(sa[c], 4 + threadIdx.x, 4 + threadIdx.y * RY, c1, c2, 0.0, J[c], dx_[c],
+      column_jets<T, AX, RY, MIXED, false>(sa[c], 4 + threadIdx.x, 4 + wy * RY, c1, c2, 0.0, J[c], dx_[c],
                                            dy_[c]);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      const int gj = y0 + threadIdx.y * RY + r;
+      const int gj = y0 + wy * RY + r;
       if (gi >= Nx || gj >= Ny) continue;
       Jet<T> Js[4];
 #pragma unroll
       for (int c = 0; c < C; ++c) Js[c] = J[c][r];
       T G[4] = {T(0), T(0), T(0), T(0)};
       site_gradient<T, TH>(Js, V, G);
-      const int ib = (2 + threadIdx.y * RY + r) * BX + 2 + threadIdx.x;
+      const int ib = (2 + wy * RY + r) * BX + 2 + threadIdx.x;
       T pn[4], vnew[4];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
