@@ -165,6 +165,8 @@ struct ss_ctx {
     DmVecs v;
     int nlev;
     DmLevel lv[kDmMaxLevels];
+    double* cinv;  // inverse of Laplace_h on the coarsest level (cn x cn), or cn = 0
+    int cn;
   } dm;
   // BEC work buffers (theory SS_THEORY_BEC): stage point, gradient, partials, scalars
   void* bec_S;
@@ -284,27 +286,25 @@ void dm_vcycle(const ss_ctx::Demag& d, int l, const DevStatus* skip, hipStream_t
     DmHierarchy H;
     for (int k = 0; k < d.nlev; ++k) H.lv[k] = d.lv[k];
     H.nlev = d.nlev;
+    H.cinv = d.cinv;
+    H.cn = d.cn;
     hipLaunchKernelGGL(dm_vcycle_small, dim3(1), dim3(256), (unsigned)small, s, H, l, skip);
     return;
   }
-  const int g = dm_groups((long)L.Nx * L.Ny);
-  auto sweeps = [&](int n) {
-    for (int k = 0; k < n; k += 2) {
-      hipLaunchKernelGGL(dm_jacobi, dim3(g), dim3(256), 0, s, L, (const double*)L.psi, L.tmp, skip);
-      hipLaunchKernelGGL(dm_jacobi, dim3(g), dim3(256), 0, s, L, (const double*)L.tmp, L.psi, skip);
-    }
-  };
   if (l == d.nlev - 1) {
     hipLaunchKernelGGL(dm_coarse_solve, dim3(1), dim3(256), 0, s, L, skip);
     return;
   }
+  // two sweeps psi -> tmp, the residual of tmp restricted, the coarse
+  // correction, then tmp + P c smoothed by two sweeps into psi
+  static_assert(kDmSmooth == 2, "one launch smooths twice");
   const DmLevel& Cl = d.lv[l + 1];
-  sweeps(kDmSmooth);
-  hipLaunchKernelGGL(dm_residual, dim3(g), dim3(256), 0, s, L, skip);
-  hipLaunchKernelGGL(dm_restrict, dim3(dm_groups((long)Cl.Nx * Cl.Ny)), dim3(256), 0, s, L, Cl, skip);
+  const int gt = std::min(dm_tiles(L), 2048);
+  hipLaunchKernelGGL(dm_jacobi2, dim3(gt), dim3(256), 0, s, L, (const double*)L.psi, L.tmp, Cl, 0, skip);
+  hipLaunchKernelGGL(dm_restrict_res, dim3(std::min(dm_rtiles(Cl), 2048)), dim3(256), 0, s, L,
+                     (const double*)L.tmp, Cl, skip);
   dm_vcycle(d, l + 1, skip, s);
-  hipLaunchKernelGGL(dm_prolong, dim3(g), dim3(256), 0, s, Cl, L, skip);
-  sweeps(kDmSmooth);
+  hipLaunchKernelGGL(dm_jacobi2, dim3(gt), dim3(256), 0, s, L, (const double*)L.tmp, L.psi, Cl, 1, skip);
 }
 
 // Demagnetising potential of the stage point of pass PASS (Sec. 4.2, eq. (6)),
@@ -774,12 +774,62 @@ size_t demag_region(int Nx, int Ny, double h, const Layout& L, int esize, char* 
   }
   double* part = (double*)take(kDmRedGroups * sizeof(double));
   double* sc = (double*)take(8 * sizeof(double));
+  const int cn = (long)nx * ny <= kDmExactMax ? nx * ny : 0;
+  double* cinv = cn ? (double*)take((size_t)cn * cn * sizeof(double)) : nullptr;
   if (d) {
     d->nlev = nlev;
     d->v.part = part;
     d->v.sc = sc;
+    d->cinv = cinv;
+    d->cn = cn;
   }
   return off;
+}
+
+// Inverse of Laplace_h (eq. (2) along both axes, zero outside the interior) on
+// an nx x ny level of spacing h, sites numbered row-major: Gauss-Jordan
+// elimination with partial pivoting in FP64 on the host. out holds n x n, n = nx ny.
+void dm_coarse_inverse(int nx, int ny, double h, std::vector<double>& out) {
+  const int n = nx * ny;
+  std::vector<double> a((size_t)n * n, 0.0);
+  out.assign((size_t)n * n, 0.0);
+  const double w = 1.0 / (12.0 * h * h);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int m = j * nx + i;
+      a[(size_t)m * n + m] = -60.0 * w;
+      const int dj[8] = {0, 0, 0, 0, -1, 1, -2, 2}, di[8] = {-1, 1, -2, 2, 0, 0, 0, 0};
+      const double cw[8] = {16.0, 16.0, -1.0, -1.0, 16.0, 16.0, -1.0, -1.0};
+      for (int q = 0; q < 8; ++q) {
+        const int jj = j + dj[q], ii = i + di[q];
+        if (jj >= 0 && jj < ny && ii >= 0 && ii < nx) a[(size_t)m * n + jj * nx + ii] += cw[q] * w;
+      }
+      out[(size_t)m * n + m] = 1.0;
+    }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[(size_t)r * n + c]) > std::fabs(a[(size_t)piv * n + c])) piv = r;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(a[(size_t)c * n + k], a[(size_t)piv * n + k]);
+        std::swap(out[(size_t)c * n + k], out[(size_t)piv * n + k]);
+      }
+    const double inv = 1.0 / a[(size_t)c * n + c];
+    for (int k = 0; k < n; ++k) {
+      a[(size_t)c * n + k] *= inv;
+      out[(size_t)c * n + k] *= inv;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[(size_t)r * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        a[(size_t)r * n + k] -= f * a[(size_t)c * n + k];
+        out[(size_t)r * n + k] -= f * out[(size_t)c * n + k];
+      }
+    }
+  }
 }
 
 }  // namespace
@@ -867,10 +917,18 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   }
   // zero the whole workspace once: halos of velocity and stage arrays stay 0
   e = hipMemsetAsync(c->ws, 0, c->ws_total, c->stream);
+  if (e == hipSuccess && c->dm.on && c->dm.cn > 0) {
+    // the demagnetisation solver's coarsest-level inverse
+    const DmLevel& B = c->dm.lv[c->dm.nlev - 1];
+    std::vector<double> inv;
+    dm_coarse_inverse(B.Nx, B.Ny, B.h, inv);
+    e = hipMemcpyAsync(c->dm.cinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
   if (e != hipSuccess) {
     (void)hipStreamDestroy(c->cap_stream);
     delete c;
-    return fail(SS_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+    return fail(SS_EHIP, std::string("workspace set-up: ") + hipGetErrorString(e));
   }
   *out = c;
   return SS_OK;

@@ -14,8 +14,9 @@
 // eq. (2) at its spacing 2^l h with a zero halo of width two. The V-cycle is
 // symmetric, as the preconditioner of conjugate gradients must be: two weighted
 // Jacobi sweeps before and after the coarse correction, bilinear prolongation P
-// (weights 3/4 and 1/4 per axis), restriction P^T / 4, and an even number of
-// Jacobi sweeps from zero on the coarsest level. A solve runs a fixed number of
+// (weights 3/4 and 1/4 per axis), restriction P^T / 4, and on the coarsest level
+// an exact solve by its inverse (computed once on the host; up to kDmExactMax
+// sites) or else an even number of Jacobi sweeps from zero. A solve runs a fixed number of
 // iterations, warm-started from the last potential (stage points change little
 // from one pass to the next), so that it can be captured in a graph. Dot
 // products are summed per workgroup and then in workgroup order (deterministic).
@@ -29,7 +30,8 @@ constexpr int kDmMaxLevels = 20;
 constexpr int kDmRedGroups = 256;  // workgroups of the dot-product launches (one partial per thread of the sum)
 constexpr double kDmOmega = 0.8;   // Jacobi weight (stable below 15/16 for this operator)
 constexpr int kDmSmooth = 2;       // sweeps before and after the coarse correction
-constexpr int kDmCoarse = 40;      // sweeps on the coarsest level (even)
+constexpr int kDmCoarse = 40;      // sweeps on the coarsest level (even) where it has no inverse
+constexpr int kDmExactMax = 256;   // coarsest levels up to this many sites are solved exactly
 
 // One level of the hierarchy: padded planes of (Ny + 4) rows of pitch = Nx + 4 doubles.
 struct DmLevel {
@@ -68,19 +70,6 @@ __device__ __forceinline__ double dm_lap(const double* __restrict__ x, long p, i
   for (long k_ = blockIdx.x * 256L + threadIdx.x; k_ < (long)(L).Nx * (L).Ny;              \
        k_ += (long)gridDim.x * 256L)
 
-// Weighted Jacobi: dst = src - omega h^2/5 (rhs - Laplace_h src) (the operator's
-// diagonal is -5/h^2). Only interior sites are written; halos stay zero.
-__global__ void __launch_bounds__(256) dm_jacobi(DmLevel L, const double* __restrict__ src, double* __restrict__ dst,
-                                                 const DevStatus* st) {
-  if (dm_skip(st)) return;
-  const double s = kDmOmega * L.h * L.h / 5.0;
-  DM_SITES(L) {
-    const int j = (int)(k_ / L.Nx), i = (int)(k_ - (long)j * L.Nx);
-    const long o = dm_at(L, j, i);
-    dst[o] = src[o] - s * (L.rhs[o] - dm_lap(src, L.pitch, j, i, L.h));
-  }
-}
-
 // The coarsest level: kDmCoarse Jacobi sweeps (psi -> tmp -> psi ...) from the
 // zero start the restriction left, in one workgroup, with a barrier between sweeps
 // (one launch instead of kDmCoarse). Global memory is coherent within a workgroup
@@ -108,6 +97,17 @@ __device__ __forceinline__ double dm_w(int f, int J) {
   return (d == 0 || d == 1) ? 0.75 : 0.25;
 }
 
+// (P c)(j, i): the bilinear correction at fine site (j, i) from the coarse plane
+// c of level C (cell-centred positions; coarse cells outside the level count as zero).
+__device__ __forceinline__ double dm_prolong_at(const DmLevel& C, const double* __restrict__ c, int j, int i) {
+  const int J = j >> 1, I = i >> 1;
+  const int J2 = J + ((j & 1) ? 1 : -1), I2 = I + ((i & 1) ? 1 : -1);
+  auto cv = [&](int jj, int ii) -> double {
+    return (ii >= 0 && ii < C.Nx && jj >= 0 && jj < C.Ny) ? c[dm_at(C, jj, ii)] : 0.0;
+  };
+  return 0.5625 * cv(J, I) + 0.1875 * (cv(J, I2) + cv(J2, I)) + 0.0625 * cv(J2, I2);
+}
+
 // ---- the small levels of a V-cycle in one workgroup, in LDS
 // The coarse levels of a V-cycle cost a few microseconds per launch and almost
 // nothing to compute. From the first level whose planes and those of every
@@ -121,6 +121,10 @@ constexpr int kDmSmallLds = 64 * 1024;
 struct DmHierarchy {
   DmLevel lv[kDmMaxLevels];
   int nlev;
+  // inverse of Laplace_h on the coarsest level (cn x cn, row-major, sites
+  // numbered row-major over the interior), or cn = 0 for Jacobi sweeps there
+  const double* cinv;
+  int cn;
 };
 
 // LDS bytes of levels l .. nlev - 1 (three padded planes each)
@@ -204,9 +208,23 @@ __global__ void __launch_bounds__(256) dm_vcycle_small(DmHierarchy H, int l0, co
     __syncthreads();
   }
   const DmLevel B = lds_level(last);
-  for (int k = 0; k < kDmCoarse; k += 2) {
-    dm_wg_jacobi(B, B.psi, B.tmp);
-    dm_wg_jacobi(B, B.tmp, B.psi);
+  if (H.cn > 0) {
+    // the coarsest level solved exactly: psi = (Laplace_h)^-1 rhs, each row summed in site order
+    for (int k = threadIdx.x; k < H.cn; k += 256) {
+      double acc = 0.0;
+      for (int m = 0; m < H.cn; ++m) {
+        const int jm = m / B.Nx, im = m - jm * B.Nx;
+        acc += H.cinv[(long)k * H.cn + m] * B.rhs[dm_at(B, jm, im)];
+      }
+      const int jk = k / B.Nx, ik = k - jk * B.Nx;
+      B.psi[dm_at(B, jk, ik)] = acc;
+    }
+    __syncthreads();
+  } else {
+    for (int k = 0; k < kDmCoarse; k += 2) {
+      dm_wg_jacobi(B, B.psi, B.tmp);
+      dm_wg_jacobi(B, B.tmp, B.psi);
+    }
   }
   for (int l = last - 1; l >= l0; --l) {
     const DmLevel F = lds_level(l);
@@ -214,12 +232,7 @@ __global__ void __launch_bounds__(256) dm_vcycle_small(DmHierarchy H, int l0, co
     const long nf = (long)F.Nx * F.Ny;
     for (long k = threadIdx.x; k < nf; k += 256) {
       const int j = (int)(k / F.Nx), i = (int)(k - (long)j * F.Nx);
-      const int J = j >> 1, I = i >> 1;
-      const int J2 = J + ((j & 1) ? 1 : -1), I2 = I + ((i & 1) ? 1 : -1);
-      auto cv = [&](int jj, int ii) -> double {
-        return (ii >= 0 && ii < C.Nx && jj >= 0 && jj < C.Ny) ? C.psi[dm_at(C, jj, ii)] : 0.0;
-      };
-      F.psi[dm_at(F, j, i)] += 0.5625 * cv(J, I) + 0.1875 * (cv(J, I2) + cv(J2, I)) + 0.0625 * cv(J2, I2);
+      F.psi[dm_at(F, j, i)] += dm_prolong_at(C, C.psi, j, i);
     }
     __syncthreads();
     for (int k = 0; k < kDmSmooth; k += 2) {
@@ -238,45 +251,162 @@ __global__ void __launch_bounds__(256) dm_vcycle_small(DmHierarchy H, int l0, co
   }
 }
 
-// tmp = rhs - Laplace_h psi
-__global__ void __launch_bounds__(256) dm_residual(DmLevel L, const DevStatus* st) {
-  if (dm_skip(st)) return;
-  DM_SITES(L) {
-    const int j = (int)(k_ / L.Nx), i = (int)(k_ - (long)j * L.Nx);
-    const long o = dm_at(L, j, i);
-    L.tmp[o] = L.rhs[o] - dm_lap(L.psi, L.pitch, j, i, L.h);
-  }
+// ---- the large levels: three launches per level and V-cycle
+// Pre-smoothing (two sweeps, psi -> tmp), the residual restricted to the next
+// level, and prolongation with post-smoothing (tmp + P c -> psi, two sweeps).
+// Weighted Jacobi: x' = x - omega h^2/5 (rhs - Laplace_h x) (the operator's
+// diagonal is -5/h^2), on interior sites only; halos stay zero. These are the
+// same updates, in the same arithmetic, as the one-workgroup small levels and
+// the coarsest-level solve use.
+constexpr int kDmTile = 16;                // interior sites per side of a smoothing tile
+constexpr int kDmTA = kDmTile + 8;         // the input on the tile and a halo of 4
+constexpr int kDmTB = kDmTile + 4;         // after one sweep, and rhs: tile and halo 2
+constexpr int kDmCT = 8;                   // coarse sites per side of a restriction tile
+constexpr int kDmRF = 2 * kDmCT + 2;       // fine residuals it needs per side
+constexpr int kDmRP = kDmRF + 4;           // fine psi per side (residuals and a halo of 2)
+
+__host__ __device__ inline int dm_tiles(const DmLevel& L) {
+  return ((L.Nx + kDmTile - 1) / kDmTile) * ((L.Ny + kDmTile - 1) / kDmTile);
 }
 
-// Coarse right-hand side = P^T (fine residual) / 4; coarse psi = 0.
-__global__ void __launch_bounds__(256) dm_restrict(DmLevel F, DmLevel C, const DevStatus* st) {
+__host__ __device__ inline int dm_rtiles(const DmLevel& C) {
+  return ((C.Nx + kDmCT - 1) / kDmCT) * ((C.Ny + kDmCT - 1) / kDmCT);
+}
+
+// Two weighted Jacobi sweeps of level L from src into dst, through LDS: the
+// first on the tile and a ring of two (zero outside the interior, as the halo of
+// a plane is), the second on the tile. With prolong != 0 the input is
+// src + P (C.psi), the fine correction of the coarse solve. The loads of a phase
+// are unrolled so that a thread has them in flight together.
+__global__ void __launch_bounds__(256) dm_jacobi2(DmLevel L, const double* __restrict__ src, double* __restrict__ dst,
+                                                  DmLevel C, int prolong, const DevStatus* st) {
   if (dm_skip(st)) return;
-  DM_SITES(C) {
-    const int J = (int)(k_ / C.Nx), I = (int)(k_ - (long)J * C.Nx);
-    double acc = 0.0;
-    for (int j = max(2 * J - 1, 0); j <= min(2 * J + 2, F.Ny - 1); ++j) {
-      double row = 0.0;
-      for (int i = max(2 * I - 1, 0); i <= min(2 * I + 2, F.Nx - 1); ++i) row += dm_w(i, I) * F.tmp[dm_at(F, j, i)];
-      acc += dm_w(j, J) * row;
+  constexpr int NA = kDmTA * kDmTA, NB = kDmTB * kDmTB, NT = kDmTile * kDmTile;
+  __shared__ double a[NA];
+  __shared__ double b[NB];
+  __shared__ double r[NB];
+  const double s = kDmOmega * L.h * L.h / 5.0;
+  const int ntx = (L.Nx + kDmTile - 1) / kDmTile;
+  const int nt = dm_tiles(L);
+  auto inside = [&](int j, int i) { return j >= 0 && j < L.Ny && i >= 0 && i < L.Nx; };
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const int y0 = (t / ntx) * kDmTile, x0 = (t % ntx) * kDmTile;
+    double va[(NA + 255) / 256], vr[(NB + 255) / 256];
+#pragma unroll
+    for (int q = 0; q < (NA + 255) / 256; ++q) {
+      const int k = threadIdx.x + 256 * q;
+      const int ly = k / kDmTA, lx = k - ly * kDmTA;
+      const int j = y0 - 4 + ly, i = x0 - 4 + lx;
+      va[q] = (k < NA && inside(j, i)) ? src[dm_at(L, j, i)] : 0.0;
+      if (prolong && k < NA && inside(j, i)) va[q] += dm_prolong_at(C, C.psi, j, i);
     }
-    const long o = dm_at(C, J, I);
-    C.rhs[o] = 0.25 * acc;
-    C.psi[o] = 0.0;
+#pragma unroll
+    for (int q = 0; q < (NB + 255) / 256; ++q) {
+      const int k = threadIdx.x + 256 * q;
+      const int ly = k / kDmTB, lx = k - ly * kDmTB;
+      const int j = y0 - 2 + ly, i = x0 - 2 + lx;
+      vr[q] = (k < NB && inside(j, i)) ? L.rhs[dm_at(L, j, i)] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < (NA + 255) / 256; ++q) {
+      const int k = threadIdx.x + 256 * q;
+      if (k < NA) a[k] = va[q];
+    }
+#pragma unroll
+    for (int q = 0; q < (NB + 255) / 256; ++q) {
+      const int k = threadIdx.x + 256 * q;
+      if (k < NB) r[k] = vr[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (NB + 255) / 256; ++q) {
+      const int k = threadIdx.x + 256 * q;
+      if (k < NB) {
+        const int ly = k / kDmTB, lx = k - ly * kDmTB;
+        const int j = y0 - 2 + ly, i = x0 - 2 + lx;
+        double v = 0.0;
+        if (inside(j, i)) v = a[(ly + 2) * kDmTA + (lx + 2)] - s * (r[k] - dm_lap(a, kDmTA, ly, lx, L.h));
+        b[k] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (NT + 255) / 256; ++q) {
+      const int k = threadIdx.x + 256 * q;
+      const int ly = k / kDmTile, lx = k - ly * kDmTile;
+      const int j = y0 + ly, i = x0 + lx;
+      if (k < NT && inside(j, i)) {
+        const int o = (ly + 2) * kDmTB + (lx + 2);
+        dst[dm_at(L, j, i)] = b[o] - s * (r[o] - dm_lap(b, kDmTB, ly, lx, L.h));
+      }
+    }
+    __syncthreads();
   }
 }
 
-// Fine psi += P (coarse psi): bilinear in cell-centred positions; coarse cells
-// outside the level count as zero.
-__global__ void __launch_bounds__(256) dm_prolong(DmLevel C, DmLevel F, const DevStatus* st) {
+// Coarse rhs = P^T (rhs - Laplace_h psi) / 4 on a tile of coarse sites, with the
+// fine residuals it needs formed once in LDS (zero outside the fine interior,
+// where the restriction gives them no weight); coarse psi = 0.
+__global__ void __launch_bounds__(256) dm_restrict_res(DmLevel F, const double* __restrict__ psi, DmLevel C,
+                                                       const DevStatus* st) {
   if (dm_skip(st)) return;
-  DM_SITES(F) {
-    const int j = (int)(k_ / F.Nx), i = (int)(k_ - (long)j * F.Nx);
-    const int J = j >> 1, I = i >> 1;
-    const int J2 = J + ((j & 1) ? 1 : -1), I2 = I + ((i & 1) ? 1 : -1);
-    auto cv = [&](int jj, int ii) -> double {
-      return (ii >= 0 && ii < C.Nx && jj >= 0 && jj < C.Ny) ? C.psi[dm_at(C, jj, ii)] : 0.0;
-    };
-    F.psi[dm_at(F, j, i)] += 0.5625 * cv(J, I) + 0.1875 * (cv(J, I2) + cv(J2, I)) + 0.0625 * cv(J2, I2);
+  constexpr int NP = kDmRP * kDmRP, NR = kDmRF * kDmRF, NC = kDmCT * kDmCT;
+  __shared__ double x[NP];
+  __shared__ double res[NR];
+  const int ntx = (C.Nx + kDmCT - 1) / kDmCT;
+  const int nt = dm_rtiles(C);
+  auto inside = [&](int j, int i) { return j >= 0 && j < F.Ny && i >= 0 && i < F.Nx; };
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const int Y0 = (t / ntx) * kDmCT, X0 = (t % ntx) * kDmCT;
+    // fine residual rows and columns 2*Y0 - 1 .. 2*Y0 + 2*kDmCT
+    const int fy0 = 2 * Y0 - 1, fx0 = 2 * X0 - 1;
+    double vx[(NP + 255) / 256], vb[(NR + 255) / 256];
+#pragma unroll
+    for (int q = 0; q < (NP + 255) / 256; ++q) {
+      const int k = threadIdx.x + 256 * q;
+      const int ly = k / kDmRP, lx = k - ly * kDmRP;
+      const int j = fy0 - 2 + ly, i = fx0 - 2 + lx;
+      vx[q] = (k < NP && inside(j, i)) ? psi[dm_at(F, j, i)] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < (NR + 255) / 256; ++q) {
+      const int k = threadIdx.x + 256 * q;
+      const int ly = k / kDmRF, lx = k - ly * kDmRF;
+      const int j = fy0 + ly, i = fx0 + lx;
+      vb[q] = (k < NR && inside(j, i)) ? F.rhs[dm_at(F, j, i)] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < (NP + 255) / 256; ++q) {
+      const int k = threadIdx.x + 256 * q;
+      if (k < NP) x[k] = vx[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (NR + 255) / 256; ++q) {
+      const int k = threadIdx.x + 256 * q;
+      if (k < NR) {
+        const int ly = k / kDmRF, lx = k - ly * kDmRF;
+        res[k] = inside(fy0 + ly, fx0 + lx) ? vb[q] - dm_lap(x, kDmRP, ly, lx, F.h) : 0.0;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < NC) {
+      const int cy = threadIdx.x / kDmCT, cx = threadIdx.x - cy * kDmCT;
+      const int J = Y0 + cy, I = X0 + cx;
+      if (J < C.Ny && I < C.Nx) {
+        double acc = 0.0;
+        for (int j = max(2 * J - 1, 0); j <= min(2 * J + 2, F.Ny - 1); ++j) {
+          double row = 0.0;
+          for (int i = max(2 * I - 1, 0); i <= min(2 * I + 2, F.Nx - 1); ++i)
+            row += dm_w(i, I) * res[(j - fy0) * kDmRF + (i - fx0)];
+          acc += dm_w(j, J) * row;
+        }
+        const long o = dm_at(C, J, I);
+        C.rhs[o] = 0.25 * acc;
+        C.psi[o] = 0.0;
+      }
+    }
+    __syncthreads();
   }
 }
 
