@@ -326,12 +326,11 @@ void demag_solve(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   for (int it = 0; it < iters; ++it) {
     const int first = it == 0 ? 1 : 0;
     dm_vcycle(d, 0, skip, s);
+    // r.z partials; beta and the direction; Ad with the d.Ad partials; alpha and the update
     hipLaunchKernelGGL(dm_dot, dim3(kDmRedGroups), dim3(256), 0, s, L0, (const double*)d.v.r, (const double*)L0.psi,
                        d.v.part, skip);
-    hipLaunchKernelGGL(dm_beta, dim3(1), dim3(256), 0, s, (const double*)d.v.part, d.v.sc, first, skip);
     hipLaunchKernelGGL(dm_dir, dim3(g), dim3(256), 0, s, L0, d.v, first, skip);
     hipLaunchKernelGGL(dm_matvec, dim3(kDmRedGroups), dim3(256), 0, s, L0, d.v, skip);
-    hipLaunchKernelGGL(dm_alpha, dim3(1), dim3(256), 0, s, d.v, skip);
     hipLaunchKernelGGL(dm_update, dim3(g), dim3(256), 0, s, L0, d.v, skip);
   }
 }
@@ -773,12 +772,14 @@ size_t demag_region(int Nx, int Ny, double h, const Layout& L, int esize, char* 
     hl *= 2.0;
   }
   double* part = (double*)take(kDmRedGroups * sizeof(double));
+  double* pmv = (double*)take(kDmRedGroups * sizeof(double));
   double* sc = (double*)take(8 * sizeof(double));
   const int cn = (long)nx * ny <= kDmExactMax ? nx * ny : 0;
   double* cinv = cn ? (double*)take((size_t)cn * cn * sizeof(double)) : nullptr;
   if (d) {
     d->nlev = nlev;
     d->v.part = part;
+    d->v.pmv = pmv;
     d->v.sc = sc;
     d->cinv = cinv;
     d->cn = cn;

@@ -50,8 +50,9 @@ struct DmVecs {
   double* r;
   double* d;
   double* Ad;
-  double* part;
-  double* sc;
+  double* part;  // kDmRedGroups partials of r.z
+  double* pmv;   // kDmRedGroups partials of d.Ad
+  double* sc;    // {r.z of the last iteration, beta, alpha, d.Ad}
 };
 
 __device__ __forceinline__ bool dm_skip(const DevStatus* st) { return st != nullptr && st->done != 0; }
@@ -456,22 +457,16 @@ __global__ void __launch_bounds__(256) dm_dot(DmLevel L0, const double* __restri
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// rz = sum of the partials; beta = rz / rz_previous (0 on the first iteration or
-// once rz_previous is 0).
-__global__ void __launch_bounds__(256) dm_beta(const double* __restrict__ part, double* sc, int first,
-                                               const DevStatus* st) {
-  if (dm_skip(st)) return;
-  __shared__ double red[4];
-  const double rz = dm_block_sum(part[threadIdx.x], red);  // kDmRedGroups == 256 partials
-  if (threadIdx.x != 0) return;
-  sc[1] = (first || sc[0] == 0.0) ? 0.0 : rz / sc[0];
-  sc[0] = rz;
-}
-
-// d = z (first iteration) or z + beta d
+// d = z (first iteration) or z + beta d, with beta = r.z / (r.z of the last
+// iteration) (0 on the first iteration or once that is 0). Every workgroup sums
+// the r.z partials itself, in the same fixed order, so no launch of its own is
+// needed for the scalar.
 __global__ void __launch_bounds__(256) dm_dir(DmLevel L0, DmVecs D, int first, const DevStatus* st) {
   if (dm_skip(st)) return;
-  const double beta = D.sc[1];
+  __shared__ double red[4];
+  const double rz = dm_block_sum(D.part[threadIdx.x], red);  // kDmRedGroups == 256 partials
+  const double beta = (first || D.sc[0] == 0.0) ? 0.0 : rz / D.sc[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) D.sc[1] = beta;
   DM_SITES(L0) {
     const int j = (int)(k_ / L0.Nx), i = (int)(k_ - (long)j * L0.Nx);
     const long o = dm_at(L0, j, i);
@@ -479,7 +474,7 @@ __global__ void __launch_bounds__(256) dm_dir(DmLevel L0, DmVecs D, int first, c
   }
 }
 
-// Ad = -Laplace_h d and part[block] = sum of d . Ad over the block's sites
+// Ad = -Laplace_h d and pmv[block] = sum of d . Ad over the block's sites
 __global__ void __launch_bounds__(256) dm_matvec(DmLevel L0, DmVecs D, const DevStatus* st) {
   if (dm_skip(st)) return;
   __shared__ double red[4];
@@ -492,23 +487,24 @@ __global__ void __launch_bounds__(256) dm_matvec(DmLevel L0, DmVecs D, const Dev
     acc += D.d[o] * ad;
   }
   const double s = dm_block_sum(acc, red);
-  if (threadIdx.x == 0) D.part[blockIdx.x] = s;
+  if (threadIdx.x == 0) D.pmv[blockIdx.x] = s;
 }
 
-// alpha = r.z / d.Ad (0 once d.Ad is 0: the residual has vanished)
-__global__ void __launch_bounds__(256) dm_alpha(DmVecs D, const DevStatus* st) {
-  if (dm_skip(st)) return;
-  __shared__ double red[4];
-  const double dad = dm_block_sum(D.part[threadIdx.x], red);
-  if (threadIdx.x != 0) return;
-  D.sc[3] = dad;
-  D.sc[2] = dad > 0.0 ? D.sc[0] / dad : 0.0;
-}
-
-// x += alpha d, r -= alpha Ad, and the next V-cycle's input (rhs = -r, psi = 0)
+// alpha = r.z / d.Ad (0 once d.Ad is 0: the residual has vanished), summed by
+// every workgroup from the partials in fixed order; then x += alpha d,
+// r -= alpha Ad, and the next V-cycle's input (rhs = -r, psi = 0). Workgroup 0
+// keeps r.z for the next iteration's beta.
 __global__ void __launch_bounds__(256) dm_update(DmLevel L0, DmVecs D, const DevStatus* st) {
   if (dm_skip(st)) return;
-  const double alpha = D.sc[2];
+  __shared__ double red[4], red2[4];
+  const double rz = dm_block_sum(D.part[threadIdx.x], red);
+  const double dad = dm_block_sum(D.pmv[threadIdx.x], red2);
+  const double alpha = dad > 0.0 ? rz / dad : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    D.sc[0] = rz;
+    D.sc[2] = alpha;
+    D.sc[3] = dad;
+  }
   DM_SITES(L0) {
     const int j = (int)(k_ / L0.Nx), i = (int)(k_ - (long)j * L0.Nx);
     const long o = dm_at(L0, j, i);
