@@ -122,9 +122,10 @@ Layout make_layout(int C, int Nx, int Ny, int esize) {
 // BEC work region (after the flow's buffers): stage point and gradient sets,
 // kBecGroups * 4 partials and eight scalars. With base == nullptr only the size.
 size_t bec_region(const Layout& L, char* base, void** ptrs) {
-  const size_t sizes[4] = {L.set_bytes, L.set_bytes, (size_t)round_up(kBecGroups * 4 * 8, 256), 256};
+  const size_t sizes[6] = {L.set_bytes, L.set_bytes, (size_t)round_up(kBecGroups * 4 * 8, 256), 256,
+                           (size_t)round_up(kBecGroups * 8, 256), (size_t)round_up(kBecGroups * 4 * 8, 256)};
   size_t off = 0;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 6; ++k) {
     if (ptrs) ptrs[k] = base + off;
     off += sizes[k];
   }
@@ -173,6 +174,8 @@ struct ss_ctx {
   void* bec_G;
   double* bec_part;
   double* bec_sc;
+  double* bec_ps;  // stage-point norm partials
+  double* bec_pg;  // gradient-sum partials
 };
 
 namespace {
@@ -336,10 +339,10 @@ void demag_solve(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
 }
 
 // A BEC pass (RK4 stages, the one-pass steps, the check, the prime pass and the
-// evaluation): the stage point and its norm, its scale to the atom number, G and
-// the sums for mu, mu, the force and the pass's update; P4 ends with the step's
-// constraint, velocity Verlet with the projection of v', a reducing pass with the
-// status update.
+// evaluation) in three launches: the stage point and its norm partials; its scale
+// to the atom number, G and the partials for mu; mu, the force and the pass's
+// update. P4 ends with the step's constraint, velocity Verlet with the projection
+// of v', a reducing pass with the status update.
 template <class T, int PASS>
 void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   BecBufs<T> W;
@@ -347,12 +350,11 @@ void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   W.G = (T*)c->bec_G;
   W.part = c->bec_part;
   W.sc = c->bec_sc;
-  const int flow = PASS == kEval ? 0 : 1;
+  W.ps = c->bec_ps;
+  W.pg = c->bec_pg;
   const dim3 g(kBecGroups), b(256), b1(256);
   hipLaunchKernelGGL((bec_stage<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, a.src, W);
-  hipLaunchKernelGGL(bec_scale, dim3(1), b1, 0, s, (const double*)W.part, W.sc, a.cf, (const DevStatus*)c->st, flow);
-  hipLaunchKernelGGL((bec_grad<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, W, (const double*)W.sc);
-  hipLaunchKernelGGL(bec_mu, dim3(1), b1, 0, s, (const double*)W.part, W.sc, a.cf, (const DevStatus*)c->st, flow);
+  hipLaunchKernelGGL((bec_grad<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, W);
   hipLaunchKernelGGL((bec_apply<T, PASS>), g, b, 0, s, a.B, a.cf, (const DevStatus*)c->st, W, (const double*)W.sc,
                      a.out, a.out_pitch, a.out_plane);
   if constexpr (PASS == kP4 || PASS == kVVA) {
@@ -896,14 +898,16 @@ int ss_create(const char* theory, int Nx, int Ny, double h, const ss_params* par
   c->ws_total = need;
   std::memset(&c->dm, 0, sizeof(c->dm));
   c->bec_S = c->bec_G = nullptr;
-  c->bec_part = c->bec_sc = nullptr;
+  c->bec_part = c->bec_sc = c->bec_ps = c->bec_pg = nullptr;
   if (th == SS_THEORY_BEC) {
-    void* ptrs[4];
+    void* ptrs[6];
     bec_region(c->L, c->ws + c->L.total, ptrs);
     c->bec_S = (char*)ptrs[0] + c->L.col0 * esize_of(dtype);
     c->bec_G = (char*)ptrs[1] + c->L.col0 * esize_of(dtype);
     c->bec_part = (double*)ptrs[2];
     c->bec_sc = (double*)ptrs[3];
+    c->bec_ps = (double*)ptrs[4];
+    c->bec_pg = (double*)ptrs[5];
   }
   if (pb.demag) {
     c->dm.on = 1;

@@ -13,9 +13,10 @@
 // mu = <psi, G> / <psi, psi> (its projection on the tangent space of that
 // sphere), and after each step the field is scaled to N and the velocity
 // projected on the tangent space. Both need sums over the whole lattice, so a
-// stage is five launches: the stage point and its norm, the scale, G and the
-// sums of psi.G and psi.psi, mu, and the pass's own update. All sums are FP64
-// per-workgroup partials added in workgroup order.
+// stage is three launches: the stage point and the partials of its norm; the
+// scale and G with the partials of psi.G and psi.psi; mu and the pass's own
+// update. All sums are FP64 per-workgroup partials added in workgroup order, by
+// every workgroup of the launch that needs the total.
 #pragma once
 
 #include "ss_internal.hpp"
@@ -25,14 +26,20 @@ namespace ss {
 constexpr int kBecGroups = 512;  // workgroups of every BEC launch (grid-stride over sites)
 
 // Work buffers: the stage point S and the gradient G (two planes each, the flow's
-// layout), kBecGroups * 4 FP64 partials, and the scalars of a stage
-// {c (scale to N), mu, E h^2, non-finite count, c' (end of step), m (velocity projection)}.
+// layout), three sets of FP64 workgroup partials (the stage point's norm,
+// kBecGroups; the gradient's sums and the update's, kBecGroups * 4 each), and the
+// scalars of a stage {c (scale to N), mu, E h^2, non-finite count, c' (end of
+// step), m (velocity projection)}. The scale c and mu are summed from their
+// partials by every workgroup of the launch that uses them (in the same fixed
+// order), workgroup 0 keeping them in sc for the launches after.
 template <class T>
 struct BecBufs {
   T* S;
   T* G;
-  double* part;
+  double* part;  // partials of the update (bec_apply)
   double* sc;
+  double* ps;    // partials of the stage point's norm (bec_stage)
+  double* pg;    // partials of the gradient's sums (bec_grad)
 };
 
 #define BEC_SITES(n) for (long k_ = blockIdx.x * 256L + threadIdx.x; k_ < (n); k_ += (long)gridDim.x * 256L)
@@ -106,16 +113,14 @@ __global__ void __launch_bounds__(256) bec_stage(Bufs<T> B, Coeffs cf, const Dev
     }
   }
   const double s = bec_block_sum(acc, red);
-  if (threadIdx.x == 0) W.part[blockIdx.x] = s;
+  if (threadIdx.x == 0) W.ps[blockIdx.x] = s;
 }
 
-// c = sqrt(N / (h^2 sum S^2)): the scale of the stage point onto the sphere of atom number N.
-__global__ void __launch_bounds__(256) bec_scale(const double* __restrict__ part, double* sc, Coeffs cf,
-                                                 const DevStatus* __restrict__ st, int flow) {
-  if (flow && st->done) return;
-  __shared__ double red[4];
-  const double s = bec_partials_sum(part, 1, 0, red);
-  if (threadIdx.x == 0) sc[0] = sqrt(cf.p[2] / (cf.h * cf.h * s));
+// c = sqrt(N / (h^2 sum S^2)): the scale of the stage point onto the sphere of
+// atom number N, from the stage partials (every thread of the workgroup).
+__device__ __forceinline__ double bec_scale_of(const double* __restrict__ ps, const Coeffs& cf, double* red) {
+  const double s = bec_partials_sum(ps, 1, 0, red);
+  return sqrt(cf.p[2] / (cf.h * cf.h * s));
 }
 
 // Value of the scaled stage point at padded (jj, ii): c S inside the interior, S on the halo.
@@ -131,11 +136,13 @@ __device__ __forceinline__ T bec_at(const T* __restrict__ S, long pitch, int Nx,
 // RK4; the scaled stage point, which becomes the new field, for a one-pass step.
 template <class T, int PASS>
 __global__ void __launch_bounds__(256) bec_grad(Bufs<T> B, Coeffs cf, const DevStatus* __restrict__ st,
-                                                BecBufs<T> W, const double* __restrict__ sc) {
+                                                BecBufs<T> W) {
   if (PASS != kEval && st->done) return;
   __shared__ double red[4];
   constexpr bool REDUCE = reduces(PASS);
-  const T c = (T)sc[0];
+  const double cd = bec_scale_of(W.ps, cf, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) W.sc[0] = cd;
+  const T c = (T)cd;
   const T g = (T)cf.p[0], Om = (T)cf.p[1];
   const double h = cf.h;
   const T c1 = T(1.0 / (12.0 * h)), c2 = T(1.0 / (12.0 * h * h));
@@ -192,7 +199,7 @@ __global__ void __launch_bounds__(256) bec_grad(Bufs<T> B, Coeffs cf, const DevS
   const double a2 = bec_block_sum(se, red);
   const double a3 = bec_block_sum(nf, red);
   if (threadIdx.x == 0) {
-    double* p = W.part + 4 * (long)blockIdx.x;
+    double* p = W.pg + 4 * (long)blockIdx.x;
     p[0] = a0;
     p[1] = a1;
     p[2] = a2;
@@ -200,20 +207,21 @@ __global__ void __launch_bounds__(256) bec_grad(Bufs<T> B, Coeffs cf, const DevS
   }
 }
 
-// mu = <psi, G> / <psi, psi>, E h^2 and the non-finite count of the stage.
-__global__ void __launch_bounds__(256) bec_mu(const double* __restrict__ part, double* sc, Coeffs cf,
-                                              const DevStatus* __restrict__ st, int flow) {
-  if (flow && st->done) return;
-  __shared__ double red[4];
-  const double sG = bec_partials_sum(part, 4, 0, red);
-  const double ss = bec_partials_sum(part, 4, 1, red);
-  const double se = bec_partials_sum(part, 4, 2, red);
-  const double nf = bec_partials_sum(part, 4, 3, red);
-  if (threadIdx.x == 0) {
+// mu = <psi, G> / <psi, psi> from the gradient partials (every thread of the
+// workgroup); workgroup 0 also keeps mu, E h^2 and the non-finite count of the
+// stage in sc[1..3].
+__device__ __forceinline__ double bec_mu_of(const double* __restrict__ pg, double* sc, const Coeffs& cf,
+                                            double* red) {
+  const double sG = bec_partials_sum(pg, 4, 0, red);
+  const double ss = bec_partials_sum(pg, 4, 1, red);
+  const double se = bec_partials_sum(pg, 4, 2, red);
+  const double nf = bec_partials_sum(pg, 4, 3, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[1] = sG / ss;
     sc[2] = cf.h * cf.h * se;
     sc[3] = nf;
   }
+  return sG / ss;
 }
 
 // The force a = -(G - mu psi) at the scaled stage point and the pass's update; a
@@ -230,7 +238,8 @@ __global__ void __launch_bounds__(256) bec_apply(Bufs<T> B, Coeffs cf, const Dev
   const long long step = st->step;
   const int cur = STAGED ? int((step - 1) & 1) : int(step & 1);
   const bool arrest = (STAGED || PASS == kVVA) ? (st->arrest != 0) : false;
-  const T c = (T)sc[0], mu = (T)sc[1];
+  const T mu = (T)bec_mu_of(W.pg, W.sc, cf, red);
+  const T c = (T)sc[0];
   // one-pass integrators: current force (read) and new force (written) by parity
   const T* __restrict__ a_cur = cur ? B.a2 : B.a1;
   T* __restrict__ a_new = cur ? B.a1 : B.a2;
