@@ -687,6 +687,8 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   const T c1 = T(1.0 / (12.0 * h));
   const double d1 = 1.0 / (12.0 * h);
   const int tid = threadIdx.y * TX + threadIdx.x;
+  // a 64-wide tile row is one wavefront: its row index is wave-uniform
+  const int wy = (TX == 64) ? __builtin_amdgcn_readfirstlane((int)threadIdx.y) : (int)threadIdx.y;
   const int gi = x0 + threadIdx.x;
 
   auto stage_at = [&](int gi_, int gj_, T (&raw_p)[4], T (&raw_v)[4], T (&raw_a)[4], T (&S)[4]) {
@@ -720,7 +722,7 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   T rp[RY][4], rv[RY][4], ra[RY][4], so[RY][4];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    const int ly = 4 + threadIdx.y * RY + r;
+    const int ly = 4 + wy * RY + r;
     stage_at(gi, y0 + ly - 4, rp[r], rv[r], ra[r], so[r]);
     // the stored-force step keeps w = v0 + dt/2 a in rv (the epilogue's u)
     if (PASS == kVVA) {
@@ -753,7 +755,7 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   if (REDUCE) {
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      const int ly = 4 + threadIdx.y * RY + r, lx = 4 + threadIdx.x;
+      const int ly = 4 + wy * RY + r, lx = 4 + threadIdx.x;
       const int gj = y0 + ly - 4;
       if (gi < Nx && gj < Ny) {
         Jet<double> Jd[4];
@@ -791,7 +793,7 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   T g[RY][4], cen[RY][4];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    const int ly = 4 + threadIdx.y * RY + r, lx = 4 + threadIdx.x;
+    const int ly = 4 + wy * RY + r, lx = 4 + threadIdx.x;
     const int o = ly * LX + lx;
     T dx[4], dy[4];
 #pragma unroll
@@ -868,7 +870,7 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
   T gmx = T(0);
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    const int tr = threadIdx.y * RY + r;
+    const int tr = wy * RY + r;
     const int gj = y0 + tr;
     if (gi >= Nx || gj >= Ny) continue;
     T dfx[3], dfy[3];
