@@ -162,15 +162,18 @@ def other_theory_bytes(name, wl, demag_iters=2, nlev=1, half_step=False):
         a' (6 x 3 x 4 B; in the half-step form phi and u in and out, 4 x 3 x 4 B); the
         solve forms the stage point (reads 3 sets, writes one: 48 B; half-step form
         2 and one, 36 B), starts conjugate gradients (reads S_1, S_2 and x, writes r,
-        rhs, psi: 40 B) and per iteration moves about 312 B on the lattice (V-cycle
-        144 B, the coarser levels a third of that, the conjugate-gradient kernels 120 B);
+        rhs, psi: 40 B) and per iteration moves about 210 B on the lattice (the V-cycle's
+        three launches on level 0 70 B: pre-smoothing reads psi and rhs and writes tmp,
+        the restriction reads tmp and rhs, post-smoothing reads tmp, rhs and the coarse
+        correction and writes psi; the coarser levels a third of that; the
+        conjugate-gradient kernels 120 B);
       bec256, RK4 with the atom-number constraint: stage points 104 B, gradients 64 B,
         forces and updates 152 B, the end-of-step scaling 32 B (two components);
       bs512, velocity Verlet: 6 x 3 x 4 B (half-step form 4 x 3 x 4 B).
     The half-step form's restart pass after an arrest (reads phi, writes u) is not
     counted."""
     if name == "heusler_demag512":
-        return (48 + 36 if half_step else 72 + 48) + 40 + demag_iters * 312
+        return (48 + 36 if half_step else 72 + 48) + 40 + demag_iters * 210
     if name == "bec256":
         return 352
     return 48 if half_step else 72

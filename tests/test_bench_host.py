@@ -71,5 +71,5 @@ def test_other_theory_step_models():
     assert bench.other_theory_bytes("bs512", {}) == 72
     assert bench.other_theory_bytes("bs512", {}, half_step=True) == 48
     assert bench.other_theory_bytes("bec256", {}) == 352
-    assert bench.other_theory_bytes("heusler_demag512", {}, demag_iters=2) == 72 + 48 + 40 + 2 * 312
-    assert bench.other_theory_bytes("heusler_demag512", {}, demag_iters=2, half_step=True) == 48 + 36 + 40 + 2 * 312
+    assert bench.other_theory_bytes("heusler_demag512", {}, demag_iters=2) == 72 + 48 + 40 + 2 * 210
+    assert bench.other_theory_bytes("heusler_demag512", {}, demag_iters=2, half_step=True) == 48 + 36 + 40 + 2 * 210
