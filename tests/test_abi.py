@@ -164,3 +164,14 @@ def test_workspace_for_demagnetisation_and_dmi_options(L):
     assert _wsf("CM", [1, 1, 2, 0, 1.0], [0, 0, 1, 0])[0] == -1  # ni > 3
     assert _wsf("CM", [1, 1, 2, 0], [0, 2])[0] == -1          # unknown dmi_kind
     assert L.ss_set_demag_iters(None, 2, 40) == -1
+
+
+def test_integrator_and_form_calls_validate_their_arguments(L):
+    """The integrator and velocity Verlet form calls refuse a null context on the
+    host, before any device work."""
+    assert L.ss_set_integrator(None, ss.SS_INTEG_VV) == -1
+    assert L.ss_get_integrator(None) == -1
+    assert L.ss_set_vv_form(None, ss.SS_VV_HALF_STEP) == -1
+    assert L.ss_get_vv_form(None) == -1
+    assert (ss.SS_VV_AUTO, ss.SS_VV_STORED_FORCE, ss.SS_VV_HALF_STEP) == (0, 1, 2)
+    assert set(ss.VV_FORMS) == {"auto", "stored_force", "half_step"}
