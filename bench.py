@@ -41,9 +41,10 @@ HBM_PEAK_GBS = 8000.0
 #   GF (gradient flow, one pass) reads phi, a, writes phi', a'.
 # field sets (C components of one lattice) read and written per launch; velocity
 # Verlet in kick-drift-kick form (VV) reads phi and u and writes phi' and u', in
-# its stored-force form (VVA) reads phi, v, a and writes phi', v', a'
+# its stored-force form (VVA) reads phi, v, a and writes phi', v', a'; gradient
+# flow on the lattice theories (GF) reads phi and writes phi'
 PASS_SETS = {"P1": (1, 1), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "P234": (3, 2), "VV": (2, 2), "VVA": (3, 3),
-             "GF": (2, 2)}
+             "GF": (1, 1)}
 STEP_SETS = 17          # separate stage passes
 STEP_SETS_FUSED = 7     # P1 + fused stages 2-4
 PLAN_NAMES = ["stages", "fused"]

@@ -399,13 +399,18 @@ int ss_get_plan(ss_ctx* ctx);
  *                 step after an arrest (v = 0) is preceded by a pass that sets
  *                 u = dt/2 a from the field;
  *   SS_INTEG_GF   gradient flow phi' = phi + tau a with tau = dt^2/2 (the step
- *                 velocity Verlet takes from rest), one pass reading phi and a,
- *                 writing phi' and a' (4 field sets); no velocity, no arrest.
- * dt = C h as for RK4. Every run of a one-pass integrator (ss_flow_step,
- * ss_minimise) begins with one pass that tests the current field and stores
- * its force (kick-drift-kick: forms u) and ends with the velocity of the last
- * field (0 after an arrest; kick-drift-kick: v = u - dt/2 a), so between runs
- * the velocity buffer holds v. Chiral magnet: phi' is normalised
+ *                 velocity Verlet takes from rest); no velocity, no arrest. On
+ *                 the lattice theories one pass per step reads phi, tests it
+ *                 (E_h, max |G|, stop rules) and writes phi' (2 field sets), the
+ *                 step counter advancing after the test as after RK4's first
+ *                 stage; the BEC's pass reads phi and the stored force a and
+ *                 writes phi' and a' (4 sets).
+ * dt = C h as for RK4. Every run of velocity Verlet (ss_flow_step, ss_minimise)
+ * begins with one pass that tests the current field and stores its force
+ * (kick-drift-kick: forms u) and ends with the velocity of the last field (0
+ * after an arrest; kick-drift-kick: v = u - dt/2 a), so between runs the
+ * velocity buffer holds v; an ss_flow_step run of gradient flow ends, as RK4's
+ * does, with a pass that tests the last field. Chiral magnet: phi' is normalised
  * before its force is taken and v' is projected on its tangent plane.
  * Batches: ss_batch_set_integrator. Synchronises. */
 #define SS_INTEG_RK4 0

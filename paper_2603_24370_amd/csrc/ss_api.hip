@@ -254,7 +254,7 @@ template <class T, int TH, int PASS, int CFG>
 int launch_cfg(const PassArgs<T>& a, int nlaunch, hipStream_t s) {
   constexpr TileCfg tc = kTiles[CFG];
   PassArgs<T> b = a;
-  if constexpr (PASS == kP1 || PASS == kPrime || advances_first(PASS) || vv_in_place(PASS)) {
+  if constexpr (PASS == kP1 || PASS == kPrime || advances_first(PASS) || fixed_tile(PASS) || PASS == kGD) {
     const long r = resident_groups<T, TH, PASS, tc.TX, tc.TY, tc.RY>();
     if (nlaunch > r) {
       nlaunch = (int)r;
@@ -374,7 +374,7 @@ void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
 // demagnetisation the pass is preceded by the solve for its stage point.
 template <class T, int PASS>
 void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
-  if constexpr (!vv_in_place(PASS)) {
+  if constexpr (!fixed_tile(PASS) && PASS != kGD) {
     if (c->theory == SS_THEORY_BEC) {
       bec_pass<T, PASS>(c, a, s);
       return;
@@ -392,7 +392,7 @@ void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
       hipLaunchKernelGGL((stage_pass_exact<T, kCM, PASS>), dim3(groups), dim3(kExTX, kExTY / kExRY), 0, s, a);
     else
       hipLaunchKernelGGL((stage_pass_exact<T, kBS, PASS>), dim3(groups), dim3(kExTX, kExTY / kExRY), 0, s, a);
-  } else if constexpr (vv_in_place(PASS)) {
+  } else if constexpr (fixed_tile(PASS)) {
     // once per run, or after an arrest: one tile shape (64 x 16) whatever the
     // context's tile
     PassArgs<T> b = a;
@@ -480,6 +480,9 @@ bool vv_kdk_form(const ss_ctx* c) {
   return (long)c->Nx * c->Ny >= kKdkMinSites;
 }
 bool vv_kdk(const ss_ctx* c) { return c->integ == SS_INTEG_VV && vv_kdk_form(c); }
+// Gradient flow keeping only the field (the lattice theories; the BEC keeps the
+// force of the current field between steps).
+bool gd_form(const ss_ctx* c) { return c->integ == SS_INTEG_GF && c->theory != SS_THEORY_BEC; }
 
 template <class T>
 void enqueue_steps(const ss_ctx* c, int n, hipStream_t s) {
@@ -488,7 +491,9 @@ void enqueue_steps(const ss_ctx* c, int n, hipStream_t s) {
     // one pass (and its finalise) per step; velocity Verlet's restart pass
     // before it returns at once unless the last step was arrested
     for (int k = 0; k < n; ++k) {
-      if (c->integ == SS_INTEG_GF) {
+      if (gd_form(c)) {
+        launch_pass<T, kGD>(c, a, s);
+      } else if (c->integ == SS_INTEG_GF) {
         launch_pass<T, kGF>(c, a, s);
       } else if (vv_kdk(c)) {
         launch_pass<T, kVVRestart>(c, a, s);
@@ -532,6 +537,7 @@ void enqueue_check_any(const ss_ctx* c, hipStream_t s) {
 // (as a check pass) and its force stored in the buffer of the step's parity, or
 // for velocity Verlet in kick-drift-kick form u = v + dt/2 a in place of v.
 void enqueue_prime_any(const ss_ctx* c, hipStream_t s) {
+  if (gd_form(c)) return;  // its first step tests the current field
   if (vv_kdk(c)) {
     if (c->dtype == SS_F32) launch_pass<float, kVVStart>(c, pass_args<float>(c), s);
     else launch_pass<double, kVVStart>(c, pass_args<double>(c), s);
@@ -563,8 +569,15 @@ void enqueue_settle_any(const ss_ctx* c, hipStream_t s) {
 // End of a run of steps: the arrest test of the final field where the
 // integrator has not taken it already, then the velocity zeroed if it fired.
 void enqueue_end_of_run_any(const ss_ctx* c, hipStream_t s) {
-  if (c->integ == SS_INTEG_RK4) enqueue_check_any(c, s);
-  else enqueue_settle_any(c, s);
+  if (c->integ == SS_INTEG_RK4) {
+    enqueue_check_any(c, s);
+  } else if (gd_form(c)) {
+    // the last field is untested: its energy and gradient
+    if (c->dtype == SS_F32) launch_pass<float, kGDCheck>(c, pass_args<float>(c), s);
+    else launch_pass<double, kGDCheck>(c, pass_args<double>(c), s);
+  } else {
+    enqueue_settle_any(c, s);
+  }
 }
 
 int read_status(ss_ctx* c, DevStatus* out) {
@@ -1020,11 +1033,13 @@ int ss_time_passes(ss_ctx* c, int n_steps, double* ms) {
       }
       SS_HIP(hipEventRecord(ev[1], c->stream));
       if (c->dtype == SS_F32) {
-        if (c->integ == SS_INTEG_GF) launch_pass<float, kGF>(c, pass_args<float>(c), c->stream);
+        if (gd_form(c)) launch_pass<float, kGD>(c, pass_args<float>(c), c->stream);
+        else if (c->integ == SS_INTEG_GF) launch_pass<float, kGF>(c, pass_args<float>(c), c->stream);
         else if (vv_kdk(c)) launch_pass<float, kVV>(c, pass_args<float>(c), c->stream);
         else launch_pass<float, kVVA>(c, pass_args<float>(c), c->stream);
       } else {
-        if (c->integ == SS_INTEG_GF) launch_pass<double, kGF>(c, pass_args<double>(c), c->stream);
+        if (gd_form(c)) launch_pass<double, kGD>(c, pass_args<double>(c), c->stream);
+        else if (c->integ == SS_INTEG_GF) launch_pass<double, kGF>(c, pass_args<double>(c), c->stream);
         else if (vv_kdk(c)) launch_pass<double, kVV>(c, pass_args<double>(c), c->stream);
         else launch_pass<double, kVVA>(c, pass_args<double>(c), c->stream);
       }
@@ -2004,7 +2019,7 @@ void batch_enqueue_steps(const ss_batch* b, int n, hipStream_t s) {
         batch_launch<T, kVVRestart>(b, s);
         batch_launch<T, kVV>(b, s);
       } else {
-        batch_launch<T, kGF>(b, s);
+        batch_launch<T, kGD>(b, s);
       }
     }
     return;
@@ -2027,17 +2042,13 @@ void batch_enqueue_steps_any(const ss_batch* b, int n, hipStream_t s) {
   else batch_enqueue_steps<double>(b, n, s);
 }
 
-// First pass of a one-pass run: each member's current field tested and its
-// force stored (velocity Verlet: u formed).
+// First pass of a velocity Verlet run: each member's current field tested and
+// its u formed.
 void batch_enqueue_prime(const ss_batch* b, hipStream_t s) {
-  if (b->integ == SS_INTEG_RK4) return;
-  if (b->integ == SS_INTEG_VV) {
-    if (b->dtype == SS_F32) batch_launch<float, kVVStart>(b, s);
-    else batch_launch<double, kVVStart>(b, s);
-    return;
-  }
-  if (b->dtype == SS_F32) batch_launch<float, kPrime>(b, s);
-  else batch_launch<double, kPrime>(b, s);
+  // RK4 and gradient flow test the current field in their first step
+  if (b->integ != SS_INTEG_VV) return;
+  if (b->dtype == SS_F32) batch_launch<float, kVVStart>(b, s);
+  else batch_launch<double, kVVStart>(b, s);
 }
 
 void batch_enqueue_apply_arrest(const ss_batch* b, hipStream_t s);
@@ -2055,9 +2066,15 @@ void batch_enqueue_settle(const ss_batch* b, hipStream_t s) {
   }
 }
 
-// End of a run: RK4 tests the last field (the check pass); the one-pass
-// integrators have tested it already. Then a pending arrest zeroes the velocity.
+// End of a run: RK4 and gradient flow test the last field (their check passes);
+// velocity Verlet has tested it already and turns u back into v.
 void batch_enqueue_check(const ss_batch* b, hipStream_t s) {
+  if (b->integ == SS_INTEG_GF) {
+    // the last fields are untested: their energies and gradients
+    if (b->dtype == SS_F32) batch_launch<float, kGDCheck>(b, s);
+    else batch_launch<double, kGDCheck>(b, s);
+    return;
+  }
   if (b->integ != SS_INTEG_RK4) {
     batch_enqueue_settle(b, s);
     return;

@@ -89,6 +89,12 @@ enum Pass : int {
                     //   of the current field as kCheck
   kVVRestart = 10,  // before a step that follows an arrest (v = 0): u = -dt/2 G(phi)
   kVVEnd = 11,      // end of a run: v = u + dt/2 G(phi), or 0 after an arrest
+  // Gradient flow on the lattice theories keeps only the field: a step tests the
+  // field it reads and writes the next one.
+  kGD = 13,       // E_h(phi), G(phi) and the stop rules of phi (no arrest); writes
+                  //   phi' = phi - tau G(phi) (tau = dt^2/2; on the unit sphere for
+                  //   unit fields); the step advances unless a rule fired
+  kGDCheck = 14,  // end of a run: E_h and G of the current field, tested without arrest
 };
 
 // The pass writes a new field and tests it (its finalise advances the step first).
@@ -96,8 +102,10 @@ constexpr bool advances_first(int pass) { return pass == kVV || pass == kVVA || 
 // The pass reduces energy, max |G| and a non-finite count.
 constexpr bool reduces(int pass) {
   return pass == kP1 || pass == kEval || pass == kCheck || pass == kPrime || advances_first(pass) ||
-         pass == kVVStart;
+         pass == kVVStart || pass == kGD || pass == kGDCheck;
 }
+// The pass's status update takes no arrest decision (gradient flow has no velocity).
+constexpr bool no_arrest(int pass) { return pass == kGF || pass == kGD || pass == kGDCheck; }
 // The pass evaluates G at a stage point phi + cv v + ca a (stage_coeffs) rather
 // than at the current field.
 constexpr bool staged(int pass) { return pass == kP2 || pass == kP3 || pass == kP4 || advances_first(pass); }
@@ -112,6 +120,9 @@ constexpr bool uses_arrest(int pass) {
 // The pass writes the velocity buffer of the current field in place (each site
 // by the thread that reads it): the velocity Verlet passes around the steps.
 constexpr bool vv_in_place(int pass) { return pass == kVVStart || pass == kVVRestart || pass == kVVEnd; }
+// Passes launched once per run (or after an arrest) on one tile shape, whatever
+// the context's tile.
+constexpr bool fixed_tile(int pass) { return vv_in_place(pass) || pass == kGDCheck; }
 
 // Coefficients of the stage point phi + cv v + ca a of a pass. After an arrest
 // the RK4 stages 2-4 and the stored-force velocity Verlet step start from rest

@@ -224,6 +224,25 @@ __device__ __forceinline__ void one_pass_epilogue(T dt, const T (&u)[4], const T
   }
 }
 
+// Epilogue of a gradient-flow step at one site: phi' = phi - tau G(phi) with
+// tau = dt^2/2, put on the unit sphere for unit fields, into the other buffer.
+template <class T, int TH>
+__device__ __forceinline__ void gd_epilogue(T dt, const T (&phi)[4], const T (&G)[4], T* __restrict__ phn,
+                                            long plane, long off) {
+  constexpr int C = NComp<TH>::value;
+  const T tau = T(0.5) * dt * dt;
+  T pn[4];
+#pragma unroll
+  for (int c = 0; c < C; ++c) pn[c] = phi[c] - tau * G[c];
+  if (unit_field(TH)) {
+    const T inv = T(1) / sqrt(pn[0] * pn[0] + pn[1] * pn[1] + pn[2] * pn[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pn[c] *= inv;
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) __builtin_nontemporal_store(pn[c], &phn[c * plane + off]);
+}
+
 // Epilogue of the velocity Verlet passes around the steps at one site of the
 // current field, whose velocity buffer vc is updated in place (G = G(phi)):
 // start u = v - dt/2 G, restart u = -dt/2 G, end v = u + dt/2 G (0 after an
@@ -255,7 +274,7 @@ template <class T, int TH, int PASS, int TX, int TY>
 struct TileLds {
   static constexpr int C = NComp<TH>::value;
   static constexpr int LX = TX + 4, LY = TY + 4;
-  static constexpr bool CARRY = advances_first(PASS) || vv_in_place(PASS);
+  static constexpr bool CARRY = advances_first(PASS) || vv_in_place(PASS) || PASS == kGD;
   static constexpr int STAGE = C * LY * LX;
   static constexpr int ROWS = CARRY ? C * 4 * LX : 0;
   static constexpr int RAW = (PASS == kVV || PASS == kVVA) ? 2 * 2 * C * TX : 0;
@@ -546,6 +565,8 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
       one_pass_epilogue<T, TH, PASS>(dt, rv[r], so[r], G, phn, vn, a_store, plane, off);
     } else if (vv_in_place(PASS)) {
       vv_in_place_epilogue<T, TH, PASS>(dt, arrest, G, vcur, plane, off);
+    } else if (PASS == kGD) {
+      gd_epilogue<T, TH>(dt, so[r], G, phn, plane, off);
     } else if (PASS == kEval) {
       if (out != nullptr) {
         const long o = (long)(gj + 2) * out_pitch + (gi + 2);
@@ -910,6 +931,8 @@ __device__ __forceinline__ void tile_body_exact(const InstView<T>& V, int cur, b
       one_pass_epilogue<T, TH, PASS>(dt, rv[r], so[r], G, phn, vn, a_store, plane, off);
     } else if (vv_in_place(PASS)) {
       vv_in_place_epilogue<T, TH, PASS>(dt, arrest, G, vcur, plane, off);
+    } else if (PASS == kGD) {
+      gd_epilogue<T, TH>(dt, so[r], G, phn, plane, off);
     } else if (PASS == kEval) {
       if (out != nullptr) {
         const long o = (long)(gj + 2) * out_pitch + (gi + 2);
@@ -972,7 +995,7 @@ __device__ __forceinline__ void finalise_status(DevStatus* st, double E, double 
   long long s0 = st->step;
   if (advances_first(PASS)) st->step = ++s0;
   // gradient flow has no velocity, hence no arrest
-  const int arr = (PASS != kGF && E > st->E_prev) ? 1 : 0;
+  const int arr = (!no_arrest(PASS) && E > st->E_prev) ? 1 : 0;
   st->arrest = arr;
   if (arr) st->n_arrests += 1;
   st->E_prev = E;
@@ -991,7 +1014,7 @@ __device__ __forceinline__ void finalise_status(DevStatus* st, double E, double 
     else if (s0 >= st->max_steps) done = 3;
   }
   if (done) st->done = done;
-  else if (PASS == kP1) st->step = s0 + 1;
+  else if (PASS == kP1 || PASS == kGD) st->step = s0 + 1;
 }
 
 // Launch: gridDim.x is a multiple of 8; tiles are assigned by for_each_tile.
@@ -1004,7 +1027,7 @@ __device__ __forceinline__ void finalise_status(DevStatus* st, double E, double 
 // passes fit it uncapped.
 template <class T, int TH, int PASS, int RY>
 struct StageWaves {
-  static constexpr int value = (sizeof(T) == 4 && TH == 0 && RY == 2 && advances_first(PASS)) ? 4 : 1;
+  static constexpr int value = (sizeof(T) == 4 && TH == 0 && RY == 2 && (advances_first(PASS) || PASS == kGD)) ? 4 : 1;
 };
 
 template <class T, int TH, int PASS, int TX, int TY, int RY>

@@ -43,10 +43,11 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 # field sets read and written per site by each pass (stage passes P1..P4, the
 # fused pass of stages 2-4, velocity Verlet in kick-drift-kick form, gradient flow)
 ALG_SETS = {"P1": (1, 1), "P234": (3, 2), "P2": (2, 1), "P3": (4, 1), "P4": (5, 2), "VV": (2, 2), "VVA": (3, 3),
-            "GF": (2, 2)}
+            "GF": (1, 1)}
 # the kernels' pass template argument (VV: velocity Verlet in kick-drift-kick form,
-# VVR: its restart pass, VVA: velocity Verlet with the stored force)
-PASS_INDEX = {"P1": 0, "P2": 1, "P3": 2, "P4": 3, "VV": 7, "GF": 8, "VVR": 10, "VVA": 12}
+# VVR: its restart pass, VVA: velocity Verlet with the stored force, GF: gradient
+# flow keeping only the field)
+PASS_INDEX = {"P1": 0, "P2": 1, "P3": 2, "P4": 3, "VV": 7, "GF": 13, "VVR": 10, "VVA": 12}
 # passes each integrator launches every step
 INTEG_PASSES = {"rk4": ("P1", "P234"), "vv": ("VV",), "gf": ("GF",)}
 TILES = [(64, 16, 2), (64, 8, 2), (64, 16, 4), (64, 32, 4)]  # (TX, TY, rows per thread)
