@@ -369,17 +369,33 @@ void bec_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
     hipLaunchKernelGGL((bec_finalise<PASS>), dim3(1), b1, 0, s, c->st, (const double*)W.part, (const double*)W.sc);
 }
 
+template <class T, int PASS>
+void launch_lattice_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s);
+
 // A pass; a reducing pass (P1, evaluation, check) is followed by its finalise
 // launch, which sums the workgroup partials and updates the status. With
 // demagnetisation the pass is preceded by the solve for its stage point.
 template <class T, int PASS>
 void launch_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
-  if constexpr (!fixed_tile(PASS) && PASS != kGD) {
-    if (c->theory == SS_THEORY_BEC) {
-      bec_pass<T, PASS>(c, a, s);
-      return;
+  if constexpr (PASS == kGF) {
+    // only the BEC keeps the force between gradient-flow steps (the lattice
+    // theories run kGD)
+    bec_pass<T, PASS>(c, a, s);
+    return;
+  } else {
+    if constexpr (!fixed_tile(PASS) && PASS != kGD) {
+      if (c->theory == SS_THEORY_BEC) {
+        bec_pass<T, PASS>(c, a, s);
+        return;
+      }
     }
+    launch_lattice_pass<T, PASS>(c, a, s);
   }
+}
+
+// A pass of the lattice theories (everything but the BEC).
+template <class T, int PASS>
+void launch_lattice_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   // velocity Verlet's restart and end of run evaluate the current field, whose
   // potential the step that made it has solved for
   if (c->dm.on && PASS != kVVRestart && PASS != kVVEnd) demag_solve<T, PASS>(c, a, s);
