@@ -411,15 +411,16 @@ void launch_lattice_pass(const ss_ctx* c, const PassArgs<T>& a, hipStream_t s) {
   } else if constexpr (fixed_tile(PASS)) {
     // once per run, or after an arrest: one tile shape (64 x 16) whatever the
     // context's tile
+    constexpr int kFixedTile = 0;
     PassArgs<T> b = a;
     Layout L = c->L;
-    set_tiles(L, c->Nx, c->Ny, 0);
+    set_tiles(L, c->Nx, c->Ny, kFixedTile);
     b.ntx = L.ntx;
     b.nty = L.nty;
     b.seg = L.seg;
-    if (c->theory == SS_THEORY_AH) groups = launch_cfg<T, kAH, PASS, 0>(b, L.nlaunch, s);
-    else if (c->theory == SS_THEORY_CM) groups = launch_cfg<T, kCM, PASS, 0>(b, L.nlaunch, s);
-    else groups = launch_cfg<T, kBS, PASS, 0>(b, L.nlaunch, s);
+    if (c->theory == SS_THEORY_AH) groups = launch_cfg<T, kAH, PASS, kFixedTile>(b, L.nlaunch, s);
+    else if (c->theory == SS_THEORY_CM) groups = launch_cfg<T, kCM, PASS, kFixedTile>(b, L.nlaunch, s);
+    else groups = launch_cfg<T, kBS, PASS, kFixedTile>(b, L.nlaunch, s);
   } else if (c->theory == SS_THEORY_AH) {
     groups = launch_pass_t<T, kAH, PASS>(c->tile, a, groups, s);
   } else if (c->theory == SS_THEORY_CM) {

@@ -34,7 +34,8 @@ struct DevStatus {
   int minimise;          // 1: the arrest pass applies the stop rules
   unsigned counter;      // last-block counter of the arrest pass
   unsigned counter_obs;  // last-block counter of the observable passes
-  int pad_;
+  int fresh;             // set when a run is armed: its first test is of the field
+                         // the last run ended on (or a fresh one), whose arrest is decided
   double e_target;       // minimise stops once E <= e_target (-inf: never)
   double hist[kHistLen]; // E at step s is kept at hist[s % kHistLen]
   double obs[16];        // observable sums (see ss_api)

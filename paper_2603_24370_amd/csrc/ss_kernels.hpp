@@ -994,11 +994,18 @@ __device__ __forceinline__ void finalise_status(DevStatus* st, double E, double 
   // the tests below are those of the new field
   long long s0 = st->step;
   if (advances_first(PASS)) st->step = ++s0;
+  // The first test of a run is of the field the last run ended on, whose arrest
+  // that run decided (and applied), or of a fresh field (E_prev infinite): it
+  // takes no new arrest decision and keeps the energy the next test compares
+  // with, so a run split in two decides its arrests as one run does. (Its own
+  // sum of the same field may differ in the last bits: another launch shape.)
+  const bool retest = st->fresh != 0;
+  st->fresh = 0;
   // gradient flow has no velocity, hence no arrest
-  const int arr = (!no_arrest(PASS) && E > st->E_prev) ? 1 : 0;
-  st->arrest = arr;
+  const int arr = (!no_arrest(PASS) && !retest && E > st->E_prev) ? 1 : 0;
+  if (!retest) st->arrest = arr;
   if (arr) st->n_arrests += 1;
-  st->E_prev = E;
+  if (!retest || !isfinite(st->E_prev)) st->E_prev = E;
   st->E = E;
   st->gmax = gmax;
   st->nonfinite = nfin;
@@ -1585,6 +1592,7 @@ __global__ void batch_arm(DevStatus* const* st, int n, int minimise, double grad
   if (i < n) {
     DevStatus* s = st[i];
     s->done = 0;
+    s->fresh = 1;
     s->minimise = minimise;
     s->grad_tol = grad_tol;
     s->rel_e_tol = rel_e_tol;
@@ -1614,6 +1622,7 @@ __global__ void arm_status(DevStatus* st, int minimise, double grad_tol, double 
                            long long max_steps) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->done = 0;
+    st->fresh = 1;
     st->minimise = minimise;
     st->grad_tol = grad_tol;
     st->rel_e_tol = rel_e_tol;

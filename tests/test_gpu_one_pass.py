@@ -255,3 +255,33 @@ def test_one_pass_units_of_several_tiles(ss, orc, integ, theory, dtype):
     if dtype == "f64":
         assert info["energy"] == pytest.approx(E_r, rel=1e-12)
     s.close()
+
+
+@pytest.mark.parametrize("integ", ["vv", "vv_half", "rk4"])
+def test_split_runs_keep_the_oracle_arrests(ss, orc, integ):
+    """A flow split into four runs of 50 steps on 64 x 8 tiles, where the passes
+    around the half-step form's steps run on 64 x 16 tiles, and RK4's end-of-run
+    check and first stage are different launches: each run's first test
+    re-evaluates the field the last run ended on, possibly summed in another
+    order, and takes no new arrest decision, so the arrests are those of the
+    oracle's one continued flow."""
+    Nx, Ny, h = 48, 40, 0.25
+    print(f"[case] split runs {integ}", flush=True)
+    f = I.ah_vortex_ansatz(Nx, Ny, h, [(0.3, -0.2), (-1.1, 0.9)]) + I.noise(5, 4, Nx, Ny, 1e-3)
+    s = ss.Solver(AH, Nx, Ny, h, [1.0], dtype="f64")
+    if integ == "rk4":
+        s.set_integrator("rk4")
+    else:
+        _set_integ(s, integ)
+    s.set_tile(1)
+    s.set_field(f)
+    scheme = "rk4" if integ == "rk4" else "vv"
+    phi_r, v_r, E, total = f, np.zeros_like(f), None, 0
+    for _ in range(4):
+        info = s.flow_step(50)
+        phi_r, v_r, E, na = orc.flow(AH, phi_r, v_r, h, [1.0], 50, E_cur=E, scheme=scheme)
+        total += na
+        assert info["n_arrests"] == total
+    assert total > 0
+    assert np.abs(_np(s.get_field()) - phi_r).max() <= 1e-10 * np.abs(phi_r).max()
+    s.close()
