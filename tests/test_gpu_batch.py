@@ -200,19 +200,21 @@ def test_one_pass_batch_flow_matches_oracle_per_member(ss, orc, dtype, scheme, t
     B.close()
 
 
-def test_velocity_verlet_batch_minimise_stops_each_member_where_the_oracle_does(ss, orc):
-    """FP64 velocity Verlet: every member stops at the oracle's step with its arrest
-    count, across graph replays and work-list compaction."""
+@pytest.mark.parametrize("scheme,tol", [("vv", 2e-3), ("gf", 5e-2)])
+def test_one_pass_batch_minimise_stops_each_member_where_the_oracle_does(ss, orc, scheme, tol):
+    """FP64 velocity Verlet (half-step form) and gradient flow (the field only):
+    every member stops at the oracle's step with its arrest count, across graph
+    replays and work-list compaction."""
     insts = _members(30, 5, sides=[32, 48, 40, 56, 36])
     B = ss.Batch(AH, [(m.Nx, m.Ny, m.h, m.params) for m in insts], dtype="f64")
-    B.set_integrator("vv")
+    B.set_integrator(scheme)
     fields = [m.field() for m in insts]
     for f, mem in zip(fields, B.members):
         mem.set_field(f)
-    rc, infos = B.minimise(grad_tol=2e-3, max_steps=3000, graph_steps=8)
+    rc, infos = B.minimise(grad_tol=tol, max_steps=3000, graph_steps=8)
     steps = set()
     for k, (m, f) in enumerate(zip(insts, fields)):
-        phi_r, v_r, info_r = orc.minimise(AH, f, m.h, m.params, grad_tol=2e-3, max_steps=3000, scheme="vv")
+        phi_r, v_r, info_r = orc.minimise(AH, f, m.h, m.params, grad_tol=tol, max_steps=3000, scheme=scheme)
         assert infos[k]["step"] == info_r["steps"], k
         assert infos[k]["n_arrests"] == info_r["arrests"], k
         assert infos[k]["reason"] == {1: "grad", 2: "stall", 0: "max_steps"}[info_r["reason"]]
