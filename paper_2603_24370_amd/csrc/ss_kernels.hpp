@@ -339,35 +339,62 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
   const int ly0 = wy * RY + 2;
   const int gi = x0 + threadIdx.x;
 
-  // stage point of padded element (gi, gj) (interior coordinates), and its raw inputs
-  auto stage_at = [&](int gi_, int gj_, T (&raw_p)[4], T (&raw_v)[4], T (&raw_a)[4], T (&S)[4]) {
+  // Stage point of padded element (gi, gj) (interior coordinates) and its raw
+  // inputs, in two halves, so that a thread can have the loads of all its own
+  // rows in flight together. load_raw: the raw inputs (a row past the padded
+  // lattice reads its last row instead; it is discarded below).
+  auto load_raw = [&](int gi_, int gj_, T (&raw_p)[4], T (&raw_v)[4], T (&raw_a)[4]) {
+    const long off = (long)(min(gj_, Ny + 1) + 2) * pitch + (gi_ + 2);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) raw_p[c] = raw_v[c] = raw_a[c] = S[c] = T(0);
-    // Columns right of the padded lattice feed only discarded sites. The flow's
-    // own rows are long enough to read them; an evaluated field may come in a
-    // caller's tight layout (pitch Nx + 4), so there they are not read.
-    if (gj_ > Ny + 1 || (PASS == kEval && gi_ > Nx + 1)) return;
-    const long off = (long)(gj_ + 2) * pitch + (gi_ + 2);
+    for (int c = 0; c < 4; ++c) {
+      raw_p[c] = raw_v[c] = raw_a[c] = T(0);
+      if (c < C) {
+        raw_p[c] = ph[c * plane + off];
+        if (STAGED && WITH_V) raw_v[c] = vv[c * plane + off];
+        if (STAGED && WITH_A) raw_a[c] = aa[c * plane + off];
+      }
+    }
+  };
+  // stage_of_raw: the stage point (zero past the padded lattice, raw inputs
+  // too). Unit fields are normalised with the squared norm in a fixed fma
+  // order: a site is formed by its own tile and again in its neighbours' halo
+  // rings, and every copy must have the same bits.
+  auto stage_of_raw = [&](int gi_, int gj_, T (&raw_p)[4], T (&raw_v)[4], T (&raw_a)[4], T (&S)[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) S[c] = T(0);
+    if (gj_ > Ny + 1) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) raw_p[c] = raw_v[c] = raw_a[c] = T(0);
+      return;
+    }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      raw_p[c] = ph[c * plane + off];
       T x = raw_p[c];
       if (STAGED) {
-        if (WITH_V) raw_v[c] = vv[c * plane + off];
-        x += cv * raw_v[c];
-        if (WITH_A) {
-          raw_a[c] = aa[c * plane + off];
-          x += ca * raw_a[c];
-        }
+        x = fma(cv, raw_v[c], x);
+        if (WITH_A) x = fma(ca, raw_a[c], x);
       }
       S[c] = x;
     }
     if (unit_field(TH) && STAGED && gi_ >= 0 && gi_ < Nx && gj_ >= 0 && gj_ < Ny) {
-      const T inv = T(1) / sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+      const T inv = T(1) / sqrt(fma(S[2], S[2], fma(S[1], S[1], S[0] * S[0])));
       S[0] *= inv;
       S[1] *= inv;
       S[2] *= inv;
     }
+  };
+  // Both halves at once (halo rings). Columns right of the padded lattice feed
+  // only discarded sites. The flow's own rows are long enough to read them; an
+  // evaluated field may come in a caller's tight layout (pitch Nx + 4), so
+  // there they are not read.
+  auto stage_at = [&](int gi_, int gj_, T (&raw_p)[4], T (&raw_v)[4], T (&raw_a)[4], T (&S)[4]) {
+    if (gj_ > Ny + 1 || (PASS == kEval && gi_ > Nx + 1)) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) raw_p[c] = raw_v[c] = raw_a[c] = S[c] = T(0);
+      return;
+    }
+    load_raw(gi_, gj_, raw_p, raw_v, raw_a);
+    stage_of_raw(gi_, gj_, raw_p, raw_v, raw_a, S);
   };
 
   // ---- carried rows: stage rows 0-3 from the tile above
@@ -385,29 +412,13 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
   // ---- own sites: raw inputs kept in registers, stage point to LDS (and, for
   // the one-pass integrators, in registers: it is the new field that is stored)
   T rp[RY][4], rv[RY][4], ra[RY][4], so[RY][4];
+  // an evaluated field may lack the columns right of the lattice, so its loads
+  // keep stage_at's guard
+  constexpr bool SPLIT = PASS != kEval;
+  if (SPLIT) {
 #pragma unroll
-  for (int r = 0; r < RY; ++r) {
-    const int ly = ly0 + r;
-    if (carried && ly < 4) {
-      const T* __restrict__ q = cr + ((par ^ 1) * 2 + (ly - 2)) * C * TX + threadIdx.x;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        rp[r][c] = rv[r][c] = ra[r][c] = so[r][c] = T(0);
-        if (c < C) {
-          so[r][c] = cs[(c * 4 + ly) * LX + lx];
-          if (PASS == kVV || PASS == kVVA) rv[r][c] = q[c * TX];
-        }
-      }
-    } else {
-      stage_at(gi, y0 + ly - 2, rp[r], rv[r], ra[r], so[r]);
-      // the stored-force step keeps w = v0 + dt/2 a in rv (the epilogue's u)
-      if (PASS == kVVA) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) rv[r][c] = vv_partial(arrest, dt, rv[r][c], ra[r][c]);
-      }
-#pragma unroll
-      for (int c = 0; c < C; ++c) s[c][ly * LX + lx] = so[r][c];
-    }
+    for (int r = 0; r < RY; ++r)
+      if (!(carried && ly0 + r < 4)) load_raw(gi, y0 + ly0 + r - 2, rp[r], rv[r], ra[r]);
   }
   // ---- halo ring of the tile: all of it, or for a carried tile the x halo of
   // rows 4 .. TY+1 and the two bottom rows
@@ -444,6 +455,32 @@ __device__ __forceinline__ void tile_body(const InstView<T>& V, int cur, bool ar
       T* __restrict__ q = cr + (par * 2 + (ly - (LY - 2))) * C * TX + (lxr - 2);
 #pragma unroll
       for (int c = 0; c < C; ++c) q[c * TX] = PASS == kVV ? d1v[c] : vv_partial(arrest, dt, d1v[c], d2[c]);
+    }
+  }
+  // ---- own sites' stage points (their loads were issued before the ring's)
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int ly = ly0 + r;
+    if (carried && ly < 4) {
+      const T* __restrict__ q = cr + ((par ^ 1) * 2 + (ly - 2)) * C * TX + threadIdx.x;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        rp[r][c] = rv[r][c] = ra[r][c] = so[r][c] = T(0);
+        if (c < C) {
+          so[r][c] = cs[(c * 4 + ly) * LX + lx];
+          if (PASS == kVV || PASS == kVVA) rv[r][c] = q[c * TX];
+        }
+      }
+    } else {
+      if (SPLIT) stage_of_raw(gi, y0 + ly - 2, rp[r], rv[r], ra[r], so[r]);
+      else stage_at(gi, y0 + ly - 2, rp[r], rv[r], ra[r], so[r]);
+      // the stored-force step keeps w = v0 + dt/2 a in rv (the epilogue's u)
+      if (PASS == kVVA) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rv[r][c] = vv_partial(arrest, dt, rv[r][c], ra[r][c]);
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) s[c][ly * LX + lx] = so[r][c];
     }
   }
   __syncthreads();
