@@ -195,16 +195,20 @@ def test_one_pass_arrests_and_stops_like_the_oracle(ss, orc, integ):
     s.close()
 
 
+@pytest.mark.parametrize("tile", [0, 1])
 @pytest.mark.parametrize("integ", ["vv", "vv_stored", "gf"])
-def test_large_lattice_one_pass_step_sampled_parity(ss, orc, integ):
+def test_large_lattice_one_pass_step_sampled_parity(ss, orc, integ, tile):
     """One step of the 4096^2 GL workload with a one-pass integrator, as the
-    benchmark times it, on sampled windows: the oracle steps a window whose outer
-    ring of M >= 4 sites (two radius-2 stencils per step) is held fixed."""
+    benchmark times it (on 64 x 16 and on 64 x 8 tiles, the shapes its autotuner
+    picks), on sampled windows: the oracle steps a window whose outer ring of
+    M >= 4 sites (two radius-2 stencils per step) is held fixed."""
     N, h, M, S = 4096, 0.2, 6, 64
-    print(f"[case] gl4096 one-pass {integ}", flush=True)
+    print(f"[case] gl4096 one-pass {integ} tile {tile}", flush=True)
     inst = I.gl_large_instance(N, h)
     lam = I.gl_lambda_from_kappa(1.5)
     s = ss.Solver(AH, N, N, h, [lam], dtype="f32")
+    s.set_tile(tile)
+    assert ss.ss_get_tile(s.ctx) == tile
     _set_integ(s, integ)
     if integ == "vv":
         assert s.vv_form == ss.SS_VV_HALF_STEP  # the form a lattice of this size picks
